@@ -1,0 +1,353 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these checks re-types the oracle's own formulas: they compare it to
+brute-force subset enumeration, to the simple backtracking lister, to closed
+forms of graph families, to algebraic identities of the clique polynomial, to
+invariance under the free choices of the method (Thm. scr), and to a
+hand-traced worked example (tests/golden/wheel_w4.json).
+"""
+import json
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2001_06784_amd import graphgen as gg
+from tests import brute
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _vertex_ints(res):
+    return O.limbs_to_int(res.vertex)
+
+
+def _edge_ints(res):
+    return O.limbs_to_int(res.edge)
+
+
+# ------------------------------------------------------------ brute force
+
+TINY = [(n, p, s) for n in (1, 2, 5, 9, 12, 14) for p in (0.2, 0.5, 0.85) for s in (1, 2)]
+
+
+@pytest.mark.parametrize("n,p,seed", TINY)
+def test_brute_force_all_counts(n, p, seed):
+    g = gg.gnp(n, p, seed)
+    C, cv, ce = brute.brute_counts(g)
+    K = n + 1
+    r = O.count(g, vertex=(1, K), edge=(1, K))
+    for k in range(1, K + 1):
+        got = r.glob[k] if k < len(r.glob) else 0
+        assert got == C[k], (k, got, C[k])
+    V = _vertex_ints(r)
+    for v in range(n):
+        for k in range(1, K + 1):
+            assert V[v][k - 1] == cv[v][k], (v, k)
+    E = _edge_ints(r)
+    for e in range(g.m):
+        for k in range(1, K + 1):
+            assert E[e][k - 1] == ce[e][k], (e, k)
+    assert not r.glob_ovf.any() and not r.vertex_ovf.any() and not r.edge_ovf.any()
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_enumerator_medium(seed):
+    g = gg.gnp(70, 0.35, seed)
+    C, cliques = brute.enum_counts(g)
+    r = O.count(g, vertex=(3, 6))
+    for k in range(1, len(C)):
+        assert r.glob[k] == C[k]
+    assert r.omega == len(C) - 2
+    V = _vertex_ints(r)
+    cv = np.zeros((g.n, 4), dtype=object)
+    for c in cliques:
+        if 3 <= len(c) <= 6:
+            for v in c:
+                cv[v][len(c) - 3] += 1
+    assert (V == cv).all()
+
+
+# ----------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 20, 40])
+def test_complete_graph(n):
+    r = O.count(gg.complete(n), vertex=(1, n), edge=(1, n))
+    assert r.glob[: n + 1] == [comb(n, k) for k in range(n + 1)]
+    assert r.stats["leaves"] == n  # each root child is a clique: one pivot chain
+    V = _vertex_ints(r)
+    for k in range(1, n + 1):
+        assert all(V[v][k - 1] == comb(n - 1, k - 1) for v in range(n))
+    if n >= 2:
+        E = _edge_ints(r)
+        for k in range(1, n + 1):
+            assert all(E[e][k - 1] == (comb(n - 2, k - 2) if k >= 2 else 0) for e in range(r.edge.shape[0]))
+
+
+@pytest.mark.parametrize("parts", [[1, 1], [2, 3], [3, 3, 3], [1, 2, 3, 4], [5, 1, 5, 2, 2]])
+def test_complete_multipartite(parts):
+    g = gg.complete_multipartite(parts)
+    r = O.count(g, vertex=(1, len(parts)), edge=(1, len(parts)))
+    for k in range(0, len(parts) + 2):
+        want = brute.elementary_symmetric(parts, k) if k <= len(parts) else 0
+        got = r.glob[k] if k < len(r.glob) else 0
+        assert got == want
+    label = np.repeat(np.arange(len(parts)), parts)
+    V = _vertex_ints(r)
+    for v in range(g.n):
+        others = [a for i, a in enumerate(parts) if i != label[v]]
+        for k in range(1, len(parts) + 1):
+            assert V[v][k - 1] == brute.elementary_symmetric(others, k - 1)
+    E = _edge_ints(r)
+    a, b = g.edges()
+    for e in range(g.m):
+        others = [x for i, x in enumerate(parts) if i not in (label[a[e]], label[b[e]])]
+        for k in range(2, len(parts) + 1):
+            assert E[e][k - 1] == brute.elementary_symmetric(others, k - 2)
+
+
+@pytest.mark.parametrize("r_", [1, 2, 5, 8])
+def test_moon_moser(r_):
+    res = O.count(gg.moon_moser(r_))
+    assert res.glob[: r_ + 1] == [comb(r_, k) * 3 ** k for k in range(r_ + 1)]
+
+
+@pytest.mark.parametrize("r_", [2, 4, 7])
+def test_cocktail_party(r_):
+    res = O.count(gg.complete_multipartite([2] * r_))
+    assert res.glob[: r_ + 1] == [comb(r_, k) * 2 ** k for k in range(r_ + 1)]
+
+
+@pytest.mark.parametrize("maker", [lambda: gg.empty(7), lambda: gg.path(9), lambda: gg.star(8),
+                                   lambda: gg.cycle(4), lambda: gg.cycle(11)])
+def test_triangle_free(maker):
+    g = maker()
+    r = O.count(g)
+    assert r.glob[0] == 1 and r.glob[1] == g.n and r.glob[2] == g.m
+    assert all(c == 0 for c in r.glob[3:])
+    # each N+(v) is independent: one leaf per out-edge, one per sink vertex
+    od = O.out_degrees(g, O.peel(g).sub)
+    assert r.stats["leaves"] == g.m + int((od == 0).sum())
+
+
+def test_triangle_cycle3():
+    r = O.count(gg.cycle(3))
+    assert r.glob[:4] == [1, 3, 3, 1]
+
+
+# ---------------------------------------------------- algebraic identities
+
+def _poly(r):
+    return [int(x) for x in r.glob]
+
+
+def _mul(a, b):
+    out = [0] * (len(a) + len(b))
+    for i, x in enumerate(a):
+        for j, y in enumerate(b):
+            out[i + j] += x * y
+    return out
+
+
+def _trim(a):
+    a = list(a)
+    while a and a[-1] == 0:
+        a.pop()
+    return a
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_join_multiplies_clique_polynomial(seed):
+    g = gg.gnp(13, 0.4, seed)
+    h = gg.gnp(11, 0.6, seed + 10)
+    pg, ph = _poly(O.count(g)), _poly(O.count(h))
+    pj = _poly(O.count(gg.join(g, h)))
+    assert _trim(pj) == _trim(_mul(pg, ph))
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_disjoint_union_adds(seed):
+    g = gg.gnp(15, 0.5, seed)
+    h = gg.complete(9)
+    pg, ph = _poly(O.count(g)), _poly(O.count(h))
+    pu = _poly(O.count(gg.disjoint_union(g, h)))
+    L = max(len(pg), len(ph))
+    s = [(pg[i] if i < len(pg) else 0) + (ph[i] if i < len(ph) else 0) for i in range(L)]
+    s[0] -= 1
+    assert _trim(pu) == _trim(s)
+
+
+@pytest.mark.parametrize("seed", [7, 8])
+def test_local_sum_identities(seed):
+    g = gg.plant_cliques(gg.gnp(120, 0.08, seed), [9, 7], seed)
+    r = O.count(g, vertex=(1, 9), edge=(1, 9))
+    V, E = _vertex_ints(r), _edge_ints(r)
+    for k in range(1, 10):
+        assert sum(V[:, k - 1]) == k * r.glob[k]
+        if k >= 2:
+            assert sum(E[:, k - 1]) == comb(k, 2) * r.glob[k]
+    deg = g.degrees()
+    assert all(V[v][1] == deg[v] for v in range(g.n))
+    assert all(E[e][1] == 1 for e in range(g.m))
+    adj = brute.adjacency_sets(g)
+    a, b = g.edges()
+    assert all(E[e][2] == len(adj[a[e]] & adj[b[e]]) for e in range(g.m))
+    assert r.glob[3] == brute.triangles_by_matrix(g)
+    # sum over leaves of 2^p = number of non-empty cliques
+    assert r.glob[1] == g.n and r.glob[2] == g.m
+
+
+# ------------------------------------------------- invariance (Thm. scr)
+
+@pytest.mark.parametrize("seed", [11, 12, 13])
+def test_invariance_under_free_choices(seed):
+    g = gg.plant_cliques(gg.gnp(60, 0.25, seed), [8], seed)
+    base = O.count(g, vertex=(1, 10), edge=(2, 8))
+    rng = np.random.default_rng(seed)
+    # a random acyclic orientation (any vertex order), random tie-breaks
+    key = rng.permutation(g.n).astype(np.int32)
+    prio = rng.permutation(g.n).astype(np.int32)
+    alt = O.count(g, key=key, prio=prio, vertex=(1, 10), edge=(2, 8))
+    n_top = base.omega + 1
+    assert alt.glob[:n_top] == base.glob[:n_top]
+    assert (alt.vertex == base.vertex).all()
+    assert (alt.edge == base.edge).all()
+    # relabelled graph: counts move with the labels
+    perm = rng.permutation(g.n)
+    h = gg.relabel(g, perm)
+    rel = O.count(h, vertex=(1, 10))
+    assert rel.glob[:n_top] == base.glob[:n_top]
+    assert (rel.vertex[perm] == base.vertex).all()
+
+
+def test_root_subsets_partition_the_cliques():
+    g = gg.gnp(80, 0.3, 21)
+    full = O.count(g)
+    pe = O.peel(g)
+    idx = np.arange(g.n, dtype=np.int32)
+    a = O.count(g, key=pe.sub, roots=idx[::2])
+    b = O.count(g, key=pe.sub, roots=idx[1::2])
+    for k in range(1, full.omega + 1):
+        assert a.glob[k] + b.glob[k] == full.glob[k]
+
+
+# ------------------------------------------------------------- truncation
+
+@pytest.mark.parametrize("kmax", [1, 2, 3, 5])
+def test_truncation_keeps_small_k(kmax):
+    g = gg.plant_cliques(gg.gnp(90, 0.2, 5), [10], 5)
+    full = O.count(g, vertex=(1, 6), edge=(2, 6))
+    tr = O.count(g, kmax=kmax, vertex=(1, 6), edge=(2, 6))
+    assert tr.glob[: kmax + 1] == full.glob[: kmax + 1]
+    assert all(c == 0 for c in tr.glob[kmax + 1:])
+    kv = min(kmax, 6)
+    assert (tr.vertex[:, :kv] == full.vertex[:, :kv]).all()
+    if kmax >= 2:
+        assert (tr.edge[:, : kmax - 1] == full.edge[:, : kmax - 1]).all()
+    assert tr.stats["leaves"] <= full.stats["leaves"]
+
+
+# -------------------------------------------------------- 128-bit counts
+
+def test_u128_beyond_2_64():
+    g = gg.plant_cliques(gg.gnp(200, 0.05, 9), [70], 9)
+    r = O.count(g, vertex=(30, 40))
+    assert comb(70, 35) > 2 ** 64
+    base = O.count(gg.gnp(200, 0.05, 9))
+    # planted clique dominates large k exactly
+    for k in range(20, 71):
+        assert r.glob[k] == comb(70, k)
+    assert not r.glob_ovf.any()
+    V = _vertex_ints(r)
+    assert max(V[:, 5]) == comb(69, 34)
+    assert base.omega < 20
+
+
+def test_overflow_flagged_at_2_128():
+    r = O.count(gg.complete(132))
+    assert comb(132, 66) >= 2 ** 128
+    for k in range(133):
+        big = comb(132, k) >= 2 ** 128
+        assert bool(r.glob_ovf[k]) == big, k
+        if not big:
+            assert r.glob[k] == comb(132, k)
+
+
+# -------------------------------------------------------------- the peel
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_peel_is_a_degeneracy_order(seed):
+    g = gg.chung_lu(400, 12, 2.3, 120, seed)
+    pe = O.peel(g)
+    od = O.out_degrees(g, pe.sub)
+    alpha = brute.matula_beck_degeneracy(g)
+    assert pe.alpha == alpha
+    assert od.max() == alpha
+
+
+def test_golden_wheel():
+    with open(os.path.join(HERE, "golden", "wheel_w4.json")) as f:
+        gold = json.load(f)
+    e = np.array(gold["edges"])
+    g = gg.from_edges(gold["n"], e[:, 0], e[:, 1])
+    pe = O.peel(g)
+    assert pe.sub.tolist() == gold["sub_round"]
+    assert pe.alpha == gold["degeneracy"]
+    key = pe.sub
+    for v in range(g.n):
+        nb = g.col[g.row_ptr[v]:g.row_ptr[v + 1]]
+        outs = sorted(int(u) for u in nb if (key[u], u) > (key[v], v))
+        assert outs == gold["out_neighbours"][v]
+    r = O.count(g, vertex=(3, 3), hist_dim=8)
+    assert r.glob[: len(gold["global"])] == gold["global"]
+    assert r.stats["nodes"] == gold["nodes"]
+    assert r.stats["leaves"] == gold["leaves"]
+    hist = {f"{h},{p}": int(r.hist[h, p]) for h in range(8) for p in range(8) if r.hist[h, p]}
+    assert hist == gold["leaf_hist"]
+    assert [int(x) for x in _vertex_ints(r)[:, 0]] == gold["per_vertex_k3"]
+
+
+def test_golden_pivot_tie_break():
+    with open(os.path.join(HERE, "golden", "tiebreak_7.json")) as f:
+        gold = json.load(f)
+    e = np.array(gold["edges"])
+    g = gg.from_edges(gold["n"], e[:, 0], e[:, 1])
+    r = O.count(g, key=np.array(gold["key"], dtype=np.int32), hist_dim=8)
+    assert r.glob[: len(gold["global"])] == gold["global"]
+    assert r.stats["nodes"] == gold["nodes"]
+    assert r.stats["leaves"] == gold["leaves"]
+    hist = {f"{h},{p}": int(r.hist[h, p]) for h in range(8) for p in range(8) if r.hist[h, p]}
+    assert hist == gold["leaf_hist"]
+
+
+def test_overflow_of_a_binomial_addend():
+    # leaves (1, p) for p = 0..139; addends C(p, k-1) reach 2^128 once p >= 132
+    r = O.count(gg.complete(140))
+    for k in range(141):
+        big = comb(140, k) >= 2 ** 128
+        assert bool(r.glob_ovf[k]) == big, k
+        if not big:
+            assert r.glob[k] == comb(140, k)
+
+
+@pytest.mark.parametrize("maker", [lambda: gg.star(9), lambda: gg.path(12), lambda: gg.cycle(10)])
+def test_truncation_bound_is_exact(maker):
+    # triangle-free: with kmax = 1 every root keeps only its pivot chain,
+    # so there is exactly one leaf per vertex
+    g = maker()
+    r = O.count(g, kmax=1)
+    assert r.stats["leaves"] == g.n
+    assert r.glob[1] == g.n and all(c == 0 for c in r.glob[2:])
+
+
+def test_overflow_of_a_single_leaf():
+    # only the root child of vertex 0 of K_133: one leaf (h=1, p=132), so
+    # C_{1+i} = C(132, i) and the flag can only come from the addend itself
+    r = O.count(gg.complete(133), roots=np.array([0], dtype=np.int32))
+    for i in range(133):
+        big = comb(132, i) >= 2 ** 128
+        assert bool(r.glob_ovf[1 + i]) == big, i
+        if not big:
+            assert r.glob[1 + i] == comb(132, i)
