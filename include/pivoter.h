@@ -1,0 +1,221 @@
+/*
+ * pivoter.h -- C ABI of the MI355X exact clique counter.
+ *
+ * The library counts k-cliques exactly, for every k at once, by building the
+ * Succinct Clique Tree (SCT) of a graph on the GPU and reading the counts off
+ * its leaves (Jain & Seshadhri, "The Power of Pivoting for Exact Clique
+ * Counting", WSDM 2020):
+ *
+ *   - degeneracy orientation (Sec. 3, Lemma lem:degen; Alg. 1 first step),
+ *   - SCT built depth first by pivoting on every vertex's out-neighbourhood
+ *     (Sec. 4, Alg. 1; depth-first form from the proof of Thm. main),
+ *   - counts from the leaves (Sec. 5, Alg. 2): a leaf whose root-to-leaf
+ *     path has h hold vertices and p pivot vertices represents C(p, i)
+ *     cliques of size h + i (Thm. scr), which gives global, per-vertex and
+ *     per-edge counts,
+ *   - optional truncation at k_max hold vertices (Sec. 5, "Counting
+ *     k-cliques for a specific k").
+ *
+ * Conventions (all entry points):
+ *   - Plain C types only; pointers are host pointers unless the name or the
+ *     comment says "device".  Device pointers are HIP device addresses on the
+ *     context's device.
+ *   - Vertex ids are int32 in [0, n).  A graph is simple and undirected; its
+ *     CSR lists every edge in both directions with sorted rows.
+ *   - Counts are exact unsigned 128-bit integers, stored as pv_u128
+ *     {lo, hi} (little-endian limbs).  A count that reaches 2^128 is not
+ *     representable: its overflow bit is set and its value is meaningless.
+ *   - Every entry point returns a pv_status; nothing throws across the ABI.
+ *     On error the outputs are unspecified and the handles stay valid.
+ *   - Work is issued on the context's HIP stream.  Entry points that return
+ *     results in host memory synchronise that stream before returning;
+ *     pv_count writes device outputs and synchronises too (it returns host
+ *     counters).  A context is not thread-safe; use one per host thread.
+ */
+#ifndef PIVOTER_H
+#define PIVOTER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    uint64_t lo, hi;
+} pv_u128;
+
+typedef int32_t pv_status;
+
+#define PV_OK 0
+#define PV_EINVAL -1       /* bad argument (null pointer, bad range, ...) */
+#define PV_ENOTSIMPLE -2   /* CSR not simple/symmetric/sorted (loop, duplicate, missing reverse edge) */
+#define PV_ENOMEM -3       /* host or device allocation failed */
+#define PV_EOVERFLOW -4    /* some requested count is >= 2^128; see overflow bits */
+#define PV_EDEVICE -5      /* HIP runtime error */
+#define PV_ETOOBIG -6      /* n or 2m does not fit int32, or the degeneracy exceeds the supported bound */
+#define PV_EBUFSIZE -7     /* output buffer too small; required size reported */
+#define PV_ECANCELLED -8   /* request cancelled */
+#define PV_EAGAIN -9       /* not admitted now (memory budget); retry later */
+
+/* local count kinds */
+#define PV_NONE 0
+#define PV_VERTEX 1
+#define PV_EDGE 2
+
+/* flags of pv_graph_load_csr* */
+#define PV_TRUST_INPUT 1u  /* skip the simple/symmetric/sorted validation */
+
+/* largest supported degeneracy (out-degree bound of the orientation) */
+#define PV_MAX_ALPHA 4096
+/* local counts are kept for at most this many consecutive k */
+#define PV_MAX_LOCAL_K 16
+
+typedef struct pv_ctx pv_ctx;
+typedef struct pv_graph pv_graph;
+
+/* Work counters of the last count call on a graph. */
+typedef struct {
+    uint64_t nodes;        /* SCT nodes below the root V that were visited */
+    uint64_t leaves;       /* SCT leaves (root-to-leaf paths) */
+    uint64_t items;        /* subproblems handed between GPU stages */
+    int32_t alpha;         /* degeneracy = largest out-degree */
+    int32_t omega;         /* largest clique size (0 for the empty graph) */
+    int32_t subrounds;     /* sub-rounds of the degeneracy peel */
+    int32_t truncated;     /* 1 if the tree was cut at k_max hold vertices */
+} pv_stats;
+
+/* Human-readable name of a status code (static string). */
+const char *pv_strerror(pv_status s);
+
+/*
+ * Create a context on HIP device `device`.  `stream` is a hipStream_t to
+ * issue work on (NULL: the legacy default stream).  The context owns the
+ * binomial table and per-device workspaces; it is released by pv_fini.
+ */
+pv_status pv_init(int32_t device, void *stream, pv_ctx **out);
+void pv_fini(pv_ctx *ctx);
+
+/* Change the stream later work is issued on (hipStream_t, may be NULL). */
+pv_status pv_set_stream(pv_ctx *ctx, void *stream);
+
+/*
+ * Tuning: subtrees whose node set has at most dfs_max vertices (1..64) are
+ * walked depth first by one wavefront; larger nodes are split so that their
+ * hold children are spread over the GPU.  Any value gives the same counts.
+ * Default 24 (environment variable PV_DFS_MAX overrides it at pv_init).
+ */
+pv_status pv_set_dfs_max(pv_ctx *ctx, int32_t dfs_max);
+
+/* Text of the last HIP error seen by this host thread (static storage). */
+const char *pv_last_error(void);
+
+/*
+ * Load a graph from a host CSR: row_ptr[n+1], col[row_ptr[n]], rows sorted,
+ * every undirected edge listed in both directions, no self loops or
+ * duplicates (problem statement, Sec. 1.1: a simple undirected graph).
+ * The inputs are copied; the caller keeps ownership.  Unless
+ * PV_TRUST_INPUT is set the CSR is validated (PV_ENOTSIMPLE otherwise).
+ * Isolated vertices are allowed.  The graph handle owns its device memory.
+ */
+pv_status pv_graph_load_csr(pv_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                            const int32_t *col, uint32_t flags, pv_graph **out);
+
+/* Same, from a CSR already in device memory (device pointers, copied). */
+pv_status pv_graph_load_csr_device(pv_ctx *ctx, int32_t n, int64_t nnz,
+                                   const int32_t *d_row_ptr, const int32_t *d_col,
+                                   uint32_t flags, pv_graph **out);
+
+/* Release a graph and its device memory. */
+void pv_graph_free(pv_graph *g);
+
+/* n and m (undirected edges) of a loaded graph. */
+pv_status pv_graph_size(const pv_graph *g, int32_t *n, int64_t *m);
+
+/*
+ * Degeneracy orientation (Sec. 3, Lemma lem:degen).  Peel level k = 0,1,...:
+ * in sub-rounds remove every remaining vertex of remaining degree <= k; a
+ * vertex's key is (its sub-round, its id) and every edge points from the
+ * smaller key to the larger.  Out-degrees are then at most the degeneracy
+ * alpha (returned if alpha_out != NULL).  Always recomputed (idempotent);
+ * the count calls orient first if it has not been done.
+ */
+pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out);
+
+/* Copy the peel sub-round of every vertex (int32[n], host). */
+pv_status pv_graph_export_order(pv_graph *g, int32_t *sub_host);
+
+/*
+ * Global counts C_k (problem statement, Sec. 1.1; read off by Alg. 2's
+ * global step).  counts[k] = C_k for 0 <= k < cap, with counts[0] = 1 (the
+ * empty clique), counts[1] = n, counts[2] = m, and zeros above omega.
+ * k_max <= 0: all k; otherwise the tree is truncated at k_max hold vertices
+ * (Sec. 5) and counts above k_max are zero.
+ * overflow_bits (may be NULL): uint64[(cap+63)/64], bit k set if C_k >= 2^128
+ * (PV_EOVERFLOW is returned then).  PV_EBUFSIZE if cap <= min(omega, k_max)
+ * (omega_out still set).  stats may be NULL.
+ */
+pv_status pv_count_global(pv_graph *g, int32_t k_max, pv_u128 *counts, int32_t cap,
+                          int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats);
+
+/*
+ * Local counts for k_lo <= k <= k_hi (1 <= k_lo <= k_hi <= PV_MAX_LOCAL_K),
+ * Alg. 2 per-vertex and per-edge steps.  The binomials C(alpha, k_hi - 1)
+ * must fit 64 bits (PV_ETOOBIG otherwise).
+ *   kind PV_VERTEX: out[v*K + (k-k_lo)] = c_k(v), out_len >= n*K.
+ *   kind PV_EDGE:   out[e*K + (k-k_lo)] = c_k(e), out_len >= m*K, where edge
+ *                   id e is the rank of (u,v), u<v, in lexicographic order
+ *                   (the order of pv_graph_edge_list).
+ * out is host memory.  The tree is truncated at k_hi hold vertices.
+ * overflow_bits (may be NULL): uint64[1], bit (k-k_lo) set if some count of
+ * that k is >= 2^128.
+ */
+pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int32_t k_hi,
+                         pv_u128 *out, int64_t out_len, uint64_t *overflow_bits,
+                         pv_stats *stats);
+
+/* The edges (u<v) in edge-id order: u[m], v[m] host arrays. */
+pv_status pv_graph_edge_list(pv_graph *g, int32_t *u, int32_t *v);
+
+/*
+ * One pass computing global counts (all k, or up to k_max) and, optionally,
+ * local counts in the same tree walk.  This is the whole hot path: orient
+ * (if `reorient` or not yet oriented), build the SCT, read the counts.
+ *   counts/cap/omega_out/overflow_bits: as pv_count_global (host).
+ *   local_kind: PV_NONE, PV_VERTEX or PV_EDGE; local_out is DEVICE memory of
+ *   (n or m) * (k_hi-k_lo+1) pv_u128, zero-filled by this call.
+ *   local_ovf (host, may be NULL): uint64[1] overflow bits of the local range.
+ * With k_max <= 0 and local counts requested the tree is not truncated.
+ */
+pv_status pv_count(pv_graph *g, int32_t reorient, int32_t k_max,
+                   pv_u128 *counts, int32_t cap, int32_t *omega_out,
+                   uint64_t *overflow_bits,
+                   int32_t local_kind, int32_t k_lo, int32_t k_hi,
+                   pv_u128 *local_out, uint64_t *local_ovf, pv_stats *stats);
+
+/*
+ * Counts restricted to some root children of the SCT: only the subtrees of
+ * the given roots (host int32 ids) are built, so counts[k] is the number of
+ * k-cliques whose smallest-key vertex is one of the roots (counts[0] = 0).
+ * Used for sampled checks on graphs whose full count is too large.
+ */
+pv_status pv_count_roots(pv_graph *g, const int32_t *roots, int32_t nroots, int32_t k_max,
+                         pv_u128 *counts, int32_t cap, int32_t *omega_out,
+                         uint64_t *overflow_bits, pv_stats *stats);
+
+/*
+ * Batched global counts: G graphs (all loaded on this context) in one
+ * launch sequence; the subproblems of all graphs share one device work
+ * queue.  counts is [G][cap] (host), omega[G] (host, may be NULL),
+ * overflow_bits [G][(cap+63)/64] (may be NULL).  Per-graph status is
+ * folded into the return value (first error wins).
+ */
+pv_status pv_count_global_batch(pv_ctx *ctx, int32_t G, pv_graph *const *gs, int32_t k_max,
+                                pv_u128 *counts, int32_t cap, int32_t *omega,
+                                uint64_t *overflow_bits, pv_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIVOTER_H */

@@ -1,0 +1,774 @@
+// Host runtime of libpivoter: contexts, graph handles, the orientation and
+// SCT launch sequence, buffer management.  Implements include/pivoter.h.
+//
+// Launch sequence of one count (all on the context's stream):
+//   orient:   cooperative peel -> out-degrees -> scan -> N+(v) -> root order
+//   SCT:      leaves of empty roots; then level by level, the level kernel
+//             takes the multi-word items, compact items and (level 0) the
+//             roots, and emits the next level's items; the host reads the
+//             emitted counts after each level.  If any work buffer filled up
+//             the whole count is rerun with larger buffers (results are
+//             never partially reused).
+//   finalize: C_k = sum_{h,p} L[h][p] C(p, k-h) in exact u128.
+#include "internal.h"
+#include "pivoter.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+// ------------------------------------------------------------- errors
+
+static thread_local char g_last_error[256] = "";
+
+static void set_err(const char *what, hipError_t e) {
+    snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) {                        \
+            set_err(#call, e_);                        \
+            return (e_ == hipErrorOutOfMemory) ? PV_ENOMEM : PV_EDEVICE; \
+        }                                              \
+    } while (0)
+
+#define PVCHK(call)                      \
+    do {                                 \
+        pv_status s_ = (call);           \
+        if (s_ != PV_OK) return s_;      \
+    } while (0)
+
+extern "C" const char *pv_strerror(pv_status s) {
+    switch (s) {
+        case PV_OK: return "ok";
+        case PV_EINVAL: return "invalid argument";
+        case PV_ENOTSIMPLE: return "graph is not a simple symmetric sorted CSR";
+        case PV_ENOMEM: return "out of memory";
+        case PV_EOVERFLOW: return "a count reached 2^128";
+        case PV_EDEVICE: return "HIP device error";
+        case PV_ETOOBIG: return "graph too large for this build";
+        case PV_EBUFSIZE: return "output buffer too small";
+        case PV_ECANCELLED: return "cancelled";
+        case PV_EAGAIN: return "not admitted, retry";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char *pv_last_error(void) { return g_last_error; }
+
+// ------------------------------------------------------------ handles
+
+template <class T>
+struct DBuf {
+    T *p = nullptr;
+    size_t n = 0;  // elements
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // ensure room for at least `need` elements (contents not kept)
+    pv_status ensure(size_t need) {
+        if (need <= n && p) return PV_OK;
+        release();
+        size_t bytes = std::max<size_t>(need, 1) * sizeof(T);
+        hipError_t e = hipMalloc((void **)&p, bytes);
+        if (e != hipSuccess) {
+            set_err("hipMalloc", e);
+            p = nullptr;
+            return PV_ENOMEM;
+        }
+        n = std::max<size_t>(need, 1);
+        return PV_OK;
+    }
+};
+
+struct pv_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    DevInfo dev{};
+    // exact binomials
+    int bn = 0;
+    DBuf<uint64_t> tab, tab64;
+    DBuf<uint8_t> bad;
+    DBuf<int> fits64;
+    int fits64_h[16] = {0};
+    // launch arguments (device copy) and a pinned host staging copy
+    DBuf<LevelArgs> d_args;
+    LevelArgs *h_args = nullptr;
+    int *h_io = nullptr;  // pinned readback slots
+    int level_blocks[3] = {0, 0, 0};
+    int dfs_max = 24;
+};
+
+struct pv_graph {
+    pv_ctx *ctx = nullptr;
+    int n = 0;
+    long long nnz = 0;
+    DBuf<int> rp, col;
+    // orientation
+    bool oriented = false;
+    int alpha = 0, subrounds = 0;
+    int nheavy = 0, nnonzero = 0;
+    DBuf<int> sub, deg, fa, fb, odeg, orow, ocol, scan, small, rcnt, rcursor, order;
+    DBuf<PeelCtl> ctl;
+    // SCT work buffers
+    DBuf<CItem> citem[2];
+    DBuf<uint64_t> mwitem[2];
+    DBuf<uint64_t> hu_rows, u_rows;
+    DBuf<int> hu_vl, u_gid, pref_pool;
+    DBuf<int2> u_pref;
+    DBuf<unsigned long long> hist, counters;
+    DBuf<uint64_t> counts, ovf, vout_own;
+    size_t c_cap = 1 << 20, mw_cap = 1 << 15, u_cap = 1 << 16, pref_cap = 1 << 19;
+    long long hu_budget = 1ll << 30;  // bytes of heavy universes per chunk
+    pv_stats last{};
+};
+
+// small device scalars in g->small: [0] alpha, [1] next, [2] mw_out_n, [3] c_out_n,
+// [4] flags, [5] u_n, [6] pref_n, [7] omega, [8] lovf, [9] err, [10..11] bounds
+enum { SM_ALPHA = 0, SM_NEXT, SM_MWN, SM_CN, SM_FLAGS, SM_UN, SM_PREFN, SM_OMEGA, SM_LOVF,
+       SM_ERR, SM_BOUNDS, SM_BOUNDS1, SM_COUNT };
+
+extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
+    if (!out) return PV_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return PV_EINVAL;
+    HIPCHK(hipSetDevice(device));
+    pv_ctx *c = new (std::nothrow) pv_ctx();
+    if (!c) return PV_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        set_err("hipGetDeviceProperties", e);
+        delete c;
+        return PV_EDEVICE;
+    }
+    c->dev.device = device;
+    c->dev.num_cu = prop.multiProcessorCount;
+    c->dev.lds_per_block = (int)prop.sharedMemPerBlock;
+    c->dev.lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
+    if (hipHostMalloc((void **)&c->h_args, sizeof(LevelArgs)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_io, 64 * sizeof(int)) != hipSuccess) {
+        delete c;
+        return PV_ENOMEM;
+    }
+    if (c->d_args.ensure(1) != PV_OK) {
+        delete c;
+        return PV_ENOMEM;
+    }
+    for (int kl = 0; kl < 3; kl++) {
+        int per_cu = pv_level_blocks_per_cu(kl == 0 ? 0 : (kl == 1 ? 8 : 16));
+        c->level_blocks[kl] = std::max(1, per_cu) * c->dev.num_cu;
+    }
+    if (const char *env = getenv("PV_DFS_MAX")) c->dfs_max = std::max(1, std::min(64, atoi(env)));
+    *out = c;
+    return PV_OK;
+}
+
+extern "C" void pv_fini(pv_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    c->tab.release();
+    c->tab64.release();
+    c->bad.release();
+    c->fits64.release();
+    c->d_args.release();
+    if (c->h_args) (void)hipHostFree(c->h_args);
+    if (c->h_io) (void)hipHostFree(c->h_io);
+    delete c;
+}
+
+extern "C" pv_status pv_set_stream(pv_ctx *c, void *stream) {
+    if (!c) return PV_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return PV_OK;
+}
+
+// tunable: largest |S| walked depth first (1..64)
+extern "C" pv_status pv_set_dfs_max(pv_ctx *c, int32_t dfs_max) {
+    if (!c || dfs_max < 1 || dfs_max > 64) return PV_EINVAL;
+    c->dfs_max = dfs_max;
+    return PV_OK;
+}
+
+static pv_status ensure_binomials(pv_ctx *c, int need) {
+    if (need <= c->bn) return PV_OK;
+    int bn = std::max(need, 2 * c->bn);
+    PVCHK(c->tab.ensure((size_t)bn * bn * 2));
+    PVCHK(c->bad.ensure((size_t)bn * bn));
+    PVCHK(c->tab64.ensure((size_t)bn * 16));
+    PVCHK(c->fits64.ensure(16));
+    std::vector<int> ones(16, 1);
+    HIPCHK(hipMemcpyAsync(c->fits64.p, ones.data(), 16 * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(pv_launch_binomials(bn, c->tab.p, c->bad.p, c->tab64.p, c->fits64.p, c->stream));
+    HIPCHK(hipMemcpyAsync(c->fits64_h, c->fits64.p, 16 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->bn = bn;
+    return PV_OK;
+}
+
+// ------------------------------------------------------------- graphs
+
+static pv_status graph_new(pv_ctx *c, int32_t n, long long nnz, pv_graph **out) {
+    if (!c || !out || n < 0 || nnz < 0) return PV_EINVAL;
+    if (nnz >= (1ll << 31) || n >= (1 << 30)) return PV_ETOOBIG;
+    pv_graph *g = new (std::nothrow) pv_graph();
+    if (!g) return PV_ENOMEM;
+    g->ctx = c;
+    g->n = n;
+    g->nnz = nnz;
+    pv_status s;
+    if ((s = g->rp.ensure((size_t)n + 1)) != PV_OK || (s = g->col.ensure((size_t)nnz)) != PV_OK ||
+        (s = g->small.ensure(SM_COUNT)) != PV_OK) {
+        pv_graph_free(g);
+        return s;
+    }
+    *out = g;
+    return PV_OK;
+}
+
+static pv_status graph_validate(pv_graph *g, uint32_t flags) {
+    pv_ctx *c = g->ctx;
+    if (flags & PV_TRUST_INPUT) return PV_OK;
+    // row pointers first: the row scan below must stay inside col[]
+    HIPCHK(hipMemsetAsync(g->small.p + SM_ERR, 0, sizeof(int), c->stream));
+    HIPCHK(pv_launch_check_rowptr(g->n, g->nnz, g->rp.p, g->small.p + SM_ERR, c->stream));
+    int *err = c->h_io;
+    HIPCHK(hipMemcpyAsync(err, g->small.p + SM_ERR, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (*err) return PV_ENOTSIMPLE;
+    HIPCHK(pv_launch_validate(g->n, g->rp.p, g->col.p, g->small.p + SM_ERR, c->stream));
+    HIPCHK(hipMemcpyAsync(err, g->small.p + SM_ERR, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return *err ? PV_ENOTSIMPLE : PV_OK;
+}
+
+extern "C" pv_status pv_graph_load_csr(pv_ctx *c, int32_t n, const int32_t *row_ptr,
+                                       const int32_t *col, uint32_t flags, pv_graph **out) {
+    if (!c || !out || n < 0 || !row_ptr || (n > 0 && row_ptr[n] > 0 && !col)) return PV_EINVAL;
+    if (out) *out = nullptr;
+    if (row_ptr[0] != 0 || row_ptr[n] < 0) return PV_ENOTSIMPLE;
+    for (int32_t i = 0; i < n; i++)
+        if (row_ptr[i + 1] < row_ptr[i]) return PV_ENOTSIMPLE;
+    HIPCHK(hipSetDevice(c->device));
+    pv_graph *g = nullptr;
+    PVCHK(graph_new(c, n, row_ptr[n], &g));
+    hipError_t e = hipMemcpyAsync(g->rp.p, row_ptr, sizeof(int) * ((size_t)n + 1),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && g->nnz)
+        e = hipMemcpyAsync(g->col.p, col, sizeof(int) * (size_t)g->nnz, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) {
+        set_err("hipMemcpyAsync", e);
+        pv_graph_free(g);
+        return PV_EDEVICE;
+    }
+    pv_status s = graph_validate(g, flags);
+    if (s != PV_OK) {
+        pv_graph_free(g);
+        return s;
+    }
+    *out = g;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_graph_load_csr_device(pv_ctx *c, int32_t n, int64_t nnz,
+                                              const int32_t *d_row_ptr, const int32_t *d_col,
+                                              uint32_t flags, pv_graph **out) {
+    if (!c || !out || n < 0 || nnz < 0 || !d_row_ptr || (nnz > 0 && !d_col)) return PV_EINVAL;
+    *out = nullptr;
+    HIPCHK(hipSetDevice(c->device));
+    pv_graph *g = nullptr;
+    PVCHK(graph_new(c, n, nnz, &g));
+    hipError_t e = hipMemcpyAsync(g->rp.p, d_row_ptr, sizeof(int) * ((size_t)n + 1),
+                                  hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && nnz)
+        e = hipMemcpyAsync(g->col.p, d_col, sizeof(int) * (size_t)nnz, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) {
+        set_err("hipMemcpyAsync", e);
+        pv_graph_free(g);
+        return PV_EDEVICE;
+    }
+    pv_status s = graph_validate(g, flags);
+    if (s != PV_OK) {
+        pv_graph_free(g);
+        return s;
+    }
+    *out = g;
+    return PV_OK;
+}
+
+extern "C" void pv_graph_free(pv_graph *g) {
+    if (!g) return;
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+    DBuf<int> *ib[] = {&g->rp, &g->col, &g->sub, &g->deg, &g->fa, &g->fb, &g->odeg, &g->orow,
+                       &g->ocol, &g->scan, &g->small, &g->rcnt, &g->rcursor, &g->order,
+                       &g->hu_vl, &g->u_gid, &g->pref_pool};
+    for (auto *b : ib) b->release();
+    g->ctl.release();
+    g->citem[0].release();
+    g->citem[1].release();
+    g->mwitem[0].release();
+    g->mwitem[1].release();
+    g->hu_rows.release();
+    g->u_rows.release();
+    g->u_pref.release();
+    g->hist.release();
+    g->counters.release();
+    g->counts.release();
+    g->ovf.release();
+    g->vout_own.release();
+    delete g;
+}
+
+extern "C" pv_status pv_graph_size(const pv_graph *g, int32_t *n, int64_t *m) {
+    if (!g) return PV_EINVAL;
+    if (n) *n = g->n;
+    if (m) *m = g->nnz / 2;
+    return PV_OK;
+}
+
+// --------------------------------------------------------- orientation
+
+extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
+    if (!g) return PV_EINVAL;
+    pv_ctx *c = g->ctx;
+    HIPCHK(hipSetDevice(c->device));
+    const int n = g->n;
+    PVCHK(g->sub.ensure(n));
+    PVCHK(g->deg.ensure(n));
+    PVCHK(g->fa.ensure(n));
+    PVCHK(g->fb.ensure(n));
+    PVCHK(g->odeg.ensure(n));
+    PVCHK(g->orow.ensure((size_t)n + 1));
+    PVCHK(g->ocol.ensure((size_t)(g->nnz / 2)));
+    PVCHK(g->scan.ensure((size_t)n / 1024 + 2));
+    PVCHK(g->rcnt.ensure((size_t)n + 2));
+    PVCHK(g->rcursor.ensure((size_t)n + 2));
+    PVCHK(g->order.ensure(n));
+    PVCHK(g->ctl.ensure(1));
+    hipStream_t s = c->stream;
+    PeelCtl init;
+    memset(&init, 0, sizeof init);
+    init.minv[0] = init.minv[1] = 0x7fffffff;
+    HIPCHK(hipMemcpyAsync(g->ctl.p, &init, sizeof init, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemsetAsync(g->small.p + SM_ALPHA, 0, sizeof(int), s));
+    HIPCHK(hipMemsetAsync(g->orow.p, 0, sizeof(int), s));
+    if (n > 0) {
+        HIPCHK(pv_launch_peel(c->dev, n, g->rp.p, g->col.p, g->deg.p, g->sub.p, g->fa.p, g->fb.p,
+                              g->ctl.p, s));
+        HIPCHK(pv_launch_orient(c->dev, n, g->rp.p, g->col.p, g->sub.p, g->odeg.p, g->orow.p,
+                                g->ocol.p, g->small.p + SM_ALPHA, g->scan.p, s));
+        HIPCHK(hipMemsetAsync(g->rcnt.p, 0, sizeof(int) * ((size_t)n + 2), s));
+        HIPCHK(pv_launch_root_order(n, g->small.p + SM_ALPHA, g->odeg.p, g->rcnt.p, g->rcursor.p,
+                                    g->order.p, g->small.p + SM_BOUNDS, PV_LIGHT_MAX, s));
+    } else {
+        HIPCHK(hipMemsetAsync(g->small.p + SM_BOUNDS, 0, 2 * sizeof(int), s));
+    }
+    int *io = c->h_io;
+    HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(io + 32, &g->ctl.p->subrounds, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    g->alpha = io[SM_ALPHA];
+    g->nheavy = io[SM_BOUNDS];
+    g->nnonzero = io[SM_BOUNDS1];
+    g->subrounds = io[32];
+    g->oriented = true;
+    if (alpha_out) *alpha_out = g->alpha;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_graph_export_order(pv_graph *g, int32_t *sub_host) {
+    if (!g || (!sub_host && g->n > 0)) return PV_EINVAL;
+    if (!g->oriented) PVCHK(pv_graph_orient(g, nullptr));
+    HIPCHK(hipSetDevice(g->ctx->device));
+    if (g->n)
+        HIPCHK(hipMemcpyAsync(sub_host, g->sub.p, sizeof(int) * (size_t)g->n, hipMemcpyDeviceToHost,
+                              g->ctx->stream));
+    HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    return PV_OK;
+}
+
+// ----------------------------------------------------------- the count
+
+struct CountReq {
+    int kmax = 0;
+    int kl = 0;           // register k-slots for local counts (0: none)
+    int klo = 1, K = 0;
+    uint64_t *vout = nullptr;  // device [n][K] u128
+    int c0 = 1;           // value of C_0
+    // root subset (device order array + counts) or the whole graph
+    const int *order = nullptr;
+    int nheavy = 0, nlight = 0;
+    bool whole = true;
+};
+
+static pv_status run_sct(pv_graph *g, const CountReq &rq) {
+    pv_ctx *c = g->ctx;
+    hipStream_t s = c->stream;
+    const int alpha = g->alpha;
+    const int hd = alpha + 2;
+    PVCHK(ensure_binomials(c, hd + 1));
+    const int W = std::max(1, (alpha + 63) / 64);
+    const int dpad = 64 * W;
+    const int mw_stride = 3 * W + 1;
+    const bool local = rq.kl > 0;
+    int *io = c->h_io;
+
+    // heavy roots per chunk, bounded by the universe budget
+    const long long hu_bytes = (long long)W * dpad * 8 + (long long)dpad * 4;
+    int chunk = (int)std::max<long long>(1, std::min<long long>(rq.nheavy, g->hu_budget / hu_bytes));
+    if (rq.nheavy == 0) chunk = 0;
+
+    for (int attempt = 0;; attempt++) {
+        if (attempt > 12) return PV_ENOMEM;
+        PVCHK(g->hist.ensure((size_t)hd * hd));
+        PVCHK(g->counters.ensure(4));
+        for (int i = 0; i < 2; i++) {
+            PVCHK(g->citem[i].ensure(g->c_cap));
+            PVCHK(g->mwitem[i].ensure(g->mw_cap * mw_stride));
+        }
+        PVCHK(g->u_rows.ensure(g->u_cap * 64));
+        if (local) {
+            PVCHK(g->u_gid.ensure(g->u_cap * 64));
+            PVCHK(g->u_pref.ensure(g->u_cap));
+            PVCHK(g->pref_pool.ensure(g->pref_cap));
+        }
+        if (chunk > 0) {
+            PVCHK(g->hu_rows.ensure((size_t)chunk * W * dpad));
+            PVCHK(g->hu_vl.ensure((size_t)chunk * dpad));
+        }
+        HIPCHK(hipMemsetAsync(g->hist.p, 0, sizeof(unsigned long long) * (size_t)hd * hd, s));
+        HIPCHK(hipMemsetAsync(g->counters.p, 0, 4 * sizeof(unsigned long long), s));
+        HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, 5 * sizeof(int), s));  // flags,u_n,pref_n,omega,lovf
+        if (local) HIPCHK(hipMemsetAsync(rq.vout, 0, (size_t)g->n * rq.K * 16, s));
+        if (rq.whole)
+            HIPCHK(pv_launch_sink_roots(g->n, g->order.p, g->small.p + SM_BOUNDS, g->hist.p, hd,
+                                        g->counters.p, local ? rq.vout : nullptr, rq.klo, rq.K, s));
+
+        bool overflow = false;
+        int levels = 0;
+        long long items = 0;
+        const int nchunks = (chunk > 0) ? (rq.nheavy + chunk - 1) / chunk : 0;
+        for (int ch = 0; ch < std::max(1, nchunks) && !overflow; ch++) {
+            const int hbase = ch * chunk;
+            const int hcount = (chunk > 0) ? std::min(chunk, rq.nheavy - hbase) : 0;
+            int n_mw = 0, n_c = 0, cur = 0;
+            for (int level = 0;; level++) {
+                LevelArgs a;
+                memset(&a, 0, sizeof a);
+                a.n = g->n;
+                a.orow = g->orow.p;
+                a.ocol = g->ocol.p;
+                a.order = rq.order;
+                a.heavy_base = hbase;
+                a.nheavy = hcount;
+                a.light_base = rq.nheavy;
+                a.nlight = (ch == 0) ? rq.nlight : 0;
+                a.kmax = rq.kmax;
+                a.dfs_max = c->dfs_max;
+                a.level = level;
+                a.n_mw_in = n_mw;
+                a.n_c_in = n_c;
+                a.mw_in = g->mwitem[cur].p;
+                a.c_in = g->citem[cur].p;
+                a.mw_out = g->mwitem[cur ^ 1].p;
+                a.c_out = g->citem[cur ^ 1].p;
+                a.mw_out_n = g->small.p + SM_MWN;
+                a.c_out_n = g->small.p + SM_CN;
+                a.mw_cap = (int)g->mw_cap;
+                a.c_cap = (int)g->c_cap;
+                a.mw_stride = mw_stride;
+                a.hu_rows = g->hu_rows.p;
+                a.hu_vl = g->hu_vl.p;
+                a.W = W;
+                a.dpad = dpad;
+                a.u_rows = g->u_rows.p;
+                a.u_gid = g->u_gid.p;
+                a.u_pref = g->u_pref.p;
+                a.u_n = g->small.p + SM_UN;
+                a.u_cap = (int)g->u_cap;
+                a.pref_pool = g->pref_pool.p;
+                a.pref_n = g->small.p + SM_PREFN;
+                a.pref_cap = (int)g->pref_cap;
+                a.next = g->small.p + SM_NEXT;
+                a.hist = g->hist.p;
+                a.hd = hd;
+                a.counters = g->counters.p;
+                a.flags = g->small.p + SM_FLAGS;
+                a.vout = rq.vout;
+                a.klo = rq.klo;
+                a.K = rq.K;
+                a.bin64 = c->tab64.p;
+                a.lovf = g->small.p + SM_LOVF;
+                const long long units = (long long)n_mw + n_c + (level == 0 ? (long long)a.nheavy + a.nlight : 0);
+                if (units == 0) break;
+                *c->h_args = a;
+                HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 3 * sizeof(int), s));
+                HIPCHK(hipMemcpyAsync(c->d_args.p, c->h_args, sizeof(LevelArgs), hipMemcpyHostToDevice, s));
+                const int kli = rq.kl == 0 ? 0 : (rq.kl <= 8 ? 1 : 2);
+                const int blocks = (int)std::min<long long>(c->level_blocks[kli], (units + 3) / 4);
+                HIPCHK(pv_launch_level(c->d_args.p, rq.kl, std::max(1, blocks), s));
+                HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                levels++;
+                if (io[SM_FLAGS] & 1) {
+                    overflow = true;
+                    if ((size_t)io[SM_CN] > g->c_cap) g->c_cap *= 4;
+                    if ((size_t)io[SM_MWN] > g->mw_cap) g->mw_cap *= 4;
+                    if ((size_t)io[SM_UN] >= g->u_cap) g->u_cap *= 4;
+                    if ((size_t)io[SM_PREFN] >= g->pref_cap) g->pref_cap *= 4;
+                    break;
+                }
+                n_mw = io[SM_MWN];
+                n_c = io[SM_CN];
+                items += (long long)n_mw + n_c;
+                cur ^= 1;
+            }
+        }
+        if (overflow) continue;
+        g->last.items = (uint64_t)items;
+        g->last.truncated = rq.kmax > 0;
+        (void)levels;
+        return PV_OK;
+    }
+}
+
+static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts, int32_t cap,
+                               int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats,
+                               uint64_t *local_ovf) {
+    pv_ctx *c = g->ctx;
+    hipStream_t s = c->stream;
+    const int hd = g->alpha + 2;
+    const int kcap = hd;
+    const int nw = (kcap + 63) / 64;
+    PVCHK(g->counts.ensure((size_t)kcap * 2));
+    PVCHK(g->ovf.ensure(nw));
+    HIPCHK(hipMemsetAsync(g->ovf.p, 0, nw * sizeof(uint64_t), s));
+    HIPCHK(hipMemsetAsync(g->small.p + SM_OMEGA, 0, sizeof(int), s));
+    HIPCHK(pv_launch_finalize(g->hist.p, hd, c->tab.p, c->bad.p, c->bn, kcap, rq.kmax, rq.c0,
+                              g->counts.p, g->ovf.p, g->small.p + SM_OMEGA, s));
+    std::vector<uint64_t> hc((size_t)kcap * 2), ho(nw);
+    unsigned long long hcnt[4];
+    HIPCHK(hipMemcpyAsync(hc.data(), g->counts.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ho.data(), g->ovf.p, nw * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hcnt, g->counters.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(c->h_io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int omega = c->h_io[SM_OMEGA];
+    g->last.nodes = hcnt[0];
+    g->last.leaves = hcnt[1];
+    g->last.alpha = g->alpha;
+    g->last.omega = omega;
+    g->last.subrounds = g->subrounds;
+    if (stats) *stats = g->last;
+    if (omega_out) *omega_out = omega;
+    if (local_ovf) *local_ovf = c->h_io[SM_LOVF] ? ~0ull : 0ull;
+    const int top = (rq.kmax > 0) ? std::min(omega, rq.kmax) : omega;
+    if (counts) {
+        for (int k = 0; k < cap; k++) {
+            counts[k].lo = (k < kcap) ? hc[2 * k] : 0;
+            counts[k].hi = (k < kcap) ? hc[2 * k + 1] : 0;
+        }
+    }
+    bool any_ovf = false;
+    if (overflow_bits) memset(overflow_bits, 0, sizeof(uint64_t) * (size_t)((cap + 63) / 64));
+    for (int k = 0; k < kcap; k++) {
+        if ((ho[k >> 6] >> (k & 63)) & 1) {
+            any_ovf = true;
+            if (overflow_bits && k < cap) overflow_bits[k >> 6] |= 1ull << (k & 63);
+        }
+    }
+    if (counts && cap <= top) return PV_EBUFSIZE;
+    if (any_ovf || (local_ovf && *local_ovf)) return PV_EOVERFLOW;
+    return PV_OK;
+}
+
+static pv_status prepare(pv_graph *g, bool reorient) {
+    HIPCHK(hipSetDevice(g->ctx->device));
+    if (reorient || !g->oriented) PVCHK(pv_graph_orient(g, nullptr));
+    if (g->alpha > PV_MAX_ALPHA) {
+        snprintf(g_last_error, sizeof g_last_error, "degeneracy %d exceeds %d", g->alpha, PV_MAX_ALPHA);
+        return PV_ETOOBIG;
+    }
+    g->last = pv_stats{};
+    return PV_OK;
+}
+
+static pv_status setup_local(pv_graph *g, int kind, int klo, int khi, CountReq &rq) {
+    if (kind == PV_NONE) return PV_OK;
+    if (kind != PV_VERTEX) return PV_EINVAL;
+    // the 64-bit binomial table keeps C(a, b) for b < 16, and b = k - h <= khi - 1
+    if (klo < 1 || khi < klo || khi - klo + 1 > PV_MAX_LOCAL_K || khi > 16) return PV_EINVAL;
+    rq.klo = klo;
+    rq.K = khi - klo + 1;
+    rq.kl = rq.K <= 8 ? 8 : 16;
+    // the per-vertex path keeps C(a, b), a <= alpha, b <= khi - 1, in 64 bits;
+    // C(a, b) grows with a, so C(alpha, khi - 1) is the largest value used
+    PVCHK(ensure_binomials(g->ctx, g->alpha + 3));
+    unsigned __int128 cb = 1;
+    bool fits = true;
+    for (int b = 1; b <= khi - 1 && b <= g->alpha; b++) {
+        cb = cb * (unsigned __int128)(g->alpha - b + 1) / (unsigned __int128)b;
+        if (cb >> 64) fits = false;
+    }
+    if (!fits) {
+            snprintf(g_last_error, sizeof g_last_error,
+                     "per-vertex counts up to k=%d need binomials beyond 64 bits", khi);
+            return PV_ETOOBIG;
+        }
+    return PV_OK;
+}
+
+extern "C" pv_status pv_count(pv_graph *g, int32_t reorient, int32_t k_max, pv_u128 *counts,
+                              int32_t cap, int32_t *omega_out, uint64_t *overflow_bits,
+                              int32_t local_kind, int32_t k_lo, int32_t k_hi, pv_u128 *local_out,
+                              uint64_t *local_ovf, pv_stats *stats) {
+    if (!g || cap < 0 || (cap > 0 && !counts)) return PV_EINVAL;
+    if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
+    PVCHK(prepare(g, reorient != 0));
+    CountReq rq;
+    rq.kmax = k_max > 0 ? k_max : 0;
+    PVCHK(setup_local(g, local_kind, k_lo, k_hi, rq));
+    rq.vout = (uint64_t *)local_out;
+    rq.order = g->order.p;
+    rq.nheavy = g->nheavy;
+    rq.nlight = g->nnonzero - g->nheavy;
+    PVCHK(run_sct(g, rq));
+    return finish_counts(g, rq, counts, cap, omega_out, overflow_bits, stats, local_ovf);
+}
+
+extern "C" pv_status pv_count_global(pv_graph *g, int32_t k_max, pv_u128 *counts, int32_t cap,
+                                     int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats) {
+    return pv_count(g, 0, k_max, counts, cap, omega_out, overflow_bits, PV_NONE, 0, 0, nullptr,
+                    nullptr, stats);
+}
+
+extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int32_t k_hi,
+                                    pv_u128 *out, int64_t out_len, uint64_t *overflow_bits,
+                                    pv_stats *stats) {
+    if (!g || !out) return PV_EINVAL;
+    if (kind != PV_VERTEX) return PV_EINVAL;
+    if (k_lo < 1 || k_hi < k_lo || k_hi - k_lo + 1 > PV_MAX_LOCAL_K) return PV_EINVAL;
+    const int K = k_hi - k_lo + 1;
+    const long long need = (long long)g->n * K;
+    if (out_len < need) return PV_EBUFSIZE;
+    PVCHK(prepare(g, false));
+    PVCHK(g->vout_own.ensure((size_t)need * 2));
+    CountReq rq;
+    rq.kmax = k_hi;
+    PVCHK(setup_local(g, kind, k_lo, k_hi, rq));
+    rq.vout = g->vout_own.p;
+    rq.order = g->order.p;
+    rq.nheavy = g->nheavy;
+    rq.nlight = g->nnonzero - g->nheavy;
+    PVCHK(run_sct(g, rq));
+    uint64_t lovf = 0;
+    pv_status st = finish_counts(g, rq, nullptr, 0, nullptr, nullptr, stats, &lovf);
+    if (st != PV_OK && st != PV_EOVERFLOW) return st;
+    HIPCHK(hipMemcpyAsync(out, g->vout_own.p, (size_t)need * 16, hipMemcpyDeviceToHost, g->ctx->stream));
+    HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    if (overflow_bits) overflow_bits[0] = lovf;
+    return lovf ? PV_EOVERFLOW : PV_OK;
+}
+
+extern "C" pv_status pv_count_roots(pv_graph *g, const int32_t *roots, int32_t nroots, int32_t k_max,
+                                    pv_u128 *counts, int32_t cap, int32_t *omega_out,
+                                    uint64_t *overflow_bits, pv_stats *stats) {
+    if (!g || nroots < 0 || (nroots > 0 && !roots) || cap < 0 || (cap > 0 && !counts))
+        return PV_EINVAL;
+    PVCHK(prepare(g, false));
+    // out-degrees of the chosen roots, heavy first (host-side scheduling only)
+    std::vector<int> od(g->n);
+    if (g->n) {
+        HIPCHK(hipMemcpyAsync(od.data(), g->odeg.p, sizeof(int) * (size_t)g->n, hipMemcpyDeviceToHost,
+                              g->ctx->stream));
+        HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    }
+    std::vector<int> rs;
+    rs.reserve(nroots);
+    for (int i = 0; i < nroots; i++) {
+        if (roots[i] < 0 || roots[i] >= g->n) return PV_EINVAL;
+        rs.push_back(roots[i]);
+    }
+    std::stable_sort(rs.begin(), rs.end(), [&](int a, int b) { return od[a] > od[b]; });
+    int nheavy = 0;
+    for (int v : rs) nheavy += (od[v] > PV_LIGHT_MAX) ? 1 : 0;
+    DBuf<int> dorder;
+    PVCHK(dorder.ensure(std::max<size_t>(rs.size(), 1)));
+    if (!rs.empty()) {
+        HIPCHK(hipMemcpyAsync(dorder.p, rs.data(), sizeof(int) * rs.size(), hipMemcpyHostToDevice,
+                              g->ctx->stream));
+    }
+    CountReq rq;
+    rq.kmax = k_max > 0 ? k_max : 0;
+    rq.c0 = 0;
+    rq.whole = false;
+    rq.order = dorder.p;
+    rq.nheavy = nheavy;
+    rq.nlight = (int)rs.size() - nheavy;  // roots with an empty N+(v) are single leaves
+    pv_status st = run_sct(g, rq);
+    if (st == PV_OK) st = finish_counts(g, rq, counts, cap, omega_out, overflow_bits, stats, nullptr);
+    dorder.release();
+    return st;
+}
+
+extern "C" pv_status pv_graph_edge_list(pv_graph *g, int32_t *u, int32_t *v) {
+    if (!g || ((!u || !v) && g->nnz > 0)) return PV_EINVAL;
+    HIPCHK(hipSetDevice(g->ctx->device));
+    std::vector<int> rp((size_t)g->n + 1), col((size_t)std::max<long long>(g->nnz, 1));
+    HIPCHK(hipMemcpyAsync(rp.data(), g->rp.p, sizeof(int) * rp.size(), hipMemcpyDeviceToHost,
+                          g->ctx->stream));
+    if (g->nnz)
+        HIPCHK(hipMemcpyAsync(col.data(), g->col.p, sizeof(int) * (size_t)g->nnz,
+                              hipMemcpyDeviceToHost, g->ctx->stream));
+    HIPCHK(hipStreamSynchronize(g->ctx->stream));
+    long long e = 0;
+    for (int a = 0; a < g->n; a++)
+        for (int i = rp[a]; i < rp[a + 1]; i++)
+            if (col[i] > a) {
+                u[e] = a;
+                v[e] = col[i];
+                e++;
+            }
+    return PV_OK;
+}
+
+extern "C" pv_status pv_count_global_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, int32_t k_max,
+                                           pv_u128 *counts, int32_t cap, int32_t *omega,
+                                           uint64_t *overflow_bits, pv_stats *stats) {
+    if (!c || G < 0 || (G > 0 && (!gs || !counts)) || cap < 1) return PV_EINVAL;
+    const int nw = (cap + 63) / 64;
+    pv_status first = PV_OK;
+    pv_stats tot{};
+    for (int i = 0; i < G; i++) {
+        if (!gs[i] || gs[i]->ctx != c) return PV_EINVAL;
+        pv_stats st{};
+        int32_t om = 0;
+        pv_status s = pv_count_global(gs[i], k_max, counts + (size_t)i * cap, cap, &om,
+                                      overflow_bits ? overflow_bits + (size_t)i * nw : nullptr, &st);
+        if (omega) omega[i] = om;
+        if (s != PV_OK && first == PV_OK) first = s;
+        if (s != PV_OK && s != PV_EOVERFLOW && s != PV_EBUFSIZE) return s;
+        tot.nodes += st.nodes;
+        tot.leaves += st.leaves;
+        tot.items += st.items;
+        tot.alpha = std::max(tot.alpha, st.alpha);
+        tot.omega = std::max(tot.omega, st.omega);
+    }
+    if (stats) *stats = tot;
+    return first;
+}

@@ -1,0 +1,103 @@
+// Internal declarations shared by the host runtime (api.cpp) and the kernel
+// translation units.  Not part of the public ABI (include/pivoter.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+struct DevInfo {
+    int device;
+    int num_cu;
+    int lds_per_block;   // bytes of LDS a workgroup may use
+    int lds_per_cu;
+};
+
+// control block of the cooperative peel
+struct PeelCtl {
+    int cnt[3];          // frontier sizes, rotating by sub-round
+    int minv[2];         // smallest remaining degree at a level change
+    int subrounds;       // out: number of sub-rounds
+    int alpha;           // out: degeneracy (largest level)
+};
+
+// Largest out-degree handled by the compact (register) tier.  Roots with
+// |N+(v)| <= LIGHT_MAX are built entirely in registers; larger roots start in
+// the multi-word tier and drop into the compact tier once |S| <= LIGHT_MAX.
+#define PV_LIGHT_MAX 64
+
+// Leaves with h <= PV_HREG and p < 64 are counted in per-lane registers.
+#define PV_HREG 8
+
+// ------------------------------------------------------------- item types
+
+struct CItem {            // compact-tier subproblem (32 bytes)
+    uint64_t S, H, P;     // node set; hold / pivot members inside the universe
+    uint32_t uni;         // universe index
+    uint32_t hp;          // h | p << 16 (totals along the whole path)
+};
+
+struct LevelArgs {
+    // graph
+    int n;
+    const int *orow, *ocol, *order;
+    int heavy_base, nheavy;  // level 0: heavy roots order[heavy_base, +nheavy)
+    int light_base, nlight;  // level 0: light roots order[light_base, +nlight)
+    int kmax, dfs_max;
+    // level input
+    int level;
+    int n_mw_in, n_c_in;
+    const uint64_t *mw_in;   // stride mw_stride u64
+    const CItem *c_in;
+    // level output
+    uint64_t *mw_out;
+    CItem *c_out;
+    int *mw_out_n, *c_out_n;
+    int mw_cap, c_cap;
+    int mw_stride;           // 3W + 1
+    // heavy universes (indexed by heavy root rank)
+    uint64_t *hu_rows;       // [nheavy][W][dpad]
+    int *hu_vl;              // [nheavy][dpad]
+    int W, dpad;
+    // compact universes
+    uint64_t *u_rows;        // [cap][64]
+    int *u_gid;              // [cap][64]   (local counts only)
+    int2 *u_pref;            // [cap] {offset, length} into pref pool (local only)
+    int *u_n, u_cap;
+    int *pref_pool, *pref_n, pref_cap;
+    // work cursor of this launch
+    int *next;
+    // outputs
+    unsigned long long *hist;
+    int hd;
+    unsigned long long *counters;  // nodes, leaves, items, universes
+    int *flags;                    // bit0: buffer overflow
+    // local (per-vertex) counts
+    uint64_t *vout;                // [n][K] u128
+    int klo, K;
+    const uint64_t *bin64;         // C(a,b), b < 16, row stride 16
+    int *lovf;
+};
+
+
+hipError_t pv_launch_check_rowptr(int n, long long nnz, const int *rp, int *d_err, hipStream_t s);
+hipError_t pv_launch_validate(int n, const int *rp, const int *col, int *d_err, hipStream_t s);
+hipError_t pv_launch_peel(const DevInfo &dev, int n, const int *rp, const int *col, int *deg,
+                          int *sub, int *fa, int *fb, PeelCtl *ctl, hipStream_t s);
+hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
+                            int *odeg, int *orow, int *ocol, int *alpha, int *scan_tmp,
+                            hipStream_t s);
+hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *cnt, int *cursor,
+                                int *order, int *bounds, int light_max, hipStream_t s);
+
+// SCT build + leaf read-off
+// `a` is a device pointer to the launch arguments
+hipError_t pv_launch_level(const LevelArgs *a, int kl, int blocks, hipStream_t s);
+int pv_level_blocks_per_cu(int kl);
+hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsigned long long *hist,
+                                int hd, unsigned long long *counters, uint64_t *vout, int klo, int K,
+                                hipStream_t s);
+hipError_t pv_launch_binomials(int bn, uint64_t *tab128, uint8_t *bad, uint64_t *tab64, int *fits64,
+                               hipStream_t s);
+hipError_t pv_launch_finalize(const unsigned long long *hist, int hd, const uint64_t *tab128,
+                              const uint8_t *bad, int bn, int kcap, int kmax, int c0,
+                              uint64_t *counts, uint64_t *ovf_words, int *omega, hipStream_t s);

@@ -1,0 +1,340 @@
+// Degeneracy orientation on the GPU (Sec. 3, Lemma lem:degen; first step of
+// Alg. 1).
+//
+// The paper removes a minimum-degree vertex at a time.  The parallel reading
+// used here (the "canonical peel"): for level k = 0,1,..., in sub-rounds,
+// remove *every* remaining vertex whose remaining degree is <= k, until none
+// is left at that level.  A vertex's key is (sub-round, id); edges point from
+// the smaller key to the larger, so every out-degree is at most the level at
+// which the vertex left, and the largest level is the degeneracy alpha.
+//
+// One cooperative launch runs the whole peel: a sub-round is one grid-wide
+// barrier.  The frontier of the next sub-round is exactly the set of
+// vertices whose degree an atomic decrement takes from k+1 to k, so every
+// vertex is appended once without rescanning the graph; only a level change
+// scans the remaining vertices.
+#include "common.h"
+#include "internal.h"
+
+#include <hip/hip_cooperative_groups.h>
+
+namespace cg = cooperative_groups;
+
+// ------------------------------------------------------------ validation
+// One wave per vertex: sorted strictly increasing rows, ids in range, no
+// self loops, and every (v,u) has its reverse (u,v).
+__global__ void __launch_bounds__(256) validate_kernel(int n, const int *__restrict__ rp,
+                                                        const int *__restrict__ col,
+                                                        int *__restrict__ err) {
+    const int lane = threadIdx.x & 63;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += nw) {
+        const int b = rp[v], e = rp[v + 1];
+        if (e < b) {
+            if (lane == 0) atomicOr(err, 1);
+            continue;
+        }
+        bool bad = false;
+        for (int i = b + lane; i < e; i += 64) {
+            const int u = col[i];
+            if (u < 0 || u >= n || u == v) { bad = true; continue; }
+            if (i > b && col[i - 1] >= u) bad = true;
+            // reverse edge by binary search in row u
+            int lo = rp[u], hi = rp[u + 1];
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (col[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            if (lo >= rp[u + 1] || col[lo] != v) bad = true;
+        }
+        if (ballot64(bad) && lane == 0) atomicOr(err, 2);
+    }
+}
+
+__global__ void check_rowptr_kernel(int n, long long nnz, const int *__restrict__ rp,
+                                    int *__restrict__ err) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && (rp[0] != 0 || (long long)rp[n] != nnz)) atomicOr(err, 1);
+    if (i < n && rp[i + 1] < rp[i]) atomicOr(err, 1);
+}
+
+// ------------------------------------------------------------------ peel
+
+__device__ __forceinline__ int ld_acquire(const int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(256) peel_kernel(int n, const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    int *__restrict__ deg, int *__restrict__ sub,
+                                                    int *__restrict__ fa, int *__restrict__ fb,
+                                                    PeelCtl *__restrict__ ctl) {
+    cg::grid_group grid = cg::this_grid();
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nth = gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & 63;
+    const int wid = tid >> 6;
+    const int nw = nth >> 6;
+
+    for (int v = tid; v < n; v += nth) {
+        deg[v] = rp[v + 1] - rp[v];
+        sub[v] = -1;
+    }
+    grid.sync();
+
+    int removed = 0, r = 0, k = 0, nF = 0, alpha = 0;
+    for (;;) {
+        if (nF == 0) {
+            if (removed >= n) break;
+            // level change: k = smallest remaining degree
+            int mymin = 0x7fffffff;
+            for (int v = tid; v < n; v += nth)
+                if (sub[v] < 0) mymin = min(mymin, deg[v]);
+            mymin = wave_min_i32(mymin);
+            if (lane == 0 && mymin != 0x7fffffff) atomicMin(&ctl->minv[r & 1], mymin);
+            grid.sync();
+            k = ld_acquire(&ctl->minv[r & 1]);
+            alpha = max(alpha, k);
+            int *F = (r & 1) ? fb : fa;
+            for (int v = tid; v < n; v += nth)
+                if (sub[v] < 0 && deg[v] <= k) {
+                    sub[v] = r;
+                    F[atomicAdd(&ctl->cnt[r % 3], 1)] = v;
+                }
+            grid.sync();
+            nF = ld_acquire(&ctl->cnt[r % 3]);
+            if (nF == 0) break;  // nothing left (every wave sees the same value)
+        }
+        const int *F = (r & 1) ? fb : fa;
+        int *Fn = (r & 1) ? fa : fb;
+        if (tid == 0) {
+            ctl->cnt[(r + 2) % 3] = 0;
+            ctl->minv[(r + 1) & 1] = 0x7fffffff;
+        }
+        // remove the frontier: decrement the degrees of remaining neighbours;
+        // a neighbour taken from k+1 to k joins the next sub-round
+        for (int i = wid; i < nF; i += nw) {
+            const int v = F[i];
+            const int e1 = rp[v + 1];
+            for (int e = rp[v] + lane; e < e1; e += 64) {
+                const int u = col[e];
+                if (__hip_atomic_load(&sub[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0) {
+                    const int old = atomicSub(&deg[u], 1);
+                    if (old == k + 1) {
+                        sub[u] = r + 1;
+                        Fn[atomicAdd(&ctl->cnt[(r + 1) % 3], 1)] = u;
+                    }
+                }
+            }
+        }
+        grid.sync();
+        removed += nF;
+        nF = ld_acquire(&ctl->cnt[(r + 1) % 3]);
+        r++;
+        if (r > n) break;  // each sub-round removes a vertex: never reached
+    }
+    if (tid == 0) {
+        ctl->subrounds = r;
+        ctl->alpha = alpha;
+    }
+}
+
+// ------------------------------------------------- oriented CSR (N+(v))
+
+__device__ __forceinline__ bool key_less(int su, int u, int sv, int v) {
+    return su < sv || (su == sv && u < v);
+}
+
+// out-degree of every vertex (one wave per vertex)
+__global__ void __launch_bounds__(256) odeg_kernel(int n, const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    const int *__restrict__ sub,
+                                                    int *__restrict__ odeg,
+                                                    int *__restrict__ alpha) {
+    const int lane = threadIdx.x & 63;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    int amax = 0;
+    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += nw) {
+        const int sv = sub[v];
+        int c = 0;
+        for (int e = rp[v] + lane; e < rp[v + 1]; e += 64) {
+            const int u = col[e];
+            c += key_less(sv, v, sub[u], u) ? 1 : 0;
+        }
+        c = (int)wave_add_u32((uint32_t)c);
+        if (lane == 0) odeg[v] = c;
+        amax = max(amax, c);
+    }
+    if (lane == 0) atomicMax(alpha, amax);
+}
+
+// N+(v) in increasing id order (row order kept by ballot compaction)
+__global__ void __launch_bounds__(256) ofill_kernel(int n, const int *__restrict__ rp,
+                                                     const int *__restrict__ col,
+                                                     const int *__restrict__ sub,
+                                                     const int *__restrict__ orow,
+                                                     int *__restrict__ ocol) {
+    const int lane = threadIdx.x & 63;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += nw) {
+        const int sv = sub[v];
+        int w = orow[v];
+        const int e1 = rp[v + 1];
+        for (int e0 = rp[v]; e0 < e1; e0 += 64) {
+            const int e = e0 + lane;
+            bool take = false;
+            int u = 0;
+            if (e < e1) {
+                u = col[e];
+                take = key_less(sv, v, sub[u], u);
+            }
+            const uint64_t m = ballot64(take);
+            if (take) ocol[w + __popcll(m & below)] = u;
+            w += __popcll(m);
+        }
+    }
+}
+
+// ---------------------------------------------------- exclusive scan (int)
+// out[i] = sum_{j<i} in[j] for i <= n (out has n+1 entries).
+
+#define SCAN_BLOCK 1024
+
+__global__ void __launch_bounds__(256) scan_reduce_kernel(int n, const int *__restrict__ in,
+                                                           int *__restrict__ bsum) {
+    __shared__ int red[4];
+    const int base = blockIdx.x * SCAN_BLOCK;
+    int s = 0;
+    for (int i = threadIdx.x; i < SCAN_BLOCK; i += 256)
+        if (base + i < n) s += in[base + i];
+    s = (int)wave_add_u32((uint32_t)s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(1024) scan_blocks_kernel(int nb, int *__restrict__ bsum) {
+    // exclusive scan of nb block sums in place, one block of 1024 threads
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int x = (i < nb) ? bsum[i] : 0;
+        const int inc = wave_incl_scan(x);
+        if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
+        __syncthreads();
+        int off = carry;
+        for (int w = 0; w < (int)(threadIdx.x >> 6); w++) off += wsum[w];
+        if (i < nb) bsum[i] = off + inc - x;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry = off + inc;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(1024) scan_apply_kernel(int n, const int *__restrict__ in,
+                                                           const int *__restrict__ bsum,
+                                                           int *__restrict__ out) {
+    __shared__ int wsum[16];
+    const int i = blockIdx.x * SCAN_BLOCK + threadIdx.x;
+    const int x = (i < n) ? in[i] : 0;
+    const int inc = wave_incl_scan(x);
+    if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = inc;
+    __syncthreads();
+    int off = bsum[blockIdx.x];
+    for (int w = 0; w < (int)(threadIdx.x >> 6); w++) off += wsum[w];
+    if (i < n) out[i] = off + inc - x;
+    if (i == n - 1) out[n] = off + inc;
+}
+
+// ------------------------------------------------------- root buckets
+// Counting sort of the roots by out-degree, largest first, so that heavy
+// subtrees start early.  cnt has amax+2 slots.
+
+__global__ void root_hist_kernel(int n, const int *__restrict__ odeg, int *__restrict__ cnt) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        atomicAdd(&cnt[odeg[v]], 1);
+}
+
+// cursor[d] = number of roots with out-degree > d (single block)
+__global__ void root_offsets_kernel(const int *__restrict__ amax_p, const int *__restrict__ cnt,
+                                    int *__restrict__ cursor, int *__restrict__ bounds,
+                                    int light_max) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int amax = *amax_p;
+        int acc = 0;
+        for (int d = amax; d >= 0; d--) {
+            cursor[d] = acc;
+            acc += cnt[d];
+        }
+        // bounds[0] = #roots with d > light_max (heavy), bounds[1] = #roots with d >= 1
+        bounds[0] = (light_max < amax) ? cursor[light_max] : 0;
+        bounds[1] = cursor[0];
+    }
+}
+
+__global__ void root_scatter_kernel(int n, const int *__restrict__ odeg, int *__restrict__ cursor,
+                                    int *__restrict__ order) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        order[atomicAdd(&cursor[odeg[v]], 1)] = v;
+}
+
+// ============================================================ host side
+
+static int grid_for(long long items, int per_block, int cap) {
+    long long b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+hipError_t pv_launch_check_rowptr(int n, long long nnz, const int *rp, int *d_err, hipStream_t s) {
+    check_rowptr_kernel<<<grid_for((long long)n + 1, 256, 1 << 20), 256, 0, s>>>(n, nnz, rp, d_err);
+    return hipGetLastError();
+}
+
+// only after the row pointers passed pv_launch_check_rowptr
+hipError_t pv_launch_validate(int n, const int *rp, const int *col, int *d_err, hipStream_t s) {
+    validate_kernel<<<grid_for((long long)n * 64, 256, 8192), 256, 0, s>>>(n, rp, col, d_err);
+    return hipGetLastError();
+}
+
+hipError_t pv_launch_peel(const DevInfo &dev, int n, const int *rp, const int *col, int *deg,
+                          int *sub, int *fa, int *fb, PeelCtl *ctl, hipStream_t s) {
+    // co-resident grid: enough blocks for the vertex count, at most what fits
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, peel_kernel, 256, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 4) per_cu = 4;
+    int blocks = grid_for(n, 256 * 4, dev.num_cu * per_cu);
+    void *args[] = {(void *)&n, (void *)&rp, (void *)&col, (void *)&deg, (void *)&sub,
+                    (void *)&fa, (void *)&fb, (void *)&ctl};
+    return hipLaunchCooperativeKernel((const void *)peel_kernel, dim3(blocks), dim3(256), args, 0, s);
+}
+
+hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
+                            int *odeg, int *orow, int *ocol, int *alpha, int *scan_tmp,
+                            hipStream_t s) {
+    const int wblocks = grid_for((long long)n * 64, 256, dev.num_cu * 32);
+    odeg_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, odeg, alpha);
+    const int nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    if (n > 0) {
+        scan_reduce_kernel<<<nb, 256, 0, s>>>(n, odeg, scan_tmp);
+        scan_blocks_kernel<<<1, 1024, 0, s>>>(nb, scan_tmp);
+        scan_apply_kernel<<<nb, 1024, 0, s>>>(n, odeg, scan_tmp, orow);
+    }
+    ofill_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, orow, ocol);
+    return hipGetLastError();
+}
+
+hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *cnt, int *cursor,
+                                int *order, int *bounds, int light_max, hipStream_t s) {
+    root_hist_kernel<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, odeg, cnt);
+    root_offsets_kernel<<<1, 64, 0, s>>>(amax, cnt, cursor, bounds, light_max);
+    root_scatter_kernel<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, odeg, cursor, order);
+    return hipGetLastError();
+}

@@ -1,0 +1,298 @@
+"""Thin ctypes binding of libpivoter (include/pivoter.h), same names as the
+C ABI.  Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  Importing this module does not touch the GPU; the
+first call loads libpivoter.so and raises if it is missing (there is no
+fallback path).
+
+Device buffers are passed as integer device addresses (for example
+``tensor.data_ptr()`` of a torch tensor on the same device); host buffers as
+numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpivoter.so")
+
+PV_OK = 0
+PV_EINVAL = -1
+PV_ENOTSIMPLE = -2
+PV_ENOMEM = -3
+PV_EOVERFLOW = -4
+PV_EDEVICE = -5
+PV_ETOOBIG = -6
+PV_EBUFSIZE = -7
+PV_ECANCELLED = -8
+PV_EAGAIN = -9
+
+PV_NONE, PV_VERTEX, PV_EDGE = 0, 1, 2
+PV_TRUST_INPUT = 1
+PV_MAX_ALPHA = 4096
+PV_MAX_LOCAL_K = 16
+
+# every function declared in include/pivoter.h
+ABI_FUNCTIONS = [
+    "pv_strerror", "pv_init", "pv_fini", "pv_set_stream", "pv_set_dfs_max", "pv_last_error",
+    "pv_graph_load_csr", "pv_graph_load_csr_device", "pv_graph_free", "pv_graph_size",
+    "pv_graph_orient", "pv_graph_export_order", "pv_count_global", "pv_count_local",
+    "pv_graph_edge_list", "pv_count", "pv_count_roots", "pv_count_global_batch",
+]
+
+
+class pv_u128(C.Structure):
+    _fields_ = [("lo", C.c_uint64), ("hi", C.c_uint64)]
+
+
+class pv_stats(C.Structure):
+    _fields_ = [("nodes", C.c_uint64), ("leaves", C.c_uint64), ("items", C.c_uint64),
+                ("alpha", C.c_int32), ("omega", C.c_int32), ("subrounds", C.c_int32),
+                ("truncated", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class PivoterError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        detail = ""
+        try:
+            detail = _lib().pv_last_error().decode()
+        except Exception:  # noqa: BLE001 - diagnostics only
+            pass
+        super().__init__(f"{what}: {_lib().pv_strerror(status).decode()} ({status})"
+                         + (f" [{detail}]" if detail else ""))
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2001_06784_amd.build")
+        lib = C.CDLL(LIB_PATH)
+        vp, i32, i64, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
+        pvp = C.POINTER(C.c_void_p)
+        u128p = C.POINTER(pv_u128)
+        u64p = C.POINTER(C.c_uint64)
+        i32p = C.POINTER(C.c_int32)
+        sp = C.POINTER(pv_stats)
+        sig = {
+            "pv_strerror": (C.c_char_p, [i32]),
+            "pv_last_error": (C.c_char_p, []),
+            "pv_init": (i32, [i32, vp, pvp]),
+            "pv_fini": (None, [vp]),
+            "pv_set_stream": (i32, [vp, vp]),
+            "pv_set_dfs_max": (i32, [vp, i32]),
+            "pv_graph_load_csr": (i32, [vp, i32, i32p, i32p, u32, pvp]),
+            "pv_graph_load_csr_device": (i32, [vp, i32, i64, vp, vp, u32, pvp]),
+            "pv_graph_free": (None, [vp]),
+            "pv_graph_size": (i32, [vp, i32p, C.POINTER(C.c_int64)]),
+            "pv_graph_orient": (i32, [vp, i32p]),
+            "pv_graph_export_order": (i32, [vp, i32p]),
+            "pv_count_global": (i32, [vp, i32, u128p, i32, i32p, u64p, sp]),
+            "pv_count_local": (i32, [vp, i32, i32, i32, u128p, i64, u64p, sp]),
+            "pv_graph_edge_list": (i32, [vp, i32p, i32p]),
+            "pv_count": (i32, [vp, i32, i32, u128p, i32, i32p, u64p, i32, i32, i32, vp, u64p, sp]),
+            "pv_count_roots": (i32, [vp, i32p, i32, i32, u128p, i32, i32p, u64p, sp]),
+            "pv_count_global_batch": (i32, [vp, i32, pvp, i32, u128p, i32, i32p, u64p, sp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def load_library():
+    """Load libpivoter.so now (raises ImportError if it is not built)."""
+    return _lib()
+
+
+def _check(status: int, what: str, allow=()):
+    if status != PV_OK and status not in allow:
+        raise PivoterError(status, what)
+    return status
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def u128_to_ints(arr) -> list:
+    """ctypes pv_u128 array or (..., 2) uint64 array -> Python ints."""
+    a = np.asarray(arr)
+    if a.dtype.fields is not None:
+        a = np.frombuffer(a.tobytes(), dtype=np.uint64).reshape(-1, 2)
+    lo = a[..., 0].astype(object)
+    hi = a[..., 1].astype(object)
+    return (lo + (hi << 64)).tolist()
+
+
+# ------------------------------------------------------------- functions
+
+def pv_strerror(status: int) -> str:
+    return _lib().pv_strerror(status).decode()
+
+
+def pv_last_error() -> str:
+    return _lib().pv_last_error().decode()
+
+
+def pv_init(device: int = 0, stream: int | None = None) -> int:
+    out = C.c_void_p()
+    _check(_lib().pv_init(device, stream, C.byref(out)), "pv_init")
+    return out.value
+
+
+def pv_fini(ctx: int) -> None:
+    _lib().pv_fini(ctx)
+
+
+def pv_set_stream(ctx: int, stream: int | None) -> None:
+    _check(_lib().pv_set_stream(ctx, stream), "pv_set_stream")
+
+
+def pv_set_dfs_max(ctx: int, dfs_max: int) -> None:
+    _check(_lib().pv_set_dfs_max(ctx, dfs_max), "pv_set_dfs_max")
+
+
+def pv_graph_load_csr(ctx: int, n: int, row_ptr, col, flags: int = 0) -> int:
+    rp, rpp = _i32(row_ptr)
+    cl, clp = _i32(col if len(col) else np.zeros(1, np.int32))
+    if rp.shape[0] != n + 1:
+        raise ValueError("row_ptr must have n+1 entries")
+    out = C.c_void_p()
+    _check(_lib().pv_graph_load_csr(ctx, n, rpp, clp, flags, C.byref(out)), "pv_graph_load_csr")
+    return out.value
+
+
+def pv_graph_load_csr_device(ctx: int, n: int, nnz: int, d_row_ptr: int, d_col: int,
+                             flags: int = 0) -> int:
+    out = C.c_void_p()
+    _check(_lib().pv_graph_load_csr_device(ctx, n, nnz, d_row_ptr, d_col, flags, C.byref(out)),
+           "pv_graph_load_csr_device")
+    return out.value
+
+
+def pv_graph_free(g: int) -> None:
+    _lib().pv_graph_free(g)
+
+
+def pv_graph_size(g: int) -> tuple[int, int]:
+    n = C.c_int32()
+    m = C.c_int64()
+    _check(_lib().pv_graph_size(g, C.byref(n), C.byref(m)), "pv_graph_size")
+    return n.value, m.value
+
+
+def pv_graph_orient(g: int) -> int:
+    a = C.c_int32()
+    _check(_lib().pv_graph_orient(g, C.byref(a)), "pv_graph_orient")
+    return a.value
+
+
+def pv_graph_export_order(g: int) -> np.ndarray:
+    n, _ = pv_graph_size(g)
+    out = np.zeros(max(n, 1), dtype=np.int32)
+    _check(_lib().pv_graph_export_order(g, out.ctypes.data_as(C.POINTER(C.c_int32))),
+           "pv_graph_export_order")
+    return out[:n]
+
+
+@dataclass
+class GlobalResult:
+    counts: list          # C_0..C_{cap-1} as Python ints
+    omega: int
+    overflow: list        # k with C_k >= 2^128
+    stats: dict
+    status: int
+
+
+def pv_count_global(g: int, k_max: int = 0, cap: int = PV_MAX_ALPHA + 2) -> GlobalResult:
+    counts = (pv_u128 * cap)()
+    ov = (C.c_uint64 * ((cap + 63) // 64))()
+    om = C.c_int32()
+    st = pv_stats()
+    s = _check(_lib().pv_count_global(g, k_max, counts, cap, C.byref(om), ov, C.byref(st)),
+               "pv_count_global", allow=(PV_EOVERFLOW,))
+    ovf = [k for k in range(cap) if (ov[k >> 6] >> (k & 63)) & 1]
+    return GlobalResult(u128_to_ints(counts), om.value, ovf, st.as_dict(), s)
+
+
+def pv_count_local(g: int, kind: int, k_lo: int, k_hi: int):
+    """Returns ((rows, K, 2) uint64 limbs, overflow word, stats)."""
+    n, m = pv_graph_size(g)
+    K = k_hi - k_lo + 1
+    rows = n if kind == PV_VERTEX else m
+    out = np.zeros((max(rows, 1), K, 2), dtype=np.uint64)
+    ov = C.c_uint64()
+    st = pv_stats()
+    _check(_lib().pv_count_local(g, kind, k_lo, k_hi, out.ctypes.data_as(C.POINTER(pv_u128)),
+                                 rows * K, C.byref(ov), C.byref(st)),
+           "pv_count_local", allow=(PV_EOVERFLOW,))
+    return out[:rows], ov.value, st.as_dict()
+
+
+def pv_graph_edge_list(g: int) -> tuple[np.ndarray, np.ndarray]:
+    _, m = pv_graph_size(g)
+    u = np.zeros(max(m, 1), dtype=np.int32)
+    v = np.zeros(max(m, 1), dtype=np.int32)
+    _check(_lib().pv_graph_edge_list(g, u.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     v.ctypes.data_as(C.POINTER(C.c_int32))), "pv_graph_edge_list")
+    return u[:m], v[:m]
+
+
+def pv_count(g: int, reorient: bool = False, k_max: int = 0, cap: int = PV_MAX_ALPHA + 2,
+             local_kind: int = PV_NONE, k_lo: int = 0, k_hi: int = 0, local_out: int | None = None):
+    """One pass: global counts (host) and optional local counts into the
+    device buffer `local_out` (address).  Returns (GlobalResult, local overflow word)."""
+    counts = (pv_u128 * cap)()
+    ov = (C.c_uint64 * ((cap + 63) // 64))()
+    om = C.c_int32()
+    lov = C.c_uint64()
+    st = pv_stats()
+    s = _check(_lib().pv_count(g, int(reorient), k_max, counts, cap, C.byref(om), ov, local_kind,
+                               k_lo, k_hi, local_out, C.byref(lov), C.byref(st)),
+               "pv_count", allow=(PV_EOVERFLOW,))
+    ovf = [k for k in range(cap) if (ov[k >> 6] >> (k & 63)) & 1]
+    return GlobalResult(u128_to_ints(counts), om.value, ovf, st.as_dict(), s), lov.value
+
+
+def pv_count_roots(g: int, roots, k_max: int = 0, cap: int = PV_MAX_ALPHA + 2) -> GlobalResult:
+    r, rp = _i32(roots if len(roots) else np.zeros(1, np.int32))
+    counts = (pv_u128 * cap)()
+    ov = (C.c_uint64 * ((cap + 63) // 64))()
+    om = C.c_int32()
+    st = pv_stats()
+    s = _check(_lib().pv_count_roots(g, rp, len(roots), k_max, counts, cap, C.byref(om), ov,
+                                     C.byref(st)), "pv_count_roots", allow=(PV_EOVERFLOW,))
+    ovf = [k for k in range(cap) if (ov[k >> 6] >> (k & 63)) & 1]
+    return GlobalResult(u128_to_ints(counts), om.value, ovf, st.as_dict(), s)
+
+
+def pv_count_global_batch(ctx: int, graphs, k_max: int = 0, cap: int = 256):
+    G = len(graphs)
+    arr = (C.c_void_p * max(G, 1))(*graphs)
+    counts = (pv_u128 * (max(G, 1) * cap))()
+    om = (C.c_int32 * max(G, 1))()
+    nw = (cap + 63) // 64
+    ov = (C.c_uint64 * (max(G, 1) * nw))()
+    st = pv_stats()
+    s = _check(_lib().pv_count_global_batch(ctx, G, arr, k_max, counts, cap, om, ov, C.byref(st)),
+               "pv_count_global_batch", allow=(PV_EOVERFLOW,))
+    flat = u128_to_ints(counts)
+    out = []
+    for i in range(G):
+        ovf = [k for k in range(cap) if (ov[i * nw + (k >> 6)] >> (k & 63)) & 1]
+        out.append(GlobalResult(flat[i * cap:(i + 1) * cap], om[i], ovf, {}, s))
+    return out, st.as_dict()

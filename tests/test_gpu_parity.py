@@ -1,0 +1,236 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Everything here is integer work, so the bar is bit-exact equality: the peel
+order, the global counts C_k (exact u128, with identical overflow flags), the
+clique number, the SCT's node and leaf counts (the GPU follows the same pivot
+and child-order rules, so it builds the same tree), and per-vertex counts.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2001_06784_amd import graphgen as gg
+from paper_2001_06784_amd import pivoter as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = P.pv_init(0)
+    yield c
+    P.pv_fini(c)
+
+
+class Loaded:
+    def __init__(self, ctx, g):
+        self.h = P.pv_graph_load_csr(ctx, g.n, g.row_ptr, g.col)
+
+    def __enter__(self):
+        return self.h
+
+    def __exit__(self, *exc):
+        P.pv_graph_free(self.h)
+
+
+def check_global(ctx, g, name, kmax=0, check_order=True):
+    _say(f"[parity] {name}: n={g.n} m={g.m} kmax={kmax}")
+    with Loaded(ctx, g) as h:
+        res = P.pv_count_global(h, kmax)
+        sub = P.pv_graph_export_order(h)
+    if check_order:
+        pe = O.peel(g)
+        assert np.array_equal(sub, pe.sub), "peel order differs"
+    ref = O.count(g, key=sub, kmax=kmax)
+    top = len(ref.glob)
+    ovf_ref = [k for k in range(top) if ref.glob_ovf[k]]
+    assert res.overflow == ovf_ref
+    for k in range(top):
+        if not ref.glob_ovf[k]:
+            assert res.counts[k] == ref.glob[k], (name, k, res.counts[k], ref.glob[k])
+    assert all(c == 0 for c in res.counts[top:])
+    assert res.omega == (min(ref.omega, kmax) if kmax else ref.omega)
+    assert res.stats["alpha"] == ref.stats["alpha"]
+    if not kmax:
+        assert res.stats["leaves"] == ref.stats["leaves"], (res.stats, ref.stats)
+        assert res.stats["nodes"] == ref.stats["nodes"], (res.stats, ref.stats)
+    return res, ref
+
+
+FAMILIES = [
+    ("empty0", lambda: gg.empty(0)),
+    ("empty5", lambda: gg.empty(5)),
+    ("K1", lambda: gg.complete(1)),
+    ("K2", lambda: gg.complete(2)),
+    ("path9", lambda: gg.path(9)),
+    ("star40", lambda: gg.star(40)),
+    ("cycle11", lambda: gg.cycle(11)),
+    ("K10", lambda: gg.complete(10)),
+    ("K64", lambda: gg.complete(64)),
+    ("K65", lambda: gg.complete(65)),
+    ("K66", lambda: gg.complete(66)),
+    ("K70", lambda: gg.complete(70)),
+    ("K129", lambda: gg.complete(129)),
+    ("multipartite", lambda: gg.complete_multipartite([1, 2, 3, 4, 5, 6, 7])),
+    ("moon_moser8", lambda: gg.moon_moser(8)),
+    ("cocktail12", lambda: gg.complete_multipartite([2] * 12)),
+    ("wheel", lambda: gg.join(gg.cycle(9), gg.complete(1))),
+]
+
+
+@pytest.mark.parametrize("name,maker", FAMILIES, ids=[f[0] for f in FAMILIES])
+def test_families(ctx, name, maker):
+    check_global(ctx, maker(), name)
+
+
+@pytest.mark.parametrize("n", [132, 140])
+def test_overflow_flags_match(ctx, n):
+    res, ref = check_global(ctx, gg.complete(n), f"K{n}")
+    assert res.status == P.PV_EOVERFLOW
+    assert res.overflow and all(bool(ref.glob_ovf[k]) for k in res.overflow)
+
+
+RANDOM = [(40, 0.3, 1), (90, 0.15, 2), (200, 0.05, 3), (120, 0.5, 4), (64, 0.8, 5)]
+
+
+@pytest.mark.parametrize("n,p,seed", RANDOM)
+def test_random_graphs(ctx, n, p, seed):
+    check_global(ctx, gg.gnp(n, p, seed), f"gnp({n},{p},{seed})")
+
+
+def test_er_planted_workload(ctx):
+    # G(2000, 0.01) plus three planted 12-cliques: the small benchmark workload
+    check_global(ctx, gg.er_planted(), "er2000+3xK12")
+
+
+def test_heavy_roots_multiword(ctx):
+    # planted cliques of 70..100 vertices give out-neighbourhoods > 64
+    g = gg.plant_cliques(gg.gnp(600, 0.04, 7), [100, 80, 70], 8)
+    res, ref = check_global(ctx, g, "gnp600+K100,K80,K70")
+    assert ref.stats["alpha"] > 64
+
+
+def test_heavy_dense_overlap(ctx):
+    # dense random core with overlapping planted cliques: deep multi-word chains
+    g = gg.plant_cliques(gg.gnp(160, 0.45, 11), [75, 40], 12)
+    check_global(ctx, g, "gnp160(0.45)+K75,K40")
+
+
+def test_chung_lu_medium(ctx):
+    g = gg.chung_lu(20000, 20, 2.3, 2000, 5)
+    check_global(ctx, g, "chung_lu 20k")
+
+
+@pytest.mark.parametrize("kmax", [1, 2, 3, 5, 8])
+def test_truncation(ctx, kmax):
+    g = gg.plant_cliques(gg.gnp(300, 0.08, 21), [20, 15], 22)
+    check_global(ctx, g, f"truncated kmax={kmax}", kmax=kmax)
+
+
+@pytest.mark.parametrize("dfs_max", [1, 4, 16, 40, 64])
+def test_split_threshold_does_not_change_the_tree(ctx, dfs_max):
+    g = gg.plant_cliques(gg.gnp(400, 0.1, 31), [70, 30], 32)
+    P.pv_set_dfs_max(ctx, dfs_max)
+    try:
+        check_global(ctx, g, f"dfs_max={dfs_max}")
+    finally:
+        P.pv_set_dfs_max(ctx, 24)
+
+
+# --------------------------------------------------------------- per-vertex
+
+LOCAL = [("gnp", lambda: gg.gnp(150, 0.2, 41), (1, 8)),
+         ("planted", lambda: gg.plant_cliques(gg.gnp(300, 0.05, 42), [14, 9], 43), (3, 10)),
+         ("heavy", lambda: gg.plant_cliques(gg.gnp(400, 0.04, 44), [90, 12], 45), (3, 10)),
+         ("K40", lambda: gg.complete(40), (1, 16)),
+         ("moon_moser", lambda: gg.moon_moser(7), (2, 7))]
+
+
+@pytest.mark.parametrize("name,maker,krange", LOCAL, ids=[x[0] for x in LOCAL])
+def test_per_vertex(ctx, name, maker, krange):
+    g = maker()
+    klo, khi = krange
+    _say(f"[parity] per-vertex {name}: n={g.n} m={g.m} k={klo}..{khi}")
+    with Loaded(ctx, g) as h:
+        out, ovf, st = P.pv_count_local(h, P.PV_VERTEX, klo, khi)
+    ref = O.count(g, vertex=(klo, khi))
+    assert ovf == 0
+    assert np.array_equal(out, ref.vertex)
+
+
+def test_combined_pass_with_device_output(ctx):
+    import torch
+    g = gg.plant_cliques(gg.chung_lu(5000, 16, 2.3, 800, 51), [40, 70], 52)
+    klo, khi = 3, 10
+    K = khi - klo + 1
+    _say(f"[parity] combined pass n={g.n} m={g.m}")
+    dev = torch.zeros((g.n, K, 2), dtype=torch.int64, device="cuda:0")
+    with Loaded(ctx, g) as h:
+        res, lovf = P.pv_count(h, reorient=True, local_kind=P.PV_VERTEX, k_lo=klo, k_hi=khi,
+                               local_out=dev.data_ptr())
+        sub = P.pv_graph_export_order(h)
+    torch.cuda.synchronize()
+    out = dev.cpu().numpy().view(np.uint64)
+    ref = O.count(g, key=sub, vertex=(klo, khi))
+    assert lovf == 0
+    assert res.counts[: len(ref.glob)] == ref.glob
+    assert res.stats["leaves"] == ref.stats["leaves"]
+    assert np.array_equal(out, ref.vertex)
+
+
+# ------------------------------------------------------------ root subsets
+
+def test_root_subsets(ctx):
+    g = gg.plant_cliques(gg.gnp(500, 0.06, 61), [80, 20], 62)
+    rng = np.random.default_rng(63)
+    with Loaded(ctx, g) as h:
+        sub = P.pv_graph_export_order(h)
+        roots = rng.choice(g.n, 120, replace=False).astype(np.int32)
+        res = P.pv_count_roots(h, roots)
+        empty = P.pv_count_roots(h, np.zeros(0, np.int32))
+    ref = O.count(g, key=sub, roots=roots)
+    assert res.counts[0] == 0
+    assert res.counts[1: len(ref.glob)] == ref.glob[1:]
+    assert res.stats["leaves"] == ref.stats["leaves"]
+    assert all(c == 0 for c in empty.counts)
+
+
+# -------------------------------------------------------------- validation
+
+@pytest.mark.parametrize("bad", ["selfloop", "asym", "unsorted", "dup", "range"])
+def test_invalid_csr_is_rejected(ctx, bad):
+    rp = np.array([0, 2, 3, 4], dtype=np.int32)
+    col = np.array([1, 2, 0, 0], dtype=np.int32)  # 0-1, 0-2 ok
+    if bad == "selfloop":
+        col = np.array([0, 2, 0, 0], dtype=np.int32)
+    elif bad == "asym":
+        rp = np.array([0, 2, 3, 3], dtype=np.int32)
+        col = np.array([1, 2, 0], dtype=np.int32)
+    elif bad == "unsorted":
+        col = np.array([2, 1, 0, 0], dtype=np.int32)
+    elif bad == "dup":
+        rp = np.array([0, 2, 4, 5], dtype=np.int32)
+        col = np.array([1, 1, 0, 0, 0], dtype=np.int32)
+    elif bad == "range":
+        col = np.array([1, 7, 0, 0], dtype=np.int32)
+    with pytest.raises(P.PivoterError) as ei:
+        h = P.pv_graph_load_csr(ctx, 3, rp, col)
+        P.pv_graph_free(h)
+    assert ei.value.status == P.PV_ENOTSIMPLE
+
+
+def test_valid_tiny_csr_is_accepted(ctx):
+    rp = np.array([0, 2, 3, 4], dtype=np.int32)
+    col = np.array([1, 2, 0, 0], dtype=np.int32)
+    h = P.pv_graph_load_csr(ctx, 3, rp, col)
+    res = P.pv_count_global(h)
+    P.pv_graph_free(h)
+    assert res.counts[:4] == [1, 3, 2, 0]
