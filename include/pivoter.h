@@ -79,10 +79,16 @@ typedef struct {
     uint64_t nodes;        /* SCT nodes below the root V that were visited */
     uint64_t leaves;       /* SCT leaves (root-to-leaf paths) */
     uint64_t items;        /* subproblems handed between GPU stages */
+    uint64_t work;         /* pivot work: sum over nodes of |S| * ceil(|S|/64) */
     int32_t alpha;         /* degeneracy = largest out-degree */
     int32_t omega;         /* largest clique size (0 for the empty graph) */
     int32_t subrounds;     /* sub-rounds of the degeneracy peel */
     int32_t truncated;     /* 1 if the tree was cut at k_max hold vertices */
+    int32_t levels;        /* launches of the SCT level kernel */
+    float ms_peel;         /* device time of the peel kernel          \ HIP events on */
+    float ms_orient;       /* device time of the N+(v) construction    | the context */
+    float ms_levels;       /* summed device time of the level kernels  | stream, only */
+    float ms_finalize;     /* device time of the u128 finalize kernel / with timing on */
 } pv_stats;
 
 /* Human-readable name of a status code (static string). */
@@ -106,6 +112,13 @@ pv_status pv_set_stream(pv_ctx *ctx, void *stream);
  * Default 24 (environment variable PV_DFS_MAX overrides it at pv_init).
  */
 pv_status pv_set_dfs_max(pv_ctx *ctx, int32_t dfs_max);
+
+/*
+ * Record HIP events around the peel, orientation, level and finalize
+ * kernels of later calls (on = 1) and report their device times in
+ * pv_stats.  Off by default.
+ */
+pv_status pv_set_timing(pv_ctx *ctx, int32_t on);
 
 /* Text of the last HIP error seen by this host thread (static storage). */
 const char *pv_last_error(void);

@@ -107,6 +107,9 @@ struct pv_ctx {
     int *h_io = nullptr;  // pinned readback slots
     int level_blocks[3] = {0, 0, 0};
     int dfs_max = 24;
+    // device timing (HIP events on the context stream)
+    bool timing = false;
+    hipEvent_t ev[8] = {};
 };
 
 struct pv_graph {
@@ -174,6 +177,11 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
         c->level_blocks[kl] = std::max(1, per_cu) * c->dev.num_cu;
     }
     if (const char *env = getenv("PV_DFS_MAX")) c->dfs_max = std::max(1, std::min(64, atoi(env)));
+    for (auto &ev : c->ev)
+        if (hipEventCreate(&ev) != hipSuccess) {
+            pv_fini(c);
+            return PV_EDEVICE;
+        }
     *out = c;
     return PV_OK;
 }
@@ -188,6 +196,8 @@ extern "C" void pv_fini(pv_ctx *c) {
     c->d_args.release();
     if (c->h_args) (void)hipHostFree(c->h_args);
     if (c->h_io) (void)hipHostFree(c->h_io);
+    for (auto &ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
     delete c;
 }
 
@@ -195,6 +205,18 @@ extern "C" pv_status pv_set_stream(pv_ctx *c, void *stream) {
     if (!c) return PV_EINVAL;
     c->stream = (hipStream_t)stream;
     return PV_OK;
+}
+
+extern "C" pv_status pv_set_timing(pv_ctx *c, int32_t on) {
+    if (!c) return PV_EINVAL;
+    c->timing = on != 0;
+    return PV_OK;
+}
+
+static float elapsed(pv_ctx *c, int a, int b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) return 0.f;
+    return ms;
 }
 
 // tunable: largest |S| walked depth first (1..64)
@@ -368,13 +390,16 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     HIPCHK(hipMemsetAsync(g->small.p + SM_ALPHA, 0, sizeof(int), s));
     HIPCHK(hipMemsetAsync(g->orow.p, 0, sizeof(int), s));
     if (n > 0) {
+        if (c->timing) HIPCHK(hipEventRecord(c->ev[0], s));
         HIPCHK(pv_launch_peel(c->dev, n, g->rp.p, g->col.p, g->deg.p, g->sub.p, g->fa.p, g->fb.p,
                               g->ctl.p, s));
+        if (c->timing) HIPCHK(hipEventRecord(c->ev[1], s));
         HIPCHK(pv_launch_orient(c->dev, n, g->rp.p, g->col.p, g->sub.p, g->odeg.p, g->orow.p,
                                 g->ocol.p, g->small.p + SM_ALPHA, g->scan.p, s));
         HIPCHK(hipMemsetAsync(g->rcnt.p, 0, sizeof(int) * ((size_t)n + 2), s));
         HIPCHK(pv_launch_root_order(n, g->small.p + SM_ALPHA, g->odeg.p, g->rcnt.p, g->rcursor.p,
                                     g->order.p, g->small.p + SM_BOUNDS, PV_LIGHT_MAX, s));
+        if (c->timing) HIPCHK(hipEventRecord(c->ev[2], s));
     } else {
         HIPCHK(hipMemsetAsync(g->small.p + SM_BOUNDS, 0, 2 * sizeof(int), s));
     }
@@ -387,6 +412,10 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     g->nnonzero = io[SM_BOUNDS1];
     g->subrounds = io[32];
     g->oriented = true;
+    if (c->timing && n > 0) {
+        g->last.ms_peel = elapsed(c, 0, 1);
+        g->last.ms_orient = elapsed(c, 1, 2);
+    }
     if (alpha_out) *alpha_out = g->alpha;
     return PV_OK;
 }
@@ -461,6 +490,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
 
         bool overflow = false;
         int levels = 0;
+        float ms_levels = 0.f;
         long long items = 0;
         const int nchunks = (chunk > 0) ? (rq.nheavy + chunk - 1) / chunk : 0;
         for (int ch = 0; ch < std::max(1, nchunks) && !overflow; ch++) {
@@ -521,10 +551,13 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 HIPCHK(hipMemcpyAsync(c->d_args.p, c->h_args, sizeof(LevelArgs), hipMemcpyHostToDevice, s));
                 const int kli = rq.kl == 0 ? 0 : (rq.kl <= 8 ? 1 : 2);
                 const int blocks = (int)std::min<long long>(c->level_blocks[kli], (units + 3) / 4);
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[3], s));
                 HIPCHK(pv_launch_level(c->d_args.p, rq.kl, std::max(1, blocks), s));
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[4], s));
                 HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
                 levels++;
+                if (c->timing) ms_levels += elapsed(c, 3, 4);
                 if (io[SM_FLAGS] & 1) {
                     overflow = true;
                     if ((size_t)io[SM_CN] > g->c_cap) g->c_cap *= 4;
@@ -542,7 +575,8 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
         if (overflow) continue;
         g->last.items = (uint64_t)items;
         g->last.truncated = rq.kmax > 0;
-        (void)levels;
+        g->last.levels = levels;
+        g->last.ms_levels = ms_levels;
         return PV_OK;
     }
 }
@@ -559,8 +593,10 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
     PVCHK(g->ovf.ensure(nw));
     HIPCHK(hipMemsetAsync(g->ovf.p, 0, nw * sizeof(uint64_t), s));
     HIPCHK(hipMemsetAsync(g->small.p + SM_OMEGA, 0, sizeof(int), s));
+    if (c->timing) HIPCHK(hipEventRecord(c->ev[5], s));
     HIPCHK(pv_launch_finalize(g->hist.p, hd, c->tab.p, c->bad.p, c->bn, kcap, rq.kmax, rq.c0,
                               g->counts.p, g->ovf.p, g->small.p + SM_OMEGA, s));
+    if (c->timing) HIPCHK(hipEventRecord(c->ev[6], s));
     std::vector<uint64_t> hc((size_t)kcap * 2), ho(nw);
     unsigned long long hcnt[4];
     HIPCHK(hipMemcpyAsync(hc.data(), g->counts.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
@@ -571,6 +607,8 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
     const int omega = c->h_io[SM_OMEGA];
     g->last.nodes = hcnt[0];
     g->last.leaves = hcnt[1];
+    g->last.work = hcnt[2];
+    if (c->timing) g->last.ms_finalize = elapsed(c, 5, 6);
     g->last.alpha = g->alpha;
     g->last.omega = omega;
     g->last.subrounds = g->subrounds;
@@ -599,12 +637,12 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
 
 static pv_status prepare(pv_graph *g, bool reorient) {
     HIPCHK(hipSetDevice(g->ctx->device));
+    g->last = pv_stats{};
     if (reorient || !g->oriented) PVCHK(pv_graph_orient(g, nullptr));
     if (g->alpha > PV_MAX_ALPHA) {
         snprintf(g_last_error, sizeof g_last_error, "degeneracy %d exceeds %d", g->alpha, PV_MAX_ALPHA);
         return PV_ETOOBIG;
     }
-    g->last = pv_stats{};
     return PV_OK;
 }
 

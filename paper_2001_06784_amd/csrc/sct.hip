@@ -153,6 +153,12 @@ struct VertexSink {
     }
 };
 
+// Work counters of a wave: SCT nodes visited, and the algorithmic pivot
+// work sum over nodes of |S| * ceil(|S|/64) (64-bit AND+popcount pairs).
+struct Ctr {
+    unsigned long long nodes, work;
+};
+
 // ------------------------------------------------------ compact-tier DFS
 // Walk the whole subtree of node (S, H, P, h, p) of a compact universe
 // whose row for member `lane` is A.  Depth first, stack in lane-indexed
@@ -162,15 +168,16 @@ struct VertexSink {
 template <int KL>
 __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int h, int p, int lane,
                             const LevelArgs &a, GlobalSink &gs, VertexSink<KL> &vs,
-                            unsigned long long &nodes) {
+                            Ctr &ct) {
     constexpr bool LOCAL = KL > 0;
     uint64_t stS = 0, stH = 0, stP = 0;
     uint32_t stM = 0;
     int depth = 0;
     for (;;) {
-        nodes++;
+        ct.nodes++;
         if (S != 0) {
             const int s = __popcll(S);
+            ct.work += (unsigned long long)s;
             const bool in = (S >> lane) & 1;
             const uint32_t c = (uint32_t)__popcll(A & S);
             const uint32_t key = in ? (((c + 1u) << 6) | (uint32_t)(63 - lane)) : 0u;
@@ -182,7 +189,8 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                 // the pivot sees all of S: no hold child.  If every member
                 // does, S is a clique and its pivot chain ends in one leaf.
                 if (ballot64(in && (int)c + 1 != s) == 0) {
-                    nodes += (unsigned long long)s;
+                    ct.nodes += (unsigned long long)s;
+                    ct.work += (unsigned long long)s * (unsigned long long)(s - 1) / 2;
                     if (LOCAL) P |= S;
                     p += s;
                 } else {
@@ -241,15 +249,16 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
 template <int KL>
 __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int h, int p, int uni,
                             int nm, int gid, int root, int2 pref, int lane, const LevelArgs &a,
-                            GlobalSink &gs, VertexSink<KL> &vs, unsigned long long &nodes) {
+                            GlobalSink &gs, VertexSink<KL> &vs, Ctr &ct) {
     constexpr bool LOCAL = KL > 0;
     for (;;) {
         const int s = __popcll(S);
         if (s <= a.dfs_max || uni < 0) {
-            compact_dfs<KL>(A, S, H, P, h, p, lane, a, gs, vs, nodes);
+            compact_dfs<KL>(A, S, H, P, h, p, lane, a, gs, vs, ct);
             break;
         }
-        nodes++;
+        ct.nodes++;
+        ct.work += (unsigned long long)s;
         const bool in = (S >> lane) & 1;
         const uint32_t c = (uint32_t)__popcll(A & S);
         const uint32_t key = in ? (((c + 1u) << 6) | (uint32_t)(63 - lane)) : 0u;
@@ -259,7 +268,8 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
         const uint64_t pbit = 1ull << piv;
         if (pc + 1 == s) {
             if (ballot64(in && (int)c + 1 != s) == 0) {
-                nodes += (unsigned long long)s;
+                ct.nodes += (unsigned long long)s;
+                ct.work += (unsigned long long)s * (unsigned long long)(s - 1) / 2;
                 if (LOCAL) P |= S;
                 p += s;
                 gs.leaf(h, p, lane, a.hist, a.hd);
@@ -360,7 +370,7 @@ struct CState {
 
 template <int KL>
 __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int p, int lane,
-                       const LevelArgs &a, unsigned long long &nodes, int *memb, CState &cs) {
+                       const LevelArgs &a, Ctr &ct, int *memb, CState &cs) {
     constexpr bool LOCAL = KL > 0;
     const int W = a.W, dpad = a.dpad;
     const uint64_t *rows = a.hu_rows + (long long)hu * W * dpad;
@@ -409,7 +419,8 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
             cs.pref = pref;
             return true;
         }
-        nodes++;
+        ct.nodes++;
+        ct.work += (unsigned long long)s * (unsigned long long)((s + 63) / 64);
         // pivot: argmax over u in S of |N(S,u)|, ties to the smallest index
         uint32_t best = 0;
         for (int t = 0; t < W; t++) {
@@ -561,7 +572,8 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
     gs.leaves = 0;
     VertexSink<KL> vs;
     if (LOCAL) vs.reset();
-    unsigned long long nodes = 0;
+    Ctr ct;
+    ct.nodes = ct.work = 0;
 
     const int n0 = a.n_mw_in, n1 = n0 + a.n_c_in;
     const int n2 = n1 + (a.level == 0 ? a.nheavy : 0);
@@ -599,7 +611,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
                     Sw = (cnt == 64) ? ~0ull : ((1ull << cnt) - 1);
                 }
             }
-            run = mw_run<KL>(hu, Sw, Hw, Pw, h, p, lane, a, nodes, s_memb[wv], cs);
+            run = mw_run<KL>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs);
         } else if (idx < n1) {
             const CItem it = a.c_in[idx - n0];
             cs.A = a.u_rows[(long long)it.uni * 64 + lane];
@@ -637,12 +649,13 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
         }
         if (run)
             compact_run<KL>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
-                            cs.pref, lane, a, gs, vs, nodes);
+                            cs.pref, lane, a, gs, vs, ct);
     }
     gs.flush(lane, a.hist, a.hd);
     if (lane == 0) {
-        atomicAdd(&a.counters[0], nodes);
+        atomicAdd(&a.counters[0], ct.nodes);
         atomicAdd(&a.counters[1], gs.leaves);
+        atomicAdd(&a.counters[2], ct.work);
     }
 }
 

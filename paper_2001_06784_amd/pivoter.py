@@ -37,7 +37,8 @@ PV_MAX_LOCAL_K = 16
 
 # every function declared in include/pivoter.h
 ABI_FUNCTIONS = [
-    "pv_strerror", "pv_init", "pv_fini", "pv_set_stream", "pv_set_dfs_max", "pv_last_error",
+    "pv_strerror", "pv_init", "pv_fini", "pv_set_stream", "pv_set_dfs_max", "pv_set_timing",
+    "pv_last_error",
     "pv_graph_load_csr", "pv_graph_load_csr_device", "pv_graph_free", "pv_graph_size",
     "pv_graph_orient", "pv_graph_export_order", "pv_count_global", "pv_count_local",
     "pv_graph_edge_list", "pv_count", "pv_count_roots", "pv_count_global_batch",
@@ -50,8 +51,10 @@ class pv_u128(C.Structure):
 
 class pv_stats(C.Structure):
     _fields_ = [("nodes", C.c_uint64), ("leaves", C.c_uint64), ("items", C.c_uint64),
-                ("alpha", C.c_int32), ("omega", C.c_int32), ("subrounds", C.c_int32),
-                ("truncated", C.c_int32)]
+                ("work", C.c_uint64), ("alpha", C.c_int32), ("omega", C.c_int32),
+                ("subrounds", C.c_int32), ("truncated", C.c_int32), ("levels", C.c_int32),
+                ("ms_peel", C.c_float), ("ms_orient", C.c_float), ("ms_levels", C.c_float),
+                ("ms_finalize", C.c_float)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -77,6 +80,13 @@ def _lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run python -m paper_2001_06784_amd.build")
+        # PyTorch-ROCm ships its own libamdhip64.so.7.  Loading it first makes
+        # libpivoter bind to that same runtime (identical SONAME), so torch
+        # tensors and library calls share one HIP runtime in the process.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = C.CDLL(LIB_PATH)
         vp, i32, i64, u32 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32
         pvp = C.POINTER(C.c_void_p)
@@ -91,6 +101,7 @@ def _lib():
             "pv_fini": (None, [vp]),
             "pv_set_stream": (i32, [vp, vp]),
             "pv_set_dfs_max": (i32, [vp, i32]),
+            "pv_set_timing": (i32, [vp, i32]),
             "pv_graph_load_csr": (i32, [vp, i32, i32p, i32p, u32, pvp]),
             "pv_graph_load_csr_device": (i32, [vp, i32, i64, vp, vp, u32, pvp]),
             "pv_graph_free": (None, [vp]),
@@ -164,6 +175,10 @@ def pv_set_stream(ctx: int, stream: int | None) -> None:
 
 def pv_set_dfs_max(ctx: int, dfs_max: int) -> None:
     _check(_lib().pv_set_dfs_max(ctx, dfs_max), "pv_set_dfs_max")
+
+
+def pv_set_timing(ctx: int, on: bool) -> None:
+    _check(_lib().pv_set_timing(ctx, int(bool(on))), "pv_set_timing")
 
 
 def pv_graph_load_csr(ctx: int, n: int, row_ptr, col, flags: int = 0) -> int:

@@ -62,6 +62,7 @@ def check_global(ctx, g, name, kmax=0, check_order=True):
     if not kmax:
         assert res.stats["leaves"] == ref.stats["leaves"], (res.stats, ref.stats)
         assert res.stats["nodes"] == ref.stats["nodes"], (res.stats, ref.stats)
+        assert res.stats["work"] == ref.stats["work_sw"], (res.stats, ref.stats)
     return res, ref
 
 
