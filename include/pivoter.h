@@ -109,7 +109,7 @@ pv_status pv_set_stream(pv_ctx *ctx, void *stream);
  * Tuning: subtrees whose node set has at most dfs_max vertices (1..64) are
  * walked depth first by one wavefront; larger nodes are split so that their
  * hold children are spread over the GPU.  Any value gives the same counts.
- * Default 24 (environment variable PV_DFS_MAX overrides it at pv_init).
+ * Default 32 (environment variable PV_DFS_MAX overrides it at pv_init).
  */
 pv_status pv_set_dfs_max(pv_ctx *ctx, int32_t dfs_max);
 

@@ -106,7 +106,7 @@ struct pv_ctx {
     LevelArgs *h_args = nullptr;
     int *h_io = nullptr;  // pinned readback slots
     int level_blocks[3] = {0, 0, 0};
-    int dfs_max = 24;
+    int dfs_max = 32;
     // device timing (HIP events on the context stream)
     bool timing = false;
     hipEvent_t ev[8] = {};
@@ -122,6 +122,7 @@ struct pv_graph {
     int alpha = 0, subrounds = 0;
     int nheavy = 0, nnonzero = 0;
     DBuf<int> sub, deg, fa, fb, odeg, orow, ocol, scan, small, rcnt, rcursor, order;
+    DBuf<int> lid, uverts, ldeg, lrp, lcol, bcnt;  // solo phase of the peel
     DBuf<PeelCtl> ctl;
     // SCT work buffers
     DBuf<CItem> citem[2];
@@ -338,7 +339,8 @@ extern "C" void pv_graph_free(pv_graph *g) {
     (void)hipStreamSynchronize(g->ctx->stream);
     DBuf<int> *ib[] = {&g->rp, &g->col, &g->sub, &g->deg, &g->fa, &g->fb, &g->odeg, &g->orow,
                        &g->ocol, &g->scan, &g->small, &g->rcnt, &g->rcursor, &g->order,
-                       &g->hu_vl, &g->u_gid, &g->pref_pool};
+                       &g->hu_vl, &g->u_gid, &g->pref_pool, &g->lid, &g->uverts, &g->ldeg,
+                       &g->lrp, &g->lcol, &g->bcnt};
     for (auto *b : ib) b->release();
     g->ctl.release();
     g->citem[0].release();
@@ -382,6 +384,12 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     PVCHK(g->rcursor.ensure((size_t)n + 2));
     PVCHK(g->order.ensure(n));
     PVCHK(g->ctl.ensure(1));
+    PVCHK(g->lid.ensure(n));
+    PVCHK(g->uverts.ensure(PV_SOLO_MAX));
+    PVCHK(g->ldeg.ensure(PV_SOLO_MAX));
+    PVCHK(g->lrp.ensure(PV_SOLO_MAX + 1));
+    PVCHK(g->lcol.ensure((size_t)std::max<long long>(g->nnz, 1)));
+    PVCHK(g->bcnt.ensure(PV_PEEL_MAX_BLOCKS));
     hipStream_t s = c->stream;
     PeelCtl init;
     memset(&init, 0, sizeof init);
@@ -391,8 +399,22 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     HIPCHK(hipMemsetAsync(g->orow.p, 0, sizeof(int), s));
     if (n > 0) {
         if (c->timing) HIPCHK(hipEventRecord(c->ev[0], s));
-        HIPCHK(pv_launch_peel(c->dev, n, g->rp.p, g->col.p, g->deg.p, g->sub.p, g->fa.p, g->fb.p,
-                              g->ctl.p, s));
+        PeelArgs pa;
+        pa.n = n;
+        pa.rp = g->rp.p;
+        pa.col = g->col.p;
+        pa.deg = g->deg.p;
+        pa.sub = g->sub.p;
+        pa.fa = g->fa.p;
+        pa.fb = g->fb.p;
+        pa.ctl = g->ctl.p;
+        pa.lid = g->lid.p;
+        pa.uverts = g->uverts.p;
+        pa.ldeg = g->ldeg.p;
+        pa.lrp = g->lrp.p;
+        pa.lcol = g->lcol.p;
+        pa.bcnt = g->bcnt.p;
+        HIPCHK(pv_launch_peel(c->dev, pa, s));
         if (c->timing) HIPCHK(hipEventRecord(c->ev[1], s));
         HIPCHK(pv_launch_orient(c->dev, n, g->rp.p, g->col.p, g->sub.p, g->odeg.p, g->orow.p,
                                 g->ocol.p, g->small.p + SM_ALPHA, g->scan.p, s));
@@ -405,12 +427,16 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     }
     int *io = c->h_io;
     HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(io + 32, &g->ctl.p->subrounds, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(io + 32, &g->ctl.p->subrounds, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     g->alpha = io[SM_ALPHA];
     g->nheavy = io[SM_BOUNDS];
     g->nnonzero = io[SM_BOUNDS1];
     g->subrounds = io[32];
+    if (n > 0 && io[34]) {
+        snprintf(g_last_error, sizeof g_last_error, "peel grid barrier timed out");
+        return PV_EDEVICE;
+    }
     g->oriented = true;
     if (c->timing && n > 0) {
         g->last.ms_peel = elapsed(c, 0, 1);

@@ -12,12 +12,35 @@ struct DevInfo {
     int lds_per_cu;
 };
 
-// control block of the cooperative peel
+// control block of the cooperative peel (zero-filled before a launch,
+// minv set to INT_MAX)
 struct PeelCtl {
     int cnt[3];          // frontier sizes, rotating by sub-round
     int minv[2];         // smallest remaining degree at a level change
     int subrounds;       // out: number of sub-rounds
     int alpha;           // out: degeneracy (largest level)
+    int err;             // out: a grid barrier timed out
+    unsigned bar_top, bar_gen;
+    unsigned bar_arrive[8 * 32];  // one counter per 128-byte line
+};
+
+#define PV_PEEL_THREADS 1024
+#define PV_PEEL_MAX_BLOCKS 1024
+// the peel's last PV_SOLO_MAX vertices are finished by one workgroup
+#define PV_SOLO_MAX 16384
+
+struct PeelArgs {
+    int n;
+    const int *rp, *col;
+    int *deg, *sub;      // [n]
+    int *fa, *fb;        // frontiers [n]
+    PeelCtl *ctl;
+    int *lid;            // [n] local id in the solo phase, -1 outside it
+    int *uverts;         // [PV_SOLO_MAX] vertex of each local id
+    int *ldeg;           // [PV_SOLO_MAX] degree inside the solo subgraph
+    int *lrp;            // [PV_SOLO_MAX + 1] local CSR rows
+    int *lcol;           // [nnz] local CSR columns
+    int *bcnt;           // [blocks] per-block counts
 };
 
 // Largest out-degree handled by the compact (register) tier.  Roots with
@@ -81,8 +104,7 @@ struct LevelArgs {
 
 hipError_t pv_launch_check_rowptr(int n, long long nnz, const int *rp, int *d_err, hipStream_t s);
 hipError_t pv_launch_validate(int n, const int *rp, const int *col, int *d_err, hipStream_t s);
-hipError_t pv_launch_peel(const DevInfo &dev, int n, const int *rp, const int *col, int *deg,
-                          int *sub, int *fa, int *fb, PeelCtl *ctl, hipStream_t s);
+hipError_t pv_launch_peel(const DevInfo &dev, const PeelArgs &pa, hipStream_t s);
 hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
                             int *odeg, int *orow, int *ocol, int *alpha, int *scan_tmp,
                             hipStream_t s);

@@ -8,17 +8,16 @@
 // the smaller key to the larger, so every out-degree is at most the level at
 // which the vertex left, and the largest level is the degeneracy alpha.
 //
-// One cooperative launch runs the whole peel: a sub-round is one grid-wide
-// barrier.  The frontier of the next sub-round is exactly the set of
-// vertices whose degree an atomic decrement takes from k+1 to k, so every
-// vertex is appended once without rescanning the graph; only a level change
-// scans the remaining vertices.
+// One cooperative launch runs the whole peel.  The frontier of the next
+// sub-round is exactly the set of vertices whose degree an atomic decrement
+// takes from k+1 to k, so every vertex is appended once without rescanning
+// the graph; only a level change scans the remaining vertices.  Sub-rounds
+// end with a grid barrier while the graph is large; its small remainder is
+// finished by one workgroup (see below).
 #include "common.h"
 #include "internal.h"
 
-#include <hip/hip_cooperative_groups.h>
-
-namespace cg = cooperative_groups;
+#include <algorithm>
 
 // ------------------------------------------------------------ validation
 // One wave per vertex: sorted strictly increasing rows, ids in range, no
@@ -59,17 +58,94 @@ __global__ void check_rowptr_kernel(int n, long long nnz, const int *__restrict_
 }
 
 // ------------------------------------------------------------------ peel
+// Grid-wide phase: while more than PV_SOLO_MAX vertices remain, every block
+// takes part and a sub-round ends with a grid barrier.  Solo phase: the
+// remaining subgraph is compacted (local ids, local CSR of the edges among
+// the remaining vertices) and block 0 finishes the peel alone with its
+// degrees and frontiers in LDS and block-level barriers.  Both phases run
+// the same sub-rounds, so the keys are those of the canonical peel.
 
 __device__ __forceinline__ int ld_acquire(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(256) peel_kernel(int n, const int *__restrict__ rp,
-                                                    const int *__restrict__ col,
-                                                    int *__restrict__ deg, int *__restrict__ sub,
-                                                    int *__restrict__ fa, int *__restrict__ fb,
-                                                    PeelCtl *__restrict__ ctl) {
-    cg::grid_group grid = cg::this_grid();
+__device__ __forceinline__ unsigned ld_u(const unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier for a co-resident (cooperative) launch.  Blocks arrive on one
+// of 8 group counters (blocks are spread round-robin over the XCDs), the
+// last of a group arrives on the top counter, and the last group bumps the
+// generation that everyone waits on.  A bounded wait turns a lost block
+// into an error flag instead of a hang; returns false then.
+__device__ bool grid_barrier(PeelCtl *ctl, int nblocks) {
+    __syncthreads();
+    __shared__ int s_ok;
+    if (threadIdx.x == 0) {
+        const int ngroups = nblocks < 8 ? nblocks : 8;
+        const int grp = blockIdx.x % ngroups;
+        const int gsize = (nblocks - grp + ngroups - 1) / ngroups;
+        const unsigned gen = ld_u(&ctl->bar_gen);
+        __threadfence();
+        const unsigned a = atomicAdd(&ctl->bar_arrive[grp * 32], 1u);
+        if (a == (unsigned)gsize - 1) {
+            __hip_atomic_store(&ctl->bar_arrive[grp * 32], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned t = atomicAdd(&ctl->bar_top, 1u);
+            if (t == (unsigned)ngroups - 1) {
+                __hip_atomic_store(&ctl->bar_top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __threadfence();
+                __hip_atomic_store(&ctl->bar_gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        int ok = 1;
+        unsigned spins = 0;
+        while (ld_u(&ctl->bar_gen) == gen) {
+            if (ld_acquire(&ctl->err) != 0 || ++spins > (1u << 24)) {
+                atomicOr(&ctl->err, 1);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __threadfence();
+        s_ok = ok;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// exclusive prefix sum over the block (blockDim.x == PV_PEEL_THREADS);
+// returns the block total in *total
+__device__ int block_excl_scan(int x, int *total) {
+    __shared__ int s_w[PV_PEEL_THREADS / 64 + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int inc = wave_incl_scan(x);
+    if (lane == 63) s_w[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < PV_PEEL_THREADS / 64; i++) {
+            const int t = s_w[i];
+            s_w[i] = acc;
+            acc += t;
+        }
+        s_w[PV_PEEL_THREADS / 64] = acc;
+    }
+    __syncthreads();
+    const int r = s_w[w] + inc - x;
+    *total = s_w[PV_PEEL_THREADS / 64];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
+    const int n = pa.n;
+    const int *__restrict__ rp = pa.rp;
+    const int *__restrict__ col = pa.col;
+    int *__restrict__ deg = pa.deg;
+    int *__restrict__ sub = pa.sub;
+    PeelCtl *__restrict__ ctl = pa.ctl;
+    const int nb = gridDim.x;
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nth = gridDim.x * blockDim.x;
     const int lane = threadIdx.x & 63;
@@ -80,33 +156,33 @@ __global__ void __launch_bounds__(256) peel_kernel(int n, const int *__restrict_
         deg[v] = rp[v + 1] - rp[v];
         sub[v] = -1;
     }
-    grid.sync();
+    if (!grid_barrier(ctl, nb)) return;
 
+    // ---------------------------------------------------- grid-wide phase
     int removed = 0, r = 0, k = 0, nF = 0, alpha = 0;
-    for (;;) {
+    while (n - removed > PV_SOLO_MAX) {
         if (nF == 0) {
-            if (removed >= n) break;
             // level change: k = smallest remaining degree
             int mymin = 0x7fffffff;
             for (int v = tid; v < n; v += nth)
                 if (sub[v] < 0) mymin = min(mymin, deg[v]);
             mymin = wave_min_i32(mymin);
             if (lane == 0 && mymin != 0x7fffffff) atomicMin(&ctl->minv[r & 1], mymin);
-            grid.sync();
+            if (!grid_barrier(ctl, nb)) return;
             k = ld_acquire(&ctl->minv[r & 1]);
             alpha = max(alpha, k);
-            int *F = (r & 1) ? fb : fa;
+            int *F = (r & 1) ? pa.fb : pa.fa;
             for (int v = tid; v < n; v += nth)
                 if (sub[v] < 0 && deg[v] <= k) {
                     sub[v] = r;
                     F[atomicAdd(&ctl->cnt[r % 3], 1)] = v;
                 }
-            grid.sync();
+            if (!grid_barrier(ctl, nb)) return;
             nF = ld_acquire(&ctl->cnt[r % 3]);
-            if (nF == 0) break;  // nothing left (every wave sees the same value)
+            if (nF == 0) break;  // cannot happen while vertices remain
         }
-        const int *F = (r & 1) ? fb : fa;
-        int *Fn = (r & 1) ? fa : fb;
+        const int *F = (r & 1) ? pa.fb : pa.fa;
+        int *Fn = (r & 1) ? pa.fa : pa.fb;
         if (tid == 0) {
             ctl->cnt[(r + 2) % 3] = 0;
             ctl->minv[(r + 1) & 1] = 0x7fffffff;
@@ -127,13 +203,176 @@ __global__ void __launch_bounds__(256) peel_kernel(int n, const int *__restrict_
                 }
             }
         }
-        grid.sync();
+        if (!grid_barrier(ctl, nb)) return;
         removed += nF;
         nF = ld_acquire(&ctl->cnt[(r + 1) % 3]);
         r++;
+    }
+
+    // ------------------------------------ compaction of what is left (U)
+    // U = remaining vertices plus the pending frontier (keys of the pending
+    // frontier are already r; its decrements are still to be done).
+    __shared__ int s_off;
+    const int chunk = (n + nb - 1) / nb;
+    const int lo = min(n, blockIdx.x * chunk), hi = min(n, lo + chunk);
+    {
+        int cnt = 0;
+        for (int v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+            const int s = sub[v];
+            cnt += (s < 0 || s == r) ? 1 : 0;
+        }
+        int tot;
+        (void)block_excl_scan(cnt, &tot);
+        if (threadIdx.x == 0) pa.bcnt[blockIdx.x] = tot;
+    }
+    if (!grid_barrier(ctl, nb)) return;
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int b = 0; b < (int)blockIdx.x; b++) off += pa.bcnt[b];
+        s_off = off;
+    }
+    __syncthreads();
+    {
+        int base = s_off;
+        for (int v0 = lo; v0 < hi; v0 += blockDim.x) {
+            const int v = v0 + threadIdx.x;
+            bool inU = false;
+            if (v < hi) {
+                const int s = sub[v];
+                inU = (s < 0 || s == r);
+            }
+            int tot;
+            const int pos = block_excl_scan(inU ? 1 : 0, &tot);
+            if (v < hi) {
+                pa.lid[v] = inU ? base + pos : -1;
+                if (inU) pa.uverts[base + pos] = v;
+            }
+            base += tot;
+        }
+    }
+    if (!grid_barrier(ctl, nb)) return;
+    const int nu = n - removed;
+    if (nu > PV_SOLO_MAX) {  // only if the grid phase stopped early: report, never overflow
+        if (threadIdx.x == 0) atomicOr(&ctl->err, 2);
+        return;
+    }
+    // induced degree of every vertex of U (one wave per vertex)
+    for (int i = wid; i < nu; i += nw) {
+        const int v = pa.uverts[i];
+        int c = 0;
+        for (int e = rp[v] + lane; e < rp[v + 1]; e += 64) c += (pa.lid[col[e]] >= 0) ? 1 : 0;
+        c = (int)wave_add_u32((uint32_t)c);
+        if (lane == 0) pa.ldeg[i] = c;
+    }
+    if (!grid_barrier(ctl, nb)) return;
+    if (blockIdx.x == 0) {
+        int base = 0;
+        for (int i0 = 0; i0 < nu; i0 += blockDim.x) {
+            const int i = i0 + threadIdx.x;
+            const int x = (i < nu) ? pa.ldeg[i] : 0;
+            int tot;
+            const int pos = block_excl_scan(x, &tot);
+            if (i < nu) pa.lrp[i] = base + pos;
+            base += tot;
+        }
+        if (threadIdx.x == 0) pa.lrp[nu] = base;
+    }
+    if (!grid_barrier(ctl, nb)) return;
+    // local CSR: neighbours inside U, as local ids, in row order
+    {
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        for (int i = wid; i < nu; i += nw) {
+            const int v = pa.uverts[i];
+            int w = pa.lrp[i];
+            const int e1 = rp[v + 1];
+            for (int e0 = rp[v]; e0 < e1; e0 += 64) {
+                const int e = e0 + lane;
+                const int l = (e < e1) ? pa.lid[col[e]] : -1;
+                const uint64_t m = ballot64(l >= 0);
+                if (l >= 0) pa.lcol[w + __popcll(m & below)] = l;
+                w += __popcll(m);
+            }
+        }
+    }
+    if (!grid_barrier(ctl, nb)) return;
+    if (blockIdx.x != 0) return;
+
+    // ------------------------------------------------ solo phase (block 0)
+    __shared__ int s_deg[PV_SOLO_MAX];
+    __shared__ unsigned short s_F[2][PV_SOLO_MAX];
+    __shared__ unsigned char s_alive[PV_SOLO_MAX];
+    __shared__ int s_cnt, s_min;
+    const int *__restrict__ lrp = pa.lrp;
+    const int *__restrict__ lcol = pa.lcol;
+    const int *__restrict__ uverts = pa.uverts;
+    if (threadIdx.x == 0) s_cnt = 0;
+    for (int i = threadIdx.x; i < nu; i += blockDim.x) {
+        s_deg[i] = pa.ldeg[i];
+        s_alive[i] = (sub[uverts[i]] < 0) ? 1 : 0;
+    }
+    __syncthreads();
+    int cur = 0;
+    if (nF > 0) {
+        const int *F = (r & 1) ? pa.fb : pa.fa;
+        for (int j = threadIdx.x; j < nF; j += blockDim.x) s_F[0][j] = (unsigned short)pa.lid[F[j]];
+    }
+    __syncthreads();
+    const int bw = threadIdx.x >> 6, nbw = blockDim.x >> 6;
+    int left = nu;
+    for (;;) {
+        if (nF == 0) {
+            if (left == 0) break;
+            if (threadIdx.x == 0) s_min = 0x7fffffff;
+            __syncthreads();
+            int mymin = 0x7fffffff;
+            for (int i = threadIdx.x; i < nu; i += blockDim.x)
+                if (s_alive[i]) mymin = min(mymin, s_deg[i]);
+            mymin = wave_min_i32(mymin);
+            if (lane == 0) atomicMin(&s_min, mymin);
+            __syncthreads();
+            k = s_min;
+            alpha = max(alpha, k);
+            if (threadIdx.x == 0) s_cnt = 0;
+            __syncthreads();
+            for (int i = threadIdx.x; i < nu; i += blockDim.x)
+                if (s_alive[i] && s_deg[i] <= k) {
+                    s_alive[i] = 0;
+                    sub[uverts[i]] = r;
+                    s_F[cur][atomicAdd(&s_cnt, 1)] = (unsigned short)i;
+                }
+            __syncthreads();
+            nF = s_cnt;
+            __syncthreads();
+            if (nF == 0) break;
+            if (threadIdx.x == 0) s_cnt = 0;
+            __syncthreads();
+        }
+        for (int j = bw; j < nF; j += nbw) {
+            const int i = s_F[cur][j];
+            const int e1 = lrp[i + 1];
+            for (int e = lrp[i] + lane; e < e1; e += 64) {
+                const int w = lcol[e];
+                if (s_alive[w]) {
+                    const int old = atomicSub(&s_deg[w], 1);
+                    if (old == k + 1) {
+                        s_alive[w] = 0;
+                        sub[uverts[w]] = r + 1;
+                        s_F[cur ^ 1][atomicAdd(&s_cnt, 1)] = (unsigned short)w;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        left -= nF;
+        nF = s_cnt;
+        cur ^= 1;
+        r++;
+        __syncthreads();
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
         if (r > n) break;  // each sub-round removes a vertex: never reached
     }
-    if (tid == 0) {
+    if (threadIdx.x == 0) {
         ctl->subrounds = r;
         ctl->alpha = alpha;
     }
@@ -302,18 +541,18 @@ hipError_t pv_launch_validate(int n, const int *rp, const int *col, int *d_err, 
     return hipGetLastError();
 }
 
-hipError_t pv_launch_peel(const DevInfo &dev, int n, const int *rp, const int *col, int *deg,
-                          int *sub, int *fa, int *fb, PeelCtl *ctl, hipStream_t s) {
-    // co-resident grid: enough blocks for the vertex count, at most what fits
+hipError_t pv_launch_peel(const DevInfo &dev, const PeelArgs &pa, hipStream_t s) {
+    // one block per CU (co-resident), a single block when the graph already
+    // fits the solo phase
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, peel_kernel, 256, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, peel_kernel, PV_PEEL_THREADS, 0);
     if (e != hipSuccess) return e;
-    if (per_cu < 1) per_cu = 1;
-    if (per_cu > 4) per_cu = 4;
-    int blocks = grid_for(n, 256 * 4, dev.num_cu * per_cu);
-    void *args[] = {(void *)&n, (void *)&rp, (void *)&col, (void *)&deg, (void *)&sub,
-                    (void *)&fa, (void *)&fb, (void *)&ctl};
-    return hipLaunchCooperativeKernel((const void *)peel_kernel, dim3(blocks), dim3(256), args, 0, s);
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    const int blocks = (pa.n <= PV_SOLO_MAX) ? 1 : std::min(dev.num_cu, PV_PEEL_MAX_BLOCKS);
+    PeelArgs a = pa;
+    void *args[] = {(void *)&a};
+    return hipLaunchCooperativeKernel((const void *)peel_kernel, dim3(blocks), dim3(PV_PEEL_THREADS),
+                                      args, 0, s);
 }
 
 hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,

@@ -1,0 +1,86 @@
+"""Checks at the benchmark's full size (the 1M-vertex Chung-Lu workload), in
+the launch configuration bench.py times.
+
+The oracle cannot walk the whole tree in seconds, so parity here is
+sampled: the peel order is compared for every vertex, per-root counts are
+compared for a seeded sample of roots (light and heavy), and the whole-graph
+results are checked against identities that hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2001_06784_amd import graphgen as gg
+from paper_2001_06784_amd import pivoter as P
+
+pytestmark = pytest.mark.gpu
+K_LO, K_HI = 3, 10
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def full():
+    import torch
+    g = gg.chung_lu_social(n=1_000_000, avg_deg=20.0, gamma=2.3, max_deg=20_000.0, seed=1)
+    _say(f"[fullsize] n={g.n} m={g.m}")
+    ctx = P.pv_init(0, torch.cuda.current_stream().cuda_stream)
+    h = P.pv_graph_load_csr(ctx, g.n, g.row_ptr, g.col)
+    local = torch.zeros((g.n, K_HI - K_LO + 1, 2), dtype=torch.int64, device="cuda:0")
+    res, lovf = P.pv_count(h, reorient=True, local_kind=P.PV_VERTEX, k_lo=K_LO, k_hi=K_HI,
+                           local_out=local.data_ptr())
+    torch.cuda.synchronize()
+    vert = local.cpu().numpy().view(np.uint64)
+    sub = P.pv_graph_export_order(h)
+    yield g, ctx, h, res, lovf, vert, sub
+    P.pv_graph_free(h)
+    P.pv_fini(ctx)
+
+
+def _sum_u128(a):
+    """exact sum of a (..., 2) uint64 limb array over axis 0, as Python ints"""
+    lo = a[..., 0]
+    s_lo_lo = (lo & np.uint64(0xFFFFFFFF)).sum(axis=0, dtype=np.uint64)
+    s_lo_hi = (lo >> np.uint64(32)).sum(axis=0, dtype=np.uint64)
+    s_hi = a[..., 1].sum(axis=0, dtype=np.uint64)
+    return [(int(h) << 64) + (int(b) << 32) + int(c) for h, b, c in zip(s_hi, s_lo_hi, s_lo_lo)]
+
+
+def test_peel_order_full(full):
+    g, ctx, h, res, lovf, vert, sub = full
+    pe = O.peel(g)
+    assert np.array_equal(sub, pe.sub)
+    assert res.stats["alpha"] == pe.alpha
+
+
+def test_identities_full(full):
+    g, ctx, h, res, lovf, vert, sub = full
+    assert res.status == P.PV_OK and lovf == 0
+    assert res.counts[0] == 1 and res.counts[1] == g.n and res.counts[2] == g.m
+    assert res.omega >= 3 and all(c > 0 for c in res.counts[1: res.omega + 1])
+    assert all(c == 0 for c in res.counts[res.omega + 1:])
+    sums = _sum_u128(vert)
+    for i, k in enumerate(range(K_LO, K_HI + 1)):
+        assert sums[i] == k * res.counts[k], k
+
+
+def test_sampled_roots_full(full):
+    g, ctx, h, res, lovf, vert, sub = full
+    od = O.out_degrees(g, sub)
+    rng = np.random.default_rng(81)
+    heavy = np.nonzero(od > 64)[0]
+    light = np.nonzero((od > 0) & (od <= 64))[0]
+    roots = np.concatenate([rng.choice(light, 300, replace=False),
+                            rng.choice(heavy, 12, replace=False),
+                            np.nonzero(od == 0)[0][:5]]).astype(np.int32)
+    got = P.pv_count_roots(h, roots)
+    ref = O.count(g, key=sub, roots=roots)
+    _say(f"[fullsize] sampled roots: {len(roots)} leaves={ref.stats['leaves']}")
+    assert got.counts[1: len(ref.glob)] == ref.glob[1:]
+    assert got.stats["leaves"] == ref.stats["leaves"]
+    assert got.stats["nodes"] == ref.stats["nodes"]

@@ -143,7 +143,7 @@ def test_split_threshold_does_not_change_the_tree(ctx, dfs_max):
     try:
         check_global(ctx, g, f"dfs_max={dfs_max}")
     finally:
-        P.pv_set_dfs_max(ctx, 24)
+        P.pv_set_dfs_max(ctx, 32)
 
 
 # --------------------------------------------------------------- per-vertex
@@ -235,3 +235,18 @@ def test_valid_tiny_csr_is_accepted(ctx):
     res = P.pv_count_global(h)
     P.pv_graph_free(h)
     assert res.counts[:4] == [1, 3, 2, 0]
+
+
+# --------------------------------------------------- peel at larger sizes
+
+@pytest.mark.parametrize("n,deg,seed", [(60000, 12, 71), (200000, 16, 72)])
+def test_peel_order_large(ctx, n, deg, seed):
+    # large enough that the grid-wide phase runs before the one-block phase
+    g = gg.chung_lu(n, deg, 2.3, n // 20, seed)
+    _say(f"[parity] peel n={g.n} m={g.m}")
+    with Loaded(ctx, g) as h:
+        alpha = P.pv_graph_orient(h)
+        sub = P.pv_graph_export_order(h)
+    pe = O.peel(g)
+    assert alpha == pe.alpha
+    assert np.array_equal(sub, pe.sub)
