@@ -109,7 +109,7 @@ pv_status pv_set_stream(pv_ctx *ctx, void *stream);
  * Tuning: subtrees whose node set has at most dfs_max vertices (1..64) are
  * walked depth first by one wavefront; larger nodes are split so that their
  * hold children are spread over the GPU.  Any value gives the same counts.
- * Default 32 (environment variable PV_DFS_MAX overrides it at pv_init).
+ * Default 64 (environment variable PV_DFS_MAX overrides it at pv_init).
  */
 pv_status pv_set_dfs_max(pv_ctx *ctx, int32_t dfs_max);
 
@@ -119,6 +119,14 @@ pv_status pv_set_dfs_max(pv_ctx *ctx, int32_t dfs_max);
  * pv_stats.  Off by default.
  */
 pv_status pv_set_timing(pv_ctx *ctx, int32_t on);
+
+/*
+ * Tuning: a wavefront walks at most this many SCT nodes depth first before
+ * it hands the rest of its subtree (the pending node and the pending hold
+ * children on its stack) to other wavefronts.  Any value in [16, 2^20]
+ * gives the same counts.  Default 4096 (PV_DFS_BUDGET overrides it at pv_init).
+ */
+pv_status pv_set_dfs_budget(pv_ctx *ctx, int32_t nodes);
 
 /* Text of the last HIP error seen by this host thread (static storage). */
 const char *pv_last_error(void);

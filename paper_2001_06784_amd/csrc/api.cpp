@@ -64,6 +64,9 @@ extern "C" const char *pv_strerror(pv_status s) {
 
 extern "C" const char *pv_last_error(void) { return g_last_error; }
 
+// waves per block of the level kernel
+#define WAVES_PER_LAUNCH_BLOCK 4
+
 // ------------------------------------------------------------ handles
 
 template <class T>
@@ -97,7 +100,7 @@ struct pv_ctx {
     DevInfo dev{};
     // exact binomials
     int bn = 0;
-    DBuf<uint64_t> tab, tab64;
+    DBuf<uint64_t> tab, tab64, tab_pad;
     DBuf<uint8_t> bad;
     DBuf<int> fits64;
     int fits64_h[16] = {0};
@@ -105,8 +108,9 @@ struct pv_ctx {
     DBuf<LevelArgs> d_args;
     LevelArgs *h_args = nullptr;
     int *h_io = nullptr;  // pinned readback slots
-    int level_blocks[3] = {0, 0, 0};
-    int dfs_max = 32;
+    int level_blocks[3][3] = {};  // [k-slot variant][unit kind]
+    int dfs_max = 64;
+    int dfs_budget = 2048;
     // device timing (HIP events on the context stream)
     bool timing = false;
     hipEvent_t ev[8] = {};
@@ -137,10 +141,11 @@ struct pv_graph {
     pv_stats last{};
 };
 
-// small device scalars in g->small: [0] alpha, [1] next, [2] mw_out_n, [3] c_out_n,
-// [4] flags, [5] u_n, [6] pref_n, [7] omega, [8] lovf, [9] err, [10..11] bounds
-enum { SM_ALPHA = 0, SM_NEXT, SM_MWN, SM_CN, SM_FLAGS, SM_UN, SM_PREFN, SM_OMEGA, SM_LOVF,
-       SM_ERR, SM_BOUNDS, SM_BOUNDS1, SM_COUNT };
+// small device scalars in g->small: alpha, three work cursors, emitted multi-word and
+// compact item counts, flags, universes, prefix pool, omega, local overflow, error,
+// root bounds
+enum { SM_ALPHA = 0, SM_NEXT, SM_NEXT1, SM_NEXT2, SM_MWN, SM_CN, SM_FLAGS, SM_UN, SM_PREFN,
+       SM_OMEGA, SM_LOVF, SM_ERR, SM_BOUNDS, SM_BOUNDS1, SM_COUNT };
 
 extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
     if (!out) return PV_EINVAL;
@@ -173,11 +178,13 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
         delete c;
         return PV_ENOMEM;
     }
-    for (int kl = 0; kl < 3; kl++) {
-        int per_cu = pv_level_blocks_per_cu(kl == 0 ? 0 : (kl == 1 ? 8 : 16));
-        c->level_blocks[kl] = std::max(1, per_cu) * c->dev.num_cu;
-    }
+    for (int kl = 0; kl < 3; kl++)
+        for (int mode = 0; mode < 3; mode++) {
+            int per_cu = pv_level_blocks_per_cu(kl == 0 ? 0 : (kl == 1 ? 8 : 16), mode);
+            c->level_blocks[kl][mode] = std::max(1, per_cu) * c->dev.num_cu;
+        }
     if (const char *env = getenv("PV_DFS_MAX")) c->dfs_max = std::max(1, std::min(64, atoi(env)));
+    if (const char *env = getenv("PV_DFS_BUDGET")) c->dfs_budget = std::max(16, std::min(1 << 20, atoi(env)));
     for (auto &ev : c->ev)
         if (hipEventCreate(&ev) != hipSuccess) {
             pv_fini(c);
@@ -192,6 +199,7 @@ extern "C" void pv_fini(pv_ctx *c) {
     (void)hipSetDevice(c->device);
     c->tab.release();
     c->tab64.release();
+    c->tab_pad.release();
     c->bad.release();
     c->fits64.release();
     c->d_args.release();
@@ -205,6 +213,12 @@ extern "C" void pv_fini(pv_ctx *c) {
 extern "C" pv_status pv_set_stream(pv_ctx *c, void *stream) {
     if (!c) return PV_EINVAL;
     c->stream = (hipStream_t)stream;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_set_dfs_budget(pv_ctx *c, int32_t nodes) {
+    if (!c || nodes < 16 || nodes > (1 << 20)) return PV_EINVAL;
+    c->dfs_budget = nodes;
     return PV_OK;
 }
 
@@ -236,7 +250,9 @@ static pv_status ensure_binomials(pv_ctx *c, int need) {
     PVCHK(c->fits64.ensure(16));
     std::vector<int> ones(16, 1);
     HIPCHK(hipMemcpyAsync(c->fits64.p, ones.data(), 16 * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    PVCHK(c->tab_pad.ensure((size_t)(bn + 1) * 32));
     HIPCHK(pv_launch_binomials(bn, c->tab.p, c->bad.p, c->tab64.p, c->fits64.p, c->stream));
+    HIPCHK(pv_launch_binom_pad(bn, c->tab.p, c->tab_pad.p, c->stream));
     HIPCHK(hipMemcpyAsync(c->fits64_h, c->fits64.p, 16 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->bn = bn;
@@ -536,6 +552,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.nlight = (ch == 0) ? rq.nlight : 0;
                 a.kmax = rq.kmax;
                 a.dfs_max = c->dfs_max;
+                a.dfs_budget = c->dfs_budget;
                 a.level = level;
                 a.n_mw_in = n_mw;
                 a.n_c_in = n_c;
@@ -568,28 +585,39 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.vout = rq.vout;
                 a.klo = rq.klo;
                 a.K = rq.K;
-                a.bin64 = c->tab64.p;
+                a.bin_pad = c->tab_pad.p;
                 a.lovf = g->small.p + SM_LOVF;
                 const long long units = (long long)n_mw + n_c + (level == 0 ? (long long)a.nheavy + a.nlight : 0);
                 if (units == 0) break;
                 *c->h_args = a;
-                HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 3 * sizeof(int), s));
+                HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 5 * sizeof(int), s));
                 HIPCHK(hipMemcpyAsync(c->d_args.p, c->h_args, sizeof(LevelArgs), hipMemcpyHostToDevice, s));
                 const int kli = rq.kl == 0 ? 0 : (rq.kl <= 8 ? 1 : 2);
-                const int blocks = (int)std::min<long long>(c->level_blocks[kli], (units + 3) / 4);
+                const long long mode_units[3] = {(long long)n_mw + (level == 0 ? a.nheavy : 0), n_c,
+                                                 level == 0 ? a.nlight : 0};
                 if (c->timing) HIPCHK(hipEventRecord(c->ev[3], s));
-                HIPCHK(pv_launch_level(c->d_args.p, rq.kl, std::max(1, blocks), s));
+                for (int mode = 0; mode < 3; mode++) {
+                    if (mode_units[mode] == 0) continue;
+                    const long long want = (mode_units[mode] + WAVES_PER_LAUNCH_BLOCK - 1) / WAVES_PER_LAUNCH_BLOCK;
+                    const int blocks = (int)std::min<long long>(c->level_blocks[kli][mode], want);
+                    HIPCHK(pv_launch_level(c->d_args.p, rq.kl, mode, std::max(1, blocks), s));
+                }
                 if (c->timing) HIPCHK(hipEventRecord(c->ev[4], s));
                 HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
                 levels++;
                 if (c->timing) ms_levels += elapsed(c, 3, 4);
                 if (io[SM_FLAGS] & 1) {
+                    // a work buffer filled up: the counters kept counting every
+                    // request, so they give the demand of this level; grow to it
                     overflow = true;
-                    if ((size_t)io[SM_CN] > g->c_cap) g->c_cap *= 4;
-                    if ((size_t)io[SM_MWN] > g->mw_cap) g->mw_cap *= 4;
-                    if ((size_t)io[SM_UN] >= g->u_cap) g->u_cap *= 4;
-                    if ((size_t)io[SM_PREFN] >= g->pref_cap) g->pref_cap *= 4;
+                    auto grow = [](size_t &cap, long long demand) {
+                        if ((size_t)demand >= cap) cap = std::max(cap * 2, (size_t)(demand * 5 / 4) + 1024);
+                    };
+                    grow(g->c_cap, (unsigned)io[SM_CN]);
+                    grow(g->mw_cap, (unsigned)io[SM_MWN]);
+                    grow(g->u_cap, (unsigned)io[SM_UN]);
+                    grow(g->pref_cap, (unsigned)io[SM_PREFN]);
                     break;
                 }
                 n_mw = io[SM_MWN];

@@ -40,8 +40,20 @@ __device__ __forceinline__ uint64_t writelane64(uint64_t x, uint64_t v, int l) {
     return (lane_id() == l) ? v : x;
 }
 
+// A value every lane holds alike, moved to scalar registers.  Values that
+// arrive through vector loads stay in VGPRs otherwise, and then every
+// bookkeeping step and branch on them costs vector instructions and exec
+// masking.
 __device__ __forceinline__ uint32_t uniform32(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)x);
+}
+
+__device__ __forceinline__ int uniformi(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // ------------------------------------------------- wave reductions (DPP)
@@ -49,9 +61,12 @@ __device__ __forceinline__ uint32_t uniform32(uint32_t x) {
 // lane of the wave must be active.  Quad swaps, half-row and row mirrors
 // reduce each 16-lane row; row_bcast15/31 fold the four rows into lane 63.
 
+// Lanes of rows outside ROWMASK read 0, the identity of unsigned max, so
+// max(x, dpp(x)) leaves them unchanged; with that `old` value the compiler
+// folds the move into the max (v_max_u32 with a DPP source).
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ uint32_t dpp_mov(uint32_t x) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, ROWMASK, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWMASK, 0xF, false);
 }
 
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {

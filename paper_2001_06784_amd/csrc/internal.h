@@ -46,17 +46,21 @@ struct PeelArgs {
 // Largest out-degree handled by the compact (register) tier.  Roots with
 // |N+(v)| <= LIGHT_MAX are built entirely in registers; larger roots start in
 // the multi-word tier and drop into the compact tier once |S| <= LIGHT_MAX.
-#define PV_LIGHT_MAX 64
-
-// Leaves with h <= PV_HREG and p < 64 are counted in per-lane registers.
-#define PV_HREG 8
+// 62 rather than 64 keeps lanes 62 and 63 free for the per-vertex totals.
+#define PV_LIGHT_MAX 62
 
 // ------------------------------------------------------------- item types
 
-struct CItem {            // compact-tier subproblem (32 bytes)
-    uint64_t S, H, P;     // node set; hold / pivot members inside the universe
-    uint32_t uni;         // universe index
-    uint32_t hp;          // h | p << 16 (totals along the whole path)
+// Compact-tier subproblem (32 bytes), one of two kinds:
+//   node item  (uni bit 31 clear): the SCT node S with hold / pivot members
+//              H, P inside the universe; hp = h | p << 16 (path totals)
+//   frame item (uni bit 31 set): an unfinished node whose pivot child is
+//              done; S is its set with the visited hold children removed,
+//              hp = pivot | h << 6 | p << 19 as on the walk's stack
+struct CItem {
+    uint64_t S, H, P;
+    uint32_t uni;
+    uint32_t hp;
 };
 
 struct LevelArgs {
@@ -66,6 +70,7 @@ struct LevelArgs {
     int heavy_base, nheavy;  // level 0: heavy roots order[heavy_base, +nheavy)
     int light_base, nlight;  // level 0: light roots order[light_base, +nlight)
     int kmax, dfs_max;
+    int dfs_budget;          // nodes a wave walks depth first before splitting
     // level input
     int level;
     int n_mw_in, n_c_in;
@@ -87,7 +92,7 @@ struct LevelArgs {
     int2 *u_pref;            // [cap] {offset, length} into pref pool (local only)
     int *u_n, u_cap;
     int *pref_pool, *pref_n, pref_cap;
-    // work cursor of this launch
+    // work cursors, one per unit kind
     int *next;
     // outputs
     unsigned long long *hist;
@@ -97,7 +102,7 @@ struct LevelArgs {
     // local (per-vertex) counts
     uint64_t *vout;                // [n][K] u128
     int klo, K;
-    const uint64_t *bin64;         // C(a,b), b < 16, row stride 16
+    const uint64_t *bin_pad;       // padded 64-bit binomials, see VertexSink
     int *lovf;
 };
 
@@ -112,14 +117,19 @@ hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *cn
                                 int *order, int *bounds, int light_max, hipStream_t s);
 
 // SCT build + leaf read-off
+// unit kinds of a level launch
+#define PV_UNITS_MW 0
+#define PV_UNITS_ITEMS 1
+#define PV_UNITS_LIGHT 2
 // `a` is a device pointer to the launch arguments
-hipError_t pv_launch_level(const LevelArgs *a, int kl, int blocks, hipStream_t s);
-int pv_level_blocks_per_cu(int kl);
+hipError_t pv_launch_level(const LevelArgs *a, int kl, int mode, int blocks, hipStream_t s);
+int pv_level_blocks_per_cu(int kl, int mode);
 hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsigned long long *hist,
                                 int hd, unsigned long long *counters, uint64_t *vout, int klo, int K,
                                 hipStream_t s);
 hipError_t pv_launch_binomials(int bn, uint64_t *tab128, uint8_t *bad, uint64_t *tab64, int *fits64,
                                hipStream_t s);
+hipError_t pv_launch_binom_pad(int bn, const uint64_t *tab128, uint64_t *pad, hipStream_t s);
 hipError_t pv_launch_finalize(const unsigned long long *hist, int hd, const uint64_t *tab128,
                               const uint8_t *bad, int bn, int kcap, int kmax, int c0,
                               uint64_t *counts, uint64_t *ovf_words, int *omega, hipStream_t s);

@@ -36,119 +36,148 @@
 
 // ------------------------------------------------------------------ sinks
 
-// Global counts: leaf (h,p) -> L[h][p] += 1.  Lane l keeps L[h][l] for
-// h = 1..8 in registers; other leaves go straight to the device histogram.
+// Global counts: leaf (h,p) -> L[h][p] += 1.  The workgroup keeps the bins
+// h < PV_LDS_H, p < 64 as u64 counters in LDS (one LDS atomic per leaf, no
+// hot global addresses: in dense cores most leaves share a handful of (h,p)
+// bins); rarer leaves go straight to the device histogram.  The LDS bins
+// are added to the device histogram when the workgroup ends.
+#define PV_LDS_H 32
 struct GlobalSink {
-    uint32_t c1, c2, c3, c4, c5, c6, c7, c8;
-    uint32_t pending;  // leaves since the last flush (wave-uniform)
+    unsigned long long *bins;   // LDS [PV_LDS_H][64], shared by the workgroup
+    unsigned long long *hist;   // wave-uniform copies of the arguments
+    int hd;
     unsigned long long leaves;
 
-    __device__ void reset() {
-        c1 = c2 = c3 = c4 = c5 = c6 = c7 = c8 = 0;
-        pending = 0;
+    __device__ void init(const LevelArgs &a, unsigned long long *lds_bins) {
+        bins = lds_bins;
+        hist = (unsigned long long *)uniform64((uint64_t)a.hist);
+        hd = uniformi(a.hd);
+        leaves = 0;
     }
 
-    __device__ void flush(int lane, unsigned long long *hist, int hd) {
-        if (lane < hd) {
-            if (c1) atomicAdd(&hist[1 * hd + lane], (unsigned long long)c1);
-            if (c2 && 2 < hd) atomicAdd(&hist[2 * hd + lane], (unsigned long long)c2);
-            if (c3 && 3 < hd) atomicAdd(&hist[3 * hd + lane], (unsigned long long)c3);
-            if (c4 && 4 < hd) atomicAdd(&hist[4 * hd + lane], (unsigned long long)c4);
-            if (c5 && 5 < hd) atomicAdd(&hist[5 * hd + lane], (unsigned long long)c5);
-            if (c6 && 6 < hd) atomicAdd(&hist[6 * hd + lane], (unsigned long long)c6);
-            if (c7 && 7 < hd) atomicAdd(&hist[7 * hd + lane], (unsigned long long)c7);
-            if (c8 && 8 < hd) atomicAdd(&hist[8 * hd + lane], (unsigned long long)c8);
-        }
-        reset();
-    }
+    __device__ void add_leaves(uint32_t k, int) { leaves += k; }
 
-    __device__ __forceinline__ void leaf(int h, int p, int lane, unsigned long long *hist, int hd) {
-        leaves++;
-        if (h <= PV_HREG && p < 64) {
-            const uint32_t inc = (lane == p) ? 1u : 0u;
-            switch (h) {
-                case 1: c1 += inc; break;
-                case 2: c2 += inc; break;
-                case 3: c3 += inc; break;
-                case 4: c4 += inc; break;
-                case 5: c5 += inc; break;
-                case 6: c6 += inc; break;
-                case 7: c7 += inc; break;
-                default: c8 += inc; break;
-            }
-            if (++pending == 0x7fffffffu) flush(lane, hist, hd);
-        } else if (lane == 0) {
-            atomicAdd(&hist[(long long)h * hd + p], 1ull);
+    __device__ __forceinline__ void leaf(int h, int p, int lane) {
+        if (lane == 0) {
+            if (h < PV_LDS_H && p < 64) atomicAdd(&bins[h * 64 + p], 1ull);
+            else atomicAdd(&hist[(long long)h * hd + p], 1ull);
         }
     }
 };
 
-__device__ __forceinline__ uint64_t bin_at(const uint64_t *bin64, int a, int b) {
-    return (b < 0 || a < 0 || b > a) ? 0ull : bin64[a * 16 + b];
+// Load through the constant address space: uniform addresses become scalar
+// (s_load) loads instead of vector loads with full memory latency.  Only for
+// data no wave writes during the launch (the scalar cache does not see
+// vector stores): the binomial table.
+__device__ __forceinline__ uint64_t ldc64(const uint64_t *p) {
+    return *(const __attribute__((address_space(4))) uint64_t *)(uintptr_t)p;
 }
 
-// Per-vertex counts (Alg. 2 steps ht and pt).  Lane j accumulates the
-// contributions of universe member j for k = klo..klo+K-1; lane kk < K
-// accumulates the totals owed to every vertex above the universe (TH for
-// hold vertices, TP for pivot vertices).
+// Per-vertex counts (Alg. 2 steps ht and pt).  Lane j < 62 accumulates the
+// contributions of universe member j for k = klo..klo+K-1 (members sit on
+// lanes 0..61: compact universes hold at most PV_LIGHT_MAX = 62 vertices).
+// Lane 62 accumulates what every hold vertex above the universe is owed
+// (sum of C(p, k-h)) and lane 63 what every pivot vertex above it is owed
+// (sum of C(p-1, k-h-1)), with the same instructions as a member.
+//
+// Binomials come from a padded table: row a (a = -1..alpha) holds C(a, j)
+// for j = -16..15 at [(a + 1) * 32 + j + 16], zero outside 0 <= j <= a, so
+// the K values of a leaf are one contiguous, range-check-free segment.
 template <int KL>
 struct VertexSink {
     uint64_t lo[KL > 0 ? KL : 1], hi[KL > 0 ? KL : 1];
-    uint64_t thl, thh, tpl, tph;
+    // wave-uniform copies of the arguments
+    const uint64_t *tab;
+    uint64_t *vout;
+    const int *pool;
+    int *lovf;
+    int klo, K, khi;
+
+    __device__ void init(const LevelArgs &a) {
+        tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
+        vout = (uint64_t *)uniform64((uint64_t)a.vout);
+        pool = (const int *)uniform64((uint64_t)a.pref_pool);
+        lovf = (int *)uniform64((uint64_t)a.lovf);
+        klo = uniformi(a.klo);
+        K = uniformi(a.K);
+        khi = klo + K - 1;
+        reset();
+    }
 
     __device__ void reset() {
 #pragma unroll
         for (int i = 0; i < KL; i++) lo[i] = hi[i] = 0;
-        thl = thh = tpl = tph = 0;
     }
 
     __device__ __forceinline__ void leaf(int h, int p, uint64_t H, uint64_t P, int lane,
-                                         const LevelArgs &a) {
-        const bool inH = (H >> lane) & 1, inP = (P >> lane) & 1;
-        const int kfrom = max(a.klo, h), kto = min(a.klo + a.K - 1, h + p);
+                                         const LevelArgs &) {
+        // nothing for k <= khi when h > khi (every clique of the leaf has
+        // at least h vertices), nor when h + p < klo
+        if (h > khi || h + p < klo) return;
+        const bool inH = ((H >> lane) & 1) || lane == 62;
+        const bool inP = ((P >> lane) & 1) || lane == 63;
+        const uint64_t *rowH = tab + (p + 1) * 32 + (klo - h + 16);  // C(p, k-h)
+        const uint64_t *rowP = tab + p * 32 + (klo - h + 15);        // C(p-1, k-h-1)
 #pragma unroll
         for (int kk = 0; kk < KL; kk++) {
-            const int k = a.klo + kk;
-            if (k >= kfrom && k <= kto) {
-                const uint64_t bH = bin_at(a.bin64, p, k - h);
-                const uint64_t bP = bin_at(a.bin64, p - 1, k - h - 1);
+            if (kk < K) {
+                const uint64_t bH = ldc64(rowH + kk), bP = ldc64(rowP + kk);
                 const uint64_t v = inH ? bH : (inP ? bP : 0ull);
                 lo[kk] += v;
                 hi[kk] += (lo[kk] < v) ? 1ull : 0ull;
             }
         }
-        if (lane < a.K) {
-            const int i = a.klo + lane - h;
-            const uint64_t bH = bin_at(a.bin64, p, i);
-            const uint64_t bP = bin_at(a.bin64, p - 1, i - 1);
-            thl += bH;
-            thh += (thl < bH) ? 1ull : 0ull;
-            tpl += bP;
-            tph += (tpl < bP) ? 1ull : 0ull;
-        }
     }
 
     // members: lane j < nm owns vertex gid; prefix: `root` (a hold vertex,
     // or -1) plus pool[pref.x .. pref.x + pref.y)
-    __device__ void flush(int lane, int nm, int gid, int root, int2 pref, const LevelArgs &a) {
+    __device__ void flush(int lane, int nm, int gid, int root, int2 pref, const LevelArgs &) {
         bool ovf = false;
         if (lane < nm) {
 #pragma unroll
             for (int kk = 0; kk < KL; kk++)
-                if (kk < a.K && (lo[kk] | hi[kk]))
-                    ovf |= atomic_add_u128(a.vout + 2 * ((long long)gid * a.K + kk), lo[kk], hi[kk]);
+                if (kk < K && (lo[kk] | hi[kk]))
+                    ovf |= atomic_add_u128(vout + 2 * ((long long)gid * K + kk), lo[kk], hi[kk]);
         }
-        if (root >= 0 && lane < a.K && (thl | thh))
-            ovf |= atomic_add_u128(a.vout + 2 * ((long long)root * a.K + lane), thl, thh);
-        for (int i = 0; i < pref.y; i++) {
-            const int e = a.pref_pool[pref.x + i];
-            const int x = e & 0x7fffffff;
-            const bool isP = (e >> 31) & 1;
-            const uint64_t l = isP ? tpl : thl, hh = isP ? tph : thh;
-            if (lane < a.K && (l | hh))
-                ovf |= atomic_add_u128(a.vout + 2 * ((long long)x * a.K + lane), l, hh);
+        root = uniformi(root);
+        pref.x = uniformi(pref.x);
+        pref.y = uniformi(pref.y);
+        const int npref = pref.y + (root >= 0 ? 1 : 0);
+        if (npref > 0) {
+            // lane kk < K takes the owed totals for k = klo + kk from lanes 62/63
+            uint64_t thl = 0, thh = 0, tpl = 0, tph = 0;
+#pragma unroll
+            for (int kk = 0; kk < KL; kk++) {
+                if (kk < K) {
+                    const uint64_t a = readlane64(lo[kk], 62), b = readlane64(hi[kk], 62);
+                    const uint64_t c = readlane64(lo[kk], 63), d = readlane64(hi[kk], 63);
+                    if (lane == kk) {
+                        thl = a;
+                        thh = b;
+                        tpl = c;
+                        tph = d;
+                    }
+                }
+            }
+            for (int i = 0; i < npref; i++) {
+                int x;
+                bool isP;
+                if (root >= 0 && i == 0) {
+                    x = root;
+                    isP = false;
+                } else {
+                    // a plain load: the multi-word tier writes pool entries in
+                    // the same launch, and the scalar cache would not see them
+                    const int e = pool[pref.x + i - (root >= 0 ? 1 : 0)];
+                    x = e & 0x7fffffff;
+                    isP = (e >> 31) & 1;
+                }
+                const uint64_t l = isP ? tpl : thl, hh = isP ? tph : thh;
+                if (lane < K && (l | hh))
+                    ovf |= atomic_add_u128(vout + 2 * ((long long)x * K + lane), l, hh);
+            }
         }
-        if (ovf) atomicOr(a.lovf, 1);
+        if (ovf) atomicOr(lovf, 1);
         reset();
     }
 };
@@ -159,68 +188,142 @@ struct Ctr {
     unsigned long long nodes, work;
 };
 
+template <int KL>
+__device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelArgs &a,
+                             int root, uint64_t Hw, uint64_t Pw, const int *vl, int W,
+                             int2 &pref);
+
 // ------------------------------------------------------ compact-tier DFS
 // Walk the whole subtree of node (S, H, P, h, p) of a compact universe
 // whose row for member `lane` is A.  Depth first, stack in lane-indexed
 // registers (frame t in lane t; at most 63 frames since every frame's set
 // is a strict superset of the next one's).
 
+// After dfs_budget visited nodes the walk stops and hands the rest of its
+// subtree to the next level: the node it was about to visit becomes a node
+// item and every frame on its stack a frame item (the frame's remaining set,
+// pivot and path), which the receiving wave resumes by walking that frame's
+// remaining hold children.  The universe is written out first if it only
+// lived in registers.  So no single wave walks an unbounded subtree, and a
+// split hands over depth + 1 items however wide the frames are.
 template <int KL>
 __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int h, int p, int lane,
                             const LevelArgs &a, GlobalSink &gs, VertexSink<KL> &vs,
-                            Ctr &ct) {
+                            Ctr &ct, int &uni, int nm, int gid, int root, bool from_frame,
+                            uint32_t fmeta) {
     constexpr bool LOCAL = KL > 0;
     uint64_t stS = 0, stH = 0, stP = 0;
     uint32_t stM = 0;
     int depth = 0;
+    S = uniform64(S);
+    H = uniform64(H);
+    P = uniform64(P);
+    h = uniformi(h);
+    p = uniformi(p);
+    // per-call counters: a call visits at most dfs_budget + 128 <= 2^20 + 128
+    // nodes and adds at most 2080 work per node, so 32 bits suffice
+    uint32_t nodes = 0, work = 0, nleaves = 0;
+    const int kmax = uniformi(a.kmax);
+    const uint32_t limit = (uint32_t)uniformi(a.dfs_budget);
+    bool visit = true;
+    if (uniformi(from_frame ? 1 : 0)) {
+        // resume an unfinished frame: only its remaining hold children are
+        // left (S is the frame's set with the visited ones removed)
+        stS = writelane64(stS, S, 0);
+        if (LOCAL) {
+            stH = writelane64(stH, H, 0);
+            stP = writelane64(stP, P, 0);
+        }
+        stM = writelane32(stM, uniform32(fmeta), 0);
+        depth = 1;
+        visit = false;
+    }
     for (;;) {
-        ct.nodes++;
-        if (S != 0) {
-            const int s = __popcll(S);
-            ct.work += (unsigned long long)s;
-            const bool in = (S >> lane) & 1;
-            const uint32_t c = (uint32_t)__popcll(A & S);
-            const uint32_t key = in ? (((c + 1u) << 6) | (uint32_t)(63 - lane)) : 0u;
-            const uint32_t best = wave_max_u32(key);
-            const int piv = 63 - (int)(best & 63u);
-            const int pc = (int)(best >> 6) - 1;
-            const uint64_t pbit = 1ull << piv;
-            if (pc + 1 == s) {
-                // the pivot sees all of S: no hold child.  If every member
-                // does, S is a clique and its pivot chain ends in one leaf.
-                if (ballot64(in && (int)c + 1 != s) == 0) {
-                    ct.nodes += (unsigned long long)s;
-                    ct.work += (unsigned long long)s * (unsigned long long)(s - 1) / 2;
-                    if (LOCAL) P |= S;
-                    p += s;
+        if (visit) {
+            if (nodes >= limit && depth > 0) {
+                // ---- split: the pending node and every stack frame become items
+                if (uni < 0) {
+                    int2 pref;
+                    uni = make_universe<KL>(A, nm, gid, lane, a, root, 0ull, 0ull, nullptr, 0, pref);
+                    if (uni < 0) break;  // buffers full: the host reruns with larger ones
+                }
+                const int total = depth + 1;
+                int slot = 0;
+                if (lane == 0) slot = atomicAdd(a.c_out_n, total);
+                slot = bcast0(slot);
+                if (slot + total > a.c_cap) {
+                    if (lane == 0) atomicOr(a.flags, 1);
+                    break;
+                }
+                CItem it;
+                if (lane == 0) {
+                    it.S = S;
+                    it.H = H;
+                    it.P = P;
+                    it.uni = (uint32_t)uni;
+                    it.hp = (uint32_t)h | ((uint32_t)p << 16);
+                    a.c_out[slot] = it;
+                }
+                if (lane < depth) {  // lane t holds frame t
+                    it.S = stS;
+                    it.H = LOCAL ? stH : 0ull;
+                    it.P = LOCAL ? stP : 0ull;
+                    it.uni = (uint32_t)uni | 0x80000000u;
+                    it.hp = stM;
+                    a.c_out[slot + 1 + lane] = it;
+                }
+                break;
+            }
+            nodes++;
+            if (S != 0) {
+                const int s = __popcll(S);
+                work += (uint32_t)s;
+                const bool in = (S >> lane) & 1;
+                const uint32_t c = (uint32_t)__popcll(A & S);
+                const uint32_t key = in ? (((c + 1u) << 6) | (uint32_t)(63 - lane)) : 0u;
+                const uint32_t best = wave_max_u32(key);
+                const int piv = 63 - (int)(best & 63u);
+                const int pc = (int)(best >> 6) - 1;
+                const uint64_t pbit = 1ull << piv;
+                if (pc + 1 == s) {
+                    // the pivot sees all of S: no hold child.  If every member
+                    // does, S is a clique and its pivot chain ends in one leaf.
+                    if (ballot64(in && (int)c + 1 != s) == 0) {
+                        nodes += (uint32_t)s;
+                        work += (uint32_t)(s * (s - 1) / 2);
+                        if (LOCAL) P |= S;
+                        p += s;
+                    } else {
+                        S &= ~pbit;
+                        if (LOCAL) P |= pbit;
+                        p++;
+                        continue;
+                    }
                 } else {
-                    S &= ~pbit;
+                    const uint64_t Ap = readlane64(A, piv);
+                    if (!(kmax > 0 && h + 1 > kmax)) {
+                        stS = writelane64(stS, S, depth);
+                        if (LOCAL) {
+                            stH = writelane64(stH, H, depth);
+                            stP = writelane64(stP, P, depth);
+                        }
+                        stM = writelane32(stM, (uint32_t)piv | ((uint32_t)h << 6) | ((uint32_t)p << 19),
+                                          depth);
+                        depth++;
+                    }
+                    S &= Ap;
                     if (LOCAL) P |= pbit;
                     p++;
                     continue;
                 }
-            } else {
-                const uint64_t Ap = readlane64(A, piv);
-                if (!(a.kmax > 0 && h + 1 > a.kmax)) {
-                    stS = writelane64(stS, S, depth);
-                    if (LOCAL) {
-                        stH = writelane64(stH, H, depth);
-                        stP = writelane64(stP, P, depth);
-                    }
-                    stM = writelane32(stM, (uint32_t)piv | ((uint32_t)h << 6) | ((uint32_t)p << 19),
-                                      depth);
-                    depth++;
-                }
-                S &= Ap;
-                if (LOCAL) P |= pbit;
-                p++;
-                continue;
             }
+            // a leaf: S is empty (or a clique folded into P above)
+            nleaves++;
+            gs.leaf(h, p, lane);
+            if (LOCAL) vs.leaf(h, p, H, P, lane, a);
         }
-        // a leaf: S is empty (or a clique folded into P above)
-        gs.leaf(h, p, lane, a.hist, a.hd);
-        if (LOCAL) vs.leaf(h, p, H, P, lane, a);
-        if (depth == 0) return;
+        visit = true;
+        if (depth == 0) break;
         // next hold child of the top frame
         const int t = depth - 1;
         const uint64_t Sf = readlane64(stS, t);
@@ -239,6 +342,9 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
             P = readlane64(stP, t);
         }
     }
+    ct.nodes += nodes;
+    ct.work += work;
+    gs.add_leaves(nleaves, lane);
 }
 
 // ---------------------------------------------------- compact-tier chain
@@ -249,12 +355,21 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
 template <int KL>
 __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int h, int p, int uni,
                             int nm, int gid, int root, int2 pref, int lane, const LevelArgs &a,
-                            GlobalSink &gs, VertexSink<KL> &vs, Ctr &ct) {
+                            GlobalSink &gs, VertexSink<KL> &vs, Ctr &ct, bool from_frame = false,
+                            uint32_t fmeta = 0) {
     constexpr bool LOCAL = KL > 0;
+    S = uniform64(S);
+    H = uniform64(H);
+    P = uniform64(P);
+    h = uniformi(h);
+    p = uniformi(p);
+    uni = uniformi(uni);
+    nm = uniformi(nm);
     for (;;) {
         const int s = __popcll(S);
-        if (s <= a.dfs_max || uni < 0) {
-            compact_dfs<KL>(A, S, H, P, h, p, lane, a, gs, vs, ct);
+        if (from_frame || s <= a.dfs_max || uni < 0) {
+            compact_dfs<KL>(A, S, H, P, h, p, lane, a, gs, vs, ct, uni, nm, gid, root, from_frame,
+                            fmeta);
             break;
         }
         ct.nodes++;
@@ -272,7 +387,8 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                 ct.work += (unsigned long long)s * (unsigned long long)(s - 1) / 2;
                 if (LOCAL) P |= S;
                 p += s;
-                gs.leaf(h, p, lane, a.hist, a.hd);
+                gs.leaf(h, p, lane);
+                gs.add_leaves(1, lane);
                 if (LOCAL) vs.leaf(h, p, H, P, lane, a);
                 break;
             }
@@ -307,7 +423,8 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
         if (LOCAL) P |= pbit;
         p++;
     }
-    if (LOCAL) vs.flush(lane, nm, gid, root, pref, a);
+    // the caller flushes the per-vertex accumulators (vs.flush) when it
+    // leaves this universe
 }
 
 // Write a compact universe (rows, member ids, prefix list); returns its
@@ -380,7 +497,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
     if (!wl) Sw = Hw = Pw = 0;
     for (;;) {
         const int s = (int)wave_add_u32(wl ? (uint32_t)__popcll(Sw) : 0u);
-        if (s <= 64) {
+        if (s <= PV_LIGHT_MAX) {
             // re-index S into a compact universe (members in id order)
             int base = 0;
             for (int t = 0; t < W; t++) {
@@ -412,7 +529,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
             cs.H = cs.P = 0;
             cs.h = h;
             cs.p = p;
-            cs.uni = (s > a.dfs_max) ? uni : -1;
+            cs.uni = uni;
             cs.nm = s;
             cs.gid = gid;
             cs.root = -1;
@@ -554,39 +671,39 @@ __device__ void gather_heavy(int hu, int v, int lane, const LevelArgs &a) {
 }
 
 // --------------------------------------------------------- level kernel
-// Work units of a level, in this order: multi-word items, compact items,
-// and at level 0 the heavy roots then the light roots (largest first).
+// One launch per unit kind and level, each with its own register budget:
+//   PV_UNITS_MW     multi-word items of the previous level, and at level 0
+//                   the heavy roots (gather + multi-word chain)
+//   PV_UNITS_ITEMS  compact items of the previous level (the bulk of the tree)
+//   PV_UNITS_LIGHT  level 0 only: roots with |N+(v)| <= PV_LIGHT_MAX,
+//                   gathered into registers (largest first)
+// Every wave takes units from the launch's own cursor until none is left.
 
-template <int KL>
+template <int KL, int MODE>
 __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const LevelArgs *__restrict__ pa) {
     constexpr bool LOCAL = KL > 0;
     const LevelArgs &a = *pa;
-    __shared__ int s_vl[WAVES_PER_BLOCK][64];
-    __shared__ int s_pre[WAVES_PER_BLOCK][64];
-    __shared__ unsigned long long s_A[WAVES_PER_BLOCK][64];
-    __shared__ int s_memb[WAVES_PER_BLOCK][64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
+    __shared__ unsigned long long s_bins[PV_LDS_H * 64];
+    for (int i = threadIdx.x; i < PV_LDS_H * 64; i += blockDim.x) s_bins[i] = 0ull;
+    __syncthreads();
     GlobalSink gs;
-    gs.reset();
-    gs.leaves = 0;
+    gs.init(a, s_bins);
     VertexSink<KL> vs;
-    if (LOCAL) vs.reset();
+    if (LOCAL) vs.init(a);
     Ctr ct;
     ct.nodes = ct.work = 0;
+    int *cursor = a.next + MODE;
 
-    const int n0 = a.n_mw_in, n1 = n0 + a.n_c_in;
-    const int n2 = n1 + (a.level == 0 ? a.nheavy : 0);
-    const int n3 = n2 + (a.level == 0 ? a.nlight : 0);
-    for (;;) {
-        int idx = 0;
-        if (lane == 0) idx = atomicAdd(a.next, 1);
-        idx = bcast0(__shfl(idx, 0, 64));
-        if (idx >= n3) break;
-        CState cs;
-        bool run = true;
-        if (idx < n0 || (idx >= n1 && idx < n2)) {
-            // multi-word tier: an item of the previous level, or a heavy root
+    if constexpr (MODE == PV_UNITS_MW) {
+        __shared__ int s_memb[WAVES_PER_BLOCK][64];
+        const int n0 = a.n_mw_in, n1 = n0 + (a.level == 0 ? a.nheavy : 0);
+        for (;;) {
+            int idx = 0;
+            if (lane == 0) idx = atomicAdd(cursor, 1);
+            idx = bcast0(__shfl(idx, 0, 64));
+            if (idx >= n1) break;
             int hu, h = 1, p = 0;
             uint64_t Sw = 0, Hw = 0, Pw = 0;
             if (idx < n0) {
@@ -601,7 +718,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
                 h = (int)(hp & 0xFFFFu);
                 p = (int)(hp >> 16);
             } else {
-                hu = idx - n1;
+                hu = idx - n0;
                 const int v = a.order[a.heavy_base + hu];
                 gather_heavy(hu, v, lane, a);
                 const int d = a.orow[v + 1] - a.orow[v];
@@ -611,47 +728,66 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
                     Sw = (cnt == 64) ? ~0ull : ((1ull << cnt) - 1);
                 }
             }
-            run = mw_run<KL>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs);
-        } else if (idx < n1) {
-            const CItem it = a.c_in[idx - n0];
-            cs.A = a.u_rows[(long long)it.uni * 64 + lane];
-            cs.S = it.S;
-            cs.H = it.H;
-            cs.P = it.P;
-            cs.h = (int)(it.hp & 0xFFFFu);
-            cs.p = (int)(it.hp >> 16);
-            cs.uni = (int)it.uni;
-            cs.gid = -1;
-            cs.pref = make_int2(0, 0);
-            if (LOCAL) {
-                cs.gid = a.u_gid[(long long)it.uni * 64 + lane];
-                cs.pref = a.u_pref[it.uni];
+            CState cs;
+            if (mw_run<KL>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs)) {
+                compact_run<KL>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
+                                cs.pref, lane, a, gs, vs, ct);
+                if (LOCAL) vs.flush(lane, cs.nm, cs.gid, cs.root, cs.pref, a);
             }
-            cs.nm = (int)wave_add_u32(cs.gid >= 0 ? 1u : 0u);
-            cs.root = -1;
-        } else {
-            const int v = a.order[a.light_base + (idx - n2)];
-            int d, gid;
-            cs.A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_A[wv], d, gid);
-            cs.S = (d == 64) ? ~0ull : ((1ull << d) - 1);
-            cs.H = cs.P = 0;
-            cs.h = 1;
-            cs.p = 0;
-            cs.uni = -1;
-            cs.nm = d;
-            cs.gid = gid;
-            cs.pref = make_int2(0, 0);
-            if (d > a.dfs_max) {
-                cs.uni = make_universe<KL>(cs.A, d, gid, lane, a, v, 0ull, 0ull, nullptr, 0, cs.pref);
-                run = cs.uni >= 0;  // buffers full: the host reruns with larger ones
-            }
-            cs.root = (cs.uni < 0) ? v : -1;
         }
-        if (run)
-            compact_run<KL>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
-                            cs.pref, lane, a, gs, vs, ct);
+    } else if constexpr (MODE == PV_UNITS_ITEMS) {
+        const int n = a.n_c_in;
+        for (;;) {
+            int idx = 0;
+            if (lane == 0) idx = atomicAdd(cursor, 1);
+            idx = bcast0(__shfl(idx, 0, 64));
+            if (idx >= n) break;
+            const CItem it = a.c_in[idx];
+            const uint32_t uw = uniform32(it.uni);
+            const int u = (int)(uw & 0x7fffffffu);
+            const bool fr = (uw >> 31) != 0;
+            const uint64_t A = a.u_rows[(long long)u * 64 + lane];
+            int gid = -1;
+            int2 pref = make_int2(0, 0);
+            if (LOCAL) {
+                gid = a.u_gid[(long long)u * 64 + lane];
+                pref = a.u_pref[u];
+            }
+            const int nm = (int)wave_add_u32(gid >= 0 ? 1u : 0u);
+            compact_run<KL>(A, it.S, it.H, it.P, (int)(it.hp & 0xFFFFu), (int)(it.hp >> 16), u, nm,
+                            gid, -1, pref, lane, a, gs, vs, ct, fr, it.hp);
+            if (LOCAL) vs.flush(lane, nm, gid, -1, pref, a);
+        }
+    } else {
+        __shared__ int s_vl[WAVES_PER_BLOCK][64];
+        __shared__ int s_pre[WAVES_PER_BLOCK][64];
+        __shared__ unsigned long long s_A[WAVES_PER_BLOCK][64];
+        const int n = a.nlight;
+        for (;;) {
+            int idx = 0;
+            if (lane == 0) idx = atomicAdd(cursor, 1);
+            idx = bcast0(__shfl(idx, 0, 64));
+            if (idx >= n) break;
+            const int v = a.order[a.light_base + idx];
+            int d, gid;
+            const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_A[wv], d, gid);
+            int uni = -1;
+            int2 pref = make_int2(0, 0);
+            if (d > a.dfs_max) {
+                uni = make_universe<KL>(A, d, gid, lane, a, v, 0ull, 0ull, nullptr, 0, pref);
+                if (uni < 0) continue;  // buffers full: the host reruns with larger ones
+            }
+            const int root = (uni < 0) ? v : -1;
+            compact_run<KL>(A, (d == 64) ? ~0ull : ((1ull << d) - 1), 0ull, 0ull, 1, 0, uni, d, gid,
+                            root, pref, lane, a, gs, vs, ct);
+            if (LOCAL) vs.flush(lane, d, gid, root, pref, a);
+        }
     }
-    gs.flush(lane, a.hist, a.hd);
+    __syncthreads();
+    for (int i = threadIdx.x; i < PV_LDS_H * 64; i += blockDim.x) {
+        const int h = i >> 6, p = i & 63;
+        if (s_bins[i] && h < a.hd && p < a.hd) atomicAdd(&a.hist[(long long)h * a.hd + p], s_bins[i]);
+    }
     if (lane == 0) {
         atomicAdd(&a.counters[0], ct.nodes);
         atomicAdd(&a.counters[1], gs.leaves);
@@ -713,6 +849,16 @@ __global__ void binom_kernel(int bn, uint64_t *tab, uint8_t *bad, uint64_t *tab6
             }
         }
         __syncthreads();
+    }
+}
+
+// Padded 64-bit table for the per-vertex path (see VertexSink): row a =
+// -1..bn-1, column j = -16..15 at [(a + 1) * 32 + j + 16].
+__global__ void binom_pad_kernel(int bn, const uint64_t *__restrict__ tab, uint64_t *__restrict__ pad) {
+    const int total = (bn + 1) * 32;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const int a = i / 32 - 1, j = i % 32 - 16;
+        pad[i] = (a >= 0 && j >= 0 && j <= a) ? tab[2 * ((long long)a * bn + j)] : 0ull;
     }
 }
 
@@ -785,20 +931,41 @@ __global__ void __launch_bounds__(256) finalize_kernel(const unsigned long long 
 
 // ============================================================== host side
 
-hipError_t pv_launch_level(const LevelArgs *a, int kl, int blocks, hipStream_t s) {
-    if (kl == 0) sct_level_kernel<0><<<blocks, 64 * WAVES_PER_BLOCK, 0, s>>>(a);
-    else if (kl <= 8) sct_level_kernel<8><<<blocks, 64 * WAVES_PER_BLOCK, 0, s>>>(a);
-    else sct_level_kernel<16><<<blocks, 64 * WAVES_PER_BLOCK, 0, s>>>(a);
+template <int KL>
+static hipError_t launch_mode(const LevelArgs *a, int mode, int blocks, hipStream_t s) {
+    dim3 g(blocks), b(64 * WAVES_PER_BLOCK);
+    if (mode == PV_UNITS_MW) sct_level_kernel<KL, PV_UNITS_MW><<<g, b, 0, s>>>(a);
+    else if (mode == PV_UNITS_ITEMS) sct_level_kernel<KL, PV_UNITS_ITEMS><<<g, b, 0, s>>>(a);
+    else sct_level_kernel<KL, PV_UNITS_LIGHT><<<g, b, 0, s>>>(a);
     return hipGetLastError();
 }
 
-int pv_level_blocks_per_cu(int kl) {
+hipError_t pv_launch_level(const LevelArgs *a, int kl, int mode, int blocks, hipStream_t s) {
+    if (kl == 0) return launch_mode<0>(a, mode, blocks, s);
+    if (kl <= 8) return launch_mode<8>(a, mode, blocks, s);
+    return launch_mode<16>(a, mode, blocks, s);
+}
+
+template <int KL>
+static int blocks_per_cu_kl(int mode) {
     int nb = 0;
     hipError_t e;
-    if (kl == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<0>, 64 * WAVES_PER_BLOCK, 0);
-    else if (kl <= 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<8>, 64 * WAVES_PER_BLOCK, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<16>, 64 * WAVES_PER_BLOCK, 0);
+    if (mode == PV_UNITS_MW)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_MW>,
+                                                         64 * WAVES_PER_BLOCK, 0);
+    else if (mode == PV_UNITS_ITEMS)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_ITEMS>,
+                                                         64 * WAVES_PER_BLOCK, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_LIGHT>,
+                                                         64 * WAVES_PER_BLOCK, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+int pv_level_blocks_per_cu(int kl, int mode) {
+    if (kl == 0) return blocks_per_cu_kl<0>(mode);
+    if (kl <= 8) return blocks_per_cu_kl<8>(mode);
+    return blocks_per_cu_kl<16>(mode);
 }
 
 hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsigned long long *hist,
@@ -811,6 +978,11 @@ hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsi
 hipError_t pv_launch_binomials(int bn, uint64_t *tab128, uint8_t *bad, uint64_t *tab64, int *fits64,
                                hipStream_t s) {
     binom_kernel<<<1, 256, 0, s>>>(bn, tab128, bad, tab64, fits64);
+    return hipGetLastError();
+}
+
+hipError_t pv_launch_binom_pad(int bn, const uint64_t *tab128, uint64_t *pad, hipStream_t s) {
+    binom_pad_kernel<<<64, 256, 0, s>>>(bn, tab128, pad);
     return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ PV_MAX_LOCAL_K = 16
 
 # every function declared in include/pivoter.h
 ABI_FUNCTIONS = [
-    "pv_strerror", "pv_init", "pv_fini", "pv_set_stream", "pv_set_dfs_max", "pv_set_timing",
+    "pv_strerror", "pv_init", "pv_fini", "pv_set_stream", "pv_set_dfs_max", "pv_set_dfs_budget",
+    "pv_set_timing",
     "pv_last_error",
     "pv_graph_load_csr", "pv_graph_load_csr_device", "pv_graph_free", "pv_graph_size",
     "pv_graph_orient", "pv_graph_export_order", "pv_count_global", "pv_count_local",
@@ -102,6 +103,7 @@ def _lib():
             "pv_set_stream": (i32, [vp, vp]),
             "pv_set_dfs_max": (i32, [vp, i32]),
             "pv_set_timing": (i32, [vp, i32]),
+            "pv_set_dfs_budget": (i32, [vp, i32]),
             "pv_graph_load_csr": (i32, [vp, i32, i32p, i32p, u32, pvp]),
             "pv_graph_load_csr_device": (i32, [vp, i32, i64, vp, vp, u32, pvp]),
             "pv_graph_free": (None, [vp]),
@@ -175,6 +177,10 @@ def pv_set_stream(ctx: int, stream: int | None) -> None:
 
 def pv_set_dfs_max(ctx: int, dfs_max: int) -> None:
     _check(_lib().pv_set_dfs_max(ctx, dfs_max), "pv_set_dfs_max")
+
+
+def pv_set_dfs_budget(ctx: int, nodes: int) -> None:
+    _check(_lib().pv_set_dfs_budget(ctx, nodes), "pv_set_dfs_budget")
 
 
 def pv_set_timing(ctx: int, on: bool) -> None:

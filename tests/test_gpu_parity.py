@@ -143,7 +143,7 @@ def test_split_threshold_does_not_change_the_tree(ctx, dfs_max):
     try:
         check_global(ctx, g, f"dfs_max={dfs_max}")
     finally:
-        P.pv_set_dfs_max(ctx, 32)
+        P.pv_set_dfs_max(ctx, 64)
 
 
 # --------------------------------------------------------------- per-vertex
@@ -250,3 +250,24 @@ def test_peel_order_large(ctx, n, deg, seed):
     pe = O.peel(g)
     assert alpha == pe.alpha
     assert np.array_equal(sub, pe.sub)
+
+
+# ---------------------------------------------- forced depth-first splits
+
+SPLITS = [(32, 16), (8, 16), (64, 24), (64, 1 << 20)]
+
+
+@pytest.mark.parametrize("dfs_max,budget", SPLITS)
+def test_dfs_budget_splits_keep_the_tree(ctx, dfs_max, budget):
+    g = gg.plant_cliques(gg.gnp(400, 0.12, 91), [75, 30, 20], 92)
+    P.pv_set_dfs_max(ctx, dfs_max)
+    P.pv_set_dfs_budget(ctx, budget)
+    try:
+        res, ref = check_global(ctx, g, f"dfs_max={dfs_max} budget={budget}")
+        with Loaded(ctx, g) as h:
+            out, ovf, st = P.pv_count_local(h, P.PV_VERTEX, 3, 10)
+        vref = O.count(g, vertex=(3, 10))
+        assert ovf == 0 and np.array_equal(out, vref.vertex)
+    finally:
+        P.pv_set_dfs_max(ctx, 64)
+        P.pv_set_dfs_budget(ctx, 2048)
