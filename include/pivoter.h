@@ -89,6 +89,11 @@ typedef struct {
     float ms_orient;       /* device time of the N+(v) construction    | the context */
     float ms_levels;       /* summed device time of the level kernels  | stream, only */
     float ms_finalize;     /* device time of the u128 finalize kernel / with timing on */
+    /* the level kernel per unit kind: [0] multi-word nodes and heavy roots,
+       [1] compact node and frame items, [2] light roots */
+    uint32_t launches_kind[3];  /* launches */
+    float ms_kind[3];           /* summed device time (timing on) */
+    uint64_t work_kind[3];      /* pivot work done by that kind's launches */
 } pv_stats;
 
 /* Human-readable name of a status code (static string). */
@@ -124,7 +129,7 @@ pv_status pv_set_timing(pv_ctx *ctx, int32_t on);
  * Tuning: a wavefront walks at most this many SCT nodes depth first before
  * it hands the rest of its subtree (the pending node and the pending hold
  * children on its stack) to other wavefronts.  Any value in [16, 2^20]
- * gives the same counts.  Default 4096 (PV_DFS_BUDGET overrides it at pv_init).
+ * gives the same counts.  Default 2048 (PV_DFS_BUDGET overrides it at pv_init).
  */
 pv_status pv_set_dfs_budget(pv_ctx *ctx, int32_t nodes);
 

@@ -113,7 +113,7 @@ struct pv_ctx {
     int dfs_budget = 2048;
     // device timing (HIP events on the context stream)
     bool timing = false;
-    hipEvent_t ev[8] = {};
+    hipEvent_t ev[16] = {};
 };
 
 struct pv_graph {
@@ -507,7 +507,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
     for (int attempt = 0;; attempt++) {
         if (attempt > 12) return PV_ENOMEM;
         PVCHK(g->hist.ensure((size_t)hd * hd));
-        PVCHK(g->counters.ensure(4));
+        PVCHK(g->counters.ensure(8));
         for (int i = 0; i < 2; i++) {
             PVCHK(g->citem[i].ensure(g->c_cap));
             PVCHK(g->mwitem[i].ensure(g->mw_cap * mw_stride));
@@ -523,7 +523,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             PVCHK(g->hu_vl.ensure((size_t)chunk * dpad));
         }
         HIPCHK(hipMemsetAsync(g->hist.p, 0, sizeof(unsigned long long) * (size_t)hd * hd, s));
-        HIPCHK(hipMemsetAsync(g->counters.p, 0, 4 * sizeof(unsigned long long), s));
+        HIPCHK(hipMemsetAsync(g->counters.p, 0, 8 * sizeof(unsigned long long), s));
         HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, 5 * sizeof(int), s));  // flags,u_n,pref_n,omega,lovf
         if (local) HIPCHK(hipMemsetAsync(rq.vout, 0, (size_t)g->n * rq.K * 16, s));
         if (rq.whole)
@@ -533,6 +533,8 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
         bool overflow = false;
         int levels = 0;
         float ms_levels = 0.f;
+        float ms_kind[3] = {0.f, 0.f, 0.f};
+        uint32_t launches_kind[3] = {0, 0, 0};
         long long items = 0;
         const int nchunks = (chunk > 0) ? (rq.nheavy + chunk - 1) / chunk : 0;
         for (int ch = 0; ch < std::max(1, nchunks) && !overflow; ch++) {
@@ -600,13 +602,20 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                     if (mode_units[mode] == 0) continue;
                     const long long want = (mode_units[mode] + WAVES_PER_LAUNCH_BLOCK - 1) / WAVES_PER_LAUNCH_BLOCK;
                     const int blocks = (int)std::min<long long>(c->level_blocks[kli][mode], want);
+                    if (c->timing) HIPCHK(hipEventRecord(c->ev[8 + 2 * mode], s));
                     HIPCHK(pv_launch_level(c->d_args.p, rq.kl, mode, std::max(1, blocks), s));
+                    if (c->timing) HIPCHK(hipEventRecord(c->ev[9 + 2 * mode], s));
+                    launches_kind[mode]++;
                 }
                 if (c->timing) HIPCHK(hipEventRecord(c->ev[4], s));
                 HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
                 levels++;
-                if (c->timing) ms_levels += elapsed(c, 3, 4);
+                if (c->timing) {
+                    ms_levels += elapsed(c, 3, 4);
+                    for (int mode = 0; mode < 3; mode++)
+                        if (mode_units[mode]) ms_kind[mode] += elapsed(c, 8 + 2 * mode, 9 + 2 * mode);
+                }
                 if (io[SM_FLAGS] & 1) {
                     // a work buffer filled up: the counters kept counting every
                     // request, so they give the demand of this level; grow to it
@@ -631,6 +640,10 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
         g->last.truncated = rq.kmax > 0;
         g->last.levels = levels;
         g->last.ms_levels = ms_levels;
+        for (int mode = 0; mode < 3; mode++) {
+            g->last.ms_kind[mode] = ms_kind[mode];
+            g->last.launches_kind[mode] = launches_kind[mode];
+        }
         return PV_OK;
     }
 }
@@ -652,7 +665,7 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
                               g->counts.p, g->ovf.p, g->small.p + SM_OMEGA, s));
     if (c->timing) HIPCHK(hipEventRecord(c->ev[6], s));
     std::vector<uint64_t> hc((size_t)kcap * 2), ho(nw);
-    unsigned long long hcnt[4];
+    unsigned long long hcnt[8];
     HIPCHK(hipMemcpyAsync(hc.data(), g->counts.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(ho.data(), g->ovf.p, nw * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hcnt, g->counters.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
@@ -662,6 +675,7 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
     g->last.nodes = hcnt[0];
     g->last.leaves = hcnt[1];
     g->last.work = hcnt[2];
+    for (int mode = 0; mode < 3; mode++) g->last.work_kind[mode] = hcnt[4 + mode];
     if (c->timing) g->last.ms_finalize = elapsed(c, 5, 6);
     g->last.alpha = g->alpha;
     g->last.omega = omega;

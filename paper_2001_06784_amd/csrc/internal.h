@@ -97,7 +97,7 @@ struct LevelArgs {
     // outputs
     unsigned long long *hist;
     int hd;
-    unsigned long long *counters;  // nodes, leaves, items, universes
+    unsigned long long *counters;  // nodes, leaves, work, -, work per unit kind [3]
     int *flags;                    // bit0: buffer overflow
     // local (per-vertex) counts
     uint64_t *vout;                // [n][K] u128

@@ -792,6 +792,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
         atomicAdd(&a.counters[0], ct.nodes);
         atomicAdd(&a.counters[1], gs.leaves);
         atomicAdd(&a.counters[2], ct.work);
+        atomicAdd(&a.counters[4 + MODE], ct.work);
     }
 }
 

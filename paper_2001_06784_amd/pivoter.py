@@ -55,10 +55,15 @@ class pv_stats(C.Structure):
                 ("work", C.c_uint64), ("alpha", C.c_int32), ("omega", C.c_int32),
                 ("subrounds", C.c_int32), ("truncated", C.c_int32), ("levels", C.c_int32),
                 ("ms_peel", C.c_float), ("ms_orient", C.c_float), ("ms_levels", C.c_float),
-                ("ms_finalize", C.c_float)]
+                ("ms_finalize", C.c_float), ("launches_kind", C.c_uint32 * 3),
+                ("ms_kind", C.c_float * 3), ("work_kind", C.c_uint64 * 3)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {}
+        for f, _ in self._fields_:
+            v = getattr(self, f)
+            d[f] = list(v) if isinstance(v, C.Array) else v
+        return d
 
 
 class PivoterError(RuntimeError):
