@@ -108,7 +108,7 @@ struct pv_ctx {
     DBuf<LevelArgs> d_args;
     LevelArgs *h_args = nullptr;
     int *h_io = nullptr;  // pinned readback slots
-    int level_blocks[3][3] = {};  // [k-slot variant][unit kind]
+    int level_blocks[4][3] = {};  // [variant: global, vertex 8, vertex 16, edge 8][unit kind]
     int dfs_max = 64;
     int dfs_budget = 2048;
     // device timing (HIP events on the context stream)
@@ -136,6 +136,10 @@ struct pv_graph {
     DBuf<int2> u_pref;
     DBuf<unsigned long long> hist, counters;
     DBuf<uint64_t> counts, ovf, vout_own;
+    // per-edge counts: edge ids of the oriented CSR and prefix-pair sums
+    bool eids = false;
+    DBuf<int> eup, o2e;
+    DBuf<uint64_t> umem, utot;
     size_t c_cap = 1 << 20, mw_cap = 1 << 15, u_cap = 1 << 16, pref_cap = 1 << 19;
     long long hu_budget = 1ll << 30;  // bytes of heavy universes per chunk
     pv_stats last{};
@@ -178,10 +182,11 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
         delete c;
         return PV_ENOMEM;
     }
-    for (int kl = 0; kl < 3; kl++)
+    for (int kv = 0; kv < 4; kv++)
         for (int mode = 0; mode < 3; mode++) {
-            int per_cu = pv_level_blocks_per_cu(kl == 0 ? 0 : (kl == 1 ? 8 : 16), mode);
-            c->level_blocks[kl][mode] = std::max(1, per_cu) * c->dev.num_cu;
+            const int kl = kv == 0 ? 0 : (kv == 2 ? 16 : 8);
+            int per_cu = pv_level_blocks_per_cu(kl, kv == 3, mode);
+            c->level_blocks[kv][mode] = std::max(1, per_cu) * c->dev.num_cu;
         }
     if (const char *env = getenv("PV_DFS_MAX")) c->dfs_max = std::max(1, std::min(64, atoi(env)));
     if (const char *env = getenv("PV_DFS_BUDGET")) c->dfs_budget = std::max(16, std::min(1 << 20, atoi(env)));
@@ -371,6 +376,10 @@ extern "C" void pv_graph_free(pv_graph *g) {
     g->counts.release();
     g->ovf.release();
     g->vout_own.release();
+    g->eup.release();
+    g->o2e.release();
+    g->umem.release();
+    g->utot.release();
     delete g;
 }
 
@@ -454,6 +463,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
         return PV_EDEVICE;
     }
     g->oriented = true;
+    g->eids = false;
     if (c->timing && n > 0) {
         g->last.ms_peel = elapsed(c, 0, 1);
         g->last.ms_orient = elapsed(c, 1, 2);
@@ -478,6 +488,7 @@ extern "C" pv_status pv_graph_export_order(pv_graph *g, int32_t *sub_host) {
 struct CountReq {
     int kmax = 0;
     int kl = 0;           // register k-slots for local counts (0: none)
+    bool edge = false;    // local counts are per edge
     int klo = 1, K = 0;
     uint64_t *vout = nullptr;  // device [n][K] u128
     int c0 = 1;           // value of C_0
@@ -518,6 +529,10 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             PVCHK(g->u_pref.ensure(g->u_cap));
             PVCHK(g->pref_pool.ensure(g->pref_cap));
         }
+        if (rq.edge) {
+            PVCHK(g->umem.ensure(g->u_cap * 64 * 2 * rq.K * 2));
+            PVCHK(g->utot.ensure(g->u_cap * 3 * rq.K * 2));
+        }
         if (chunk > 0) {
             PVCHK(g->hu_rows.ensure((size_t)chunk * W * dpad));
             PVCHK(g->hu_vl.ensure((size_t)chunk * dpad));
@@ -525,10 +540,12 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
         HIPCHK(hipMemsetAsync(g->hist.p, 0, sizeof(unsigned long long) * (size_t)hd * hd, s));
         HIPCHK(hipMemsetAsync(g->counters.p, 0, 8 * sizeof(unsigned long long), s));
         HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, 5 * sizeof(int), s));  // flags,u_n,pref_n,omega,lovf
-        if (local) HIPCHK(hipMemsetAsync(rq.vout, 0, (size_t)g->n * rq.K * 16, s));
+        const size_t lrows = rq.edge ? (size_t)(g->nnz / 2) : (size_t)g->n;
+        if (local && lrows) HIPCHK(hipMemsetAsync(rq.vout, 0, lrows * rq.K * 16, s));
         if (rq.whole)
             HIPCHK(pv_launch_sink_roots(g->n, g->order.p, g->small.p + SM_BOUNDS, g->hist.p, hd,
-                                        g->counters.p, local ? rq.vout : nullptr, rq.klo, rq.K, s));
+                                        g->counters.p, (local && !rq.edge) ? rq.vout : nullptr,
+                                        rq.klo, rq.K, s));
 
         bool overflow = false;
         int levels = 0;
@@ -589,12 +606,16 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.K = rq.K;
                 a.bin_pad = c->tab_pad.p;
                 a.lovf = g->small.p + SM_LOVF;
+                a.sub = g->sub.p;
+                a.o2e = rq.edge ? g->o2e.p : nullptr;
+                a.umem = rq.edge ? g->umem.p : nullptr;
+                a.utot = rq.edge ? g->utot.p : nullptr;
                 const long long units = (long long)n_mw + n_c + (level == 0 ? (long long)a.nheavy + a.nlight : 0);
                 if (units == 0) break;
                 *c->h_args = a;
                 HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 5 * sizeof(int), s));
                 HIPCHK(hipMemcpyAsync(c->d_args.p, c->h_args, sizeof(LevelArgs), hipMemcpyHostToDevice, s));
-                const int kli = rq.kl == 0 ? 0 : (rq.kl <= 8 ? 1 : 2);
+                const int kli = rq.kl == 0 ? 0 : (rq.edge ? 3 : (rq.kl <= 8 ? 1 : 2));
                 const long long mode_units[3] = {(long long)n_mw + (level == 0 ? a.nheavy : 0), n_c,
                                                  level == 0 ? a.nlight : 0};
                 if (c->timing) HIPCHK(hipEventRecord(c->ev[3], s));
@@ -603,7 +624,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                     const long long want = (mode_units[mode] + WAVES_PER_LAUNCH_BLOCK - 1) / WAVES_PER_LAUNCH_BLOCK;
                     const int blocks = (int)std::min<long long>(c->level_blocks[kli][mode], want);
                     if (c->timing) HIPCHK(hipEventRecord(c->ev[8 + 2 * mode], s));
-                    HIPCHK(pv_launch_level(c->d_args.p, rq.kl, mode, std::max(1, blocks), s));
+                    HIPCHK(pv_launch_level(c->d_args.p, rq.kl, rq.edge, mode, std::max(1, blocks), s));
                     if (c->timing) HIPCHK(hipEventRecord(c->ev[9 + 2 * mode], s));
                     launches_kind[mode]++;
                 }
@@ -636,6 +657,19 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             }
         }
         if (overflow) continue;
+        if (rq.edge) {
+            // pairs with vertices above the universes; the device copy of the
+            // launch arguments still holds the last level's (the universe
+            // buffers and outputs are the same for every level)
+            const int blocks = std::max(1, std::min(c->dev.num_cu * 16, (int)((io[SM_UN] + 3) / 4)));
+            HIPCHK(pv_launch_edge_prefix(c->d_args.p, blocks, s));
+            HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        if (io[SM_FLAGS] & 4) {
+            snprintf(g_last_error, sizeof g_last_error, "edge id lookup failed");
+            return PV_EDEVICE;
+        }
         g->last.items = (uint64_t)items;
         g->last.truncated = rq.kmax > 0;
         g->last.levels = levels;
@@ -714,15 +748,31 @@ static pv_status prepare(pv_graph *g, bool reorient) {
     return PV_OK;
 }
 
+static pv_status ensure_edge_ids(pv_graph *g) {
+    if (g->eids) return PV_OK;
+    pv_ctx *c = g->ctx;
+    const long long m = g->nnz / 2;
+    PVCHK(g->eup.ensure((size_t)g->n + 1));
+    PVCHK(g->o2e.ensure((size_t)std::max<long long>(m, 1)));
+    HIPCHK(hipMemsetAsync(g->eup.p, 0, sizeof(int), c->stream));
+    HIPCHK(pv_launch_edge_ids(c->dev, g->n, g->rp.p, g->col.p, g->sub.p, g->orow.p, g->fa.p,
+                              g->eup.p, g->o2e.p, g->scan.p, c->stream));
+    g->eids = true;
+    return PV_OK;
+}
+
 static pv_status setup_local(pv_graph *g, int kind, int klo, int khi, CountReq &rq) {
     if (kind == PV_NONE) return PV_OK;
-    if (kind != PV_VERTEX) return PV_EINVAL;
+    if (kind != PV_VERTEX && kind != PV_EDGE) return PV_EINVAL;
     // the 64-bit binomial table keeps C(a, b) for b < 16, and b = k - h <= khi - 1
     if (klo < 1 || khi < klo || khi - klo + 1 > PV_MAX_LOCAL_K || khi > 16) return PV_EINVAL;
+    // per-edge sums keep 8 k-slots per lane
+    if (kind == PV_EDGE && khi - klo + 1 > 8) return PV_EINVAL;
     rq.klo = klo;
     rq.K = khi - klo + 1;
     rq.kl = rq.K <= 8 ? 8 : 16;
-    // the per-vertex path keeps C(a, b), a <= alpha, b <= khi - 1, in 64 bits;
+    rq.edge = kind == PV_EDGE;
+    // the local paths keep C(a, b), a <= alpha, b <= khi - 1, in 64 bits;
     // C(a, b) grows with a, so C(alpha, khi - 1) is the largest value used
     PVCHK(ensure_binomials(g->ctx, g->alpha + 3));
     unsigned __int128 cb = 1;
@@ -732,10 +782,11 @@ static pv_status setup_local(pv_graph *g, int kind, int klo, int khi, CountReq &
         if (cb >> 64) fits = false;
     }
     if (!fits) {
-            snprintf(g_last_error, sizeof g_last_error,
-                     "per-vertex counts up to k=%d need binomials beyond 64 bits", khi);
-            return PV_ETOOBIG;
-        }
+        snprintf(g_last_error, sizeof g_last_error,
+                 "local counts up to k=%d need binomials beyond 64 bits", khi);
+        return PV_ETOOBIG;
+    }
+    if (rq.edge) PVCHK(ensure_edge_ids(g));
     return PV_OK;
 }
 
@@ -767,13 +818,14 @@ extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int
                                     pv_u128 *out, int64_t out_len, uint64_t *overflow_bits,
                                     pv_stats *stats) {
     if (!g || !out) return PV_EINVAL;
-    if (kind != PV_VERTEX) return PV_EINVAL;
+    if (kind != PV_VERTEX && kind != PV_EDGE) return PV_EINVAL;
     if (k_lo < 1 || k_hi < k_lo || k_hi - k_lo + 1 > PV_MAX_LOCAL_K) return PV_EINVAL;
     const int K = k_hi - k_lo + 1;
-    const long long need = (long long)g->n * K;
+    const long long rows = (kind == PV_EDGE) ? g->nnz / 2 : (long long)g->n;
+    const long long need = rows * K;
     if (out_len < need) return PV_EBUFSIZE;
     PVCHK(prepare(g, false));
-    PVCHK(g->vout_own.ensure((size_t)need * 2));
+    PVCHK(g->vout_own.ensure((size_t)std::max<long long>(need, 1) * 2));
     CountReq rq;
     rq.kmax = k_hi;
     PVCHK(setup_local(g, kind, k_lo, k_hi, rq));
@@ -785,7 +837,9 @@ extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int
     uint64_t lovf = 0;
     pv_status st = finish_counts(g, rq, nullptr, 0, nullptr, nullptr, stats, &lovf);
     if (st != PV_OK && st != PV_EOVERFLOW) return st;
-    HIPCHK(hipMemcpyAsync(out, g->vout_own.p, (size_t)need * 16, hipMemcpyDeviceToHost, g->ctx->stream));
+    if (need)
+        HIPCHK(hipMemcpyAsync(out, g->vout_own.p, (size_t)need * 16, hipMemcpyDeviceToHost,
+                              g->ctx->stream));
     HIPCHK(hipStreamSynchronize(g->ctx->stream));
     if (overflow_bits) overflow_bits[0] = lovf;
     return lovf ? PV_EOVERFLOW : PV_OK;

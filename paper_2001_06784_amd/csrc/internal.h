@@ -99,11 +99,16 @@ struct LevelArgs {
     int hd;
     unsigned long long *counters;  // nodes, leaves, work, -, work per unit kind [3]
     int *flags;                    // bit0: buffer overflow
-    // local (per-vertex) counts
-    uint64_t *vout;                // [n][K] u128
+    // local counts
+    uint64_t *vout;                // [n][K] (per vertex) or [m][K] (per edge) u128
     int klo, K;
     const uint64_t *bin_pad;       // padded 64-bit binomials, see VertexSink
     int *lovf;
+    // per-edge counts: edge ids and the universes' prefix-pair sums
+    const int *sub;                // peel sub-round of every vertex (the orientation key)
+    const int *o2e;                // [m] oriented CSR position -> edge id
+    uint64_t *umem;                // [u_cap][64][2][K] u128: member sums toward H / P prefix
+    uint64_t *utot;                // [u_cap][3][K] u128: HH, HP, PP sums
 };
 
 
@@ -122,8 +127,13 @@ hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *cn
 #define PV_UNITS_ITEMS 1
 #define PV_UNITS_LIGHT 2
 // `a` is a device pointer to the launch arguments
-hipError_t pv_launch_level(const LevelArgs *a, int kl, int mode, int blocks, hipStream_t s);
-int pv_level_blocks_per_cu(int kl, int mode);
+hipError_t pv_launch_level(const LevelArgs *a, int kl, bool edge, int mode, int blocks, hipStream_t s);
+int pv_level_blocks_per_cu(int kl, bool edge, int mode);
+hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s);
+// per-edge ids: o2e[q] = lexicographic id of the edge at oriented position q
+hipError_t pv_launch_edge_ids(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
+                              const int *orow, int *ucnt, int *up, int *o2e, int *scan_tmp,
+                              hipStream_t s);
 hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsigned long long *hist,
                                 int hd, unsigned long long *counters, uint64_t *vout, int klo, int K,
                                 hipStream_t s);

@@ -489,6 +489,73 @@ __global__ void __launch_bounds__(1024) scan_apply_kernel(int n, const int *__re
     if (i == n - 1) out[n] = off + inc;
 }
 
+
+// ------------------------------------------------------------ edge ids
+// The id of edge {u, v}, u < v, is its rank in lexicographic order: the
+// position of v among the neighbours above u, after all such entries of
+// rows 0..u-1.  ucnt[v] = number of neighbours above v, up = its
+// exclusive scan; o2e maps each oriented CSR position to its edge id.
+
+__global__ void __launch_bounds__(256) ucnt_kernel(int n, const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    int *__restrict__ ucnt) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        int lo = rp[v], hi = rp[v + 1];
+        const int end = hi;
+        while (lo < hi) {  // first neighbour > v
+            const int mid = (lo + hi) >> 1;
+            if (col[mid] <= v) lo = mid + 1;
+            else hi = mid;
+        }
+        ucnt[v] = end - lo;
+    }
+}
+
+__global__ void __launch_bounds__(256) o2e_kernel(int n, const int *__restrict__ rp,
+                                                   const int *__restrict__ col,
+                                                   const int *__restrict__ sub,
+                                                   const int *__restrict__ orow,
+                                                   const int *__restrict__ up,
+                                                   int *__restrict__ o2e) {
+    const int lane = threadIdx.x & 63;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += nw) {
+        const int sv = sub[v];
+        const int r0 = rp[v], e1 = rp[v + 1];
+        const int firstup = e1 - (up[v + 1] - up[v]);  // position of the first neighbour > v
+        int w = orow[v];
+        for (int e0 = r0; e0 < e1; e0 += 64) {
+            const int e = e0 + lane;
+            bool take = false;
+            int u = 0;
+            if (e < e1) {
+                u = col[e];
+                take = key_less(sv, v, sub[u], u);
+            }
+            const uint64_t m = ballot64(take);
+            if (take) {
+                int id;
+                if (v < u) {
+                    id = up[v] + (e - firstup);
+                } else {
+                    // v sits above u in u's row
+                    int lo = rp[u], hi = rp[u + 1];
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (col[mid] < v) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    const int ufirst = rp[u + 1] - (up[u + 1] - up[u]);
+                    id = up[u] + (lo - ufirst);
+                }
+                o2e[w + __popcll(m & below)] = id;
+            }
+            w += __popcll(m);
+        }
+    }
+}
+
 // ------------------------------------------------------- root buckets
 // Counting sort of the roots by out-degree, largest first, so that heavy
 // subtrees start early.  cnt has amax+2 slots.
@@ -575,5 +642,19 @@ hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *cn
     root_hist_kernel<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, odeg, cnt);
     root_offsets_kernel<<<1, 64, 0, s>>>(amax, cnt, cursor, bounds, light_max);
     root_scatter_kernel<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, odeg, cursor, order);
+    return hipGetLastError();
+}
+
+hipError_t pv_launch_edge_ids(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
+                              const int *orow, int *ucnt, int *up, int *o2e, int *scan_tmp,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    ucnt_kernel<<<grid_for(n, 256, dev.num_cu * 32), 256, 0, s>>>(n, rp, col, ucnt);
+    const int nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    scan_reduce_kernel<<<nb, 256, 0, s>>>(n, ucnt, scan_tmp);
+    scan_blocks_kernel<<<1, 1024, 0, s>>>(nb, scan_tmp);
+    scan_apply_kernel<<<nb, 1024, 0, s>>>(n, ucnt, scan_tmp, up);
+    const int wblocks = grid_for((long long)n * 64, 256, dev.num_cu * 32);
+    o2e_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, orow, up, o2e);
     return hipGetLastError();
 }

@@ -109,6 +109,12 @@ struct VertexSink {
         for (int i = 0; i < KL; i++) lo[i] = hi[i] = 0;
     }
 
+    // path bookkeeping is only needed for pairs (EdgeSink)
+    __device__ __forceinline__ void begin(uint64_t, uint64_t, int) {}
+    __device__ __forceinline__ void join(int, uint64_t, uint64_t, int) {}
+    __device__ __forceinline__ void join_set(uint64_t, uint64_t, uint64_t, int) {}
+    __device__ __forceinline__ void leave(uint64_t, int, int) {}
+
     __device__ __forceinline__ void leaf(int h, int p, uint64_t H, uint64_t P, int lane,
                                          const LevelArgs &) {
         // nothing for k <= khi when h > khi (every clique of the leaf has
@@ -131,7 +137,7 @@ struct VertexSink {
 
     // members: lane j < nm owns vertex gid; prefix: `root` (a hold vertex,
     // or -1) plus pool[pref.x .. pref.x + pref.y)
-    __device__ void flush(int lane, int nm, int gid, int root, int2 pref, const LevelArgs &) {
+    __device__ void flush(int lane, int nm, int gid, int root, int2 pref, int, const LevelArgs &) {
         bool ovf = false;
         if (lane < nm) {
 #pragma unroll
@@ -182,13 +188,244 @@ struct VertexSink {
     }
 };
 
+
+// Edge id of the edge {x, y} (both endpoints given as vertex ids): the
+// edge is stored once in the oriented CSR, at its smaller-key end, and o2e
+// maps that position to the lexicographic edge id.  -1 if x, y are not
+// adjacent (never the case for pairs of one root-to-leaf path).
+__device__ __forceinline__ int edge_id(int x, int y, const int *__restrict__ sub,
+                                       const int *__restrict__ orow, const int *__restrict__ ocol,
+                                       const int *__restrict__ o2e) {
+    const int sx = sub[x], sy = sub[y];
+    int u = x, w = y;
+    if (sy < sx || (sy == sx && y < x)) {
+        u = y;
+        w = x;
+    }
+    int lo = orow[u], hi = orow[u + 1];
+    const int end = hi;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ocol[mid] < w) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < end && ocol[lo] == w) ? o2e[lo] : -1;
+}
+
+// Per-edge counts (Alg. 2 steps for pairs): a leaf with h hold and p pivot
+// vertices adds, for k = klo..khi,
+//     C(p, k-h)      to every pair of hold vertices          (type HH)
+//     C(p-1, k-h-1)  to every hold/pivot pair                (type HP)
+//     C(p-2, k-h-2)  to every pair of pivot vertices         (type PP).
+// Instead of touching every pair at every leaf, a member j of the walk's
+// path sums, while it stays on the path, what its pairs with the path
+// vertices *above it* are owed: sH toward hold partners, sP toward pivot
+// partners (each a type chosen by j's own role).  Those partners are fixed
+// for the whole stay (they were on the path when j joined and leave only
+// after j), so when j leaves, its sums are added once to each of those
+// pairs.  A pair is thus charged at the leave of its later-joined end.
+// Members that join together (the start of a walk, a clique folded into P)
+// are ordered by lane.
+//
+// Partners above the universe (the prefix) are on every path: a member's
+// finished stays are summed in vH/vP and added to its prefix pairs when the
+// wave leaves the universe; lanes 62 and 63 act as a hold and a pivot member
+// that never leave, which yields the sums owed to prefix/prefix pairs.  With
+// a universe in memory those sums go to per-universe accumulators and a
+// final kernel adds them to the prefix pairs once per universe.
+template <int KL>
+struct EdgeSink {
+    uint64_t shl[KL], shh[KL], spl[KL], sph[KL];  // current stay
+    uint64_t vhl[KL], vhh[KL], vpl[KL], vph[KL];  // finished stays
+    uint64_t BH, BP;                              // path members above this lane
+    // wave-uniform copies of the arguments
+    const uint64_t *tab;
+    uint64_t *eout, *umem, *utot;
+    const int *sub, *orow, *ocol, *o2e;
+    int *lovf, *flags;
+    int klo, K, khi;
+    bool ovf;
+
+    __device__ void init(const LevelArgs &a) {
+        tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
+        eout = (uint64_t *)uniform64((uint64_t)a.vout);
+        umem = (uint64_t *)uniform64((uint64_t)a.umem);
+        utot = (uint64_t *)uniform64((uint64_t)a.utot);
+        sub = (const int *)uniform64((uint64_t)a.sub);
+        orow = (const int *)uniform64((uint64_t)a.orow);
+        ocol = (const int *)uniform64((uint64_t)a.ocol);
+        o2e = (const int *)uniform64((uint64_t)a.o2e);
+        lovf = (int *)uniform64((uint64_t)a.lovf);
+        flags = (int *)uniform64((uint64_t)a.flags);
+        klo = uniformi(a.klo);
+        K = uniformi(a.K);
+        khi = klo + K - 1;
+        ovf = false;
+        BH = BP = 0;
+#pragma unroll
+        for (int i = 0; i < KL; i++) shl[i] = shh[i] = spl[i] = sph[i] = 0;
+        reset();
+    }
+
+    __device__ void reset() {
+#pragma unroll
+        for (int i = 0; i < KL; i++) vhl[i] = vhh[i] = vpl[i] = vph[i] = 0;
+    }
+
+    __device__ __forceinline__ void begin(uint64_t H, uint64_t P, int lane) {
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        if (((H | P) >> lane) & 1) {
+            BH = H & below;
+            BP = P & below;
+        }
+    }
+
+    __device__ __forceinline__ void join(int j, uint64_t Hb, uint64_t Pb, int lane) {
+        if (lane == j) {
+            BH = Hb;
+            BP = Pb;
+        }
+    }
+
+    __device__ __forceinline__ void join_set(uint64_t Sm, uint64_t Hb, uint64_t Pb, int lane) {
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        if ((Sm >> lane) & 1) {
+            BH = Hb;
+            BP = Pb | (Sm & below);
+        }
+    }
+
+    __device__ __forceinline__ void leaf(int h, int p, uint64_t H, uint64_t P, int lane,
+                                         const LevelArgs &) {
+        if (h > khi || h + p < klo) return;
+        const bool inH = ((H >> lane) & 1) || lane == 62;
+        const bool inP = ((P >> lane) & 1) || lane == 63;
+        // rows of C(p, .), C(p-1, .), C(p-2, .) at column k - h, k - h - 1,
+        // k - h - 2 (row -1 is all zeros and stands in for row -2: with
+        // p = 0 there is no pivot vertex, so PP is never owed)
+        const uint64_t *rowHH = tab + (p + 1) * 32 + (klo - h + 16);
+        const uint64_t *rowHP = tab + p * 32 + (klo - h + 15);
+        const uint64_t *rowPP = tab + max(p - 1, 0) * 32 + (klo - h + 14);
+#pragma unroll
+        for (int kk = 0; kk < KL; kk++) {
+            if (kk < K) {
+                const uint64_t hh = ldc64(rowHH + kk), hp = ldc64(rowHP + kk), pp = ldc64(rowPP + kk);
+                const uint64_t toH = inH ? hh : (inP ? hp : 0ull);
+                const uint64_t toP = inH ? hp : (inP ? pp : 0ull);
+                shl[kk] += toH;
+                shh[kk] += (shl[kk] < toH) ? 1ull : 0ull;
+                spl[kk] += toP;
+                sph[kk] += (spl[kk] < toP) ? 1ull : 0ull;
+            }
+        }
+    }
+
+    // members in L leave the path: charge their stays to their pairs
+    __device__ void leave(uint64_t L, int lane, int gid) {
+        L = uniform64(L) & ((1ull << 62) - 1);
+        uint64_t rest = L;
+        while (rest) {
+            const int j = __builtin_ctzll(rest);
+            rest &= rest - 1;
+            const uint64_t bh = readlane64(BH, j), bp = readlane64(BP, j);
+            if ((bh | bp) == 0) continue;
+            const int gj = (int)readlane32((uint32_t)gid, j);
+            const bool mine = ((bh | bp) >> lane) & 1;
+            const bool isH = (bh >> lane) & 1;
+            int e = -1;
+            if (mine) {
+                e = edge_id(gid, gj, sub, orow, ocol, o2e);
+                if (e < 0) atomicOr(flags, 4);
+            }
+#pragma unroll
+            for (int kk = 0; kk < KL; kk++) {
+                if (kk < K) {
+                    const uint64_t hl = readlane64(shl[kk], j), hh = readlane64(shh[kk], j);
+                    const uint64_t pl = readlane64(spl[kk], j), ph = readlane64(sph[kk], j);
+                    const uint64_t l = isH ? hl : pl, hv = isH ? hh : ph;
+                    if (e >= 0 && (l | hv))
+                        ovf |= atomic_add_u128(eout + 2 * ((long long)e * K + kk), l, hv);
+                }
+            }
+        }
+        if ((L >> lane) & 1) {
+#pragma unroll
+            for (int kk = 0; kk < KL; kk++) {
+                vhl[kk] += shl[kk];
+                vhh[kk] += shh[kk] + ((vhl[kk] < shl[kk]) ? 1ull : 0ull);
+                vpl[kk] += spl[kk];
+                vph[kk] += sph[kk] + ((vpl[kk] < spl[kk]) ? 1ull : 0ull);
+                shl[kk] = shh[kk] = spl[kk] = sph[kk] = 0;
+            }
+        }
+    }
+
+    // The wave leaves the universe (every stay of a member is finished):
+    // prefix pairs.  With root >= 0 the prefix is that single hold vertex;
+    // otherwise the sums go to universe `uni`'s accumulators.
+    __device__ void flush(int lane, int nm, int gid, int root, int2, int uni, const LevelArgs &) {
+        root = uniformi(root);
+        uni = uniformi(uni);
+        if (root >= 0) {
+            if (lane < nm) {
+                const int e = edge_id(root, gid, sub, orow, ocol, o2e);
+                if (e < 0) atomicOr(flags, 4);
+#pragma unroll
+                for (int kk = 0; kk < KL; kk++)
+                    if (kk < K && e >= 0 && (vhl[kk] | vhh[kk]))
+                        ovf |= atomic_add_u128(eout + 2 * ((long long)e * K + kk), vhl[kk], vhh[kk]);
+            }
+        } else if (uni >= 0) {
+            const long long ub = (long long)uni * 64 + lane;
+            if (lane < nm) {
+#pragma unroll
+                for (int kk = 0; kk < KL; kk++) {
+                    if (kk < K) {
+                        if (vhl[kk] | vhh[kk])
+                            ovf |= atomic_add_u128(umem + 2 * ((ub * 2 + 0) * K + kk), vhl[kk], vhh[kk]);
+                        if (vpl[kk] | vph[kk])
+                            ovf |= atomic_add_u128(umem + 2 * ((ub * 2 + 1) * K + kk), vpl[kk], vph[kk]);
+                    }
+                }
+            } else if (lane >= 62) {
+                // lane 62: HH (its sH) and HP (its sP); lane 63: PP (its sP)
+                const long long tb = (long long)uni * 3;
+#pragma unroll
+                for (int kk = 0; kk < KL; kk++) {
+                    if (kk < K) {
+                        if (lane == 62 && (shl[kk] | shh[kk]))
+                            ovf |= atomic_add_u128(utot + 2 * ((tb + 0) * K + kk), shl[kk], shh[kk]);
+                        if (spl[kk] | sph[kk])
+                            ovf |= atomic_add_u128(utot + 2 * ((tb + (lane == 62 ? 1 : 2)) * K + kk),
+                                                   spl[kk], sph[kk]);
+                    }
+                }
+            }
+        }
+        if (ovf) atomicOr(lovf, 1);
+        ovf = false;
+        reset();
+#pragma unroll
+        for (int kk = 0; kk < KL; kk++) shl[kk] = shh[kk] = spl[kk] = sph[kk] = 0;
+    }
+};
+
+template <int KL, bool EDGE>
+struct SinkOf {
+    using T = VertexSink<KL>;
+};
+template <int KL>
+struct SinkOf<KL, true> {
+    using T = EdgeSink<KL>;
+};
+
 // Work counters of a wave: SCT nodes visited, and the algorithmic pivot
 // work sum over nodes of |S| * ceil(|S|/64) (64-bit AND+popcount pairs).
 struct Ctr {
     unsigned long long nodes, work;
 };
 
-template <int KL>
+template <int KL, bool EDGE>
 __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelArgs &a,
                              int root, uint64_t Hw, uint64_t Pw, const int *vl, int W,
                              int2 &pref);
@@ -206,9 +443,9 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
 // remaining hold children.  The universe is written out first if it only
 // lived in registers.  So no single wave walks an unbounded subtree, and a
 // split hands over depth + 1 items however wide the frames are.
-template <int KL>
+template <int KL, bool EDGE>
 __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int h, int p, int lane,
-                            const LevelArgs &a, GlobalSink &gs, VertexSink<KL> &vs,
+                            const LevelArgs &a, GlobalSink &gs, typename SinkOf<KL, EDGE>::T &vs,
                             Ctr &ct, int &uni, int nm, int gid, int root, bool from_frame,
                             uint32_t fmeta) {
     constexpr bool LOCAL = KL > 0;
@@ -220,6 +457,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     P = uniform64(P);
     h = uniformi(h);
     p = uniformi(p);
+    if (LOCAL) vs.begin(H, P, lane);
     // per-call counters: a call visits at most dfs_budget + 128 <= 2^20 + 128
     // nodes and adds at most 2080 work per node, so 32 bits suffice
     uint32_t nodes = 0, work = 0, nleaves = 0;
@@ -244,7 +482,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                 // ---- split: the pending node and every stack frame become items
                 if (uni < 0) {
                     int2 pref;
-                    uni = make_universe<KL>(A, nm, gid, lane, a, root, 0ull, 0ull, nullptr, 0, pref);
+                    uni = make_universe<KL, EDGE>(A, nm, gid, lane, a, root, 0ull, 0ull, nullptr, 0, pref);
                     if (uni < 0) break;  // buffers full: the host reruns with larger ones
                 }
                 const int total = depth + 1;
@@ -291,11 +529,17 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                     if (ballot64(in && (int)c + 1 != s) == 0) {
                         nodes += (uint32_t)s;
                         work += (uint32_t)(s * (s - 1) / 2);
-                        if (LOCAL) P |= S;
+                        if (LOCAL) {
+                            vs.join_set(S, H, P, lane);
+                            P |= S;
+                        }
                         p += s;
                     } else {
                         S &= ~pbit;
-                        if (LOCAL) P |= pbit;
+                        if (LOCAL) {
+                            vs.join(piv, H, P, lane);
+                            P |= pbit;
+                        }
                         p++;
                         continue;
                     }
@@ -312,7 +556,10 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                         depth++;
                     }
                     S &= Ap;
-                    if (LOCAL) P |= pbit;
+                    if (LOCAL) {
+                        vs.join(piv, H, P, lane);
+                        P |= pbit;
+                    }
                     p++;
                     continue;
                 }
@@ -338,10 +585,14 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
         h = (int)((M >> 6) & 0x1FFFu) + 1;
         p = (int)(M >> 19);
         if (LOCAL) {
-            H = readlane64(stH, t) | vbit;
-            P = readlane64(stP, t);
+            const uint64_t Ht = readlane64(stH, t), Pt = readlane64(stP, t);
+            vs.leave((H | P) & ~(Ht | Pt), lane, gid);
+            vs.join(v, Ht, Pt, lane);
+            H = Ht | vbit;
+            P = Pt;
         }
     }
+    if (LOCAL) vs.leave(H | P, lane, gid);
     ct.nodes += nodes;
     ct.work += work;
     gs.add_leaves(nleaves, lane);
@@ -352,11 +603,11 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
 // children go to the next level; once |S| <= dfs_max finish depth first.
 // root/pref name the vertices above the universe (local counts only).
 
-template <int KL>
+template <int KL, bool EDGE>
 __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int h, int p, int uni,
                             int nm, int gid, int root, int2 pref, int lane, const LevelArgs &a,
-                            GlobalSink &gs, VertexSink<KL> &vs, Ctr &ct, bool from_frame = false,
-                            uint32_t fmeta = 0) {
+                            GlobalSink &gs, typename SinkOf<KL, EDGE>::T &vs, Ctr &ct,
+                            bool from_frame = false, uint32_t fmeta = 0) {
     constexpr bool LOCAL = KL > 0;
     S = uniform64(S);
     H = uniform64(H);
@@ -368,8 +619,8 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     for (;;) {
         const int s = __popcll(S);
         if (from_frame || s <= a.dfs_max || uni < 0) {
-            compact_dfs<KL>(A, S, H, P, h, p, lane, a, gs, vs, ct, uni, nm, gid, root, from_frame,
-                            fmeta);
+            compact_dfs<KL, EDGE>(A, S, H, P, h, p, lane, a, gs, vs, ct, uni, nm, gid, root,
+                                  from_frame, fmeta);
             break;
         }
         ct.nodes++;
@@ -385,11 +636,18 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
             if (ballot64(in && (int)c + 1 != s) == 0) {
                 ct.nodes += (unsigned long long)s;
                 ct.work += (unsigned long long)s * (unsigned long long)(s - 1) / 2;
-                if (LOCAL) P |= S;
+                if (LOCAL) {
+                    vs.begin(H, P, lane);
+                    vs.join_set(S, H, P, lane);
+                    P |= S;
+                }
                 p += s;
                 gs.leaf(h, p, lane);
                 gs.add_leaves(1, lane);
-                if (LOCAL) vs.leaf(h, p, H, P, lane, a);
+                if (LOCAL) {
+                    vs.leaf(h, p, H, P, lane, a);
+                    vs.leave(H | P, lane, gid);
+                }
                 break;
             }
             S &= ~pbit;
@@ -428,8 +686,10 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
 }
 
 // Write a compact universe (rows, member ids, prefix list); returns its
-// index or -1 when the buffers are full.
-template <int KL>
+// index or -1 when the buffers are full.  For per-edge counts it also
+// clears the universe's prefix-pair accumulators (each lane the slots it
+// adds to later).
+template <int KL, bool EDGE>
 __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelArgs &a,
                              int root, uint64_t Hw, uint64_t Pw, const int *vl, int W,
                              int2 &pref) {
@@ -469,6 +729,17 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
             pref = make_int2(off, tot);
             if (lane == 0) a.u_pref[uni] = pref;
         }
+        if (EDGE) {
+            const int K = a.K;
+            uint64_t *um = a.umem + 2 * (((long long)uni * 64 + lane) * 2 * K);
+            for (int i = 0; i < 4 * K; i++) um[i] = 0ull;
+            // prefix/prefix sums: HH and HP from lane 62, PP from lane 63
+            uint64_t *ut = a.utot + 2 * ((long long)uni * 3 * K);
+            if (lane == 62)
+                for (int i = 0; i < 4 * K; i++) ut[i] = 0ull;
+            if (lane == 63)
+                for (int i = 0; i < 2 * K; i++) ut[4 * K + i] = 0ull;
+        }
     }
     return uni;
 }
@@ -485,7 +756,7 @@ struct CState {
     int2 pref;
 };
 
-template <int KL>
+template <int KL, bool EDGE>
 __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int p, int lane,
                        const LevelArgs &a, Ctr &ct, int *memb, CState &cs) {
     constexpr bool LOCAL = KL > 0;
@@ -521,7 +792,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
             int uni = -1;
             // the root and the multi-word holds/pivots form the prefix
             if (s > a.dfs_max || LOCAL) {
-                uni = make_universe<KL>(A, s, gid, lane, a, root, Hw, Pw, vl, W, pref);
+                uni = make_universe<KL, EDGE>(A, s, gid, lane, a, root, Hw, Pw, vl, W, pref);
                 if (uni < 0) return false;  // buffers full: the host reruns with larger ones
             }
             cs.A = A;
@@ -679,7 +950,7 @@ __device__ void gather_heavy(int hu, int v, int lane, const LevelArgs &a) {
 //                   gathered into registers (largest first)
 // Every wave takes units from the launch's own cursor until none is left.
 
-template <int KL, int MODE>
+template <int KL, int MODE, bool EDGE>
 __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const LevelArgs *__restrict__ pa) {
     constexpr bool LOCAL = KL > 0;
     const LevelArgs &a = *pa;
@@ -690,7 +961,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
     __syncthreads();
     GlobalSink gs;
     gs.init(a, s_bins);
-    VertexSink<KL> vs;
+    typename SinkOf<KL, EDGE>::T vs;
     if (LOCAL) vs.init(a);
     Ctr ct;
     ct.nodes = ct.work = 0;
@@ -729,10 +1000,10 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
                 }
             }
             CState cs;
-            if (mw_run<KL>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs)) {
-                compact_run<KL>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
+            if (mw_run<KL, EDGE>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs)) {
+                compact_run<KL, EDGE>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
                                 cs.pref, lane, a, gs, vs, ct);
-                if (LOCAL) vs.flush(lane, cs.nm, cs.gid, cs.root, cs.pref, a);
+                if (LOCAL) vs.flush(lane, cs.nm, cs.gid, cs.root, cs.pref, cs.uni, a);
             }
         }
     } else if constexpr (MODE == PV_UNITS_ITEMS) {
@@ -754,9 +1025,9 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
                 pref = a.u_pref[u];
             }
             const int nm = (int)wave_add_u32(gid >= 0 ? 1u : 0u);
-            compact_run<KL>(A, it.S, it.H, it.P, (int)(it.hp & 0xFFFFu), (int)(it.hp >> 16), u, nm,
+            compact_run<KL, EDGE>(A, it.S, it.H, it.P, (int)(it.hp & 0xFFFFu), (int)(it.hp >> 16), u, nm,
                             gid, -1, pref, lane, a, gs, vs, ct, fr, it.hp);
-            if (LOCAL) vs.flush(lane, nm, gid, -1, pref, a);
+            if (LOCAL) vs.flush(lane, nm, gid, -1, pref, u, a);
         }
     } else {
         __shared__ int s_vl[WAVES_PER_BLOCK][64];
@@ -774,13 +1045,13 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
             int uni = -1;
             int2 pref = make_int2(0, 0);
             if (d > a.dfs_max) {
-                uni = make_universe<KL>(A, d, gid, lane, a, v, 0ull, 0ull, nullptr, 0, pref);
+                uni = make_universe<KL, EDGE>(A, d, gid, lane, a, v, 0ull, 0ull, nullptr, 0, pref);
                 if (uni < 0) continue;  // buffers full: the host reruns with larger ones
             }
             const int root = (uni < 0) ? v : -1;
-            compact_run<KL>(A, (d == 64) ? ~0ull : ((1ull << d) - 1), 0ull, 0ull, 1, 0, uni, d, gid,
+            compact_run<KL, EDGE>(A, (d == 64) ? ~0ull : ((1ull << d) - 1), 0ull, 0ull, 1, 0, uni, d, gid,
                             root, pref, lane, a, gs, vs, ct);
-            if (LOCAL) vs.flush(lane, d, gid, root, pref, a);
+            if (LOCAL) vs.flush(lane, d, gid, root, pref, uni, a);
         }
     }
     __syncthreads();
@@ -794,6 +1065,57 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
         atomicAdd(&a.counters[2], ct.work);
         atomicAdd(&a.counters[4 + MODE], ct.work);
     }
+}
+
+// Per-edge counts: pairs with a vertex above a universe, once per universe
+// after the last level (a wave per universe).  Members add their sums
+// toward hold / pivot prefix vertices; every prefix pair gets the
+// universe's HH, HP or PP total by the roles of its two ends.
+__global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__restrict__ pa) {
+    const LevelArgs &a = *pa;
+    const int lane = threadIdx.x & 63;
+    const int nu = min(*a.u_n, a.u_cap);
+    const int K = a.K;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    bool ovf = false;
+    for (int u = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < nu; u += nwaves) {
+        const int gid = a.u_gid[(long long)u * 64 + lane];
+        const int2 pref = a.u_pref[u];
+        for (int i = 0; i < pref.y; i++) {
+            const int ex = a.pref_pool[pref.x + i];
+            const int x = ex & 0x7fffffff, role = (ex >> 31) & 1;
+            if (gid < 0) continue;
+            const uint64_t *src = a.umem + 2 * ((((long long)u * 64 + lane) * 2 + role) * K);
+            int e = -2;
+            for (int kk = 0; kk < K; kk++) {
+                const uint64_t l = src[2 * kk], hv = src[2 * kk + 1];
+                if ((l | hv) == 0) continue;
+                if (e == -2) {
+                    e = edge_id(x, gid, a.sub, a.orow, a.ocol, a.o2e);
+                    if (e < 0) atomicOr(a.flags, 4);
+                }
+                if (e >= 0) ovf |= atomic_add_u128(a.vout + 2 * ((long long)e * K + kk), l, hv);
+            }
+        }
+        const uint64_t *tot = a.utot + 2 * ((long long)u * 3 * K);
+        for (int i = 0; i + 1 < pref.y; i++) {
+            const int ex = a.pref_pool[pref.x + i];
+            for (int j = i + 1 + lane; j < pref.y; j += 64) {
+                const int ey = a.pref_pool[pref.x + j];
+                const int type = ((ex >> 31) & 1) + ((ey >> 31) & 1);
+                const int e = edge_id(ex & 0x7fffffff, ey & 0x7fffffff, a.sub, a.orow, a.ocol, a.o2e);
+                if (e < 0) {
+                    atomicOr(a.flags, 4);
+                    continue;
+                }
+                for (int kk = 0; kk < K; kk++) {
+                    const uint64_t l = tot[2 * (type * K + kk)], hv = tot[2 * (type * K + kk) + 1];
+                    if (l | hv) ovf |= atomic_add_u128(a.vout + 2 * ((long long)e * K + kk), l, hv);
+                }
+            }
+        }
+    }
+    if (ovf) atomicOr(a.lovf, 1);
 }
 
 // Roots with an empty out-neighbourhood are leaves (h=1, p=0) of the SCT.
@@ -932,41 +1254,48 @@ __global__ void __launch_bounds__(256) finalize_kernel(const unsigned long long 
 
 // ============================================================== host side
 
-template <int KL>
+template <int KL, bool EDGE>
 static hipError_t launch_mode(const LevelArgs *a, int mode, int blocks, hipStream_t s) {
     dim3 g(blocks), b(64 * WAVES_PER_BLOCK);
-    if (mode == PV_UNITS_MW) sct_level_kernel<KL, PV_UNITS_MW><<<g, b, 0, s>>>(a);
-    else if (mode == PV_UNITS_ITEMS) sct_level_kernel<KL, PV_UNITS_ITEMS><<<g, b, 0, s>>>(a);
-    else sct_level_kernel<KL, PV_UNITS_LIGHT><<<g, b, 0, s>>>(a);
+    if (mode == PV_UNITS_MW) sct_level_kernel<KL, PV_UNITS_MW, EDGE><<<g, b, 0, s>>>(a);
+    else if (mode == PV_UNITS_ITEMS) sct_level_kernel<KL, PV_UNITS_ITEMS, EDGE><<<g, b, 0, s>>>(a);
+    else sct_level_kernel<KL, PV_UNITS_LIGHT, EDGE><<<g, b, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t pv_launch_level(const LevelArgs *a, int kl, int mode, int blocks, hipStream_t s) {
-    if (kl == 0) return launch_mode<0>(a, mode, blocks, s);
-    if (kl <= 8) return launch_mode<8>(a, mode, blocks, s);
-    return launch_mode<16>(a, mode, blocks, s);
+hipError_t pv_launch_level(const LevelArgs *a, int kl, bool edge, int mode, int blocks, hipStream_t s) {
+    if (kl == 0) return launch_mode<0, false>(a, mode, blocks, s);
+    if (edge) return launch_mode<8, true>(a, mode, blocks, s);
+    if (kl <= 8) return launch_mode<8, false>(a, mode, blocks, s);
+    return launch_mode<16, false>(a, mode, blocks, s);
 }
 
-template <int KL>
+template <int KL, bool EDGE>
 static int blocks_per_cu_kl(int mode) {
     int nb = 0;
     hipError_t e;
     if (mode == PV_UNITS_MW)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_MW>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_MW, EDGE>,
                                                          64 * WAVES_PER_BLOCK, 0);
     else if (mode == PV_UNITS_ITEMS)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_ITEMS>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_ITEMS, EDGE>,
                                                          64 * WAVES_PER_BLOCK, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_LIGHT>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_LIGHT, EDGE>,
                                                          64 * WAVES_PER_BLOCK, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-int pv_level_blocks_per_cu(int kl, int mode) {
-    if (kl == 0) return blocks_per_cu_kl<0>(mode);
-    if (kl <= 8) return blocks_per_cu_kl<8>(mode);
-    return blocks_per_cu_kl<16>(mode);
+int pv_level_blocks_per_cu(int kl, bool edge, int mode) {
+    if (kl == 0) return blocks_per_cu_kl<0, false>(mode);
+    if (edge) return blocks_per_cu_kl<8, true>(mode);
+    if (kl <= 8) return blocks_per_cu_kl<8, false>(mode);
+    return blocks_per_cu_kl<16, false>(mode);
+}
+
+hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s) {
+    edge_prefix_kernel<<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsigned long long *hist,

@@ -271,3 +271,74 @@ def test_dfs_budget_splits_keep_the_tree(ctx, dfs_max, budget):
     finally:
         P.pv_set_dfs_max(ctx, 64)
         P.pv_set_dfs_budget(ctx, 2048)
+
+
+# ----------------------------------------------------------------- per-edge
+
+EDGE = [("gnp", lambda: gg.gnp(150, 0.2, 141), (1, 8)),
+        ("planted", lambda: gg.plant_cliques(gg.gnp(300, 0.05, 142), [14, 9], 143), (3, 10)),
+        ("heavy", lambda: gg.plant_cliques(gg.gnp(400, 0.04, 144), [90, 12], 145), (3, 8)),
+        ("heavy_dense", lambda: gg.plant_cliques(gg.gnp(160, 0.45, 146), [75, 40], 147), (2, 6)),
+        ("K40", lambda: gg.complete(40), (2, 9)),
+        ("multipartite", lambda: gg.complete_multipartite([1, 2, 3, 4, 5, 6, 7]), (1, 7)),
+        ("moon_moser", lambda: gg.moon_moser(7), (2, 7)),
+        ("star", lambda: gg.star(30), (1, 4)),
+        ("empty", lambda: gg.empty(6), (2, 4))]
+
+
+@pytest.mark.parametrize("name,maker,krange", EDGE, ids=[x[0] for x in EDGE])
+def test_per_edge(ctx, name, maker, krange):
+    g = maker()
+    klo, khi = krange
+    _say(f"[parity] per-edge {name}: n={g.n} m={g.m} k={klo}..{khi}")
+    with Loaded(ctx, g) as h:
+        out, ovf, st = P.pv_count_local(h, P.PV_EDGE, klo, khi)
+        eu, ev = P.pv_graph_edge_list(h)
+    ref = O.count(g, edge=(klo, khi))
+    a, b = g.edges()
+    assert np.array_equal(eu, a) and np.array_equal(ev, b)
+    assert ovf == 0
+    assert np.array_equal(out, ref.edge)
+
+
+@pytest.mark.parametrize("dfs_max,budget", [(8, 16), (64, 24), (16, 1 << 20)])
+def test_per_edge_splits(ctx, dfs_max, budget):
+    g = gg.plant_cliques(gg.gnp(400, 0.12, 191), [75, 30, 20], 192)
+    P.pv_set_dfs_max(ctx, dfs_max)
+    P.pv_set_dfs_budget(ctx, budget)
+    try:
+        _say(f"[parity] per-edge splits dfs_max={dfs_max} budget={budget}")
+        with Loaded(ctx, g) as h:
+            out, ovf, st = P.pv_count_local(h, P.PV_EDGE, 3, 8)
+        ref = O.count(g, edge=(3, 8))
+        assert ovf == 0 and np.array_equal(out, ref.edge)
+    finally:
+        P.pv_set_dfs_max(ctx, 64)
+        P.pv_set_dfs_budget(ctx, 2048)
+
+
+def test_per_edge_combined_device_output(ctx):
+    import torch
+    g = gg.plant_cliques(gg.chung_lu(5000, 16, 2.3, 800, 151), [40, 70], 152)
+    klo, khi = 3, 8
+    K = khi - klo + 1
+    _say(f"[parity] per-edge combined pass n={g.n} m={g.m}")
+    dev = torch.zeros((g.m, K, 2), dtype=torch.int64, device="cuda:0")
+    with Loaded(ctx, g) as h:
+        res, lovf = P.pv_count(h, reorient=True, local_kind=P.PV_EDGE, k_lo=klo, k_hi=khi,
+                               local_out=dev.data_ptr())
+        sub = P.pv_graph_export_order(h)
+    torch.cuda.synchronize()
+    out = dev.cpu().numpy().view(np.uint64)
+    ref = O.count(g, key=sub, edge=(klo, khi))
+    assert lovf == 0
+    assert res.counts[: len(ref.glob)] == ref.glob
+    assert np.array_equal(out, ref.edge)
+
+
+def test_per_edge_rejects_wide_range(ctx):
+    g = gg.gnp(50, 0.2, 161)
+    with Loaded(ctx, g) as h:
+        with pytest.raises(P.PivoterError) as ei:
+            P.pv_count_local(h, P.PV_EDGE, 2, 10)
+    assert ei.value.status == P.PV_EINVAL
