@@ -547,7 +547,8 @@ __global__ void __launch_bounds__(256) o2e_kernel(int n, const int *__restrict__
                         else hi = mid;
                     }
                     const int ufirst = rp[u + 1] - (up[u + 1] - up[u]);
-                    id = up[u] + (lo - ufirst);
+                    // -1 only for an asymmetric CSR loaded unchecked
+                    id = (lo < rp[u + 1] && col[lo] == v) ? up[u] + (lo - ufirst) : -1;
                 }
                 o2e[w + __popcll(m & below)] = id;
             }
