@@ -138,8 +138,8 @@ struct pv_graph {
     DBuf<uint64_t> counts, ovf, vout_own;
     // per-edge counts: edge ids of the oriented CSR and prefix-pair sums
     bool eids = false;
-    DBuf<int> eup, o2e;
-    DBuf<uint64_t> umem, utot;
+    DBuf<int> eup, o2e, ueid, weid;
+    DBuf<uint64_t> umem, utot, escr;
     size_t c_cap = 1 << 20, mw_cap = 1 << 15, u_cap = 1 << 16, pref_cap = 1 << 19;
     long long hu_budget = 1ll << 30;  // bytes of heavy universes per chunk
     pv_stats last{};
@@ -378,8 +378,11 @@ extern "C" void pv_graph_free(pv_graph *g) {
     g->vout_own.release();
     g->eup.release();
     g->o2e.release();
+    g->ueid.release();
+    g->weid.release();
     g->umem.release();
     g->utot.release();
+    g->escr.release();
     delete g;
 }
 
@@ -532,6 +535,12 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
         if (rq.edge) {
             PVCHK(g->umem.ensure(g->u_cap * 64 * 2 * rq.K * 2));
             PVCHK(g->utot.ensure(g->u_cap * 3 * rq.K * 2));
+            PVCHK(g->ueid.ensure(g->u_cap * 4096));
+            PVCHK(g->weid.ensure((size_t)c->level_blocks[3][PV_UNITS_LIGHT] * WAVES_PER_LAUNCH_BLOCK * 4096));
+            const int eb = std::max({c->level_blocks[3][0], c->level_blocks[3][1], c->level_blocks[3][2]});
+            const size_t escr_words = (size_t)eb * WAVES_PER_LAUNCH_BLOCK * 2 * 64 * 2 * rq.K * 2;
+            PVCHK(g->escr.ensure(escr_words));
+            HIPCHK(hipMemsetAsync(g->escr.p, 0, escr_words * 8, s));
         }
         if (chunk > 0) {
             PVCHK(g->hu_rows.ensure((size_t)chunk * W * dpad));
@@ -610,6 +619,9 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.o2e = rq.edge ? g->o2e.p : nullptr;
                 a.umem = rq.edge ? g->umem.p : nullptr;
                 a.utot = rq.edge ? g->utot.p : nullptr;
+                a.ueid = rq.edge ? g->ueid.p : nullptr;
+                a.weid = rq.edge ? g->weid.p : nullptr;
+                a.escr = rq.edge ? g->escr.p : nullptr;
                 const long long units = (long long)n_mw + n_c + (level == 0 ? (long long)a.nheavy + a.nlight : 0);
                 if (units == 0) break;
                 *c->h_args = a;

@@ -109,6 +109,10 @@ struct LevelArgs {
     const int *o2e;                // [m] oriented CSR position -> edge id
     uint64_t *umem;                // [u_cap][64][2][K] u128: member sums toward H / P prefix
     uint64_t *utot;                // [u_cap][3][K] u128: HH, HP, PP sums
+    int *ueid;                     // [u_cap][64][64] edge id of each member pair of a universe
+    int *weid;                     // [waves of a light-root launch][64][64] the same per wave
+    uint64_t *escr;                // [waves of a launch][2][64][2][K] u128: join snapshots and
+                                   // finished-stay sums of the path members
 };
 
 

@@ -93,7 +93,7 @@ struct VertexSink {
     int *lovf;
     int klo, K, khi;
 
-    __device__ void init(const LevelArgs &a) {
+    __device__ void init(const LevelArgs &a, uint64_t *) {
         tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
         vout = (uint64_t *)uniform64((uint64_t)a.vout);
         pool = (const int *)uniform64((uint64_t)a.pref_pool);
@@ -110,10 +110,12 @@ struct VertexSink {
     }
 
     // path bookkeeping is only needed for pairs (EdgeSink)
+    __device__ __forceinline__ void set_table(const int *) {}
+    __device__ __forceinline__ const int *etab_ptr() const { return nullptr; }
     __device__ __forceinline__ void begin(uint64_t, uint64_t, int) {}
-    __device__ __forceinline__ void join(int, uint64_t, uint64_t, int) {}
+    __device__ __forceinline__ void join(int, uint64_t, uint64_t, bool, int) {}
     __device__ __forceinline__ void join_set(uint64_t, uint64_t, uint64_t, int) {}
-    __device__ __forceinline__ void leave(uint64_t, int, int) {}
+    __device__ __forceinline__ void leave(uint64_t, uint64_t, uint64_t, int, int) {}
 
     __device__ __forceinline__ void leaf(int h, int p, uint64_t H, uint64_t P, int lane,
                                          const LevelArgs &) {
@@ -217,89 +219,119 @@ __device__ __forceinline__ int edge_id(int x, int y, const int *__restrict__ sub
 //     C(p, k-h)      to every pair of hold vertices          (type HH)
 //     C(p-1, k-h-1)  to every hold/pivot pair                (type HP)
 //     C(p-2, k-h-2)  to every pair of pivot vertices         (type PP).
-// Instead of touching every pair at every leaf, a member j of the walk's
-// path sums, while it stays on the path, what its pairs with the path
-// vertices *above it* are owed: sH toward hold partners, sP toward pivot
-// partners (each a type chosen by j's own role).  Those partners are fixed
-// for the whole stay (they were on the path when j joined and leave only
-// after j), so when j leaves, its sums are added once to each of those
-// pairs.  A pair is thus charged at the leave of its later-joined end.
-// Members that join together (the start of a walk, a clique folded into P)
-// are ordered by lane.
+// Instead of touching every pair at every leaf, a pair is charged once per
+// stay of its later-joined end j on the walk's path: the partners above j
+// stay on the path for all of j's stay, and the leaves of a stay are a
+// contiguous run of the depth-first order.  The wave keeps running sums T
+// of each type over the leaves it has visited (lane kk holds slot k = klo +
+// kk), each member records T when it joins (a snapshot in per-wave scratch
+// memory), and its stay owes T - snapshot: toward hold partners the type
+// (H, role of j), toward pivot partners (P, role of j).  Members that join
+// together (the start of a walk, a clique folded into P) are ordered by lane.
 //
 // Partners above the universe (the prefix) are on every path: a member's
-// finished stays are summed in vH/vP and added to its prefix pairs when the
-// wave leaves the universe; lanes 62 and 63 act as a hold and a pivot member
-// that never leave, which yields the sums owed to prefix/prefix pairs.  With
-// a universe in memory those sums go to per-universe accumulators and a
-// final kernel adds them to the prefix pairs once per universe.
+// finished stays are summed in per-wave scratch and added to its prefix
+// pairs when the wave leaves the universe, and T itself is what the
+// prefix/prefix pairs are owed.  With a universe in memory these sums go to
+// per-universe accumulators that a final kernel adds to the prefix pairs
+// once per universe.
 template <int KL>
 struct EdgeSink {
-    uint64_t shl[KL], shh[KL], spl[KL], sph[KL];  // current stay
-    uint64_t vhl[KL], vhh[KL], vpl[KL], vph[KL];  // finished stays
-    uint64_t BH, BP;                              // path members above this lane
+    // lane kk < K: running sums over the visit's leaves, types HH, HP, PP
+    uint64_t t0l, t0h, t1l, t1h, t2l, t2h;
+    uint64_t BH, BP;  // path members above this lane
+    const int *etab;  // edge ids of the member pairs of the universe walked now
+    uint64_t *xch;    // LDS hand-over slot of this wave (4 * KL words)
+    uint64_t *snap;   // scratch [64][2][K] u128: T at the member's join (its role's two types)
+    uint64_t *vacc;   // scratch [64][2][K] u128: finished stays toward hold / pivot prefix vertices
     // wave-uniform copies of the arguments
     const uint64_t *tab;
     uint64_t *eout, *umem, *utot;
-    const int *sub, *orow, *ocol, *o2e;
+    const int *orow, *o2e;
     int *lovf, *flags;
     int klo, K, khi;
     bool ovf;
 
-    __device__ void init(const LevelArgs &a) {
+    __device__ void init(const LevelArgs &a, uint64_t *lds_xch) {
+        xch = lds_xch;
         tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
         eout = (uint64_t *)uniform64((uint64_t)a.vout);
         umem = (uint64_t *)uniform64((uint64_t)a.umem);
         utot = (uint64_t *)uniform64((uint64_t)a.utot);
-        sub = (const int *)uniform64((uint64_t)a.sub);
         orow = (const int *)uniform64((uint64_t)a.orow);
-        ocol = (const int *)uniform64((uint64_t)a.ocol);
         o2e = (const int *)uniform64((uint64_t)a.o2e);
         lovf = (int *)uniform64((uint64_t)a.lovf);
         flags = (int *)uniform64((uint64_t)a.flags);
         klo = uniformi(a.klo);
         K = uniformi(a.K);
         khi = klo + K - 1;
+        const long long slot = (long long)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+        snap = a.escr + slot * (2ll * 64 * 2 * K * 2);
+        snap = (uint64_t *)uniform64((uint64_t)snap);
+        vacc = snap + 64 * 2 * K * 2;
+        // vacc is zero on entry (cleared by the host before the first level,
+        // and by every flush after use)
         ovf = false;
         BH = BP = 0;
-#pragma unroll
-        for (int i = 0; i < KL; i++) shl[i] = shh[i] = spl[i] = sph[i] = 0;
-        reset();
+        etab = nullptr;
+        t0l = t0h = t1l = t1h = t2l = t2h = 0;
     }
 
-    __device__ void reset() {
-#pragma unroll
-        for (int i = 0; i < KL; i++) vhl[i] = vhh[i] = vpl[i] = vph[i] = 0;
+    __device__ __forceinline__ void set_table(const int *t) { etab = (const int *)uniform64((uint64_t)t); }
+    __device__ __forceinline__ const int *etab_ptr() const { return etab; }
+
+    // member j (wave-uniform) joins in role P (isP) or H: record T
+    __device__ __forceinline__ void snap_one(int j, bool isP, int lane) {
+        if (lane < K) {
+            uint64_t *d = snap + 2 * (((long long)j * 2) * K + lane);
+            d[0] = isP ? t1l : t0l;
+            d[1] = isP ? t1h : t0h;
+            d[2 * K] = isP ? t2l : t1l;
+            d[2 * K + 1] = isP ? t2h : t1h;
+        }
     }
 
-    __device__ __forceinline__ void begin(uint64_t H, uint64_t P, int lane) {
+    __device__ void begin(uint64_t H, uint64_t P, int lane) {
+        H = uniform64(H);
+        P = uniform64(P);
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         if (((H | P) >> lane) & 1) {
             BH = H & below;
             BP = P & below;
         }
+        for (uint64_t r = H | P; r; r &= r - 1) {
+            const int j = __builtin_ctzll(r);
+            snap_one(j, (P >> j) & 1, lane);
+        }
     }
 
-    __device__ __forceinline__ void join(int j, uint64_t Hb, uint64_t Pb, int lane) {
+    __device__ __forceinline__ void join(int j, uint64_t Hb, uint64_t Pb, bool isP, int lane) {
         if (lane == j) {
             BH = Hb;
             BP = Pb;
         }
+        snap_one(j, isP, lane);
     }
 
-    __device__ __forceinline__ void join_set(uint64_t Sm, uint64_t Hb, uint64_t Pb, int lane) {
+    __device__ void join_set(uint64_t Sm, uint64_t Hb, uint64_t Pb, int lane) {
+        Sm = uniform64(Sm);
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         if ((Sm >> lane) & 1) {
             BH = Hb;
             BP = Pb | (Sm & below);
         }
+        for (uint64_t r = Sm; r; r &= r - 1) snap_one(__builtin_ctzll(r), true, lane);
     }
 
-    __device__ __forceinline__ void leaf(int h, int p, uint64_t H, uint64_t P, int lane,
-                                         const LevelArgs &) {
+    // add x (wave-uniform) to the u128 (lo, hi) of lane kk
+    static __device__ __forceinline__ void add_at(uint64_t &lo, uint64_t &hi, uint64_t x, int kk, int lane) {
+        const uint64_t v = (lane == kk) ? x : 0ull;
+        lo += v;
+        hi += (lo < v) ? 1ull : 0ull;
+    }
+
+    __device__ __forceinline__ void leaf(int h, int p, uint64_t, uint64_t, int lane, const LevelArgs &) {
         if (h > khi || h + p < klo) return;
-        const bool inH = ((H >> lane) & 1) || lane == 62;
-        const bool inP = ((P >> lane) & 1) || lane == 63;
         // rows of C(p, .), C(p-1, .), C(p-2, .) at column k - h, k - h - 1,
         // k - h - 2 (row -1 is all zeros and stands in for row -2: with
         // p = 0 there is no pivot vertex, so PP is never owed)
@@ -309,104 +341,103 @@ struct EdgeSink {
 #pragma unroll
         for (int kk = 0; kk < KL; kk++) {
             if (kk < K) {
-                const uint64_t hh = ldc64(rowHH + kk), hp = ldc64(rowHP + kk), pp = ldc64(rowPP + kk);
-                const uint64_t toH = inH ? hh : (inP ? hp : 0ull);
-                const uint64_t toP = inH ? hp : (inP ? pp : 0ull);
-                shl[kk] += toH;
-                shh[kk] += (shl[kk] < toH) ? 1ull : 0ull;
-                spl[kk] += toP;
-                sph[kk] += (spl[kk] < toP) ? 1ull : 0ull;
+                add_at(t0l, t0h, ldc64(rowHH + kk), kk, lane);
+                add_at(t1l, t1h, ldc64(rowHP + kk), kk, lane);
+                add_at(t2l, t2h, ldc64(rowPP + kk), kk, lane);
             }
         }
     }
 
-    // members in L leave the path: charge their stays to their pairs
-    __device__ void leave(uint64_t L, int lane, int gid) {
+    // members in L leave the path (H, P: the path they leave from)
+    __device__ void leave(uint64_t L, uint64_t H, uint64_t P, int lane, int) {
         L = uniform64(L) & ((1ull << 62) - 1);
-        uint64_t rest = L;
-        while (rest) {
+        P = uniform64(P);
+        for (uint64_t rest = L; rest; rest &= rest - 1) {
             const int j = __builtin_ctzll(rest);
-            rest &= rest - 1;
+            const bool isP = (P >> j) & 1;
             const uint64_t bh = readlane64(BH, j), bp = readlane64(BP, j);
-            if ((bh | bp) == 0) continue;
-            const int gj = (int)readlane32((uint32_t)gid, j);
-            const bool mine = ((bh | bp) >> lane) & 1;
-            const bool isH = (bh >> lane) & 1;
-            int e = -1;
-            if (mine) {
-                e = edge_id(gid, gj, sub, orow, ocol, o2e);
-                if (e < 0) atomicOr(flags, 4);
+            // lane kk: what the stay owes toward hold (a) and pivot (b) partners
+            uint64_t al = 0, ah = 0, bl = 0, bhh = 0;
+            if (lane < K) {
+                const uint64_t *sp = snap + 2 * (((long long)j * 2) * K + lane);
+                uint64_t *va = vacc + 2 * (((long long)j * 2) * K + lane);
+                const uint64_t s0l = sp[0], s0h = sp[1], s1l = sp[2 * K], s1h = sp[2 * K + 1];
+                const uint64_t ta_l = isP ? t1l : t0l, ta_h = isP ? t1h : t0h;
+                const uint64_t tb_l = isP ? t2l : t1l, tb_h = isP ? t2h : t1h;
+                al = ta_l - s0l;
+                ah = ta_h - s0h - ((ta_l < s0l) ? 1ull : 0ull);
+                bl = tb_l - s1l;
+                bhh = tb_h - s1h - ((tb_l < s1l) ? 1ull : 0ull);
+                const uint64_t v0l = va[0], v0h = va[1], v1l = va[2 * K], v1h = va[2 * K + 1];
+                const uint64_t n0 = v0l + al, n1 = v1l + bl;
+                va[0] = n0;
+                va[1] = v0h + ah + ((n0 < al) ? 1ull : 0ull);
+                va[2 * K] = n1;
+                va[2 * K + 1] = v1h + bhh + ((n1 < bl) ? 1ull : 0ull);
             }
-#pragma unroll
-            for (int kk = 0; kk < KL; kk++) {
-                if (kk < K) {
-                    const uint64_t hl = readlane64(shl[kk], j), hh = readlane64(shh[kk], j);
-                    const uint64_t pl = readlane64(spl[kk], j), ph = readlane64(sph[kk], j);
-                    const uint64_t l = isH ? hl : pl, hv = isH ? hh : ph;
-                    if (e >= 0 && (l | hv))
-                        ovf |= atomic_add_u128(eout + 2 * ((long long)e * K + kk), l, hv);
+            if ((bh | bp) == 0) continue;
+            if (lane < K) {
+                xch[4 * lane + 0] = al;
+                xch[4 * lane + 1] = ah;
+                xch[4 * lane + 2] = bl;
+                xch[4 * lane + 3] = bhh;
+            }
+            wave_sync();
+            if (((bh | bp) >> lane) & 1) {
+                const int e = etab[j * 64 + lane];
+                if (e < 0) atomicOr(flags, 4);
+                const int sel = ((bh >> lane) & 1) ? 0 : 2;
+                uint64_t *dst = eout + 2 * ((long long)e * K);
+                for (int kk = 0; kk < K; kk++) {
+                    const uint64_t l = xch[4 * kk + sel], hv = xch[4 * kk + sel + 1];
+                    if (e >= 0 && (l | hv)) ovf |= atomic_add_u128(dst + 2 * kk, l, hv);
                 }
             }
-        }
-        if ((L >> lane) & 1) {
-#pragma unroll
-            for (int kk = 0; kk < KL; kk++) {
-                vhl[kk] += shl[kk];
-                vhh[kk] += shh[kk] + ((vhl[kk] < shl[kk]) ? 1ull : 0ull);
-                vpl[kk] += spl[kk];
-                vph[kk] += sph[kk] + ((vpl[kk] < spl[kk]) ? 1ull : 0ull);
-                shl[kk] = shh[kk] = spl[kk] = sph[kk] = 0;
-            }
+            wave_sync();
         }
     }
 
     // The wave leaves the universe (every stay of a member is finished):
     // prefix pairs.  With root >= 0 the prefix is that single hold vertex;
     // otherwise the sums go to universe `uni`'s accumulators.
-    __device__ void flush(int lane, int nm, int gid, int root, int2, int uni, const LevelArgs &) {
+    __device__ void flush(int lane, int nm, int, int root, int2, int uni, const LevelArgs &) {
         root = uniformi(root);
         uni = uniformi(uni);
+        nm = uniformi(nm);
         if (root >= 0) {
+            // a light root's walk: member `lane` is the root's lane-th out-neighbour
             if (lane < nm) {
-                const int e = edge_id(root, gid, sub, orow, ocol, o2e);
+                const int e = o2e[orow[root] + lane];
                 if (e < 0) atomicOr(flags, 4);
-#pragma unroll
-                for (int kk = 0; kk < KL; kk++)
-                    if (kk < K && e >= 0 && (vhl[kk] | vhh[kk]))
-                        ovf |= atomic_add_u128(eout + 2 * ((long long)e * K + kk), vhl[kk], vhh[kk]);
+                const uint64_t *va = vacc + 2 * (((long long)lane * 2) * K);
+                for (int kk = 0; kk < K; kk++) {
+                    const uint64_t l = va[2 * kk], hv = va[2 * kk + 1];
+                    if (e >= 0 && (l | hv)) ovf |= atomic_add_u128(eout + 2 * ((long long)e * K + kk), l, hv);
+                }
             }
         } else if (uni >= 0) {
-            const long long ub = (long long)uni * 64 + lane;
             if (lane < nm) {
-#pragma unroll
-                for (int kk = 0; kk < KL; kk++) {
-                    if (kk < K) {
-                        if (vhl[kk] | vhh[kk])
-                            ovf |= atomic_add_u128(umem + 2 * ((ub * 2 + 0) * K + kk), vhl[kk], vhh[kk]);
-                        if (vpl[kk] | vph[kk])
-                            ovf |= atomic_add_u128(umem + 2 * ((ub * 2 + 1) * K + kk), vpl[kk], vph[kk]);
-                    }
+                const uint64_t *va = vacc + 2 * (((long long)lane * 2) * K);
+                uint64_t *um = umem + 2 * ((((long long)uni * 64 + lane) * 2) * K);
+                for (int i = 0; i < 2 * K; i++) {
+                    const uint64_t l = va[2 * i], hv = va[2 * i + 1];
+                    if (l | hv) ovf |= atomic_add_u128(um + 2 * i, l, hv);
                 }
-            } else if (lane >= 62) {
-                // lane 62: HH (its sH) and HP (its sP); lane 63: PP (its sP)
-                const long long tb = (long long)uni * 3;
-#pragma unroll
-                for (int kk = 0; kk < KL; kk++) {
-                    if (kk < K) {
-                        if (lane == 62 && (shl[kk] | shh[kk]))
-                            ovf |= atomic_add_u128(utot + 2 * ((tb + 0) * K + kk), shl[kk], shh[kk]);
-                        if (spl[kk] | sph[kk])
-                            ovf |= atomic_add_u128(utot + 2 * ((tb + (lane == 62 ? 1 : 2)) * K + kk),
-                                                   spl[kk], sph[kk]);
-                    }
-                }
+            }
+            if (lane < K) {
+                uint64_t *ut = utot + 2 * ((long long)uni * 3 * K + lane);
+                if (t0l | t0h) ovf |= atomic_add_u128(ut, t0l, t0h);
+                if (t1l | t1h) ovf |= atomic_add_u128(ut + 2 * K, t1l, t1h);
+                if (t2l | t2h) ovf |= atomic_add_u128(ut + 4 * K, t2l, t2h);
             }
         }
         if (ovf) atomicOr(lovf, 1);
         ovf = false;
-        reset();
-#pragma unroll
-        for (int kk = 0; kk < KL; kk++) shl[kk] = shh[kk] = spl[kk] = sph[kk] = 0;
+        if (lane < nm) {
+            uint64_t *va = vacc + 2 * (((long long)lane * 2) * K);
+            for (int i = 0; i < 4 * K; i++) va[i] = 0ull;
+        }
+        t0l = t0h = t1l = t1h = t2l = t2h = 0;
     }
 };
 
@@ -428,7 +459,7 @@ struct Ctr {
 template <int KL, bool EDGE>
 __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelArgs &a,
                              int root, uint64_t Hw, uint64_t Pw, const int *vl, int W,
-                             int2 &pref);
+                             int2 &pref, const int *src_etab);
 
 // ------------------------------------------------------ compact-tier DFS
 // Walk the whole subtree of node (S, H, P, h, p) of a compact universe
@@ -482,7 +513,8 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                 // ---- split: the pending node and every stack frame become items
                 if (uni < 0) {
                     int2 pref;
-                    uni = make_universe<KL, EDGE>(A, nm, gid, lane, a, root, 0ull, 0ull, nullptr, 0, pref);
+                    uni = make_universe<KL, EDGE>(A, nm, gid, lane, a, root, 0ull, 0ull, nullptr, 0, pref,
+                                                  EDGE ? vs.etab_ptr() : nullptr);
                     if (uni < 0) break;  // buffers full: the host reruns with larger ones
                 }
                 const int total = depth + 1;
@@ -537,7 +569,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                     } else {
                         S &= ~pbit;
                         if (LOCAL) {
-                            vs.join(piv, H, P, lane);
+                            vs.join(piv, H, P, true, lane);
                             P |= pbit;
                         }
                         p++;
@@ -557,7 +589,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                     }
                     S &= Ap;
                     if (LOCAL) {
-                        vs.join(piv, H, P, lane);
+                        vs.join(piv, H, P, true, lane);
                         P |= pbit;
                     }
                     p++;
@@ -586,13 +618,13 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
         p = (int)(M >> 19);
         if (LOCAL) {
             const uint64_t Ht = readlane64(stH, t), Pt = readlane64(stP, t);
-            vs.leave((H | P) & ~(Ht | Pt), lane, gid);
-            vs.join(v, Ht, Pt, lane);
+            vs.leave((H | P) & ~(Ht | Pt), H, P, lane, gid);
+            vs.join(v, Ht, Pt, false, lane);
             H = Ht | vbit;
             P = Pt;
         }
     }
-    if (LOCAL) vs.leave(H | P, lane, gid);
+    if (LOCAL) vs.leave(H | P, H, P, lane, gid);
     ct.nodes += nodes;
     ct.work += work;
     gs.add_leaves(nleaves, lane);
@@ -646,7 +678,7 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                 gs.add_leaves(1, lane);
                 if (LOCAL) {
                     vs.leaf(h, p, H, P, lane, a);
-                    vs.leave(H | P, lane, gid);
+                    vs.leave(H | P, H, P, lane, gid);
                 }
                 break;
             }
@@ -692,7 +724,7 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
 template <int KL, bool EDGE>
 __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelArgs &a,
                              int root, uint64_t Hw, uint64_t Pw, const int *vl, int W,
-                             int2 &pref) {
+                             int2 &pref, const int *src_etab) {
     constexpr bool LOCAL = KL > 0;
     int uni = 0;
     if (lane == 0) uni = atomicAdd(a.u_n, 1);
@@ -739,6 +771,27 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
                 for (int i = 0; i < 4 * K; i++) ut[i] = 0ull;
             if (lane == 63)
                 for (int i = 0; i < 2 * K; i++) ut[4 * K + i] = 0ull;
+            // edge ids of the member pairs: copied from the walk's own table,
+            // or looked up once here (u_gid above must be visible first)
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            __builtin_amdgcn_wave_barrier();
+            int *dst = a.ueid + (long long)uni * 4096;
+            if (src_etab) {
+                for (int r = 0; r < nm; r++) dst[r * 64 + lane] = src_etab[r * 64 + lane];
+            } else if (lane < nm) {
+                const uint64_t above = (lane == 63) ? 0ull : (~0ull << (lane + 1));
+                uint64_t rest = A & above;
+                while (rest) {
+                    const int j = __builtin_ctzll(rest);
+                    rest &= rest - 1;
+                    const int gj = a.u_gid[(long long)uni * 64 + j];
+                    const int e = edge_id(gid, gj, a.sub, a.orow, a.ocol, a.o2e);
+                    dst[lane * 64 + j] = e;
+                    dst[j * 64 + lane] = e;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            __builtin_amdgcn_wave_barrier();
         }
     }
     return uni;
@@ -792,7 +845,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
             int uni = -1;
             // the root and the multi-word holds/pivots form the prefix
             if (s > a.dfs_max || LOCAL) {
-                uni = make_universe<KL, EDGE>(A, s, gid, lane, a, root, Hw, Pw, vl, W, pref);
+                uni = make_universe<KL, EDGE>(A, s, gid, lane, a, root, Hw, Pw, vl, W, pref, nullptr);
                 if (uni < 0) return false;  // buffers full: the host reruns with larger ones
             }
             cs.A = A;
@@ -870,7 +923,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
 // once, from its smaller-key end).
 
 __device__ uint64_t gather_light(int v, int lane, const LevelArgs &a, int *s_vl, int *s_pre,
-                                 unsigned long long *s_A, int &d, int &gid) {
+                                 unsigned long long *s_A, int &d, int &gid, int *etab) {
     const int b = a.orow[v];
     d = a.orow[v + 1] - b;
     const int u = (lane < d) ? a.ocol[b + lane] : 0x7fffffff;
@@ -891,7 +944,8 @@ __device__ uint64_t gather_light(int v, int lane, const LevelArgs &a, int *s_vl,
                 if (s_pre[mid] <= q) lo = mid; else hi = mid - 1;
             }
             const int j = lo;
-            const int w = a.ocol[a.orow[s_vl[j]] + (q - s_pre[j])];
+            const int pos = a.orow[s_vl[j]] + (q - s_pre[j]);
+            const int w = a.ocol[pos];
             int l2 = 0, h2 = d;
             while (l2 < h2) {
                 const int mid = (l2 + h2) >> 1;
@@ -900,8 +954,18 @@ __device__ uint64_t gather_light(int v, int lane, const LevelArgs &a, int *s_vl,
             if (l2 < d && s_vl[l2] == w) {
                 atomicOr(&s_A[j], 1ull << l2);
                 atomicOr(&s_A[l2], 1ull << j);
+                if (etab) {
+                    // per-edge counts: the pair's edge id comes with the oriented edge
+                    const int e = a.o2e[pos];
+                    etab[j * 64 + l2] = e;
+                    etab[l2 * 64 + j] = e;
+                }
             }
         }
+    }
+    if (etab) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        __builtin_amdgcn_wave_barrier();
     }
     wave_sync();
     const uint64_t A = (lane < d) ? (uint64_t)s_A[lane] : 0ull;
@@ -962,7 +1026,8 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
     GlobalSink gs;
     gs.init(a, s_bins);
     typename SinkOf<KL, EDGE>::T vs;
-    if (LOCAL) vs.init(a);
+    __shared__ uint64_t s_xch[WAVES_PER_BLOCK][EDGE ? 4 * KL : 1];
+    if (LOCAL) vs.init(a, s_xch[wv]);
     Ctr ct;
     ct.nodes = ct.work = 0;
     int *cursor = a.next + MODE;
@@ -1001,6 +1066,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
             }
             CState cs;
             if (mw_run<KL, EDGE>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs)) {
+                if (EDGE) vs.set_table(a.ueid + (long long)cs.uni * 4096);
                 compact_run<KL, EDGE>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
                                 cs.pref, lane, a, gs, vs, ct);
                 if (LOCAL) vs.flush(lane, cs.nm, cs.gid, cs.root, cs.pref, cs.uni, a);
@@ -1025,6 +1091,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
                 pref = a.u_pref[u];
             }
             const int nm = (int)wave_add_u32(gid >= 0 ? 1u : 0u);
+            if (EDGE) vs.set_table(a.ueid + (long long)u * 4096);
             compact_run<KL, EDGE>(A, it.S, it.H, it.P, (int)(it.hp & 0xFFFFu), (int)(it.hp >> 16), u, nm,
                             gid, -1, pref, lane, a, gs, vs, ct, fr, it.hp);
             if (LOCAL) vs.flush(lane, nm, gid, -1, pref, u, a);
@@ -1034,6 +1101,9 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
         __shared__ int s_pre[WAVES_PER_BLOCK][64];
         __shared__ unsigned long long s_A[WAVES_PER_BLOCK][64];
         const int n = a.nlight;
+        // per-edge counts: this wave's table of member-pair edge ids
+        int *etab_w = EDGE ? a.weid + (long long)(blockIdx.x * WAVES_PER_BLOCK + wv) * 4096 : nullptr;
+        if (EDGE) vs.set_table(etab_w);
         for (;;) {
             int idx = 0;
             if (lane == 0) idx = atomicAdd(cursor, 1);
@@ -1041,11 +1111,11 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
             if (idx >= n) break;
             const int v = a.order[a.light_base + idx];
             int d, gid;
-            const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_A[wv], d, gid);
+            const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_A[wv], d, gid, etab_w);
             int uni = -1;
             int2 pref = make_int2(0, 0);
             if (d > a.dfs_max) {
-                uni = make_universe<KL, EDGE>(A, d, gid, lane, a, v, 0ull, 0ull, nullptr, 0, pref);
+                uni = make_universe<KL, EDGE>(A, d, gid, lane, a, v, 0ull, 0ull, nullptr, 0, pref, etab_w);
                 if (uni < 0) continue;  // buffers full: the host reruns with larger ones
             }
             const int root = (uni < 0) ? v : -1;
