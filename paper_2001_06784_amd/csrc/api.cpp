@@ -111,6 +111,9 @@ struct pv_ctx {
     int level_blocks[4][3] = {};  // [variant: global, vertex 8, vertex 16, edge 8][unit kind]
     int dfs_max = 64;
     int dfs_budget = 2048;
+    // batches: the union graph (reused between calls) and its part table
+    pv_graph *batch = nullptr;
+    DBuf<BatchPart> parts;
     // device timing (HIP events on the context stream)
     bool timing = false;
     hipEvent_t ev[16] = {};
@@ -136,6 +139,9 @@ struct pv_graph {
     DBuf<int2> u_pref;
     DBuf<unsigned long long> hist, counters;
     DBuf<uint64_t> counts, ovf, vout_own;
+    DBuf<int> omegas;
+    // batches: graph of every union vertex, root vertex of every universe
+    DBuf<int> vgraph, u_root;
     // per-edge counts: edge ids of the oriented CSR and prefix-pair sums
     bool eids = false;
     DBuf<int> eup, o2e, ueid, weid;
@@ -202,6 +208,9 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
 extern "C" void pv_fini(pv_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    if (c->batch) pv_graph_free(c->batch);
+    c->batch = nullptr;
+    c->parts.release();
     c->tab.release();
     c->tab64.release();
     c->tab_pad.release();
@@ -279,6 +288,10 @@ static pv_status graph_new(pv_ctx *c, int32_t n, long long nnz, pv_graph **out) 
         (s = g->small.ensure(SM_COUNT)) != PV_OK) {
         pv_graph_free(g);
         return s;
+    }
+    if (hipMemsetAsync(g->small.p, 0, SM_COUNT * sizeof(int), c->stream) != hipSuccess) {
+        pv_graph_free(g);
+        return PV_EDEVICE;
     }
     *out = g;
     return PV_OK;
@@ -376,6 +389,9 @@ extern "C" void pv_graph_free(pv_graph *g) {
     g->counts.release();
     g->ovf.release();
     g->vout_own.release();
+    g->omegas.release();
+    g->vgraph.release();
+    g->u_root.release();
     g->eup.release();
     g->o2e.release();
     g->ueid.release();
@@ -492,6 +508,8 @@ struct CountReq {
     int kmax = 0;
     int kl = 0;           // register k-slots for local counts (0: none)
     bool edge = false;    // local counts are per edge
+    int graphs = 1;       // batch: parts of the disjoint union (one histogram each)
+    const int *vgraph = nullptr;  // batch: part of every vertex
     int klo = 1, K = 0;
     uint64_t *vout = nullptr;  // device [n][K] u128
     int c0 = 1;           // value of C_0
@@ -520,7 +538,8 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
 
     for (int attempt = 0;; attempt++) {
         if (attempt > 12) return PV_ENOMEM;
-        PVCHK(g->hist.ensure((size_t)hd * hd));
+        PVCHK(g->hist.ensure((size_t)rq.graphs * hd * hd));
+        if (rq.vgraph) PVCHK(g->u_root.ensure(g->u_cap));
         PVCHK(g->counters.ensure(8));
         for (int i = 0; i < 2; i++) {
             PVCHK(g->citem[i].ensure(g->c_cap));
@@ -546,7 +565,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             PVCHK(g->hu_rows.ensure((size_t)chunk * W * dpad));
             PVCHK(g->hu_vl.ensure((size_t)chunk * dpad));
         }
-        HIPCHK(hipMemsetAsync(g->hist.p, 0, sizeof(unsigned long long) * (size_t)hd * hd, s));
+        HIPCHK(hipMemsetAsync(g->hist.p, 0, sizeof(unsigned long long) * (size_t)rq.graphs * hd * hd, s));
         HIPCHK(hipMemsetAsync(g->counters.p, 0, 8 * sizeof(unsigned long long), s));
         HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, 5 * sizeof(int), s));  // flags,u_n,pref_n,omega,lovf
         const size_t lrows = rq.edge ? (size_t)(g->nnz / 2) : (size_t)g->n;
@@ -554,9 +573,10 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
         if (rq.whole)
             HIPCHK(pv_launch_sink_roots(g->n, g->order.p, g->small.p + SM_BOUNDS, g->hist.p, hd,
                                         g->counters.p, (local && !rq.edge) ? rq.vout : nullptr,
-                                        rq.klo, rq.K, s));
+                                        rq.klo, rq.K, rq.vgraph, s));
 
         bool overflow = false;
+        bool io_fresh = false;  // io holds a readback of this attempt's flags
         int levels = 0;
         float ms_levels = 0.f;
         float ms_kind[3] = {0.f, 0.f, 0.f};
@@ -622,6 +642,8 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.ueid = rq.edge ? g->ueid.p : nullptr;
                 a.weid = rq.edge ? g->weid.p : nullptr;
                 a.escr = rq.edge ? g->escr.p : nullptr;
+                a.vgraph = rq.vgraph;
+                a.u_root = rq.vgraph ? g->u_root.p : nullptr;
                 const long long units = (long long)n_mw + n_c + (level == 0 ? (long long)a.nheavy + a.nlight : 0);
                 if (units == 0) break;
                 *c->h_args = a;
@@ -643,6 +665,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 if (c->timing) HIPCHK(hipEventRecord(c->ev[4], s));
                 HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
+                io_fresh = true;
                 levels++;
                 if (c->timing) {
                     ms_levels += elapsed(c, 3, 4);
@@ -674,11 +697,13 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             // launch arguments still holds the last level's (the universe
             // buffers and outputs are the same for every level)
             const int blocks = std::max(1, std::min(c->dev.num_cu * 16, (int)((io[SM_UN] + 3) / 4)));
-            HIPCHK(pv_launch_edge_prefix(c->d_args.p, blocks, s));
-            HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            if (io_fresh) {  // no level ran: no universe, nothing to add
+                HIPCHK(pv_launch_edge_prefix(c->d_args.p, blocks, s));
+                HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+            }
         }
-        if (io[SM_FLAGS] & 4) {
+        if (io_fresh && (io[SM_FLAGS] & 4)) {
             snprintf(g_last_error, sizeof g_last_error, "edge id lookup failed");
             return PV_EDEVICE;
         }
@@ -702,49 +727,62 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
     const int hd = g->alpha + 2;
     const int kcap = hd;
     const int nw = (kcap + 63) / 64;
-    PVCHK(g->counts.ensure((size_t)kcap * 2));
-    PVCHK(g->ovf.ensure(nw));
-    HIPCHK(hipMemsetAsync(g->ovf.p, 0, nw * sizeof(uint64_t), s));
-    HIPCHK(hipMemsetAsync(g->small.p + SM_OMEGA, 0, sizeof(int), s));
+    const int G = rq.graphs;  // 1, or the parts of a batch (one histogram each)
+    PVCHK(g->counts.ensure((size_t)G * kcap * 2));
+    PVCHK(g->ovf.ensure((size_t)G * nw));
+    PVCHK(g->omegas.ensure(G));
+    HIPCHK(hipMemsetAsync(g->ovf.p, 0, (size_t)G * nw * sizeof(uint64_t), s));
+    HIPCHK(hipMemsetAsync(g->omegas.p, 0, (size_t)G * sizeof(int), s));
     if (c->timing) HIPCHK(hipEventRecord(c->ev[5], s));
     HIPCHK(pv_launch_finalize(g->hist.p, hd, c->tab.p, c->bad.p, c->bn, kcap, rq.kmax, rq.c0,
-                              g->counts.p, g->ovf.p, g->small.p + SM_OMEGA, s));
+                              g->counts.p, g->ovf.p, g->omegas.p, G, s));
     if (c->timing) HIPCHK(hipEventRecord(c->ev[6], s));
-    std::vector<uint64_t> hc((size_t)kcap * 2), ho(nw);
+    std::vector<uint64_t> hc((size_t)G * kcap * 2), ho((size_t)G * nw);
+    std::vector<int> hom(G);
     unsigned long long hcnt[8];
     HIPCHK(hipMemcpyAsync(hc.data(), g->counts.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(ho.data(), g->ovf.p, nw * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ho.data(), g->ovf.p, ho.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hom.data(), g->omegas.p, (size_t)G * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hcnt, g->counters.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(c->h_io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const int omega = c->h_io[SM_OMEGA];
+    int omega_max = 0;
+    for (int b = 0; b < G; b++) omega_max = std::max(omega_max, hom[b]);
     g->last.nodes = hcnt[0];
     g->last.leaves = hcnt[1];
     g->last.work = hcnt[2];
     for (int mode = 0; mode < 3; mode++) g->last.work_kind[mode] = hcnt[4 + mode];
     if (c->timing) g->last.ms_finalize = elapsed(c, 5, 6);
     g->last.alpha = g->alpha;
-    g->last.omega = omega;
+    g->last.omega = omega_max;
     g->last.subrounds = g->subrounds;
     if (stats) *stats = g->last;
-    if (omega_out) *omega_out = omega;
     if (local_ovf) *local_ovf = c->h_io[SM_LOVF] ? ~0ull : 0ull;
-    const int top = (rq.kmax > 0) ? std::min(omega, rq.kmax) : omega;
-    if (counts) {
-        for (int k = 0; k < cap; k++) {
-            counts[k].lo = (k < kcap) ? hc[2 * k] : 0;
-            counts[k].hi = (k < kcap) ? hc[2 * k + 1] : 0;
+    bool any_ovf = false, short_buf = false;
+    const int cw = (cap + 63) / 64;
+    for (int b = 0; b < G; b++) {
+        const int omega = hom[b];
+        if (omega_out) omega_out[b] = omega;
+        const int top = (rq.kmax > 0) ? std::min(omega, rq.kmax) : omega;
+        if (counts) {
+            pv_u128 *row = counts + (size_t)b * cap;
+            const uint64_t *src = hc.data() + (size_t)b * kcap * 2;
+            for (int k = 0; k < cap; k++) {
+                row[k].lo = (k < kcap) ? src[2 * k] : 0;
+                row[k].hi = (k < kcap) ? src[2 * k + 1] : 0;
+            }
+            if (cap <= top) short_buf = true;
+        }
+        uint64_t *ob = overflow_bits ? overflow_bits + (size_t)b * cw : nullptr;
+        if (ob) memset(ob, 0, sizeof(uint64_t) * (size_t)cw);
+        for (int k = 0; k < kcap; k++) {
+            if ((ho[(size_t)b * nw + (k >> 6)] >> (k & 63)) & 1) {
+                any_ovf = true;
+                if (ob && k < cap) ob[k >> 6] |= 1ull << (k & 63);
+            }
         }
     }
-    bool any_ovf = false;
-    if (overflow_bits) memset(overflow_bits, 0, sizeof(uint64_t) * (size_t)((cap + 63) / 64));
-    for (int k = 0; k < kcap; k++) {
-        if ((ho[k >> 6] >> (k & 63)) & 1) {
-            any_ovf = true;
-            if (overflow_bits && k < cap) overflow_bits[k >> 6] |= 1ull << (k & 63);
-        }
-    }
-    if (counts && cap <= top) return PV_EBUFSIZE;
+    if (short_buf) return PV_EBUFSIZE;
     if (any_ovf || (local_ovf && *local_ovf)) return PV_EOVERFLOW;
     return PV_OK;
 }
@@ -923,24 +961,51 @@ extern "C" pv_status pv_count_global_batch(pv_ctx *c, int32_t G, pv_graph *const
                                            pv_u128 *counts, int32_t cap, int32_t *omega,
                                            uint64_t *overflow_bits, pv_stats *stats) {
     if (!c || G < 0 || (G > 0 && (!gs || !counts)) || cap < 1) return PV_EINVAL;
-    const int nw = (cap + 63) / 64;
-    pv_status first = PV_OK;
-    pv_stats tot{};
-    for (int i = 0; i < G; i++) {
-        if (!gs[i] || gs[i]->ctx != c) return PV_EINVAL;
-        pv_stats st{};
-        int32_t om = 0;
-        pv_status s = pv_count_global(gs[i], k_max, counts + (size_t)i * cap, cap, &om,
-                                      overflow_bits ? overflow_bits + (size_t)i * nw : nullptr, &st);
-        if (omega) omega[i] = om;
-        if (s != PV_OK && first == PV_OK) first = s;
-        if (s != PV_OK && s != PV_EOVERFLOW && s != PV_EBUFSIZE) return s;
-        tot.nodes += st.nodes;
-        tot.leaves += st.leaves;
-        tot.items += st.items;
-        tot.alpha = std::max(tot.alpha, st.alpha);
-        tot.omega = std::max(tot.omega, st.omega);
+    if (G == 0) {
+        if (stats) *stats = pv_stats{};
+        return PV_OK;
     }
-    if (stats) *stats = tot;
-    return first;
+    HIPCHK(hipSetDevice(c->device));
+    // the batch is counted as the disjoint union of its graphs
+    std::vector<BatchPart> parts(G);
+    long long N = 0, NNZ = 0;
+    for (int b = 0; b < G; b++) {
+        const pv_graph *g = gs[b];
+        if (!g || g->ctx != c) return PV_EINVAL;
+        parts[b].rp = g->rp.p;
+        parts[b].col = g->col.p;
+        parts[b].n = g->n;
+        parts[b].voff = (int)N;
+        parts[b].eoff = NNZ;
+        parts[b].nnz = g->nnz;
+        N += g->n;
+        NNZ += g->nnz;
+    }
+    if (N >= (1ll << 30) || NNZ >= (1ll << 31)) return PV_ETOOBIG;
+    if (!c->batch) PVCHK(graph_new(c, 0, 0, &c->batch));
+    pv_graph *u = c->batch;
+    u->n = (int)N;
+    u->nnz = NNZ;
+    u->oriented = false;
+    u->eids = false;
+    PVCHK(u->rp.ensure((size_t)N + 1));
+    PVCHK(u->col.ensure((size_t)std::max<long long>(NNZ, 1)));
+    PVCHK(u->vgraph.ensure((size_t)std::max<long long>(N, 1)));
+    PVCHK(c->parts.ensure(G));
+    hipStream_t s = c->stream;
+    HIPCHK(hipMemcpyAsync(c->parts.p, parts.data(), sizeof(BatchPart) * G, hipMemcpyHostToDevice, s));
+    HIPCHK(pv_launch_concat(c->parts.p, G, 0, u->rp.p, u->col.p, u->vgraph.p, s));
+    const int nnz32 = (int)NNZ;  // the union's row_ptr[N] (a blocking copy: the source is on the stack)
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(u->rp.p + N, &nnz32, sizeof(int), hipMemcpyHostToDevice));
+    PVCHK(prepare(u, true));
+    CountReq rq;
+    rq.kmax = k_max > 0 ? k_max : 0;
+    rq.graphs = G;
+    rq.vgraph = u->vgraph.p;
+    rq.order = u->order.p;
+    rq.nheavy = u->nheavy;
+    rq.nlight = u->nnonzero - u->nheavy;
+    PVCHK(run_sct(u, rq));
+    return finish_counts(u, rq, counts, cap, omega, overflow_bits, stats, nullptr);
 }

@@ -113,6 +113,10 @@ struct LevelArgs {
     int *weid;                     // [waves of a light-root launch][64][64] the same per wave
     uint64_t *escr;                // [waves of a launch][2][64][2][K] u128: join snapshots and
                                    // finished-stay sums of the path members
+    // batches (a disjoint union of graphs): graph of every vertex, nullptr
+    // for a single graph; hist then holds one hd*hd histogram per graph
+    const int *vgraph;
+    int *u_root;                   // [u_cap] root vertex of each universe (batch only)
 };
 
 
@@ -140,10 +144,19 @@ hipError_t pv_launch_edge_ids(const DevInfo &dev, int n, const int *rp, const in
                               hipStream_t s);
 hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsigned long long *hist,
                                 int hd, unsigned long long *counters, uint64_t *vout, int klo, int K,
-                                hipStream_t s);
+                                const int *vgraph, hipStream_t s);
 hipError_t pv_launch_binomials(int bn, uint64_t *tab128, uint8_t *bad, uint64_t *tab64, int *fits64,
                                hipStream_t s);
 hipError_t pv_launch_binom_pad(int bn, const uint64_t *tab128, uint64_t *pad, hipStream_t s);
 hipError_t pv_launch_finalize(const unsigned long long *hist, int hd, const uint64_t *tab128,
                               const uint8_t *bad, int bn, int kcap, int kmax, int c0,
-                              uint64_t *counts, uint64_t *ovf_words, int *omega, hipStream_t s);
+                              uint64_t *counts, uint64_t *ovf_words, int *omega, int graphs,
+                              hipStream_t s);
+// batches: concatenate graphs into one disjoint union (device descriptors)
+struct BatchPart {
+    const int *rp, *col;   // the part's own CSR (device)
+    int n, voff;           // its vertices and their offset in the union
+    long long eoff, nnz;   // its column entries and their offset in the union
+};
+hipError_t pv_launch_concat(const BatchPart *parts, int G, int maxn, int *rp, int *col, int *vgraph,
+                            hipStream_t s);

@@ -490,6 +490,24 @@ __global__ void __launch_bounds__(1024) scan_apply_kernel(int n, const int *__re
 }
 
 
+
+// ------------------------------------------------------------- batches
+// A batch of graphs is counted as their disjoint union: part b's vertices
+// are renumbered voff_b + i and its columns shifted alike (a workgroup per
+// part).  vgraph[v] names the part of union vertex v.
+__global__ void __launch_bounds__(256) concat_kernel(const BatchPart *__restrict__ parts, int G,
+                                                      int *__restrict__ rp, int *__restrict__ col,
+                                                      int *__restrict__ vgraph) {
+    for (int b = blockIdx.x; b < G; b += gridDim.x) {
+        const BatchPart pt = parts[b];
+        for (int i = threadIdx.x; i < pt.n; i += blockDim.x) {
+            rp[pt.voff + i] = pt.rp[i] + (int)pt.eoff;
+            vgraph[pt.voff + i] = b;
+        }
+        for (long long e = threadIdx.x; e < pt.nnz; e += blockDim.x) col[pt.eoff + e] = pt.col[e] + pt.voff;
+    }
+}
+
 // ------------------------------------------------------------ edge ids
 // The id of edge {u, v}, u < v, is its rank in lexicographic order: the
 // position of v among the neighbours above u, after all such entries of
@@ -657,5 +675,13 @@ hipError_t pv_launch_edge_ids(const DevInfo &dev, int n, const int *rp, const in
     scan_apply_kernel<<<nb, 1024, 0, s>>>(n, ucnt, scan_tmp, up);
     const int wblocks = grid_for((long long)n * 64, 256, dev.num_cu * 32);
     o2e_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, orow, up, o2e);
+    return hipGetLastError();
+}
+
+hipError_t pv_launch_concat(const BatchPart *parts, int G, int maxn, int *rp, int *col, int *vgraph,
+                            hipStream_t s) {
+    (void)maxn;
+    if (G <= 0) return hipSuccess;
+    concat_kernel<<<std::min(G, 65535), 256, 0, s>>>(parts, G, rp, col, vgraph);
     return hipGetLastError();
 }

@@ -42,24 +42,39 @@
 // bins); rarer leaves go straight to the device histogram.  The LDS bins
 // are added to the device histogram when the workgroup ends.
 #define PV_LDS_H 32
+//
+// A batch of graphs is counted as one disjoint union: every graph has its
+// own histogram (stride hd*hd), and a wave sets the graph of each unit it
+// takes.  The workgroup's LDS bins are not used then (a workgroup's units
+// come from many graphs); leaves go straight to the graph's histogram.
 struct GlobalSink {
     unsigned long long *bins;   // LDS [PV_LDS_H][64], shared by the workgroup
     unsigned long long *hist;   // wave-uniform copies of the arguments
+    unsigned long long *ghist;  // batch: the current graph's histogram
+    const int *vgraph;          // batch: graph of every vertex (nullptr: one graph)
     int hd;
     unsigned long long leaves;
 
     __device__ void init(const LevelArgs &a, unsigned long long *lds_bins) {
         bins = lds_bins;
         hist = (unsigned long long *)uniform64((uint64_t)a.hist);
+        vgraph = (const int *)uniform64((uint64_t)a.vgraph);
         hd = uniformi(a.hd);
+        ghist = hist;
         leaves = 0;
+    }
+
+    // batch: the unit being walked belongs to the graph of vertex v
+    __device__ __forceinline__ void set_vertex(int v) {
+        if (vgraph) ghist = hist + (long long)uniformi(vgraph[v]) * hd * hd;
     }
 
     __device__ void add_leaves(uint32_t k, int) { leaves += k; }
 
     __device__ __forceinline__ void leaf(int h, int p, int lane) {
         if (lane == 0) {
-            if (h < PV_LDS_H && p < 64) atomicAdd(&bins[h * 64 + p], 1ull);
+            if (vgraph) atomicAdd(&ghist[(long long)h * hd + p], 1ull);
+            else if (h < PV_LDS_H && p < 64) atomicAdd(&bins[h * 64 + p], 1ull);
             else atomicAdd(&hist[(long long)h * hd + p], 1ull);
         }
     }
@@ -734,6 +749,7 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
         return -1;
     }
     a.u_rows[(long long)uni * 64 + lane] = (lane < nm) ? A : 0ull;
+    if (a.vgraph && lane == 0) a.u_root[uni] = root;  // batch: names the universe's graph
     pref = make_int2(0, 0);
     if (LOCAL) {
         a.u_gid[(long long)uni * 64 + lane] = (lane < nm) ? gid : -1;
@@ -1064,6 +1080,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
                     Sw = (cnt == 64) ? ~0ull : ((1ull << cnt) - 1);
                 }
             }
+            gs.set_vertex(a.order[a.heavy_base + hu]);
             CState cs;
             if (mw_run<KL, EDGE>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs)) {
                 if (EDGE) vs.set_table(a.ueid + (long long)cs.uni * 4096);
@@ -1084,6 +1101,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
             const int u = (int)(uw & 0x7fffffffu);
             const bool fr = (uw >> 31) != 0;
             const uint64_t A = a.u_rows[(long long)u * 64 + lane];
+            if (a.vgraph) gs.set_vertex(a.u_root[u]);
             int gid = -1;
             int2 pref = make_int2(0, 0);
             if (LOCAL) {
@@ -1110,6 +1128,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
             idx = bcast0(__shfl(idx, 0, 64));
             if (idx >= n) break;
             const int v = a.order[a.light_base + idx];
+            gs.set_vertex(v);
             int d, gid;
             const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_A[wv], d, gid, etab_w);
             int uni = -1;
@@ -1191,14 +1210,21 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
 // Roots with an empty out-neighbourhood are leaves (h=1, p=0) of the SCT.
 __global__ void sct_sink_roots_kernel(int n, const int *__restrict__ order, const int *__restrict__ bounds,
                                       unsigned long long *hist, int hd, unsigned long long *counters,
-                                      uint64_t *vout, int klo, int K) {
+                                      uint64_t *vout, int klo, int K, const int *__restrict__ vgraph) {
     const int first = bounds[1];
     const int cnt = n - first;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0 && cnt > 0) {
-        atomicAdd(&hist[1 * hd + 0], (unsigned long long)cnt);
+        if (!vgraph) atomicAdd(&hist[1 * hd + 0], (unsigned long long)cnt);
         atomicAdd(&counters[0], (unsigned long long)cnt);
         atomicAdd(&counters[1], (unsigned long long)cnt);
+    }
+    if (vgraph) {
+        // batch: each sink root is a leaf of its own graph's tree
+        for (int j = i; j < cnt; j += gridDim.x * blockDim.x) {
+            const int v = order[first + j];
+            atomicAdd(&hist[(long long)vgraph[v] * hd * hd + 1 * hd + 0], 1ull);
+        }
     }
     if (vout && klo == 1) {
         for (int j = i; j < cnt; j += gridDim.x * blockDim.x) {
@@ -1265,6 +1291,12 @@ __global__ void __launch_bounds__(256) finalize_kernel(const unsigned long long 
     __shared__ uint64_t s_lo[256], s_hi[256];
     __shared__ int s_ovf[256];
     const int k = blockIdx.x;
+    // batch: graph blockIdx.y has its own histogram, counts row and flags
+    const int gb = blockIdx.y;
+    hist += (long long)gb * hd * hd;
+    counts += (long long)gb * gridDim.x * 2;
+    ovf_words += (long long)gb * ((gridDim.x + 63) / 64);
+    omega += gb;
     uint64_t lo = 0, hi = 0;
     int ovf = 0;
     for (int p = threadIdx.x; p < hd; p += blockDim.x) {
@@ -1370,8 +1402,8 @@ hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s) 
 
 hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsigned long long *hist,
                                 int hd, unsigned long long *counters, uint64_t *vout, int klo, int K,
-                                hipStream_t s) {
-    sct_sink_roots_kernel<<<256, 256, 0, s>>>(n, order, bounds, hist, hd, counters, vout, klo, K);
+                                const int *vgraph, hipStream_t s) {
+    sct_sink_roots_kernel<<<256, 256, 0, s>>>(n, order, bounds, hist, hd, counters, vout, klo, K, vgraph);
     return hipGetLastError();
 }
 
@@ -1388,8 +1420,9 @@ hipError_t pv_launch_binom_pad(int bn, const uint64_t *tab128, uint64_t *pad, hi
 
 hipError_t pv_launch_finalize(const unsigned long long *hist, int hd, const uint64_t *tab128,
                               const uint8_t *bad, int bn, int kcap, int kmax, int c0,
-                              uint64_t *counts, uint64_t *ovf_words, int *omega, hipStream_t s) {
-    finalize_kernel<<<kcap, 256, 0, s>>>(hist, hd, tab128, bad, bn, kmax, c0, counts, ovf_words,
-                                         omega);
+                              uint64_t *counts, uint64_t *ovf_words, int *omega, int graphs,
+                              hipStream_t s) {
+    finalize_kernel<<<dim3(kcap, graphs), 256, 0, s>>>(hist, hd, tab128, bad, bn, kmax, c0, counts,
+                                                      ovf_words, omega);
     return hipGetLastError();
 }

@@ -306,19 +306,30 @@ def pv_count_roots(g: int, roots, k_max: int = 0, cap: int = PV_MAX_ALPHA + 2) -
     return GlobalResult(u128_to_ints(counts), om.value, ovf, st.as_dict(), s)
 
 
-def pv_count_global_batch(ctx: int, graphs, k_max: int = 0, cap: int = 256):
+def pv_count_global_batch_raw(ctx: int, graphs, k_max: int = 0, cap: int = 256):
+    """Batched global counts, results as arrays: counts (G, cap, 2) uint64
+    limbs, omega (G,) int32, overflow words (G, (cap+63)//64) uint64, status,
+    stats."""
     G = len(graphs)
     arr = (C.c_void_p * max(G, 1))(*graphs)
-    counts = (pv_u128 * (max(G, 1) * cap))()
-    om = (C.c_int32 * max(G, 1))()
     nw = (cap + 63) // 64
-    ov = (C.c_uint64 * (max(G, 1) * nw))()
+    counts = np.zeros((max(G, 1), cap, 2), dtype=np.uint64)
+    om = np.zeros(max(G, 1), dtype=np.int32)
+    ov = np.zeros((max(G, 1), nw), dtype=np.uint64)
     st = pv_stats()
-    s = _check(_lib().pv_count_global_batch(ctx, G, arr, k_max, counts, cap, om, ov, C.byref(st)),
+    s = _check(_lib().pv_count_global_batch(ctx, G, arr, k_max,
+                                            counts.ctypes.data_as(C.POINTER(pv_u128)), cap,
+                                            om.ctypes.data_as(C.POINTER(C.c_int32)),
+                                            ov.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(st)),
                "pv_count_global_batch", allow=(PV_EOVERFLOW,))
-    flat = u128_to_ints(counts)
+    return counts[:G], om[:G], ov[:G], s, st.as_dict()
+
+
+def pv_count_global_batch(ctx: int, graphs, k_max: int = 0, cap: int = 256):
+    """Batched global counts: ([GlobalResult per graph], stats)."""
+    counts, om, ov, s, st = pv_count_global_batch_raw(ctx, graphs, k_max, cap)
     out = []
-    for i in range(G):
-        ovf = [k for k in range(cap) if (ov[i * nw + (k >> 6)] >> (k & 63)) & 1]
-        out.append(GlobalResult(flat[i * cap:(i + 1) * cap], om[i], ovf, {}, s))
-    return out, st.as_dict()
+    for i in range(len(graphs)):
+        ovf = [k for k in range(cap) if (int(ov[i, k >> 6]) >> (k & 63)) & 1]
+        out.append(GlobalResult(u128_to_ints(counts[i]), int(om[i]), ovf, {}, s))
+    return out, st

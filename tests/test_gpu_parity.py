@@ -342,3 +342,66 @@ def test_per_edge_rejects_wide_range(ctx):
         with pytest.raises(P.PivoterError) as ei:
             P.pv_count_local(h, P.PV_EDGE, 2, 10)
     assert ei.value.status == P.PV_EINVAL
+
+
+# ------------------------------------------------------------------ batches
+
+def _check_batch(ctx, graphs, kmax=0, tag=""):
+    _say(f"[parity] batch {tag}: {len(graphs)} graphs kmax={kmax}")
+    hs = [P.pv_graph_load_csr(ctx, g.n, g.row_ptr, g.col) for g in graphs]
+    try:
+        res, st = P.pv_count_global_batch(ctx, hs, k_max=kmax)
+        single = [P.pv_count_global(h, kmax) for h in hs]
+    finally:
+        for h in hs:
+            P.pv_graph_free(h)
+    leaves = 0
+    for i, g in enumerate(graphs):
+        ref = O.count(g, kmax=kmax)
+        top = len(ref.glob)
+        ovf_ref = [k for k in range(top) if ref.glob_ovf[k]]
+        assert res[i].overflow == ovf_ref, (tag, i)
+        for k in range(top):
+            if not ref.glob_ovf[k]:
+                assert res[i].counts[k] == ref.glob[k], (tag, i, k)
+        assert all(c == 0 for c in res[i].counts[top:])
+        assert res[i].omega == (min(ref.omega, kmax) if kmax else ref.omega)
+        # the batch walks the same trees as one call per graph
+        assert res[i].counts[:top] == single[i].counts[:top] and res[i].omega == single[i].omega
+        leaves += ref.stats["leaves"]
+    if not kmax:
+        assert st["leaves"] == leaves
+    return res
+
+
+MIXED = [gg.empty(0), gg.empty(5), gg.complete(1), gg.complete(10), gg.gnp(40, 0.3, 301),
+         gg.plant_cliques(gg.gnp(600, 0.04, 302), [100, 80, 70], 303), gg.moon_moser(6),
+         gg.chung_lu(2000, 12, 2.5, 200, 304), gg.star(25), gg.cycle(9), gg.complete(66)]
+
+
+def test_batch_mixed(ctx):
+    _check_batch(ctx, MIXED, tag="mixed")
+
+
+@pytest.mark.parametrize("kmax", [3, 6])
+def test_batch_truncated(ctx, kmax):
+    _check_batch(ctx, MIXED, kmax=kmax, tag="mixed truncated")
+
+
+def test_batch_overflow_flags_are_per_graph(ctx):
+    res = _check_batch(ctx, [gg.complete(20), gg.complete(133), gg.gnp(50, 0.2, 305)], tag="ovf")
+    assert res[0].overflow == [] and res[2].overflow == []
+    assert res[1].overflow
+
+
+def test_batch_workload_members(ctx):
+    # the first members of the 4096-graph batch workload
+    specs = gg.batch_graph_specs()[:48]
+    graphs = [gg.chung_lu(n, d, 2.5, n - 1, s) for (n, d, s) in specs]
+    _check_batch(ctx, graphs, tag="workload[:48]")
+
+
+def test_batch_reuses_union_buffers(ctx):
+    # a second, smaller batch on the same context after a larger one
+    _check_batch(ctx, MIXED, tag="first")
+    _check_batch(ctx, MIXED[:4], tag="second")
