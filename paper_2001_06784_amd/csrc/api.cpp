@@ -94,6 +94,48 @@ struct DBuf {
     }
 };
 
+
+// Scratch of one count call: the peel's temporaries and the SCT work
+// buffers.  A context runs one call at a time, so all its graphs share one
+// workspace (graph handles keep only the graph and its orientation).
+struct Workspace {
+    // peel / orientation temporaries
+    DBuf<int> deg, fa, fb, scan, rcnt, rcursor;
+    DBuf<int> lid, uverts, ldeg, lrp, lcol, bcnt;  // solo phase of the peel
+    DBuf<PeelCtl> ctl;
+    // SCT work buffers
+    DBuf<CItem> citem[2];
+    DBuf<uint64_t> mwitem[2];
+    DBuf<uint64_t> hu_rows, u_rows;
+    DBuf<int> hu_vl, u_gid, pref_pool;
+    DBuf<int2> u_pref;
+    DBuf<unsigned long long> hist, counters;
+    DBuf<uint64_t> counts, ovf, vout_own;
+    DBuf<int> omegas;
+    DBuf<int> u_root;  // batches: root vertex of every universe
+    // per-edge counts
+    DBuf<int> ueid, weid;
+    DBuf<uint64_t> umem, utot, escr;
+    size_t c_cap = 1 << 20, mw_cap = 1 << 15, u_cap = 1 << 16, pref_cap = 1 << 19;
+    long long hu_budget = 1ll << 30;  // bytes of heavy universes per chunk
+
+    void release() {
+        DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &rcursor, &lid, &uverts, &ldeg, &lrp, &lcol,
+                           &bcnt, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid};
+        for (auto *b : ib) b->release();
+        ctl.release();
+        citem[0].release();
+        citem[1].release();
+        mwitem[0].release();
+        mwitem[1].release();
+        DBuf<uint64_t> *ub[] = {&hu_rows, &u_rows, &counts, &ovf, &vout_own, &umem, &utot, &escr};
+        for (auto *b : ub) b->release();
+        u_pref.release();
+        hist.release();
+        counters.release();
+    }
+};
+
 struct pv_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -111,6 +153,7 @@ struct pv_ctx {
     int level_blocks[4][3] = {};  // [variant: global, vertex 8, vertex 16, edge 8][unit kind]
     int dfs_max = 64;
     int dfs_budget = 2048;
+    Workspace ws;
     // batches: the union graph (reused between calls) and its part table
     pv_graph *batch = nullptr;
     DBuf<BatchPart> parts;
@@ -128,26 +171,12 @@ struct pv_graph {
     bool oriented = false;
     int alpha = 0, subrounds = 0;
     int nheavy = 0, nnonzero = 0;
-    DBuf<int> sub, deg, fa, fb, odeg, orow, ocol, scan, small, rcnt, rcursor, order;
-    DBuf<int> lid, uverts, ldeg, lrp, lcol, bcnt;  // solo phase of the peel
-    DBuf<PeelCtl> ctl;
-    // SCT work buffers
-    DBuf<CItem> citem[2];
-    DBuf<uint64_t> mwitem[2];
-    DBuf<uint64_t> hu_rows, u_rows;
-    DBuf<int> hu_vl, u_gid, pref_pool;
-    DBuf<int2> u_pref;
-    DBuf<unsigned long long> hist, counters;
-    DBuf<uint64_t> counts, ovf, vout_own;
-    DBuf<int> omegas;
-    // batches: graph of every union vertex, root vertex of every universe
-    DBuf<int> vgraph, u_root;
-    // per-edge counts: edge ids of the oriented CSR and prefix-pair sums
+    DBuf<int> sub, odeg, orow, ocol, small, order;
+    // batches (the union graph): graph of every vertex
+    DBuf<int> vgraph;
+    // per-edge counts: edge ids of the oriented CSR
     bool eids = false;
-    DBuf<int> eup, o2e, ueid, weid;
-    DBuf<uint64_t> umem, utot, escr;
-    size_t c_cap = 1 << 20, mw_cap = 1 << 15, u_cap = 1 << 16, pref_cap = 1 << 19;
-    long long hu_budget = 1ll << 30;  // bytes of heavy universes per chunk
+    DBuf<int> eup, o2e;
     pv_stats last{};
 };
 
@@ -211,6 +240,7 @@ extern "C" void pv_fini(pv_ctx *c) {
     if (c->batch) pv_graph_free(c->batch);
     c->batch = nullptr;
     c->parts.release();
+    c->ws.release();
     c->tab.release();
     c->tab64.release();
     c->tab_pad.release();
@@ -371,34 +401,9 @@ extern "C" void pv_graph_free(pv_graph *g) {
     if (!g) return;
     (void)hipSetDevice(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
-    DBuf<int> *ib[] = {&g->rp, &g->col, &g->sub, &g->deg, &g->fa, &g->fb, &g->odeg, &g->orow,
-                       &g->ocol, &g->scan, &g->small, &g->rcnt, &g->rcursor, &g->order,
-                       &g->hu_vl, &g->u_gid, &g->pref_pool, &g->lid, &g->uverts, &g->ldeg,
-                       &g->lrp, &g->lcol, &g->bcnt};
+    DBuf<int> *ib[] = {&g->rp, &g->col, &g->sub, &g->odeg, &g->orow, &g->ocol, &g->small, &g->order,
+                       &g->vgraph, &g->eup, &g->o2e};
     for (auto *b : ib) b->release();
-    g->ctl.release();
-    g->citem[0].release();
-    g->citem[1].release();
-    g->mwitem[0].release();
-    g->mwitem[1].release();
-    g->hu_rows.release();
-    g->u_rows.release();
-    g->u_pref.release();
-    g->hist.release();
-    g->counters.release();
-    g->counts.release();
-    g->ovf.release();
-    g->vout_own.release();
-    g->omegas.release();
-    g->vgraph.release();
-    g->u_root.release();
-    g->eup.release();
-    g->o2e.release();
-    g->ueid.release();
-    g->weid.release();
-    g->umem.release();
-    g->utot.release();
-    g->escr.release();
     delete g;
 }
 
@@ -417,28 +422,28 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     HIPCHK(hipSetDevice(c->device));
     const int n = g->n;
     PVCHK(g->sub.ensure(n));
-    PVCHK(g->deg.ensure(n));
-    PVCHK(g->fa.ensure(n));
-    PVCHK(g->fb.ensure(n));
+    PVCHK(c->ws.deg.ensure(n));
+    PVCHK(c->ws.fa.ensure(n));
+    PVCHK(c->ws.fb.ensure(n));
     PVCHK(g->odeg.ensure(n));
     PVCHK(g->orow.ensure((size_t)n + 1));
     PVCHK(g->ocol.ensure((size_t)(g->nnz / 2)));
-    PVCHK(g->scan.ensure((size_t)n / 1024 + 2));
-    PVCHK(g->rcnt.ensure((size_t)n + 2));
-    PVCHK(g->rcursor.ensure((size_t)n + 2));
+    PVCHK(c->ws.scan.ensure((size_t)n / 1024 + 2));
+    PVCHK(c->ws.rcnt.ensure((size_t)n + 2));
+    PVCHK(c->ws.rcursor.ensure((size_t)n + 2));
     PVCHK(g->order.ensure(n));
-    PVCHK(g->ctl.ensure(1));
-    PVCHK(g->lid.ensure(n));
-    PVCHK(g->uverts.ensure(PV_SOLO_MAX));
-    PVCHK(g->ldeg.ensure(PV_SOLO_MAX));
-    PVCHK(g->lrp.ensure(PV_SOLO_MAX + 1));
-    PVCHK(g->lcol.ensure((size_t)std::max<long long>(g->nnz, 1)));
-    PVCHK(g->bcnt.ensure(PV_PEEL_MAX_BLOCKS));
+    PVCHK(c->ws.ctl.ensure(1));
+    PVCHK(c->ws.lid.ensure(n));
+    PVCHK(c->ws.uverts.ensure(PV_SOLO_MAX));
+    PVCHK(c->ws.ldeg.ensure(PV_SOLO_MAX));
+    PVCHK(c->ws.lrp.ensure(PV_SOLO_MAX + 1));
+    PVCHK(c->ws.lcol.ensure((size_t)std::max<long long>(g->nnz, 1)));
+    PVCHK(c->ws.bcnt.ensure(PV_PEEL_MAX_BLOCKS));
     hipStream_t s = c->stream;
     PeelCtl init;
     memset(&init, 0, sizeof init);
     init.minv[0] = init.minv[1] = 0x7fffffff;
-    HIPCHK(hipMemcpyAsync(g->ctl.p, &init, sizeof init, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(c->ws.ctl.p, &init, sizeof init, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemsetAsync(g->small.p + SM_ALPHA, 0, sizeof(int), s));
     HIPCHK(hipMemsetAsync(g->orow.p, 0, sizeof(int), s));
     if (n > 0) {
@@ -447,23 +452,23 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
         pa.n = n;
         pa.rp = g->rp.p;
         pa.col = g->col.p;
-        pa.deg = g->deg.p;
+        pa.deg = c->ws.deg.p;
         pa.sub = g->sub.p;
-        pa.fa = g->fa.p;
-        pa.fb = g->fb.p;
-        pa.ctl = g->ctl.p;
-        pa.lid = g->lid.p;
-        pa.uverts = g->uverts.p;
-        pa.ldeg = g->ldeg.p;
-        pa.lrp = g->lrp.p;
-        pa.lcol = g->lcol.p;
-        pa.bcnt = g->bcnt.p;
+        pa.fa = c->ws.fa.p;
+        pa.fb = c->ws.fb.p;
+        pa.ctl = c->ws.ctl.p;
+        pa.lid = c->ws.lid.p;
+        pa.uverts = c->ws.uverts.p;
+        pa.ldeg = c->ws.ldeg.p;
+        pa.lrp = c->ws.lrp.p;
+        pa.lcol = c->ws.lcol.p;
+        pa.bcnt = c->ws.bcnt.p;
         HIPCHK(pv_launch_peel(c->dev, pa, s));
         if (c->timing) HIPCHK(hipEventRecord(c->ev[1], s));
         HIPCHK(pv_launch_orient(c->dev, n, g->rp.p, g->col.p, g->sub.p, g->odeg.p, g->orow.p,
-                                g->ocol.p, g->small.p + SM_ALPHA, g->scan.p, s));
-        HIPCHK(hipMemsetAsync(g->rcnt.p, 0, sizeof(int) * ((size_t)n + 2), s));
-        HIPCHK(pv_launch_root_order(n, g->small.p + SM_ALPHA, g->odeg.p, g->rcnt.p, g->rcursor.p,
+                                g->ocol.p, g->small.p + SM_ALPHA, c->ws.scan.p, s));
+        HIPCHK(hipMemsetAsync(c->ws.rcnt.p, 0, sizeof(int) * ((size_t)n + 2), s));
+        HIPCHK(pv_launch_root_order(n, g->small.p + SM_ALPHA, g->odeg.p, c->ws.rcnt.p, c->ws.rcursor.p,
                                     g->order.p, g->small.p + SM_BOUNDS, PV_LIGHT_MAX, s));
         if (c->timing) HIPCHK(hipEventRecord(c->ev[2], s));
     } else {
@@ -471,7 +476,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     }
     int *io = c->h_io;
     HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(io + 32, &g->ctl.p->subrounds, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(io + 32, &c->ws.ctl.p->subrounds, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     g->alpha = io[SM_ALPHA];
     g->nheavy = io[SM_BOUNDS];
@@ -533,46 +538,46 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
 
     // heavy roots per chunk, bounded by the universe budget
     const long long hu_bytes = (long long)W * dpad * 8 + (long long)dpad * 4;
-    int chunk = (int)std::max<long long>(1, std::min<long long>(rq.nheavy, g->hu_budget / hu_bytes));
+    int chunk = (int)std::max<long long>(1, std::min<long long>(rq.nheavy, c->ws.hu_budget / hu_bytes));
     if (rq.nheavy == 0) chunk = 0;
 
     for (int attempt = 0;; attempt++) {
         if (attempt > 12) return PV_ENOMEM;
-        PVCHK(g->hist.ensure((size_t)rq.graphs * hd * hd));
-        if (rq.vgraph) PVCHK(g->u_root.ensure(g->u_cap));
-        PVCHK(g->counters.ensure(8));
+        PVCHK(c->ws.hist.ensure((size_t)rq.graphs * hd * hd));
+        if (rq.vgraph) PVCHK(c->ws.u_root.ensure(c->ws.u_cap));
+        PVCHK(c->ws.counters.ensure(8));
         for (int i = 0; i < 2; i++) {
-            PVCHK(g->citem[i].ensure(g->c_cap));
-            PVCHK(g->mwitem[i].ensure(g->mw_cap * mw_stride));
+            PVCHK(c->ws.citem[i].ensure(c->ws.c_cap));
+            PVCHK(c->ws.mwitem[i].ensure(c->ws.mw_cap * mw_stride));
         }
-        PVCHK(g->u_rows.ensure(g->u_cap * 64));
+        PVCHK(c->ws.u_rows.ensure(c->ws.u_cap * 64));
         if (local) {
-            PVCHK(g->u_gid.ensure(g->u_cap * 64));
-            PVCHK(g->u_pref.ensure(g->u_cap));
-            PVCHK(g->pref_pool.ensure(g->pref_cap));
+            PVCHK(c->ws.u_gid.ensure(c->ws.u_cap * 64));
+            PVCHK(c->ws.u_pref.ensure(c->ws.u_cap));
+            PVCHK(c->ws.pref_pool.ensure(c->ws.pref_cap));
         }
         if (rq.edge) {
-            PVCHK(g->umem.ensure(g->u_cap * 64 * 2 * rq.K * 2));
-            PVCHK(g->utot.ensure(g->u_cap * 3 * rq.K * 2));
-            PVCHK(g->ueid.ensure(g->u_cap * 4096));
-            PVCHK(g->weid.ensure((size_t)c->level_blocks[3][PV_UNITS_LIGHT] * WAVES_PER_LAUNCH_BLOCK * 4096));
+            PVCHK(c->ws.umem.ensure(c->ws.u_cap * 64 * 2 * rq.K * 2));
+            PVCHK(c->ws.utot.ensure(c->ws.u_cap * 3 * rq.K * 2));
+            PVCHK(c->ws.ueid.ensure(c->ws.u_cap * 4096));
+            PVCHK(c->ws.weid.ensure((size_t)c->level_blocks[3][PV_UNITS_LIGHT] * WAVES_PER_LAUNCH_BLOCK * 4096));
             const int eb = std::max({c->level_blocks[3][0], c->level_blocks[3][1], c->level_blocks[3][2]});
             const size_t escr_words = (size_t)eb * WAVES_PER_LAUNCH_BLOCK * 2 * 64 * 2 * rq.K * 2;
-            PVCHK(g->escr.ensure(escr_words));
-            HIPCHK(hipMemsetAsync(g->escr.p, 0, escr_words * 8, s));
+            PVCHK(c->ws.escr.ensure(escr_words));
+            HIPCHK(hipMemsetAsync(c->ws.escr.p, 0, escr_words * 8, s));
         }
         if (chunk > 0) {
-            PVCHK(g->hu_rows.ensure((size_t)chunk * W * dpad));
-            PVCHK(g->hu_vl.ensure((size_t)chunk * dpad));
+            PVCHK(c->ws.hu_rows.ensure((size_t)chunk * W * dpad));
+            PVCHK(c->ws.hu_vl.ensure((size_t)chunk * dpad));
         }
-        HIPCHK(hipMemsetAsync(g->hist.p, 0, sizeof(unsigned long long) * (size_t)rq.graphs * hd * hd, s));
-        HIPCHK(hipMemsetAsync(g->counters.p, 0, 8 * sizeof(unsigned long long), s));
+        HIPCHK(hipMemsetAsync(c->ws.hist.p, 0, sizeof(unsigned long long) * (size_t)rq.graphs * hd * hd, s));
+        HIPCHK(hipMemsetAsync(c->ws.counters.p, 0, 8 * sizeof(unsigned long long), s));
         HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, 5 * sizeof(int), s));  // flags,u_n,pref_n,omega,lovf
         const size_t lrows = rq.edge ? (size_t)(g->nnz / 2) : (size_t)g->n;
         if (local && lrows) HIPCHK(hipMemsetAsync(rq.vout, 0, lrows * rq.K * 16, s));
         if (rq.whole)
-            HIPCHK(pv_launch_sink_roots(g->n, g->order.p, g->small.p + SM_BOUNDS, g->hist.p, hd,
-                                        g->counters.p, (local && !rq.edge) ? rq.vout : nullptr,
+            HIPCHK(pv_launch_sink_roots(g->n, g->order.p, g->small.p + SM_BOUNDS, c->ws.hist.p, hd,
+                                        c->ws.counters.p, (local && !rq.edge) ? rq.vout : nullptr,
                                         rq.klo, rq.K, rq.vgraph, s));
 
         bool overflow = false;
@@ -604,31 +609,31 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.level = level;
                 a.n_mw_in = n_mw;
                 a.n_c_in = n_c;
-                a.mw_in = g->mwitem[cur].p;
-                a.c_in = g->citem[cur].p;
-                a.mw_out = g->mwitem[cur ^ 1].p;
-                a.c_out = g->citem[cur ^ 1].p;
+                a.mw_in = c->ws.mwitem[cur].p;
+                a.c_in = c->ws.citem[cur].p;
+                a.mw_out = c->ws.mwitem[cur ^ 1].p;
+                a.c_out = c->ws.citem[cur ^ 1].p;
                 a.mw_out_n = g->small.p + SM_MWN;
                 a.c_out_n = g->small.p + SM_CN;
-                a.mw_cap = (int)g->mw_cap;
-                a.c_cap = (int)g->c_cap;
+                a.mw_cap = (int)c->ws.mw_cap;
+                a.c_cap = (int)c->ws.c_cap;
                 a.mw_stride = mw_stride;
-                a.hu_rows = g->hu_rows.p;
-                a.hu_vl = g->hu_vl.p;
+                a.hu_rows = c->ws.hu_rows.p;
+                a.hu_vl = c->ws.hu_vl.p;
                 a.W = W;
                 a.dpad = dpad;
-                a.u_rows = g->u_rows.p;
-                a.u_gid = g->u_gid.p;
-                a.u_pref = g->u_pref.p;
+                a.u_rows = c->ws.u_rows.p;
+                a.u_gid = c->ws.u_gid.p;
+                a.u_pref = c->ws.u_pref.p;
                 a.u_n = g->small.p + SM_UN;
-                a.u_cap = (int)g->u_cap;
-                a.pref_pool = g->pref_pool.p;
+                a.u_cap = (int)c->ws.u_cap;
+                a.pref_pool = c->ws.pref_pool.p;
                 a.pref_n = g->small.p + SM_PREFN;
-                a.pref_cap = (int)g->pref_cap;
+                a.pref_cap = (int)c->ws.pref_cap;
                 a.next = g->small.p + SM_NEXT;
-                a.hist = g->hist.p;
+                a.hist = c->ws.hist.p;
                 a.hd = hd;
-                a.counters = g->counters.p;
+                a.counters = c->ws.counters.p;
                 a.flags = g->small.p + SM_FLAGS;
                 a.vout = rq.vout;
                 a.klo = rq.klo;
@@ -637,13 +642,13 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.lovf = g->small.p + SM_LOVF;
                 a.sub = g->sub.p;
                 a.o2e = rq.edge ? g->o2e.p : nullptr;
-                a.umem = rq.edge ? g->umem.p : nullptr;
-                a.utot = rq.edge ? g->utot.p : nullptr;
-                a.ueid = rq.edge ? g->ueid.p : nullptr;
-                a.weid = rq.edge ? g->weid.p : nullptr;
-                a.escr = rq.edge ? g->escr.p : nullptr;
+                a.umem = rq.edge ? c->ws.umem.p : nullptr;
+                a.utot = rq.edge ? c->ws.utot.p : nullptr;
+                a.ueid = rq.edge ? c->ws.ueid.p : nullptr;
+                a.weid = rq.edge ? c->ws.weid.p : nullptr;
+                a.escr = rq.edge ? c->ws.escr.p : nullptr;
                 a.vgraph = rq.vgraph;
-                a.u_root = rq.vgraph ? g->u_root.p : nullptr;
+                a.u_root = rq.vgraph ? c->ws.u_root.p : nullptr;
                 const long long units = (long long)n_mw + n_c + (level == 0 ? (long long)a.nheavy + a.nlight : 0);
                 if (units == 0) break;
                 *c->h_args = a;
@@ -679,10 +684,10 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                     auto grow = [](size_t &cap, long long demand) {
                         if ((size_t)demand >= cap) cap = std::max(cap * 2, (size_t)(demand * 5 / 4) + 1024);
                     };
-                    grow(g->c_cap, (unsigned)io[SM_CN]);
-                    grow(g->mw_cap, (unsigned)io[SM_MWN]);
-                    grow(g->u_cap, (unsigned)io[SM_UN]);
-                    grow(g->pref_cap, (unsigned)io[SM_PREFN]);
+                    grow(c->ws.c_cap, (unsigned)io[SM_CN]);
+                    grow(c->ws.mw_cap, (unsigned)io[SM_MWN]);
+                    grow(c->ws.u_cap, (unsigned)io[SM_UN]);
+                    grow(c->ws.pref_cap, (unsigned)io[SM_PREFN]);
                     break;
                 }
                 n_mw = io[SM_MWN];
@@ -728,22 +733,22 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
     const int kcap = hd;
     const int nw = (kcap + 63) / 64;
     const int G = rq.graphs;  // 1, or the parts of a batch (one histogram each)
-    PVCHK(g->counts.ensure((size_t)G * kcap * 2));
-    PVCHK(g->ovf.ensure((size_t)G * nw));
-    PVCHK(g->omegas.ensure(G));
-    HIPCHK(hipMemsetAsync(g->ovf.p, 0, (size_t)G * nw * sizeof(uint64_t), s));
-    HIPCHK(hipMemsetAsync(g->omegas.p, 0, (size_t)G * sizeof(int), s));
+    PVCHK(c->ws.counts.ensure((size_t)G * kcap * 2));
+    PVCHK(c->ws.ovf.ensure((size_t)G * nw));
+    PVCHK(c->ws.omegas.ensure(G));
+    HIPCHK(hipMemsetAsync(c->ws.ovf.p, 0, (size_t)G * nw * sizeof(uint64_t), s));
+    HIPCHK(hipMemsetAsync(c->ws.omegas.p, 0, (size_t)G * sizeof(int), s));
     if (c->timing) HIPCHK(hipEventRecord(c->ev[5], s));
-    HIPCHK(pv_launch_finalize(g->hist.p, hd, c->tab.p, c->bad.p, c->bn, kcap, rq.kmax, rq.c0,
-                              g->counts.p, g->ovf.p, g->omegas.p, G, s));
+    HIPCHK(pv_launch_finalize(c->ws.hist.p, hd, c->tab.p, c->bad.p, c->bn, kcap, rq.kmax, rq.c0,
+                              c->ws.counts.p, c->ws.ovf.p, c->ws.omegas.p, G, s));
     if (c->timing) HIPCHK(hipEventRecord(c->ev[6], s));
     std::vector<uint64_t> hc((size_t)G * kcap * 2), ho((size_t)G * nw);
     std::vector<int> hom(G);
     unsigned long long hcnt[8];
-    HIPCHK(hipMemcpyAsync(hc.data(), g->counts.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(ho.data(), g->ovf.p, ho.size() * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hom.data(), g->omegas.p, (size_t)G * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hcnt, g->counters.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hc.data(), c->ws.counts.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ho.data(), c->ws.ovf.p, ho.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hom.data(), c->ws.omegas.p, (size_t)G * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hcnt, c->ws.counters.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(c->h_io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     int omega_max = 0;
@@ -805,8 +810,8 @@ static pv_status ensure_edge_ids(pv_graph *g) {
     PVCHK(g->eup.ensure((size_t)g->n + 1));
     PVCHK(g->o2e.ensure((size_t)std::max<long long>(m, 1)));
     HIPCHK(hipMemsetAsync(g->eup.p, 0, sizeof(int), c->stream));
-    HIPCHK(pv_launch_edge_ids(c->dev, g->n, g->rp.p, g->col.p, g->sub.p, g->orow.p, g->fa.p,
-                              g->eup.p, g->o2e.p, g->scan.p, c->stream));
+    HIPCHK(pv_launch_edge_ids(c->dev, g->n, g->rp.p, g->col.p, g->sub.p, g->orow.p, c->ws.fa.p,
+                              g->eup.p, g->o2e.p, c->ws.scan.p, c->stream));
     g->eids = true;
     return PV_OK;
 }
@@ -874,12 +879,13 @@ extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int
     const long long rows = (kind == PV_EDGE) ? g->nnz / 2 : (long long)g->n;
     const long long need = rows * K;
     if (out_len < need) return PV_EBUFSIZE;
+    pv_ctx *c = g->ctx;
     PVCHK(prepare(g, false));
-    PVCHK(g->vout_own.ensure((size_t)std::max<long long>(need, 1) * 2));
+    PVCHK(c->ws.vout_own.ensure((size_t)std::max<long long>(need, 1) * 2));
     CountReq rq;
     rq.kmax = k_hi;
     PVCHK(setup_local(g, kind, k_lo, k_hi, rq));
-    rq.vout = g->vout_own.p;
+    rq.vout = c->ws.vout_own.p;
     rq.order = g->order.p;
     rq.nheavy = g->nheavy;
     rq.nlight = g->nnonzero - g->nheavy;
@@ -888,7 +894,7 @@ extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int
     pv_status st = finish_counts(g, rq, nullptr, 0, nullptr, nullptr, stats, &lovf);
     if (st != PV_OK && st != PV_EOVERFLOW) return st;
     if (need)
-        HIPCHK(hipMemcpyAsync(out, g->vout_own.p, (size_t)need * 16, hipMemcpyDeviceToHost,
+        HIPCHK(hipMemcpyAsync(out, c->ws.vout_own.p, (size_t)need * 16, hipMemcpyDeviceToHost,
                               g->ctx->stream));
     HIPCHK(hipStreamSynchronize(g->ctx->stream));
     if (overflow_bits) overflow_bits[0] = lovf;
