@@ -230,15 +230,95 @@ pv_status pv_count_roots(pv_graph *g, const int32_t *roots, int32_t nroots, int3
                          uint64_t *overflow_bits, pv_stats *stats);
 
 /*
- * Batched global counts: G graphs (all loaded on this context) in one
- * launch sequence; the subproblems of all graphs share one device work
- * queue.  counts is [G][cap] (host), omega[G] (host, may be NULL),
- * overflow_bits [G][(cap+63)/64] (may be NULL).  Per-graph status is
- * folded into the return value (first error wins).
+ * Batched counts: G graphs (loaded on this context's device) counted in one
+ * launch sequence as their disjoint union.  Root subproblems are
+ * independent (Sec. 5, parallel version) and a union's canonical peel orders
+ * each graph as it would alone, so every graph's tree and counts are those
+ * of a single call; all graphs' subproblems share the device work queues.
+ *   counts [G][cap] (host), omega [G] (host, may be NULL),
+ *   overflow_bits [G][(cap+63)/64] (host, may be NULL): as pv_count_global
+ *   per graph; PV_EBUFSIZE if some graph's omega needs more than cap.
+ *   local_kind PV_NONE or PV_VERTEX; local_out is DEVICE memory of
+ *   (sum of n) * (k_hi-k_lo+1) pv_u128, graph b's rows first at the sum of
+ *   the earlier graphs' n (zero-filled by this call).  Global counts are for
+ *   all k (k_max <= 0) or truncated at k_max.
+ * The graphs may be used again afterwards; the union is internal scratch.
  */
+pv_status pv_count_batch(pv_ctx *ctx, int32_t G, pv_graph *const *gs, int32_t k_max,
+                         pv_u128 *counts, int32_t cap, int32_t *omega, uint64_t *overflow_bits,
+                         int32_t local_kind, int32_t k_lo, int32_t k_hi, pv_u128 *local_out,
+                         uint64_t *local_ovf, pv_stats *stats);
+
+/* pv_count_batch with global counts only. */
 pv_status pv_count_global_batch(pv_ctx *ctx, int32_t G, pv_graph *const *gs, int32_t k_max,
                                 pv_u128 *counts, int32_t cap, int32_t *omega,
                                 uint64_t *overflow_bits, pv_stats *stats);
+
+/* ------------------------------------------------------------ serving
+ * A request loop (continuous batching) over graphs that stay resident on
+ * the device.  Worker threads, each with its own context and HIP stream,
+ * take all pending requests that fit one pass's HBM budget and count them in
+ * one pv_count_batch pass; requests that arrive meanwhile go to the next free
+ * worker, so passes overlap on the GPU.  Results are identical to one call
+ * per request (the union's trees are the graphs' own).
+ */
+typedef struct pv_server pv_server;
+
+typedef struct {
+    int32_t device;       /* HIP device */
+    int32_t workers;      /* worker threads (>= 1), one context and stream each */
+    int32_t max_batch;    /* most requests in one pass (>= 1) */
+    int64_t cache_bytes;  /* device bytes of resident graph CSRs kept between requests (LRU) */
+    int64_t batch_bytes;  /* device bytes one pass may use (admission); larger requests are refused */
+} pv_server_cfg;
+
+#define PV_REQ_GLOBAL 0   /* global counts C_k for all k */
+#define PV_REQ_VERTEX 1   /* global counts plus c_k(v) for k_lo <= k <= k_hi (at most 8 values) */
+
+typedef struct {
+    uint64_t graph_key;       /* names the graph; a resident graph is reused by key */
+    int32_t n;                /* host CSR (as pv_graph_load_csr): read during the request's */
+    const int32_t *row_ptr;   /* pass when the key is not resident, so it stays valid until */
+    const int32_t *col;       /* the request completes; row_ptr[n] is read at submit */
+    int32_t kind;             /* PV_REQ_GLOBAL or PV_REQ_VERTEX */
+    int32_t k_lo, k_hi;       /* PV_REQ_VERTEX only */
+    pv_u128 *counts;          /* host [cap]: counts[k] = C_k (as pv_count_global) */
+    int32_t cap;
+    pv_u128 *vertex_out;      /* host [n][k_hi-k_lo+1] (PV_REQ_VERTEX only) */
+} pv_request;
+
+typedef struct {
+    pv_status status;         /* PV_OK, PV_EBUFSIZE (cap too small), PV_EOVERFLOW, PV_ECANCELLED, ... */
+    int32_t omega;
+    uint64_t overflow;        /* overflow bits of C_0..C_63 */
+    uint64_t local_overflow;  /* nonzero if a per-vertex count reached 2^128 */
+    double queue_us;          /* submit -> start of its pass */
+    double run_us;            /* duration of its pass */
+    double total_us;          /* submit -> outputs written and the request complete */
+    int32_t batch_size;       /* requests in its pass */
+} pv_result;
+
+/* Start the workers.  PV_EINVAL on a bad configuration. */
+pv_status pv_server_start(const pv_server_cfg *cfg, pv_server **out);
+
+/* Queue a request (thread-safe).  The outputs are written before the
+ * request completes.  PV_ENOMEM if the request alone exceeds batch_bytes. */
+pv_status pv_server_submit(pv_server *s, const pv_request *req, uint64_t *ticket);
+
+/* Result of a completed request (its ticket is then retired); PV_EAGAIN if
+ * it is not complete (after timeout_us microseconds; < 0 waits forever). */
+pv_status pv_server_wait(pv_server *s, uint64_t ticket, int64_t timeout_us, pv_result *out);
+pv_status pv_server_poll(pv_server *s, uint64_t ticket, pv_result *out);
+
+/* Cancel a request that is not yet in a pass (its result reports
+ * PV_ECANCELLED); PV_EAGAIN if it already runs. */
+pv_status pv_server_cancel(pv_server *s, uint64_t ticket);
+
+/* Resident graphs, their device bytes, and requests waiting for a pass. */
+pv_status pv_server_stats(pv_server *s, int32_t *resident, int64_t *resident_bytes, int32_t *pending);
+
+/* Finish running passes, cancel queued requests, free everything. */
+void pv_server_stop(pv_server *s);
 
 #ifdef __cplusplus
 }

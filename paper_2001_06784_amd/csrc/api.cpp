@@ -963,10 +963,15 @@ extern "C" pv_status pv_graph_edge_list(pv_graph *g, int32_t *u, int32_t *v) {
     return PV_OK;
 }
 
-extern "C" pv_status pv_count_global_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, int32_t k_max,
-                                           pv_u128 *counts, int32_t cap, int32_t *omega,
-                                           uint64_t *overflow_bits, pv_stats *stats) {
+extern "C" pv_status pv_count_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, int32_t k_max,
+                                    pv_u128 *counts, int32_t cap, int32_t *omega,
+                                    uint64_t *overflow_bits, int32_t local_kind, int32_t k_lo,
+                                    int32_t k_hi, pv_u128 *local_out, uint64_t *local_ovf,
+                                    pv_stats *stats) {
     if (!c || G < 0 || (G > 0 && (!gs || !counts)) || cap < 1) return PV_EINVAL;
+    if (local_kind != PV_NONE && local_kind != PV_VERTEX) return PV_EINVAL;
+    if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
+    if (local_ovf) *local_ovf = 0;
     if (G == 0) {
         if (stats) *stats = pv_stats{};
         return PV_OK;
@@ -977,7 +982,7 @@ extern "C" pv_status pv_count_global_batch(pv_ctx *c, int32_t G, pv_graph *const
     long long N = 0, NNZ = 0;
     for (int b = 0; b < G; b++) {
         const pv_graph *g = gs[b];
-        if (!g || g->ctx != c) return PV_EINVAL;
+        if (!g || g->ctx->device != c->device) return PV_EINVAL;
         parts[b].rp = g->rp.p;
         parts[b].col = g->col.p;
         parts[b].n = g->n;
@@ -1007,11 +1012,20 @@ extern "C" pv_status pv_count_global_batch(pv_ctx *c, int32_t G, pv_graph *const
     PVCHK(prepare(u, true));
     CountReq rq;
     rq.kmax = k_max > 0 ? k_max : 0;
+    PVCHK(setup_local(u, local_kind, k_lo, k_hi, rq));
+    rq.vout = (uint64_t *)local_out;
     rq.graphs = G;
     rq.vgraph = u->vgraph.p;
     rq.order = u->order.p;
     rq.nheavy = u->nheavy;
     rq.nlight = u->nnonzero - u->nheavy;
     PVCHK(run_sct(u, rq));
-    return finish_counts(u, rq, counts, cap, omega, overflow_bits, stats, nullptr);
+    return finish_counts(u, rq, counts, cap, omega, overflow_bits, stats, local_ovf);
+}
+
+extern "C" pv_status pv_count_global_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, int32_t k_max,
+                                           pv_u128 *counts, int32_t cap, int32_t *omega,
+                                           uint64_t *overflow_bits, pv_stats *stats) {
+    return pv_count_batch(c, G, gs, k_max, counts, cap, omega, overflow_bits, PV_NONE, 0, 0, nullptr,
+                          nullptr, stats);
 }

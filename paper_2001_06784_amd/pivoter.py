@@ -42,8 +42,12 @@ ABI_FUNCTIONS = [
     "pv_last_error",
     "pv_graph_load_csr", "pv_graph_load_csr_device", "pv_graph_free", "pv_graph_size",
     "pv_graph_orient", "pv_graph_export_order", "pv_count_global", "pv_count_local",
-    "pv_graph_edge_list", "pv_count", "pv_count_roots", "pv_count_global_batch",
+    "pv_graph_edge_list", "pv_count", "pv_count_roots", "pv_count_batch", "pv_count_global_batch",
+    "pv_server_start", "pv_server_submit", "pv_server_wait", "pv_server_poll", "pv_server_cancel",
+    "pv_server_stats", "pv_server_stop",
 ]
+
+PV_REQ_GLOBAL, PV_REQ_VERTEX = 0, 1
 
 
 class pv_u128(C.Structure):
@@ -64,6 +68,25 @@ class pv_stats(C.Structure):
             v = getattr(self, f)
             d[f] = list(v) if isinstance(v, C.Array) else v
         return d
+
+
+class pv_server_cfg(C.Structure):
+    _fields_ = [("device", C.c_int32), ("workers", C.c_int32), ("max_batch", C.c_int32),
+                ("cache_bytes", C.c_int64), ("batch_bytes", C.c_int64)]
+
+
+class pv_request(C.Structure):
+    _fields_ = [("graph_key", C.c_uint64), ("n", C.c_int32),
+                ("row_ptr", C.POINTER(C.c_int32)), ("col", C.POINTER(C.c_int32)),
+                ("kind", C.c_int32), ("k_lo", C.c_int32), ("k_hi", C.c_int32),
+                ("counts", C.POINTER(pv_u128)), ("cap", C.c_int32),
+                ("vertex_out", C.POINTER(pv_u128))]
+
+
+class pv_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("omega", C.c_int32), ("overflow", C.c_uint64),
+                ("local_overflow", C.c_uint64), ("queue_us", C.c_double), ("run_us", C.c_double),
+                ("total_us", C.c_double), ("batch_size", C.c_int32)]
 
 
 class PivoterError(RuntimeError):
@@ -120,7 +143,16 @@ def _lib():
             "pv_graph_edge_list": (i32, [vp, i32p, i32p]),
             "pv_count": (i32, [vp, i32, i32, u128p, i32, i32p, u64p, i32, i32, i32, vp, u64p, sp]),
             "pv_count_roots": (i32, [vp, i32p, i32, i32, u128p, i32, i32p, u64p, sp]),
+            "pv_count_batch": (i32, [vp, i32, pvp, i32, u128p, i32, i32p, u64p, i32, i32, i32, vp,
+                                     u64p, sp]),
             "pv_count_global_batch": (i32, [vp, i32, pvp, i32, u128p, i32, i32p, u64p, sp]),
+            "pv_server_start": (i32, [C.POINTER(pv_server_cfg), pvp]),
+            "pv_server_submit": (i32, [vp, C.POINTER(pv_request), u64p]),
+            "pv_server_wait": (i32, [vp, C.c_uint64, i64, C.POINTER(pv_result)]),
+            "pv_server_poll": (i32, [vp, C.c_uint64, C.POINTER(pv_result)]),
+            "pv_server_cancel": (i32, [vp, C.c_uint64]),
+            "pv_server_stats": (i32, [vp, i32p, C.POINTER(C.c_int64), i32p]),
+            "pv_server_stop": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -333,3 +365,79 @@ def pv_count_global_batch(ctx: int, graphs, k_max: int = 0, cap: int = 256):
         ovf = [k for k in range(cap) if (int(ov[i, k >> 6]) >> (k & 63)) & 1]
         out.append(GlobalResult(u128_to_ints(counts[i]), int(om[i]), ovf, {}, s))
     return out, st
+
+
+def pv_count_batch(ctx: int, graphs, k_max: int = 0, cap: int = 256, local_kind: int = PV_NONE,
+                   k_lo: int = 0, k_hi: int = 0, local_out: int | None = None):
+    """Batched counts with optional per-vertex counts into the device buffer
+    `local_out` ((sum of n) x K u128).  Returns (counts (G, cap, 2) uint64,
+    omega, overflow words, status, local overflow word, stats)."""
+    G = len(graphs)
+    arr = (C.c_void_p * max(G, 1))(*graphs)
+    nw = (cap + 63) // 64
+    counts = np.zeros((max(G, 1), cap, 2), dtype=np.uint64)
+    om = np.zeros(max(G, 1), dtype=np.int32)
+    ov = np.zeros((max(G, 1), nw), dtype=np.uint64)
+    lov = C.c_uint64()
+    st = pv_stats()
+    s = _check(_lib().pv_count_batch(ctx, G, arr, k_max, counts.ctypes.data_as(C.POINTER(pv_u128)),
+                                     cap, om.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     ov.ctypes.data_as(C.POINTER(C.c_uint64)), local_kind, k_lo, k_hi,
+                                     local_out, C.byref(lov), C.byref(st)),
+               "pv_count_batch", allow=(PV_EOVERFLOW,))
+    return counts[:G], om[:G], ov[:G], s, lov.value, st.as_dict()
+
+
+class Server:
+    """The library's request loop (pv_server_*).  Requests keep references to
+    their CSR and output arrays until they complete."""
+
+    def __init__(self, device: int = 0, workers: int = 2, max_batch: int = 64,
+                 cache_bytes: int = 8 << 30, batch_bytes: int = 4 << 30):
+        cfg = pv_server_cfg(device, workers, max_batch, cache_bytes, batch_bytes)
+        h = C.c_void_p()
+        _check(_lib().pv_server_start(C.byref(cfg), C.byref(h)), "pv_server_start")
+        self.h = h
+        self._live = {}
+
+    def submit(self, key: int, g, kind: int = PV_REQ_GLOBAL, k_lo: int = 0, k_hi: int = 0,
+               cap: int = PV_MAX_ALPHA + 2) -> int:
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+        col = np.ascontiguousarray(g.col if len(g.col) else np.zeros(1, np.int32), dtype=np.int32)
+        counts = np.zeros((cap, 2), dtype=np.uint64)
+        vout = None
+        if kind == PV_REQ_VERTEX:
+            vout = np.zeros((max(g.n, 1), k_hi - k_lo + 1, 2), dtype=np.uint64)
+        req = pv_request(key, g.n, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                         col.ctypes.data_as(C.POINTER(C.c_int32)), kind, k_lo, k_hi,
+                         counts.ctypes.data_as(C.POINTER(pv_u128)), cap,
+                         vout.ctypes.data_as(C.POINTER(pv_u128)) if vout is not None else None)
+        t = C.c_uint64()
+        _check(_lib().pv_server_submit(self.h, C.byref(req), C.byref(t)), "pv_server_submit")
+        self._live[t.value] = (rp, col, counts, vout, g.n)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        """(status, GlobalResult-like dict, vertex counts or None, result struct)."""
+        r = pv_result()
+        s = _lib().pv_server_wait(self.h, ticket, timeout_us, C.byref(r))
+        if s == PV_EAGAIN:
+            return None
+        _check(s, "pv_server_wait")
+        rp, col, counts, vout, n = self._live.pop(ticket)
+        return r, counts, (vout[:n] if vout is not None else None)
+
+    def cancel(self, ticket: int) -> int:
+        return _lib().pv_server_cancel(self.h, ticket)
+
+    def stats(self):
+        res, by, pend = C.c_int32(), C.c_int64(), C.c_int32()
+        _check(_lib().pv_server_stats(self.h, C.byref(res), C.byref(by), C.byref(pend)), "pv_server_stats")
+        return res.value, by.value, pend.value
+
+    def stop(self):
+        if self.h:
+            _lib().pv_server_stop(self.h)
+            self.h = None
+            self._live.clear()
+

@@ -1,0 +1,167 @@
+"""Batched per-vertex counts and the serving loop (through the C ABI).
+
+Every result must be the one a single call on the graph alone gives (the
+union pass builds each graph's own tree), bit for bit, whatever else shares
+the pass.
+"""
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2001_06784_amd import graphgen as gg
+from paper_2001_06784_amd import pivoter as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _pool():
+    return [gg.empty(0), gg.complete(1), gg.complete(12), gg.gnp(60, 0.25, 401),
+            gg.plant_cliques(gg.gnp(500, 0.05, 402), [90, 20], 403), gg.moon_moser(5),
+            gg.chung_lu(3000, 14, 2.5, 300, 404), gg.star(20), gg.cycle(7),
+            gg.plant_cliques(gg.chung_lu(1500, 10, 2.5, 150, 405), [30], 406)]
+
+
+@pytest.fixture(scope="module")
+def pool():
+    return _pool()
+
+
+def test_batch_per_vertex(pool):
+    import torch
+    ctx = P.pv_init(0, torch.cuda.current_stream().cuda_stream)
+    klo, khi = 2, 7
+    K = khi - klo + 1
+    N = sum(g.n for g in pool)
+    _say(f"[serving] batch per-vertex: {len(pool)} graphs N={N}")
+    hs = [P.pv_graph_load_csr(ctx, g.n, g.row_ptr, g.col) for g in pool]
+    try:
+        dev = torch.zeros((max(N, 1), K, 2), dtype=torch.int64, device="cuda:0")
+        counts, om, ov, s, lov, st = P.pv_count_batch(ctx, hs, local_kind=P.PV_VERTEX, k_lo=klo,
+                                                      k_hi=khi, local_out=dev.data_ptr())
+        torch.cuda.synchronize()
+        out = dev.cpu().numpy().view(np.uint64)
+    finally:
+        for h in hs:
+            P.pv_graph_free(h)
+        P.pv_fini(ctx)
+    assert lov == 0
+    off = 0
+    for i, g in enumerate(pool):
+        ref = O.count(g, vertex=(klo, khi))
+        assert P.u128_to_ints(counts[i])[:len(ref.glob)] == ref.glob, i
+        assert np.array_equal(out[off:off + g.n], ref.vertex), i
+        off += g.n
+
+
+def _alone(ctx, g, kind, klo, khi):
+    h = P.pv_graph_load_csr(ctx, g.n, g.row_ptr, g.col)
+    try:
+        r = P.pv_count_global(h)
+        v = P.pv_count_local(h, P.PV_VERTEX, klo, khi)[0] if kind == P.PV_REQ_VERTEX else None
+    finally:
+        P.pv_graph_free(h)
+    return r, v
+
+
+def test_server_results_equal_single_calls(pool):
+    ctx = P.pv_init(0)
+    rng = np.random.default_rng(407)
+    plan = []
+    for i in range(60):
+        j = int(rng.integers(len(pool)))
+        kind = P.PV_REQ_VERTEX if rng.random() < 0.5 else P.PV_REQ_GLOBAL
+        klo = int(rng.integers(1, 4))
+        khi = klo + int(rng.integers(0, 6))
+        plan.append((j, kind, klo, khi))
+    alone = {}
+    for (j, kind, klo, khi) in plan:
+        if (j, kind, klo, khi) not in alone:
+            alone[(j, kind, klo, khi)] = _alone(ctx, pool[j], kind, klo, khi)
+    P.pv_fini(ctx)
+    srv = P.Server(workers=2, max_batch=8)
+    tickets = [None] * len(plan)
+    try:
+        def submit(part):
+            for i in part:
+                j, kind, klo, khi = plan[i]
+                tickets[i] = srv.submit(1000 + j, pool[j], kind, klo, khi)
+        ts = [threading.Thread(target=submit, args=(range(k, len(plan), 3),)) for k in range(3)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        sizes = []
+        for i, (j, kind, klo, khi) in enumerate(plan):
+            r, counts, vout = srv.wait(tickets[i])
+            assert r.status == P.PV_OK, (i, r.status)
+            sizes.append(r.batch_size)
+            ref, vref = alone[(j, kind, klo, khi)]
+            got = P.u128_to_ints(counts)
+            assert got[: ref.omega + 1] == ref.counts[: ref.omega + 1], i
+            assert all(x == 0 for x in got[ref.omega + 1:])
+            assert r.omega == ref.omega
+            if kind == P.PV_REQ_VERTEX:
+                assert np.array_equal(vout, vref), i
+        resident, nbytes, pending = srv.stats()
+        _say(f"[serving] 60 requests: batch sizes {sorted(set(sizes))}, resident {resident}")
+        assert pending == 0 and resident <= len(pool)
+    finally:
+        srv.stop()
+
+
+def test_server_small_cache_evicts_and_stays_exact(pool):
+    graphs = [gg.chung_lu(800 + 50 * i, 12, 2.5, 100, 410 + i) for i in range(8)]
+    ctx = P.pv_init(0)
+    ref = [_alone(ctx, g, P.PV_REQ_GLOBAL, 0, 0)[0] for g in graphs]
+    P.pv_fini(ctx)
+    one = 4 * (graphs[0].n + 1) + 8 * graphs[0].m
+    srv = P.Server(workers=1, max_batch=3, cache_bytes=2 * one)
+    try:
+        ts = [srv.submit(i % 8, graphs[i % 8]) for i in range(24)]
+        for i, t in enumerate(ts):
+            r, counts, _ = srv.wait(t)
+            assert r.status == P.PV_OK
+            assert P.u128_to_ints(counts)[: ref[i % 8].omega + 1] == ref[i % 8].counts[: ref[i % 8].omega + 1]
+        resident, nbytes, pending = srv.stats()
+        assert nbytes <= 2 * one + 8 * (graphs[-1].m + graphs[-1].n + 1)
+    finally:
+        srv.stop()
+
+
+def test_server_admission_and_errors(pool):
+    g = pool[6]
+    srv = P.Server(workers=1, max_batch=4, batch_bytes=1 << 16)
+    try:
+        with pytest.raises(P.PivoterError) as ei:
+            srv.submit(1, g)  # needs more than one pass may hold
+        assert ei.value.status == P.PV_ENOMEM
+        t = srv.submit(2, pool[2], cap=5)  # K12 has omega 12 > cap
+        r, counts, _ = srv.wait(t)
+        assert r.status == P.PV_EBUFSIZE and r.omega == 12
+    finally:
+        srv.stop()
+
+
+def test_server_cancel(pool):
+    srv = P.Server(workers=1, max_batch=1)
+    try:
+        big = gg.chung_lu(20000, 16, 2.3, 1500, 420)
+        ts = [srv.submit(7, big) for _ in range(6)]
+        outcome = [srv.cancel(t) for t in ts]
+        for t, c in zip(ts, outcome):
+            r, counts, _ = srv.wait(t)
+            if c == P.PV_OK:
+                assert r.status == P.PV_ECANCELLED
+            else:
+                assert c == P.PV_EAGAIN and r.status == P.PV_OK
+        assert any(c == P.PV_OK for c in outcome)
+    finally:
+        srv.stop()
