@@ -9,7 +9,18 @@ global counts for every k, and per-vertex counts for k = 3..10, all in one
 pv_count call.
 
 Prints one JSON line.  value = undirected edges / second of wall time per
-step; leaves_per_s = SCT leaves / second.  The roofline object describes the
+step; leaves_per_s = SCT leaves / second.
+
+Two more workloads are selected with --workload:
+  batch  4096 small Chung-Lu graphs (n log-uniform in [50, 5000], average
+         degree uniform in [8, 40], exponent 2.5), global counts for all k:
+         one batched union pass against one call per graph (graphs/s).
+  serve  an open-loop Poisson stream (200 requests/s) over a pool of 256
+         Chung-Lu graphs (edge counts log-uniform in [1e3, 2e6], exponent
+         2.5); graph per request Zipf(1.1) over the pool, type 50/50 global
+         all-k / global + per-vertex k=3..8.  The library's serving loop with
+         batching against the same loop taking one request per pass;
+         latency from the scheduled arrival to the result in host memory.  The roofline object describes the
 dominant kernel (the SCT level kernel): integer ALU work, measured with HIP
 events on the library's stream.  The cpu_baseline object times the CPU
 oracle (single thread) on a uniform random sample of root subproblems and
@@ -72,11 +83,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-fraction", type=float, default=0.03)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["social", "batch", "serve"], default="social")
+    ap.add_argument("--duration", type=float, default=20.0, help="serve: measured seconds")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
               "described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import torch
     from paper_2001_06784_amd import pivoter as P
@@ -169,6 +187,138 @@ def main():
         line["cpu_baseline"] = cpu_baseline(g, args.cpu_fraction, seed=7)
     P.pv_graph_free(h)
     P.pv_fini(ctx)
+    print(json.dumps(line), flush=True)
+
+
+def bench_batch(args):
+    import torch
+    from paper_2001_06784_amd import graphgen as gg
+    from paper_2001_06784_amd import pivoter as P
+    t0 = time.perf_counter()
+    graphs = gg.batch_graphs()
+    print(f"[bench] {len(graphs)} graphs generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    ctx = P.pv_init(0, torch.cuda.current_stream().cuda_stream)
+    hs = [P.pv_graph_load_csr(ctx, g.n, g.row_ptr, g.col) for g in graphs]
+    m_total = sum(g.m for g in graphs)
+    for _ in range(args.warmup):
+        P.pv_count_global_batch_raw(ctx, hs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        counts, om, ov, s, st = P.pv_count_global_batch_raw(ctx, hs)
+    dt = (time.perf_counter() - t0) / args.steps
+    # the plain path: one pv_count_global call per graph, same GPU
+    lat = []
+    t1 = time.perf_counter()
+    for h in hs:
+        t2 = time.perf_counter()
+        P.pv_count_global(h)
+        lat.append(time.perf_counter() - t2)
+    dt_plain = time.perf_counter() - t1
+    for h in hs:
+        P.pv_graph_free(h)
+    P.pv_fini(ctx)
+    line = {
+        "metric": "graphs/sec, batched global all-k counts", "value": len(hs) / dt, "unit": "graphs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u128",
+        "data": "synthetic",
+        "config": {"workload": "4096 Chung-Lu graphs, n log-uniform [50,5000], avg deg U[8,40], "
+                               "gamma 2.5, seeds 1000+i; global counts all k",
+                   "graphs": len(hs), "m_total": m_total, "sct_leaves": st["leaves"]},
+        "edges_per_s": m_total / dt,
+        "plain": {"graphs_per_s": len(hs) / dt_plain, "s": dt_plain,
+                  "p50_ms_per_graph": 1e3 * float(np.percentile(lat, 50)),
+                  "p99_ms_per_graph": 1e3 * float(np.percentile(lat, 99))},
+        "batched_over_plain": (len(hs) / dt) / (len(hs) / dt_plain),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _serve_trace(duration: float, warm: float, rate: float = 200.0):
+    from paper_2001_06784_amd import graphgen as gg
+    specs = gg.serve_pool_specs()
+    t0 = time.perf_counter()
+    pool = [gg.chung_lu(n, d, 2.5, n - 1, s) for (n, d, s) in specs]
+    print(f"[bench] serving pool of {len(pool)} graphs (sum m {sum(g.m for g in pool)}) in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    arr = gg.poisson_arrivals(rate, warm + duration, seed=3)
+    rng = np.random.default_rng(4)
+    ranks = np.arange(1, len(pool) + 1, dtype=np.float64)
+    pz = ranks ** -1.1
+    pz /= pz.sum()
+    perm = rng.permutation(len(pool))
+    which = perm[rng.choice(len(pool), size=len(arr), p=pz)]
+    kinds = rng.random(len(arr)) < 0.5
+    return pool, arr, which, kinds
+
+
+def _run_trace(P, pool, arr, which, kinds, warm, workers, max_batch):
+    import threading
+    srv = P.Server(workers=workers, max_batch=max_batch, cache_bytes=16 << 30, batch_bytes=8 << 30)
+    out = [None] * len(arr)
+    sub = []
+    done = threading.Event()
+
+    def waiter():
+        i = 0
+        while i < len(arr):
+            while i >= len(sub):
+                time.sleep(0.0005)
+            tk, t_sched, t_sub = sub[i]
+            r, counts, v = srv.wait(tk)
+            out[i] = (t_sched, (t_sub - t_sched) + r.total_us * 1e-6, r.status, r.batch_size)
+            i += 1
+        done.set()
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t_start = time.perf_counter()
+    for i, t in enumerate(arr):
+        now = time.perf_counter() - t_start
+        if t > now:
+            time.sleep(t - now)
+        g = pool[which[i]]
+        kind = P.PV_REQ_VERTEX if kinds[i] else P.PV_REQ_GLOBAL
+        tk = srv.submit(int(which[i]), g, kind, 3, 8)
+        sub.append((tk, float(t), time.perf_counter() - t_start))
+    th.join()
+    t_end = time.perf_counter() - t_start
+    srv.stop()
+    meas = [o for o in out if o[0] >= warm]
+    lat = np.array([o[1] for o in meas])
+    ok = all(o[2] == P.PV_OK for o in out)
+    m_meas = sum(pool[which[i]].m for i in range(len(arr)) if arr[i] >= warm)
+    span = max(t_end, arr[-1]) - warm
+    return {"requests": len(meas), "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_ms": 1e3 * float(np.percentile(lat, 99)), "mean_ms": 1e3 * float(lat.mean()),
+            "graphs_per_s": len(meas) / span, "edges_per_s": m_meas / span, "all_ok": ok,
+            "mean_batch": float(np.mean([o[3] for o in meas])), "workers": workers,
+            "max_batch": max_batch, "finished_s_after_last_arrival": t_end - float(arr[-1])}
+
+
+def bench_serve(args):
+    from paper_2001_06784_amd import pivoter as P
+    warm = 5.0
+    pool, arr, which, kinds = _serve_trace(args.duration, warm)
+    P.load_library()
+    served = _run_trace(P, pool, arr, which, kinds, warm, workers=2, max_batch=64)
+    print(f"[bench] served: {served}", file=sys.stderr, flush=True)
+    plain = _run_trace(P, pool, arr, which, kinds, warm, workers=1, max_batch=1)
+    print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "p50/p99 request latency (ms) and graphs/sec under a 200 req/s Poisson stream",
+        "value": served["p99_ms"], "unit": "ms (p99)", "n_gpus": 1, "steps": len(arr),
+        "warmup": int(np.sum(arr < warm)), "ms_per_step": served["mean_ms"],
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u128",
+        "data": "synthetic",
+        "config": {"workload": "Poisson 200/s over 256 Chung-Lu graphs, m log-uniform [1e3,2e6], "
+                               "avg deg U[8,40], gamma 2.5, Zipf(1.1) reuse, 50/50 global all-k / "
+                               "global + per-vertex k=3..8", "measured_s": args.duration,
+                   "warmup_s": warm},
+        "served": served, "plain_one_request_per_pass": plain,
+    }
     print(json.dumps(line), flush=True)
 
 
