@@ -556,6 +556,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             PVCHK(c->ws.u_pref.ensure(c->ws.u_cap));
             PVCHK(c->ws.pref_pool.ensure(c->ws.pref_cap));
         }
+        if (local && !rq.edge) PVCHK(c->ws.utot.ensure(c->ws.u_cap * 2 * rq.K * 2));
         if (rq.edge) {
             PVCHK(c->ws.umem.ensure(c->ws.u_cap * 64 * 2 * rq.K * 2));
             PVCHK(c->ws.utot.ensure(c->ws.u_cap * 3 * rq.K * 2));
@@ -643,7 +644,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.sub = g->sub.p;
                 a.o2e = rq.edge ? g->o2e.p : nullptr;
                 a.umem = rq.edge ? c->ws.umem.p : nullptr;
-                a.utot = rq.edge ? c->ws.utot.p : nullptr;
+                a.utot = local ? c->ws.utot.p : nullptr;
                 a.ueid = rq.edge ? c->ws.ueid.p : nullptr;
                 a.weid = rq.edge ? c->ws.weid.p : nullptr;
                 a.escr = rq.edge ? c->ws.escr.p : nullptr;
@@ -697,13 +698,15 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             }
         }
         if (overflow) continue;
-        if (rq.edge) {
-            // pairs with vertices above the universes; the device copy of the
-            // launch arguments still holds the last level's (the universe
-            // buffers and outputs are the same for every level)
+        if (local) {
+            // what the universes' walks owe the vertices above them; the
+            // device copy of the launch arguments still holds the last
+            // level's (the universe buffers and outputs are the same for
+            // every level)
             const int blocks = std::max(1, std::min(c->dev.num_cu * 16, (int)((io[SM_UN] + 3) / 4)));
             if (io_fresh) {  // no level ran: no universe, nothing to add
-                HIPCHK(pv_launch_edge_prefix(c->d_args.p, blocks, s));
+                if (rq.edge) HIPCHK(pv_launch_edge_prefix(c->d_args.p, blocks, s));
+                else HIPCHK(pv_launch_vertex_prefix(c->d_args.p, blocks, s));
                 HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
             }

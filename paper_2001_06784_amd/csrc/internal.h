@@ -108,7 +108,8 @@ struct LevelArgs {
     const int *sub;                // peel sub-round of every vertex (the orientation key)
     const int *o2e;                // [m] oriented CSR position -> edge id
     uint64_t *umem;                // [u_cap][64][2][K] u128: member sums toward H / P prefix
-    uint64_t *utot;                // [u_cap][3][K] u128: HH, HP, PP sums
+    uint64_t *utot;                // per edge [u_cap][3][K] u128: HH, HP, PP sums; per vertex
+                                   // [u_cap][2][K]: totals owed to hold / pivot prefix vertices
     int *ueid;                     // [u_cap][64][64] edge id of each member pair of a universe
     int *weid;                     // [waves of a light-root launch][64][64] the same per wave
     uint64_t *escr;                // [waves of a launch][2][64][2][K] u128: join snapshots and
@@ -138,6 +139,7 @@ hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *cn
 hipError_t pv_launch_level(const LevelArgs *a, int kl, bool edge, int mode, int blocks, hipStream_t s);
 int pv_level_blocks_per_cu(int kl, bool edge, int mode);
 hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s);
+hipError_t pv_launch_vertex_prefix(const LevelArgs *a, int blocks, hipStream_t s);
 // per-edge ids: o2e[q] = lexicographic id of the edge at oriented position q
 hipError_t pv_launch_edge_ids(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
                               const int *orow, int *ucnt, int *up, int *o2e, int *scan_tmp,

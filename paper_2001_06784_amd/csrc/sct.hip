@@ -88,6 +88,15 @@ __device__ __forceinline__ uint64_t ldc64(const uint64_t *p) {
     return *(const __attribute__((address_space(4))) uint64_t *)(uintptr_t)p;
 }
 
+// Eight consecutive table entries in one scalar load (s_load_dwordx16; the
+// scalar unit needs only dword alignment).  Callers keep p + 8 inside the
+// table: every row segment read here is followed by at least one more row.
+typedef uint64_t u64x8 __attribute__((ext_vector_type(8)));
+typedef u64x8 u64x8_a8 __attribute__((aligned(8)));
+__device__ __forceinline__ u64x8 ldc64x8(const uint64_t *p) {
+    return *(const __attribute__((address_space(4))) u64x8_a8 *)(uintptr_t)p;
+}
+
 // Per-vertex counts (Alg. 2 steps ht and pt).  Lane j < 62 accumulates the
 // contributions of universe member j for k = klo..klo+K-1 (members sit on
 // lanes 0..61: compact universes hold at most PV_LIGHT_MAX = 62 vertices).
@@ -104,6 +113,7 @@ struct VertexSink {
     // wave-uniform copies of the arguments
     const uint64_t *tab;
     uint64_t *vout;
+    uint64_t *utot;  // [u_cap][2][K]: what the hold / pivot vertices above a universe are owed
     const int *pool;
     int *lovf;
     int klo, K, khi;
@@ -111,6 +121,7 @@ struct VertexSink {
     __device__ void init(const LevelArgs &a, uint64_t *) {
         tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
         vout = (uint64_t *)uniform64((uint64_t)a.vout);
+        utot = (uint64_t *)uniform64((uint64_t)a.utot);
         pool = (const int *)uniform64((uint64_t)a.pref_pool);
         lovf = (int *)uniform64((uint64_t)a.lovf);
         klo = uniformi(a.klo);
@@ -141,20 +152,34 @@ struct VertexSink {
         const bool inP = ((P >> lane) & 1) || lane == 63;
         const uint64_t *rowH = tab + (p + 1) * 32 + (klo - h + 16);  // C(p, k-h)
         const uint64_t *rowP = tab + p * 32 + (klo - h + 15);        // C(p-1, k-h-1)
+        constexpr int NC = KL > 0 ? (KL + 7) / 8 : 1;
+        u64x8 vH[NC], vP[NC];
+#pragma unroll
+        for (int c = 0; c < (KL + 7) / 8; c++) {
+            vH[c] = ldc64x8(rowH + 8 * c);
+            vP[c] = ldc64x8(rowP + 8 * c);
+        }
+        // every slot accumulates (slots >= K read in-table entries and are
+        // never flushed), so no per-slot guard; a lane takes the hold or the
+        // pivot binomial through masks
+        uint64_t mH = inH ? ~0ull : 0ull;
+        uint64_t mP = (!inH && inP) ? ~0ull : 0ull;
+        // keep the masks as opaque vector values: the AND/OR form then takes
+        // the scalar binomials as direct operands (no per-slot moves/selects)
+        asm volatile("" : "+v"(mH), "+v"(mP));
 #pragma unroll
         for (int kk = 0; kk < KL; kk++) {
-            if (kk < K) {
-                const uint64_t bH = ldc64(rowH + kk), bP = ldc64(rowP + kk);
-                const uint64_t v = inH ? bH : (inP ? bP : 0ull);
-                lo[kk] += v;
-                hi[kk] += (lo[kk] < v) ? 1ull : 0ull;
-            }
+            const uint64_t v = (vH[kk / 8][kk % 8] & mH) | (vP[kk / 8][kk % 8] & mP);
+            lo[kk] += v;
+            hi[kk] += (lo[kk] < v) ? 1ull : 0ull;
         }
     }
 
-    // members: lane j < nm owns vertex gid; prefix: `root` (a hold vertex,
-    // or -1) plus pool[pref.x .. pref.x + pref.y)
-    __device__ void flush(int lane, int nm, int gid, int root, int2 pref, int, const LevelArgs &) {
+    // members: lane j < nm owns vertex gid; above the universe: `root` (a
+    // light root walked without a universe in memory, a hold vertex) or, with
+    // a universe, the totals go to its accumulators (a final kernel adds them
+    // to every vertex of its prefix once)
+    __device__ void flush(int lane, int nm, int gid, int root, int2, int uni, const LevelArgs &) {
         bool ovf = false;
         if (lane < nm) {
 #pragma unroll
@@ -163,10 +188,8 @@ struct VertexSink {
                     ovf |= atomic_add_u128(vout + 2 * ((long long)gid * K + kk), lo[kk], hi[kk]);
         }
         root = uniformi(root);
-        pref.x = uniformi(pref.x);
-        pref.y = uniformi(pref.y);
-        const int npref = pref.y + (root >= 0 ? 1 : 0);
-        if (npref > 0) {
+        uni = uniformi(uni);
+        if (root >= 0 || uni >= 0) {
             // lane kk < K takes the owed totals for k = klo + kk from lanes 62/63
             uint64_t thl = 0, thh = 0, tpl = 0, tph = 0;
 #pragma unroll
@@ -182,22 +205,14 @@ struct VertexSink {
                     }
                 }
             }
-            for (int i = 0; i < npref; i++) {
-                int x;
-                bool isP;
-                if (root >= 0 && i == 0) {
-                    x = root;
-                    isP = false;
+            if (lane < K) {
+                if (root >= 0) {
+                    if (thl | thh) ovf |= atomic_add_u128(vout + 2 * ((long long)root * K + lane), thl, thh);
                 } else {
-                    // a plain load: the multi-word tier writes pool entries in
-                    // the same launch, and the scalar cache would not see them
-                    const int e = pool[pref.x + i - (root >= 0 ? 1 : 0)];
-                    x = e & 0x7fffffff;
-                    isP = (e >> 31) & 1;
+                    uint64_t *ut = utot + 2 * ((long long)uni * 2 * K + lane);
+                    if (thl | thh) ovf |= atomic_add_u128(ut, thl, thh);
+                    if (tpl | tph) ovf |= atomic_add_u128(ut + 2 * K, tpl, tph);
                 }
-                const uint64_t l = isP ? tpl : thl, hh = isP ? tph : thh;
-                if (lane < K && (l | hh))
-                    ovf |= atomic_add_u128(vout + 2 * ((long long)x * K + lane), l, hh);
             }
         }
         if (ovf) atomicOr(lovf, 1);
@@ -353,12 +368,13 @@ struct EdgeSink {
         const uint64_t *rowHH = tab + (p + 1) * 32 + (klo - h + 16);
         const uint64_t *rowHP = tab + p * 32 + (klo - h + 15);
         const uint64_t *rowPP = tab + max(p - 1, 0) * 32 + (klo - h + 14);
+        const u64x8 xHH = ldc64x8(rowHH), xHP = ldc64x8(rowHP), xPP = ldc64x8(rowPP);
 #pragma unroll
         for (int kk = 0; kk < KL; kk++) {
             if (kk < K) {
-                add_at(t0l, t0h, ldc64(rowHH + kk), kk, lane);
-                add_at(t1l, t1h, ldc64(rowHP + kk), kk, lane);
-                add_at(t2l, t2h, ldc64(rowPP + kk), kk, lane);
+                add_at(t0l, t0h, xHH[kk], kk, lane);
+                add_at(t1l, t1h, xHP[kk], kk, lane);
+                add_at(t2l, t2h, xPP[kk], kk, lane);
             }
         }
     }
@@ -776,6 +792,12 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
             }
             pref = make_int2(off, tot);
             if (lane == 0) a.u_pref[uni] = pref;
+        }
+        if (!EDGE && lane < a.K) {
+            // per-vertex: the universe's totals owed to its prefix, hold and pivot
+            uint64_t *ut = a.utot + 2 * ((long long)uni * 2 * a.K + lane);
+            ut[0] = ut[1] = 0ull;
+            ut[2 * a.K] = ut[2 * a.K + 1] = 0ull;
         }
         if (EDGE) {
             const int K = a.K;
@@ -1207,6 +1229,32 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
     if (ovf) atomicOr(a.lovf, 1);
 }
 
+// Per-vertex counts: what each universe's walks owe the vertices above it
+// (its prefix: hold or pivot), added once per universe after the last level.
+__global__ void __launch_bounds__(256) vertex_prefix_kernel(const LevelArgs *__restrict__ pa) {
+    const LevelArgs &a = *pa;
+    const int lane = threadIdx.x & 63;
+    const int nu = min(*a.u_n, a.u_cap);
+    const int K = a.K;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    bool ovf = false;
+    for (int u = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < nu; u += nwaves) {
+        const int2 pref = a.u_pref[u];
+        const uint64_t *tot = a.utot + 2 * ((long long)u * 2 * K);
+        if (lane >= K) continue;
+        const uint64_t hl = tot[2 * lane], hh = tot[2 * lane + 1];
+        const uint64_t pl = tot[2 * (K + lane)], ph = tot[2 * (K + lane) + 1];
+        for (int i = 0; i < pref.y; i++) {
+            const int e = a.pref_pool[pref.x + i];
+            const int x = e & 0x7fffffff;
+            const bool isP = (e >> 31) & 1;
+            const uint64_t l = isP ? pl : hl, h = isP ? ph : hh;
+            if (l | h) ovf |= atomic_add_u128(a.vout + 2 * ((long long)x * K + lane), l, h);
+        }
+    }
+    if (ovf) atomicOr(a.lovf, 1);
+}
+
 // Roots with an empty out-neighbourhood are leaves (h=1, p=0) of the SCT.
 __global__ void sct_sink_roots_kernel(int n, const int *__restrict__ order, const int *__restrict__ bounds,
                                       unsigned long long *hist, int hd, unsigned long long *counters,
@@ -1397,6 +1445,11 @@ int pv_level_blocks_per_cu(int kl, bool edge, int mode) {
 
 hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s) {
     edge_prefix_kernel<<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t pv_launch_vertex_prefix(const LevelArgs *a, int blocks, hipStream_t s) {
+    vertex_prefix_kernel<<<blocks, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
