@@ -47,8 +47,10 @@
 // own histogram (stride hd*hd), and a wave sets the graph of each unit it
 // takes.  The workgroup's LDS bins are not used then (a workgroup's units
 // come from many graphs); leaves go straight to the graph's histogram.
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+
 struct GlobalSink {
-    unsigned long long *bins;   // LDS [PV_LDS_H][64], shared by the workgroup
+    lds_u64 *bins;              // LDS [PV_LDS_H][64], shared by the workgroup
     unsigned long long *hist;   // wave-uniform copies of the arguments
     unsigned long long *ghist;  // batch: the current graph's histogram
     const int *vgraph;          // batch: graph of every vertex (nullptr: one graph)
@@ -56,7 +58,8 @@ struct GlobalSink {
     unsigned long long leaves;
 
     __device__ void init(const LevelArgs &a, unsigned long long *lds_bins) {
-        bins = lds_bins;
+        // an LDS-typed pointer: the bin update is a ds_add, not a flat atomic
+        bins = (lds_u64 *)lds_bins;
         hist = (unsigned long long *)uniform64((uint64_t)a.hist);
         vgraph = (const int *)uniform64((uint64_t)a.vgraph);
         hd = uniformi(a.hd);
@@ -72,10 +75,13 @@ struct GlobalSink {
     __device__ void add_leaves(uint32_t k, int) { leaves += k; }
 
     __device__ __forceinline__ void leaf(int h, int p, int lane) {
-        if (lane == 0) {
-            if (vgraph) atomicAdd(&ghist[(long long)h * hd + p], 1ull);
-            else if (h < PV_LDS_H && p < 64) atomicAdd(&bins[h * 64 + p], 1ull);
-            else atomicAdd(&hist[(long long)h * hd + p], 1ull);
+        if (vgraph) {
+            if (lane == 0) atomicAdd(&ghist[(long long)h * hd + p], 1ull);
+        } else if (h < PV_LDS_H && p < 64) {
+            if (lane == 0)
+                __hip_atomic_fetch_add(&bins[h * 64 + p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else if (lane == 0) {
+            atomicAdd(&hist[(long long)h * hd + p], 1ull);
         }
     }
 };
@@ -524,6 +530,8 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     // nodes and adds at most 2080 work per node, so 32 bits suffice
     uint32_t nodes = 0, work = 0, nleaves = 0;
     const int kmax = uniformi(a.kmax);
+    // a hold child (h + 1 holds) exists only while h < hlim
+    const int hlim = kmax > 0 ? kmax : 0x7fffffff;
     const uint32_t limit = (uint32_t)uniformi(a.dfs_budget);
     bool visit = true;
     if (uniformi(from_frame ? 1 : 0)) {
@@ -540,41 +548,6 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     }
     for (;;) {
         if (visit) {
-            if (nodes >= limit && depth > 0) {
-                // ---- split: the pending node and every stack frame become items
-                if (uni < 0) {
-                    int2 pref;
-                    uni = make_universe<KL, EDGE>(A, nm, gid, lane, a, root, 0ull, 0ull, nullptr, 0, pref,
-                                                  EDGE ? vs.etab_ptr() : nullptr);
-                    if (uni < 0) break;  // buffers full: the host reruns with larger ones
-                }
-                const int total = depth + 1;
-                int slot = 0;
-                if (lane == 0) slot = atomicAdd(a.c_out_n, total);
-                slot = bcast0(slot);
-                if (slot + total > a.c_cap) {
-                    if (lane == 0) atomicOr(a.flags, 1);
-                    break;
-                }
-                CItem it;
-                if (lane == 0) {
-                    it.S = S;
-                    it.H = H;
-                    it.P = P;
-                    it.uni = (uint32_t)uni;
-                    it.hp = (uint32_t)h | ((uint32_t)p << 16);
-                    a.c_out[slot] = it;
-                }
-                if (lane < depth) {  // lane t holds frame t
-                    it.S = stS;
-                    it.H = LOCAL ? stH : 0ull;
-                    it.P = LOCAL ? stP : 0ull;
-                    it.uni = (uint32_t)uni | 0x80000000u;
-                    it.hp = stM;
-                    a.c_out[slot + 1 + lane] = it;
-                }
-                break;
-            }
             nodes++;
             if (S != 0) {
                 const int s = __popcll(S);
@@ -608,7 +581,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                     }
                 } else {
                     const uint64_t Ap = readlane64(A, piv);
-                    if (!(kmax > 0 && h + 1 > kmax)) {
+                    if (h < hlim) {
                         stS = writelane64(stS, S, depth);
                         if (LOCAL) {
                             stH = writelane64(stH, H, depth);
@@ -653,6 +626,43 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
             vs.join(v, Ht, Pt, false, lane);
             H = Ht | vbit;
             P = Pt;
+        }
+        // budget spent: the pending hold child and every stack frame become
+        // items of the next level (checked where a walk resumes a frame, so a
+        // call visits at most dfs_budget plus one pivot chain)
+        if (nodes >= limit && depth > 0) {
+            if (uni < 0) {
+                int2 pref;
+                uni = make_universe<KL, EDGE>(A, nm, gid, lane, a, root, 0ull, 0ull, nullptr, 0, pref,
+                                              EDGE ? vs.etab_ptr() : nullptr);
+                if (uni < 0) break;  // buffers full: the host reruns with larger ones
+            }
+            const int total = depth + 1;
+            int slot = 0;
+            if (lane == 0) slot = atomicAdd(a.c_out_n, total);
+            slot = bcast0(slot);
+            if (slot + total > a.c_cap) {
+                if (lane == 0) atomicOr(a.flags, 1);
+                break;
+            }
+            CItem it;
+            if (lane == 0) {
+                it.S = S;
+                it.H = H;
+                it.P = P;
+                it.uni = (uint32_t)uni;
+                it.hp = (uint32_t)h | ((uint32_t)p << 16);
+                a.c_out[slot] = it;
+            }
+            if (lane < depth) {  // lane t holds frame t
+                it.S = stS;
+                it.H = LOCAL ? stH : 0ull;
+                it.P = LOCAL ? stP : 0ull;
+                it.uni = (uint32_t)uni | 0x80000000u;
+                it.hp = stM;
+                a.c_out[slot + 1 + lane] = it;
+            }
+            break;
         }
     }
     if (LOCAL) vs.leave(H | P, H, P, lane, gid);
