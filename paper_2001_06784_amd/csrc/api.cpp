@@ -67,6 +67,23 @@ extern "C" const char *pv_last_error(void) { return g_last_error; }
 // waves per block of the level kernel
 #define WAVES_PER_LAUNCH_BLOCK 4
 
+// level-kernel variants: 0 global only; 1/2 per vertex, 8/16 k-slots, u128
+// per-visit sums; 3 per edge; 4/5 per vertex, 8/16 k-slots, u64 sums
+static void variant_params(int kv, int &kl, int &lk) {
+    static const int KL[6] = {0, 8, 16, 8, 8, 16};
+    static const int LK[6] = {PV_LK_VERTEX128, PV_LK_VERTEX128, PV_LK_VERTEX128, PV_LK_EDGE,
+                              PV_LK_VERTEX64, PV_LK_VERTEX64};
+    kl = KL[kv];
+    lk = LK[kv];
+}
+
+static int variant_of(int kl, int lk) {
+    if (kl == 0) return 0;
+    if (lk == PV_LK_EDGE) return 3;
+    if (lk == PV_LK_VERTEX64) return kl <= 8 ? 4 : 5;
+    return kl <= 8 ? 1 : 2;
+}
+
 // ------------------------------------------------------------ handles
 
 template <class T>
@@ -150,7 +167,7 @@ struct pv_ctx {
     DBuf<LevelArgs> d_args;
     LevelArgs *h_args = nullptr;
     int *h_io = nullptr;  // pinned readback slots
-    int level_blocks[4][3] = {};  // [variant: global, vertex 8, vertex 16, edge 8][unit kind]
+    int level_blocks[6][3] = {};  // [kernel variant, see variant_of][unit kind]
     int dfs_max = 64;
     int dfs_budget = 2048;
     Workspace ws;
@@ -217,10 +234,11 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
         delete c;
         return PV_ENOMEM;
     }
-    for (int kv = 0; kv < 4; kv++)
+    for (int kv = 0; kv < 6; kv++)
         for (int mode = 0; mode < 3; mode++) {
-            const int kl = kv == 0 ? 0 : (kv == 2 ? 16 : 8);
-            int per_cu = pv_level_blocks_per_cu(kl, kv == 3, mode);
+            int kl, lk;
+            variant_params(kv, kl, lk);
+            int per_cu = pv_level_blocks_per_cu(kl, lk, mode);
             c->level_blocks[kv][mode] = std::max(1, per_cu) * c->dev.num_cu;
         }
     if (const char *env = getenv("PV_DFS_MAX")) c->dfs_max = std::max(1, std::min(64, atoi(env)));
@@ -513,6 +531,7 @@ struct CountReq {
     int kmax = 0;
     int kl = 0;           // register k-slots for local counts (0: none)
     bool edge = false;    // local counts are per edge
+    int lk = PV_LK_VERTEX128;  // level-kernel local kind (PV_LK_*)
     int graphs = 1;       // batch: parts of the disjoint union (one histogram each)
     const int *vgraph = nullptr;  // batch: part of every vertex
     int klo = 1, K = 0;
@@ -655,7 +674,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 *c->h_args = a;
                 HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 5 * sizeof(int), s));
                 HIPCHK(hipMemcpyAsync(c->d_args.p, c->h_args, sizeof(LevelArgs), hipMemcpyHostToDevice, s));
-                const int kli = rq.kl == 0 ? 0 : (rq.edge ? 3 : (rq.kl <= 8 ? 1 : 2));
+                const int kli = variant_of(rq.kl, rq.lk);
                 const long long mode_units[3] = {(long long)n_mw + (level == 0 ? a.nheavy : 0), n_c,
                                                  level == 0 ? a.nlight : 0};
                 if (c->timing) HIPCHK(hipEventRecord(c->ev[3], s));
@@ -664,7 +683,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                     const long long want = (mode_units[mode] + WAVES_PER_LAUNCH_BLOCK - 1) / WAVES_PER_LAUNCH_BLOCK;
                     const int blocks = (int)std::min<long long>(c->level_blocks[kli][mode], want);
                     if (c->timing) HIPCHK(hipEventRecord(c->ev[8 + 2 * mode], s));
-                    HIPCHK(pv_launch_level(c->d_args.p, rq.kl, rq.edge, mode, std::max(1, blocks), s));
+                    HIPCHK(pv_launch_level(c->d_args.p, rq.kl, rq.lk, mode, std::max(1, blocks), s));
                     if (c->timing) HIPCHK(hipEventRecord(c->ev[9 + 2 * mode], s));
                     launches_kind[mode]++;
                 }
@@ -831,14 +850,23 @@ static pv_status setup_local(pv_graph *g, int kind, int klo, int khi, CountReq &
     rq.kl = rq.K <= 8 ? 8 : 16;
     rq.edge = kind == PV_EDGE;
     // the local paths keep C(a, b), a <= alpha, b <= khi - 1, in 64 bits;
-    // C(a, b) grows with a, so C(alpha, khi - 1) is the largest value used
+    // C(a, b) grows with a, so the largest value used is max over b of
+    // C(alpha, b)
     PVCHK(ensure_binomials(g->ctx, g->alpha + 3));
-    unsigned __int128 cb = 1;
+    unsigned __int128 cb = 1, cmax = 1;
     bool fits = true;
     for (int b = 1; b <= khi - 1 && b <= g->alpha; b++) {
         cb = cb * (unsigned __int128)(g->alpha - b + 1) / (unsigned __int128)b;
         if (cb >> 64) fits = false;
+        cmax = std::max(cmax, cb);
     }
+    // per vertex: one 64-bit word per k-slot suffices when a universe
+    // visit's sums stay below 2^64 (a visit walks at most dfs_budget nodes
+    // plus two pivot chains, each leaf adding at most cmax)
+    const unsigned __int128 visit_leaves = (unsigned __int128)g->ctx->dfs_budget + 256;
+    rq.lk = rq.edge ? PV_LK_EDGE
+                    : ((fits && cmax * visit_leaves < ((unsigned __int128)1 << 64)) ? PV_LK_VERTEX64
+                                                                                      : PV_LK_VERTEX128);
     if (!fits) {
         snprintf(g_last_error, sizeof g_last_error,
                  "local counts up to k=%d need binomials beyond 64 bits", khi);

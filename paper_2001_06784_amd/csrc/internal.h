@@ -136,8 +136,13 @@ hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *cn
 #define PV_UNITS_ITEMS 1
 #define PV_UNITS_LIGHT 2
 // `a` is a device pointer to the launch arguments
-hipError_t pv_launch_level(const LevelArgs *a, int kl, bool edge, int mode, int blocks, hipStream_t s);
-int pv_level_blocks_per_cu(int kl, bool edge, int mode);
+// local-count kinds of the level kernel: per vertex with u128 or u64 per-visit
+// accumulators, or per edge
+#define PV_LK_VERTEX128 0
+#define PV_LK_EDGE 1
+#define PV_LK_VERTEX64 2
+hipError_t pv_launch_level(const LevelArgs *a, int kl, int lk, int mode, int blocks, hipStream_t s);
+int pv_level_blocks_per_cu(int kl, int lk, int mode);
 hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s);
 hipError_t pv_launch_vertex_prefix(const LevelArgs *a, int blocks, hipStream_t s);
 // per-edge ids: o2e[q] = lexicographic id of the edge at oriented position q

@@ -113,9 +113,14 @@ __device__ __forceinline__ u64x8 ldc64x8(const uint64_t *p) {
 // Binomials come from a padded table: row a (a = -1..alpha) holds C(a, j)
 // for j = -16..15 at [(a + 1) * 32 + j + 16], zero outside 0 <= j <= a, so
 // the K values of a leaf are one contiguous, range-check-free segment.
-template <int KL>
+//
+// WIDE = false keeps one 64-bit word per slot: the host picks it when a
+// wave's sums for one universe visit cannot reach 2^64 (a visit reaches at
+// most dfs_budget plus two pivot chains of leaves, each adding a binomial
+// of at most C(alpha, k_hi - 1)); the flush widens to u128.
+template <int KL, bool WIDE>
 struct VertexSink {
-    uint64_t lo[KL > 0 ? KL : 1], hi[KL > 0 ? KL : 1];
+    uint64_t lo[KL > 0 ? KL : 1], hi[(KL > 0 && WIDE) ? KL : 1];
     // wave-uniform copies of the arguments
     const uint64_t *tab;
     uint64_t *vout;
@@ -138,8 +143,13 @@ struct VertexSink {
 
     __device__ void reset() {
 #pragma unroll
-        for (int i = 0; i < KL; i++) lo[i] = hi[i] = 0;
+        for (int i = 0; i < KL; i++) {
+            lo[i] = 0;
+            if (WIDE) hi[i] = 0;
+        }
     }
+
+    __device__ __forceinline__ uint64_t hiw(int i) const { return WIDE ? hi[i] : 0ull; }
 
     // path bookkeeping is only needed for pairs (EdgeSink)
     __device__ __forceinline__ void set_table(const int *) {}
@@ -177,7 +187,7 @@ struct VertexSink {
         for (int kk = 0; kk < KL; kk++) {
             const uint64_t v = (vH[kk / 8][kk % 8] & mH) | (vP[kk / 8][kk % 8] & mP);
             lo[kk] += v;
-            hi[kk] += (lo[kk] < v) ? 1ull : 0ull;
+            if (WIDE) hi[kk] += (lo[kk] < v) ? 1ull : 0ull;
         }
     }
 
@@ -190,8 +200,8 @@ struct VertexSink {
         if (lane < nm) {
 #pragma unroll
             for (int kk = 0; kk < KL; kk++)
-                if (kk < K && (lo[kk] | hi[kk]))
-                    ovf |= atomic_add_u128(vout + 2 * ((long long)gid * K + kk), lo[kk], hi[kk]);
+                if (kk < K && (lo[kk] | hiw(kk)))
+                    ovf |= atomic_add_u128(vout + 2 * ((long long)gid * K + kk), lo[kk], hiw(kk));
         }
         root = uniformi(root);
         uni = uniformi(uni);
@@ -201,8 +211,8 @@ struct VertexSink {
 #pragma unroll
             for (int kk = 0; kk < KL; kk++) {
                 if (kk < K) {
-                    const uint64_t a = readlane64(lo[kk], 62), b = readlane64(hi[kk], 62);
-                    const uint64_t c = readlane64(lo[kk], 63), d = readlane64(hi[kk], 63);
+                    const uint64_t a = readlane64(lo[kk], 62), b = WIDE ? readlane64(hiw(kk), 62) : 0ull;
+                    const uint64_t c = readlane64(lo[kk], 63), d = WIDE ? readlane64(hiw(kk), 63) : 0ull;
                     if (lane == kk) {
                         thl = a;
                         thh = b;
@@ -478,12 +488,12 @@ struct EdgeSink {
     }
 };
 
-template <int KL, bool EDGE>
+template <int KL, int LK>
 struct SinkOf {
-    using T = VertexSink<KL>;
+    using T = VertexSink<KL, LK == PV_LK_VERTEX128>;
 };
 template <int KL>
-struct SinkOf<KL, true> {
+struct SinkOf<KL, PV_LK_EDGE> {
     using T = EdgeSink<KL>;
 };
 
@@ -493,7 +503,7 @@ struct Ctr {
     unsigned long long nodes, work;
 };
 
-template <int KL, bool EDGE>
+template <int KL, int LK>
 __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelArgs &a,
                              int root, uint64_t Hw, uint64_t Pw, const int *vl, int W,
                              int2 &pref, const int *src_etab);
@@ -511,11 +521,12 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
 // remaining hold children.  The universe is written out first if it only
 // lived in registers.  So no single wave walks an unbounded subtree, and a
 // split hands over depth + 1 items however wide the frames are.
-template <int KL, bool EDGE>
+template <int KL, int LK>
 __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int h, int p, int lane,
-                            const LevelArgs &a, GlobalSink &gs, typename SinkOf<KL, EDGE>::T &vs,
+                            const LevelArgs &a, GlobalSink &gs, typename SinkOf<KL, LK>::T &vs,
                             Ctr &ct, int &uni, int nm, int gid, int root, bool from_frame,
                             uint32_t fmeta) {
+    constexpr bool EDGE = LK == PV_LK_EDGE;
     constexpr bool LOCAL = KL > 0;
     uint64_t stS = 0, stH = 0, stP = 0;
     uint32_t stM = 0;
@@ -633,7 +644,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
         if (nodes >= limit && depth > 0) {
             if (uni < 0) {
                 int2 pref;
-                uni = make_universe<KL, EDGE>(A, nm, gid, lane, a, root, 0ull, 0ull, nullptr, 0, pref,
+                uni = make_universe<KL, LK>(A, nm, gid, lane, a, root, 0ull, 0ull, nullptr, 0, pref,
                                               EDGE ? vs.etab_ptr() : nullptr);
                 if (uni < 0) break;  // buffers full: the host reruns with larger ones
             }
@@ -676,11 +687,12 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
 // children go to the next level; once |S| <= dfs_max finish depth first.
 // root/pref name the vertices above the universe (local counts only).
 
-template <int KL, bool EDGE>
+template <int KL, int LK>
 __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int h, int p, int uni,
                             int nm, int gid, int root, int2 pref, int lane, const LevelArgs &a,
-                            GlobalSink &gs, typename SinkOf<KL, EDGE>::T &vs, Ctr &ct,
+                            GlobalSink &gs, typename SinkOf<KL, LK>::T &vs, Ctr &ct,
                             bool from_frame = false, uint32_t fmeta = 0) {
+    constexpr bool EDGE = LK == PV_LK_EDGE;
     constexpr bool LOCAL = KL > 0;
     S = uniform64(S);
     H = uniform64(H);
@@ -692,7 +704,7 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     for (;;) {
         const int s = __popcll(S);
         if (from_frame || s <= a.dfs_max || uni < 0) {
-            compact_dfs<KL, EDGE>(A, S, H, P, h, p, lane, a, gs, vs, ct, uni, nm, gid, root,
+            compact_dfs<KL, LK>(A, S, H, P, h, p, lane, a, gs, vs, ct, uni, nm, gid, root,
                                   from_frame, fmeta);
             break;
         }
@@ -762,10 +774,11 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
 // index or -1 when the buffers are full.  For per-edge counts it also
 // clears the universe's prefix-pair accumulators (each lane the slots it
 // adds to later).
-template <int KL, bool EDGE>
+template <int KL, int LK>
 __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelArgs &a,
                              int root, uint64_t Hw, uint64_t Pw, const int *vl, int W,
                              int2 &pref, const int *src_etab) {
+    constexpr bool EDGE = LK == PV_LK_EDGE;
     constexpr bool LOCAL = KL > 0;
     int uni = 0;
     if (lane == 0) uni = atomicAdd(a.u_n, 1);
@@ -857,9 +870,10 @@ struct CState {
     int2 pref;
 };
 
-template <int KL, bool EDGE>
+template <int KL, int LK>
 __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int p, int lane,
                        const LevelArgs &a, Ctr &ct, int *memb, CState &cs) {
+    constexpr bool EDGE = LK == PV_LK_EDGE;
     constexpr bool LOCAL = KL > 0;
     const int W = a.W, dpad = a.dpad;
     const uint64_t *rows = a.hu_rows + (long long)hu * W * dpad;
@@ -893,7 +907,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
             int uni = -1;
             // the root and the multi-word holds/pivots form the prefix
             if (s > a.dfs_max || LOCAL) {
-                uni = make_universe<KL, EDGE>(A, s, gid, lane, a, root, Hw, Pw, vl, W, pref, nullptr);
+                uni = make_universe<KL, LK>(A, s, gid, lane, a, root, Hw, Pw, vl, W, pref, nullptr);
                 if (uni < 0) return false;  // buffers full: the host reruns with larger ones
             }
             cs.A = A;
@@ -1062,8 +1076,9 @@ __device__ void gather_heavy(int hu, int v, int lane, const LevelArgs &a) {
 //                   gathered into registers (largest first)
 // Every wave takes units from the launch's own cursor until none is left.
 
-template <int KL, int MODE, bool EDGE>
+template <int KL, int MODE, int LK>
 __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const LevelArgs *__restrict__ pa) {
+    constexpr bool EDGE = LK == PV_LK_EDGE;
     constexpr bool LOCAL = KL > 0;
     const LevelArgs &a = *pa;
     const int lane = threadIdx.x & 63;
@@ -1073,7 +1088,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
     __syncthreads();
     GlobalSink gs;
     gs.init(a, s_bins);
-    typename SinkOf<KL, EDGE>::T vs;
+    typename SinkOf<KL, LK>::T vs;
     __shared__ uint64_t s_xch[WAVES_PER_BLOCK][EDGE ? 4 * KL : 1];
     if (LOCAL) vs.init(a, s_xch[wv]);
     Ctr ct;
@@ -1114,9 +1129,9 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
             }
             gs.set_vertex(a.order[a.heavy_base + hu]);
             CState cs;
-            if (mw_run<KL, EDGE>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs)) {
+            if (mw_run<KL, LK>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs)) {
                 if (EDGE) vs.set_table(a.ueid + (long long)cs.uni * 4096);
-                compact_run<KL, EDGE>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
+                compact_run<KL, LK>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
                                 cs.pref, lane, a, gs, vs, ct);
                 if (LOCAL) vs.flush(lane, cs.nm, cs.gid, cs.root, cs.pref, cs.uni, a);
             }
@@ -1142,7 +1157,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
             }
             const int nm = (int)wave_add_u32(gid >= 0 ? 1u : 0u);
             if (EDGE) vs.set_table(a.ueid + (long long)u * 4096);
-            compact_run<KL, EDGE>(A, it.S, it.H, it.P, (int)(it.hp & 0xFFFFu), (int)(it.hp >> 16), u, nm,
+            compact_run<KL, LK>(A, it.S, it.H, it.P, (int)(it.hp & 0xFFFFu), (int)(it.hp >> 16), u, nm,
                             gid, -1, pref, lane, a, gs, vs, ct, fr, it.hp);
             if (LOCAL) vs.flush(lane, nm, gid, -1, pref, u, a);
         }
@@ -1166,11 +1181,11 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
             int uni = -1;
             int2 pref = make_int2(0, 0);
             if (d > a.dfs_max) {
-                uni = make_universe<KL, EDGE>(A, d, gid, lane, a, v, 0ull, 0ull, nullptr, 0, pref, etab_w);
+                uni = make_universe<KL, LK>(A, d, gid, lane, a, v, 0ull, 0ull, nullptr, 0, pref, etab_w);
                 if (uni < 0) continue;  // buffers full: the host reruns with larger ones
             }
             const int root = (uni < 0) ? v : -1;
-            compact_run<KL, EDGE>(A, (d == 64) ? ~0ull : ((1ull << d) - 1), 0ull, 0ull, 1, 0, uni, d, gid,
+            compact_run<KL, LK>(A, (d == 64) ? ~0ull : ((1ull << d) - 1), 0ull, 0ull, 1, 0, uni, d, gid,
                             root, pref, lane, a, gs, vs, ct);
             if (LOCAL) vs.flush(lane, d, gid, root, pref, uni, a);
         }
@@ -1414,43 +1429,50 @@ __global__ void __launch_bounds__(256) finalize_kernel(const unsigned long long 
 
 // ============================================================== host side
 
-template <int KL, bool EDGE>
+template <int KL, int LK>
 static hipError_t launch_mode(const LevelArgs *a, int mode, int blocks, hipStream_t s) {
     dim3 g(blocks), b(64 * WAVES_PER_BLOCK);
-    if (mode == PV_UNITS_MW) sct_level_kernel<KL, PV_UNITS_MW, EDGE><<<g, b, 0, s>>>(a);
-    else if (mode == PV_UNITS_ITEMS) sct_level_kernel<KL, PV_UNITS_ITEMS, EDGE><<<g, b, 0, s>>>(a);
-    else sct_level_kernel<KL, PV_UNITS_LIGHT, EDGE><<<g, b, 0, s>>>(a);
+    if (mode == PV_UNITS_MW) sct_level_kernel<KL, PV_UNITS_MW, LK><<<g, b, 0, s>>>(a);
+    else if (mode == PV_UNITS_ITEMS) sct_level_kernel<KL, PV_UNITS_ITEMS, LK><<<g, b, 0, s>>>(a);
+    else sct_level_kernel<KL, PV_UNITS_LIGHT, LK><<<g, b, 0, s>>>(a);
     return hipGetLastError();
 }
 
-hipError_t pv_launch_level(const LevelArgs *a, int kl, bool edge, int mode, int blocks, hipStream_t s) {
-    if (kl == 0) return launch_mode<0, false>(a, mode, blocks, s);
-    if (edge) return launch_mode<8, true>(a, mode, blocks, s);
-    if (kl <= 8) return launch_mode<8, false>(a, mode, blocks, s);
-    return launch_mode<16, false>(a, mode, blocks, s);
+// kl: 0 (global counts only), 8 or 16 k-slots; lk: PV_LK_*
+hipError_t pv_launch_level(const LevelArgs *a, int kl, int lk, int mode, int blocks, hipStream_t s) {
+    if (kl == 0) return launch_mode<0, PV_LK_VERTEX128>(a, mode, blocks, s);
+    if (lk == PV_LK_EDGE) return launch_mode<8, PV_LK_EDGE>(a, mode, blocks, s);
+    if (kl <= 8)
+        return lk == PV_LK_VERTEX64 ? launch_mode<8, PV_LK_VERTEX64>(a, mode, blocks, s)
+                                    : launch_mode<8, PV_LK_VERTEX128>(a, mode, blocks, s);
+    return lk == PV_LK_VERTEX64 ? launch_mode<16, PV_LK_VERTEX64>(a, mode, blocks, s)
+                                : launch_mode<16, PV_LK_VERTEX128>(a, mode, blocks, s);
 }
 
-template <int KL, bool EDGE>
+template <int KL, int LK>
 static int blocks_per_cu_kl(int mode) {
     int nb = 0;
     hipError_t e;
     if (mode == PV_UNITS_MW)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_MW, EDGE>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_MW, LK>,
                                                          64 * WAVES_PER_BLOCK, 0);
     else if (mode == PV_UNITS_ITEMS)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_ITEMS, EDGE>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_ITEMS, LK>,
                                                          64 * WAVES_PER_BLOCK, 0);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_LIGHT, EDGE>,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_LIGHT, LK>,
                                                          64 * WAVES_PER_BLOCK, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-int pv_level_blocks_per_cu(int kl, bool edge, int mode) {
-    if (kl == 0) return blocks_per_cu_kl<0, false>(mode);
-    if (edge) return blocks_per_cu_kl<8, true>(mode);
-    if (kl <= 8) return blocks_per_cu_kl<8, false>(mode);
-    return blocks_per_cu_kl<16, false>(mode);
+int pv_level_blocks_per_cu(int kl, int lk, int mode) {
+    if (kl == 0) return blocks_per_cu_kl<0, PV_LK_VERTEX128>(mode);
+    if (lk == PV_LK_EDGE) return blocks_per_cu_kl<8, PV_LK_EDGE>(mode);
+    if (kl <= 8)
+        return lk == PV_LK_VERTEX64 ? blocks_per_cu_kl<8, PV_LK_VERTEX64>(mode)
+                                    : blocks_per_cu_kl<8, PV_LK_VERTEX128>(mode);
+    return lk == PV_LK_VERTEX64 ? blocks_per_cu_kl<16, PV_LK_VERTEX64>(mode)
+                                : blocks_per_cu_kl<16, PV_LK_VERTEX128>(mode);
 }
 
 hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s) {

@@ -405,3 +405,16 @@ def test_batch_reuses_union_buffers(ctx):
     # a second, smaller batch on the same context after a larger one
     _check_batch(ctx, MIXED, tag="first")
     _check_batch(ctx, MIXED[:4], tag="second")
+
+
+@pytest.mark.parametrize("khi", [8, 15])
+def test_per_vertex_wide_and_narrow_sums(ctx, khi):
+    # K_100 with k up to 15: C(99, 14) * (budget + 256) exceeds 2^64, so the
+    # per-visit sums take the 128-bit path; up to 8 they take the 64-bit one
+    g = gg.plant_cliques(gg.gnp(300, 0.05, 171), [100], 172)
+    _say(f"[parity] per-vertex k=1..{khi} on gnp300+K100")
+    with Loaded(ctx, g) as h:
+        out, ovf, st = P.pv_count_local(h, P.PV_VERTEX, 1, khi)
+    ref = O.count(g, vertex=(1, khi))
+    assert ovf == 0
+    assert np.array_equal(out, ref.vertex)
