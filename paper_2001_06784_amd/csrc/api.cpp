@@ -117,7 +117,7 @@ struct DBuf {
 // workspace (graph handles keep only the graph and its orientation).
 struct Workspace {
     // peel / orientation temporaries
-    DBuf<int> deg, fa, fb, scan, rcnt, rcursor;
+    DBuf<int> deg, fa, fb, scan, rcnt;  // rcnt: per-chunk out-degree histograms of the root order
     DBuf<int> lid, uverts, ldeg, lrp, lcol, bcnt;  // solo phase of the peel
     DBuf<PeelCtl> ctl;
     // SCT work buffers
@@ -137,7 +137,7 @@ struct Workspace {
     long long hu_budget = 1ll << 30;  // bytes of heavy universes per chunk
 
     void release() {
-        DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &rcursor, &lid, &uverts, &ldeg, &lrp, &lcol,
+        DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &lid, &uverts, &ldeg, &lrp, &lcol,
                            &bcnt, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid};
         for (auto *b : ib) b->release();
         ctl.release();
@@ -447,8 +447,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     PVCHK(g->orow.ensure((size_t)n + 1));
     PVCHK(g->ocol.ensure((size_t)(g->nnz / 2)));
     PVCHK(c->ws.scan.ensure((size_t)n / 1024 + 2));
-    PVCHK(c->ws.rcnt.ensure((size_t)n + 2));
-    PVCHK(c->ws.rcursor.ensure((size_t)n + 2));
+    PVCHK(c->ws.rcnt.ensure((size_t)pv_root_chunks(n) * (PV_MAX_ALPHA + 1)));
     PVCHK(g->order.ensure(n));
     PVCHK(c->ws.ctl.ensure(1));
     PVCHK(c->ws.lid.ensure(n));
@@ -485,8 +484,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
         if (c->timing) HIPCHK(hipEventRecord(c->ev[1], s));
         HIPCHK(pv_launch_orient(c->dev, n, g->rp.p, g->col.p, g->sub.p, g->odeg.p, g->orow.p,
                                 g->ocol.p, g->small.p + SM_ALPHA, c->ws.scan.p, s));
-        HIPCHK(hipMemsetAsync(c->ws.rcnt.p, 0, sizeof(int) * ((size_t)n + 2), s));
-        HIPCHK(pv_launch_root_order(n, g->small.p + SM_ALPHA, g->odeg.p, c->ws.rcnt.p, c->ws.rcursor.p,
+        HIPCHK(pv_launch_root_order(n, g->small.p + SM_ALPHA, g->odeg.p, c->ws.rcnt.p, pv_root_chunks(n),
                                     g->order.p, g->small.p + SM_BOUNDS, PV_LIGHT_MAX, s));
         if (c->timing) HIPCHK(hipEventRecord(c->ev[2], s));
     } else {

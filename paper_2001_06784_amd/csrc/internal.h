@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pivoter.h"  // PV_MAX_ALPHA and the status codes
+
 struct DevInfo {
     int device;
     int num_cu;
@@ -127,8 +129,14 @@ hipError_t pv_launch_peel(const DevInfo &dev, const PeelArgs &pa, hipStream_t s)
 hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
                             int *odeg, int *orow, int *ocol, int *alpha, int *scan_tmp,
                             hipStream_t s);
-hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *cnt, int *cursor,
+// roots by out-degree, largest first; bh: chunks * (PV_MAX_ALPHA + 1) ints
+hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *bh, int chunks,
                                 int *order, int *bounds, int light_max, hipStream_t s);
+// chunks of the root ordering for n vertices
+static inline int pv_root_chunks(int n) {
+    const int c = (n + 4095) / 4096;
+    return c < 1 ? 1 : (c > 1024 ? 1024 : c);
+}
 
 // SCT build + leaf read-off
 // unit kinds of a level launch

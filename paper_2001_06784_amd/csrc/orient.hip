@@ -579,32 +579,74 @@ __global__ void __launch_bounds__(256) o2e_kernel(int n, const int *__restrict__
 // Counting sort of the roots by out-degree, largest first, so that heavy
 // subtrees start early.  cnt has amax+2 slots.
 
-__global__ void root_hist_kernel(int n, const int *__restrict__ odeg, int *__restrict__ cnt) {
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        atomicAdd(&cnt[odeg[v]], 1);
+// Three kernels without contended global atomics: every workgroup
+// histograms a contiguous chunk of vertices in LDS, one workgroup turns the
+// per-chunk histograms into output offsets (degree buckets largest first,
+// chunks in order inside a bucket), and every workgroup scatters its chunk
+// with LDS cursors.  bh is [chunks][PV_MAX_ALPHA + 1].
+#define ROOT_BINS (PV_MAX_ALPHA + 1)
+
+__global__ void __launch_bounds__(1024) root_hist_kernel(int n, int chunk, const int *__restrict__ amax_p,
+                                                         const int *__restrict__ odeg,
+                                                         int *__restrict__ bh) {
+    __shared__ int h[ROOT_BINS];
+    const int amax = *amax_p;
+    if (amax > PV_MAX_ALPHA) return;  // refused by the host (PV_ETOOBIG)
+    for (int d = threadIdx.x; d <= amax; d += blockDim.x) h[d] = 0;
+    __syncthreads();
+    const int v0 = blockIdx.x * chunk, v1 = min(n, v0 + chunk);
+    for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) atomicAdd(&h[odeg[v]], 1);
+    __syncthreads();
+    for (int d = threadIdx.x; d <= amax; d += blockDim.x) bh[(long long)blockIdx.x * ROOT_BINS + d] = h[d];
 }
 
-// cursor[d] = number of roots with out-degree > d (single block)
-__global__ void root_offsets_kernel(const int *__restrict__ amax_p, const int *__restrict__ cnt,
-                                    int *__restrict__ cursor, int *__restrict__ bounds,
-                                    int light_max) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const int amax = *amax_p;
+// bh[b][d] becomes the first output slot of chunk b's roots of out-degree d
+__global__ void __launch_bounds__(1024) root_offsets_kernel(int chunks, const int *__restrict__ amax_p,
+                                                            int *__restrict__ bh, int *__restrict__ bounds,
+                                                            int light_max) {
+    __shared__ int tot[ROOT_BINS];
+    __shared__ int start[ROOT_BINS];
+    const int amax = *amax_p;
+    if (amax > PV_MAX_ALPHA) return;  // refused by the host (PV_ETOOBIG)
+    for (int d = threadIdx.x; d <= amax; d += blockDim.x) {
+        int t = 0;
+        for (int b = 0; b < chunks; b++) t += bh[(long long)b * ROOT_BINS + d];
+        tot[d] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // buckets from the largest out-degree down
         int acc = 0;
         for (int d = amax; d >= 0; d--) {
-            cursor[d] = acc;
-            acc += cnt[d];
+            start[d] = acc;
+            acc += tot[d];
         }
         // bounds[0] = #roots with d > light_max (heavy), bounds[1] = #roots with d >= 1
-        bounds[0] = (light_max < amax) ? cursor[light_max] : 0;
-        bounds[1] = cursor[0];
+        bounds[0] = (light_max < amax) ? start[light_max] : 0;
+        bounds[1] = start[0];
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d <= amax; d += blockDim.x) {
+        int acc = start[d];
+        for (int b = 0; b < chunks; b++) {
+            const int c = bh[(long long)b * ROOT_BINS + d];
+            bh[(long long)b * ROOT_BINS + d] = acc;
+            acc += c;
+        }
     }
 }
 
-__global__ void root_scatter_kernel(int n, const int *__restrict__ odeg, int *__restrict__ cursor,
-                                    int *__restrict__ order) {
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        order[atomicAdd(&cursor[odeg[v]], 1)] = v;
+__global__ void __launch_bounds__(1024) root_scatter_kernel(int n, int chunk, const int *__restrict__ amax_p,
+                                                            const int *__restrict__ odeg,
+                                                            const int *__restrict__ bh,
+                                                            int *__restrict__ order) {
+    __shared__ int cur[ROOT_BINS];
+    const int amax = *amax_p;
+    if (amax > PV_MAX_ALPHA) return;  // refused by the host (PV_ETOOBIG)
+    for (int d = threadIdx.x; d <= amax; d += blockDim.x) cur[d] = bh[(long long)blockIdx.x * ROOT_BINS + d];
+    __syncthreads();
+    const int v0 = blockIdx.x * chunk, v1 = min(n, v0 + chunk);
+    for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) order[atomicAdd(&cur[odeg[v]], 1)] = v;
 }
 
 // ============================================================ host side
@@ -656,11 +698,13 @@ hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int 
     return hipGetLastError();
 }
 
-hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *cnt, int *cursor,
+hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *bh, int chunks,
                                 int *order, int *bounds, int light_max, hipStream_t s) {
-    root_hist_kernel<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, odeg, cnt);
-    root_offsets_kernel<<<1, 64, 0, s>>>(amax, cnt, cursor, bounds, light_max);
-    root_scatter_kernel<<<grid_for(n, 256, 4096), 256, 0, s>>>(n, odeg, cursor, order);
+    if (n <= 0) return hipSuccess;
+    const int chunk = (n + chunks - 1) / chunks;
+    root_hist_kernel<<<chunks, 1024, 0, s>>>(n, chunk, amax, odeg, bh);
+    root_offsets_kernel<<<1, 1024, 0, s>>>(chunks, amax, bh, bounds, light_max);
+    root_scatter_kernel<<<chunks, 1024, 0, s>>>(n, chunk, amax, odeg, bh, order);
     return hipGetLastError();
 }
 
