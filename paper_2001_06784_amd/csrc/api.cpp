@@ -177,6 +177,11 @@ struct pv_ctx {
     // device timing (HIP events on the context stream)
     bool timing = false;
     hipEvent_t ev[16] = {};
+    // the unit kinds of one level run concurrently: kinds 1 and 2 on their
+    // own streams (default priority), forked from and joined to the context
+    // stream with events
+    hipStream_t aux[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
 };
 
 struct pv_graph {
@@ -248,6 +253,20 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
             pv_fini(c);
             return PV_EDEVICE;
         }
+    for (auto &st : c->aux)
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            pv_fini(c);
+            return PV_EDEVICE;
+        }
+    if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        pv_fini(c);
+        return PV_EDEVICE;
+    }
+    for (auto &ev : c->ev_join)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            pv_fini(c);
+            return PV_EDEVICE;
+        }
     *out = c;
     return PV_OK;
 }
@@ -267,6 +286,14 @@ extern "C" void pv_fini(pv_ctx *c) {
     c->d_args.release();
     if (c->h_args) (void)hipHostFree(c->h_args);
     if (c->h_io) (void)hipHostFree(c->h_io);
+    for (auto &st : c->aux)
+        if (st) {
+            (void)hipStreamSynchronize(st);
+            (void)hipStreamDestroy(st);
+        }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    for (auto &ev : c->ev_join)
+        if (ev) (void)hipEventDestroy(ev);
     for (auto &ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
     delete c;
@@ -579,7 +606,8 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             PVCHK(c->ws.utot.ensure(c->ws.u_cap * 3 * rq.K * 2));
             PVCHK(c->ws.ueid.ensure(c->ws.u_cap * 4096));
             PVCHK(c->ws.weid.ensure((size_t)c->level_blocks[3][PV_UNITS_LIGHT] * WAVES_PER_LAUNCH_BLOCK * 4096));
-            const int eb = std::max({c->level_blocks[3][0], c->level_blocks[3][1], c->level_blocks[3][2]});
+            // one region per unit kind (the kinds of a level run concurrently)
+            const int eb = c->level_blocks[3][0] + c->level_blocks[3][1] + c->level_blocks[3][2];
             const size_t escr_words = (size_t)eb * WAVES_PER_LAUNCH_BLOCK * 2 * 64 * 2 * rq.K * 2;
             PVCHK(c->ws.escr.ensure(escr_words));
             HIPCHK(hipMemsetAsync(c->ws.escr.p, 0, escr_words * 8, s));
@@ -665,6 +693,9 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.ueid = rq.edge ? c->ws.ueid.p : nullptr;
                 a.weid = rq.edge ? c->ws.weid.p : nullptr;
                 a.escr = rq.edge ? c->ws.escr.p : nullptr;
+                a.escr_wave0[0] = 0;
+                a.escr_wave0[1] = c->level_blocks[3][0] * WAVES_PER_LAUNCH_BLOCK;
+                a.escr_wave0[2] = (c->level_blocks[3][0] + c->level_blocks[3][1]) * WAVES_PER_LAUNCH_BLOCK;
                 a.vgraph = rq.vgraph;
                 a.u_root = rq.vgraph ? c->ws.u_root.p : nullptr;
                 const long long units = (long long)n_mw + n_c + (level == 0 ? (long long)a.nheavy + a.nlight : 0);
@@ -676,13 +707,23 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 const long long mode_units[3] = {(long long)n_mw + (level == 0 ? a.nheavy : 0), n_c,
                                                  level == 0 ? a.nlight : 0};
                 if (c->timing) HIPCHK(hipEventRecord(c->ev[3], s));
+                // the kinds of a level are independent (they only append to
+                // the next level's queues): kinds 1 and 2 run on the
+                // auxiliary streams, concurrently with kind 0
+                HIPCHK(hipEventRecord(c->ev_fork, s));
                 for (int mode = 0; mode < 3; mode++) {
                     if (mode_units[mode] == 0) continue;
+                    hipStream_t ms = (mode == 0) ? s : c->aux[mode - 1];
+                    if (ms != s) HIPCHK(hipStreamWaitEvent(ms, c->ev_fork, 0));
                     const long long want = (mode_units[mode] + WAVES_PER_LAUNCH_BLOCK - 1) / WAVES_PER_LAUNCH_BLOCK;
                     const int blocks = (int)std::min<long long>(c->level_blocks[kli][mode], want);
-                    if (c->timing) HIPCHK(hipEventRecord(c->ev[8 + 2 * mode], s));
-                    HIPCHK(pv_launch_level(c->d_args.p, rq.kl, rq.lk, mode, std::max(1, blocks), s));
-                    if (c->timing) HIPCHK(hipEventRecord(c->ev[9 + 2 * mode], s));
+                    if (c->timing) HIPCHK(hipEventRecord(c->ev[8 + 2 * mode], ms));
+                    HIPCHK(pv_launch_level(c->d_args.p, rq.kl, rq.lk, mode, std::max(1, blocks), ms));
+                    if (c->timing) HIPCHK(hipEventRecord(c->ev[9 + 2 * mode], ms));
+                    if (ms != s) {
+                        HIPCHK(hipEventRecord(c->ev_join[mode], ms));
+                        HIPCHK(hipStreamWaitEvent(s, c->ev_join[mode], 0));
+                    }
                     launches_kind[mode]++;
                 }
                 if (c->timing) HIPCHK(hipEventRecord(c->ev[4], s));

@@ -114,8 +114,10 @@ struct LevelArgs {
                                    // [u_cap][2][K]: totals owed to hold / pivot prefix vertices
     int *ueid;                     // [u_cap][64][64] edge id of each member pair of a universe
     int *weid;                     // [waves of a light-root launch][64][64] the same per wave
-    uint64_t *escr;                // [waves of a launch][2][64][2][K] u128: join snapshots and
-                                   // finished-stay sums of the path members
+    uint64_t *escr;                // [waves][2][64][2][K] u128: join snapshots and finished-stay
+                                   // sums of the path members; the kinds of a level run
+                                   // concurrently, so kind m's waves start at escr_wave0[m]
+    int escr_wave0[3];
     // batches (a disjoint union of graphs): graph of every vertex, nullptr
     // for a single graph; hist then holds one hd*hd histogram per graph
     const int *vgraph;

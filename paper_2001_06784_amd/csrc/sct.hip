@@ -129,7 +129,7 @@ struct VertexSink {
     int *lovf;
     int klo, K, khi;
 
-    __device__ void init(const LevelArgs &a, uint64_t *) {
+    __device__ void init(const LevelArgs &a, uint64_t *, int) {
         tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
         vout = (uint64_t *)uniform64((uint64_t)a.vout);
         utot = (uint64_t *)uniform64((uint64_t)a.utot);
@@ -298,7 +298,7 @@ struct EdgeSink {
     int klo, K, khi;
     bool ovf;
 
-    __device__ void init(const LevelArgs &a, uint64_t *lds_xch) {
+    __device__ void init(const LevelArgs &a, uint64_t *lds_xch, int wave0) {
         xch = lds_xch;
         tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
         eout = (uint64_t *)uniform64((uint64_t)a.vout);
@@ -311,7 +311,7 @@ struct EdgeSink {
         klo = uniformi(a.klo);
         K = uniformi(a.K);
         khi = klo + K - 1;
-        const long long slot = (long long)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+        const long long slot = wave0 + (long long)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
         snap = a.escr + slot * (2ll * 64 * 2 * K * 2);
         snap = (uint64_t *)uniform64((uint64_t)snap);
         vacc = snap + 64 * 2 * K * 2;
@@ -1090,7 +1090,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
     gs.init(a, s_bins);
     typename SinkOf<KL, LK>::T vs;
     __shared__ uint64_t s_xch[WAVES_PER_BLOCK][EDGE ? 4 * KL : 1];
-    if (LOCAL) vs.init(a, s_xch[wv]);
+    if (LOCAL) vs.init(a, s_xch[wv], EDGE ? a.escr_wave0[MODE] : 0);
     Ctr ct;
     ct.nodes = ct.work = 0;
     int *cursor = a.next + MODE;
