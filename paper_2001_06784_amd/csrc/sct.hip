@@ -560,7 +560,10 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     for (;;) {
         if (visit) {
             nodes++;
-            if (S != 0) {
+            // with h = k_max hold vertices (truncated tree) the rest of the
+            // subtree is one pivot chain whose single leaf counts only toward
+            // C_{k_max} (C(p', 0) = 1 for any p'), as a leaf here does
+            if (S != 0 && h < hlim) {
                 const int s = __popcll(S);
                 work += (uint32_t)s;
                 const bool in = (S >> lane) & 1;
@@ -701,6 +704,9 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     p = uniformi(p);
     uni = uniformi(uni);
     nm = uniformi(nm);
+    // truncated tree: at h = k_max the subtree is one leaf (see compact_dfs);
+    // a frame item carries its path totals in fmeta, not in h and p
+    if (!from_frame && a.kmax > 0 && h >= a.kmax) S = 0;
     for (;;) {
         const int s = __popcll(S);
         if (from_frame || s <= a.dfs_max || uni < 0) {
@@ -881,6 +887,8 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
     const int root = a.order[a.heavy_base + hu];
     const bool wl = lane < W;
     if (!wl) Sw = Hw = Pw = 0;
+    // truncated tree: at h = k_max the subtree is one leaf (see compact_dfs)
+    if (a.kmax > 0 && h >= a.kmax) Sw = 0;
     for (;;) {
         const int s = (int)wave_add_u32(wl ? (uint32_t)__popcll(Sw) : 0u);
         if (s <= PV_LIGHT_MAX) {

@@ -418,3 +418,17 @@ def test_per_vertex_wide_and_narrow_sums(ctx, khi):
     ref = O.count(g, vertex=(1, khi))
     assert ovf == 0
     assert np.array_equal(out, ref.vertex)
+
+
+@pytest.mark.parametrize("kmax", [2, 4, 7, 11])
+def test_truncation_heavy_roots(ctx, kmax):
+    # multi-word roots (a planted K_90) under truncation: the walk stops at
+    # k_max hold vertices in every tier
+    g = gg.plant_cliques(gg.gnp(500, 0.06, 181), [90, 30], 182)
+    check_global(ctx, g, f"heavy truncated kmax={kmax}", kmax=kmax)
+    with Loaded(ctx, g) as h:
+        out, ovf, st = P.pv_count_local(h, P.PV_VERTEX, 2, kmax)
+        eout, eovf, _ = P.pv_count_local(h, P.PV_EDGE, 2, min(kmax, 9))
+    ref = O.count(g, vertex=(2, kmax), edge=(2, min(kmax, 9)))
+    assert ovf == 0 and np.array_equal(out, ref.vertex)
+    assert eovf == 0 and np.array_equal(eout, ref.edge)
