@@ -42,6 +42,34 @@ METRIC = "graph edges/sec and SCT leaves/sec for all-k counts; p50/p99 request l
 # operation per lane per clock on the vector ALUs
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 K_LO, K_HI = 3, 10
+# HBM traffic of the dominant kernel from two rocprofv3 counter runs
+# (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter reads for a
+# plain copy of known size; valid only for the kernel sources it was taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sct_level_kernel_chunglu1M_vertex3-10.json")
+KERNEL_SOURCES = ["paper_2001_06784_amd/csrc/sct.hip", "paper_2001_06784_amd/csrc/common.h",
+                  "paper_2001_06784_amd/csrc/internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """Bytes per launch of `kernel` from the committed counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash() or t.get("kernel") != kernel:
+        return None
+    return t.get("hbm_bytes_per_launch")
 
 
 def make_graph():
@@ -49,30 +77,56 @@ def make_graph():
     return gg.chung_lu_social(n=1_000_000, avg_deg=20.0, gamma=2.3, max_deg=20_000.0, seed=1)
 
 
-def cpu_baseline(g, fraction: float, seed: int):
+def cpu_baseline(g, h, total_nodes: int, seed: int, heavy_sample: int = 16,
+                 light_fraction: float = 0.02):
     """The oracle as it stands, single-threaded: its own peel over the whole
-    graph plus the SCT and Alg. 2 updates (global all k, per-vertex k=3..10)
-    for a uniform random sample of roots; the sample time is scaled by
-    1/fraction (root subproblems are independent, Sec. 5)."""
+    graph plus the SCT and Alg. 2 updates (global all k, per-vertex
+    k=3..10) for a sample of roots, scaled to the whole graph.
+
+    Root subproblems are independent (Sec. 5) but their costs are extremely
+    skewed, so the scaling is a ratio estimate per stratum: the oracle's
+    time per SCT node on sampled roots times the stratum's exact node count.
+    Strata: roots with |N+(v)| > 62 and the others; their node counts come
+    from the GPU (the same tree: node counts are parity-tested), the heavy
+    stratum from one pv_count_roots call, the rest as the remainder of the
+    timed run's total."""
     from oracle import oracle as O
+    from paper_2001_06784_amd import pivoter as P
     t0 = time.perf_counter()
     pe = O.peel(g)
     t_peel = time.perf_counter() - t0
+    od = O.out_degrees(g, pe.sub)
     rng = np.random.default_rng(seed)
-    nroots = max(1, int(round(fraction * g.n)))
-    roots = np.sort(rng.choice(g.n, nroots, replace=False)).astype(np.int32)
+    heavy = np.nonzero(od > 62)[0].astype(np.int32)
+    light = np.nonzero((od > 0) & (od <= 62))[0].astype(np.int32)
+    sinks = int(np.sum(od == 0))
+    nh = min(heavy_sample, len(heavy))
+    nl = max(1, int(round(light_fraction * len(light))))
+    hs = np.sort(rng.choice(heavy, nh, replace=False)).astype(np.int32) if nh else heavy[:0]
+    ls = np.sort(rng.choice(light, nl, replace=False)).astype(np.int32)
+    N_h = P.pv_count_roots(h, heavy).stats["nodes"] if len(heavy) else 0
+    N_l = total_nodes - N_h - sinks
+    t_h = n_h = 0
+    if nh:
+        t0 = time.perf_counter()
+        rh = O.count(g, key=pe.sub, roots=hs, vertex=(K_LO, K_HI))
+        t_h = time.perf_counter() - t0
+        n_h = rh.stats["nodes"]
     t0 = time.perf_counter()
-    O.count(g, key=pe.sub, roots=roots, vertex=(K_LO, K_HI))
-    t_sample = time.perf_counter() - t0
-    t_full = t_peel + t_sample * g.n / nroots
+    rl = O.count(g, key=pe.sub, roots=ls, vertex=(K_LO, K_HI))
+    t_l = time.perf_counter() - t0
+    n_l = rl.stats["nodes"]
+    t_full = t_peel + (t_h * N_h / n_h if n_h else 0.0) + (t_l * N_l / n_l if n_l else 0.0)
     return {
         "value": g.m / t_full,
         "unit": "edges/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"uniform random {nroots} of {g.n} roots (seed {seed}), global all-k + "
-                   f"per-vertex k={K_LO}..{K_HI}; sample {t_sample:.1f} s scaled by n/{nroots}, "
-                   f"plus full peel {t_peel:.2f} s; estimated full run {t_full:.0f} s"),
+        "sample": (f"{nh} of {len(heavy)} roots with |N+(v)| > 62 ({t_h:.1f} s, {n_h} SCT nodes) "
+                   f"and {nl} of {len(light)} others ({t_l:.1f} s, {n_l} nodes), seed {seed}; "
+                   f"global all-k + per-vertex k={K_LO}..{K_HI}; each stratum's seconds per node "
+                   f"times its exact node count ({N_h} and {N_l}), plus the full peel "
+                   f"{t_peel:.2f} s; estimated full run {t_full:.0f} s"),
     }
 
 
@@ -81,9 +135,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-fraction", type=float, default=0.03)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["social", "batch", "serve"], default="social")
+    ap.add_argument("--workload", choices=["social", "batch", "serve", "copy"], default="social")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: measured seconds")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -95,6 +148,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "copy":
+        return bench_copy()
 
     import torch
     from paper_2001_06784_amd import pivoter as P
@@ -145,7 +200,7 @@ def main():
     # algorithmic ALU work: each 64-bit AND + popcount of the pivot search is
     # 4 lane operations (two 32-bit ANDs, two 32-bit bit counts)
     achieved_tops = 4.0 * work[dom] / (ms_kind[dom] * 1e-3) / 1e12 if ms_kind[dom] > 0 else 0.0
-    kl = 8 if K <= 8 else 16
+    kname = f"sct_level_kernel<{st['kernel_kl']}, {dom}, {st['kernel_lk']}>"
     line = {
         "metric": METRIC,
         "value": g.m / dt,
@@ -172,19 +227,19 @@ def main():
                       "levels_by_kind": {kinds[i]: st["ms_kind"][i] for i in range(3)}},
         "roofline": {
             "bound": "alu",
-            "kernel": f"sct_level_kernel<{kl}, {dom}> ({kinds[dom]})",
+            "kernel": f"{kname} ({kinds[dom]})",
             "achieved": achieved_tops,
             "peak": ALU_PEAK_TOPS,
             "unit": "TOP/s",
             "frac": achieved_tops / ALU_PEAK_TOPS,
-            "traffic": None,
+            "traffic": measured_traffic(kname),
             "avg_launch_ms": ms_kind[dom] / max(launches[dom], 1),
             "launches": launches[dom],
         },
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(g, args.cpu_fraction, seed=7)
+        line["cpu_baseline"] = cpu_baseline(g, h, st["nodes"], seed=7)
     P.pv_graph_free(h)
     P.pv_fini(ctx)
     print(json.dumps(line), flush=True)
@@ -234,6 +289,18 @@ def bench_batch(args):
         "batched_over_plain": (len(hs) / dt) / (len(hs) / dt_plain),
     }
     print(json.dumps(line), flush=True)
+
+
+def bench_copy():
+    """A plain device copy of 1 GiB: the known-size reference that scales the
+    FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy", "bytes_read": src.numel() * 4,
+                      "bytes_written": dst.numel() * 4}), flush=True)
 
 
 def _serve_trace(duration: float, warm: float, rate: float = 200.0):

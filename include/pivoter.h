@@ -94,6 +94,10 @@ typedef struct {
     uint32_t launches_kind[3];  /* launches */
     float ms_kind[3];           /* summed device time (timing on) */
     uint64_t work_kind[3];      /* pivot work done by that kind's launches */
+    int32_t kernel_kl;          /* the level kernel's k-slots (0: global counts only) */
+    int32_t kernel_lk;          /* its local-count kind: 0 per vertex (u128 visit sums),
+                                   1 per edge, 2 per vertex (u64 visit sums) */
+    int32_t attempts;           /* walks of the tree: 1, plus one rerun per work-buffer overflow */
 } pv_stats;
 
 /* Human-readable name of a status code (static string). */

@@ -585,8 +585,22 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
     int chunk = (int)std::max<long long>(1, std::min<long long>(rq.nheavy, c->ws.hu_budget / hu_bytes));
     if (rq.nheavy == 0) chunk = 0;
 
+    // first capacities from the graph's size (buffers only grow): most
+    // calls then run the tree once; an overflow still reruns the whole walk
+    // with the demand the counters saw
+    {
+        auto at_least = [](size_t &cap, long long want) {
+            if ((long long)cap < want) cap = (size_t)want;
+        };
+        const long long n = g->n, m = g->nnz / 2;
+        at_least(c->ws.c_cap, std::min<long long>(2 * n + m / 8, 1ll << 26));
+        at_least(c->ws.u_cap, std::min<long long>(n / 4 + 1024, 1ll << 22));
+        at_least(c->ws.pref_cap, std::min<long long>(2 * n + 4096, 1ll << 26));
+        at_least(c->ws.mw_cap, std::min<long long>(rq.nheavy * 4 + 1024, 1ll << 20));
+    }
     for (int attempt = 0;; attempt++) {
         if (attempt > 12) return PV_ENOMEM;
+        g->last.attempts = attempt + 1;
         PVCHK(c->ws.hist.ensure((size_t)rq.graphs * hd * hd));
         if (rq.vgraph) PVCHK(c->ws.u_root.ensure(c->ws.u_cap));
         PVCHK(c->ws.counters.ensure(8));
@@ -774,6 +788,8 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             return PV_EDEVICE;
         }
         g->last.items = (uint64_t)items;
+        g->last.kernel_kl = rq.kl;
+        g->last.kernel_lk = rq.kl ? rq.lk : 0;
         g->last.truncated = rq.kmax > 0;
         g->last.levels = levels;
         g->last.ms_levels = ms_levels;

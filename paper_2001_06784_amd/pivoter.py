@@ -60,7 +60,8 @@ class pv_stats(C.Structure):
                 ("subrounds", C.c_int32), ("truncated", C.c_int32), ("levels", C.c_int32),
                 ("ms_peel", C.c_float), ("ms_orient", C.c_float), ("ms_levels", C.c_float),
                 ("ms_finalize", C.c_float), ("launches_kind", C.c_uint32 * 3),
-                ("ms_kind", C.c_float * 3), ("work_kind", C.c_uint64 * 3)]
+                ("ms_kind", C.c_float * 3), ("work_kind", C.c_uint64 * 3),
+                ("kernel_kl", C.c_int32), ("kernel_lk", C.c_int32), ("attempts", C.c_int32)]
 
     def as_dict(self) -> dict:
         d = {}

@@ -53,4 +53,4 @@ def test_header_constants_match_binding():
         assert m, name
         assert int(m.group(1)) == getattr(P, name), name
     assert ctypes.sizeof(P.pv_u128) == 16
-    assert ctypes.sizeof(P.pv_stats) == 120
+    assert ctypes.sizeof(P.pv_stats) == 136
