@@ -170,6 +170,7 @@ struct pv_ctx {
     int level_blocks[6][3] = {};  // [kernel variant, see variant_of][unit kind]
     int dfs_max = 64;
     int dfs_budget = 2048;
+    bool debug = false;  // PV_DEBUG set: per-level buffer demands on stderr
     Workspace ws;
     // batches: the union graph (reused between calls) and its part table
     pv_graph *batch = nullptr;
@@ -247,6 +248,7 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
             c->level_blocks[kv][mode] = std::max(1, per_cu) * c->dev.num_cu;
         }
     if (const char *env = getenv("PV_DFS_MAX")) c->dfs_max = std::max(1, std::min(64, atoi(env)));
+    c->debug = getenv("PV_DEBUG") != nullptr;
     if (const char *env = getenv("PV_DFS_BUDGET")) c->dfs_budget = std::max(16, std::min(1 << 20, atoi(env)));
     for (auto &ev : c->ev)
         if (hipEventCreate(&ev) != hipSuccess) {
@@ -750,6 +752,10 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                     for (int mode = 0; mode < 3; mode++)
                         if (mode_units[mode]) ms_kind[mode] += elapsed(c, 8 + 2 * mode, 9 + 2 * mode);
                 }
+                if (c->debug)
+                    fprintf(stderr, "[pivoter] attempt %d level %d: mw %d items %d universes %d prefix %d "
+                            "(caps %zu %zu %zu %zu)\n", attempt, level, io[SM_MWN], io[SM_CN], io[SM_UN],
+                            io[SM_PREFN], c->ws.mw_cap, c->ws.c_cap, c->ws.u_cap, c->ws.pref_cap);
                 if (io[SM_FLAGS] & 1) {
                     // a work buffer filled up: the counters kept counting every
                     // request, so they give the demand of this level; grow to it
