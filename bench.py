@@ -20,11 +20,14 @@ Two more workloads are selected with --workload:
          2.5); graph per request Zipf(1.1) over the pool, type 50/50 global
          all-k / global + per-vertex k=3..8.  The library's serving loop with
          batching against the same loop taking one request per pass;
-         latency from the scheduled arrival to the result in host memory.  The roofline object describes the
-dominant kernel (the SCT level kernel): integer ALU work, measured with HIP
-events on the library's stream.  The cpu_baseline object times the CPU
-oracle (single thread) on a uniform random sample of root subproblems and
-scales it to the whole graph.
+         latency from the scheduled arrival to the result in host memory.
+
+The roofline object describes the dominant kernel (the compact-item
+specialisation of the SCT level kernel): integer ALU work, its launches
+timed with HIP events on the library's stream, and its HBM traffic from
+counter runs while the kernel sources are unchanged.  The cpu_baseline
+object times the CPU oracle (single thread) on a stratified sample of root
+subproblems and scales each stratum by its exact SCT node count.
 """
 import argparse
 import json

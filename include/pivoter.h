@@ -137,6 +137,15 @@ pv_status pv_set_timing(pv_ctx *ctx, int32_t on);
  */
 pv_status pv_set_dfs_budget(pv_ctx *ctx, int32_t nodes);
 
+/*
+ * Tuning: subtrees whose node set has at most lane_max vertices (0..8) are
+ * walked one per lane, up to 64 at once per wavefront, instead of one node
+ * at a time by the whole wavefront.  0 turns this off.  Any value gives the
+ * same counts and tree.  Default 8 (PV_LANE_MAX overrides it at pv_init).
+ * Used for global counts.
+ */
+pv_status pv_set_lane_max(pv_ctx *ctx, int32_t lane_max);
+
 /* Text of the last HIP error seen by this host thread (static storage). */
 const char *pv_last_error(void);
 

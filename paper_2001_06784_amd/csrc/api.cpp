@@ -118,7 +118,7 @@ struct DBuf {
 struct Workspace {
     // peel / orientation temporaries
     DBuf<int> deg, fa, fb, scan, rcnt;  // rcnt: per-chunk out-degree histograms of the root order
-    DBuf<int> lid, uverts, ldeg, lrp, lcol, bcnt;  // solo phase of the peel
+    DBuf<int> lid, uverts, ldeg, lrp, lcol, bcnt, lfr;  // solo phase of the peel
     DBuf<PeelCtl> ctl;
     // SCT work buffers
     DBuf<CItem> citem[2];
@@ -138,7 +138,7 @@ struct Workspace {
 
     void release() {
         DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &lid, &uverts, &ldeg, &lrp, &lcol,
-                           &bcnt, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid};
+                           &bcnt, &lfr, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid};
         for (auto *b : ib) b->release();
         ctl.release();
         citem[0].release();
@@ -170,6 +170,7 @@ struct pv_ctx {
     int level_blocks[6][3] = {};  // [kernel variant, see variant_of][unit kind]
     int dfs_max = 64;
     int dfs_budget = 2048;
+    int lane_max = PV_LANE_MAX;
     bool debug = false;  // PV_DEBUG set: per-level buffer demands on stderr
     Workspace ws;
     // batches: the union graph (reused between calls) and its part table
@@ -250,6 +251,7 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
     if (const char *env = getenv("PV_DFS_MAX")) c->dfs_max = std::max(1, std::min(64, atoi(env)));
     c->debug = getenv("PV_DEBUG") != nullptr;
     if (const char *env = getenv("PV_DFS_BUDGET")) c->dfs_budget = std::max(16, std::min(1 << 20, atoi(env)));
+    if (const char *env = getenv("PV_LANE_MAX")) c->lane_max = std::max(0, std::min(PV_LANE_MAX, atoi(env)));
     for (auto &ev : c->ev)
         if (hipEventCreate(&ev) != hipSuccess) {
             pv_fini(c);
@@ -310,6 +312,12 @@ extern "C" pv_status pv_set_stream(pv_ctx *c, void *stream) {
 extern "C" pv_status pv_set_dfs_budget(pv_ctx *c, int32_t nodes) {
     if (!c || nodes < 16 || nodes > (1 << 20)) return PV_EINVAL;
     c->dfs_budget = nodes;
+    return PV_OK;
+}
+
+extern "C" pv_status pv_set_lane_max(pv_ctx *c, int32_t lane_max) {
+    if (!c || lane_max < 0 || lane_max > PV_LANE_MAX) return PV_EINVAL;
+    c->lane_max = lane_max;
     return PV_OK;
 }
 
@@ -485,6 +493,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     PVCHK(c->ws.lrp.ensure(PV_SOLO_MAX + 1));
     PVCHK(c->ws.lcol.ensure((size_t)std::max<long long>(g->nnz, 1)));
     PVCHK(c->ws.bcnt.ensure(PV_PEEL_MAX_BLOCKS));
+    PVCHK(c->ws.lfr.ensure(2 * PV_SOLO_MAX));
     hipStream_t s = c->stream;
     PeelCtl init;
     memset(&init, 0, sizeof init);
@@ -509,6 +518,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
         pa.lrp = c->ws.lrp.p;
         pa.lcol = c->ws.lcol.p;
         pa.bcnt = c->ws.bcnt.p;
+        pa.lfr = c->ws.lfr.p;
         HIPCHK(pv_launch_peel(c->dev, pa, s));
         if (c->timing) HIPCHK(hipEventRecord(c->ev[1], s));
         HIPCHK(pv_launch_orient(c->dev, n, g->rp.p, g->col.p, g->sub.p, g->odeg.p, g->orow.p,
@@ -671,6 +681,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.kmax = rq.kmax;
                 a.dfs_max = c->dfs_max;
                 a.dfs_budget = c->dfs_budget;
+                a.lane_max = local ? 0 : c->lane_max;
                 a.level = level;
                 a.n_mw_in = n_mw;
                 a.n_c_in = n_c;

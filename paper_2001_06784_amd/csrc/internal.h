@@ -29,7 +29,8 @@ struct PeelCtl {
 #define PV_PEEL_THREADS 1024
 #define PV_PEEL_MAX_BLOCKS 1024
 // the peel's last PV_SOLO_MAX vertices are finished by one workgroup
-#define PV_SOLO_MAX 16384
+// (local ids and remaining degrees below 2^16)
+#define PV_SOLO_MAX 32768
 
 struct PeelArgs {
     int n;
@@ -43,6 +44,7 @@ struct PeelArgs {
     int *lrp;            // [PV_SOLO_MAX + 1] local CSR rows
     int *lcol;           // [nnz] local CSR columns
     int *bcnt;           // [blocks] per-block counts
+    int *lfr;            // [2 * PV_SOLO_MAX] frontiers of local ids in the solo phase
 };
 
 // Largest out-degree handled by the compact (register) tier.  Roots with
@@ -50,6 +52,10 @@ struct PeelArgs {
 // the multi-word tier and drop into the compact tier once |S| <= LIGHT_MAX.
 // 62 rather than 64 keeps lanes 62 and 63 free for the per-vertex totals.
 #define PV_LIGHT_MAX 62
+
+// Largest node set walked by the lane tier (one subtree per lane, up to 64
+// at once per wave); its rows are 8-bit masks.
+#define PV_LANE_MAX 8
 
 // ------------------------------------------------------------- item types
 
@@ -73,6 +79,7 @@ struct LevelArgs {
     int light_base, nlight;  // level 0: light roots order[light_base, +nlight)
     int kmax, dfs_max;
     int dfs_budget;          // nodes a wave walks depth first before splitting
+    int lane_max;            // nodes with |S| <= lane_max go to the lane tier (0: off)
     // level input
     int level;
     int n_mw_in, n_c_in;

@@ -114,6 +114,26 @@ __device__ bool grid_barrier(PeelCtl *ctl, int nblocks) {
     return s_ok != 0;
 }
 
+// Frontier slot of every lane where pred holds, taken from *cnt with one
+// atomic per wave (the order inside a frontier is immaterial: a vertex's key
+// is its sub-round); -1 elsewhere.  All lanes of the wave take part.
+__device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
+    const uint64_t m = ballot64(pred);
+    if (m == 0) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(m);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cnt, __popcll(m));
+    base = __shfl(base, leader);
+    return pred ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
+// edges a wave takes per step of a frontier vertex's row (4 per lane, so
+// that four independent load/atomic chains are in flight)
+#define PEEL_UNROLL 4
+// frontier entries of the one-block phase kept in LDS (16-bit local ids)
+#define SOLO_LDS_F 16384
+
 // exclusive prefix sum over the block (blockDim.x == PV_PEEL_THREADS);
 // returns the block total in *total
 __device__ int block_excl_scan(int x, int *total) {
@@ -172,11 +192,15 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             k = ld_acquire(&ctl->minv[r & 1]);
             alpha = max(alpha, k);
             int *F = (r & 1) ? pa.fb : pa.fa;
-            for (int v = tid; v < n; v += nth)
-                if (sub[v] < 0 && deg[v] <= k) {
+            for (int vb = wid * 64; vb < n; vb += nw * 64) {
+                const int v = vb + lane;
+                const bool take = v < n && sub[v] < 0 && deg[v] <= k;
+                const int slot = wave_slot(take, &ctl->cnt[r % 3]);
+                if (take) {
                     sub[v] = r;
-                    F[atomicAdd(&ctl->cnt[r % 3], 1)] = v;
+                    F[slot] = v;
                 }
+            }
             if (!grid_barrier(ctl, nb)) return;
             nF = ld_acquire(&ctl->cnt[r % 3]);
             if (nF == 0) break;  // cannot happen while vertices remain
@@ -189,16 +213,33 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         }
         // remove the frontier: decrement the degrees of remaining neighbours;
         // a neighbour taken from k+1 to k joins the next sub-round
+        int *ncnt = &ctl->cnt[(r + 1) % 3];
         for (int i = wid; i < nF; i += nw) {
             const int v = F[i];
-            const int e1 = rp[v + 1];
-            for (int e = rp[v] + lane; e < e1; e += 64) {
-                const int u = col[e];
-                if (__hip_atomic_load(&sub[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0) {
-                    const int old = atomicSub(&deg[u], 1);
-                    if (old == k + 1) {
-                        sub[u] = r + 1;
-                        Fn[atomicAdd(&ctl->cnt[(r + 1) % 3], 1)] = u;
+            const int e0 = rp[v], e1 = rp[v + 1];
+            for (int eb = e0; eb < e1; eb += 64 * PEEL_UNROLL) {
+                int u[PEEL_UNROLL];
+                bool live[PEEL_UNROLL];
+#pragma unroll
+                for (int q = 0; q < PEEL_UNROLL; q++) {
+                    const int e = eb + q * 64 + lane;
+                    live[q] = e < e1;
+                    u[q] = col[live[q] ? e : e0];
+                }
+#pragma unroll
+                for (int q = 0; q < PEEL_UNROLL; q++)
+                    live[q] = live[q] &&
+                              __hip_atomic_load(&sub[u[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0;
+                int old[PEEL_UNROLL];
+#pragma unroll
+                for (int q = 0; q < PEEL_UNROLL; q++) old[q] = live[q] ? atomicSub(&deg[u[q]], 1) : 0;
+#pragma unroll
+                for (int q = 0; q < PEEL_UNROLL; q++) {
+                    const bool join = live[q] && old[q] == k + 1;
+                    const int slot = wave_slot(join, ncnt);
+                    if (join) {
+                        sub[u[q]] = r + 1;
+                        Fn[slot] = u[q];
                     }
                 }
             }
@@ -298,23 +339,43 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     if (blockIdx.x != 0) return;
 
     // ------------------------------------------------ solo phase (block 0)
-    __shared__ int s_deg[PV_SOLO_MAX];
-    __shared__ unsigned short s_F[2][PV_SOLO_MAX];
-    __shared__ unsigned char s_alive[PV_SOLO_MAX];
+    // LDS holds the remaining degrees as 16-bit halves of 32-bit words (a
+    // degree only counts neighbours still in U and is decremented at most
+    // once per neighbour, so a half never borrows from the other), liveness
+    // as a bitmask, and the first SOLO_LDS_F entries of the two frontiers of
+    // local ids; entries past those go to global memory (pa.lfr, two halves
+    // of PV_SOLO_MAX).
+    __shared__ unsigned s_deg2[PV_SOLO_MAX / 2];
+    __shared__ unsigned s_alive[PV_SOLO_MAX / 32];
+    __shared__ unsigned short s_F[2][SOLO_LDS_F];
     __shared__ int s_cnt, s_min;
     const int *__restrict__ lrp = pa.lrp;
     const int *__restrict__ lcol = pa.lcol;
     const int *__restrict__ uverts = pa.uverts;
     if (threadIdx.x == 0) s_cnt = 0;
-    for (int i = threadIdx.x; i < nu; i += blockDim.x) {
-        s_deg[i] = pa.ldeg[i];
-        s_alive[i] = (sub[uverts[i]] < 0) ? 1 : 0;
-    }
+    for (int i = threadIdx.x; i < PV_SOLO_MAX / 32; i += blockDim.x) s_alive[i] = 0u;
     __syncthreads();
+    for (int i = threadIdx.x; i < (nu + 1) / 2; i += blockDim.x) {
+        const int a = 2 * i, b = 2 * i + 1;
+        const unsigned lo = (unsigned)pa.ldeg[a] & 0xFFFFu;
+        const unsigned hi = (b < nu) ? ((unsigned)pa.ldeg[b] & 0xFFFFu) : 0u;
+        s_deg2[i] = lo | (hi << 16);
+    }
+    for (int i = threadIdx.x; i < nu; i += blockDim.x)
+        if (sub[uverts[i]] < 0) atomicOr(&s_alive[i >> 5], 1u << (i & 31));
+    __syncthreads();
+    auto alive = [&](int i) -> bool { return (s_alive[i >> 5] >> (i & 31)) & 1u; };
+    auto degof = [&](int i) -> int { return (int)((s_deg2[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu); };
+    int *lf[2] = {pa.lfr, pa.lfr + PV_SOLO_MAX};
+    auto fput = [&](int c, int j, int x) {
+        if (j < SOLO_LDS_F) s_F[c][j] = (unsigned short)x;
+        else lf[c][j] = x;
+    };
+    auto fget = [&](int c, int j) -> int { return j < SOLO_LDS_F ? (int)s_F[c][j] : lf[c][j]; };
     int cur = 0;
     if (nF > 0) {
         const int *F = (r & 1) ? pa.fb : pa.fa;
-        for (int j = threadIdx.x; j < nF; j += blockDim.x) s_F[0][j] = (unsigned short)pa.lid[F[j]];
+        for (int j = threadIdx.x; j < nF; j += blockDim.x) fput(0, j, pa.lid[F[j]]);
     }
     __syncthreads();
     const int bw = threadIdx.x >> 6, nbw = blockDim.x >> 6;
@@ -326,7 +387,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             __syncthreads();
             int mymin = 0x7fffffff;
             for (int i = threadIdx.x; i < nu; i += blockDim.x)
-                if (s_alive[i]) mymin = min(mymin, s_deg[i]);
+                if (alive(i)) mymin = min(mymin, degof(i));
             mymin = wave_min_i32(mymin);
             if (lane == 0) atomicMin(&s_min, mymin);
             __syncthreads();
@@ -334,12 +395,16 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             alpha = max(alpha, k);
             if (threadIdx.x == 0) s_cnt = 0;
             __syncthreads();
-            for (int i = threadIdx.x; i < nu; i += blockDim.x)
-                if (s_alive[i] && s_deg[i] <= k) {
-                    s_alive[i] = 0;
+            for (int ib = bw * 64; ib < nu; ib += nbw * 64) {
+                const int i = ib + lane;
+                const bool take = i < nu && alive(i) && degof(i) <= k;
+                const int slot = wave_slot(take, &s_cnt);
+                if (take) {
+                    atomicAnd(&s_alive[i >> 5], ~(1u << (i & 31)));
                     sub[uverts[i]] = r;
-                    s_F[cur][atomicAdd(&s_cnt, 1)] = (unsigned short)i;
+                    fput(cur, slot, i);
                 }
+            }
             __syncthreads();
             nF = s_cnt;
             __syncthreads();
@@ -348,17 +413,31 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             __syncthreads();
         }
         for (int j = bw; j < nF; j += nbw) {
-            const int i = s_F[cur][j];
-            const int e1 = lrp[i + 1];
-            for (int e = lrp[i] + lane; e < e1; e += 64) {
-                const int w = lcol[e];
-                if (s_alive[w]) {
-                    const int old = atomicSub(&s_deg[w], 1);
-                    if (old == k + 1) {
-                        s_alive[w] = 0;
-                        sub[uverts[w]] = r + 1;
-                        s_F[cur ^ 1][atomicAdd(&s_cnt, 1)] = (unsigned short)w;
+            const int i = fget(cur, j);
+            const int e0 = lrp[i], e1 = lrp[i + 1];
+            for (int eb = e0; eb < e1; eb += 64 * PEEL_UNROLL) {
+                int w[PEEL_UNROLL];
+                bool live[PEEL_UNROLL];
+#pragma unroll
+                for (int q = 0; q < PEEL_UNROLL; q++) {
+                    const int e = eb + q * 64 + lane;
+                    live[q] = e < e1;
+                    w[q] = lcol[live[q] ? e : e0];
+                }
+#pragma unroll
+                for (int q = 0; q < PEEL_UNROLL; q++) {
+                    bool join = false;
+                    if (live[q] && alive(w[q])) {
+                        const unsigned sh = (w[q] & 1) * 16;
+                        const unsigned old = atomicSub(&s_deg2[w[q] >> 1], 1u << sh);
+                        if ((int)((old >> sh) & 0xFFFFu) == k + 1) {
+                            atomicAnd(&s_alive[w[q] >> 5], ~(1u << (w[q] & 31)));
+                            sub[uverts[w[q]]] = r + 1;
+                            join = true;
+                        }
                     }
+                    const int slot = wave_slot(join, &s_cnt);
+                    if (join) fput(cur ^ 1, slot, w[q]);
                 }
             }
         }

@@ -84,6 +84,16 @@ struct GlobalSink {
             atomicAdd(&hist[(long long)h * hd + p], 1ull);
         }
     }
+
+    // a leaf of one lane's own subtree (lane tier): every lane its own (h,p)
+    __device__ __forceinline__ void leaf_lane(int h, int p) {
+        if (vgraph)
+            atomicAdd(&ghist[(long long)h * hd + p], 1ull);
+        else if (h < PV_LDS_H && p < 64)
+            __hip_atomic_fetch_add(&bins[h * 64 + p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            atomicAdd(&hist[(long long)h * hd + p], 1ull);
+    }
 };
 
 // Load through the constant address space: uniform addresses become scalar
@@ -508,6 +518,126 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
                              int root, uint64_t Hw, uint64_t Pw, const int *vl, int W,
                              int2 &pref, const int *src_etab);
 
+// ------------------------------------------------------------ lane tier
+// On sparse graphs most SCT nodes have a set of at most 8 vertices, and a
+// wave that walks such a node keeps most of its lanes idle.  The compact
+// walk instead queues these nodes, one per lane, and walks up to 64 of
+// their subtrees at once, each lane its own: the induced adjacency of the
+// node's set as eight 8-bit rows in one register (local index = rank in
+// the universe, so "smallest id" is still "lowest bit"), and the depth-first
+// stack of at most 8 frames (a frame's set strictly contains the next
+// one's) in LDS, frame t of lane l at [t][l] (no bank conflicts).  Pivot rule, child order and the node, work and
+// leaf accounting are those of compact_dfs: same tree, same counts.
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t x, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(x >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t row8(uint64_t rows, int i) {
+    return (uint32_t)(rows >> (8 * i)) & 0xFFu;
+}
+
+// Walk the queued subtrees: lane i < qn holds node qS (a set of at most
+// PV_LANE_MAX members of the universe whose row for member `lane` is A) with
+// path totals h = qhp & 0xFFFF, p = qhp >> 16.  All lanes take part.
+__device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint32_t qhp, int qn, int lane, int hlim,
+                          GlobalSink &gs, uint32_t &nodes, uint32_t &work, uint32_t &nleaves) {
+    const bool act = lane < qn;
+    const uint64_t S0 = act ? qS : 0ull;
+    const int s = __popcll(S0);
+    // members in increasing order and their rows restricted to S0, as 8-bit
+    // local masks (byte i = row of the i-th member)
+    int m[PV_LANE_MAX];
+    uint64_t T = S0;
+#pragma unroll
+    for (int i = 0; i < PV_LANE_MAX; i++) {
+        m[i] = T ? __builtin_ctzll(T) : 0;
+        T &= T - 1ull;  // stays 0 once empty
+    }
+    const uint32_t smask = (1u << s) - 1u;
+    uint64_t rows = 0;
+#pragma unroll
+    for (int i = 0; i < PV_LANE_MAX; i++) {
+        const uint64_t r = shfl64(A, m[i]);
+        uint32_t b = 0;
+#pragma unroll
+        for (int j = 0; j < PV_LANE_MAX; j++) b |= (uint32_t)((r >> m[j]) & 1ull) << j;
+        if (i >= s) b = 0;
+        rows |= (uint64_t)(b & smask) << (8 * i);
+    }
+    const int h0 = (int)(qhp & 0xFFFFu), p0 = (int)(qhp >> 16);
+    uint32_t S = smask;
+    int hl = 0, pl = 0, depth = 0;  // hold / pivot vertices taken inside the subtree
+    __shared__ uint32_t s_lst[WAVES_PER_BLOCK][PV_LANE_MAX][64];
+    uint32_t(*st)[64] = s_lst[threadIdx.x >> 6];
+    uint32_t nn = 0, ww = 0, nl = 0;
+    bool visit = true, live = act;
+    while (live) {
+        if (visit) {
+            nn++;
+            if (S != 0 && h0 + hl < hlim) {
+                const int sc = __popc(S);
+                ww += (uint32_t)sc;
+                int best = -1, piv = 0;
+                bool full = true;
+#pragma unroll
+                for (int i = 0; i < PV_LANE_MAX; i++) {
+                    if ((S >> i) & 1u) {
+                        const int c = __popc(row8(rows, i) & S);
+                        if (c > best) {
+                            best = c;
+                            piv = i;
+                        }
+                        full = full && (c + 1 == sc);
+                    }
+                }
+                if (best + 1 != sc) {
+                    // frame: set, pivot, path totals; then the pivot child
+                    st[depth][lane] = S | ((uint32_t)piv << 8) | ((uint32_t)hl << 11) | ((uint32_t)pl << 15);
+                    depth++;
+                    S &= row8(rows, piv);
+                    pl++;
+                    continue;
+                }
+                if (!full) {
+                    // the pivot sees all of S: no hold child
+                    S &= ~(1u << piv);
+                    pl++;
+                    continue;
+                }
+                // S is a clique: its pivot chain ends in one leaf
+                nn += (uint32_t)sc;
+                ww += (uint32_t)(sc * (sc - 1) / 2);
+                pl += sc;
+            }
+            nl++;
+            gs.leaf_lane(h0 + hl, p0 + pl);
+        }
+        visit = true;
+        if (depth == 0) {
+            live = false;
+            continue;
+        }
+        // next hold child of the top frame
+        const int t = depth - 1;
+        const uint32_t F = st[t][lane];
+        const uint32_t Sf = F & 0xFFu;
+        const int pf = (int)((F >> 8) & 7u);
+        const uint32_t R = Sf & ~row8(rows, pf) & ~(1u << pf);
+        const int v = __builtin_ctz(R);
+        S = row8(rows, v) & Sf;
+        if ((R & (R - 1u)) == 0) depth--;
+        else st[t][lane] = F & ~(1u << v);
+        hl = (int)((F >> 11) & 15u) + 1;
+        pl = (int)((F >> 15) & 15u);
+    }
+    nodes += wave_add_u32(nn);
+    work += wave_add_u32(ww);
+    nleaves += wave_add_u32(nl);
+}
+
 // ------------------------------------------------------ compact-tier DFS
 // Walk the whole subtree of node (S, H, P, h, p) of a compact universe
 // whose row for member `lane` is A.  Depth first, stack in lane-indexed
@@ -544,6 +674,13 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     // a hold child (h + 1 holds) exists only while h < hlim
     const int hlim = kmax > 0 ? kmax : 0x7fffffff;
     const uint32_t limit = (uint32_t)uniformi(a.dfs_budget);
+    // lane tier (global counts): nodes with |S| <= lmax are queued, lane qn
+    // holding the qn-th, and walked 64 at a time
+    constexpr bool LANE = !LOCAL;
+    const int lmax = LANE ? uniformi(a.lane_max) : 0;
+    uint64_t qS = 0;
+    uint32_t qhp = 0;
+    int qn = 0;
     bool visit = true;
     if (uniformi(from_frame ? 1 : 0)) {
         // resume an unfinished frame: only its remaining hold children are
@@ -558,7 +695,16 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
         visit = false;
     }
     for (;;) {
-        if (visit) {
+        if (LANE && visit && S != 0 && h < hlim && __popcll(S) <= lmax) {
+            if (lane == qn) {
+                qS = S;
+                qhp = (uint32_t)h | ((uint32_t)p << 16);
+            }
+            if (++qn == 64) {
+                lane_walk(A, qS, qhp, qn, lane, hlim, gs, nodes, work, nleaves);
+                qn = 0;
+            }
+        } else if (visit) {
             nodes++;
             // with h = k_max hold vertices (truncated tree) the rest of the
             // subtree is one pivot chain whose single leaf counts only toward
@@ -679,6 +825,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
             break;
         }
     }
+    if (LANE && qn > 0) lane_walk(A, qS, qhp, qn, lane, hlim, gs, nodes, work, nleaves);
     if (LOCAL) vs.leave(H | P, H, P, lane, gid);
     ct.nodes += nodes;
     ct.work += work;

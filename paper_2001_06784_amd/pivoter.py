@@ -37,7 +37,7 @@ PV_MAX_LOCAL_K = 16
 
 # every function declared in include/pivoter.h
 ABI_FUNCTIONS = [
-    "pv_strerror", "pv_init", "pv_fini", "pv_set_stream", "pv_set_dfs_max", "pv_set_dfs_budget",
+    "pv_strerror", "pv_init", "pv_fini", "pv_set_stream", "pv_set_dfs_max", "pv_set_dfs_budget", "pv_set_lane_max",
     "pv_set_timing",
     "pv_last_error",
     "pv_graph_load_csr", "pv_graph_load_csr_device", "pv_graph_free", "pv_graph_size",
@@ -133,6 +133,7 @@ def _lib():
             "pv_set_dfs_max": (i32, [vp, i32]),
             "pv_set_timing": (i32, [vp, i32]),
             "pv_set_dfs_budget": (i32, [vp, i32]),
+            "pv_set_lane_max": (i32, [vp, i32]),
             "pv_graph_load_csr": (i32, [vp, i32, i32p, i32p, u32, pvp]),
             "pv_graph_load_csr_device": (i32, [vp, i32, i64, vp, vp, u32, pvp]),
             "pv_graph_free": (None, [vp]),
@@ -219,6 +220,10 @@ def pv_set_dfs_max(ctx: int, dfs_max: int) -> None:
 
 def pv_set_dfs_budget(ctx: int, nodes: int) -> None:
     _check(_lib().pv_set_dfs_budget(ctx, nodes), "pv_set_dfs_budget")
+
+
+def pv_set_lane_max(ctx: int, lane_max: int) -> None:
+    _check(_lib().pv_set_lane_max(ctx, lane_max), "pv_set_lane_max")
 
 
 def pv_set_timing(ctx: int, on: bool) -> None:

@@ -239,11 +239,43 @@ def test_valid_tiny_csr_is_accepted(ctx):
 
 # --------------------------------------------------- peel at larger sizes
 
-@pytest.mark.parametrize("n,deg,seed", [(60000, 12, 71), (200000, 16, 72)])
+@pytest.mark.parametrize("n,deg,seed", [(30000, 12, 71), (40000, 10, 73), (200000, 16, 72)])
 def test_peel_order_large(ctx, n, deg, seed):
-    # large enough that the grid-wide phase runs before the one-block phase
+    # one-block phase only (30000), a few grid sub-rounds first (40000), and
+    # a long grid-wide phase (200000)
     g = gg.chung_lu(n, deg, 2.3, n // 20, seed)
     _say(f"[parity] peel n={g.n} m={g.m}")
+    with Loaded(ctx, g) as h:
+        alpha = P.pv_graph_orient(h)
+        sub = P.pv_graph_export_order(h)
+    pe = O.peel(g)
+    assert alpha == pe.alpha
+    assert np.array_equal(sub, pe.sub)
+
+
+@pytest.mark.parametrize("n", [32768, 32769, 65536])
+def test_peel_order_with_a_hub(ctx, n):
+    # a vertex adjacent to all others: remaining degrees up to n - 1 in the
+    # one-block phase (its largest size), just past it, and far past it
+    g0 = gg.chung_lu(n, 6, 2.3, 500, 74)
+    hub = np.arange(1, n, dtype=np.int64)
+    ia, ja = g0.edges()
+    g = gg.from_edges(n, np.concatenate([ia, np.zeros_like(hub)]), np.concatenate([ja, hub]))
+    _say(f"[parity] peel with hub n={g.n} m={g.m}")
+    with Loaded(ctx, g) as h:
+        alpha = P.pv_graph_orient(h)
+        sub = P.pv_graph_export_order(h)
+    pe = O.peel(g)
+    assert alpha == pe.alpha
+    assert np.array_equal(sub, pe.sub)
+
+
+@pytest.mark.parametrize("name,g", [("cycle 32768", gg.cycle(32768)), ("cycle 40000", gg.cycle(40000)),
+                                    ("empty 30000", gg.empty(30000))])
+def test_peel_order_one_big_frontier(ctx, name, g):
+    # every vertex leaves in the first sub-round: frontiers larger than the
+    # part the one-block phase keeps on chip
+    _say(f"[parity] peel {name}")
     with Loaded(ctx, g) as h:
         alpha = P.pv_graph_orient(h)
         sub = P.pv_graph_export_order(h)
