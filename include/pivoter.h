@@ -142,7 +142,8 @@ pv_status pv_set_dfs_budget(pv_ctx *ctx, int32_t nodes);
  * walked one per lane, up to 64 at once per wavefront, instead of one node
  * at a time by the whole wavefront.  0 turns this off.  Any value gives the
  * same counts and tree.  Default 8 (PV_LANE_MAX overrides it at pv_init).
- * Used for global counts.
+ * Used for global counts, and for per-vertex counts of at most 8 values of
+ * k whose per-visit sums fit 64 bits.
  */
 pv_status pv_set_lane_max(pv_ctx *ctx, int32_t lane_max);
 

@@ -569,6 +569,7 @@ struct CountReq {
     int kl = 0;           // register k-slots for local counts (0: none)
     bool edge = false;    // local counts are per edge
     int lk = PV_LK_VERTEX128;  // level-kernel local kind (PV_LK_*)
+    bool lane_ok = true;  // the lane tier may run (its per-vertex sums fit 64 bits)
     int graphs = 1;       // batch: parts of the disjoint union (one histogram each)
     const int *vgraph = nullptr;  // batch: part of every vertex
     int klo = 1, K = 0;
@@ -681,7 +682,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.kmax = rq.kmax;
                 a.dfs_max = c->dfs_max;
                 a.dfs_budget = c->dfs_budget;
-                a.lane_max = local ? 0 : c->lane_max;
+                a.lane_max = (!local || rq.lane_ok) ? c->lane_max : 0;
                 a.level = level;
                 a.n_mw_in = n_mw;
                 a.n_c_in = n_c;
@@ -942,6 +943,11 @@ static pv_status setup_local(pv_graph *g, int kind, int klo, int khi, CountReq &
     rq.lk = rq.edge ? PV_LK_EDGE
                     : ((fits && cmax * visit_leaves < ((unsigned __int128)1 << 64)) ? PV_LK_VERTEX64
                                                                                       : PV_LK_VERTEX128);
+    // the lane tier (per vertex: 64-bit sums, 8 k-slots) adds up to one
+    // batch of 64 subtrees of at most 34 nodes each (the largest SCT on 8
+    // vertices) to a visit, and a lane's or a batch's sums stay below that
+    rq.lane_ok = rq.lk == PV_LK_VERTEX64 && rq.kl == 8 &&
+                 cmax * (visit_leaves + 64 * 34) < ((unsigned __int128)1 << 64);
     if (!fits) {
         snprintf(g_last_error, sizeof g_last_error,
                  "local counts up to k=%d need binomials beyond 64 bits", khi);

@@ -201,6 +201,35 @@ struct VertexSink {
         }
     }
 
+    // lane tier: sums av (toward hold vertices) and bv (toward pivot
+    // vertices) owed by one queued node's leaves to the vertices above it,
+    // whose members are H, P; lanes 62/63 as in leaf()
+    __device__ __forceinline__ void add_sums(const uint64_t *av, const uint64_t *bv, uint64_t H, uint64_t P,
+                                             int lane) {
+        const bool inH = ((H >> lane) & 1) || lane == 62;
+        const bool inP = ((P >> lane) & 1) || lane == 63;
+        uint64_t mH = inH ? ~0ull : 0ull;
+        uint64_t mP = (!inH && inP) ? ~0ull : 0ull;
+        asm volatile("" : "+v"(mH), "+v"(mP));
+#pragma unroll
+        for (int kk = 0; kk < KL; kk++) {
+            const uint64_t v = (av[kk] & mH) | (bv[kk] & mP);
+            lo[kk] += v;
+            if (WIDE) hi[kk] += (lo[kk] < v) ? 1ull : 0ull;
+        }
+    }
+
+    // lane tier: add this member's LDS slots and clear them
+    __device__ __forceinline__ void add_slots(lds_u64 *slot, int) {
+#pragma unroll
+        for (int kk = 0; kk < KL; kk++) {
+            const uint64_t v = slot[kk];
+            slot[kk] = 0ull;
+            lo[kk] += v;
+            if (WIDE) hi[kk] += (lo[kk] < v) ? 1ull : 0ull;
+        }
+    }
+
     // members: lane j < nm owns vertex gid; above the universe: `root` (a
     // light root walked without a universe in memory, a hold vertex) or, with
     // a universe, the totals go to its accumulators (a final kernel adds them
@@ -539,21 +568,41 @@ __device__ __forceinline__ uint32_t row8(uint64_t rows, int i) {
     return (uint32_t)(rows >> (8 * i)) & 0xFFu;
 }
 
+// LDS slots of the lane tier's per-member sums (per vertex): member j's
+// slot kk of this wave at [j * (KL + 1) + kk]; zero between batches
+template <int KL>
+__device__ __forceinline__ lds_u64 *lane_acc() {
+    __shared__ unsigned long long s_lacc[WAVES_PER_BLOCK][64 * (KL + 1)];
+    return (lds_u64 *)s_lacc[threadIdx.x >> 6];
+}
+
 // Walk the queued subtrees: lane i < qn holds node qS (a set of at most
 // PV_LANE_MAX members of the universe whose row for member `lane` is A) with
-// path totals h = qhp & 0xFFFF, p = qhp >> 16.  All lanes take part.
-__device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint32_t qhp, int qn, int lane, int hlim,
-                          GlobalSink &gs, uint32_t &nodes, uint32_t &work, uint32_t &nleaves) {
+// path totals h = qhp & 0xFFFF, p = qhp >> 16 and, for per-vertex counts,
+// the path's hold and pivot members qH, qP.  All lanes take part.
+//
+// Per-vertex counts (Alg. 2): a leaf owes C(p, k-h) to every hold vertex of
+// its path and C(p-1, k-h-1) to every pivot vertex.  Members taken inside
+// the lane's subtree get theirs at the leaf through LDS atomics on their
+// slots; for the vertices above the queued node every leaf owes the same,
+// so the lane sums its leaves' binomials and the wave adds each lane's sums
+// to those vertices once (member lanes and the lanes 62/63 of VertexSink).
+template <int KL, bool LOC, class VS>
+__device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qH, uint64_t qP, uint32_t qhp,
+                                          int qn, int lane, int hlim, GlobalSink &gs, VS &vs,
+                                          uint32_t &nodes, uint32_t &work, uint32_t &nleaves) {
+    constexpr int NK = LOC ? KL : 1;
     const bool act = lane < qn;
     const uint64_t S0 = act ? qS : 0ull;
     const int s = __popcll(S0);
-    // members in increasing order and their rows restricted to S0, as 8-bit
-    // local masks (byte i = row of the i-th member)
+    // members in increasing order (6 bits each in mpack) and their rows
+    // restricted to S0, as 8-bit local masks (byte i = row of the i-th member)
     int m[PV_LANE_MAX];
-    uint64_t T = S0;
+    uint64_t T = S0, mpack = 0;
 #pragma unroll
     for (int i = 0; i < PV_LANE_MAX; i++) {
         m[i] = T ? __builtin_ctzll(T) : 0;
+        mpack |= (uint64_t)m[i] << (6 * i);
         T &= T - 1ull;  // stays 0 once empty
     }
     const uint32_t smask = (1u << s) - 1u;
@@ -569,15 +618,21 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint32_t qhp,
     }
     const int h0 = (int)(qhp & 0xFFFFu), p0 = (int)(qhp >> 16);
     uint32_t S = smask;
-    int hl = 0, pl = 0, depth = 0;  // hold / pivot vertices taken inside the subtree
+    uint32_t Hl = 0, Pl = 0;  // hold / pivot members taken inside the subtree (local masks)
+    int depth = 0;
     __shared__ uint32_t s_lst[WAVES_PER_BLOCK][PV_LANE_MAX][64];
     uint32_t(*st)[64] = s_lst[threadIdx.x >> 6];
+    lds_u64 *acc = nullptr;
+    if constexpr (LOC) acc = lane_acc<KL>();
+    uint64_t sH[NK], sP[NK];  // this lane's sums toward the vertices above its node
+#pragma unroll
+    for (int kk = 0; kk < NK; kk++) sH[kk] = sP[kk] = 0;
     uint32_t nn = 0, ww = 0, nl = 0;
     bool visit = true, live = act;
     while (live) {
         if (visit) {
             nn++;
-            if (S != 0 && h0 + hl < hlim) {
+            if (S != 0 && h0 + __popc(Hl) < hlim) {
                 const int sc = __popc(S);
                 ww += (uint32_t)sc;
                 int best = -1, piv = 0;
@@ -594,26 +649,49 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint32_t qhp,
                     }
                 }
                 if (best + 1 != sc) {
-                    // frame: set, pivot, path totals; then the pivot child
-                    st[depth][lane] = S | ((uint32_t)piv << 8) | ((uint32_t)hl << 11) | ((uint32_t)pl << 15);
+                    // frame: set, pivot, path members; then the pivot child
+                    st[depth][lane] = S | ((uint32_t)piv << 8) | (Hl << 11) | (Pl << 19);
                     depth++;
                     S &= row8(rows, piv);
-                    pl++;
+                    Pl |= 1u << piv;
                     continue;
                 }
                 if (!full) {
                     // the pivot sees all of S: no hold child
                     S &= ~(1u << piv);
-                    pl++;
+                    Pl |= 1u << piv;
                     continue;
                 }
                 // S is a clique: its pivot chain ends in one leaf
                 nn += (uint32_t)sc;
                 ww += (uint32_t)(sc * (sc - 1) / 2);
-                pl += sc;
+                Pl |= S;
             }
             nl++;
-            gs.leaf_lane(h0 + hl, p0 + pl);
+            const int h = h0 + __popc(Hl), p = p0 + __popc(Pl);
+            gs.leaf_lane(h, p);
+            if (LOC && h <= vs.khi && h + p >= vs.klo) {
+                // same table segments as VertexSink::leaf
+                const uint64_t *rowH = vs.tab + (p + 1) * 32 + (vs.klo - h + 16);  // C(p, k-h)
+                const uint64_t *rowP = vs.tab + p * 32 + (vs.klo - h + 15);        // C(p-1, k-h-1)
+                uint64_t vH[NK], vP[NK];
+#pragma unroll
+                for (int kk = 0; kk < NK; kk++) {
+                    vH[kk] = rowH[kk];
+                    vP[kk] = rowP[kk];
+                    sH[kk] += vH[kk];
+                    sP[kk] += vP[kk];
+                }
+                for (uint32_t M = Hl | Pl; M; M &= M - 1u) {
+                    const int i = __builtin_ctz(M);
+                    const bool isH = (Hl >> i) & 1u;
+                    lds_u64 *slot = acc + (int)((mpack >> (6 * i)) & 63u) * (KL + 1);
+#pragma unroll
+                    for (int kk = 0; kk < NK; kk++)
+                        __hip_atomic_fetch_add(slot + kk, isH ? vH[kk] : vP[kk], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
         }
         visit = true;
         if (depth == 0) {
@@ -630,12 +708,32 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint32_t qhp,
         S = row8(rows, v) & Sf;
         if ((R & (R - 1u)) == 0) depth--;
         else st[t][lane] = F & ~(1u << v);
-        hl = (int)((F >> 11) & 15u) + 1;
-        pl = (int)((F >> 15) & 15u);
+        Hl = ((F >> 11) & 0xFFu) | (1u << v);
+        Pl = (F >> 19) & 0xFFu;
     }
     nodes += wave_add_u32(nn);
     work += wave_add_u32(ww);
     nleaves += wave_add_u32(nl);
+    if constexpr (LOC) {
+        // the vertices above each queued node: its lane's sums, once
+        bool nz = false;
+#pragma unroll
+        for (int kk = 0; kk < NK; kk++) nz = nz || (sH[kk] | sP[kk]) != 0;
+        for (uint64_t bl = ballot64(nz); bl; bl &= bl - 1ull) {
+            const int L = __builtin_ctzll(bl);
+            uint64_t aH[NK], aP[NK];
+#pragma unroll
+            for (int kk = 0; kk < NK; kk++) {
+                aH[kk] = readlane64(sH[kk], L);
+                aP[kk] = readlane64(sP[kk], L);
+            }
+            vs.add_sums(aH, aP, readlane64(qH, L), readlane64(qP, L), lane);
+        }
+        // members taken inside the subtrees: their LDS slots (then cleared)
+        wave_sync();
+        vs.add_slots(acc + lane * (KL + 1), lane);
+        wave_sync();
+    }
 }
 
 // ------------------------------------------------------ compact-tier DFS
@@ -674,11 +772,12 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     // a hold child (h + 1 holds) exists only while h < hlim
     const int hlim = kmax > 0 ? kmax : 0x7fffffff;
     const uint32_t limit = (uint32_t)uniformi(a.dfs_budget);
-    // lane tier (global counts): nodes with |S| <= lmax are queued, lane qn
-    // holding the qn-th, and walked 64 at a time
-    constexpr bool LANE = !LOCAL;
+    // lane tier (global counts; per vertex with 64-bit sums and 8 k-slots):
+    // nodes with |S| <= lmax are queued, lane qn holding the qn-th, and
+    // walked 64 at a time
+    constexpr bool LANE = !LOCAL || (LK == PV_LK_VERTEX64 && KL == 8);
     const int lmax = LANE ? uniformi(a.lane_max) : 0;
-    uint64_t qS = 0;
+    uint64_t qS = 0, qH = 0, qP = 0;
     uint32_t qhp = 0;
     int qn = 0;
     bool visit = true;
@@ -695,16 +794,25 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
         visit = false;
     }
     for (;;) {
-        if (LANE && visit && S != 0 && h < hlim && __popcll(S) <= lmax) {
-            if (lane == qn) {
-                qS = S;
-                qhp = (uint32_t)h | ((uint32_t)p << 16);
+        bool queued = false;
+        if constexpr (LANE) {
+            if (visit && S != 0 && h < hlim && __popcll(S) <= lmax) {
+                if (lane == qn) {
+                    qS = S;
+                    if (LOCAL) {
+                        qH = H;
+                        qP = P;
+                    }
+                    qhp = (uint32_t)h | ((uint32_t)p << 16);
+                }
+                if (++qn == 64) {
+                    lane_walk<KL, LOCAL>(A, qS, qH, qP, qhp, qn, lane, hlim, gs, vs, nodes, work, nleaves);
+                    qn = 0;
+                }
+                queued = true;
             }
-            if (++qn == 64) {
-                lane_walk(A, qS, qhp, qn, lane, hlim, gs, nodes, work, nleaves);
-                qn = 0;
-            }
-        } else if (visit) {
+        }
+        if (visit && !queued) {
             nodes++;
             // with h = k_max hold vertices (truncated tree) the rest of the
             // subtree is one pivot chain whose single leaf counts only toward
@@ -825,7 +933,9 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
             break;
         }
     }
-    if (LANE && qn > 0) lane_walk(A, qS, qhp, qn, lane, hlim, gs, nodes, work, nleaves);
+    if constexpr (LANE) {
+        if (qn > 0) lane_walk<KL, LOCAL>(A, qS, qH, qP, qhp, qn, lane, hlim, gs, vs, nodes, work, nleaves);
+    }
     if (LOCAL) vs.leave(H | P, H, P, lane, gid);
     ct.nodes += nodes;
     ct.work += work;
@@ -1246,6 +1356,12 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
     typename SinkOf<KL, LK>::T vs;
     __shared__ uint64_t s_xch[WAVES_PER_BLOCK][EDGE ? 4 * KL : 1];
     if (LOCAL) vs.init(a, s_xch[wv], EDGE ? a.escr_wave0[MODE] : 0);
+    if constexpr (LOCAL && LK == PV_LK_VERTEX64 && KL == 8) {
+        // the lane tier's per-member slots of this wave start at zero
+        lds_u64 *acc = lane_acc<KL>();
+        for (int i = lane; i < 64 * (KL + 1); i += 64) acc[i] = 0ull;
+        wave_sync();
+    }
     Ctr ct;
     ct.nodes = ct.work = 0;
     int *cursor = a.next + MODE;

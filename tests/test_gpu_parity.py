@@ -284,6 +284,58 @@ def test_peel_order_one_big_frontier(ctx, name, g):
     assert np.array_equal(sub, pe.sub)
 
 
+# ------------------------------------------------------------- lane tier
+
+LANE_GRAPHS = [
+    ("gnp 300 0.1", lambda: gg.gnp(300, 0.1, 95)),
+    ("planted 400", lambda: gg.plant_cliques(gg.gnp(400, 0.05, 96), [14, 9, 8, 8], 97)),
+    ("chung-lu 3000", lambda: gg.chung_lu(3000, 16, 2.2, 300, 98)),
+    ("multipartite", lambda: gg.complete_multipartite([2] * 12)),
+]
+
+
+def _local_run(ctx, g, lane_max, budget=2048):
+    P.pv_set_lane_max(ctx, lane_max)
+    P.pv_set_dfs_budget(ctx, budget)
+    try:
+        with Loaded(ctx, g) as h:
+            out, ovf, st = P.pv_count_local(h, P.PV_VERTEX, 3, 10)
+            tr = P.pv_count_global(h, k_max=5)
+    finally:
+        P.pv_set_lane_max(ctx, 8)
+        P.pv_set_dfs_budget(ctx, 2048)
+    return out, ovf, st, tr
+
+
+@pytest.mark.parametrize("lane_max", [3, 8])
+@pytest.mark.parametrize("name,make", LANE_GRAPHS)
+def test_lane_tier_keeps_tree_and_counts(ctx, name, make, lane_max):
+    # subtrees of at most lane_max vertices walked one per lane: the same
+    # tree (node, leaf and work counts) and the same global and per-vertex
+    # counts, also on truncated trees (local counts for k <= 10 walk the tree
+    # truncated at 10 holds; there the oracle walks the rest of a truncated
+    # pivot chain node by node, so node counts are compared with the
+    # wave-only walk) and with depth-first splits between the batches
+    g = make()
+    _say(f"[parity] lane tier {name} lane_max={lane_max}")
+    P.pv_set_lane_max(ctx, lane_max)
+    try:
+        check_global(ctx, g, f"{name} lane_max={lane_max}")
+        check_global(ctx, g, f"{name} lane_max={lane_max}", kmax=5, check_order=False)
+    finally:
+        P.pv_set_lane_max(ctx, 8)
+    ref = O.count(g, vertex=(3, 10))
+    w_out, w_ovf, w_st, w_tr = _local_run(ctx, g, 0)
+    assert w_ovf == 0 and np.array_equal(w_out, ref.vertex)
+    for budget in (2048, 16):
+        out, ovf, st, tr = _local_run(ctx, g, lane_max, budget)
+        assert ovf == 0 and np.array_equal(out, ref.vertex), budget
+        for key in ("nodes", "leaves", "work"):
+            assert st[key] == w_st[key], (key, budget, st[key], w_st[key])
+            assert tr.stats[key] == w_tr.stats[key], (key, budget)
+        assert tr.counts == w_tr.counts
+
+
 # ---------------------------------------------- forced depth-first splits
 
 SPLITS = [(32, 16), (8, 16), (64, 24), (64, 1 << 20)]
