@@ -30,7 +30,7 @@ struct PeelCtl {
 #define PV_PEEL_MAX_BLOCKS 1024
 // the peel's last PV_SOLO_MAX vertices are finished by one workgroup
 // (local ids and remaining degrees below 2^16)
-#define PV_SOLO_MAX 32768
+#define PV_SOLO_MAX 16384
 
 struct PeelArgs {
     int n;
@@ -44,7 +44,6 @@ struct PeelArgs {
     int *lrp;            // [PV_SOLO_MAX + 1] local CSR rows
     int *lcol;           // [nnz] local CSR columns
     int *bcnt;           // [blocks] per-block counts
-    int *lfr;            // [2 * PV_SOLO_MAX] frontiers of local ids in the solo phase
 };
 
 // Largest out-degree handled by the compact (register) tier.  Roots with

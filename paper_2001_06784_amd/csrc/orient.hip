@@ -131,8 +131,6 @@ __device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
 // edges a wave takes per step of a frontier vertex's row (4 per lane, so
 // that four independent load/atomic chains are in flight)
 #define PEEL_UNROLL 4
-// frontier entries of the one-block phase kept in LDS (16-bit local ids)
-#define SOLO_LDS_F 16384
 
 // exclusive prefix sum over the block (blockDim.x == PV_PEEL_THREADS);
 // returns the block total in *total
@@ -342,12 +340,10 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     // LDS holds the remaining degrees as 16-bit halves of 32-bit words (a
     // degree only counts neighbours still in U and is decremented at most
     // once per neighbour, so a half never borrows from the other), liveness
-    // as a bitmask, and the first SOLO_LDS_F entries of the two frontiers of
-    // local ids; entries past those go to global memory (pa.lfr, two halves
-    // of PV_SOLO_MAX).
+    // as a bitmask, and the two frontiers as 16-bit local ids.
     __shared__ unsigned s_deg2[PV_SOLO_MAX / 2];
     __shared__ unsigned s_alive[PV_SOLO_MAX / 32];
-    __shared__ unsigned short s_F[2][SOLO_LDS_F];
+    __shared__ unsigned short s_F[2][PV_SOLO_MAX];
     __shared__ int s_cnt, s_min;
     const int *__restrict__ lrp = pa.lrp;
     const int *__restrict__ lcol = pa.lcol;
@@ -366,12 +362,8 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     __syncthreads();
     auto alive = [&](int i) -> bool { return (s_alive[i >> 5] >> (i & 31)) & 1u; };
     auto degof = [&](int i) -> int { return (int)((s_deg2[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu); };
-    int *lf[2] = {pa.lfr, pa.lfr + PV_SOLO_MAX};
-    auto fput = [&](int c, int j, int x) {
-        if (j < SOLO_LDS_F) s_F[c][j] = (unsigned short)x;
-        else lf[c][j] = x;
-    };
-    auto fget = [&](int c, int j) -> int { return j < SOLO_LDS_F ? (int)s_F[c][j] : lf[c][j]; };
+    auto fput = [&](int c, int j, int x) { s_F[c][j] = (unsigned short)x; };
+    auto fget = [&](int c, int j) -> int { return (int)s_F[c][j]; };
     int cur = 0;
     if (nF > 0) {
         const int *F = (r & 1) ? pa.fb : pa.fa;
@@ -749,13 +741,17 @@ hipError_t pv_launch_validate(int n, const int *rp, const int *col, int *d_err, 
 }
 
 hipError_t pv_launch_peel(const DevInfo &dev, const PeelArgs &pa, hipStream_t s) {
-    // one block per CU (co-resident), a single block when the graph already
-    // fits the solo phase
+    // co-resident blocks on a quarter of the CUs (8 per XCD on MI355X): a
+    // grid barrier costs about 12 us with a block on every CU and under 5 us
+    // with 64, and the sub-rounds' work does not need the wider grid (on a
+    // 1M-vertex power-law graph the whole peel takes 15 ms instead of 21);
+    // a single block when the graph already fits the solo phase
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, peel_kernel, PV_PEEL_THREADS, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    const int blocks = (pa.n <= PV_SOLO_MAX) ? 1 : std::min(dev.num_cu, PV_PEEL_MAX_BLOCKS);
+    const int blocks =
+        (pa.n <= PV_SOLO_MAX) ? 1 : std::max(1, std::min(dev.num_cu / 4, PV_PEEL_MAX_BLOCKS));
     PeelArgs a = pa;
     void *args[] = {(void *)&a};
     return hipLaunchCooperativeKernel((const void *)peel_kernel, dim3(blocks), dim3(PV_PEEL_THREADS),
