@@ -729,12 +729,23 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.u_root = rq.vgraph ? c->ws.u_root.p : nullptr;
                 const long long units = (long long)n_mw + n_c + (level == 0 ? (long long)a.nheavy + a.nlight : 0);
                 if (units == 0) break;
-                *c->h_args = a;
-                HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 5 * sizeof(int), s));
-                HIPCHK(hipMemcpyAsync(c->d_args.p, c->h_args, sizeof(LevelArgs), hipMemcpyHostToDevice, s));
                 const int kli = variant_of(rq.kl, rq.lk);
                 const long long mode_units[3] = {(long long)n_mw + (level == 0 ? a.nheavy : 0), n_c,
                                                  level == 0 ? a.nlight : 0};
+                int mode_blocks[3];
+                for (int mode = 0; mode < 3; mode++) {
+                    const long long want = (mode_units[mode] + WAVES_PER_LAUNCH_BLOCK - 1) / WAVES_PER_LAUNCH_BLOCK;
+                    mode_blocks[mode] = std::max(1, (int)std::min<long long>(c->level_blocks[kli][mode], want));
+                    // claim chunks: about 16 claims per wave, at most 32 units
+                    // each; multi-word units are heavy, one at a time
+                    const long long waves = (long long)mode_blocks[mode] * WAVES_PER_LAUNCH_BLOCK;
+                    a.chunk[mode] = (mode == PV_UNITS_MW)
+                                        ? 1
+                                        : (int)std::max(1ll, std::min(32ll, mode_units[mode] / (waves * 16)));
+                }
+                *c->h_args = a;
+                HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 5 * sizeof(int), s));
+                HIPCHK(hipMemcpyAsync(c->d_args.p, c->h_args, sizeof(LevelArgs), hipMemcpyHostToDevice, s));
                 if (c->timing) HIPCHK(hipEventRecord(c->ev[3], s));
                 // the kinds of a level are independent (they only append to
                 // the next level's queues): kinds 1 and 2 run on the
@@ -744,10 +755,8 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                     if (mode_units[mode] == 0) continue;
                     hipStream_t ms = (mode == 0) ? s : c->aux[mode - 1];
                     if (ms != s) HIPCHK(hipStreamWaitEvent(ms, c->ev_fork, 0));
-                    const long long want = (mode_units[mode] + WAVES_PER_LAUNCH_BLOCK - 1) / WAVES_PER_LAUNCH_BLOCK;
-                    const int blocks = (int)std::min<long long>(c->level_blocks[kli][mode], want);
                     if (c->timing) HIPCHK(hipEventRecord(c->ev[8 + 2 * mode], ms));
-                    HIPCHK(pv_launch_level(c->d_args.p, rq.kl, rq.lk, mode, std::max(1, blocks), ms));
+                    HIPCHK(pv_launch_level(c->d_args.p, rq.kl, rq.lk, mode, mode_blocks[mode], ms));
                     if (c->timing) HIPCHK(hipEventRecord(c->ev[9 + 2 * mode], ms));
                     if (ms != s) {
                         HIPCHK(hipEventRecord(c->ev_join[mode], ms));
@@ -761,9 +770,15 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 io_fresh = true;
                 levels++;
                 if (c->timing) {
-                    ms_levels += elapsed(c, 3, 4);
+                    const float lv = elapsed(c, 3, 4);
+                    float km[3] = {0.f, 0.f, 0.f};
+                    ms_levels += lv;
                     for (int mode = 0; mode < 3; mode++)
-                        if (mode_units[mode]) ms_kind[mode] += elapsed(c, 8 + 2 * mode, 9 + 2 * mode);
+                        if (mode_units[mode]) ms_kind[mode] += (km[mode] = elapsed(c, 8 + 2 * mode, 9 + 2 * mode));
+                    if (c->debug)
+                        fprintf(stderr, "[pivoter] level %d: %.2f ms (multi-word %lld units %.2f ms, items %lld %.2f ms, "
+                                "light roots %lld %.2f ms)\n", level, lv, mode_units[0], km[0], mode_units[1], km[1],
+                                mode_units[2], km[2]);
                 }
                 if (c->debug)
                     fprintf(stderr, "[pivoter] attempt %d level %d: mw %d items %d universes %d prefix %d "

@@ -100,8 +100,10 @@ struct LevelArgs {
     int2 *u_pref;            // [cap] {offset, length} into pref pool (local only)
     int *u_n, u_cap;
     int *pref_pool, *pref_n, pref_cap;
-    // work cursors, one per unit kind
+    // work cursors, one per unit kind; a wave claims chunk[kind] units per
+    // atomic
     int *next;
+    int chunk[3];
     // outputs
     unsigned long long *hist;
     int hd;

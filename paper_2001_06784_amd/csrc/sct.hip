@@ -1341,6 +1341,38 @@ __device__ void gather_heavy(int hu, int v, int lane, const LevelArgs &a) {
 //                   gathered into registers (largest first)
 // Every wave takes units from the launch's own cursor until none is left.
 
+// Units of a kind are claimed `chunk` at a time, one atomic per chunk: a
+// single cursor taken by every wave one unit at a time serialises across the
+// XCDs (about 14 ns per claim, which bounded a launch over a million small
+// roots).  Chunks interleave: chunk c holds units c, c + nch, c + 2 nch, ...
+// of the first n0 units (nch chunks in all), so units that sit next to each
+// other in a queue (the pieces of one split subtree, roots of equal degree)
+// go to different waves.  The last 8 units per wave of the launch are
+// claimed one at a time, so waves finish together.  All values
+// wave-uniform; -1 when the kind's n units are gone.
+struct Claim {
+    int c = 0, left = 0;
+    __device__ __forceinline__ int next(int *cursor, int n, int chunk, int lane) {
+        const int waves = (int)(gridDim.x * (blockDim.x >> 6));
+        const int n0 = (chunk > 1) ? max(0, n - 8 * waves) : 0;
+        const int nch = (n0 + chunk - 1) / chunk;
+        if (left == 0) {
+            int b = 0;
+            if (lane == 0) b = atomicAdd(cursor, 1);
+            c = bcast0(__shfl(b, 0, 64));
+            if (c >= nch) {
+                const int idx = n0 + (c - nch);
+                return idx < n ? idx : -1;
+            }
+            left = (n0 - 1 - c) / nch + 1;
+        }
+        left--;
+        const int idx = c;
+        c += nch;
+        return idx;
+    }
+};
+
 template <int KL, int MODE, int LK>
 __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const LevelArgs *__restrict__ pa) {
     constexpr bool EDGE = LK == PV_LK_EDGE;
@@ -1365,15 +1397,15 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
     Ctr ct;
     ct.nodes = ct.work = 0;
     int *cursor = a.next + MODE;
+    const int chunk = max(1, uniformi(a.chunk[MODE]));
+    Claim claim;
 
     if constexpr (MODE == PV_UNITS_MW) {
         __shared__ int s_memb[WAVES_PER_BLOCK][64];
         const int n0 = a.n_mw_in, n1 = n0 + (a.level == 0 ? a.nheavy : 0);
         for (;;) {
-            int idx = 0;
-            if (lane == 0) idx = atomicAdd(cursor, 1);
-            idx = bcast0(__shfl(idx, 0, 64));
-            if (idx >= n1) break;
+            const int idx = claim.next(cursor, n1, chunk, lane);
+            if (idx < 0) break;
             int hu, h = 1, p = 0;
             uint64_t Sw = 0, Hw = 0, Pw = 0;
             if (idx < n0) {
@@ -1410,10 +1442,8 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
     } else if constexpr (MODE == PV_UNITS_ITEMS) {
         const int n = a.n_c_in;
         for (;;) {
-            int idx = 0;
-            if (lane == 0) idx = atomicAdd(cursor, 1);
-            idx = bcast0(__shfl(idx, 0, 64));
-            if (idx >= n) break;
+            const int idx = claim.next(cursor, n, chunk, lane);
+            if (idx < 0) break;
             const CItem it = a.c_in[idx];
             const uint32_t uw = uniform32(it.uni);
             const int u = (int)(uw & 0x7fffffffu);
@@ -1441,10 +1471,8 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
         int *etab_w = EDGE ? a.weid + (long long)(blockIdx.x * WAVES_PER_BLOCK + wv) * 4096 : nullptr;
         if (EDGE) vs.set_table(etab_w);
         for (;;) {
-            int idx = 0;
-            if (lane == 0) idx = atomicAdd(cursor, 1);
-            idx = bcast0(__shfl(idx, 0, 64));
-            if (idx >= n) break;
+            const int idx = claim.next(cursor, n, chunk, lane);
+            if (idx < 0) break;
             const int v = a.order[a.light_base + idx];
             gs.set_vertex(v);
             int d, gid;
