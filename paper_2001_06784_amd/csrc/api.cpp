@@ -737,11 +737,15 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                     const long long want = (mode_units[mode] + WAVES_PER_LAUNCH_BLOCK - 1) / WAVES_PER_LAUNCH_BLOCK;
                     mode_blocks[mode] = std::max(1, (int)std::min<long long>(c->level_blocks[kli][mode], want));
                     // claim chunks: about 16 claims per wave, at most 32 units
-                    // each; multi-word units are heavy, one at a time
+                    // each, interleaved over all but the last 8 units per
+                    // wave; multi-word units are heavy, one at a time
                     const long long waves = (long long)mode_blocks[mode] * WAVES_PER_LAUNCH_BLOCK;
-                    a.chunk[mode] = (mode == PV_UNITS_MW)
-                                        ? 1
-                                        : (int)std::max(1ll, std::min(32ll, mode_units[mode] / (waves * 16)));
+                    const long long chunk = (mode == PV_UNITS_MW)
+                                                ? 1
+                                                : std::max(1ll, std::min(32ll, mode_units[mode] / (waves * 16)));
+                    const long long n0 = (chunk > 1) ? std::max(0ll, mode_units[mode] - 8 * waves) : 0;
+                    a.n0[mode] = (int)n0;
+                    a.nch[mode] = (int)((n0 + chunk - 1) / chunk);
                 }
                 *c->h_args = a;
                 HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 5 * sizeof(int), s));

@@ -100,10 +100,11 @@ struct LevelArgs {
     int2 *u_pref;            // [cap] {offset, length} into pref pool (local only)
     int *u_n, u_cap;
     int *pref_pool, *pref_n, pref_cap;
-    // work cursors, one per unit kind; a wave claims chunk[kind] units per
-    // atomic
+    // work cursors, one per unit kind.  A claim takes chunk c < nch[kind]:
+    // units c, c + nch, c + 2 nch, ... below n0[kind]; claims past nch take
+    // one unit each from n0 on
     int *next;
-    int chunk[3];
+    int n0[3], nch[3];
     // outputs
     unsigned long long *hist;
     int hd;

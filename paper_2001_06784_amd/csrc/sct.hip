@@ -201,21 +201,14 @@ struct VertexSink {
         }
     }
 
-    // lane tier: sums av (toward hold vertices) and bv (toward pivot
-    // vertices) owed by one queued node's leaves to the vertices above it,
-    // whose members are H, P; lanes 62/63 as in leaf()
-    __device__ __forceinline__ void add_sums(const uint64_t *av, const uint64_t *bv, uint64_t H, uint64_t P,
-                                             int lane) {
-        const bool inH = ((H >> lane) & 1) || lane == 62;
-        const bool inP = ((P >> lane) & 1) || lane == 63;
-        uint64_t mH = inH ? ~0ull : 0ull;
-        uint64_t mP = (!inH && inP) ? ~0ull : 0ull;
-        asm volatile("" : "+v"(mH), "+v"(mP));
+    // lane tier: add x to slot kk
+    __device__ __forceinline__ void add_val(int kk, uint64_t x) {
 #pragma unroll
-        for (int kk = 0; kk < KL; kk++) {
-            const uint64_t v = (av[kk] & mH) | (bv[kk] & mP);
-            lo[kk] += v;
-            if (WIDE) hi[kk] += (lo[kk] < v) ? 1ull : 0ull;
+        for (int i = 0; i < KL; i++) {
+            if (i == kk) {
+                lo[i] += x;
+                if (WIDE) hi[i] += (lo[i] < x) ? 1ull : 0ull;
+            }
         }
     }
 
@@ -576,19 +569,39 @@ __device__ __forceinline__ lds_u64 *lane_acc() {
     return (lds_u64 *)s_lacc[threadIdx.x >> 6];
 }
 
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, unsigned d) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// inclusive prefix sum of a 64-bit value over the wave's lanes
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x, int lane) {
+#pragma unroll
+    for (unsigned d = 1; d < 64; d <<= 1) {
+        const uint64_t y = shfl_up64(x, d);
+        if (lane >= (int)d) x += y;
+    }
+    return x;
+}
+
 // Walk the queued subtrees: lane i < qn holds node qS (a set of at most
 // PV_LANE_MAX members of the universe whose row for member `lane` is A) with
-// path totals h = qhp & 0xFFFF, p = qhp >> 16 and, for per-vertex counts,
-// the path's hold and pivot members qH, qP.  All lanes take part.
+// path totals h = qhp & 0xFFFF, p = qhp >> 16.  For per-vertex counts, bit i
+// of a member lane's qmH (qmP) says that the member was a hold (pivot)
+// vertex of the i-th queued node's path; lanes 62 and 63 stand for the hold
+// and pivot vertices above the universe, as in VertexSink.  All lanes take
+// part.
 //
 // Per-vertex counts (Alg. 2): a leaf owes C(p, k-h) to every hold vertex of
 // its path and C(p-1, k-h-1) to every pivot vertex.  Members taken inside
 // the lane's subtree get theirs at the leaf through LDS atomics on their
-// slots; for the vertices above the queued node every leaf owes the same,
-// so the lane sums its leaves' binomials and the wave adds each lane's sums
-// to those vertices once (member lanes and the lanes 62/63 of VertexSink).
+// slots.  For the vertices above a queued node every leaf of its subtree
+// owes the same, so the lane sums its leaves' binomials; a member is on the
+// path for runs of consecutive queued nodes, and a run [a, b) owes the
+// difference of two inclusive prefix sums of those sums over the lanes.
 template <int KL, bool LOC, class VS>
-__device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qH, uint64_t qP, uint32_t qhp,
+__device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH, uint64_t qmP, uint32_t qhp,
                                           int qn, int lane, int hlim, GlobalSink &gs, VS &vs,
                                           uint32_t &nodes, uint32_t &work, uint32_t &nleaves) {
     constexpr int NK = LOC ? KL : 1;
@@ -715,23 +728,47 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qH, 
     work += wave_add_u32(ww);
     nleaves += wave_add_u32(nl);
     if constexpr (LOC) {
-        // the vertices above each queued node: its lane's sums, once
-        bool nz = false;
-#pragma unroll
-        for (int kk = 0; kk < NK; kk++) nz = nz || (sH[kk] | sP[kk]) != 0;
-        for (uint64_t bl = ballot64(nz); bl; bl &= bl - 1ull) {
-            const int L = __builtin_ctzll(bl);
-            uint64_t aH[NK], aP[NK];
-#pragma unroll
-            for (int kk = 0; kk < NK; kk++) {
-                aH[kk] = readlane64(sH[kk], L);
-                aP[kk] = readlane64(sP[kk], L);
-            }
-            vs.add_sums(aH, aP, readlane64(qH, L), readlane64(qP, L), lane);
-        }
         // members taken inside the subtrees: their LDS slots (then cleared)
         wave_sync();
         vs.add_slots(acc + lane * (KL + 1), lane);
+        wave_sync();
+        // the vertices above the queued nodes.  The slot region (64 x
+        // (KL + 1) entries, free again) holds rows [v][lane] of 8 values
+        // (4 k-slots x hold / pivot) and a ninth row for the lanes' inclusive
+        // prefix sums; per value, a member adds for each of its runs [a, b)
+        // entry b-1 minus entry a-1 and leaves its total in the value's row
+        static_assert(KL + 1 >= 9, "slot region too small for the distribution");
+        lds_u64 *psum = acc + 8 * 64;
+#pragma unroll
+        for (int k0 = 0; k0 < NK; k0 += 4) {
+#pragma unroll
+            for (int v = 0; v < 8; v++) {
+                const int kk = k0 + (v >> 1);
+                acc[v * 64 + lane] = (kk < NK) ? ((v & 1) ? sP[kk] : sH[kk]) : 0ull;
+            }
+#pragma unroll 1
+            for (int v = 0; v < 8; v++) {
+                psum[lane] = wave_incl_scan_u64(acc[v * 64 + lane], lane);
+                wave_sync();
+                uint64_t t = 0;
+                for (uint64_t M = (v & 1) ? qmP : qmH; M;) {
+                    const int a0 = __builtin_ctzll(M);
+                    const uint64_t Z = ~M & (~0ull << a0);
+                    const int b0 = Z ? __builtin_ctzll(Z) : 64;
+                    M = (b0 == 64) ? 0ull : (M & (~0ull << b0));
+                    t += psum[b0 - 1] - (a0 > 0 ? psum[a0 - 1] : 0ull);
+                }
+                wave_sync();
+                acc[v * 64 + lane] = t;
+            }
+#pragma unroll
+            for (int v = 0; v < 8; v++) {
+                const int kk = k0 + (v >> 1);
+                if (kk < NK) vs.add_val(kk, acc[v * 64 + lane]);
+            }
+        }
+        // the region starts the next batch at zero
+        for (int i = lane; i < 9 * 64; i += 64) acc[i] = 0ull;
         wave_sync();
     }
 }
@@ -778,7 +815,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     // are too small to fill a batch keeps its registers for occupancy).
     constexpr bool LANE = LT && (!LOCAL || (LK == PV_LK_VERTEX64 && KL == 8));
     const int lmax = LANE ? uniformi(a.lane_max) : 0;
-    uint64_t qS = 0, qH = 0, qP = 0;
+    uint64_t qS = 0, qmH = 0, qmP = 0;
     uint32_t qhp = 0;
     int qn = 0;
     bool visit = true;
@@ -800,15 +837,20 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
             if (visit && S != 0 && h < hlim && __popcll(S) <= lmax) {
                 if (lane == qn) {
                     qS = S;
-                    if (LOCAL) {
-                        qH = H;
-                        qP = P;
-                    }
                     qhp = (uint32_t)h | ((uint32_t)p << 16);
                 }
+                if (LOCAL) {
+                    // this member's role on the queued node's path (lanes
+                    // 62/63: the vertices above the universe)
+                    const bool inH = ((H >> lane) & 1) || lane == 62;
+                    const bool inP = !inH && (((P >> lane) & 1) || lane == 63);
+                    qmH |= (uint64_t)inH << qn;
+                    qmP |= (uint64_t)inP << qn;
+                }
                 if (++qn == 64) {
-                    lane_walk<KL, LOCAL>(A, qS, qH, qP, qhp, qn, lane, hlim, gs, vs, nodes, work, nleaves);
+                    lane_walk<KL, LOCAL>(A, qS, qmH, qmP, qhp, qn, lane, hlim, gs, vs, nodes, work, nleaves);
                     qn = 0;
+                    qmH = qmP = 0;
                 }
                 queued = true;
             }
@@ -935,7 +977,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
         }
     }
     if constexpr (LANE) {
-        if (qn > 0) lane_walk<KL, LOCAL>(A, qS, qH, qP, qhp, qn, lane, hlim, gs, vs, nodes, work, nleaves);
+        if (qn > 0) lane_walk<KL, LOCAL>(A, qS, qmH, qmP, qhp, qn, lane, hlim, gs, vs, nodes, work, nleaves);
     }
     if (LOCAL) vs.leave(H | P, H, P, lane, gid);
     ct.nodes += nodes;
@@ -1342,40 +1384,37 @@ __device__ void gather_heavy(int hu, int v, int lane, const LevelArgs &a) {
 //                   gathered into registers (largest first)
 // Every wave takes units from the launch's own cursor until none is left.
 
-// Units of a kind are claimed `chunk` at a time, one atomic per chunk: a
+// Units of a kind are claimed a chunk at a time, one atomic per chunk: a
 // single cursor taken by every wave one unit at a time serialises across the
 // XCDs (about 14 ns per claim, which bounded a launch over a million small
 // roots).  Chunks interleave: chunk c holds units c, c + nch, c + 2 nch, ...
-// of the first n0 units (nch chunks in all), so units that sit next to each
-// other in a queue (the pieces of one split subtree, roots of equal degree)
-// go to different waves.  The last 8 units per wave of the launch are
-// claimed one at a time, so waves finish together.  All values
+// of the first n0 units, so units that sit next to each other in a queue
+// (the pieces of one split subtree, roots of equal degree) go to different
+// waves; the units from n0 on (8 per wave of the launch) are claimed one at
+// a time, so waves finish together.  The host picks n0 and nch.  All values
 // wave-uniform; -1 when the kind's n units are gone.
 struct Claim {
-    int c = 0, left = 0;
-    __device__ __forceinline__ int next(int *cursor, int n, int chunk, int lane) {
-        const int waves = (int)(gridDim.x * (blockDim.x >> 6));
-        const int n0 = (chunk > 1) ? max(0, n - 8 * waves) : 0;
-        const int nch = (n0 + chunk - 1) / chunk;
-        if (left == 0) {
-            int b = 0;
-            if (lane == 0) b = atomicAdd(cursor, 1);
-            c = bcast0(__shfl(b, 0, 64));
-            if (c >= nch) {
-                const int idx = n0 + (c - nch);
-                return idx < n ? idx : -1;
-            }
-            left = (n0 - 1 - c) / nch + 1;
+    int idx = -1;
+    __device__ __forceinline__ int next(int *cursor, int n, int n0, int nch, int lane) {
+        if (idx >= 0) {
+            idx += nch;
+            if (idx < n0) return idx;
         }
-        left--;
-        const int idx = c;
-        c += nch;
-        return idx;
+        int b = 0;
+        if (lane == 0) b = atomicAdd(cursor, 1);
+        const int c = bcast0(__shfl(b, 0, 64));
+        if (c < nch) {
+            idx = c;
+            return idx;
+        }
+        idx = -1;
+        const int t = n0 + (c - nch);
+        return t < n ? t : -1;
     }
 };
 
 template <int KL, int MODE, int LK>
-__global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const LevelArgs *__restrict__ pa) {
+__global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, 3) sct_level_kernel(const LevelArgs *__restrict__ pa) {
     constexpr bool EDGE = LK == PV_LK_EDGE;
     constexpr bool LOCAL = KL > 0;
     const LevelArgs &a = *pa;
@@ -1398,14 +1437,14 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
     Ctr ct;
     ct.nodes = ct.work = 0;
     int *cursor = a.next + MODE;
-    const int chunk = max(1, uniformi(a.chunk[MODE]));
+    const int claim_n0 = uniformi(a.n0[MODE]), claim_nch = uniformi(a.nch[MODE]);
     Claim claim;
 
     if constexpr (MODE == PV_UNITS_MW) {
         __shared__ int s_memb[WAVES_PER_BLOCK][64];
         const int n0 = a.n_mw_in, n1 = n0 + (a.level == 0 ? a.nheavy : 0);
         for (;;) {
-            const int idx = claim.next(cursor, n1, chunk, lane);
+            const int idx = claim.next(cursor, n1, claim_n0, claim_nch, lane);
             if (idx < 0) break;
             int hu, h = 1, p = 0;
             uint64_t Sw = 0, Hw = 0, Pw = 0;
@@ -1443,7 +1482,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
     } else if constexpr (MODE == PV_UNITS_ITEMS) {
         const int n = a.n_c_in;
         for (;;) {
-            const int idx = claim.next(cursor, n, chunk, lane);
+            const int idx = claim.next(cursor, n, claim_n0, claim_nch, lane);
             if (idx < 0) break;
             const CItem it = a.c_in[idx];
             const uint32_t uw = uniform32(it.uni);
@@ -1472,7 +1511,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK) sct_level_kernel(const L
         int *etab_w = EDGE ? a.weid + (long long)(blockIdx.x * WAVES_PER_BLOCK + wv) * 4096 : nullptr;
         if (EDGE) vs.set_table(etab_w);
         for (;;) {
-            const int idx = claim.next(cursor, n, chunk, lane);
+            const int idx = claim.next(cursor, n, claim_n0, claim_nch, lane);
             if (idx < 0) break;
             const int v = a.order[a.light_base + idx];
             gs.set_vertex(v);
