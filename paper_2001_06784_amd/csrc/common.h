@@ -125,6 +125,25 @@ __device__ __forceinline__ bool atomic_add_u128(uint64_t *out, uint64_t lo, uint
     return ovf;
 }
 
+// The same add in two halves, so that several can be in flight: first the
+// low limb (returns the limb's old value), later the carry and high limb.
+__device__ __forceinline__ uint64_t atomic_add_u128_lo(uint64_t *out, uint64_t lo) {
+    return lo ? (uint64_t)atomicAdd((unsigned long long *)out, (unsigned long long)lo) : 0ull;
+}
+
+__device__ __forceinline__ bool atomic_add_u128_hi(uint64_t *out, uint64_t lo, uint64_t old, uint64_t hi) {
+    bool ovf = false;
+    if (lo && old + lo < old) {
+        hi += 1;
+        if (hi == 0) ovf = true;
+    }
+    if (hi) {
+        const uint64_t o = atomicAdd((unsigned long long *)(out + 1), (unsigned long long)hi);
+        if (o + hi < o) ovf = true;
+    }
+    return ovf;
+}
+
 // Make this wave's LDS / memory writes visible to its other lanes and keep
 // the compiler from moving accesses across the point.
 __device__ __forceinline__ void wave_sync() {

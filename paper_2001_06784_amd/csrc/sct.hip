@@ -230,10 +230,19 @@ struct VertexSink {
     __device__ void flush(int lane, int nm, int gid, int root, int2, int uni, const LevelArgs &) {
         bool ovf = false;
         if (lane < nm) {
+            // the low-limb adds of all slots first, so that their latencies
+            // overlap; then the (rare) carries and the high limbs
+            uint64_t old[KL > 0 ? KL : 1];
 #pragma unroll
             for (int kk = 0; kk < KL; kk++)
-                if (kk < K && (lo[kk] | hiw(kk)))
-                    ovf |= atomic_add_u128(vout + 2 * ((long long)gid * K + kk), lo[kk], hiw(kk));
+                old[kk] = (kk < K) ? atomic_add_u128_lo(vout + 2 * ((long long)gid * K + kk), lo[kk]) : 0ull;
+            // the returned limbs are first needed here (keeps the compiler
+            // from waiting for each atomic inside its own branch)
+#pragma unroll
+            for (int kk = 0; kk < KL; kk++) asm volatile("" : "+v"(old[kk]));
+#pragma unroll
+            for (int kk = 0; kk < KL; kk++)
+                if (kk < K) ovf |= atomic_add_u128_hi(vout + 2 * ((long long)gid * K + kk), lo[kk], old[kk], hiw(kk));
         }
         root = uniformi(root);
         uni = uniformi(uni);
@@ -258,8 +267,10 @@ struct VertexSink {
                     if (thl | thh) ovf |= atomic_add_u128(vout + 2 * ((long long)root * K + lane), thl, thh);
                 } else {
                     uint64_t *ut = utot + 2 * ((long long)uni * 2 * K + lane);
-                    if (thl | thh) ovf |= atomic_add_u128(ut, thl, thh);
-                    if (tpl | tph) ovf |= atomic_add_u128(ut + 2 * K, tpl, tph);
+                    uint64_t oh = atomic_add_u128_lo(ut, thl), op = atomic_add_u128_lo(ut + 2 * K, tpl);
+                    asm volatile("" : "+v"(oh), "+v"(op));
+                    ovf |= atomic_add_u128_hi(ut, thl, oh, thh);
+                    ovf |= atomic_add_u128_hi(ut + 2 * K, tpl, op, tph);
                 }
             }
         }
@@ -569,22 +580,6 @@ __device__ __forceinline__ lds_u64 *lane_acc() {
     return (lds_u64 *)s_lacc[threadIdx.x >> 6];
 }
 
-__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, unsigned d) {
-    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
-    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// inclusive prefix sum of a 64-bit value over the wave's lanes
-__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x, int lane) {
-#pragma unroll
-    for (unsigned d = 1; d < 64; d <<= 1) {
-        const uint64_t y = shfl_up64(x, d);
-        if (lane >= (int)d) x += y;
-    }
-    return x;
-}
-
 // Walk the queued subtrees: lane i < qn holds node qS (a set of at most
 // PV_LANE_MAX members of the universe whose row for member `lane` is A) with
 // path totals h = qhp & 0xFFFF, p = qhp >> 16.  For per-vertex counts, bit i
@@ -734,11 +729,11 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
         wave_sync();
         // the vertices above the queued nodes.  The slot region (64 x
         // (KL + 1) entries, free again) holds rows [v][lane] of 8 values
-        // (4 k-slots x hold / pivot) and a ninth row for the lanes' inclusive
-        // prefix sums; per value, a member adds for each of its runs [a, b)
-        // entry b-1 minus entry a-1 and leaves its total in the value's row
-        static_assert(KL + 1 >= 9, "slot region too small for the distribution");
-        lds_u64 *psum = acc + 8 * 64;
+        // (4 k-slots x hold / pivot); lane v < 8 turns row v into its
+        // inclusive prefix sums over the first qn lanes, and a member adds,
+        // for each of its runs [a, b), entry b-1 minus entry a-1
+        static_assert(KL + 1 >= 8, "slot region too small for the distribution");
+        const int qn8 = (qn + 7) & ~7;
 #pragma unroll
         for (int k0 = 0; k0 < NK; k0 += 4) {
 #pragma unroll
@@ -746,29 +741,47 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
                 const int kk = k0 + (v >> 1);
                 acc[v * 64 + lane] = (kk < NK) ? ((v & 1) ? sP[kk] : sH[kk]) : 0ull;
             }
+            wave_sync();
+            if (lane < 8) {
+                lds_u64 *row = acc + lane * 64;
+                uint64_t run = 0;
 #pragma unroll 1
-            for (int v = 0; v < 8; v++) {
-                psum[lane] = wave_incl_scan_u64(acc[v * 64 + lane], lane);
-                wave_sync();
-                uint64_t t = 0;
-                for (uint64_t M = (v & 1) ? qmP : qmH; M;) {
+                for (int L0 = 0; L0 < qn8; L0 += 8) {
+                    uint64_t x[8];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) x[i] = row[L0 + i];
+#pragma unroll
+                    for (int i = 0; i < 8; i++) {
+                        run += x[i];
+                        row[L0 + i] = run;
+                    }
+                }
+            }
+            wave_sync();
+            uint64_t add[8];
+#pragma unroll
+            for (int v = 0; v < 8; v++) add[v] = 0;
+#pragma unroll
+            for (int role = 0; role < 2; role++) {
+                for (uint64_t M = role ? qmP : qmH; M;) {
                     const int a0 = __builtin_ctzll(M);
                     const uint64_t Z = ~M & (~0ull << a0);
                     const int b0 = Z ? __builtin_ctzll(Z) : 64;
                     M = (b0 == 64) ? 0ull : (M & (~0ull << b0));
-                    t += psum[b0 - 1] - (a0 > 0 ? psum[a0 - 1] : 0ull);
+#pragma unroll
+                    for (int v = role; v < 8; v += 2)
+                        add[v] += acc[v * 64 + b0 - 1] - (a0 > 0 ? acc[v * 64 + a0 - 1] : 0ull);
                 }
-                wave_sync();
-                acc[v * 64 + lane] = t;
             }
 #pragma unroll
             for (int v = 0; v < 8; v++) {
                 const int kk = k0 + (v >> 1);
-                if (kk < NK) vs.add_val(kk, acc[v * 64 + lane]);
+                if (kk < NK) vs.add_val(kk, add[v]);
             }
+            wave_sync();
         }
         // the region starts the next batch at zero
-        for (int i = lane; i < 9 * 64; i += 64) acc[i] = 0ull;
+        for (int i = lane; i < 8 * 64; i += 64) acc[i] = 0ull;
         wave_sync();
     }
 }
