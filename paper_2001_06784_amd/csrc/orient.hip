@@ -131,6 +131,11 @@ __device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
 // edges a wave takes per step of a frontier vertex's row (4 per lane, so
 // that four independent load/atomic chains are in flight)
 #define PEEL_UNROLL 4
+// frontier rows of at most this many entries are walked one per lane
+#define PEEL_LANE_ROW 32
+// joins a block gathers in LDS per sub-round before the rest go straight to
+// the next frontier
+#define PEEL_JOIN_LDS 4096
 
 // exclusive prefix sum over the block (blockDim.x == PV_PEEL_THREADS);
 // returns the block total in *total
@@ -177,6 +182,8 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     if (!grid_barrier(ctl, nb)) return;
 
     // ---------------------------------------------------- grid-wide phase
+    __shared__ int s_join[PEEL_JOIN_LDS];
+    __shared__ int s_nj, s_jbase;
     int removed = 0, r = 0, k = 0, nF = 0, alpha = 0;
     while (n - removed > PV_SOLO_MAX) {
         if (nF == 0) {
@@ -212,35 +219,89 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         // remove the frontier: decrement the degrees of remaining neighbours;
         // a neighbour taken from k+1 to k joins the next sub-round
         int *ncnt = &ctl->cnt[(r + 1) % 3];
-        for (int i = wid; i < nF; i += nw) {
-            const int v = F[i];
-            const int e0 = rp[v], e1 = rp[v + 1];
-            for (int eb = e0; eb < e1; eb += 64 * PEEL_UNROLL) {
+        // joins of this sub-round are gathered per block in LDS and moved to
+        // the next frontier with one global atomic per block: a single
+        // counter taken by every wave serialises across the XCDs
+        if (threadIdx.x == 0) s_nj = 0;
+        __syncthreads();
+        // one decrement per remaining neighbour; a neighbour taken from k+1
+        // to k joins the next sub-round (appended, one atomic per wave)
+        const auto visit = [&](const int (&u)[PEEL_UNROLL], bool (&live)[PEEL_UNROLL]) {
+#pragma unroll
+            for (int q = 0; q < PEEL_UNROLL; q++)
+                live[q] = live[q] &&
+                          __hip_atomic_load(&sub[u[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0;
+            int old[PEEL_UNROLL];
+#pragma unroll
+            for (int q = 0; q < PEEL_UNROLL; q++) old[q] = live[q] ? atomicSub(&deg[u[q]], 1) : 0;
+#pragma unroll
+            for (int q = 0; q < PEEL_UNROLL; q++) {
+                const bool join = live[q] && old[q] == k + 1;
+                if (join) sub[u[q]] = r + 1;
+                // the block's LDS list first; past its end, the frontier
+                const int slot = wave_slot(join, &s_nj);
+                if (join) {
+                    if (slot < PEEL_JOIN_LDS) s_join[slot] = u[q];
+                    else Fn[atomicAdd(ncnt, 1)] = u[q];
+                }
+            }
+        };
+        // a row walked by the whole wave, 64 * PEEL_UNROLL entries at a time
+        const auto wave_row = [&](int w0, int w1) {
+            for (int eb = w0; eb < w1; eb += 64 * PEEL_UNROLL) {
                 int u[PEEL_UNROLL];
                 bool live[PEEL_UNROLL];
 #pragma unroll
                 for (int q = 0; q < PEEL_UNROLL; q++) {
                     const int e = eb + q * 64 + lane;
-                    live[q] = e < e1;
-                    u[q] = col[live[q] ? e : e0];
+                    live[q] = e < w1;
+                    u[q] = col[live[q] ? e : w0];
                 }
+                visit(u, live);
+            }
+        };
+        if (nF >= nw * 8) {
+            // a large frontier (the first sub-rounds of the low levels): a
+            // wave takes 64 vertices at a time, vertex i0 + lane * nw + wid
+            // in lane `lane`; rows of at most PEEL_LANE_ROW entries are
+            // walked one per lane, longer ones by the whole wave
+            for (int i0 = 0; i0 < nF; i0 += nw * 64) {
+                const int i = i0 + lane * nw + wid;
+                int v = 0, e0 = 0, e1 = 0;
+                if (i < nF) {
+                    v = F[i];
+                    e0 = rp[v];
+                    e1 = rp[v + 1];
+                }
+                const bool wide = i < nF && e1 - e0 > PEEL_LANE_ROW;
+                const int end = (i < nF && !wide) ? e1 : 0;
+                for (int e = (i < nF && !wide) ? e0 : 0; ballot64(e < end); e += PEEL_UNROLL) {
+                    int u[PEEL_UNROLL];
+                    bool live[PEEL_UNROLL];
 #pragma unroll
-                for (int q = 0; q < PEEL_UNROLL; q++)
-                    live[q] = live[q] &&
-                              __hip_atomic_load(&sub[u[q]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0;
-                int old[PEEL_UNROLL];
-#pragma unroll
-                for (int q = 0; q < PEEL_UNROLL; q++) old[q] = live[q] ? atomicSub(&deg[u[q]], 1) : 0;
-#pragma unroll
-                for (int q = 0; q < PEEL_UNROLL; q++) {
-                    const bool join = live[q] && old[q] == k + 1;
-                    const int slot = wave_slot(join, ncnt);
-                    if (join) {
-                        sub[u[q]] = r + 1;
-                        Fn[slot] = u[q];
+                    for (int q = 0; q < PEEL_UNROLL; q++) {
+                        live[q] = e + q < end;
+                        u[q] = live[q] ? col[e + q] : 0;
                     }
+                    visit(u, live);
+                }
+                for (uint64_t wm = ballot64(wide); wm; wm &= wm - 1ull) {
+                    const int vv = __shfl(v, __builtin_ctzll(wm), 64);
+                    wave_row(rp[vv], rp[vv + 1]);
                 }
             }
+        } else {
+            for (int i = wid; i < nF; i += nw) {
+                const int v = F[i];
+                wave_row(rp[v], rp[v + 1]);
+            }
+        }
+        __syncthreads();
+        {
+            const int nj = min(s_nj, PEEL_JOIN_LDS);
+            if (threadIdx.x == 0) s_jbase = nj ? atomicAdd(ncnt, nj) : 0;
+            __syncthreads();
+            for (int j = threadIdx.x; j < nj; j += blockDim.x) Fn[s_jbase + j] = s_join[j];
         }
         if (!grid_barrier(ctl, nb)) return;
         removed += nF;
