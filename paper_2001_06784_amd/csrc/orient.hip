@@ -182,30 +182,55 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     if (!grid_barrier(ctl, nb)) return;
 
     // ---------------------------------------------------- grid-wide phase
+    // vertices a block appends to a frontier are gathered in LDS and moved
+    // with one global atomic per block (a counter taken by every wave
+    // serialises across the XCDs); past the LDS list's end they go straight
+    // to the frontier.  s_nj is zero when a list starts (the caller's
+    // barrier orders the reset); list_flush ends with the block's copies
+    // done.
     __shared__ int s_join[PEEL_JOIN_LDS];
-    __shared__ int s_nj, s_jbase;
+    __shared__ int s_nj, s_jbase, s_kmin;
+    const auto list_add = [&](bool add, int x, int *Fo, int *cnt) {
+        const int slot = wave_slot(add, &s_nj);
+        if (add) {
+            if (slot < PEEL_JOIN_LDS) s_join[slot] = x;
+            else Fo[atomicAdd(cnt, 1)] = x;
+        }
+    };
+    const auto list_flush = [&](int *Fo, int *cnt) {
+        __syncthreads();
+        const int nj = min(s_nj, PEEL_JOIN_LDS);
+        if (threadIdx.x == 0) s_jbase = nj ? atomicAdd(cnt, nj) : 0;
+        __syncthreads();
+        for (int j = threadIdx.x; j < nj; j += blockDim.x) Fo[s_jbase + j] = s_join[j];
+    };
     int removed = 0, r = 0, k = 0, nF = 0, alpha = 0;
     while (n - removed > PV_SOLO_MAX) {
         if (nF == 0) {
-            // level change: k = smallest remaining degree
+            // level change: k = smallest remaining degree (a block minimum
+            // in LDS, one global atomic per block)
+            if (threadIdx.x == 0) s_kmin = 0x7fffffff;
+            __syncthreads();
             int mymin = 0x7fffffff;
             for (int v = tid; v < n; v += nth)
                 if (sub[v] < 0) mymin = min(mymin, deg[v]);
             mymin = wave_min_i32(mymin);
-            if (lane == 0 && mymin != 0x7fffffff) atomicMin(&ctl->minv[r & 1], mymin);
+            if (lane == 0) atomicMin(&s_kmin, mymin);
+            __syncthreads();
+            if (threadIdx.x == 0 && s_kmin != 0x7fffffff) atomicMin(&ctl->minv[r & 1], s_kmin);
             if (!grid_barrier(ctl, nb)) return;
             k = ld_acquire(&ctl->minv[r & 1]);
             alpha = max(alpha, k);
             int *F = (r & 1) ? pa.fb : pa.fa;
+            if (threadIdx.x == 0) s_nj = 0;
+            __syncthreads();
             for (int vb = wid * 64; vb < n; vb += nw * 64) {
                 const int v = vb + lane;
                 const bool take = v < n && sub[v] < 0 && deg[v] <= k;
-                const int slot = wave_slot(take, &ctl->cnt[r % 3]);
-                if (take) {
-                    sub[v] = r;
-                    F[slot] = v;
-                }
+                if (take) sub[v] = r;
+                list_add(take, v, F, &ctl->cnt[r % 3]);
             }
+            list_flush(F, &ctl->cnt[r % 3]);
             if (!grid_barrier(ctl, nb)) return;
             nF = ld_acquire(&ctl->cnt[r % 3]);
             if (nF == 0) break;  // cannot happen while vertices remain
@@ -219,9 +244,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         // remove the frontier: decrement the degrees of remaining neighbours;
         // a neighbour taken from k+1 to k joins the next sub-round
         int *ncnt = &ctl->cnt[(r + 1) % 3];
-        // joins of this sub-round are gathered per block in LDS and moved to
-        // the next frontier with one global atomic per block: a single
-        // counter taken by every wave serialises across the XCDs
+        // joins of this sub-round: the block's LDS list
         if (threadIdx.x == 0) s_nj = 0;
         __syncthreads();
         // one decrement per remaining neighbour; a neighbour taken from k+1
@@ -238,12 +261,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             for (int q = 0; q < PEEL_UNROLL; q++) {
                 const bool join = live[q] && old[q] == k + 1;
                 if (join) sub[u[q]] = r + 1;
-                // the block's LDS list first; past its end, the frontier
-                const int slot = wave_slot(join, &s_nj);
-                if (join) {
-                    if (slot < PEEL_JOIN_LDS) s_join[slot] = u[q];
-                    else Fn[atomicAdd(ncnt, 1)] = u[q];
-                }
+                list_add(join, u[q], Fn, ncnt);
             }
         };
         // a row walked by the whole wave, 64 * PEEL_UNROLL entries at a time
@@ -296,13 +314,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                 wave_row(rp[v], rp[v + 1]);
             }
         }
-        __syncthreads();
-        {
-            const int nj = min(s_nj, PEEL_JOIN_LDS);
-            if (threadIdx.x == 0) s_jbase = nj ? atomicAdd(ncnt, nj) : 0;
-            __syncthreads();
-            for (int j = threadIdx.x; j < nj; j += blockDim.x) Fn[s_jbase + j] = s_join[j];
-        }
+        list_flush(Fn, ncnt);
         if (!grid_barrier(ctl, nb)) return;
         removed += nF;
         nF = ld_acquire(&ctl->cnt[(r + 1) % 3]);
