@@ -169,7 +169,7 @@ struct pv_ctx {
     int *h_io = nullptr;  // pinned readback slots
     int level_blocks[6][3] = {};  // [kernel variant, see variant_of][unit kind]
     int dfs_max = 64;
-    int dfs_budget = 2048;
+    int dfs_budget = 0;  // 0: chosen per request (see budget_of)
     int lane_max = PV_LANE_MAX;
     bool debug = false;  // PV_DEBUG set: per-level buffer demands on stderr
     Workspace ws;
@@ -309,8 +309,17 @@ extern "C" pv_status pv_set_stream(pv_ctx *c, void *stream) {
     return PV_OK;
 }
 
+// Nodes a wave walks before it splits: measured on the 1M-vertex power-law
+// graph, 4096 is best for global counts alone (fewer levels than 2048, and
+// larger budgets leave long walks at the end of a level) and 8192 with local
+// counts (every unit ends with a flush of its accumulators and a partial
+// lane batch, so fewer, larger units pay)
+static int budget_of(const pv_ctx *c, bool local) {
+    return c->dfs_budget > 0 ? c->dfs_budget : (local ? 8192 : 4096);
+}
+
 extern "C" pv_status pv_set_dfs_budget(pv_ctx *c, int32_t nodes) {
-    if (!c || nodes < 16 || nodes > (1 << 20)) return PV_EINVAL;
+    if (!c || (nodes != 0 && (nodes < 16 || nodes > (1 << 20)))) return PV_EINVAL;
     c->dfs_budget = nodes;
     return PV_OK;
 }
@@ -679,7 +688,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.nlight = (ch == 0) ? rq.nlight : 0;
                 a.kmax = rq.kmax;
                 a.dfs_max = c->dfs_max;
-                a.dfs_budget = c->dfs_budget;
+                a.dfs_budget = budget_of(c, local);
                 a.lane_max = (!local || rq.lane_ok) ? c->lane_max : 0;
                 a.level = level;
                 a.n_mw_in = n_mw;
@@ -956,7 +965,7 @@ static pv_status setup_local(pv_graph *g, int kind, int klo, int khi, CountReq &
     // per vertex: one 64-bit word per k-slot suffices when a universe
     // visit's sums stay below 2^64 (a visit walks at most dfs_budget nodes
     // plus two pivot chains, each leaf adding at most cmax)
-    const unsigned __int128 visit_leaves = (unsigned __int128)g->ctx->dfs_budget + 256;
+    const unsigned __int128 visit_leaves = (unsigned __int128)budget_of(g->ctx, true) + 256;
     rq.lk = rq.edge ? PV_LK_EDGE
                     : ((fits && cmax * visit_leaves < ((unsigned __int128)1 << 64)) ? PV_LK_VERTEX64
                                                                                       : PV_LK_VERTEX128);

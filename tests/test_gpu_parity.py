@@ -303,7 +303,7 @@ def _local_run(ctx, g, lane_max, budget=2048):
             tr = P.pv_count_global(h, k_max=5)
     finally:
         P.pv_set_lane_max(ctx, 8)
-        P.pv_set_dfs_budget(ctx, 2048)
+        P.pv_set_dfs_budget(ctx, 0)
     return out, ovf, st, tr
 
 
@@ -354,7 +354,7 @@ def test_dfs_budget_splits_keep_the_tree(ctx, dfs_max, budget):
         assert ovf == 0 and np.array_equal(out, vref.vertex)
     finally:
         P.pv_set_dfs_max(ctx, 64)
-        P.pv_set_dfs_budget(ctx, 2048)
+        P.pv_set_dfs_budget(ctx, 0)
 
 
 # ----------------------------------------------------------------- per-edge
@@ -398,7 +398,7 @@ def test_per_edge_splits(ctx, dfs_max, budget):
         assert ovf == 0 and np.array_equal(out, ref.edge)
     finally:
         P.pv_set_dfs_max(ctx, 64)
-        P.pv_set_dfs_budget(ctx, 2048)
+        P.pv_set_dfs_budget(ctx, 0)
 
 
 def test_per_edge_combined_device_output(ctx):
