@@ -68,7 +68,8 @@ typedef int32_t pv_status;
 
 /* largest supported degeneracy (out-degree bound of the orientation) */
 #define PV_MAX_ALPHA 4096
-/* local counts are kept for at most this many consecutive k */
+/* one tree walk keeps local counts for at most this many consecutive k
+   (pv_count_local covers wider ranges window by window) */
 #define PV_MAX_LOCAL_K 16
 
 typedef struct pv_ctx pv_ctx;
@@ -201,16 +202,19 @@ pv_status pv_count_global(pv_graph *g, int32_t k_max, pv_u128 *counts, int32_t c
                           int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats);
 
 /*
- * Local counts for k_lo <= k <= k_hi (1 <= k_lo <= k_hi <= PV_MAX_LOCAL_K),
- * Alg. 2 per-vertex and per-edge steps.  The binomials C(alpha, k_hi - 1)
- * must fit 64 bits (PV_ETOOBIG otherwise).
+ * Local counts for k_lo <= k <= k_hi (1 <= k_lo <= k_hi <= PV_MAX_ALPHA + 1),
+ * Alg. 2 per-vertex and per-edge steps.  The binomials C(alpha, b) for
+ * b < k_hi must fit 64 bits (PV_ETOOBIG otherwise; every k when alpha <= 67).
  *   kind PV_VERTEX: out[v*K + (k-k_lo)] = c_k(v), out_len >= n*K.
  *   kind PV_EDGE:   out[e*K + (k-k_lo)] = c_k(e), out_len >= m*K, where edge
  *                   id e is the rank of (u,v), u<v, in lexicographic order
  *                   (the order of pv_graph_edge_list).
- * out is host memory.  The tree is truncated at k_hi hold vertices.
- * overflow_bits (may be NULL): uint64[1], bit (k-k_lo) set if some count of
- * that k is >= 2^128.
+ * out is host memory.  A range wider than PV_MAX_LOCAL_K (per vertex) or 8
+ * (per edge) values of k is counted window by window, one tree walk each;
+ * each walk is truncated at its window's largest k hold vertices.  stats
+ * describe the last walk.
+ * overflow_bits (may be NULL): uint64[1], all bits set if some count is
+ * >= 2^128.
  */
 pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int32_t k_hi,
                          pv_u128 *out, int64_t out_len, uint64_t *overflow_bits,

@@ -159,6 +159,7 @@ struct pv_ctx {
     DevInfo dev{};
     // exact binomials
     int bn = 0;
+    int ts = 32;  // row stride of tab_pad (columns j = -16..ts-17)
     DBuf<uint64_t> tab, tab64, tab_pad;
     DBuf<uint8_t> bad;
     DBuf<int> fits64;
@@ -349,18 +350,22 @@ extern "C" pv_status pv_set_dfs_max(pv_ctx *c, int32_t dfs_max) {
     return PV_OK;
 }
 
-static pv_status ensure_binomials(pv_ctx *c, int need) {
-    if (need <= c->bn) return PV_OK;
-    int bn = std::max(need, 2 * c->bn);
+// Binomials for a up to need - 1; the padded table's rows hold columns
+// j = -16..ts-17 with ts >= ts_need
+static pv_status ensure_binomials(pv_ctx *c, int need, int ts_need = 32) {
+    if (need <= c->bn && ts_need <= c->ts) return PV_OK;
+    int bn = std::max(need, c->bn);
+    if (need > c->bn) bn = std::max(need, 2 * c->bn);
+    c->ts = std::max(c->ts, (ts_need + 7) / 8 * 8);
     PVCHK(c->tab.ensure((size_t)bn * bn * 2));
     PVCHK(c->bad.ensure((size_t)bn * bn));
     PVCHK(c->tab64.ensure((size_t)bn * 16));
     PVCHK(c->fits64.ensure(16));
     std::vector<int> ones(16, 1);
     HIPCHK(hipMemcpyAsync(c->fits64.p, ones.data(), 16 * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    PVCHK(c->tab_pad.ensure((size_t)(bn + 1) * 32));
+    PVCHK(c->tab_pad.ensure((size_t)(bn + 1) * c->ts));
     HIPCHK(pv_launch_binomials(bn, c->tab.p, c->bad.p, c->tab64.p, c->fits64.p, c->stream));
-    HIPCHK(pv_launch_binom_pad(bn, c->tab.p, c->tab_pad.p, c->stream));
+    HIPCHK(pv_launch_binom_pad(bn, c->ts, c->tab.p, c->tab_pad.p, c->stream));
     HIPCHK(hipMemcpyAsync(c->fits64_h, c->fits64.p, 16 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->bn = bn;
@@ -580,7 +585,8 @@ struct CountReq {
     int graphs = 1;       // batch: parts of the disjoint union (one histogram each)
     const int *vgraph = nullptr;  // batch: part of every vertex
     int klo = 1, K = 0;
-    uint64_t *vout = nullptr;  // device [n][K] u128
+    uint64_t *vout = nullptr;  // device [n][kstride] u128; this pass writes columns 0..K-1
+    int kstride = 0;           // row stride of vout in slots (0: K)
     int c0 = 1;           // value of C_0
     // root subset (device order array + counts) or the whole graph
     const int *order = nullptr;
@@ -657,11 +663,15 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
         HIPCHK(hipMemsetAsync(c->ws.counters.p, 0, 8 * sizeof(unsigned long long), s));
         HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, 5 * sizeof(int), s));  // flags,u_n,pref_n,omega,lovf
         const size_t lrows = rq.edge ? (size_t)(g->nnz / 2) : (size_t)g->n;
-        if (local && lrows) HIPCHK(hipMemsetAsync(rq.vout, 0, lrows * rq.K * 16, s));
+        const int kstride = rq.kstride > 0 ? rq.kstride : rq.K;
+        if (local && lrows) {
+            if (kstride == rq.K) HIPCHK(hipMemsetAsync(rq.vout, 0, lrows * rq.K * 16, s));
+            else HIPCHK(hipMemset2DAsync(rq.vout, (size_t)kstride * 16, 0, (size_t)rq.K * 16, lrows, s));
+        }
         if (rq.whole)
             HIPCHK(pv_launch_sink_roots(g->n, g->order.p, g->small.p + SM_BOUNDS, c->ws.hist.p, hd,
                                         c->ws.counters.p, (local && !rq.edge) ? rq.vout : nullptr,
-                                        rq.klo, rq.K, rq.vgraph, s));
+                                        rq.klo, kstride, rq.vgraph, s));
 
         bool overflow = false;
         bool io_fresh = false;  // io holds a readback of this attempt's flags
@@ -722,7 +732,9 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.vout = rq.vout;
                 a.klo = rq.klo;
                 a.K = rq.K;
+                a.kstride = kstride;
                 a.bin_pad = c->tab_pad.p;
+                a.tab_stride = c->ts;
                 a.lovf = g->small.p + SM_LOVF;
                 a.sub = g->sub.p;
                 a.o2e = rq.edge ? g->o2e.p : nullptr;
@@ -943,8 +955,8 @@ static pv_status ensure_edge_ids(pv_graph *g) {
 static pv_status setup_local(pv_graph *g, int kind, int klo, int khi, CountReq &rq) {
     if (kind == PV_NONE) return PV_OK;
     if (kind != PV_VERTEX && kind != PV_EDGE) return PV_EINVAL;
-    // the 64-bit binomial table keeps C(a, b) for b < 16, and b = k - h <= khi - 1
-    if (klo < 1 || khi < klo || khi - klo + 1 > PV_MAX_LOCAL_K || khi > 16) return PV_EINVAL;
+    // one pass keeps at most PV_MAX_LOCAL_K k-slots per lane
+    if (klo < 1 || khi < klo || khi - klo + 1 > PV_MAX_LOCAL_K) return PV_EINVAL;
     // per-edge sums keep 8 k-slots per lane
     if (kind == PV_EDGE && khi - klo + 1 > 8) return PV_EINVAL;
     rq.klo = klo;
@@ -954,7 +966,9 @@ static pv_status setup_local(pv_graph *g, int kind, int klo, int khi, CountReq &
     // the local paths keep C(a, b), a <= alpha, b <= khi - 1, in 64 bits;
     // C(a, b) grows with a, so the largest value used is max over b of
     // C(alpha, b)
-    PVCHK(ensure_binomials(g->ctx, g->alpha + 3));
+    // padded rows reach column klo + kl + 14 (a leaf's segment starts at
+    // klo - h + 16 with h >= 1 and spans the kernel's kl slots)
+    PVCHK(ensure_binomials(g->ctx, g->alpha + 3, klo + rq.kl + 15));
     unsigned __int128 cb = 1, cmax = 1;
     bool fits = true;
     for (int b = 1; b <= khi - 1 && b <= g->alpha; b++) {
@@ -1012,7 +1026,7 @@ extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int
                                     pv_stats *stats) {
     if (!g || !out) return PV_EINVAL;
     if (kind != PV_VERTEX && kind != PV_EDGE) return PV_EINVAL;
-    if (k_lo < 1 || k_hi < k_lo || k_hi - k_lo + 1 > PV_MAX_LOCAL_K) return PV_EINVAL;
+    if (k_lo < 1 || k_hi < k_lo || k_hi > PV_MAX_ALPHA + 1) return PV_EINVAL;
     const int K = k_hi - k_lo + 1;
     const long long rows = (kind == PV_EDGE) ? g->nnz / 2 : (long long)g->n;
     const long long need = rows * K;
@@ -1020,17 +1034,27 @@ extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int
     pv_ctx *c = g->ctx;
     PVCHK(prepare(g, false));
     PVCHK(c->ws.vout_own.ensure((size_t)std::max<long long>(need, 1) * 2));
-    CountReq rq;
-    rq.kmax = k_hi;
-    PVCHK(setup_local(g, kind, k_lo, k_hi, rq));
-    rq.vout = c->ws.vout_own.p;
-    rq.order = g->order.p;
-    rq.nheavy = g->nheavy;
-    rq.nlight = g->nnonzero - g->nheavy;
-    PVCHK(run_sct(g, rq));
+    // k ranges wider than one pass's slots (16 per vertex, 8 per edge) are
+    // counted window by window, each pass walking the tree truncated at its
+    // own k_hi and writing its columns of the [rows][K] output
+    const int win = (kind == PV_EDGE) ? 8 : PV_MAX_LOCAL_K;
     uint64_t lovf = 0;
-    pv_status st = finish_counts(g, rq, nullptr, 0, nullptr, nullptr, stats, &lovf);
-    if (st != PV_OK && st != PV_EOVERFLOW) return st;
+    for (int w0 = k_lo; w0 <= k_hi; w0 += win) {
+        const int w1 = std::min(k_hi, w0 + win - 1);
+        CountReq rq;
+        rq.kmax = w1;
+        PVCHK(setup_local(g, kind, w0, w1, rq));
+        rq.vout = c->ws.vout_own.p + 2 * (w0 - k_lo);
+        rq.kstride = K;
+        rq.order = g->order.p;
+        rq.nheavy = g->nheavy;
+        rq.nlight = g->nnonzero - g->nheavy;
+        PVCHK(run_sct(g, rq));
+        uint64_t wovf = 0;
+        pv_status st = finish_counts(g, rq, nullptr, 0, nullptr, nullptr, stats, &wovf);
+        if (st != PV_OK && st != PV_EOVERFLOW) return st;
+        lovf |= wovf;
+    }
     if (need)
         HIPCHK(hipMemcpyAsync(out, c->ws.vout_own.p, (size_t)need * 16, hipMemcpyDeviceToHost,
                               g->ctx->stream));

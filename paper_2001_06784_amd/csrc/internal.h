@@ -111,9 +111,11 @@ struct LevelArgs {
     unsigned long long *counters;  // nodes, leaves, work, -, work per unit kind [3]
     int *flags;                    // bit0: buffer overflow
     // local counts
-    uint64_t *vout;                // [n][K] (per vertex) or [m][K] (per edge) u128
-    int klo, K;
-    const uint64_t *bin_pad;       // padded 64-bit binomials, see VertexSink
+    uint64_t *vout;                // [n][kstride] (per vertex) or [m][kstride] (per edge) u128;
+                                   // this pass writes columns 0..K-1
+    int klo, K, kstride;
+    const uint64_t *bin_pad;       // padded 64-bit binomials, rows tab_stride apart, see VertexSink
+    int tab_stride;
     int *lovf;
     // per-edge counts: edge ids and the universes' prefix-pair sums
     const int *sub;                // peel sub-round of every vertex (the orientation key)
@@ -169,11 +171,11 @@ hipError_t pv_launch_edge_ids(const DevInfo &dev, int n, const int *rp, const in
                               const int *orow, int *ucnt, int *up, int *o2e, int *scan_tmp,
                               hipStream_t s);
 hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsigned long long *hist,
-                                int hd, unsigned long long *counters, uint64_t *vout, int klo, int K,
+                                int hd, unsigned long long *counters, uint64_t *vout, int klo, int kstride,
                                 const int *vgraph, hipStream_t s);
 hipError_t pv_launch_binomials(int bn, uint64_t *tab128, uint8_t *bad, uint64_t *tab64, int *fits64,
                                hipStream_t s);
-hipError_t pv_launch_binom_pad(int bn, const uint64_t *tab128, uint64_t *pad, hipStream_t s);
+hipError_t pv_launch_binom_pad(int bn, int ts, const uint64_t *tab128, uint64_t *pad, hipStream_t s);
 hipError_t pv_launch_finalize(const unsigned long long *hist, int hd, const uint64_t *tab128,
                               const uint8_t *bad, int bn, int kcap, int kmax, int c0,
                               uint64_t *counts, uint64_t *ovf_words, int *omega, int graphs,

@@ -121,8 +121,10 @@ __device__ __forceinline__ u64x8 ldc64x8(const uint64_t *p) {
 // (sum of C(p-1, k-h-1)), with the same instructions as a member.
 //
 // Binomials come from a padded table: row a (a = -1..alpha) holds C(a, j)
-// for j = -16..15 at [(a + 1) * 32 + j + 16], zero outside 0 <= j <= a, so
-// the K values of a leaf are one contiguous, range-check-free segment.
+// for j = -16..ts-17 at [(a + 1) * ts + j + 16] (ts = a.tab_stride, at
+// least k_hi + 24), zero outside 0 <= j <= a, so the K values of a leaf are
+// one contiguous, range-check-free segment.  Output rows are kstride slots
+// apart (a window of a wider k range writes its own columns).
 //
 // WIDE = false keeps one 64-bit word per slot: the host picks it when a
 // wave's sums for one universe visit cannot reach 2^64 (a visit reaches at
@@ -137,7 +139,7 @@ struct VertexSink {
     uint64_t *utot;  // [u_cap][2][K]: what the hold / pivot vertices above a universe are owed
     const int *pool;
     int *lovf;
-    int klo, K, khi;
+    int klo, K, khi, ks, ts;
 
     __device__ void init(const LevelArgs &a, uint64_t *, int) {
         tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
@@ -148,6 +150,8 @@ struct VertexSink {
         klo = uniformi(a.klo);
         K = uniformi(a.K);
         khi = klo + K - 1;
+        ks = uniformi(a.kstride);
+        ts = uniformi(a.tab_stride);
         reset();
     }
 
@@ -176,8 +180,8 @@ struct VertexSink {
         if (h > khi || h + p < klo) return;
         const bool inH = ((H >> lane) & 1) || lane == 62;
         const bool inP = ((P >> lane) & 1) || lane == 63;
-        const uint64_t *rowH = tab + (p + 1) * 32 + (klo - h + 16);  // C(p, k-h)
-        const uint64_t *rowP = tab + p * 32 + (klo - h + 15);        // C(p-1, k-h-1)
+        const uint64_t *rowH = tab + (p + 1) * ts + (klo - h + 16);  // C(p, k-h)
+        const uint64_t *rowP = tab + p * ts + (klo - h + 15);        // C(p-1, k-h-1)
         constexpr int NC = KL > 0 ? (KL + 7) / 8 : 1;
         u64x8 vH[NC], vP[NC];
 #pragma unroll
@@ -235,14 +239,14 @@ struct VertexSink {
             uint64_t old[KL > 0 ? KL : 1];
 #pragma unroll
             for (int kk = 0; kk < KL; kk++)
-                old[kk] = (kk < K) ? atomic_add_u128_lo(vout + 2 * ((long long)gid * K + kk), lo[kk]) : 0ull;
+                old[kk] = (kk < K) ? atomic_add_u128_lo(vout + 2 * ((long long)gid * ks + kk), lo[kk]) : 0ull;
             // the returned limbs are first needed here (keeps the compiler
             // from waiting for each atomic inside its own branch)
 #pragma unroll
             for (int kk = 0; kk < KL; kk++) asm volatile("" : "+v"(old[kk]));
 #pragma unroll
             for (int kk = 0; kk < KL; kk++)
-                if (kk < K) ovf |= atomic_add_u128_hi(vout + 2 * ((long long)gid * K + kk), lo[kk], old[kk], hiw(kk));
+                if (kk < K) ovf |= atomic_add_u128_hi(vout + 2 * ((long long)gid * ks + kk), lo[kk], old[kk], hiw(kk));
         }
         root = uniformi(root);
         uni = uniformi(uni);
@@ -264,7 +268,7 @@ struct VertexSink {
             }
             if (lane < K) {
                 if (root >= 0) {
-                    if (thl | thh) ovf |= atomic_add_u128(vout + 2 * ((long long)root * K + lane), thl, thh);
+                    if (thl | thh) ovf |= atomic_add_u128(vout + 2 * ((long long)root * ks + lane), thl, thh);
                 } else {
                     uint64_t *ut = utot + 2 * ((long long)uni * 2 * K + lane);
                     uint64_t oh = atomic_add_u128_lo(ut, thl), op = atomic_add_u128_lo(ut + 2 * K, tpl);
@@ -338,7 +342,7 @@ struct EdgeSink {
     uint64_t *eout, *umem, *utot;
     const int *orow, *o2e;
     int *lovf, *flags;
-    int klo, K, khi;
+    int klo, K, khi, ks, ts;
     bool ovf;
 
     __device__ void init(const LevelArgs &a, uint64_t *lds_xch, int wave0) {
@@ -354,6 +358,8 @@ struct EdgeSink {
         klo = uniformi(a.klo);
         K = uniformi(a.K);
         khi = klo + K - 1;
+        ks = uniformi(a.kstride);
+        ts = uniformi(a.tab_stride);
         const long long slot = wave0 + (long long)blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
         snap = a.escr + slot * (2ll * 64 * 2 * K * 2);
         snap = (uint64_t *)uniform64((uint64_t)snap);
@@ -424,9 +430,9 @@ struct EdgeSink {
         // rows of C(p, .), C(p-1, .), C(p-2, .) at column k - h, k - h - 1,
         // k - h - 2 (row -1 is all zeros and stands in for row -2: with
         // p = 0 there is no pivot vertex, so PP is never owed)
-        const uint64_t *rowHH = tab + (p + 1) * 32 + (klo - h + 16);
-        const uint64_t *rowHP = tab + p * 32 + (klo - h + 15);
-        const uint64_t *rowPP = tab + max(p - 1, 0) * 32 + (klo - h + 14);
+        const uint64_t *rowHH = tab + (p + 1) * ts + (klo - h + 16);
+        const uint64_t *rowHP = tab + p * ts + (klo - h + 15);
+        const uint64_t *rowPP = tab + max(p - 1, 0) * ts + (klo - h + 14);
         const u64x8 xHH = ldc64x8(rowHH), xHP = ldc64x8(rowHP), xPP = ldc64x8(rowPP);
 #pragma unroll
         for (int kk = 0; kk < KL; kk++) {
@@ -477,7 +483,7 @@ struct EdgeSink {
                 const int e = etab[j * 64 + lane];
                 if (e < 0) atomicOr(flags, 4);
                 const int sel = ((bh >> lane) & 1) ? 0 : 2;
-                uint64_t *dst = eout + 2 * ((long long)e * K);
+                uint64_t *dst = eout + 2 * ((long long)e * ks);
                 for (int kk = 0; kk < K; kk++) {
                     const uint64_t l = xch[4 * kk + sel], hv = xch[4 * kk + sel + 1];
                     if (e >= 0 && (l | hv)) ovf |= atomic_add_u128(dst + 2 * kk, l, hv);
@@ -502,7 +508,7 @@ struct EdgeSink {
                 const uint64_t *va = vacc + 2 * (((long long)lane * 2) * K);
                 for (int kk = 0; kk < K; kk++) {
                     const uint64_t l = va[2 * kk], hv = va[2 * kk + 1];
-                    if (e >= 0 && (l | hv)) ovf |= atomic_add_u128(eout + 2 * ((long long)e * K + kk), l, hv);
+                    if (e >= 0 && (l | hv)) ovf |= atomic_add_u128(eout + 2 * ((long long)e * ks + kk), l, hv);
                 }
             }
         } else if (uni >= 0) {
@@ -680,8 +686,8 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
             gs.leaf_lane(h, p);
             if (LOC && h <= vs.khi && h + p >= vs.klo) {
                 // same table segments as VertexSink::leaf
-                const uint64_t *rowH = vs.tab + (p + 1) * 32 + (vs.klo - h + 16);  // C(p, k-h)
-                const uint64_t *rowP = vs.tab + p * 32 + (vs.klo - h + 15);        // C(p-1, k-h-1)
+                const uint64_t *rowH = vs.tab + (p + 1) * vs.ts + (vs.klo - h + 16);  // C(p, k-h)
+                const uint64_t *rowP = vs.tab + p * vs.ts + (vs.klo - h + 15);        // C(p-1, k-h-1)
                 uint64_t vH[NK], vP[NK];
 #pragma unroll
                 for (int kk = 0; kk < NK; kk++) {
@@ -1587,7 +1593,7 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
                     e = edge_id(x, gid, a.sub, a.orow, a.ocol, a.o2e);
                     if (e < 0) atomicOr(a.flags, 4);
                 }
-                if (e >= 0) ovf |= atomic_add_u128(a.vout + 2 * ((long long)e * K + kk), l, hv);
+                if (e >= 0) ovf |= atomic_add_u128(a.vout + 2 * ((long long)e * a.kstride + kk), l, hv);
             }
         }
         const uint64_t *tot = a.utot + 2 * ((long long)u * 3 * K);
@@ -1603,7 +1609,7 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
                 }
                 for (int kk = 0; kk < K; kk++) {
                     const uint64_t l = tot[2 * (type * K + kk)], hv = tot[2 * (type * K + kk) + 1];
-                    if (l | hv) ovf |= atomic_add_u128(a.vout + 2 * ((long long)e * K + kk), l, hv);
+                    if (l | hv) ovf |= atomic_add_u128(a.vout + 2 * ((long long)e * a.kstride + kk), l, hv);
                 }
             }
         }
@@ -1631,7 +1637,7 @@ __global__ void __launch_bounds__(256) vertex_prefix_kernel(const LevelArgs *__r
             const int x = e & 0x7fffffff;
             const bool isP = (e >> 31) & 1;
             const uint64_t l = isP ? pl : hl, h = isP ? ph : hh;
-            if (l | h) ovf |= atomic_add_u128(a.vout + 2 * ((long long)x * K + lane), l, h);
+            if (l | h) ovf |= atomic_add_u128(a.vout + 2 * ((long long)x * a.kstride + lane), l, h);
         }
     }
     if (ovf) atomicOr(a.lovf, 1);
@@ -1640,7 +1646,7 @@ __global__ void __launch_bounds__(256) vertex_prefix_kernel(const LevelArgs *__r
 // Roots with an empty out-neighbourhood are leaves (h=1, p=0) of the SCT.
 __global__ void sct_sink_roots_kernel(int n, const int *__restrict__ order, const int *__restrict__ bounds,
                                       unsigned long long *hist, int hd, unsigned long long *counters,
-                                      uint64_t *vout, int klo, int K, const int *__restrict__ vgraph) {
+                                      uint64_t *vout, int klo, int kstride, const int *__restrict__ vgraph) {
     const int first = bounds[1];
     const int cnt = n - first;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1659,7 +1665,7 @@ __global__ void sct_sink_roots_kernel(int n, const int *__restrict__ order, cons
     if (vout && klo == 1) {
         for (int j = i; j < cnt; j += gridDim.x * blockDim.x) {
             const int v = order[first + j];
-            atomicAdd((unsigned long long *)(vout + 2 * ((long long)v * K)), 1ull);
+            atomicAdd((unsigned long long *)(vout + 2 * ((long long)v * kstride)), 1ull);
         }
     }
 }
@@ -1702,11 +1708,11 @@ __global__ void binom_kernel(int bn, uint64_t *tab, uint8_t *bad, uint64_t *tab6
 }
 
 // Padded 64-bit table for the per-vertex path (see VertexSink): row a =
-// -1..bn-1, column j = -16..15 at [(a + 1) * 32 + j + 16].
-__global__ void binom_pad_kernel(int bn, const uint64_t *__restrict__ tab, uint64_t *__restrict__ pad) {
-    const int total = (bn + 1) * 32;
+// -1..bn-1, column j = -16..ts-17 at [(a + 1) * ts + j + 16].
+__global__ void binom_pad_kernel(int bn, int ts, const uint64_t *__restrict__ tab, uint64_t *__restrict__ pad) {
+    const int total = (bn + 1) * ts;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        const int a = i / 32 - 1, j = i % 32 - 16;
+        const int a = i / ts - 1, j = i % ts - 16;
         pad[i] = (a >= 0 && j >= 0 && j <= a) ? tab[2 * ((long long)a * bn + j)] : 0ull;
     }
 }
@@ -1843,9 +1849,9 @@ hipError_t pv_launch_vertex_prefix(const LevelArgs *a, int blocks, hipStream_t s
 }
 
 hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsigned long long *hist,
-                                int hd, unsigned long long *counters, uint64_t *vout, int klo, int K,
+                                int hd, unsigned long long *counters, uint64_t *vout, int klo, int kstride,
                                 const int *vgraph, hipStream_t s) {
-    sct_sink_roots_kernel<<<256, 256, 0, s>>>(n, order, bounds, hist, hd, counters, vout, klo, K, vgraph);
+    sct_sink_roots_kernel<<<256, 256, 0, s>>>(n, order, bounds, hist, hd, counters, vout, klo, kstride, vgraph);
     return hipGetLastError();
 }
 
@@ -1855,8 +1861,8 @@ hipError_t pv_launch_binomials(int bn, uint64_t *tab128, uint8_t *bad, uint64_t 
     return hipGetLastError();
 }
 
-hipError_t pv_launch_binom_pad(int bn, const uint64_t *tab128, uint64_t *pad, hipStream_t s) {
-    binom_pad_kernel<<<64, 256, 0, s>>>(bn, tab128, pad);
+hipError_t pv_launch_binom_pad(int bn, int ts, const uint64_t *tab128, uint64_t *pad, hipStream_t s) {
+    binom_pad_kernel<<<64, 256, 0, s>>>(bn, ts, tab128, pad);
     return hipGetLastError();
 }
 

@@ -336,6 +336,35 @@ def test_lane_tier_keeps_tree_and_counts(ctx, name, make, lane_max):
         assert tr.counts == w_tr.counts
 
 
+# ------------------------------------------------ local counts for all k
+
+ALLK_GRAPHS = [
+    ("K30", lambda: gg.complete(30)),
+    ("planted 300", lambda: gg.plant_cliques(gg.gnp(300, 0.05, 171), [26, 19], 172)),
+    ("multipartite 3x11", lambda: gg.complete_multipartite([3] * 11)),
+]
+
+
+@pytest.mark.parametrize("name,make", ALLK_GRAPHS)
+def test_local_counts_for_all_k(ctx, name, make):
+    # k ranges wider than one walk's slots go window by window (16 values
+    # per vertex, 8 per edge), including windows that start above k = 16
+    g = make()
+    with Loaded(ctx, g) as h:
+        res = P.pv_count_global(h)
+        w = res.omega + 2
+        _say(f"[parity] all-k local counts {name}: omega={res.omega}, k=1..{w}")
+        vout, vovf, _ = P.pv_count_local(h, P.PV_VERTEX, 1, w)
+        eout, eovf, _ = P.pv_count_local(h, P.PV_EDGE, 2, w)
+        hi_v = P.pv_count_local(h, P.PV_VERTEX, 17, w) if w >= 17 else None
+    ref = O.count(g, vertex=(1, w), edge=(2, w))
+    assert vovf == 0 and eovf == 0
+    assert np.array_equal(vout, ref.vertex)
+    assert np.array_equal(eout, ref.edge)
+    if hi_v is not None:
+        assert hi_v[1] == 0 and np.array_equal(hi_v[0], ref.vertex[:, 16:])
+
+
 # ---------------------------------------------- forced depth-first splits
 
 SPLITS = [(32, 16), (8, 16), (64, 24), (64, 1 << 20)]
@@ -420,12 +449,18 @@ def test_per_edge_combined_device_output(ctx):
     assert np.array_equal(out, ref.edge)
 
 
-def test_per_edge_rejects_wide_range(ctx):
+def test_per_edge_wide_range(ctx):
+    # one walk keeps 8 per-edge k-slots: pv_count refuses a wider range,
+    # pv_count_local covers it window by window
+    import torch
     g = gg.gnp(50, 0.2, 161)
     with Loaded(ctx, g) as h:
+        dev = torch.zeros((g.m, 9, 2), dtype=torch.int64, device="cuda:0")
         with pytest.raises(P.PivoterError) as ei:
-            P.pv_count_local(h, P.PV_EDGE, 2, 10)
+            P.pv_count(h, local_kind=P.PV_EDGE, k_lo=2, k_hi=10, local_out=dev.data_ptr())
+        out, ovf, _ = P.pv_count_local(h, P.PV_EDGE, 2, 10)
     assert ei.value.status == P.PV_EINVAL
+    assert ovf == 0 and np.array_equal(out, O.count(g, edge=(2, 10)).edge)
 
 
 # ------------------------------------------------------------------ batches
