@@ -528,7 +528,11 @@ __device__ __forceinline__ bool key_less(int su, int u, int sv, int v) {
     return su < sv || (su == sv && u < v);
 }
 
-// out-degree of every vertex (one wave per vertex)
+// Rows of at most ORIENT_LANE_ROW entries are walked one vertex per lane
+// (most rows of a sparse graph are short), longer ones by the whole wave.
+#define ORIENT_LANE_ROW 32
+
+// out-degree of every vertex
 __global__ void __launch_bounds__(256) odeg_kernel(int n, const int *__restrict__ rp,
                                                     const int *__restrict__ col,
                                                     const int *__restrict__ sub,
@@ -537,21 +541,42 @@ __global__ void __launch_bounds__(256) odeg_kernel(int n, const int *__restrict_
     const int lane = threadIdx.x & 63;
     const int nw = (gridDim.x * blockDim.x) >> 6;
     int amax = 0;
-    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += nw) {
-        const int sv = sub[v];
-        int c = 0;
-        for (int e = rp[v] + lane; e < rp[v + 1]; e += 64) {
-            const int u = col[e];
-            c += key_less(sv, v, sub[u], u) ? 1 : 0;
+    for (int vb = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; vb < n; vb += nw * 64) {
+        const int v = vb + lane;
+        int b = 0, e = 0, sv = 0;
+        if (v < n) {
+            b = rp[v];
+            e = rp[v + 1];
+            sv = sub[v];
         }
-        c = (int)wave_add_u32((uint32_t)c);
-        if (lane == 0) odeg[v] = c;
+        const bool wide = v < n && e - b > ORIENT_LANE_ROW;
+        int c = 0;
+        if (v < n && !wide)
+            for (int i = b; i < e; i++) {
+                const int u = col[i];
+                c += key_less(sv, v, sub[u], u) ? 1 : 0;
+            }
+        for (uint64_t wm = ballot64(wide); wm; wm &= wm - 1ull) {
+            const int L = __builtin_ctzll(wm);
+            const int x = vb + L, sx = __shfl(sv, L, 64);
+            const int xb = __shfl(b, L, 64), xe = __shfl(e, L, 64);
+            int cx = 0;
+            for (int i = xb + lane; i < xe; i += 64) {
+                const int u = col[i];
+                cx += key_less(sx, x, sub[u], u) ? 1 : 0;
+            }
+            cx = (int)wave_add_u32((uint32_t)cx);
+            if (lane == L) c = cx;
+        }
+        if (v < n) odeg[v] = c;
         amax = max(amax, c);
     }
+    amax = wave_max_i32(amax);
     if (lane == 0) atomicMax(alpha, amax);
 }
 
-// N+(v) in increasing id order (row order kept by ballot compaction)
+// N+(v) in increasing id order (row order kept: serial per lane, ballot
+// compaction per wave)
 __global__ void __launch_bounds__(256) ofill_kernel(int n, const int *__restrict__ rp,
                                                      const int *__restrict__ col,
                                                      const int *__restrict__ sub,
@@ -560,21 +585,39 @@ __global__ void __launch_bounds__(256) ofill_kernel(int n, const int *__restrict
     const int lane = threadIdx.x & 63;
     const int nw = (gridDim.x * blockDim.x) >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += nw) {
-        const int sv = sub[v];
-        int w = orow[v];
-        const int e1 = rp[v + 1];
-        for (int e0 = rp[v]; e0 < e1; e0 += 64) {
-            const int e = e0 + lane;
-            bool take = false;
-            int u = 0;
-            if (e < e1) {
-                u = col[e];
-                take = key_less(sv, v, sub[u], u);
+    for (int vb = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; vb < n; vb += nw * 64) {
+        const int v = vb + lane;
+        int b = 0, e = 0, sv = 0;
+        if (v < n) {
+            b = rp[v];
+            e = rp[v + 1];
+            sv = sub[v];
+        }
+        const bool wide = v < n && e - b > ORIENT_LANE_ROW;
+        if (v < n && !wide) {
+            int w = orow[v];
+            for (int i = b; i < e; i++) {
+                const int u = col[i];
+                if (key_less(sv, v, sub[u], u)) ocol[w++] = u;
             }
-            const uint64_t m = ballot64(take);
-            if (take) ocol[w + __popcll(m & below)] = u;
-            w += __popcll(m);
+        }
+        for (uint64_t wm = ballot64(wide); wm; wm &= wm - 1ull) {
+            const int L = __builtin_ctzll(wm);
+            const int x = vb + L, sx = __shfl(sv, L, 64);
+            const int xb = __shfl(b, L, 64), xe = __shfl(e, L, 64);
+            int w = orow[x];
+            for (int i0 = xb; i0 < xe; i0 += 64) {
+                const int i = i0 + lane;
+                bool take = false;
+                int u = 0;
+                if (i < xe) {
+                    u = col[i];
+                    take = key_less(sx, x, sub[u], u);
+                }
+                const uint64_t m = ballot64(take);
+                if (take) ocol[w + __popcll(m & below)] = u;
+                w += __popcll(m);
+            }
         }
     }
 }
@@ -834,7 +877,8 @@ hipError_t pv_launch_peel(const DevInfo &dev, const PeelArgs &pa, hipStream_t s)
 hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
                             int *odeg, int *orow, int *ocol, int *alpha, int *scan_tmp,
                             hipStream_t s) {
-    const int wblocks = grid_for((long long)n * 64, 256, dev.num_cu * 32);
+    // a wave takes 64 vertices per step
+    const int wblocks = grid_for((long long)n, 256, dev.num_cu * 32);
     odeg_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, odeg, alpha);
     const int nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
     if (n > 0) {

@@ -564,9 +564,10 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
 // their subtrees at once, each lane its own: the induced adjacency of the
 // node's set as eight 8-bit rows in one register (local index = rank in
 // the universe, so "smallest id" is still "lowest bit"), and the depth-first
-// stack of at most 8 frames (a frame's set strictly contains the next
-// one's) in LDS, frame t of lane l at [t][l] (no bank conflicts).  Pivot rule, child order and the node, work and
-// leaf accounting are those of compact_dfs: same tree, same counts.
+// stack of at most 7 frames (a frame's set strictly contains the next one's
+// and has at least 2 vertices) in LDS, frame t of lane l at [t][l] (no bank
+// conflicts).  Pivot rule, child order and the node, work and leaf
+// accounting are those of compact_dfs: same tree, same counts.
 
 __device__ __forceinline__ uint64_t shfl64(uint64_t x, int src) {
     const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)x, src, 64);
@@ -634,7 +635,8 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
     uint32_t S = smask;
     uint32_t Hl = 0, Pl = 0;  // hold / pivot members taken inside the subtree (local masks)
     int depth = 0;
-    __shared__ uint32_t s_lst[WAVES_PER_BLOCK][PV_LANE_MAX][64];
+    // at most PV_LANE_MAX - 1 frames: each needs |S| >= 2 and sets shrink
+    __shared__ uint32_t s_lst[WAVES_PER_BLOCK][PV_LANE_MAX - 1][64];
     uint32_t(*st)[64] = s_lst[threadIdx.x >> 6];
     lds_u64 *acc = nullptr;
     if constexpr (LOC) acc = lane_acc<KL>();
