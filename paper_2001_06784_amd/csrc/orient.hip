@@ -413,16 +413,24 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     // LDS holds the remaining degrees as 16-bit halves of 32-bit words (a
     // degree only counts neighbours still in U and is decremented at most
     // once per neighbour, so a half never borrows from the other), liveness
-    // as a bitmask, and the two frontiers as 16-bit local ids.
+    // as a bitmask, the local row offsets, and the frontiers as 16-bit local
+    // ids, one after the other (every vertex joins one frontier, so all fit
+    // in PV_SOLO_MAX entries).  A removed vertex's degree half is not read
+    // again: once its sub-round's decrements are over (after the barrier)
+    // it holds the vertex's sub-round minus r0, and one pass at the end
+    // writes the keys.
     __shared__ unsigned s_deg2[PV_SOLO_MAX / 2];
     __shared__ unsigned s_alive[PV_SOLO_MAX / 32];
-    __shared__ unsigned short s_F[2][PV_SOLO_MAX];
+    __shared__ unsigned short s_Fq[PV_SOLO_MAX];
+    __shared__ int s_lrp[PV_SOLO_MAX + 1];
     __shared__ int s_cnt, s_min;
-    const int *__restrict__ lrp = pa.lrp;
+    unsigned short *const s_h16 = (unsigned short *)s_deg2;  // half i = vertex i
     const int *__restrict__ lcol = pa.lcol;
     const int *__restrict__ uverts = pa.uverts;
+    const int r0 = r;
     if (threadIdx.x == 0) s_cnt = 0;
     for (int i = threadIdx.x; i < PV_SOLO_MAX / 32; i += blockDim.x) s_alive[i] = 0u;
+    for (int i = threadIdx.x; i <= nu; i += blockDim.x) s_lrp[i] = pa.lrp[i];
     __syncthreads();
     for (int i = threadIdx.x; i < (nu + 1) / 2; i += blockDim.x) {
         const int a = 2 * i, b = 2 * i + 1;
@@ -434,14 +442,15 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         if (sub[uverts[i]] < 0) atomicOr(&s_alive[i >> 5], 1u << (i & 31));
     __syncthreads();
     auto alive = [&](int i) -> bool { return (s_alive[i >> 5] >> (i & 31)) & 1u; };
-    auto degof = [&](int i) -> int { return (int)((s_deg2[i >> 1] >> ((i & 1) * 16)) & 0xFFFFu); };
-    auto fput = [&](int c, int j, int x) { s_F[c][j] = (unsigned short)x; };
-    auto fget = [&](int c, int j) -> int { return (int)s_F[c][j]; };
-    int cur = 0;
+    auto degof = [&](int i) -> int { return (int)s_h16[i]; };
+    int fbase = 0;  // the current frontier is s_Fq[fbase, fbase + nF)
     if (nF > 0) {
+        // the pending frontier of the grid phase (its sub-round is r0)
         const int *F = (r & 1) ? pa.fb : pa.fa;
-        for (int j = threadIdx.x; j < nF; j += blockDim.x) fput(0, j, pa.lid[F[j]]);
+        for (int j = threadIdx.x; j < nF; j += blockDim.x) s_Fq[j] = (unsigned short)pa.lid[F[j]];
     }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nF; j += blockDim.x) s_h16[s_Fq[j]] = 0;
     __syncthreads();
     const int bw = threadIdx.x >> 6, nbw = blockDim.x >> 6;
     int left = nu;
@@ -466,20 +475,22 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                 const int slot = wave_slot(take, &s_cnt);
                 if (take) {
                     atomicAnd(&s_alive[i >> 5], ~(1u << (i & 31)));
-                    sub[uverts[i]] = r;
-                    fput(cur, slot, i);
+                    s_Fq[fbase + slot] = (unsigned short)i;
                 }
             }
             __syncthreads();
             nF = s_cnt;
-            __syncthreads();
             if (nF == 0) break;
+            for (int j = threadIdx.x; j < nF; j += blockDim.x) s_h16[s_Fq[fbase + j]] = (unsigned short)(r - r0);
+            __syncthreads();
             if (threadIdx.x == 0) s_cnt = 0;
             __syncthreads();
         }
+        // joins are appended after the current frontier
+        const int nbase = fbase + nF;
         for (int j = bw; j < nF; j += nbw) {
-            const int i = fget(cur, j);
-            const int e0 = lrp[i], e1 = lrp[i + 1];
+            const int i = s_Fq[fbase + j];
+            const int e0 = s_lrp[i], e1 = s_lrp[i + 1];
             for (int eb = e0; eb < e1; eb += 64 * PEEL_UNROLL) {
                 int w[PEEL_UNROLL];
                 bool live[PEEL_UNROLL];
@@ -497,25 +508,28 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                         const unsigned old = atomicSub(&s_deg2[w[q] >> 1], 1u << sh);
                         if ((int)((old >> sh) & 0xFFFFu) == k + 1) {
                             atomicAnd(&s_alive[w[q] >> 5], ~(1u << (w[q] & 31)));
-                            sub[uverts[w[q]]] = r + 1;
                             join = true;
                         }
                     }
                     const int slot = wave_slot(join, &s_cnt);
-                    if (join) fput(cur ^ 1, slot, w[q]);
+                    if (join) s_Fq[nbase + slot] = (unsigned short)w[q];
                 }
             }
         }
         __syncthreads();
         left -= nF;
+        fbase = nbase;
         nF = s_cnt;
-        cur ^= 1;
         r++;
+        // the new frontier's decrements are over: its halves take its sub-round
+        for (int j = threadIdx.x; j < nF; j += blockDim.x) s_h16[s_Fq[fbase + j]] = (unsigned short)(r - r0);
         __syncthreads();
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
         if (r > n) break;  // each sub-round removes a vertex: never reached
     }
+    // keys of every vertex of U
+    for (int i = threadIdx.x; i < nu; i += blockDim.x) sub[uverts[i]] = r0 + (int)s_h16[i];
     if (threadIdx.x == 0) {
         ctl->subrounds = r;
         ctl->alpha = alpha;
