@@ -112,6 +112,19 @@ const char *pv_strerror(pv_status s);
 pv_status pv_init(int32_t device, void *stream, pv_ctx **out);
 void pv_fini(pv_ctx *ctx);
 
+/*
+ * Environment variables read by pv_init besides the tuning defaults below;
+ * none changes a result, they choose how the work is split:
+ *   PV_HU_BUDGET    bytes of device memory for the gathered neighbourhoods
+ *                   of heavy roots (|N+(v)| > 64) per pass over them; the
+ *                   roots are taken in as many chunks as that needs
+ *                   (default 2^30).
+ *   PV_PREFIX_ROWS  per-vertex counts: rows of N+(root) summed per on-chip
+ *                   pass when what the universes owe the vertices above them
+ *                   is added up per heavy root (default: as many as fit).
+ *   PV_DEBUG        per-level buffer demands and times on stderr.
+ */
+
 /* Change the stream later work is issued on (hipStream_t, may be NULL). */
 pv_status pv_set_stream(pv_ctx *ctx, void *stream);
 

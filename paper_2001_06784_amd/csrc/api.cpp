@@ -130,6 +130,8 @@ struct Workspace {
     DBuf<uint64_t> counts, ovf, vout_own;
     DBuf<int> omegas;
     DBuf<int> u_root;  // batches: root vertex of every universe
+    // per-vertex prefix sums grouped by heavy root
+    DBuf<int> u_grp, pg_cnt, pg_off, pg_pos, pg_list;
     // per-edge counts
     DBuf<int> ueid, weid;
     DBuf<uint64_t> umem, utot, escr;
@@ -138,7 +140,8 @@ struct Workspace {
 
     void release() {
         DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &lid, &uverts, &ldeg, &lrp, &lcol,
-                           &bcnt, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid};
+                           &bcnt, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid,
+                           &u_grp, &pg_cnt, &pg_off, &pg_pos, &pg_list};
         for (auto *b : ib) b->release();
         ctl.release();
         citem[0].release();
@@ -172,6 +175,7 @@ struct pv_ctx {
     int dfs_max = 64;
     int dfs_budget = 0;  // 0: chosen per request (see budget_of)
     int lane_max = PV_LANE_MAX;
+    int prefix_rows = 0;  // PV_PREFIX_ROWS: N+(root) rows per LDS pass of the prefix sums (0: all that fit)
     bool debug = false;  // PV_DEBUG set: per-level buffer demands on stderr
     Workspace ws;
     // batches: the union graph (reused between calls) and its part table
@@ -253,6 +257,11 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
     c->debug = getenv("PV_DEBUG") != nullptr;
     if (const char *env = getenv("PV_DFS_BUDGET")) c->dfs_budget = std::max(16, std::min(1 << 20, atoi(env)));
     if (const char *env = getenv("PV_LANE_MAX")) c->lane_max = std::max(0, std::min(PV_LANE_MAX, atoi(env)));
+    if (const char *env = getenv("PV_PREFIX_ROWS")) c->prefix_rows = std::max(0, atoi(env));
+    if (const char *env = getenv("PV_HU_BUDGET")) {
+        const long long b = atoll(env);
+        if (b > 0) c->ws.hu_budget = b;
+    }
     for (auto &ev : c->ev)
         if (hipEventCreate(&ev) != hipSuccess) {
             pv_fini(c);
@@ -643,7 +652,15 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             PVCHK(c->ws.u_pref.ensure(c->ws.u_cap));
             PVCHK(c->ws.pref_pool.ensure(c->ws.pref_cap));
         }
-        if (local && !rq.edge) PVCHK(c->ws.utot.ensure(c->ws.u_cap * 2 * rq.K * 2));
+        if (local && !rq.edge) {
+            PVCHK(c->ws.utot.ensure(c->ws.u_cap * 2 * rq.K * 2));
+            PVCHK(c->ws.u_grp.ensure(c->ws.u_cap));
+            PVCHK(c->ws.pg_pos.ensure(c->ws.u_cap));
+            PVCHK(c->ws.pg_list.ensure(c->ws.u_cap));
+            PVCHK(c->ws.pg_cnt.ensure((size_t)rq.nheavy + 1));
+            PVCHK(c->ws.pg_off.ensure((size_t)rq.nheavy + 1));
+            PVCHK(c->ws.scan.ensure((size_t)rq.nheavy / 1024 + 2));
+        }
         if (rq.edge) {
             PVCHK(c->ws.umem.ensure(c->ws.u_cap * 64 * 2 * rq.K * 2));
             PVCHK(c->ws.utot.ensure(c->ws.u_cap * 3 * rq.K * 2));
@@ -724,6 +741,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.pref_pool = c->ws.pref_pool.p;
                 a.pref_n = g->small.p + SM_PREFN;
                 a.pref_cap = (int)c->ws.pref_cap;
+                a.u_grp = c->ws.u_grp.p;
                 a.next = g->small.p + SM_NEXT;
                 a.hist = c->ws.hist.p;
                 a.hd = hd;
@@ -836,8 +854,16 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             // every level)
             const int blocks = std::max(1, std::min(c->dev.num_cu * 16, (int)((io[SM_UN] + 3) / 4)));
             if (io_fresh) {  // no level ran: no universe, nothing to add
-                if (rq.edge) HIPCHK(pv_launch_edge_prefix(c->d_args.p, blocks, s));
-                else HIPCHK(pv_launch_vertex_prefix(c->d_args.p, blocks, s));
+                if (rq.edge) {
+                    HIPCHK(pv_launch_edge_prefix(c->d_args.p, blocks, s));
+                } else {
+                    const PrefixWork pw{c->ws.pg_cnt.p, c->ws.pg_off.p, c->ws.pg_pos.p, c->ws.pg_list.p,
+                                        c->ws.scan.p};
+                    const int rmax = PV_PREFIX_SLOTS / rq.K - 1;
+                    const int rows = c->prefix_rows > 0 ? std::min(c->prefix_rows, rmax) : rmax;
+                    HIPCHK(pv_launch_vertex_prefix(c->d_args.p, std::min(io[SM_UN], (int)c->ws.u_cap), rq.nheavy,
+                                                   pw, rows, s));
+                }
                 HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
             }

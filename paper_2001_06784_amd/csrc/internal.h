@@ -99,7 +99,11 @@ struct LevelArgs {
     int *u_gid;              // [cap][64]   (local counts only)
     int2 *u_pref;            // [cap] {offset, length} into pref pool (local only)
     int *u_n, u_cap;
+    // prefix entries: the root's id, then hold / pivot vertices (bit 31 set
+    // for a pivot); per vertex, those of a multi-word universe are local
+    // indices into N+(root), per edge they are vertex ids
     int *pref_pool, *pref_n, pref_cap;
+    int *u_grp;              // [cap] per vertex: the heavy-root index of a multi-word universe, else -1
     // work cursors, one per unit kind.  A claim takes chunk c < nch[kind]:
     // units c, c + nch, c + 2 nch, ... below n0[kind]; claims past nch take
     // one unit each from n0 on
@@ -165,7 +169,18 @@ static inline int pv_root_chunks(int n) {
 hipError_t pv_launch_level(const LevelArgs *a, int kl, int lk, int mode, int blocks, hipStream_t s);
 int pv_level_blocks_per_cu(int kl, int lk, int mode);
 hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s);
-hipError_t pv_launch_vertex_prefix(const LevelArgs *a, int blocks, hipStream_t s);
+// per-vertex prefix sums, grouped by heavy root (max_units >= universes made;
+// ngroups = number of heavy roots; rows: N+(root) rows summed per LDS pass,
+// at most PV_PREFIX_SLOTS / K - 1)
+#define PV_PREFIX_SLOTS 2048
+#define PV_PREFIX_SLICE 64
+struct PrefixWork {
+    int *gcnt, *goff, *gpos, *glist, *scan_tmp;  // [ngroups], [ngroups+1], [u_cap], [u_cap], scan temp
+};
+hipError_t pv_launch_vertex_prefix(const LevelArgs *a, int max_units, int ngroups, const PrefixWork &w,
+                                   int rows, hipStream_t s);
+// exclusive scan: out[i] = sum_{j<i} in[j] for i <= n; tmp: n / 1024 + 2 ints
+hipError_t pv_launch_excl_scan(int n, const int *in, int *tmp, int *out, hipStream_t s);
 // per-edge ids: o2e[q] = lexicographic id of the edge at oriented position q
 hipError_t pv_launch_edge_ids(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
                               const int *orow, int *ucnt, int *up, int *o2e, int *scan_tmp,

@@ -888,18 +888,22 @@ hipError_t pv_launch_peel(const DevInfo &dev, const PeelArgs &pa, hipStream_t s)
                                       args, 0, s);
 }
 
+hipError_t pv_launch_excl_scan(int n, const int *in, int *tmp, int *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    scan_reduce_kernel<<<nb, 256, 0, s>>>(n, in, tmp);
+    scan_blocks_kernel<<<1, 1024, 0, s>>>(nb, tmp);
+    scan_apply_kernel<<<nb, 1024, 0, s>>>(n, in, tmp, out);
+    return hipGetLastError();
+}
+
 hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
                             int *odeg, int *orow, int *ocol, int *alpha, int *scan_tmp,
                             hipStream_t s) {
     // a wave takes 64 vertices per step
     const int wblocks = grid_for((long long)n, 256, dev.num_cu * 32);
     odeg_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, odeg, alpha);
-    const int nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    if (n > 0) {
-        scan_reduce_kernel<<<nb, 256, 0, s>>>(n, odeg, scan_tmp);
-        scan_blocks_kernel<<<1, 1024, 0, s>>>(nb, scan_tmp);
-        scan_apply_kernel<<<nb, 1024, 0, s>>>(n, odeg, scan_tmp, orow);
-    }
+    (void)pv_launch_excl_scan(n, odeg, scan_tmp, orow, s);
     ofill_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, orow, ocol);
     return hipGetLastError();
 }

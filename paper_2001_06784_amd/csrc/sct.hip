@@ -554,7 +554,7 @@ struct Ctr {
 
 template <int KL, int LK>
 __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelArgs &a,
-                             int root, uint64_t Hw, uint64_t Pw, const int *vl, int W,
+                             int root, int grp, uint64_t Hw, uint64_t Pw, const int *vl, int W,
                              int2 &pref, const int *src_etab);
 
 // ------------------------------------------------------------ lane tier
@@ -965,7 +965,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
         if (nodes >= limit && depth > 0) {
             if (uni < 0) {
                 int2 pref;
-                uni = make_universe<KL, LK>(A, nm, gid, lane, a, root, 0ull, 0ull, nullptr, 0, pref,
+                uni = make_universe<KL, LK>(A, nm, gid, lane, a, root, -1, 0ull, 0ull, nullptr, 0, pref,
                                               EDGE ? vs.etab_ptr() : nullptr);
                 if (uni < 0) break;  // buffers full: the host reruns with larger ones
             }
@@ -1103,7 +1103,7 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
 // adds to later).
 template <int KL, int LK>
 __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelArgs &a,
-                             int root, uint64_t Hw, uint64_t Pw, const int *vl, int W,
+                             int root, int grp, uint64_t Hw, uint64_t Pw, const int *vl, int W,
                              int2 &pref, const int *src_etab) {
     constexpr bool EDGE = LK == PV_LK_EDGE;
     constexpr bool LOCAL = KL > 0;
@@ -1116,6 +1116,7 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
     }
     a.u_rows[(long long)uni * 64 + lane] = (lane < nm) ? A : 0ull;
     if (a.vgraph && lane == 0) a.u_root[uni] = root;  // batch: names the universe's graph
+    if (LOCAL && !EDGE && lane == 0) a.u_grp[uni] = grp;
     pref = make_int2(0, 0);
     if (LOCAL) {
         a.u_gid[(long long)uni * 64 + lane] = (lane < nm) ? gid : -1;
@@ -1134,10 +1135,11 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
             for (int w = 0; w < W; w++) {
                 const uint64_t hw = readlane64(Hw, w), pw = readlane64(Pw, w);
                 const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                if ((hw >> lane) & 1) a.pref_pool[cur + __popcll(hw & below)] = vl[w * 64 + lane];
+                // per vertex: local indices (grouped by heavy root later); per edge: ids
+                const int x = EDGE ? vl[w * 64 + lane] : w * 64 + lane;
+                if ((hw >> lane) & 1) a.pref_pool[cur + __popcll(hw & below)] = x;
                 cur += __popcll(hw);
-                if ((pw >> lane) & 1)
-                    a.pref_pool[cur + __popcll(pw & below)] = (int)(vl[w * 64 + lane] | 0x80000000u);
+                if ((pw >> lane) & 1) a.pref_pool[cur + __popcll(pw & below)] = (int)((unsigned)x | 0x80000000u);
                 cur += __popcll(pw);
             }
             pref = make_int2(off, tot);
@@ -1236,7 +1238,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
             int uni = -1;
             // the root and the multi-word holds/pivots form the prefix
             if (s > a.dfs_max || LOCAL) {
-                uni = make_universe<KL, LK>(A, s, gid, lane, a, root, Hw, Pw, vl, W, pref, nullptr);
+                uni = make_universe<KL, LK>(A, s, gid, lane, a, root, a.heavy_base + hu, Hw, Pw, vl, W, pref, nullptr);
                 if (uni < 0) return false;  // buffers full: the host reruns with larger ones
             }
             cs.A = A;
@@ -1541,7 +1543,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, 3) sct_level_kernel(cons
             int uni = -1;
             int2 pref = make_int2(0, 0);
             if (d > a.dfs_max) {
-                uni = make_universe<KL, LK>(A, d, gid, lane, a, v, 0ull, 0ull, nullptr, 0, pref, etab_w);
+                uni = make_universe<KL, LK>(A, d, gid, lane, a, v, -1, 0ull, 0ull, nullptr, 0, pref, etab_w);
                 if (uni < 0) continue;  // buffers full: the host reruns with larger ones
             }
             const int root = (uni < 0) ? v : -1;
@@ -1620,26 +1622,175 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
 }
 
 // Per-vertex counts: what each universe's walks owe the vertices above it
-// (its prefix: hold or pivot), added once per universe after the last level.
-__global__ void __launch_bounds__(256) vertex_prefix_kernel(const LevelArgs *__restrict__ pa) {
+// (its prefix: the root, then hold or pivot vertices), added once after the
+// last level.  The universes of one heavy root share most of their prefix
+// (siblings differ in one vertex), so adding every entry straight to HBM
+// makes their atomics on one line wait for each other.  Instead the
+// universes are grouped by heavy root, each group's totals are summed per
+// prefix vertex in LDS, and each sum reaches HBM with one atomic per k.
+// In the pool, a multi-word universe's entries after the root are local
+// indices into N+(root) (oriented CSR order); other universes hold the root
+// alone.
+
+// 128-bit add into LDS (two 64-bit atomics, the carry between them)
+__device__ __forceinline__ bool lds_add_u128(uint64_t *p, uint64_t lo, uint64_t hi) {
+    bool ovf = false;
+    if (lo) {
+        const uint64_t old = __hip_atomic_fetch_add(p, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old + lo < old) {
+            hi += 1;
+            if (hi == 0) ovf = true;
+        }
+    }
+    if (hi) {
+        const uint64_t old = __hip_atomic_fetch_add(p + 1, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old + hi < old) ovf = true;
+    }
+    return ovf;
+}
+
+// Pass 1: each grouped universe takes its position in its heavy root's
+// group (one counter atomic per distinct group of a wave); a universe of a
+// light root adds its totals to the root directly.
+__global__ void __launch_bounds__(256) prefix_count_kernel(const LevelArgs *__restrict__ pa,
+                                                           int *__restrict__ gcnt, int *__restrict__ gpos) {
     const LevelArgs &a = *pa;
     const int lane = threadIdx.x & 63;
     const int nu = min(*a.u_n, a.u_cap);
     const int K = a.K;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool ovf = false;
-    for (int u = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; u < nu; u += nwaves) {
-        const int2 pref = a.u_pref[u];
-        const uint64_t *tot = a.utot + 2 * ((long long)u * 2 * K);
-        if (lane >= K) continue;
-        const uint64_t hl = tot[2 * lane], hh = tot[2 * lane + 1];
-        const uint64_t pl = tot[2 * (K + lane)], ph = tot[2 * (K + lane) + 1];
-        for (int i = 0; i < pref.y; i++) {
-            const int e = a.pref_pool[pref.x + i];
-            const int x = e & 0x7fffffff;
-            const bool isP = (e >> 31) & 1;
-            const uint64_t l = isP ? pl : hl, h = isP ? ph : hh;
-            if (l | h) ovf |= atomic_add_u128(a.vout + 2 * ((long long)x * a.kstride + lane), l, h);
+    for (int u0 = blockIdx.x * blockDim.x; u0 < nu; u0 += gridDim.x * blockDim.x) {
+        const int u = u0 + (int)threadIdx.x;
+        const int g = (u < nu) ? a.u_grp[u] : -1;
+        bool pending = g >= 0;
+        for (uint64_t bl = ballot64(pending); bl; bl = ballot64(pending)) {
+            const int lead = __builtin_ctzll(bl);
+            const int lg = (int)readlane32((uint32_t)g, lead);
+            const bool mine = pending && g == lg;
+            const uint64_t m = ballot64(mine);
+            int base = 0;
+            if (lane == lead) base = atomicAdd(&gcnt[lg], __popcll(m));
+            base = (int)readlane32((uint32_t)base, lead);
+            if (mine) {
+                gpos[u] = base + __popcll(m & below);
+                pending = false;
+            }
+        }
+        if (u < nu && g < 0) {
+            const int2 pref = a.u_pref[u];
+            const uint64_t *tot = a.utot + 2 * ((long long)u * 2 * K);
+            for (int i = 0; i < pref.y; i++) {
+                const int e = a.pref_pool[pref.x + i];
+                const uint64_t *t = tot + (((e >> 31) & 1) ? 2 * K : 0);
+                uint64_t *dst = a.vout + 2 * ((long long)(e & 0x7fffffff) * a.kstride);
+                uint64_t lo[PV_MAX_LOCAL_K], old[PV_MAX_LOCAL_K];
+#pragma unroll
+                for (int kk = 0; kk < PV_MAX_LOCAL_K; kk++) {
+                    lo[kk] = (kk < K) ? t[2 * kk] : 0ull;
+                    old[kk] = atomic_add_u128_lo(dst + 2 * kk, lo[kk]);
+                }
+#pragma unroll
+                for (int kk = 0; kk < PV_MAX_LOCAL_K; kk++) asm volatile("" : "+v"(old[kk]));
+#pragma unroll
+                for (int kk = 0; kk < PV_MAX_LOCAL_K; kk++)
+                    if (kk < K) ovf |= atomic_add_u128_hi(dst + 2 * kk, lo[kk], old[kk], t[2 * kk + 1]);
+            }
+        }
+    }
+    if (ovf) atomicOr(a.lovf, 1);
+}
+
+// Pass 3: universes listed group by group
+__global__ void __launch_bounds__(256) prefix_scatter_kernel(const LevelArgs *__restrict__ pa,
+                                                             const int *__restrict__ goff,
+                                                             const int *__restrict__ gpos,
+                                                             int *__restrict__ glist) {
+    const LevelArgs &a = *pa;
+    const int nu = min(*a.u_n, a.u_cap);
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+        const int g = a.u_grp[u];
+        if (g >= 0) glist[goff[g] + gpos[u]] = u;
+    }
+}
+
+// Pass 4: a workgroup takes PV_PREFIX_SLICE consecutive entries of the
+// grouped list; per group segment it sums the totals owed to each prefix
+// vertex in LDS (rows: N+(root) indices r0 .. r0+rows-1 per pass, plus one
+// row for the root) and adds the nonzero sums to HBM.
+__global__ void __launch_bounds__(256) prefix_group_kernel(const LevelArgs *__restrict__ pa, int ngroups,
+                                                           const int *__restrict__ goff,
+                                                           const int *__restrict__ glist, int rows) {
+    __shared__ uint64_t s_acc[2 * PV_PREFIX_SLOTS];
+    const LevelArgs &a = *pa;
+    const int K = a.K, ks = a.kstride;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    // a wave adds E = 64 / K prefix entries side by side: lane = slot * K + kk
+    const int E = 64 / K;
+    const int slot = lane / K, kk = lane - slot * K;
+    const bool act = slot < E;
+    const int R = rows;  // (R + 1) * K <= PV_PREFIX_SLOTS
+    const int total = goff[ngroups];
+    bool ovf = false;
+    for (int p0 = blockIdx.x * PV_PREFIX_SLICE; p0 < total; p0 += gridDim.x * PV_PREFIX_SLICE) {
+        const int p1 = min(p0 + PV_PREFIX_SLICE, total);
+        // the group holding entry p0: the last g with goff[g] <= p0
+        int lo = 0, hi = ngroups - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (goff[mid] <= p0) lo = mid; else hi = mid - 1;
+        }
+        for (int g = lo; g < ngroups && goff[g] < p1; g++) {
+            const int q0 = max(p0, goff[g]), q1 = min(p1, goff[g + 1]);
+            if (q0 >= q1) continue;
+            const int root = a.order[g];
+            const int rb = a.orow[root], d = a.orow[root + 1] - rb;
+            for (int r0 = 0; r0 == 0 || r0 < d; r0 += R) {
+                // rows in use: local indices r0 .. r0+nr-1, then the root's row
+                const int nr = max(0, min(R, d - r0));
+                const int nslot = (nr + 1) * K;
+                for (int i = threadIdx.x; i < nslot; i += blockDim.x) {
+                    const bool mem = i < nr * K;
+                    const int row = mem ? i / K : R;
+                    const int j = row * K + (mem ? i - row * K : i - nr * K);
+                    s_acc[2 * j] = 0ull;
+                    s_acc[2 * j + 1] = 0ull;
+                }
+                __syncthreads();
+                for (int q = q0 + wv; q < q1; q += nwv) {
+                    const int u = glist[q];
+                    const int2 pref = a.u_pref[u];
+                    if (!act) continue;
+                    const uint64_t *tot = a.utot + 2 * ((long long)u * 2 * K);
+                    const uint64_t hl = tot[2 * kk], hh = tot[2 * kk + 1];
+                    const uint64_t pl = tot[2 * (K + kk)], ph = tot[2 * (K + kk) + 1];
+                    if ((hl | hh | pl | ph) == 0) continue;
+                    for (int i = slot; i < pref.y; i += E) {
+                        const int e = a.pref_pool[pref.x + i];
+                        int row = -1;
+                        if (i == 0) {
+                            if (r0 == 0) row = R;  // the root (a global id)
+                        } else {
+                            const int jj = (e & 0x7fffffff) - r0;
+                            if (jj >= 0 && jj < nr) row = jj;
+                        }
+                        if (row < 0) continue;
+                        const bool isP = (e >> 31) & 1;
+                        ovf |= lds_add_u128(&s_acc[2 * (row * K + kk)], isP ? pl : hl, isP ? ph : hh);
+                    }
+                }
+                __syncthreads();
+                for (int i = threadIdx.x; i < nslot; i += blockDim.x) {
+                    const bool mem = i < nr * K;
+                    const int row = mem ? i / K : R;
+                    const int k2 = mem ? i - row * K : i - nr * K;
+                    const uint64_t l = s_acc[2 * (row * K + k2)], h = s_acc[2 * (row * K + k2) + 1];
+                    if ((l | h) == 0) continue;
+                    const int x = mem ? a.ocol[rb + r0 + row] : root;
+                    ovf |= atomic_add_u128(a.vout + 2 * ((long long)x * ks + k2), l, h);
+                }
+                __syncthreads();
+            }
         }
     }
     if (ovf) atomicOr(a.lovf, 1);
@@ -1845,8 +1996,18 @@ hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t pv_launch_vertex_prefix(const LevelArgs *a, int blocks, hipStream_t s) {
-    vertex_prefix_kernel<<<blocks, 256, 0, s>>>(a);
+hipError_t pv_launch_vertex_prefix(const LevelArgs *a, int max_units, int ngroups, const PrefixWork &w,
+                                   int rows, hipStream_t s) {
+    if (max_units <= 0) return hipSuccess;
+    const int ub = (max_units + 255) / 256;
+    hipError_t e = hipSuccess;
+    if (ngroups > 0 && (e = hipMemsetAsync(w.gcnt, 0, (size_t)ngroups * sizeof(int), s)) != hipSuccess) return e;
+    prefix_count_kernel<<<ub, 256, 0, s>>>(a, w.gcnt, w.gpos);
+    if (ngroups <= 0) return hipGetLastError();
+    if ((e = pv_launch_excl_scan(ngroups, w.gcnt, w.scan_tmp, w.goff, s)) != hipSuccess) return e;
+    prefix_scatter_kernel<<<ub, 256, 0, s>>>(a, w.goff, w.gpos, w.glist);
+    prefix_group_kernel<<<(max_units + PV_PREFIX_SLICE - 1) / PV_PREFIX_SLICE, 256, 0, s>>>(a, ngroups, w.goff,
+                                                                                           w.glist, rows);
     return hipGetLastError();
 }
 

@@ -551,3 +551,74 @@ def test_truncation_heavy_roots(ctx, kmax):
     ref = O.count(g, vertex=(2, kmax), edge=(2, min(kmax, 9)))
     assert ovf == 0 and np.array_equal(out, ref.vertex)
     assert eovf == 0 and np.array_equal(eout, ref.edge)
+
+
+# ------------------------------------- heavy roots: prefix sums and chunks
+
+def _ctx_env(**env):
+    """A fresh context created while the given environment variables are set."""
+    saved = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return P.pv_init(0)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+HEAVY = [("heavy", lambda: gg.plant_cliques(gg.gnp(400, 0.04, 44), [90, 12], 45), (3, 10)),
+         ("heavy_dense", lambda: gg.plant_cliques(gg.gnp(160, 0.45, 146), [75, 40], 147), (2, 9)),
+         ("K129", lambda: gg.complete(129), (1, 16))]
+_HEAVY_REF = {}
+
+
+def _heavy_case(name):
+    if name not in _HEAVY_REF:
+        maker, (klo, khi) = {x[0]: (x[1], x[2]) for x in HEAVY}[name]
+        g = maker()
+        ref = O.count(g, vertex=(klo, khi), edge=(2, min(khi, 6)))
+        _HEAVY_REF[name] = (g, klo, khi, ref)
+    return _HEAVY_REF[name]
+
+
+@pytest.mark.parametrize("rows", [1, 7, 0])
+@pytest.mark.parametrize("name", [x[0] for x in HEAVY])
+def test_per_vertex_prefix_passes(name, rows):
+    # what the universes of a heavy root owe the vertices above them is
+    # summed per heavy root on chip, `rows` vertices of N+(root) per pass
+    # (0: as many as fit); any pass size gives the same counts
+    g, klo, khi, ref = _heavy_case(name)
+    _say(f"[parity] per-vertex prefix passes {name}: n={g.n} m={g.m} k={klo}..{khi} rows={rows}")
+    c = _ctx_env(PV_PREFIX_ROWS=rows)
+    try:
+        with Loaded(c, g) as h:
+            out, ovf, st = P.pv_count_local(h, P.PV_VERTEX, klo, khi)
+    finally:
+        P.pv_fini(c)
+    assert ovf == 0
+    assert np.array_equal(out, ref.vertex)
+
+
+@pytest.mark.parametrize("name", [x[0] for x in HEAVY])
+def test_heavy_roots_in_chunks(name):
+    # a 1-byte budget for gathered neighbourhoods takes the heavy roots one
+    # per chunk: global, per-vertex and per-edge results are unchanged
+    g, klo, khi, ref = _heavy_case(name)
+    _say(f"[parity] heavy roots one per chunk {name}: n={g.n} m={g.m}")
+    c = _ctx_env(PV_HU_BUDGET=1)
+    try:
+        with Loaded(c, g) as h:
+            res = P.pv_count_global(h, 0)
+            out, ovf, st = P.pv_count_local(h, P.PV_VERTEX, klo, khi)
+            eout, eovf, est = P.pv_count_local(h, P.PV_EDGE, 2, min(khi, 6))
+    finally:
+        P.pv_fini(c)
+    top = len(ref.glob)
+    assert [res.counts[k] for k in range(top)] == [int(x) for x in ref.glob]
+    assert res.stats["nodes"] == ref.stats["nodes"] and res.stats["leaves"] == ref.stats["leaves"]
+    assert ovf == 0 and eovf == 0
+    assert np.array_equal(out, ref.vertex)
+    assert np.array_equal(eout, ref.edge)
