@@ -249,6 +249,17 @@ def chung_lu_social(n: int = 1_000_000, avg_deg: float = 20.0, gamma: float = 2.
     return chung_lu(n, avg_deg, gamma, max_deg, seed)
 
 
+def rmat_web(scale: int = 22, edge_factor: int = 24, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+             seed: int = 1, cliques: int = 50, clique_lo: int = 20, clique_hi: int = 60,
+             plant_seed: int = 2) -> Graph:
+    """Heavy-tailed web-like stand-in: R-MAT plus `cliques` cliques whose sizes
+    are uniform on {clique_lo..clique_hi}, planted on disjoint random vertex
+    sets (sizes and sets drawn from plant_seed)."""
+    g = rmat(scale, edge_factor, a, b, c, seed)
+    sizes = _rng(plant_seed).integers(clique_lo, clique_hi + 1, cliques)
+    return plant_cliques(g, sizes, plant_seed + 1)
+
+
 def batch_graph_specs(count: int = 4096, n_lo: int = 50, n_hi: int = 5000,
                       deg_lo: float = 8.0, deg_hi: float = 40.0, seed: int = 1000):
     """(n, avg_deg, seed) of each member of a batch of small Chung-Lu graphs:
