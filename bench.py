@@ -11,10 +11,14 @@ pv_count call.
 Prints one JSON line.  value = undirected edges / second of wall time per
 step; leaves_per_s = SCT leaves / second.
 
-Two more workloads are selected with --workload:
+Other workloads are selected with --workload:
   batch  4096 small Chung-Lu graphs (n log-uniform in [50, 5000], average
          degree uniform in [8, 40], exponent 2.5), global counts for all k:
          one batched union pass against one call per graph (graphs/s).
+  rmat   global counts for all k on an R-MAT graph (--scale, edge factor 24,
+         a/b/c = 0.57/0.19/0.19) with 50 planted cliques of 20..60 vertices;
+         --edge adds per-edge counts for k = 3..8.  Scale 22 itself is a
+         parity case: its tree is far too large to walk whole.
   serve  an open-loop Poisson stream (200 requests/s) over a pool of 256
          Chung-Lu graphs (edge counts log-uniform in [1e3, 2e6], exponent
          2.5); graph per request Zipf(1.1) over the pool, type 50/50 global
@@ -139,7 +143,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["social", "batch", "serve", "copy"], default="social")
+    ap.add_argument("--workload", choices=["social", "batch", "serve", "copy", "rmat"], default="social")
+    ap.add_argument("--scale", type=int, default=14, help="rmat: log2 of the vertex count")
+    ap.add_argument("--edge", action="store_true", help="rmat: also per-edge counts for k=3..8")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: measured seconds")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -153,6 +159,8 @@ def main():
         return bench_serve(args)
     if args.workload == "copy":
         return bench_copy()
+    if args.workload == "rmat":
+        return bench_rmat(args)
 
     import torch
     from paper_2001_06784_amd import pivoter as P
@@ -291,6 +299,57 @@ def bench_batch(args):
                   "p99_ms_per_graph": 1e3 * float(np.percentile(lat, 99))},
         "batched_over_plain": (len(hs) / dt) / (len(hs) / dt_plain),
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_rmat(args):
+    """Whole-graph global counts for all k on an R-MAT graph with 50 planted
+    cliques (the web-like workload at a scale small enough to finish); the
+    warm-up call also sizes the work buffers, so timed calls walk the tree
+    once.  With --edge, per-edge counts for k = 3..8 as well."""
+    import torch
+    from paper_2001_06784_amd import graphgen as gg
+    from paper_2001_06784_amd import pivoter as P
+    t0 = time.perf_counter()
+    g = gg.rmat_web(scale=args.scale)
+    print(f"[bench] rmat scale {args.scale}: n={g.n} m={g.m} generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    ctx = P.pv_init(0, torch.cuda.current_stream().cuda_stream)
+    h = P.pv_graph_load_csr(ctx, g.n, g.row_ptr, g.col)
+    for i in range(max(1, args.warmup)):
+        t1 = time.perf_counter()
+        P.pv_count_global(h)
+        print(f"[bench] warm-up {i}: {time.perf_counter() - t1:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = P.pv_count_global(h)
+        print(f"[bench] step {i}: {time.perf_counter() - t0:.2f} s so far", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    st = res.stats
+    line = {
+        "metric": "graph edges/sec and SCT leaves/sec for all-k counts", "value": g.m / dt, "unit": "edges/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": max(1, args.warmup), "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u128",
+        "data": "synthetic", "leaves_per_s": st["leaves"] / dt,
+        "config": {"workload": (f"rmat scale={args.scale} edge_factor=24 a=0.57 b=0.19 c=0.19 seed=1 "
+                                "+ 50 planted cliques of 20..60; global counts all k"),
+                   "n": g.n, "m": g.m, "alpha": st["alpha"], "omega": res.omega,
+                   "sct_nodes": st["nodes"], "sct_leaves": st["leaves"], "overflow_k": res.overflow},
+    }
+    if args.edge:
+        P.pv_count_local(h, P.PV_EDGE, 3, 8)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out, ovf, est = P.pv_count_local(h, P.PV_EDGE, 3, 8)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t1
+        # the call returns the m x 6 u128 counts in host memory (copy included)
+        line["per_edge_k3_8"] = {"s": te, "edges_per_s": g.m / te, "overflow": int(ovf),
+                                 "sct_nodes": est["nodes"], "sct_leaves": est["leaves"]}
+    P.pv_graph_free(h)
+    P.pv_fini(ctx)
     print(json.dumps(line), flush=True)
 
 
