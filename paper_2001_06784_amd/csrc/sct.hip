@@ -37,10 +37,12 @@
 // ------------------------------------------------------------------ sinks
 
 // Global counts: leaf (h,p) -> L[h][p] += 1.  The workgroup keeps the bins
-// h < PV_LDS_H, p < 64 as u64 counters in LDS (one LDS atomic per leaf, no
+// h < lds_h, p < 64 as u64 counters in LDS (one LDS atomic per leaf, no
 // hot global addresses: in dense cores most leaves share a handful of (h,p)
 // bins); rarer leaves go straight to the device histogram.  The LDS bins
-// are added to the device histogram when the workgroup ends.
+// are added to the device histogram when the workgroup ends.  lds_h is 32,
+// or 16 in the kernels whose lane-tier member slots need the LDS (so that
+// four workgroups fit a CU).
 #define PV_LDS_H 32
 //
 // A batch of graphs is counted as one disjoint union: every graph has its
@@ -50,16 +52,17 @@
 typedef __attribute__((address_space(3))) unsigned long long lds_u64;
 
 struct GlobalSink {
-    lds_u64 *bins;              // LDS [PV_LDS_H][64], shared by the workgroup
+    lds_u64 *bins;              // LDS [lds_h][64], shared by the workgroup
     unsigned long long *hist;   // wave-uniform copies of the arguments
     unsigned long long *ghist;  // batch: the current graph's histogram
     const int *vgraph;          // batch: graph of every vertex (nullptr: one graph)
-    int hd;
+    int hd, lds_h;
     unsigned long long leaves;
 
-    __device__ void init(const LevelArgs &a, unsigned long long *lds_bins) {
+    __device__ void init(const LevelArgs &a, unsigned long long *lds_bins, int rows) {
         // an LDS-typed pointer: the bin update is a ds_add, not a flat atomic
         bins = (lds_u64 *)lds_bins;
+        lds_h = rows;
         hist = (unsigned long long *)uniform64((uint64_t)a.hist);
         vgraph = (const int *)uniform64((uint64_t)a.vgraph);
         hd = uniformi(a.hd);
@@ -77,7 +80,7 @@ struct GlobalSink {
     __device__ __forceinline__ void leaf(int h, int p, int lane) {
         if (vgraph) {
             if (lane == 0) atomicAdd(&ghist[(long long)h * hd + p], 1ull);
-        } else if (h < PV_LDS_H && p < 64) {
+        } else if (h < lds_h && p < 64) {
             if (lane == 0)
                 __hip_atomic_fetch_add(&bins[h * 64 + p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         } else if (lane == 0) {
@@ -89,7 +92,7 @@ struct GlobalSink {
     __device__ __forceinline__ void leaf_lane(int h, int p) {
         if (vgraph)
             atomicAdd(&ghist[(long long)h * hd + p], 1ull);
-        else if (h < PV_LDS_H && p < 64)
+        else if (h < lds_h && p < 64)
             __hip_atomic_fetch_add(&bins[h * 64 + p], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
             atomicAdd(&hist[(long long)h * hd + p], 1ull);
@@ -1436,18 +1439,32 @@ struct Claim {
     }
 };
 
+// The per-vertex kernels with 64-bit visit sums (the lane tier's member
+// slots in LDS) are held to 128 VGPRs and 16 LDS histogram rows, so that
+// four waves share a SIMD: the walk is bound by the latency of each node's
+// dependent steps, and the fourth wave hides more of it than the registers
+// spilled to scratch cost.
+template <int KL, int LK>
+struct LevelShape {
+    static constexpr bool V64 = KL == 8 && LK == PV_LK_VERTEX64;
+    static constexpr int waves_per_simd = V64 ? 4 : 3;
+    static constexpr int lds_h = V64 ? 16 : PV_LDS_H;
+};
+
 template <int KL, int MODE, int LK>
-__global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, 3) sct_level_kernel(const LevelArgs *__restrict__ pa) {
+__global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::waves_per_simd))
+    sct_level_kernel(const LevelArgs *__restrict__ pa) {
     constexpr bool EDGE = LK == PV_LK_EDGE;
     constexpr bool LOCAL = KL > 0;
+    constexpr int LDS_H = LevelShape<KL, LK>::lds_h;
     const LevelArgs &a = *pa;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    __shared__ unsigned long long s_bins[PV_LDS_H * 64];
-    for (int i = threadIdx.x; i < PV_LDS_H * 64; i += blockDim.x) s_bins[i] = 0ull;
+    __shared__ unsigned long long s_bins[LDS_H * 64];
+    for (int i = threadIdx.x; i < LDS_H * 64; i += blockDim.x) s_bins[i] = 0ull;
     __syncthreads();
     GlobalSink gs;
-    gs.init(a, s_bins);
+    gs.init(a, s_bins, LDS_H);
     typename SinkOf<KL, LK>::T vs;
     __shared__ uint64_t s_xch[WAVES_PER_BLOCK][EDGE ? 4 * KL : 1];
     if (LOCAL) vs.init(a, s_xch[wv], EDGE ? a.escr_wave0[MODE] : 0);
@@ -1558,7 +1575,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, 3) sct_level_kernel(cons
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < PV_LDS_H * 64; i += blockDim.x) {
+    for (int i = threadIdx.x; i < LDS_H * 64; i += blockDim.x) {
         const int h = i >> 6, p = i & 63;
         if (s_bins[i] && h < a.hd && p < a.hd) atomicAdd(&a.hist[(long long)h * a.hd + p], s_bins[i]);
     }
