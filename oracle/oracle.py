@@ -155,3 +155,28 @@ def count(g, key=None, prio=None, roots=None, kmax: int = 0, vertex=None, edge=N
     if key is not None and subrounds:
         st["subrounds"] = subrounds
     return Result(list(limbs_to_int(glob)), govf, vc, vovf, ec, eovf, hist, st)
+
+
+def counts_exact(g, key=None, roots=None, kmax: int = 0) -> tuple[list[int], int]:
+    """Global counts of any width: the oracle's own walk records the SCT leaf
+    histogram L[h][p] (the leaves of Alg. 1; with kmax, the truncated tree
+    of Sec. 5), and Sec. 5's read-off C_k = sum over h, p of L[h][p] C(p, k - h)
+    is evaluated with exact Python integers.  C_0 = 1 for the whole graph
+    (the empty clique), 0 for a root subset.  Returns (C_0..C_omega, omega)."""
+    import math
+    key_a = peel(g).sub if key is None else key
+    alpha = int(out_degrees(g, key_a).max()) if g.n else 0
+    hd = alpha + 2
+    r = count(g, key=key_a, roots=roots, kmax=kmax, hist_dim=hd)
+    if r.stats["hist_out"]:
+        raise RuntimeError("leaf outside the histogram")
+    L = r.hist
+    omega = r.omega
+    top = min(omega, kmax) if kmax else omega
+    out = [0] * (top + 1)
+    out[0] = 0 if roots is not None else 1
+    nz = [(h, p, int(L[h, p])) for h, p in zip(*np.nonzero(L))]
+    for k in range(1, top + 1):
+        out[k] = sum(c * math.comb(p, k - h) for h, p, c in nz if 0 <= k - h <= p)
+    return out, (top if kmax else omega)
+

@@ -351,3 +351,51 @@ def test_overflow_of_a_single_leaf():
         assert bool(r.glob_ovf[1 + i]) == big, i
         if not big:
             assert r.glob[1 + i] == comb(132, i)
+
+
+# ------------------------------------------- exact counts of any width
+
+def _elementary_symmetric(parts):
+    """e_0..e_r of the part sizes: the k-clique counts of the complete
+    multipartite graph (one vertex from each of k distinct parts)."""
+    e = [1]
+    for a in parts:
+        e = [x + (a * e[i - 1] if i else 0) for i, x in enumerate(e + [0])]
+    return e
+
+
+@pytest.mark.parametrize("n", [140, 200])
+def test_exact_counts_complete_graph(n):
+    # C_k = C(n, k) for every k, far past 2^128 in the middle
+    counts, omega = O.counts_exact(gg.complete(n))
+    assert omega == n
+    assert counts == [comb(n, k) for k in range(n + 1)]
+
+
+def test_exact_counts_multipartite_closed_form():
+    # 150 singleton parts and parts of 2, 3 and 3 vertices: omega = 153 and
+    # C_k = e_k(part sizes), which passes 2^128
+    parts = [1] * 150 + [2, 3, 3]
+    counts, omega = O.counts_exact(gg.complete_multipartite(parts))
+    want = _elementary_symmetric(parts)
+    assert omega == len(parts)
+    assert counts == want
+    assert max(want) >= 2 ** 128
+
+
+def test_exact_counts_match_the_u128_read_off():
+    # where C_k fits 128 bits the exact read-off equals the walk's own sums
+    g = gg.plant_cliques(gg.gnp(300, 0.05, 51), [40, 25], 52)
+    r = O.count(g)
+    counts, omega = O.counts_exact(g)
+    assert omega == r.omega
+    assert counts == r.glob[: omega + 1]
+
+
+def test_exact_counts_truncated_and_root_subset():
+    # truncated at k_max = 12: C(150, k) up to 12 (Sec. 5's shortcut keeps them exact)
+    counts, top = O.counts_exact(gg.complete(150), kmax=12)
+    assert top == 12 and counts == [comb(150, k) for k in range(13)]
+    # the root subproblem of vertex 0 of K_150 alone: one leaf (1, 149)
+    counts, omega = O.counts_exact(gg.complete(150), roots=np.array([0], dtype=np.int32))
+    assert counts == [0] + [comb(149, i) for i in range(150)]
