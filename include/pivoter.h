@@ -215,6 +215,23 @@ pv_status pv_count_global(pv_graph *g, int32_t k_max, pv_u128 *counts, int32_t c
                           int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats);
 
 /*
+ * Global counts C_k wider than 128 bits (Sec. 5's read-off, C_k = the sum
+ * over SCT leaves (h, p) of C(p, k - h), done in multi-limb integers; the
+ * paper's graphs with a clique number above about 130 need it).  Same tree
+ * and same k_max rule as pv_count_global.
+ *   counts: host memory, [cap][limbs] uint64, little-endian limbs:
+ *           counts[k * limbs + i] holds bits 64i..64i+63 of C_k.
+ *   limbs >= 1.  overflow_bits (may be NULL): uint64[(cap+63)/64], bit k set
+ *   if C_k >= 2^(64 limbs); those limbs then hold C_k mod 2^(64 limbs) and
+ *   PV_EOVERFLOW is returned.  PV_EBUFSIZE if cap <= min(omega, k_max).
+ *   PV_ENOMEM if the exact binomial table for the clique number (omega + 1
+ *   rows of omega + 1 entries of ceil((omega + 1) / 64) limbs) would pass
+ *   2 GiB, that is omega above about 1600.  stats may be NULL.
+ */
+pv_status pv_count_global_wide(pv_graph *g, int32_t k_max, uint64_t *counts, int32_t cap, int32_t limbs,
+                               int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats);
+
+/*
  * Local counts for k_lo <= k <= k_hi (1 <= k_lo <= k_hi <= PV_MAX_ALPHA + 1),
  * Alg. 2 per-vertex and per-edge steps.  The binomials C(alpha, b) for
  * b < k_hi must fit 64 bits (PV_ETOOBIG otherwise; every k when alpha <= 67).

@@ -132,6 +132,9 @@ struct Workspace {
     DBuf<int> u_root;  // batches: root vertex of every universe
     // per-vertex prefix sums grouped by heavy root
     DBuf<int> u_grp, pg_cnt, pg_off, pg_pos, pg_list;
+    // counts wider than u128: binomial table, per-k limbs, span and omega
+    DBuf<uint64_t> wide_tab, wide_out;
+    DBuf<int> wide_i;
     // per-edge counts
     DBuf<int> ueid, weid;
     DBuf<uint64_t> umem, utot, escr;
@@ -141,14 +144,15 @@ struct Workspace {
     void release() {
         DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &lid, &uverts, &ldeg, &lrp, &lcol,
                            &bcnt, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid,
-                           &u_grp, &pg_cnt, &pg_off, &pg_pos, &pg_list};
+                           &u_grp, &pg_cnt, &pg_off, &pg_pos, &pg_list, &wide_i};
         for (auto *b : ib) b->release();
         ctl.release();
         citem[0].release();
         citem[1].release();
         mwitem[0].release();
         mwitem[1].release();
-        DBuf<uint64_t> *ub[] = {&hu_rows, &u_rows, &counts, &ovf, &vout_own, &umem, &utot, &escr};
+        DBuf<uint64_t> *ub[] = {&hu_rows, &u_rows, &counts, &ovf, &vout_own, &umem, &utot, &escr,
+                                &wide_tab, &wide_out};
         for (auto *b : ub) b->release();
         u_pref.release();
         hist.release();
@@ -1045,6 +1049,79 @@ extern "C" pv_status pv_count_global(pv_graph *g, int32_t k_max, pv_u128 *counts
                                      int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats) {
     return pv_count(g, 0, k_max, counts, cap, omega_out, overflow_bits, PV_NONE, 0, 0, nullptr,
                     nullptr, stats);
+}
+
+extern "C" pv_status pv_count_global_wide(pv_graph *g, int32_t k_max, uint64_t *counts, int32_t cap,
+                                          int32_t limbs, int32_t *omega_out, uint64_t *overflow_bits,
+                                          pv_stats *stats) {
+    if (!g || cap < 0 || (cap > 0 && !counts) || limbs < 1) return PV_EINVAL;
+    pv_ctx *c = g->ctx;
+    PVCHK(prepare(g, false));
+    CountReq rq;
+    rq.kmax = k_max > 0 ? k_max : 0;
+    PVCHK(setup_local(g, PV_NONE, 0, 0, rq));
+    rq.order = g->order.p;
+    rq.nheavy = g->nheavy;
+    rq.nlight = g->nnonzero - g->nheavy;
+    PVCHK(run_sct(g, rq));
+    hipStream_t s = c->stream;
+    const int hd = g->alpha + 2;
+    // the binomials needed reach p <= the largest h + p of a leaf
+    PVCHK(c->ws.wide_i.ensure(2));
+    HIPCHK(hipMemsetAsync(c->ws.wide_i.p, 0, 2 * sizeof(int), s));
+    if (c->timing) HIPCHK(hipEventRecord(c->ev[5], s));
+    HIPCHK(pv_launch_count_wide(c->ws.hist.p, hd, 0, 0, 0, c->ws.wide_i.p, nullptr, 0, 0, 0, nullptr, nullptr, 0,
+                                s));
+    int span = 0;
+    HIPCHK(hipMemcpyAsync(&span, c->ws.wide_i.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int bn = span + 1;
+    const int tl = (bn + 63) / 64;  // C(p, j) < 2^p
+    const int W = tl + 1;           // any count: histogram total < 2^64
+    const int kcap = bn;
+    const size_t tab_words = (size_t)bn * bn * tl;
+    if (tab_words * 8 > ((size_t)2 << 30)) {
+        snprintf(g_last_error, sizeof g_last_error, "binomial table for clique number %d exceeds 2 GiB", span);
+        return PV_ENOMEM;
+    }
+    PVCHK(c->ws.wide_tab.ensure(tab_words));
+    PVCHK(c->ws.wide_out.ensure((size_t)kcap * W));
+    HIPCHK(pv_launch_count_wide(c->ws.hist.p, hd, kcap, rq.kmax, rq.c0, nullptr, c->ws.wide_tab.p, bn, tl, W,
+                                c->ws.wide_out.p, c->ws.wide_i.p + 1, 1, s));
+    if (c->timing) HIPCHK(hipEventRecord(c->ev[6], s));
+    std::vector<uint64_t> hc((size_t)kcap * W);
+    int omega = 0;
+    unsigned long long hcnt[8];
+    HIPCHK(hipMemcpyAsync(hc.data(), c->ws.wide_out.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&omega, c->ws.wide_i.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hcnt, c->ws.counters.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    g->last.nodes = hcnt[0];
+    g->last.leaves = hcnt[1];
+    g->last.work = hcnt[2];
+    for (int mode = 0; mode < 3; mode++) g->last.work_kind[mode] = hcnt[4 + mode];
+    if (c->timing) g->last.ms_finalize = elapsed(c, 5, 6);
+    g->last.alpha = g->alpha;
+    g->last.omega = omega;
+    g->last.subrounds = g->subrounds;
+    if (stats) *stats = g->last;
+    if (omega_out) *omega_out = omega;
+    const int cw = (cap + 63) / 64;
+    if (overflow_bits) memset(overflow_bits, 0, sizeof(uint64_t) * (size_t)cw);
+    bool any_ovf = false;
+    for (int k = 0; k < cap; k++) {
+        uint64_t *row = counts + (size_t)k * limbs;
+        for (int l = 0; l < limbs; l++) row[l] = (k < kcap && l < W) ? hc[(size_t)k * W + l] : 0ull;
+        bool ovf = false;
+        for (int l = limbs; k < kcap && l < W; l++) ovf = ovf || hc[(size_t)k * W + l] != 0;
+        if (ovf) {
+            any_ovf = true;
+            if (overflow_bits) overflow_bits[k >> 6] |= 1ull << (k & 63);
+        }
+    }
+    const int top = (rq.kmax > 0) ? std::min(omega, rq.kmax) : omega;
+    if (cap <= top) return PV_EBUFSIZE;
+    return any_ovf ? PV_EOVERFLOW : PV_OK;
 }
 
 extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int32_t k_hi,

@@ -179,6 +179,13 @@ struct PrefixWork {
 };
 hipError_t pv_launch_vertex_prefix(const LevelArgs *a, int max_units, int ngroups, const PrefixWork &w,
                                    int rows, hipStream_t s);
+// counts in W 64-bit limbs.  phase 0: *span = largest h + p of a nonzero
+// bin (span zeroed by the caller).  phase 1: table tab [bn][bn][tl] of C(p, j)
+// (tl limbs, bn = span + 1) and out [kcap][W] (W = tl + 1), omega as the
+// largest k with a nonzero count (zeroed by the caller)
+hipError_t pv_launch_count_wide(const unsigned long long *hist, int hd, int kcap, int kmax, int c0, int *span,
+                                uint64_t *tab, int bn, int tl, int W, uint64_t *out, int *omega, int phase,
+                                hipStream_t s);
 // exclusive scan: out[i] = sum_{j<i} in[j] for i <= n; tmp: n / 1024 + 2 ints
 hipError_t pv_launch_excl_scan(int n, const int *in, int *tmp, int *out, hipStream_t s);
 // per-edge ids: o2e[q] = lexicographic id of the edge at oriented position q

@@ -1960,6 +1960,120 @@ __global__ void __launch_bounds__(256) finalize_kernel(const unsigned long long 
     }
 }
 
+// ------------------------------------------------ counts wider than u128
+// The same read-off (Sec. 5: C_k = sum over leaves (h, p) of C(p, k - h))
+// in little-endian 64-bit limbs, for graphs whose counts pass 2^128.
+
+// largest h + p over the nonzero histogram bins (a leaf's H and P form a
+// clique, so every binomial needed has p <= that bound)
+__global__ void __launch_bounds__(256) hist_span_kernel(const unsigned long long *__restrict__ hist, int hd,
+                                                        int *out) {
+    int best = 0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)hd * hd;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int h = (int)(i / hd), p = (int)(i % hd);
+        if (hist[i]) best = max(best, h + p);
+    }
+    best = wave_max_i32(best);
+    if ((threadIdx.x & 63) == 0 && best > 0) atomicMax(out, best);
+}
+
+// C(p, j) for 0 <= j <= p < bn in `limbs` limbs (C(p, j) < 2^p <= 2^(64
+// limbs)), row by row by Pascal's rule; one workgroup
+__global__ void __launch_bounds__(256) binom_wide_kernel(int bn, int limbs, uint64_t *tab) {
+    for (int p = 0; p < bn; p++) {
+        for (int j = threadIdx.x; j < bn; j += blockDim.x) {
+            uint64_t *d = tab + ((long long)p * bn + j) * limbs;
+            if (j > p) {
+                for (int l = 0; l < limbs; l++) d[l] = 0ull;
+            } else if (j == 0 || j == p) {
+                d[0] = 1ull;
+                for (int l = 1; l < limbs; l++) d[l] = 0ull;
+            } else {
+                const uint64_t *a = tab + ((long long)(p - 1) * bn + j - 1) * limbs;
+                const uint64_t *b = a + limbs;  // C(p-1, j)
+                uint64_t c = 0;
+                for (int l = 0; l < limbs; l++) {
+                    const uint64_t x = a[l] + b[l];
+                    const uint64_t y = x + c;
+                    c = (x < a[l] ? 1ull : 0ull) + (y < x ? 1ull : 0ull);
+                    d[l] = y;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// One workgroup per k: thread t < W owns limb t as a 128-bit carry-save
+// sum (the low half of L * B[t] and the high half of L * B[t-1] over all
+// leaf bins); thread 0 then propagates the carries.  W = table limbs + 1
+// holds any count (the histogram total is below 2^64).  out: [kcap][W].
+__global__ void __launch_bounds__(128) finalize_wide_kernel(const unsigned long long *__restrict__ hist, int hd,
+                                                            const uint64_t *__restrict__ tab, int bn, int tl,
+                                                            int W, int kmax, int c0, uint64_t *out, int *omega) {
+    __shared__ uint64_t s_lo[128], s_hi[128];
+    const int k = blockIdx.x;
+    const int t = threadIdx.x;
+    uint64_t lo = 0, hi = 0;
+    if (t < W && k > 0 && (kmax <= 0 || k <= kmax)) {
+        for (int h = 1; h <= k && h < hd; h++) {
+            const int j = k - h;  // C(p, j) with p >= j
+            for (int p = j; p < bn && p < hd; p++) {
+                const unsigned long long L = hist[(long long)h * hd + p];
+                if (!L) continue;
+                const uint64_t *B = tab + ((long long)p * bn + j) * tl;
+                const uint64_t b0 = (t < tl) ? B[t] : 0ull;
+                const uint64_t b1 = (t >= 1 && t - 1 < tl) ? B[t - 1] : 0ull;
+                const uint64_t a = (uint64_t)L * b0;            // low half of L * B[t]
+                const uint64_t c = __umul64hi((uint64_t)L, b1);  // high half of L * B[t-1]
+                const uint64_t n1 = lo + a;
+                hi += (n1 < lo) ? 1ull : 0ull;
+                const uint64_t n2 = n1 + c;
+                hi += (n2 < n1) ? 1ull : 0ull;
+                lo = n2;
+            }
+        }
+    }
+    if (t < 128) {
+        s_lo[t] = lo;
+        s_hi[t] = hi;
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint64_t cl = 0, ch = 0;  // carry into the current limb (128-bit)
+        bool any = false;
+        for (int l = 0; l < W; l++) {
+            const uint64_t x = s_lo[l] + cl;
+            const uint64_t c1 = (x < cl) ? 1ull : 0ull;
+            out[(long long)k * W + l] = x;
+            any = any || x;
+            // next carry = s_hi[l] + ch + c1 (fits: far below 2^128)
+            const uint64_t y = s_hi[l] + ch;
+            cl = y + c1;
+            ch = (y < s_hi[l] ? 1ull : 0ull) + (cl < y ? 1ull : 0ull);
+        }
+        if (k == 0) {
+            out[0] = (uint64_t)c0;
+            for (int l = 1; l < W; l++) out[l] = 0ull;
+        } else if (any) {
+            atomicMax(omega, k);
+        }
+    }
+}
+
+hipError_t pv_launch_count_wide(const unsigned long long *hist, int hd, int kcap, int kmax, int c0, int *span,
+                                uint64_t *tab, int bn, int tl, int W, uint64_t *out, int *omega, int phase,
+                                hipStream_t s) {
+    if (phase == 0) {
+        hist_span_kernel<<<std::max(1, std::min(1024, (hd * hd + 255) / 256)), 256, 0, s>>>(hist, hd, span);
+        return hipGetLastError();
+    }
+    binom_wide_kernel<<<1, 256, 0, s>>>(bn, tl, tab);
+    finalize_wide_kernel<<<kcap, 128, 0, s>>>(hist, hd, tab, bn, tl, W, kmax, c0, out, omega);
+    return hipGetLastError();
+}
+
 // ============================================================== host side
 
 template <int KL, int LK>

@@ -41,7 +41,7 @@ ABI_FUNCTIONS = [
     "pv_set_timing",
     "pv_last_error",
     "pv_graph_load_csr", "pv_graph_load_csr_device", "pv_graph_free", "pv_graph_size",
-    "pv_graph_orient", "pv_graph_export_order", "pv_count_global", "pv_count_local",
+    "pv_graph_orient", "pv_graph_export_order", "pv_count_global", "pv_count_global_wide", "pv_count_local",
     "pv_graph_edge_list", "pv_count", "pv_count_roots", "pv_count_batch", "pv_count_global_batch",
     "pv_server_start", "pv_server_submit", "pv_server_wait", "pv_server_poll", "pv_server_cancel",
     "pv_server_stats", "pv_server_stop",
@@ -141,6 +141,7 @@ def _lib():
             "pv_graph_orient": (i32, [vp, i32p]),
             "pv_graph_export_order": (i32, [vp, i32p]),
             "pv_count_global": (i32, [vp, i32, u128p, i32, i32p, u64p, sp]),
+            "pv_count_global_wide": (i32, [vp, i32, u64p, i32, i32, i32p, u64p, sp]),
             "pv_count_local": (i32, [vp, i32, i32, i32, u128p, i64, u64p, sp]),
             "pv_graph_edge_list": (i32, [vp, i32p, i32p]),
             "pv_count": (i32, [vp, i32, i32, u128p, i32, i32p, u64p, i32, i32, i32, vp, u64p, sp]),
@@ -291,6 +292,20 @@ def pv_count_global(g: int, k_max: int = 0, cap: int = PV_MAX_ALPHA + 2) -> Glob
                "pv_count_global", allow=(PV_EOVERFLOW,))
     ovf = [k for k in range(cap) if (ov[k >> 6] >> (k & 63)) & 1]
     return GlobalResult(u128_to_ints(counts), om.value, ovf, st.as_dict(), s)
+
+
+def pv_count_global_wide(g: int, k_max: int = 0, cap: int = PV_MAX_ALPHA + 2, limbs: int = 4) -> GlobalResult:
+    """Global counts in `limbs` 64-bit limbs per k, as Python ints."""
+    counts = np.zeros((max(cap, 1), limbs), dtype=np.uint64)
+    ov = (C.c_uint64 * ((cap + 63) // 64))()
+    om = C.c_int32()
+    st = pv_stats()
+    s = _check(_lib().pv_count_global_wide(g, k_max, counts.ctypes.data_as(C.POINTER(C.c_uint64)), cap, limbs,
+                                           C.byref(om), ov, C.byref(st)),
+               "pv_count_global_wide", allow=(PV_EOVERFLOW,))
+    ovf = [k for k in range(cap) if (ov[k >> 6] >> (k & 63)) & 1]
+    vals = [sum(int(counts[k, i]) << (64 * i) for i in range(limbs)) for k in range(cap)]
+    return GlobalResult(vals, om.value, ovf, st.as_dict(), s)
 
 
 def pv_count_local(g: int, kind: int, k_lo: int, k_hi: int):

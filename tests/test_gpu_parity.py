@@ -622,3 +622,72 @@ def test_heavy_roots_in_chunks(name):
     assert ovf == 0 and eovf == 0
     assert np.array_equal(out, ref.vertex)
     assert np.array_equal(eout, ref.edge)
+
+
+# ----------------------------------------------- counts wider than 128 bits
+
+def _esym(parts):
+    e = [1]
+    for a in parts:
+        e = [x + (a * e[i - 1] if i else 0) for i, x in enumerate(e + [0])]
+    return e
+
+
+WIDE = [("K200", lambda: gg.complete(200), 4),
+        ("K300", lambda: gg.complete(300), 5),
+        ("multipartite153", lambda: gg.complete_multipartite([1] * 150 + [2, 3, 3]), 3),
+        ("planted160", lambda: gg.plant_cliques(gg.gnp(600, 0.02, 61), [160, 130], 62), 3)]
+
+
+@pytest.mark.parametrize("name,maker,limbs", WIDE, ids=[w[0] for w in WIDE])
+def test_wide_counts(ctx, name, maker, limbs):
+    from math import comb
+    g = maker()
+    _say(f"[parity] wide counts {name}: n={g.n} m={g.m} limbs={limbs}")
+    if name.startswith("K"):
+        want, omega = [comb(g.n, k) for k in range(g.n + 1)], g.n
+    elif name.startswith("multipartite"):
+        want = _esym([1] * 150 + [2, 3, 3])
+        omega = len(want) - 1
+    else:
+        want, omega = O.counts_exact(g)
+    with Loaded(ctx, g) as h:
+        res = P.pv_count_global_wide(h, 0, cap=omega + 2, limbs=limbs)
+    assert res.status == P.PV_OK and res.overflow == []
+    assert res.omega == omega
+    assert res.counts[: omega + 1] == want and res.counts[omega + 1] == 0
+    assert max(want) >= 2 ** 128 or name.startswith("planted")
+
+
+@pytest.mark.parametrize("limbs", [1, 2])
+def test_wide_counts_narrow_limbs_flag_overflow(ctx, limbs):
+    # K_200 in 64 or 128 bits: exactly the C(200, k) that do not fit are
+    # flagged, and their limbs hold the count modulo 2^(64 limbs)
+    from math import comb
+    g = gg.complete(200)
+    with Loaded(ctx, g) as h:
+        res = P.pv_count_global_wide(h, 0, cap=202, limbs=limbs)
+    mod = 2 ** (64 * limbs)
+    assert res.status == P.PV_EOVERFLOW
+    assert res.overflow == [k for k in range(202) if k <= 200 and comb(200, k) >= mod]
+    assert res.counts[:201] == [comb(200, k) % mod for k in range(201)]
+
+
+def test_wide_counts_agree_with_u128_truncation_and_tiny_graphs(ctx):
+    from math import comb
+    g = gg.plant_cliques(gg.gnp(400, 0.05, 71), [45, 30], 72)
+    with Loaded(ctx, g) as h:
+        a = P.pv_count_global(h)
+        b = P.pv_count_global_wide(h, 0, limbs=2)
+        t = P.pv_count_global_wide(h, 12, limbs=2)
+        ta = P.pv_count_global(h, 12)
+    assert b.counts == a.counts and b.omega == a.omega and b.overflow == a.overflow == []
+    assert b.stats["leaves"] == a.stats["leaves"] and b.stats["nodes"] == a.stats["nodes"]
+    assert t.counts == ta.counts and t.omega == ta.omega
+    with Loaded(ctx, gg.complete(200)) as h:
+        r = P.pv_count_global_wide(h, 20, cap=202, limbs=4)
+    assert r.counts[:21] == [comb(200, k) for k in range(21)] and all(c == 0 for c in r.counts[21:])
+    for gt, want in [(gg.empty(0), [1]), (gg.empty(5), [1, 5]), (gg.complete(1), [1, 1])]:
+        with Loaded(ctx, gt) as h:
+            r = P.pv_count_global_wide(h, 0, cap=4, limbs=1)
+        assert r.counts == want + [0] * (4 - len(want)), (gt.n, r.counts)
