@@ -232,6 +232,21 @@ pv_status pv_count_global_wide(pv_graph *g, int32_t k_max, uint64_t *counts, int
                                int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats);
 
 /*
+ * Frequency distribution of local counts (Sec. 6, demonstrations: f_k(b),
+ * the number of vertices that take part in exactly b k-cliques; on a
+ * per-edge table, the number of edges).  local: DEVICE memory, a [rows][K]
+ * pv_u128 table such as pv_count writes (column col holds k = k_lo + col).
+ * values / freq: host memory of cap entries; on success values[0..D) are
+ * the D distinct counts of the column in increasing order (0 included when
+ * present) and freq[i] the number of rows holding values[i], so the freq
+ * sum to rows.  *ndistinct = D (set also when PV_EBUFSIZE: cap < D; nothing
+ * else is written then).  rows < 2^31 - 1; the context's stream is used
+ * and the call returns when the results are in host memory.
+ */
+pv_status pv_local_frequency(pv_ctx *ctx, const pv_u128 *local, int64_t rows, int32_t K, int32_t col,
+                             pv_u128 *values, uint64_t *freq, int64_t cap, int64_t *ndistinct);
+
+/*
  * Local counts for k_lo <= k <= k_hi (1 <= k_lo <= k_hi <= PV_MAX_ALPHA + 1),
  * Alg. 2 per-vertex and per-edge steps.  The binomials C(alpha, b) for
  * b < k_hi must fit 64 bits (PV_ETOOBIG otherwise; every k when alpha <= 67).

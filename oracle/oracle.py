@@ -180,3 +180,12 @@ def counts_exact(g, key=None, roots=None, kmax: int = 0) -> tuple[list[int], int
         out[k] = sum(c * math.comb(p, k - h) for h, p, c in nz if 0 <= k - h <= p)
     return out, (top if kmax else omega)
 
+
+def frequency(limbs: np.ndarray) -> list[tuple[int, int]]:
+    """f(b) of one column of local counts (Sec. 6, demonstrations): the
+    distinct values b in increasing order with the number of rows holding
+    each.  limbs: [rows][2] uint64 (lo, hi) as count() returns them."""
+    from collections import Counter
+    vals = [int(lo) | (int(hi) << 64) for lo, hi in np.asarray(limbs, dtype=np.uint64).reshape(-1, 2)]
+    return sorted(Counter(vals).items())
+

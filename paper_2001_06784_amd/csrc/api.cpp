@@ -135,6 +135,9 @@ struct Workspace {
     // counts wider than u128: binomial table, per-k limbs, span and omega
     DBuf<uint64_t> wide_tab, wide_out;
     DBuf<int> wide_i;
+    // frequency distributions of local counts
+    DBuf<uint64_t> fq_keys, fq_vals;
+    DBuf<int> fq_flags, fq_idx, fq_pos;
     // per-edge counts
     DBuf<int> ueid, weid;
     DBuf<uint64_t> umem, utot, escr;
@@ -144,7 +147,8 @@ struct Workspace {
     void release() {
         DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &lid, &uverts, &ldeg, &lrp, &lcol,
                            &bcnt, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid,
-                           &u_grp, &pg_cnt, &pg_off, &pg_pos, &pg_list, &wide_i};
+                           &u_grp, &pg_cnt, &pg_off, &pg_pos, &pg_list, &wide_i, &fq_flags, &fq_idx,
+                           &fq_pos};
         for (auto *b : ib) b->release();
         ctl.release();
         citem[0].release();
@@ -152,7 +156,7 @@ struct Workspace {
         mwitem[0].release();
         mwitem[1].release();
         DBuf<uint64_t> *ub[] = {&hu_rows, &u_rows, &counts, &ovf, &vout_own, &umem, &utot, &escr,
-                                &wide_tab, &wide_out};
+                                &wide_tab, &wide_out, &fq_keys, &fq_vals};
         for (auto *b : ub) b->release();
         u_pref.release();
         hist.release();
@@ -1122,6 +1126,40 @@ extern "C" pv_status pv_count_global_wide(pv_graph *g, int32_t k_max, uint64_t *
     const int top = (rq.kmax > 0) ? std::min(omega, rq.kmax) : omega;
     if (cap <= top) return PV_EBUFSIZE;
     return any_ovf ? PV_EOVERFLOW : PV_OK;
+}
+
+extern "C" pv_status pv_local_frequency(pv_ctx *c, const pv_u128 *local, int64_t rows, int32_t K, int32_t col,
+                                        pv_u128 *values, uint64_t *freq, int64_t cap, int64_t *ndistinct) {
+    if (!c || rows < 0 || rows > INT32_MAX - 1 || K < 1 || col < 0 || col >= K || cap < 0 || !ndistinct ||
+        (rows > 0 && !local) || (cap > 0 && (!values || !freq)))
+        return PV_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int n = (int)rows;
+    long long npad = 1;
+    while (npad < rows) npad <<= 1;
+    PVCHK(c->ws.fq_keys.ensure((size_t)npad * 2));
+    PVCHK(c->ws.fq_vals.ensure((size_t)std::max(n, 1) * 2));
+    PVCHK(c->ws.fq_flags.ensure((size_t)n + 1));
+    PVCHK(c->ws.fq_idx.ensure((size_t)n + 1));
+    PVCHK(c->ws.fq_pos.ensure((size_t)n + 1));
+    PVCHK(c->ws.scan.ensure((size_t)n / 1024 + 2));
+    const FreqWork w{c->ws.fq_keys.p, c->ws.fq_vals.p, c->ws.fq_flags.p, c->ws.fq_idx.p, c->ws.fq_pos.p,
+                     c->ws.scan.p};
+    HIPCHK(pv_launch_frequency((const uint64_t *)local, n, K, col, npad, w, s));
+    int D = 0;
+    if (n > 0) HIPCHK(hipMemcpyAsync(&D, c->ws.fq_idx.p + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *ndistinct = D;
+    if (cap < D) return PV_EBUFSIZE;
+    if (D > 0) {
+        std::vector<int> pos((size_t)D);
+        HIPCHK(hipMemcpyAsync(values, c->ws.fq_vals.p, (size_t)D * 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(pos.data(), c->ws.fq_pos.p, (size_t)D * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int d = 0; d < D; d++) freq[d] = (uint64_t)((d + 1 < D ? pos[d + 1] : n) - pos[d]);
+    }
+    return PV_OK;
 }
 
 extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int32_t k_hi,

@@ -186,6 +186,17 @@ hipError_t pv_launch_vertex_prefix(const LevelArgs *a, int max_units, int ngroup
 hipError_t pv_launch_count_wide(const unsigned long long *hist, int hd, int kcap, int kmax, int c0, int *span,
                                 uint64_t *tab, int bn, int tl, int W, uint64_t *out, int *omega, int phase,
                                 hipStream_t s);
+// frequency distribution of one column of a [rows][K] u128 table: keys
+// [npad][2] (npad = power of two >= rows), flags / idx / pos [rows + 1],
+// vals [rows][2], scan_tmp rows / 1024 + 2 ints; after the launch idx[rows]
+// is the number of distinct values D, vals[0..D) the values in increasing
+// order and pos[0..D) the sorted position of each value's first row
+struct FreqWork {
+    uint64_t *keys, *vals;
+    int *flags, *idx, *pos, *scan_tmp;
+};
+hipError_t pv_launch_frequency(const uint64_t *src, int rows, int K, int col, long long npad, const FreqWork &w,
+                               hipStream_t s);
 // exclusive scan: out[i] = sum_{j<i} in[j] for i <= n; tmp: n / 1024 + 2 ints
 hipError_t pv_launch_excl_scan(int n, const int *in, int *tmp, int *out, hipStream_t s);
 // per-edge ids: o2e[q] = lexicographic id of the edge at oriented position q

@@ -42,6 +42,7 @@ ABI_FUNCTIONS = [
     "pv_last_error",
     "pv_graph_load_csr", "pv_graph_load_csr_device", "pv_graph_free", "pv_graph_size",
     "pv_graph_orient", "pv_graph_export_order", "pv_count_global", "pv_count_global_wide", "pv_count_local",
+    "pv_local_frequency",
     "pv_graph_edge_list", "pv_count", "pv_count_roots", "pv_count_batch", "pv_count_global_batch",
     "pv_server_start", "pv_server_submit", "pv_server_wait", "pv_server_poll", "pv_server_cancel",
     "pv_server_stats", "pv_server_stop",
@@ -142,6 +143,7 @@ def _lib():
             "pv_graph_export_order": (i32, [vp, i32p]),
             "pv_count_global": (i32, [vp, i32, u128p, i32, i32p, u64p, sp]),
             "pv_count_global_wide": (i32, [vp, i32, u64p, i32, i32, i32p, u64p, sp]),
+            "pv_local_frequency": (i32, [vp, vp, i64, i32, i32, u128p, u64p, i64, C.POINTER(C.c_int64)]),
             "pv_count_local": (i32, [vp, i32, i32, i32, u128p, i64, u64p, sp]),
             "pv_graph_edge_list": (i32, [vp, i32p, i32p]),
             "pv_count": (i32, [vp, i32, i32, u128p, i32, i32p, u64p, i32, i32, i32, vp, u64p, sp]),
@@ -306,6 +308,20 @@ def pv_count_global_wide(g: int, k_max: int = 0, cap: int = PV_MAX_ALPHA + 2, li
     ovf = [k for k in range(cap) if (ov[k >> 6] >> (k & 63)) & 1]
     vals = [sum(int(counts[k, i]) << (64 * i) for i in range(limbs)) for k in range(cap)]
     return GlobalResult(vals, om.value, ovf, st.as_dict(), s)
+
+
+def pv_local_frequency(ctx: int, local_ptr: int, rows: int, K: int, col: int):
+    """Distinct values of column `col` of a device [rows][K] u128 table, in
+    increasing order (Python ints), and how many rows hold each (uint64)."""
+    cap = max(rows, 1)
+    vals = np.zeros((cap, 2), dtype=np.uint64)
+    freq = np.zeros(cap, dtype=np.uint64)
+    nd = C.c_int64()
+    _check(_lib().pv_local_frequency(ctx, local_ptr, rows, K, col, vals.ctypes.data_as(C.POINTER(pv_u128)),
+                                     freq.ctypes.data_as(C.POINTER(C.c_uint64)), cap, C.byref(nd)),
+           "pv_local_frequency")
+    D = nd.value
+    return [int(vals[i, 0]) | (int(vals[i, 1]) << 64) for i in range(D)], freq[:D]
 
 
 def pv_count_local(g: int, kind: int, k_lo: int, k_hi: int):

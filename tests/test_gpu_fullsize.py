@@ -84,3 +84,18 @@ def test_sampled_roots_full(full):
     assert got.counts[1: len(ref.glob)] == ref.glob[1:]
     assert got.stats["leaves"] == ref.stats["leaves"]
     assert got.stats["nodes"] == ref.stats["nodes"]
+
+
+def test_frequency_identities_full(full):
+    # f_k(b) over the 1M vertices: the frequencies sum to n, and the values
+    # weighted by their frequencies sum to k C_k (each k-clique has k vertices)
+    import torch
+    g, ctx, h, res, lovf, vert, sub = full
+    K = K_HI - K_LO + 1
+    dev = torch.from_numpy(vert.reshape(g.n, K, 2).view(np.int64).copy()).to("cuda:0")
+    for c, k in enumerate(range(K_LO, K_HI + 1)):
+        vals, freq = P.pv_local_frequency(ctx, dev.data_ptr(), g.n, K, c)
+        assert all(a < b for a, b in zip(vals, vals[1:]))
+        assert int(freq.sum()) == g.n and all(int(f) >= 1 for f in freq)
+        assert sum(v * int(f) for v, f in zip(vals, freq)) == k * res.counts[k], k
+    _say(f"[fullsize] f_k(b): {len(vals)} distinct values of the k={K_HI} counts")

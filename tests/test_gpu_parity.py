@@ -691,3 +691,36 @@ def test_wide_counts_agree_with_u128_truncation_and_tiny_graphs(ctx):
         with Loaded(ctx, gt) as h:
             r = P.pv_count_global_wide(h, 0, cap=4, limbs=1)
         assert r.counts == want + [0] * (4 - len(want)), (gt.n, r.counts)
+
+
+# ---------------------------------------- frequency distributions f_k(b)
+
+def test_local_frequency_per_vertex_and_per_edge(ctx):
+    import torch
+    g = gg.plant_cliques(gg.gnp(400, 0.05, 81), [30, 18], 82)
+    klo, khi = 3, 10
+    K = khi - klo + 1
+    ref = O.count(g, vertex=(klo, khi), edge=(3, 8))
+    loc = torch.zeros((g.n, K, 2), dtype=torch.int64, device="cuda:0")
+    with Loaded(ctx, g) as h:
+        P.pv_count(h, reorient=True, local_kind=P.PV_VERTEX, k_lo=klo, k_hi=khi, local_out=loc.data_ptr())
+        torch.cuda.synchronize()
+        eout, eovf, est = P.pv_count_local(h, P.PV_EDGE, 3, 8)
+    for c in range(K):
+        vals, freq = P.pv_local_frequency(ctx, loc.data_ptr(), g.n, K, c)
+        assert list(zip(vals, (int(f) for f in freq))) == O.frequency(ref.vertex[:, c]), c
+    ed = torch.from_numpy(eout.view(np.int64).copy()).to("cuda:0")
+    for c in range(6):
+        vals, freq = P.pv_local_frequency(ctx, ed.data_ptr(), g.m, 6, c)
+        assert list(zip(vals, (int(f) for f in freq))) == O.frequency(ref.edge[:, c]), c
+    # no rows, one row, and a buffer too small for the distinct values
+    vals, freq = P.pv_local_frequency(ctx, loc.data_ptr(), 0, K, 0)
+    assert vals == [] and len(freq) == 0
+    vals, freq = P.pv_local_frequency(ctx, loc.data_ptr(), 1, K, 0)
+    assert len(vals) == 1 and int(freq[0]) == 1
+    import ctypes as C
+    one_v = (P.pv_u128 * 1)()
+    one_f = (C.c_uint64 * 1)()
+    nd = C.c_int64()
+    st = P.load_library().pv_local_frequency(ctx, loc.data_ptr(), g.n, K, 0, one_v, one_f, 1, C.byref(nd))
+    assert st == P.PV_EBUFSIZE and nd.value == len(O.frequency(ref.vertex[:, 0])) > 1

@@ -399,3 +399,20 @@ def test_exact_counts_truncated_and_root_subset():
     # the root subproblem of vertex 0 of K_150 alone: one leaf (1, 149)
     counts, omega = O.counts_exact(gg.complete(150), roots=np.array([0], dtype=np.int32))
     assert counts == [0] + [comb(149, i) for i in range(150)]
+
+
+# ------------------------------------------- frequency distributions f_k(b)
+
+def test_frequency_closed_forms():
+    # K_12: every vertex lies in C(11, k-1) k-cliques
+    r = O.count(gg.complete(12), vertex=(1, 6))
+    for c, k in enumerate(range(1, 7)):
+        assert O.frequency(r.vertex[:, c]) == [(comb(11, k - 1), 12)]
+    # star with 9 leaves: edges (k = 2) give the centre 9 and each leaf 1; no triangles
+    r = O.count(gg.star(10), vertex=(2, 3))
+    assert O.frequency(r.vertex[:, 0]) == [(1, 9), (9, 1)]
+    assert O.frequency(r.vertex[:, 1]) == [(0, 10)]
+    # K_5, K_7 and three isolated vertices, triangles: 6 for K_5's, 15 for K_7's
+    g = gg.disjoint_union(gg.disjoint_union(gg.complete(5), gg.complete(7)), gg.empty(3))
+    r = O.count(g, vertex=(3, 3))
+    assert O.frequency(r.vertex[:, 0]) == [(0, 3), (6, 5), (15, 7)]
