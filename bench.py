@@ -149,8 +149,8 @@ def main():
     ap.add_argument("--duration", type=float, default=20.0, help="serve: measured seconds")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the roots over "
+              "several GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":
