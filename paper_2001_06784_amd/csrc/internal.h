@@ -22,12 +22,11 @@ struct PeelCtl {
     int subrounds;       // out: number of sub-rounds
     int alpha;           // out: degeneracy (largest level)
     int err;             // out: a grid barrier timed out
-    unsigned bar_top, bar_gen;
-    unsigned bar_arrive[8 * 32];  // one counter per 128-byte line
+    unsigned bar_flag[256 * 32];  // grid barrier: barriers passed by each block, one 128-byte line each
 };
 
 #define PV_PEEL_THREADS 1024
-#define PV_PEEL_MAX_BLOCKS 1024
+#define PV_PEEL_MAX_BLOCKS 256
 // the peel's last PV_SOLO_MAX vertices are finished by one workgroup
 // (local ids and remaining degrees below 2^16)
 #define PV_SOLO_MAX 16384

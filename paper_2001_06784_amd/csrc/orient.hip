@@ -73,42 +73,38 @@ __device__ __forceinline__ unsigned ld_u(const unsigned *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier for a co-resident (cooperative) launch.  Blocks arrive on one
-// of 8 group counters (blocks are spread round-robin over the XCDs), the
-// last of a group arrives on the top counter, and the last group bumps the
-// generation that everyone waits on.  A bounded wait turns a lost block
-// into an error flag instead of a hang; returns false then.
-__device__ bool grid_barrier(PeelCtl *ctl, int nblocks) {
+// Grid barrier for a co-resident (cooperative) launch.  Every block
+// publishes the number of barriers it has passed on its own 128-byte line
+// (a release store; `epoch` is that number, kept by the caller), and one
+// wave of each block polls all the lines until every block has reached the
+// same barrier: no chain of read-modify-writes, one round trip after the
+// last arrival.  A bounded wait turns a lost block into an error flag
+// instead of a hang; returns false then.
+__device__ bool grid_barrier(PeelCtl *ctl, int nblocks, unsigned &epoch) {
     __syncthreads();
     __shared__ int s_ok;
-    if (threadIdx.x == 0) {
-        const int ngroups = nblocks < 8 ? nblocks : 8;
-        const int grp = blockIdx.x % ngroups;
-        const int gsize = (nblocks - grp + ngroups - 1) / ngroups;
-        const unsigned gen = ld_u(&ctl->bar_gen);
-        __threadfence();
-        const unsigned a = atomicAdd(&ctl->bar_arrive[grp * 32], 1u);
-        if (a == (unsigned)gsize - 1) {
-            __hip_atomic_store(&ctl->bar_arrive[grp * 32], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned t = atomicAdd(&ctl->bar_top, 1u);
-            if (t == (unsigned)ngroups - 1) {
-                __hip_atomic_store(&ctl->bar_top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __threadfence();
-                __hip_atomic_store(&ctl->bar_gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
+    const unsigned e = ++epoch;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        if (lane == 0) {
+            __threadfence();
+            __hip_atomic_store(&ctl->bar_flag[blockIdx.x * 32], e, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
         int ok = 1;
         unsigned spins = 0;
-        while (ld_u(&ctl->bar_gen) == gen) {
+        for (;;) {
+            bool behind = false;
+            for (int b = lane; b < nblocks; b += 64) behind = behind || ld_u(&ctl->bar_flag[b * 32]) < e;
+            if (ballot64(behind) == 0) break;
             if (ld_acquire(&ctl->err) != 0 || ++spins > (1u << 24)) {
-                atomicOr(&ctl->err, 1);
+                if (lane == 0) atomicOr(&ctl->err, 1);
                 ok = 0;
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
         __threadfence();
-        s_ok = ok;
+        if (lane == 0) s_ok = ok;
     }
     __syncthreads();
     return s_ok != 0;
@@ -175,11 +171,12 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     const int wid = tid >> 6;
     const int nw = nth >> 6;
 
+    unsigned epoch = 0;  // grid barriers this block has passed
     for (int v = tid; v < n; v += nth) {
         deg[v] = rp[v + 1] - rp[v];
         sub[v] = -1;
     }
-    if (!grid_barrier(ctl, nb)) return;
+    if (!grid_barrier(ctl, nb, epoch)) return;
 
     // ---------------------------------------------------- grid-wide phase
     // vertices a block appends to a frontier are gathered in LDS and moved
@@ -218,7 +215,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             if (lane == 0) atomicMin(&s_kmin, mymin);
             __syncthreads();
             if (threadIdx.x == 0 && s_kmin != 0x7fffffff) atomicMin(&ctl->minv[r & 1], s_kmin);
-            if (!grid_barrier(ctl, nb)) return;
+            if (!grid_barrier(ctl, nb, epoch)) return;
             k = ld_acquire(&ctl->minv[r & 1]);
             alpha = max(alpha, k);
             int *F = (r & 1) ? pa.fb : pa.fa;
@@ -231,7 +228,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                 list_add(take, v, F, &ctl->cnt[r % 3]);
             }
             list_flush(F, &ctl->cnt[r % 3]);
-            if (!grid_barrier(ctl, nb)) return;
+            if (!grid_barrier(ctl, nb, epoch)) return;
             nF = ld_acquire(&ctl->cnt[r % 3]);
             if (nF == 0) break;  // cannot happen while vertices remain
         }
@@ -315,7 +312,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             }
         }
         list_flush(Fn, ncnt);
-        if (!grid_barrier(ctl, nb)) return;
+        if (!grid_barrier(ctl, nb, epoch)) return;
         removed += nF;
         nF = ld_acquire(&ctl->cnt[(r + 1) % 3]);
         r++;
@@ -337,7 +334,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         (void)block_excl_scan(cnt, &tot);
         if (threadIdx.x == 0) pa.bcnt[blockIdx.x] = tot;
     }
-    if (!grid_barrier(ctl, nb)) return;
+    if (!grid_barrier(ctl, nb, epoch)) return;
     if (threadIdx.x == 0) {
         int off = 0;
         for (int b = 0; b < (int)blockIdx.x; b++) off += pa.bcnt[b];
@@ -362,7 +359,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             base += tot;
         }
     }
-    if (!grid_barrier(ctl, nb)) return;
+    if (!grid_barrier(ctl, nb, epoch)) return;
     const int nu = n - removed;
     if (nu > PV_SOLO_MAX) {  // only if the grid phase stopped early: report, never overflow
         if (threadIdx.x == 0) atomicOr(&ctl->err, 2);
@@ -376,7 +373,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         c = (int)wave_add_u32((uint32_t)c);
         if (lane == 0) pa.ldeg[i] = c;
     }
-    if (!grid_barrier(ctl, nb)) return;
+    if (!grid_barrier(ctl, nb, epoch)) return;
     if (blockIdx.x == 0) {
         int base = 0;
         for (int i0 = 0; i0 < nu; i0 += blockDim.x) {
@@ -389,7 +386,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         }
         if (threadIdx.x == 0) pa.lrp[nu] = base;
     }
-    if (!grid_barrier(ctl, nb)) return;
+    if (!grid_barrier(ctl, nb, epoch)) return;
     // local CSR: neighbours inside U, as local ids, in row order
     {
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -406,7 +403,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             }
         }
     }
-    if (!grid_barrier(ctl, nb)) return;
+    if (!grid_barrier(ctl, nb, epoch)) return;
     if (blockIdx.x != 0) return;
 
     // ------------------------------------------------ solo phase (block 0)
