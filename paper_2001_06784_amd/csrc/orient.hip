@@ -420,12 +420,14 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     __shared__ unsigned s_alive[PV_SOLO_MAX / 32];
     __shared__ unsigned short s_Fq[PV_SOLO_MAX];
     __shared__ int s_lrp[PV_SOLO_MAX + 1];
-    __shared__ int s_cnt, s_min;
+    // s_cnt3[(r + 1) % 3] counts the joins of sub-round r; the next but one
+    // is reset while r runs, so the counters need no barrier of their own
+    __shared__ int s_cnt3[3], s_min;
     unsigned short *const s_h16 = (unsigned short *)s_deg2;  // half i = vertex i
     const int *__restrict__ lcol = pa.lcol;
     const int *__restrict__ uverts = pa.uverts;
     const int r0 = r;
-    if (threadIdx.x == 0) s_cnt = 0;
+    if (threadIdx.x < 3) s_cnt3[threadIdx.x] = 0;
     for (int i = threadIdx.x; i < PV_SOLO_MAX / 32; i += blockDim.x) s_alive[i] = 0u;
     for (int i = threadIdx.x; i <= nu; i += blockDim.x) s_lrp[i] = pa.lrp[i];
     __syncthreads();
@@ -464,25 +466,27 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             __syncthreads();
             k = s_min;
             alpha = max(alpha, k);
-            if (threadIdx.x == 0) s_cnt = 0;
+            // the frontier of sub-round r, counted on s_cnt3[r % 3]
+            if (threadIdx.x == 0) s_cnt3[r % 3] = 0;
             __syncthreads();
             for (int ib = bw * 64; ib < nu; ib += nbw * 64) {
                 const int i = ib + lane;
                 const bool take = i < nu && alive(i) && degof(i) <= k;
-                const int slot = wave_slot(take, &s_cnt);
+                const int slot = wave_slot(take, &s_cnt3[r % 3]);
                 if (take) {
                     atomicAnd(&s_alive[i >> 5], ~(1u << (i & 31)));
                     s_Fq[fbase + slot] = (unsigned short)i;
                 }
             }
             __syncthreads();
-            nF = s_cnt;
+            nF = s_cnt3[r % 3];
             if (nF == 0) break;
+            // (a removed vertex's half is not read again; its 16-bit store
+            // leaves the other half of the word, which decrements may still
+            // change, untouched)
             for (int j = threadIdx.x; j < nF; j += blockDim.x) s_h16[s_Fq[fbase + j]] = (unsigned short)(r - r0);
-            __syncthreads();
-            if (threadIdx.x == 0) s_cnt = 0;
-            __syncthreads();
         }
+        if (threadIdx.x == 0) s_cnt3[(r + 2) % 3] = 0;
         // joins are appended after the current frontier
         const int nbase = fbase + nF;
         for (int j = bw; j < nF; j += nbw) {
@@ -508,7 +512,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                             join = true;
                         }
                     }
-                    const int slot = wave_slot(join, &s_cnt);
+                    const int slot = wave_slot(join, &s_cnt3[(r + 1) % 3]);
                     if (join) s_Fq[nbase + slot] = (unsigned short)w[q];
                 }
             }
@@ -516,15 +520,14 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         __syncthreads();
         left -= nF;
         fbase = nbase;
-        nF = s_cnt;
+        nF = s_cnt3[(r + 1) % 3];
         r++;
-        // the new frontier's decrements are over: its halves take its sub-round
+        // the new frontier's decrements are over: its halves take its
+        // sub-round (no barrier needed: see the level change above)
         for (int j = threadIdx.x; j < nF; j += blockDim.x) s_h16[s_Fq[fbase + j]] = (unsigned short)(r - r0);
-        __syncthreads();
-        if (threadIdx.x == 0) s_cnt = 0;
-        __syncthreads();
         if (r > n) break;  // each sub-round removes a vertex: never reached
     }
+    __syncthreads();
     // keys of every vertex of U
     for (int i = threadIdx.x; i < nu; i += blockDim.x) sub[uverts[i]] = r0 + (int)s_h16[i];
     if (threadIdx.x == 0) {
