@@ -551,7 +551,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
         HIPCHK(pv_launch_peel(c->dev, pa, s));
         if (c->timing) HIPCHK(hipEventRecord(c->ev[1], s));
         HIPCHK(pv_launch_orient(c->dev, n, g->rp.p, g->col.p, g->sub.p, g->odeg.p, g->orow.p,
-                                g->ocol.p, g->small.p + SM_ALPHA, c->ws.scan.p, s));
+                                g->ocol.p, g->small.p + SM_ALPHA, c->ws.scan.p, c->ws.lcol.p, s));
         HIPCHK(pv_launch_root_order(n, g->small.p + SM_ALPHA, g->odeg.p, c->ws.rcnt.p, pv_root_chunks(n),
                                     g->order.p, g->small.p + SM_BOUNDS, PV_LIGHT_MAX, s));
         if (c->timing) HIPCHK(hipEventRecord(c->ev[2], s));

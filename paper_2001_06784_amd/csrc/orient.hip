@@ -546,14 +546,17 @@ __device__ __forceinline__ bool key_less(int su, int u, int sv, int v) {
 // (most rows of a sparse graph are short), longer ones by the whole wave.
 #define ORIENT_LANE_ROW 32
 
-// out-degree of every vertex
+// out-degree of every vertex; N+(v) (row order kept, so increasing id) is
+// also written to tmp at v's own row start rp[v]: serial per lane, ballot
+// compaction per wave
 __global__ void __launch_bounds__(256) odeg_kernel(int n, const int *__restrict__ rp,
                                                     const int *__restrict__ col,
                                                     const int *__restrict__ sub,
                                                     int *__restrict__ odeg,
-                                                    int *__restrict__ alpha) {
+                                                    int *__restrict__ alpha, int *__restrict__ tmp) {
     const int lane = threadIdx.x & 63;
     const int nw = (gridDim.x * blockDim.x) >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int amax = 0;
     for (int vb = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; vb < n; vb += nw * 64) {
         const int v = vb + lane;
@@ -568,58 +571,13 @@ __global__ void __launch_bounds__(256) odeg_kernel(int n, const int *__restrict_
         if (v < n && !wide)
             for (int i = b; i < e; i++) {
                 const int u = col[i];
-                c += key_less(sv, v, sub[u], u) ? 1 : 0;
+                if (key_less(sv, v, sub[u], u)) tmp[b + c++] = u;
             }
         for (uint64_t wm = ballot64(wide); wm; wm &= wm - 1ull) {
             const int L = __builtin_ctzll(wm);
             const int x = vb + L, sx = __shfl(sv, L, 64);
             const int xb = __shfl(b, L, 64), xe = __shfl(e, L, 64);
-            int cx = 0;
-            for (int i = xb + lane; i < xe; i += 64) {
-                const int u = col[i];
-                cx += key_less(sx, x, sub[u], u) ? 1 : 0;
-            }
-            cx = (int)wave_add_u32((uint32_t)cx);
-            if (lane == L) c = cx;
-        }
-        if (v < n) odeg[v] = c;
-        amax = max(amax, c);
-    }
-    amax = wave_max_i32(amax);
-    if (lane == 0) atomicMax(alpha, amax);
-}
-
-// N+(v) in increasing id order (row order kept: serial per lane, ballot
-// compaction per wave)
-__global__ void __launch_bounds__(256) ofill_kernel(int n, const int *__restrict__ rp,
-                                                     const int *__restrict__ col,
-                                                     const int *__restrict__ sub,
-                                                     const int *__restrict__ orow,
-                                                     int *__restrict__ ocol) {
-    const int lane = threadIdx.x & 63;
-    const int nw = (gridDim.x * blockDim.x) >> 6;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int vb = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; vb < n; vb += nw * 64) {
-        const int v = vb + lane;
-        int b = 0, e = 0, sv = 0;
-        if (v < n) {
-            b = rp[v];
-            e = rp[v + 1];
-            sv = sub[v];
-        }
-        const bool wide = v < n && e - b > ORIENT_LANE_ROW;
-        if (v < n && !wide) {
-            int w = orow[v];
-            for (int i = b; i < e; i++) {
-                const int u = col[i];
-                if (key_less(sv, v, sub[u], u)) ocol[w++] = u;
-            }
-        }
-        for (uint64_t wm = ballot64(wide); wm; wm &= wm - 1ull) {
-            const int L = __builtin_ctzll(wm);
-            const int x = vb + L, sx = __shfl(sv, L, 64);
-            const int xb = __shfl(b, L, 64), xe = __shfl(e, L, 64);
-            int w = orow[x];
+            int w = xb;
             for (int i0 = xb; i0 < xe; i0 += 64) {
                 const int i = i0 + lane;
                 bool take = false;
@@ -629,9 +587,41 @@ __global__ void __launch_bounds__(256) ofill_kernel(int n, const int *__restrict
                     take = key_less(sx, x, sub[u], u);
                 }
                 const uint64_t m = ballot64(take);
-                if (take) ocol[w + __popcll(m & below)] = u;
+                if (take) tmp[w + __popcll(m & below)] = u;
                 w += __popcll(m);
             }
+            if (lane == L) c = w - xb;
+        }
+        if (v < n) odeg[v] = c;
+        amax = max(amax, c);
+    }
+    amax = wave_max_i32(amax);
+    if (lane == 0) atomicMax(alpha, amax);
+}
+
+// N+(v) moved from tmp (at rp[v]) to its place in the oriented CSR:
+// contiguous copies, short rows per lane, long ones per wave
+__global__ void __launch_bounds__(256) ofill_kernel(int n, const int *__restrict__ rp,
+                                                     const int *__restrict__ tmp,
+                                                     const int *__restrict__ orow,
+                                                     int *__restrict__ ocol) {
+    const int lane = threadIdx.x & 63;
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    for (int vb = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 64; vb < n; vb += nw * 64) {
+        const int v = vb + lane;
+        int b = 0, o = 0, d = 0;
+        if (v < n) {
+            b = rp[v];
+            o = orow[v];
+            d = orow[v + 1] - o;
+        }
+        const bool wide = d > ORIENT_LANE_ROW;
+        if (!wide)
+            for (int i = 0; i < d; i++) ocol[o + i] = tmp[b + i];
+        for (uint64_t wm = ballot64(wide); wm; wm &= wm - 1ull) {
+            const int L = __builtin_ctzll(wm);
+            const int xb = __shfl(b, L, 64), xo = __shfl(o, L, 64), xd = __shfl(d, L, 64);
+            for (int i = lane; i < xd; i += 64) ocol[xo + i] = tmp[xb + i];
         }
     }
 }
@@ -898,13 +888,13 @@ hipError_t pv_launch_excl_scan(int n, const int *in, int *tmp, int *out, hipStre
 }
 
 hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
-                            int *odeg, int *orow, int *ocol, int *alpha, int *scan_tmp,
+                            int *odeg, int *orow, int *ocol, int *alpha, int *scan_tmp, int *row_tmp,
                             hipStream_t s) {
     // a wave takes 64 vertices per step
     const int wblocks = grid_for((long long)n, 256, dev.num_cu * 32);
-    odeg_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, odeg, alpha);
+    odeg_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, odeg, alpha, row_tmp);
     (void)pv_launch_excl_scan(n, odeg, scan_tmp, orow, s);
-    ofill_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, orow, ocol);
+    ofill_kernel<<<wblocks, 256, 0, s>>>(n, rp, row_tmp, orow, ocol);
     return hipGetLastError();
 }
 
