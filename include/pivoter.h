@@ -147,9 +147,10 @@ pv_status pv_set_timing(pv_ctx *ctx, int32_t on);
  * Tuning: a wavefront walks at most this many SCT nodes depth first before
  * it hands the rest of its subtree (the pending node and the pending hold
  * children on its stack) to other wavefronts.  Any value in [16, 2^20]
- * gives the same counts.  0 (the default) picks it per request: 4096 for
- * global counts alone, 8192 with local counts.  PV_DFS_BUDGET overrides the
- * default at pv_init.
+ * gives the same counts.  0 (the default) picks it per tree level: 4096
+ * for global counts alone; with local counts 8192, or 2048 on a level with
+ * fewer than 16 units per wavefront.  PV_DFS_BUDGET overrides the default
+ * at pv_init.
  */
 pv_status pv_set_dfs_budget(pv_ctx *ctx, int32_t nodes);
 

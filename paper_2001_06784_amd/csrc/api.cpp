@@ -332,8 +332,17 @@ extern "C" pv_status pv_set_stream(pv_ctx *c, void *stream) {
 // larger budgets leave long walks at the end of a level) and 8192 with local
 // counts (every unit ends with a flush of its accumulators and a partial
 // lane batch, so fewer, larger units pay)
-static int budget_of(const pv_ctx *c, bool local) {
-    return c->dfs_budget > 0 ? c->dfs_budget : (local ? 8192 : 4096);
+// Depth-first budget of a level: the set value, else 4096 with global
+// counts alone and 8192 with local counts (each unit ends with a flush and
+// a partial lane batch there, so fewer, larger units pay).  With local
+// counts, a level whose units are fewer than 16 per wave lasts as long as
+// its longest walk; 2048 then hands the rest of each long walk to the next
+// level sooner.  Any budget gives the same tree and counts.
+static int budget_of(const pv_ctx *c, bool local, long long units = -1, long long waves = 0) {
+    if (c->dfs_budget > 0) return c->dfs_budget;
+    if (!local) return 4096;
+    if (units >= 0 && units < 16 * waves) return 2048;
+    return 8192;
 }
 
 extern "C" pv_status pv_set_dfs_budget(pv_ctx *c, int32_t nodes) {
@@ -794,6 +803,8 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                     a.n0[mode] = (int)n0;
                     a.nch[mode] = (int)((n0 + chunk - 1) / chunk);
                 }
+                a.dfs_budget = budget_of(c, local, units,
+                                         (long long)c->level_blocks[kli][PV_UNITS_ITEMS] * WAVES_PER_LAUNCH_BLOCK);
                 *c->h_args = a;
                 HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 5 * sizeof(int), s));
                 HIPCHK(hipMemcpyAsync(c->d_args.p, c->h_args, sizeof(LevelArgs), hipMemcpyHostToDevice, s));
