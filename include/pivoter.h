@@ -25,6 +25,7 @@
  *   - Counts are exact unsigned 128-bit integers, stored as pv_u128
  *     {lo, hi} (little-endian limbs).  A count that reaches 2^128 is not
  *     representable: its overflow bit is set and its value is meaningless.
+ *     pv_count_global_wide returns global counts in any number of limbs.
  *   - Every entry point returns a pv_status; nothing throws across the ABI.
  *     On error the outputs are unspecified and the handles stay valid.
  *   - Work is issued on the context's HIP stream.  Entry points that return
