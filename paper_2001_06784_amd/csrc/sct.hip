@@ -219,6 +219,19 @@ struct VertexSink {
         }
     }
 
+    // lane tier: move the sums into this member's LDS slots (zero between
+    // batches) so that no register holds them while the lanes walk; the
+    // batch's own additions land on top and add_slots takes them all back
+    __device__ __forceinline__ void park(lds_u64 *slot) {
+        if constexpr (!WIDE) {
+#pragma unroll
+            for (int kk = 0; kk < KL; kk++) {
+                slot[kk] = lo[kk];
+                lo[kk] = 0ull;
+            }
+        }
+    }
+
     // lane tier: add this member's LDS slots and clear them
     __device__ __forceinline__ void add_slots(lds_u64 *slot, int) {
 #pragma unroll
@@ -642,7 +655,11 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
     __shared__ uint32_t s_lst[WAVES_PER_BLOCK][PV_LANE_MAX - 1][64];
     uint32_t(*st)[64] = s_lst[threadIdx.x >> 6];
     lds_u64 *acc = nullptr;
-    if constexpr (LOC) acc = lane_acc<KL>();
+    if constexpr (LOC) {
+        acc = lane_acc<KL>();
+        vs.park(acc + lane * (KL + 1));
+        wave_sync();
+    }
     uint64_t sH[NK], sP[NK];  // this lane's sums toward the vertices above its node
 #pragma unroll
     for (int kk = 0; kk < NK; kk++) sH[kk] = sP[kk] = 0;
