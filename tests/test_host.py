@@ -1,0 +1,39 @@
+"""Host-side checks that need no GPU: the benchmark's command line and the
+seeded generators that feed both the oracle and the GPU path."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+from paper_2001_06784_amd import graphgen as gg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_refuses_several_gpus():
+    # one GPU only: the request is refused before anything touches a device
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_rmat_web_plants_disjoint_cliques():
+    # R-MAT plus planted cliques: every planted set is a clique, the sets are
+    # disjoint, and the generator is deterministic for its seeds
+    g = gg.rmat_web(scale=10, cliques=4, clique_lo=20, clique_hi=24)
+    h = gg.rmat_web(scale=10, cliques=4, clique_lo=20, clique_hi=24)
+    assert np.array_equal(g.row_ptr, h.row_ptr) and np.array_equal(g.col, h.col)
+    sizes = gg._rng(2).integers(20, 25, 4)
+    verts = gg._rng(3).permutation(g.n)[: int(sizes.sum())]
+    off = 0
+    seen = set()
+    for s in sizes:
+        vs = [int(v) for v in verts[off: off + s]]
+        off += s
+        assert not seen.intersection(vs)
+        seen.update(vs)
+        for a in vs:
+            row = set(g.col[g.row_ptr[a]: g.row_ptr[a + 1]].tolist())
+            assert all(b in row for b in vs if b != a)
