@@ -132,6 +132,9 @@ __device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
 // joins a block gathers in LDS per sub-round before the rest go straight to
 // the next frontier
 #define PEEL_JOIN_LDS 4096
+// vertices per thread a level change reads with their loads in flight
+// together (and holds in registers when one batch covers the graph)
+#define PEEL_LC_BATCH 16
 
 // exclusive prefix sum over the block (blockDim.x == PV_PEEL_THREADS);
 // returns the block total in *total
@@ -205,12 +208,32 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     while (n - removed > PV_SOLO_MAX) {
         if (nF == 0) {
             // level change: k = smallest remaining degree (a block minimum
-            // in LDS, one global atomic per block)
+            // in LDS, one global atomic per block).  A thread reads its
+            // vertices tid, tid + nth, ... PEEL_LC_BATCH at a time with all
+            // loads in flight together; when one batch covers the graph, the
+            // degrees stay in registers for the take pass (no decrement
+            // happens between the two passes).
             if (threadIdx.x == 0) s_kmin = 0x7fffffff;
             __syncthreads();
             int mymin = 0x7fffffff;
-            for (int v = tid; v < n; v += nth)
-                if (sub[v] < 0) mymin = min(mymin, deg[v]);
+            int dk[PEEL_LC_BATCH];  // remaining degree; INT_MAX if removed or past n
+#pragma unroll
+            for (int q = 0; q < PEEL_LC_BATCH; q++) dk[q] = 0x7fffffff;
+            for (int v0 = tid; v0 < n; v0 += nth * PEEL_LC_BATCH) {
+                int sq[PEEL_LC_BATCH];
+#pragma unroll
+                for (int q = 0; q < PEEL_LC_BATCH; q++) {
+                    const int v = v0 + q * nth < n ? v0 + q * nth : 0;
+                    sq[q] = sub[v];
+                    dk[q] = deg[v];
+                }
+#pragma unroll
+                for (int q = 0; q < PEEL_LC_BATCH; q++) {
+                    if (v0 + q * nth >= n || sq[q] >= 0) dk[q] = 0x7fffffff;
+                    mymin = min(mymin, dk[q]);
+                }
+            }
+            const bool held = n <= nth * PEEL_LC_BATCH;
             mymin = wave_min_i32(mymin);
             if (lane == 0) atomicMin(&s_kmin, mymin);
             __syncthreads();
@@ -221,11 +244,24 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             int *F = (r & 1) ? pa.fb : pa.fa;
             if (threadIdx.x == 0) s_nj = 0;
             __syncthreads();
-            for (int vb = wid * 64; vb < n; vb += nw * 64) {
-                const int v = vb + lane;
-                const bool take = v < n && sub[v] < 0 && deg[v] <= k;
-                if (take) sub[v] = r;
-                list_add(take, v, F, &ctl->cnt[r % 3]);
+            if (held) {
+                // vertex wid * 64 + lane + q * nth is this lane's q-th; the
+                // loop bound is uniform across the wave, as list_add needs
+#pragma unroll
+                for (int q = 0; q < PEEL_LC_BATCH; q++) {
+                    if (wid * 64 + q * nth >= n) break;
+                    const int v = tid + q * nth;
+                    const bool take = dk[q] <= k;
+                    if (take) sub[v] = r;
+                    list_add(take, v, F, &ctl->cnt[r % 3]);
+                }
+            } else {
+                for (int vb = wid * 64; vb < n; vb += nw * 64) {
+                    const int v = vb + lane;
+                    const bool take = v < n && sub[v] < 0 && deg[v] <= k;
+                    if (take) sub[v] = r;
+                    list_add(take, v, F, &ctl->cnt[r % 3]);
+                }
             }
             list_flush(F, &ctl->cnt[r % 3]);
             if (!grid_barrier(ctl, nb, epoch)) return;
