@@ -135,6 +135,8 @@ __device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
 // vertices per thread a level change reads with their loads in flight
 // together (and holds in registers when one batch covers the graph)
 #define PEEL_LC_BATCH 16
+// row entries per lane a step of U's compaction reads (loads in flight)
+#define PEEL_CSR_UNROLL 8
 
 // exclusive prefix sum over the block (blockDim.x == PV_PEEL_THREADS);
 // returns the block total in *total
@@ -401,11 +403,25 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         if (threadIdx.x == 0) atomicOr(&ctl->err, 2);
         return;
     }
-    // induced degree of every vertex of U (one wave per vertex)
+    // induced degree of every vertex of U (one wave per vertex, 64 *
+    // PEEL_CSR_UNROLL entries a step with their loads in flight together:
+    // the hubs' long rows are on U's critical path)
     for (int i = wid; i < nu; i += nw) {
         const int v = pa.uverts[i];
+        const int e0 = rp[v], e1 = rp[v + 1];
         int c = 0;
-        for (int e = rp[v] + lane; e < rp[v + 1]; e += 64) c += (pa.lid[col[e]] >= 0) ? 1 : 0;
+        for (int eb = e0; eb < e1; eb += 64 * PEEL_CSR_UNROLL) {
+            int u[PEEL_CSR_UNROLL];
+#pragma unroll
+            for (int q = 0; q < PEEL_CSR_UNROLL; q++) {
+                const int e = eb + q * 64 + lane;
+                u[q] = col[e < e1 ? e : e0];
+            }
+#pragma unroll
+            for (int q = 0; q < PEEL_CSR_UNROLL; q++) u[q] = pa.lid[u[q]];
+#pragma unroll
+            for (int q = 0; q < PEEL_CSR_UNROLL; q++) c += (eb + q * 64 + lane < e1 && u[q] >= 0) ? 1 : 0;
+        }
         c = (int)wave_add_u32((uint32_t)c);
         if (lane == 0) pa.ldeg[i] = c;
     }
@@ -429,13 +445,23 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         for (int i = wid; i < nu; i += nw) {
             const int v = pa.uverts[i];
             int w = pa.lrp[i];
-            const int e1 = rp[v + 1];
-            for (int e0 = rp[v]; e0 < e1; e0 += 64) {
-                const int e = e0 + lane;
-                const int l = (e < e1) ? pa.lid[col[e]] : -1;
-                const uint64_t m = ballot64(l >= 0);
-                if (l >= 0) pa.lcol[w + __popcll(m & below)] = l;
-                w += __popcll(m);
+            const int e0 = rp[v], e1 = rp[v + 1];
+            for (int eb = e0; eb < e1; eb += 64 * PEEL_CSR_UNROLL) {
+                int l[PEEL_CSR_UNROLL];
+#pragma unroll
+                for (int q = 0; q < PEEL_CSR_UNROLL; q++) {
+                    const int e = eb + q * 64 + lane;
+                    l[q] = col[e < e1 ? e : e0];
+                }
+#pragma unroll
+                for (int q = 0; q < PEEL_CSR_UNROLL; q++) l[q] = pa.lid[l[q]];
+#pragma unroll
+                for (int q = 0; q < PEEL_CSR_UNROLL; q++) {
+                    const bool in = eb + q * 64 + lane < e1 && l[q] >= 0;
+                    const uint64_t m = ballot64(in);
+                    if (in) pa.lcol[w + __popcll(m & below)] = l[q];
+                    w += __popcll(m);
+                }
             }
         }
     }
