@@ -118,7 +118,7 @@ struct DBuf {
 struct Workspace {
     // peel / orientation temporaries
     DBuf<int> deg, fa, fb, scan, rcnt;  // rcnt: per-chunk out-degree histograms of the root order
-    DBuf<int> lid, uverts, ldeg, lrp, lcol, bcnt;  // solo phase of the peel
+    DBuf<int> lid, uverts, ldeg, lrp, lcol, bcnt, lrow;  // solo phase of the peel
     DBuf<PeelCtl> ctl;
     // SCT work buffers
     DBuf<CItem> citem[2];
@@ -148,7 +148,7 @@ struct Workspace {
         DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &lid, &uverts, &ldeg, &lrp, &lcol,
                            &bcnt, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid,
                            &u_grp, &pg_cnt, &pg_off, &pg_pos, &pg_list, &wide_i, &fq_flags, &fq_idx,
-                           &fq_pos};
+                           &fq_pos, &lrow};
         for (auto *b : ib) b->release();
         ctl.release();
         citem[0].release();
@@ -533,6 +533,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     PVCHK(c->ws.lrp.ensure(PV_SOLO_MAX + 1));
     PVCHK(c->ws.lcol.ensure((size_t)std::max<long long>(g->nnz, 1)));
     PVCHK(c->ws.bcnt.ensure(PV_PEEL_MAX_BLOCKS));
+    PVCHK(c->ws.lrow.ensure(2 * PV_SOLO_MAX));
     hipStream_t s = c->stream;
     PeelCtl init;
     memset(&init, 0, sizeof init);
@@ -557,6 +558,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
         pa.lrp = c->ws.lrp.p;
         pa.lcol = c->ws.lcol.p;
         pa.bcnt = c->ws.bcnt.p;
+        pa.lrow = c->ws.lrow.p;
         HIPCHK(pv_launch_peel(c->dev, pa, s));
         if (c->timing) HIPCHK(hipEventRecord(c->ev[1], s));
         HIPCHK(pv_launch_orient(c->dev, n, g->rp.p, g->col.p, g->sub.p, g->odeg.p, g->orow.p,

@@ -22,6 +22,7 @@ struct PeelCtl {
     int subrounds;       // out: number of sub-rounds
     int alpha;           // out: degeneracy (largest level)
     int err;             // out: a grid barrier timed out
+    int nlong;           // rows of the solo subgraph split over the grid
     unsigned bar_flag[256 * 32];  // grid barrier: barriers passed by each block, one 128-byte line each
 };
 
@@ -43,6 +44,7 @@ struct PeelArgs {
     int *lrp;            // [PV_SOLO_MAX + 1] local CSR rows
     int *lcol;           // [nnz] local CSR columns
     int *bcnt;           // [blocks] per-block counts
+    int *lrow;           // [2 * PV_SOLO_MAX] long rows of U (local ids), then one fill cursor each
 };
 
 // Largest out-degree handled by the compact (register) tier.  Roots with

@@ -137,6 +137,8 @@ __device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
 #define PEEL_LC_BATCH 16
 // row entries per lane a step of U's compaction reads (loads in flight)
 #define PEEL_CSR_UNROLL 8
+// rows of U longer than this are split over the grid's waves
+#define PEEL_LONG_ROW 4096
 
 // exclusive prefix sum over the block (blockDim.x == PV_PEEL_THREADS);
 // returns the block total in *total
@@ -403,27 +405,65 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         if (threadIdx.x == 0) atomicOr(&ctl->err, 2);
         return;
     }
-    // induced degree of every vertex of U (one wave per vertex, 64 *
-    // PEEL_CSR_UNROLL entries a step with their loads in flight together:
-    // the hubs' long rows are on U's critical path)
+    // induced degree of every vertex of U and its local CSR: neighbours
+    // inside U, as local ids.  A wave reads 64 * PEEL_CSR_UNROLL entries of
+    // a row a step with the loads in flight together.  Rows longer than
+    // PEEL_LONG_ROW (the hubs, on U's critical path) are listed in
+    // pa.lrow and split over the grid's waves: G = nw / nl waves per row,
+    // each taking every G-th step of it; their degrees are summed with
+    // atomics and their CSR entries placed through a cursor per row, in no
+    // particular order (the solo phase does not depend on the order within
+    // a row).  Other rows keep their row order.
+    const auto row_step = [&](int eb, int e0, int e1, int (&l)[PEEL_CSR_UNROLL]) {
+#pragma unroll
+        for (int q = 0; q < PEEL_CSR_UNROLL; q++) {
+            const int e = eb + q * 64 + lane;
+            l[q] = col[e < e1 ? e : e0];
+        }
+#pragma unroll
+        for (int q = 0; q < PEEL_CSR_UNROLL; q++) l[q] = pa.lid[l[q]];
+#pragma unroll
+        for (int q = 0; q < PEEL_CSR_UNROLL; q++)
+            if (eb + q * 64 + lane >= e1) l[q] = -1;
+    };
+    constexpr int SEG = 64 * PEEL_CSR_UNROLL;
     for (int i = wid; i < nu; i += nw) {
         const int v = pa.uverts[i];
         const int e0 = rp[v], e1 = rp[v + 1];
-        int c = 0;
-        for (int eb = e0; eb < e1; eb += 64 * PEEL_CSR_UNROLL) {
-            int u[PEEL_CSR_UNROLL];
-#pragma unroll
-            for (int q = 0; q < PEEL_CSR_UNROLL; q++) {
-                const int e = eb + q * 64 + lane;
-                u[q] = col[e < e1 ? e : e0];
+        if (e1 - e0 > PEEL_LONG_ROW) {
+            if (lane == 0) {
+                pa.lrow[atomicAdd(&ctl->nlong, 1)] = i;  // at most nu <= PV_SOLO_MAX rows
+                pa.ldeg[i] = 0;
             }
+            continue;
+        }
+        int c = 0;
+        for (int eb = e0; eb < e1; eb += SEG) {
+            int l[PEEL_CSR_UNROLL];
+            row_step(eb, e0, e1, l);
 #pragma unroll
-            for (int q = 0; q < PEEL_CSR_UNROLL; q++) u[q] = pa.lid[u[q]];
-#pragma unroll
-            for (int q = 0; q < PEEL_CSR_UNROLL; q++) c += (eb + q * 64 + lane < e1 && u[q] >= 0) ? 1 : 0;
+            for (int q = 0; q < PEEL_CSR_UNROLL; q++) c += l[q] >= 0 ? 1 : 0;
         }
         c = (int)wave_add_u32((uint32_t)c);
         if (lane == 0) pa.ldeg[i] = c;
+    }
+    if (!grid_barrier(ctl, nb, epoch)) return;
+    const int nl = ld_acquire(&ctl->nlong);
+    const int G = nl > 0 ? max(1, nw / nl) : 1;
+    // long rows: wave t takes row t % nl from step t / nl on, every G-th step
+    for (int t = wid; t < nl * G; t += nw) {
+        const int i = pa.lrow[t % nl];
+        const int v = pa.uverts[i];
+        const int e0 = rp[v], e1 = rp[v + 1];
+        int c = 0;
+        for (int eb = e0 + (t / nl) * SEG; eb < e1; eb += G * SEG) {
+            int l[PEEL_CSR_UNROLL];
+            row_step(eb, e0, e1, l);
+#pragma unroll
+            for (int q = 0; q < PEEL_CSR_UNROLL; q++) c += l[q] >= 0 ? 1 : 0;
+        }
+        c = (int)wave_add_u32((uint32_t)c);
+        if (lane == 0 && c) atomicAdd(&pa.ldeg[i], c);
     }
     if (!grid_barrier(ctl, nb, epoch)) return;
     if (blockIdx.x == 0) {
@@ -437,30 +477,51 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             base += tot;
         }
         if (threadIdx.x == 0) pa.lrp[nu] = base;
+        __syncthreads();
+        // fill cursor of every long row: its row start
+        for (int j = threadIdx.x; j < nl; j += blockDim.x) pa.lrow[PV_SOLO_MAX + j] = pa.lrp[pa.lrow[j]];
     }
     if (!grid_barrier(ctl, nb, epoch)) return;
-    // local CSR: neighbours inside U, as local ids, in row order
     {
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         for (int i = wid; i < nu; i += nw) {
             const int v = pa.uverts[i];
-            int w = pa.lrp[i];
             const int e0 = rp[v], e1 = rp[v + 1];
-            for (int eb = e0; eb < e1; eb += 64 * PEEL_CSR_UNROLL) {
+            if (e1 - e0 > PEEL_LONG_ROW) continue;
+            int w = pa.lrp[i];
+            for (int eb = e0; eb < e1; eb += SEG) {
                 int l[PEEL_CSR_UNROLL];
+                row_step(eb, e0, e1, l);
 #pragma unroll
                 for (int q = 0; q < PEEL_CSR_UNROLL; q++) {
-                    const int e = eb + q * 64 + lane;
-                    l[q] = col[e < e1 ? e : e0];
-                }
-#pragma unroll
-                for (int q = 0; q < PEEL_CSR_UNROLL; q++) l[q] = pa.lid[l[q]];
-#pragma unroll
-                for (int q = 0; q < PEEL_CSR_UNROLL; q++) {
-                    const bool in = eb + q * 64 + lane < e1 && l[q] >= 0;
-                    const uint64_t m = ballot64(in);
-                    if (in) pa.lcol[w + __popcll(m & below)] = l[q];
+                    const uint64_t m = ballot64(l[q] >= 0);
+                    if (l[q] >= 0) pa.lcol[w + __popcll(m & below)] = l[q];
                     w += __popcll(m);
+                }
+            }
+        }
+        for (int t = wid; t < nl * G; t += nw) {
+            const int j = t % nl;
+            const int v = pa.uverts[pa.lrow[j]];
+            const int e0 = rp[v], e1 = rp[v + 1];
+            for (int eb = e0 + (t / nl) * SEG; eb < e1; eb += G * SEG) {
+                int l[PEEL_CSR_UNROLL];
+                row_step(eb, e0, e1, l);
+                uint64_t m[PEEL_CSR_UNROLL];
+                int tot = 0;
+#pragma unroll
+                for (int q = 0; q < PEEL_CSR_UNROLL; q++) {
+                    m[q] = ballot64(l[q] >= 0);
+                    tot += __popcll(m[q]);
+                }
+                if (tot == 0) continue;
+                int w = 0;
+                if (lane == 0) w = atomicAdd(&pa.lrow[PV_SOLO_MAX + j], tot);
+                w = __shfl(w, 0);
+#pragma unroll
+                for (int q = 0; q < PEEL_CSR_UNROLL; q++) {
+                    if (l[q] >= 0) pa.lcol[w + __popcll(m[q] & below)] = l[q];
+                    w += __popcll(m[q]);
                 }
             }
         }
