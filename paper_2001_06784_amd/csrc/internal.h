@@ -23,6 +23,7 @@ struct PeelCtl {
     int alpha;           // out: degeneracy (largest level)
     int err;             // out: a grid barrier timed out
     int nlong;           // rows of the solo subgraph split over the grid
+    int blk_r, blk_nf, blk_removed;  // where block 0's run of small sub-rounds stopped
     unsigned bar_flag[256 * 32];  // grid barrier: barriers passed by each block, one 128-byte line each
 };
 

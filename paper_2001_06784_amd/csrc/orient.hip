@@ -139,6 +139,10 @@ __device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
 #define PEEL_CSR_UNROLL 8
 // rows of U longer than this are split over the grid's waves
 #define PEEL_LONG_ROW 4096
+// frontiers of at most this many vertices are removed by block 0 alone, up
+// to PEEL_BLOCK_ROUNDS sub-rounds in a row between two grid barriers
+#define PEEL_BLOCK_FRONTIER 16
+#define PEEL_BLOCK_ROUNDS 256
 
 // exclusive prefix sum over the block (blockDim.x == PV_PEEL_THREADS);
 // returns the block total in *total
@@ -315,6 +319,51 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                 visit(u, live);
             }
         };
+        if (nF <= PEEL_BLOCK_FRONTIER) {
+            // a small frontier (the tail of a level): block 0 runs this
+            // sub-round and the next small ones alone, one wave per frontier
+            // vertex and workgroup barriers only, while the other blocks
+            // wait at the next grid barrier.  Within the block, frontiers
+            // are read back with agent-scope loads (never a stale L1 line);
+            // removal keys and degrees already go through atomics.  The grid
+            // barrier then publishes everything, and where block 0 stopped.
+            if (blockIdx.x == 0) {
+                const int bw = threadIdx.x >> 6, nbw = blockDim.x >> 6;
+                for (int t = 0;; t++) {
+                    for (int i = bw; i < nF; i += nbw) {
+                        const int v = ld_acquire(&F[i]);
+                        wave_row(rp[v], rp[v + 1]);
+                    }
+                    list_flush(Fn, ncnt);
+                    __syncthreads();
+                    removed += nF;
+                    nF = ld_acquire(ncnt);
+                    r++;
+                    if (nF == 0 || nF > PEEL_BLOCK_FRONTIER || t + 1 >= PEEL_BLOCK_ROUNDS ||
+                        n - removed <= PV_SOLO_MAX)
+                        break;
+                    F = (r & 1) ? pa.fb : pa.fa;
+                    Fn = (r & 1) ? pa.fa : pa.fb;
+                    ncnt = &ctl->cnt[(r + 1) % 3];
+                    if (threadIdx.x == 0) {
+                        ctl->cnt[(r + 2) % 3] = 0;
+                        ctl->minv[(r + 1) & 1] = 0x7fffffff;
+                        s_nj = 0;
+                    }
+                    __syncthreads();
+                }
+                if (threadIdx.x == 0) {
+                    ctl->blk_r = r;
+                    ctl->blk_nf = nF;
+                    ctl->blk_removed = removed;
+                }
+            }
+            if (!grid_barrier(ctl, nb, epoch)) return;
+            r = ld_acquire(&ctl->blk_r);
+            nF = ld_acquire(&ctl->blk_nf);
+            removed = ld_acquire(&ctl->blk_removed);
+            continue;
+        }
         if (nF >= nw * 8) {
             // a large frontier (the first sub-rounds of the low levels): a
             // wave takes 64 vertices at a time, vertex i0 + lane * nw + wid

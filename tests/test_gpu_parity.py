@@ -270,6 +270,29 @@ def test_peel_order_with_a_hub(ctx, n):
     assert np.array_equal(sub, pe.sub)
 
 
+def _paths(lengths):
+    g = gg.path(int(lengths[0]))
+    for L in lengths[1:]:
+        g = gg.disjoint_union(g, gg.path(int(L)))
+    return g
+
+
+@pytest.mark.parametrize("name,g", [("path 40000", gg.path(40_000)),
+                                    ("paths 2..300 and 60000", _paths(np.append(np.arange(2, 301), 60_000)))])
+def test_peel_order_small_frontiers(ctx, name, g):
+    # long runs of sub-rounds with a handful of vertices each while the
+    # graph is still large: the runs block 0 takes alone between two grid
+    # barriers (frontiers of a path shrink to two vertices; a union of paths
+    # goes from large frontiers to small ones as its shorter paths run out)
+    _say(f"[parity] peel {name} n={g.n}")
+    with Loaded(ctx, g) as h:
+        alpha = P.pv_graph_orient(h)
+        sub = P.pv_graph_export_order(h)
+    pe = O.peel(g)
+    assert alpha == pe.alpha
+    assert np.array_equal(sub, pe.sub)
+
+
 @pytest.mark.parametrize("name,g", [("cycle 16384", gg.cycle(16384)), ("cycle 40000", gg.cycle(40000)),
                                     ("empty 30000", gg.empty(30000))])
 def test_peel_order_one_big_frontier(ctx, name, g):
