@@ -141,7 +141,7 @@ __device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
 #define PEEL_LONG_ROW 4096
 // frontiers of at most this many vertices are removed by block 0 alone, up
 // to PEEL_BLOCK_ROUNDS sub-rounds in a row between two grid barriers
-#define PEEL_BLOCK_FRONTIER 16
+#define PEEL_BLOCK_FRONTIER 32
 #define PEEL_BLOCK_ROUNDS 256
 
 // exclusive prefix sum over the block (blockDim.x == PV_PEEL_THREADS);
@@ -298,11 +298,31 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             int old[PEEL_UNROLL];
 #pragma unroll
             for (int q = 0; q < PEEL_UNROLL; q++) old[q] = live[q] ? atomicSub(&deg[u[q]], 1) : 0;
+            // one slot reservation in the block's list for all the joins
+            bool join[PEEL_UNROLL];
+            uint64_t jm[PEEL_UNROLL];
+            int jt = 0;
 #pragma unroll
             for (int q = 0; q < PEEL_UNROLL; q++) {
-                const bool join = live[q] && old[q] == k + 1;
-                if (join) sub[u[q]] = r + 1;
-                list_add(join, u[q], Fn, ncnt);
+                join[q] = live[q] && old[q] == k + 1;
+                if (join[q]) sub[u[q]] = r + 1;
+                jm[q] = ballot64(join[q]);
+                jt += __popcll(jm[q]);
+            }
+            if (jt) {
+                const uint64_t bl = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                int slot = 0;
+                if (lane == 0) slot = atomicAdd(&s_nj, jt);
+                slot = __shfl(slot, 0);
+#pragma unroll
+                for (int q = 0; q < PEEL_UNROLL; q++) {
+                    if (join[q]) {
+                        const int sl = slot + __popcll(jm[q] & bl);
+                        if (sl < PEEL_JOIN_LDS) s_join[sl] = u[q];
+                        else Fn[atomicAdd(ncnt, 1)] = u[q];
+                    }
+                    slot += __popcll(jm[q]);
+                }
             }
         };
         // a row walked by the whole wave, 64 * PEEL_UNROLL entries at a time
@@ -624,6 +644,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     for (int j = threadIdx.x; j < nF; j += blockDim.x) s_h16[s_Fq[j]] = 0;
     __syncthreads();
     const int bw = threadIdx.x >> 6, nbw = blockDim.x >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int left = nu;
     for (;;) {
         if (nF == 0) {
@@ -673,19 +694,37 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                     live[q] = e < e1;
                     w[q] = lcol[live[q] ? e : e0];
                 }
+                // the step's decrements first, then one slot reservation for
+                // all its joins
+                bool join[PEEL_UNROLL];
 #pragma unroll
                 for (int q = 0; q < PEEL_UNROLL; q++) {
-                    bool join = false;
+                    join[q] = false;
                     if (live[q] && alive(w[q])) {
                         const unsigned sh = (w[q] & 1) * 16;
                         const unsigned old = atomicSub(&s_deg2[w[q] >> 1], 1u << sh);
                         if ((int)((old >> sh) & 0xFFFFu) == k + 1) {
                             atomicAnd(&s_alive[w[q] >> 5], ~(1u << (w[q] & 31)));
-                            join = true;
+                            join[q] = true;
                         }
                     }
-                    const int slot = wave_slot(join, &s_cnt3[(r + 1) % 3]);
-                    if (join) s_Fq[nbase + slot] = (unsigned short)w[q];
+                }
+                uint64_t jm[PEEL_UNROLL];
+                int jt = 0;
+#pragma unroll
+                for (int q = 0; q < PEEL_UNROLL; q++) {
+                    jm[q] = ballot64(join[q]);
+                    jt += __popcll(jm[q]);
+                }
+                if (jt) {
+                    int slot = 0;
+                    if (lane == 0) slot = atomicAdd(&s_cnt3[(r + 1) % 3], jt);
+                    slot = nbase + __shfl(slot, 0);
+#pragma unroll
+                    for (int q = 0; q < PEEL_UNROLL; q++) {
+                        if (join[q]) s_Fq[slot + __popcll(jm[q] & below)] = (unsigned short)w[q];
+                        slot += __popcll(jm[q]);
+                    }
                 }
             }
         }
