@@ -143,6 +143,9 @@ __device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
 // to PEEL_BLOCK_ROUNDS sub-rounds in a row between two grid barriers
 #define PEEL_BLOCK_FRONTIER 32
 #define PEEL_BLOCK_ROUNDS 256
+// local vertices per thread in the solo phase (blockDim.x == PV_PEEL_THREADS)
+#define PEEL_SOLO_PER_THREAD (PV_SOLO_MAX / PV_PEEL_THREADS)
+static_assert(PV_SOLO_MAX % PV_PEEL_THREADS == 0, "solo phase: whole vertices per thread");
 
 // exclusive prefix sum over the block (blockDim.x == PV_PEEL_THREADS);
 // returns the block total in *total
@@ -649,11 +652,20 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     for (;;) {
         if (nF == 0) {
             if (left == 0) break;
+            // level change: local vertex threadIdx.x + q * blockDim.x is
+            // this thread's q-th; its remaining degree (INT_MAX once removed)
+            // stays in a register from the minimum to the take, and a wave
+            // reserves the slots of all its takes with one LDS atomic
             if (threadIdx.x == 0) s_min = 0x7fffffff;
             __syncthreads();
+            int dq[PEEL_SOLO_PER_THREAD];
             int mymin = 0x7fffffff;
-            for (int i = threadIdx.x; i < nu; i += blockDim.x)
-                if (alive(i)) mymin = min(mymin, degof(i));
+#pragma unroll
+            for (int q = 0; q < PEEL_SOLO_PER_THREAD; q++) {
+                const int i = threadIdx.x + q * PV_PEEL_THREADS;
+                dq[q] = (i < nu && alive(i)) ? degof(i) : 0x7fffffff;
+                mymin = min(mymin, dq[q]);
+            }
             mymin = wave_min_i32(mymin);
             if (lane == 0) atomicMin(&s_min, mymin);
             __syncthreads();
@@ -662,13 +674,23 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             // the frontier of sub-round r, counted on s_cnt3[r % 3]
             if (threadIdx.x == 0) s_cnt3[r % 3] = 0;
             __syncthreads();
-            for (int ib = bw * 64; ib < nu; ib += nbw * 64) {
-                const int i = ib + lane;
-                const bool take = i < nu && alive(i) && degof(i) <= k;
-                const int slot = wave_slot(take, &s_cnt3[r % 3]);
-                if (take) {
-                    atomicAnd(&s_alive[i >> 5], ~(1u << (i & 31)));
-                    s_Fq[fbase + slot] = (unsigned short)i;
+            int tt = 0;
+#pragma unroll
+            for (int q = 0; q < PEEL_SOLO_PER_THREAD; q++) tt += __popcll(ballot64(dq[q] <= k));
+            if (tt) {
+                int slot = 0;
+                if (lane == 0) slot = atomicAdd(&s_cnt3[r % 3], tt);
+                slot = fbase + __shfl(slot, 0);
+#pragma unroll
+                for (int q = 0; q < PEEL_SOLO_PER_THREAD; q++) {
+                    const int i = threadIdx.x + q * PV_PEEL_THREADS;
+                    const bool take = dq[q] <= k;
+                    const uint64_t m = ballot64(take);
+                    if (take) {
+                        atomicAnd(&s_alive[i >> 5], ~(1u << (i & 31)));
+                        s_Fq[slot + __popcll(m & below)] = (unsigned short)i;
+                    }
+                    slot += __popcll(m);
                 }
             }
             __syncthreads();
