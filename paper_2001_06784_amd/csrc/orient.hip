@@ -778,6 +778,8 @@ __device__ __forceinline__ bool key_less(int su, int u, int sv, int v) {
 // Rows of at most ORIENT_LANE_ROW entries are walked one vertex per lane
 // (most rows of a sparse graph are short), longer ones by the whole wave.
 #define ORIENT_LANE_ROW 32
+// row entries a lane reads per step of such a row
+#define ORIENT_UNROLL 4
 
 // out-degree of every vertex; N+(v) (row order kept, so increasing id) is
 // also written to tmp at v's own row start rp[v]: serial per lane, ballot
@@ -802,9 +804,17 @@ __global__ void __launch_bounds__(256) odeg_kernel(int n, const int *__restrict_
         const bool wide = v < n && e - b > ORIENT_LANE_ROW;
         int c = 0;
         if (v < n && !wide)
-            for (int i = b; i < e; i++) {
-                const int u = col[i];
-                if (key_less(sv, v, sub[u], u)) tmp[b + c++] = u;
+            // ORIENT_UNROLL entries a step: their column and key loads in
+            // flight together rather than one dependent pair at a time
+            for (int i0 = b; i0 < e; i0 += ORIENT_UNROLL) {
+                int u[ORIENT_UNROLL], su[ORIENT_UNROLL];
+#pragma unroll
+                for (int q = 0; q < ORIENT_UNROLL; q++) u[q] = col[i0 + q < e ? i0 + q : i0];
+#pragma unroll
+                for (int q = 0; q < ORIENT_UNROLL; q++) su[q] = sub[u[q]];
+#pragma unroll
+                for (int q = 0; q < ORIENT_UNROLL; q++)
+                    if (i0 + q < e && key_less(sv, v, su[q], u[q])) tmp[b + c++] = u[q];
             }
         for (uint64_t wm = ballot64(wide); wm; wm &= wm - 1ull) {
             const int L = __builtin_ctzll(wm);
