@@ -12,8 +12,9 @@
 // sub-round is exactly the set of vertices whose degree an atomic decrement
 // takes from k+1 to k, so every vertex is appended once without rescanning
 // the graph; only a level change scans the remaining vertices.  Sub-rounds
-// end with a grid barrier while the graph is large; its small remainder is
-// finished by one workgroup (see below).
+// end with a grid barrier while the graph is large (runs of sub-rounds with
+// a handful of vertices each are taken by one workgroup between two grid
+// barriers); its small remainder is finished by one workgroup (see below).
 #include "common.h"
 #include "internal.h"
 
