@@ -779,8 +779,8 @@ __device__ __forceinline__ bool key_less(int su, int u, int sv, int v) {
 // Rows of at most ORIENT_LANE_ROW entries are walked one vertex per lane
 // (most rows of a sparse graph are short), longer ones by the whole wave.
 #define ORIENT_LANE_ROW 32
-// row entries a lane reads per step of such a row
-#define ORIENT_UNROLL 4
+// row entries a lane reads per step of such a row (loads in flight together)
+#define ORIENT_UNROLL 8
 
 // out-degree of every vertex; N+(v) (row order kept, so increasing id) is
 // also written to tmp at v's own row start rp[v]: serial per lane, ballot
