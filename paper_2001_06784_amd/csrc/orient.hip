@@ -257,15 +257,30 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             if (threadIdx.x == 0) s_nj = 0;
             __syncthreads();
             if (held) {
-                // vertex wid * 64 + lane + q * nth is this lane's q-th; the
-                // loop bound is uniform across the wave, as list_add needs
+                // vertex tid + q * nth is this lane's q-th (dk is INT_MAX
+                // past n); a wave reserves the list slots of all its takes
+                // with one LDS atomic
+                int tt = 0;
 #pragma unroll
-                for (int q = 0; q < PEEL_LC_BATCH; q++) {
-                    if (wid * 64 + q * nth >= n) break;
-                    const int v = tid + q * nth;
-                    const bool take = dk[q] <= k;
-                    if (take) sub[v] = r;
-                    list_add(take, v, F, &ctl->cnt[r % 3]);
+                for (int q = 0; q < PEEL_LC_BATCH; q++) tt += __popcll(ballot64(dk[q] <= k));
+                if (tt) {
+                    const uint64_t bl = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                    int slot = 0;
+                    if (lane == 0) slot = atomicAdd(&s_nj, tt);
+                    slot = __shfl(slot, 0);
+#pragma unroll
+                    for (int q = 0; q < PEEL_LC_BATCH; q++) {
+                        const bool take = dk[q] <= k;
+                        const uint64_t m = ballot64(take);
+                        if (take) {
+                            const int v = tid + q * nth;
+                            sub[v] = r;
+                            const int sl = slot + __popcll(m & bl);
+                            if (sl < PEEL_JOIN_LDS) s_join[sl] = v;
+                            else F[atomicAdd(&ctl->cnt[r % 3], 1)] = v;
+                        }
+                        slot += __popcll(m);
+                    }
                 }
             } else {
                 for (int vb = wid * 64; vb < n; vb += nw * 64) {
