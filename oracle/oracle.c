@@ -168,6 +168,9 @@ typedef struct {
     uint64_t *hist;
 
     uint64_t nodes, leaves, work_sw, hist_out;
+    uint64_t work_child; /* sum over internal nodes of (children) * ceil(|S|/64) */
+    uint64_t leaf_hp;    /* sum over leaves of h + p */
+    uint64_t leaf_pairs; /* sum over leaves of C(h + p, 2) */
     int32_t maxdepth, omega, need_kcap;
     int32_t *H, *P;      /* current path (hold / pivot vertices) */
     int32_t *arena;      /* one buffer of alpha+1 ints per depth */
@@ -228,6 +231,8 @@ static void vertex_add(orc_t *o, int32_t v, int32_t base, int32_t pp) {
 /* Alg. 2 applied to one root-to-leaf path */
 static void leaf(orc_t *o, int32_t h, int32_t p) {
     o->leaves++;
+    o->leaf_hp += (uint64_t)(h + p);
+    o->leaf_pairs += (uint64_t)(h + p) * (uint64_t)(h + p - 1) / 2;
     if (h + p > o->omega) o->omega = h + p;
     if (o->hist && h < o->hd && p < o->hd) o->hist[(size_t)h * o->hd + p]++;
     else if (o->hist) o->hist_out++;
@@ -287,6 +292,7 @@ static void rec(orc_t *o, const int32_t *S, int32_t s, int32_t h, int32_t p, int
     for (int32_t j = 0; j < s; j++)
         if (adjacent(&o->g, piv, S[j])) child[cs++] = S[j];
     o->P[p] = piv;
+    o->work_child += (uint64_t)((s + 63) / 64); /* the pivot child */
     rec(o, child, cs, h, p + 1, depth + 1);
 
     /* hold children: the non-neighbours v_1, v_2, ... of piv in S (piv itself
@@ -313,6 +319,7 @@ static void rec(orc_t *o, const int32_t *S, int32_t s, int32_t h, int32_t p, int
             child[cs++] = x;
         }
         o->H[h] = v;
+        o->work_child += (uint64_t)((s + 63) / 64); /* a hold child */
         rec(o, child, cs, h + 1, p, depth + 1);
         last = prio_of(o, v);
         first = 0;
@@ -334,9 +341,12 @@ static void rec(orc_t *o, const int32_t *S, int32_t s, int32_t h, int32_t p, int
  * ec      : NULL or [m][ehi-elo+1][2] per-edge counts, edge id = rank of (u,v),
  *           u<v, in lexicographic order; eovf[K].
  * hist    : NULL or [hd][hd] leaf histogram by (h, p).
- * stats   : [9] nodes, leaves, alpha, omega, max depth, sum |S|*ceil(|S|/64),
+ * stats   : [12] nodes, leaves, alpha, omega, max depth, sum |S|*ceil(|S|/64),
  *           sub-rounds of the peel (0 if key_in given), kcap needed,
- *           leaves outside the histogram.
+ *           leaves outside the histogram, then the work counters of the
+ *           roofline model: sum over internal nodes of (children made) *
+ *           ceil(|S|/64) (one word operation per child and word of S),
+ *           sum over leaves of h + p, sum over leaves of C(h + p, 2).
  * Returns 0, -7 if kcap is too small (stats[7] says what is needed), -3 on
  * allocation failure.
  */
@@ -449,6 +459,9 @@ int32_t orc_count(int32_t n, const int32_t *rp, const int32_t *col,
         stats[6] = (uint64_t)subrounds;
         stats[7] = (uint64_t)o.need_kcap;
         stats[8] = o.hist_out;
+        stats[9] = o.work_child;
+        stats[10] = o.leaf_hp;
+        stats[11] = o.leaf_pairs;
     }
     free(o.binom); free(o.bbad); free(o.arena); free(o.H); free(o.P);
     free(o.eoff); free(o.efirst); free(key_own);

@@ -139,7 +139,7 @@ def count(g, key=None, prio=None, roots=None, kmax: int = 0, vertex=None, edge=N
         ec = np.zeros((g.m, ehi - elo + 1, 2), dtype=np.uint64)
         eovf = np.zeros(ehi - elo + 1, dtype=np.uint8)
     hist = np.zeros((hist_dim, hist_dim), dtype=np.uint64) if hist_dim else None
-    stats = np.zeros(9, dtype=np.uint64)
+    stats = np.zeros(12, dtype=np.uint64)
     rc = lib.orc_count(g.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(key, C.c_int32),
                        _p(prio_a, C.c_int32), _p(roots_a, C.c_int32),
                        0 if roots_a is None else int(roots_a.shape[0]), int(kmax),
@@ -150,7 +150,7 @@ def count(g, key=None, prio=None, roots=None, kmax: int = 0, vertex=None, edge=N
     if rc != 0:
         raise RuntimeError(f"oracle failed with status {rc}")
     names = ["nodes", "leaves", "alpha", "omega", "max_depth", "work_sw", "subrounds",
-             "need_kcap", "hist_out"]
+             "need_kcap", "hist_out", "work_child", "leaf_hp", "leaf_pairs"]
     st = {k: int(v) for k, v in zip(names, stats)}
     if key is not None and subrounds:
         st["subrounds"] = subrounds

@@ -195,7 +195,6 @@ def test_local_sum_identities(seed):
     a, b = g.edges()
     assert all(E[e][2] == len(adj[a[e]] & adj[b[e]]) for e in range(g.m))
     assert r.glob[3] == brute.triangles_by_matrix(g)
-    # sum over leaves of 2^p = number of non-empty cliques
     assert r.glob[1] == g.n and r.glob[2] == g.m
 
 
@@ -416,3 +415,101 @@ def test_frequency_closed_forms():
     g = gg.disjoint_union(gg.disjoint_union(gg.complete(5), gg.complete(7)), gg.empty(3))
     r = O.count(g, vertex=(3, 3))
     assert O.frequency(r.vertex[:, 0]) == [(0, 3), (6, 5), (15, 7)]
+
+
+# ------------------------------------------- work counters (roofline model)
+# The counters feed the roofline figures: pivot work sum |S| * ceil(|S|/64),
+# child work sum (children) * ceil(|S|/64), and the leaves' sums of h + p and
+# C(h + p, 2).  They are pinned on trees whose shape is known in closed form.
+
+def _words(d):
+    return (d + 63) // 64
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 30, 64, 65, 66, 100, 130])
+def test_work_counters_complete_graph(n):
+    # every root child N+(v) of K_n is a clique, walked as one pivot chain:
+    # the root of out-degree s has nodes of sizes s, s-1, ..., 0, so n - d
+    # chains pass through a node of size d; each internal node has exactly
+    # one child (every other member is a neighbour of the pivot), and the
+    # leaves are (h, p) = (1, s) for s = 0..n-1
+    r = O.count(gg.complete(n))
+    st = r.stats
+    assert st["nodes"] == n * (n + 1) // 2
+    assert st["work_sw"] == sum((n - d) * d * _words(d) for d in range(n))
+    if n <= 65:  # no set wider than 64 vertices: sum over d of (n - d) d
+        assert st["work_sw"] == comb(n + 1, 3)
+    else:  # the ceil(|S|/64) factor counts: sets of 65.. vertices take two words
+        assert st["work_sw"] > comb(n + 1, 3)
+    assert st["work_child"] == sum((n - d) * _words(d) for d in range(1, n))
+    assert st["leaves"] == n
+    assert st["leaf_hp"] == n * (n + 1) // 2
+    assert st["leaf_pairs"] == comb(n + 1, 3)
+
+
+@pytest.mark.parametrize("maker", [lambda: gg.complete_multipartite([70, 70]),
+                                   lambda: gg.complete_multipartite([3, 130]),
+                                   lambda: gg.cycle(9), lambda: gg.path(7), lambda: gg.star(12)])
+def test_work_counters_triangle_free(maker):
+    # orientation by vertex id (all keys equal): N+(v) = larger neighbours.
+    # Without triangles every N+(v) is independent: the root node of size d
+    # has the pivot child and d - 1 hold children, all of them leaves
+    # (h, p) = (1, 1) or (2, 0); a vertex with d = 0 is a leaf (1, 0).
+    g = maker()
+    key = np.zeros(g.n, dtype=np.int32)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    od = np.bincount(src[g.col > src], minlength=g.n).astype(np.int64)
+    w = (od + 63) // 64
+    sinks = int((od == 0).sum())
+    r = O.count(g, key=key)
+    st = r.stats
+    assert st["nodes"] == g.n + g.m
+    assert st["leaves"] == g.m + sinks
+    assert st["work_sw"] == int((od * w).sum())
+    assert st["work_child"] == int((od * w).sum())
+    assert st["leaf_hp"] == 2 * g.m + sinks
+    assert st["leaf_pairs"] == g.m
+    if od.max() > 64:
+        assert st["work_sw"] > g.m  # the ceil(|S|/64) factor is counted
+
+
+# ------------------------- the leaves represent every clique exactly once
+# Thm. scr: a leaf with h hold and p pivot vertices stands for the 2^p
+# cliques H + Q, Q a subset of P, and every non-empty clique is one of them.
+# So sum over leaves of 2^p is the number of non-empty cliques, and summing
+# the clique sizes h + |Q| gives sum over leaves of h 2^p + p 2^(p-1).
+
+def _leaf_sums(g):
+    hd = (int(O.out_degrees(g, O.peel(g).sub).max()) if g.n else 0) + 2
+    r = O.count(g, hist_dim=hd)
+    assert r.stats["hist_out"] == 0
+    L = r.hist
+    cliques = sizes = 0
+    for h, p in zip(*np.nonzero(L)):
+        c, h, p = int(L[h, p]), int(h), int(p)
+        cliques += c * 2 ** p
+        sizes += c * (h * 2 ** p + (p * 2 ** (p - 1) if p else 0))
+    return cliques, sizes
+
+
+@pytest.mark.parametrize("n,p,seed", [(9, 0.5, 1), (12, 0.85, 2), (14, 0.5, 3), (13, 0.2, 4)])
+def test_leaf_sum_of_2_to_p_brute_force(n, p, seed):
+    g = gg.gnp(n, p, seed)
+    C, _, _ = brute.brute_counts(g)
+    cliques, sizes = _leaf_sums(g)
+    assert cliques == sum(C[k] for k in range(1, len(C)))
+    assert sizes == sum(k * C[k] for k in range(1, len(C)))
+
+
+@pytest.mark.parametrize("parts", [[1] * 40, [2, 3, 5], [1] * 20 + [4, 4], [3] * 9])
+def test_leaf_sum_of_2_to_p_closed_form(parts):
+    # complete multipartite: a clique takes at most one vertex per part, so
+    # there are prod(a + 1) - 1 non-empty cliques; K_40 is the all-ones case
+    g = gg.complete_multipartite(parts)
+    prod = 1
+    for a in parts:
+        prod *= a + 1
+    cliques, sizes = _leaf_sums(g)
+    assert cliques == prod - 1
+    # total size: each part contributes a vertex to a clique in a * prod / (a + 1) of them
+    assert sizes == sum(a * prod // (a + 1) for a in parts)
