@@ -74,7 +74,7 @@ __device__ __forceinline__ unsigned ld_u(const unsigned *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier for a co-resident (cooperative) launch.  Every block
+// Grid barrier for a launch whose blocks are all resident at once.  Every block
 // publishes the number of barriers it has passed on its own 128-byte line
 // (a release store; `epoch` is that number, kept by the caller), and one
 // wave of each block polls all the lines until every block has reached the
@@ -1131,10 +1131,16 @@ hipError_t pv_launch_peel(const DevInfo &dev, const PeelArgs &pa, hipStream_t s)
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     const int blocks =
         (pa.n <= PV_SOLO_MAX) ? 1 : std::max(1, std::min(dev.num_cu / 4, PV_PEEL_MAX_BLOCKS));
-    PeelArgs a = pa;
-    void *args[] = {(void *)&a};
-    return hipLaunchCooperativeKernel((const void *)peel_kernel, dim3(blocks), dim3(PV_PEEL_THREADS),
-                                      args, 0, s);
+    // An ordinary launch, not the cooperative API: the grid (at most a
+    // quarter of the CUs, one block per CU as the occupancy query above
+    // allows) is resident at once on the device, and the grid barrier's
+    // wait is bounded, so a block that is not scheduled turns into an error
+    // flag, not a hang.  Cooperative dispatches left the process to crash in
+    // its exit handlers under the profiler, and an ordinary launch can also
+    // be recorded into a HIP graph.
+    if (blocks > per_cu * dev.num_cu) return hipErrorInvalidConfiguration;
+    peel_kernel<<<blocks, PV_PEEL_THREADS, 0, s>>>(pa);
+    return hipGetLastError();
 }
 
 hipError_t pv_launch_excl_scan(int n, const int *in, int *tmp, int *out, hipStream_t s) {
