@@ -26,12 +26,16 @@ Other workloads are selected with --workload:
          batching against the same loop taking one request per pass;
          latency from the scheduled arrival to the result in host memory.
 
-The roofline object describes the dominant kernel (the compact-item
-specialisation of the SCT level kernel): integer ALU work, its launches
-timed with HIP events on the library's stream, and its HBM traffic from
-counter runs while the kernel sources are unchanged.  The cpu_baseline
-object times the CPU oracle (single thread) on a stratified sample of root
-subproblems and scales each stratum by its exact SCT node count.
+The roofline object describes the dominant kernel, the SCT level kernel
+(every unit kind): its algorithmic VALU, LDS and HBM work per launch (the
+model is stated with the constants below), each against MI355X's published
+or derived peak and against the rates pv_measure_peaks measures on this
+device, over its launches' summed durations (HIP events on each launch's
+stream), and its HBM traffic from counter runs while the kernel sources are
+unchanged.  The cpu_baseline
+object times the CPU oracle in the paper's parallel form (independent root
+subproblems over worker processes on the host's cores) on a systematic
+sample of every 16th root by out-degree rank, scaled by 16.
 """
 import argparse
 import json
@@ -45,11 +49,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "graph edges/sec and SCT leaves/sec for all-k counts; p50/p99 request latency"
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = one 32-bit integer
-# operation per lane per clock on the vector ALUs
+# MI355X published/derived peaks: HBM3E 8 TB/s; 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz = one 32-bit integer operation per lane per clock on the vector
+# ALUs; LDS 128 bytes per clock per CU
+HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+LDS_PEAK_GBS = 256 * 128 * 2.4e9 / 1e9
 K_LO, K_HI = 3, 10
-# HBM traffic of the dominant kernel from two rocprofv3 counter runs
+# The level kernel's algorithmic work per unit (the roofline model):
+#   VALU lane operations: 4 per 64-bit AND + popcount pair of the pivot
+#   search (two ANDs, two bit counts), 2 per word of a child's vertex set
+#   (one 64-bit AND), 2 per per-vertex addition of Alg. 2 (a 64-bit add),
+#   of which there are K per leaf vertex: sum over leaves of (h + p) * K;
+#   LDS bytes: a child's set word is written to the on-chip stack and read
+#   back (16); the per-vertex sums stay in registers and a leaf's binomial
+#   rows come through the scalar cache, so the additions add no LDS bytes;
+#   HBM bytes: the compulsory ones, every root's gather of N+(v) and its
+#   members' N+(u) (4 per id, 8 per row-pointer pair) and the per-vertex
+#   table written once (16 per u128 count).
+VALU_PER_PAIR, VALU_PER_CHILD_WORD, VALU_PER_ADD = 4, 2, 2
+LDS_PER_CHILD_WORD = 16
+# HBM traffic of the level kernel from two rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter reads for a
 # plain copy of known size; valid only for the kernel sources it was taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sct_level_kernel_chunglu1M_vertex3-10.json")
@@ -66,17 +86,80 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """Bytes per launch of `kernel` from the committed counter summary, or
-    None when it is missing or was taken on other kernel sources."""
+def measured_traffic():
+    """HBM bytes per step of the level kernel (all its launches) from the
+    committed counter summary, or None when it is missing or was taken on
+    other kernel sources."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != kernel_source_hash() or t.get("kernel") != kernel:
+    if t.get("source_sha256") != kernel_source_hash():
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t.get("hbm_bytes_per_step")
+
+
+def compulsory_hbm_bytes(g, key, K):
+    """The level kernel's compulsory HBM bytes for one step: the gathers of
+    every root (N+(v), then N+(u) of each member u) and the per-vertex
+    table written once.  Edge a->b iff (key[a], a) < (key[b], b)."""
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    cols = g.col.astype(np.int64)
+    fwd = (key[rows] < key[cols]) | ((key[rows] == key[cols]) & (rows < cols))
+    od = np.bincount(rows[fwd], minlength=g.n).astype(np.int64)
+    ind = deg - od
+    gathers = 8 * g.n + 4 * int(od.sum()) + int((ind * (8 + 4 * od)).sum())
+    return gathers + 16 * g.n * K
+
+
+def roofline(stats, peaks, hbm_bytes, traffic):
+    """Roofline of the SCT level kernel (every unit kind) over the timed
+    steps: each term's algorithmic units over its peak, against the summed
+    launch durations (HIP events on each launch's stream)."""
+    K = K_HI - K_LO + 1
+    work = sum(s["work"] for s in stats)
+    child = sum(s["child_work"] for s in stats)
+    adds = K * sum(s["leaf_hp"] for s in stats)
+    ms = sum(sum(s["ms_kind"]) for s in stats)
+    ms_wall = sum(s["ms_levels"] for s in stats)
+    launches = sum(sum(s["launches_kind"]) for s in stats)
+    steps = len(stats)
+    units = {
+        "valu": VALU_PER_PAIR * work + VALU_PER_CHILD_WORD * child + VALU_PER_ADD * adds,
+        "lds": LDS_PER_CHILD_WORD * child,
+        "hbm": hbm_bytes * steps,
+    }
+    peak = {"valu": ALU_PEAK_TOPS * 1e12, "lds": LDS_PEAK_GBS * 1e9, "hbm": HBM_PEAK_GBS * 1e9}
+    meas = {"valu": peaks["valu_gops"] * 1e9, "lds": peaks["lds_read_gbs"] * 1e9,
+            "hbm": peaks["hbm_copy_gbs"] * 1e9}
+    terms = {}
+    for t in ("valu", "lds", "hbm"):
+        terms[t] = {"units_per_launch": units[t] / max(launches, 1),
+                    "t_ms_at_peak": units[t] / peak[t] * 1e3 / max(launches, 1),
+                    "frac": units[t] / peak[t] * 1e3 / ms if ms > 0 else 0.0,
+                    "peak_measured": meas[t] / (1e12 if t == "valu" else 1e9),
+                    "frac_measured": units[t] / meas[t] * 1e3 / ms if ms > 0 and meas[t] > 0 else 0.0}
+    bound = max(terms, key=lambda t: units[t] / peak[t])
+    scale, unit = {"valu": (1e12, "TOP/s"), "lds": (1e9, "GB/s"), "hbm": (1e9, "GB/s")}[bound]
+    achieved = units[bound] / (ms * 1e-3) / scale if ms > 0 else 0.0
+    return {
+        "bound": {"valu": "alu", "lds": "lds", "hbm": "hbm"}[bound],
+        "kernel": "sct_level_kernel (every unit kind)",
+        "achieved": achieved,
+        "peak": peak[bound] / scale,
+        "unit": unit,
+        "frac": achieved * scale / peak[bound],
+        "traffic": (traffic / max(launches / steps, 1)) if traffic is not None else None,
+        "avg_launch_ms": ms / max(launches, 1),
+        "launches": launches,
+        "terms": terms,
+        "frac_wall": units[bound] / peak[bound] * 1e3 / ms_wall if ms_wall > 0 else 0.0,
+        "work_per_step": {"pivot_pairs": work / steps, "child_words": child / steps,
+                          "vertex_additions": adds / steps, "compulsory_hbm_bytes": hbm_bytes},
+        "peaks_measured": peaks,
+    }
 
 
 def make_graph():
@@ -84,56 +167,57 @@ def make_graph():
     return gg.chung_lu_social(n=1_000_000, avg_deg=20.0, gamma=2.3, max_deg=20_000.0, seed=1)
 
 
-def cpu_baseline(g, h, total_nodes: int, seed: int, heavy_sample: int = 16,
-                 light_fraction: float = 0.02):
-    """The oracle as it stands, single-threaded: its own peel over the whole
-    graph plus the SCT and Alg. 2 updates (global all k, per-vertex
-    k=3..10) for a sample of roots, scaled to the whole graph.
+def _cpu_info():
+    """(nproc, CPU model name) of this host, as lscpu reports them."""
+    import subprocess
+    nproc = os.cpu_count()
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return nproc, model
 
-    Root subproblems are independent (Sec. 5) but their costs are extremely
-    skewed, so the scaling is a ratio estimate per stratum: the oracle's
-    time per SCT node on sampled roots times the stratum's exact node count.
-    Strata: roots with |N+(v)| > 62 and the others; their node counts come
-    from the GPU (the same tree: node counts are parity-tested), the heavy
-    stratum from one pv_count_roots call, the rest as the remainder of the
-    timed run's total."""
+
+def cpu_baseline(g, stride: int = 16, max_workers: int = 16):
+    """The oracle as it stands, in the paper's parallel form (Sec. 5: the
+    root subproblems are independent; workers count them with private
+    counters and the counts are summed), on the host cores this process
+    may use (at most max_workers): its own peel over the whole graph, then
+    the SCT and Alg. 2 updates (global all k, per-vertex k=3..10) for a
+    systematic sample of the roots -- every `stride`-th root in order of
+    out-degree, so the sample holds the same share of every degree rank --
+    whose wall time times `stride` stands for the whole graph.  Nothing in
+    it comes from the GPU."""
     from oracle import oracle as O
-    from paper_2001_06784_amd import pivoter as P
+    from oracle import parallel as OP
+    workers = max(1, min(max_workers, len(os.sched_getaffinity(0))))
     t0 = time.perf_counter()
     pe = O.peel(g)
     t_peel = time.perf_counter() - t0
     od = O.out_degrees(g, pe.sub)
-    rng = np.random.default_rng(seed)
-    heavy = np.nonzero(od > 62)[0].astype(np.int32)
-    light = np.nonzero((od > 0) & (od <= 62))[0].astype(np.int32)
-    sinks = int(np.sum(od == 0))
-    nh = min(heavy_sample, len(heavy))
-    nl = max(1, int(round(light_fraction * len(light))))
-    hs = np.sort(rng.choice(heavy, nh, replace=False)).astype(np.int32) if nh else heavy[:0]
-    ls = np.sort(rng.choice(light, nl, replace=False)).astype(np.int32)
-    N_h = P.pv_count_roots(h, heavy).stats["nodes"] if len(heavy) else 0
-    N_l = total_nodes - N_h - sinks
-    t_h = n_h = 0
-    if nh:
-        t0 = time.perf_counter()
-        rh = O.count(g, key=pe.sub, roots=hs, vertex=(K_LO, K_HI))
-        t_h = time.perf_counter() - t0
-        n_h = rh.stats["nodes"]
+    order = np.argsort(-od, kind="stable").astype(np.int32)
+    sample = np.sort(order[::stride])
     t0 = time.perf_counter()
-    rl = O.count(g, key=pe.sub, roots=ls, vertex=(K_LO, K_HI))
-    t_l = time.perf_counter() - t0
-    n_l = rl.stats["nodes"]
-    t_full = t_peel + (t_h * N_h / n_h if n_h else 0.0) + (t_l * N_l / n_l if n_l else 0.0)
+    r = OP.count_parallel(g, pe.sub, roots=sample, workers=workers, vertex=(K_LO, K_HI))
+    t_sample = time.perf_counter() - t0
+    t_full = t_peel + stride * t_sample
+    nproc, model = _cpu_info()
     return {
         "value": g.m / t_full,
         "unit": "edges/s",
-        "cores": 1,
+        "cores": r["workers"],
         "kind": "oracle",
-        "sample": (f"{nh} of {len(heavy)} roots with |N+(v)| > 62 ({t_h:.1f} s, {n_h} SCT nodes) "
-                   f"and {nl} of {len(light)} others ({t_l:.1f} s, {n_l} nodes), seed {seed}; "
-                   f"global all-k + per-vertex k={K_LO}..{K_HI}; each stratum's seconds per node "
-                   f"times its exact node count ({N_h} and {N_l}), plus the full peel "
-                   f"{t_peel:.2f} s; estimated full run {t_full:.0f} s"),
+        "sample": (f"every {stride}th root by out-degree rank ({len(sample)} of {g.n} roots, "
+                   f"{r['stats']['nodes']} SCT nodes), global all-k + per-vertex k={K_LO}..{K_HI}, "
+                   f"oracle in the paper's parallel form on {r['workers']} processes: {t_sample:.1f} s wall "
+                   f"({r['busy_s']:.1f} s busy summed); the full peel {t_peel:.2f} s; estimated whole graph "
+                   f"{t_full:.0f} s = peel + {stride} x sample; host nproc {nproc}, {model}"),
+        "nproc": nproc,
+        "cpu": model,
     }
 
 
@@ -176,6 +260,8 @@ def main():
     K = K_HI - K_LO + 1
     local = torch.zeros((g.n, K, 2), dtype=torch.int64, device="cuda:0")
     torch.cuda.synchronize()
+    peaks = P.pv_measure_peaks(ctx)
+    print(f"[bench] measured peaks: {peaks}", file=sys.stderr, flush=True)
 
     def step():
         res, lovf = P.pv_count(h, reorient=True, local_kind=P.PV_VERTEX, k_lo=K_LO, k_hi=K_HI,
@@ -199,19 +285,9 @@ def main():
     print(f"[bench] {args.steps} steps, {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
     st = stats[-1]
-    levels = sum(s["levels"] for s in stats)
-    ms_levels = sum(s["ms_levels"] for s in stats)
-    # the level kernel is specialised per unit kind; the dominant kernel is
-    # the specialisation with the largest summed device time
     kinds = ("multi-word", "compact-items", "light-roots")
-    ms_kind = [sum(s["ms_kind"][i] for s in stats) for i in range(3)]
-    launches = [sum(s["launches_kind"][i] for s in stats) for i in range(3)]
-    work = [sum(s["work_kind"][i] for s in stats) for i in range(3)]
-    dom = max(range(3), key=lambda i: ms_kind[i])
-    # algorithmic ALU work: each 64-bit AND + popcount of the pivot search is
-    # 4 lane operations (two 32-bit ANDs, two 32-bit bit counts)
-    achieved_tops = 4.0 * work[dom] / (ms_kind[dom] * 1e-3) / 1e12 if ms_kind[dom] > 0 else 0.0
-    kname = f"sct_level_kernel<{st['kernel_kl']}, {dom}, {st['kernel_lk']}>"
+    key = P.pv_graph_export_order(h)
+    roof = roofline(stats, peaks, compulsory_hbm_bytes(g, key, K), measured_traffic())
     line = {
         "metric": METRIC,
         "value": g.m / dt,
@@ -236,21 +312,11 @@ def main():
                       "levels": st["ms_levels"], "finalize": st["ms_finalize"],
                       "level_launches": st["levels"],
                       "levels_by_kind": {kinds[i]: st["ms_kind"][i] for i in range(3)}},
-        "roofline": {
-            "bound": "alu",
-            "kernel": f"{kname} ({kinds[dom]})",
-            "achieved": achieved_tops,
-            "peak": ALU_PEAK_TOPS,
-            "unit": "TOP/s",
-            "frac": achieved_tops / ALU_PEAK_TOPS,
-            "traffic": measured_traffic(kname),
-            "avg_launch_ms": ms_kind[dom] / max(launches[dom], 1),
-            "launches": launches[dom],
-        },
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(g, h, st["nodes"], seed=7)
+        line["cpu_baseline"] = cpu_baseline(g)
     P.pv_graph_free(h)
     P.pv_fini(ctx)
     print(json.dumps(line), flush=True)

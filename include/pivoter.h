@@ -64,8 +64,12 @@ typedef int32_t pv_status;
 #define PV_VERTEX 1
 #define PV_EDGE 2
 
-/* flags of pv_graph_load_csr* */
+/* flags of pv_graph_load_csr* (the paper counts cliques of a simple
+   undirected graph and drops edge directions and repeats, Sec. 6's input
+   preparation; the repair flags do that here) */
 #define PV_TRUST_INPUT 1u  /* skip the simple/symmetric/sorted validation */
+#define PV_DEDUP 2u        /* repair: sort every row, drop repeated entries and self loops */
+#define PV_SYMMETRIZE 4u   /* repair: add the reverse of every entry (then as PV_DEDUP) */
 
 /* largest supported degeneracy (out-degree bound of the orientation) */
 #define PV_MAX_ALPHA 4096
@@ -100,18 +104,73 @@ typedef struct {
     int32_t kernel_lk;          /* its local-count kind: 0 per vertex (u128 visit sums),
                                    1 per edge, 2 per vertex (u64 visit sums) */
     int32_t attempts;           /* walks of the tree: 1, plus one rerun per work-buffer overflow */
+    /* algorithmic work of the walk (the terms of its roofline model) */
+    uint64_t child_work;        /* sum over internal nodes of children * ceil(|S|/64): the word
+                                   operations that form the children's vertex sets */
+    uint64_t leaf_hp;           /* sum over leaves of h + p: per-vertex additions per value of k */
+    uint64_t leaf_pp;           /* sum over leaves of p + 1: global additions (one per k <= p + h) */
 } pv_stats;
 
 /* Human-readable name of a status code (static string). */
 const char *pv_strerror(pv_status s);
 
 /*
- * Create a context on HIP device `device`.  `stream` is a hipStream_t to
- * issue work on (NULL: the legacy default stream).  The context owns the
- * binomial table and per-device workspaces; it is released by pv_fini.
+ * Configuration of a context (pv_init).  Zero fields take the defaults.
+ *   stream      hipStream_t to issue work on (NULL: the legacy default stream).
+ *   hbm_budget  bytes of device memory the context may hold at once: its
+ *               workspaces and the graphs loaded through it.  An allocation
+ *               that would pass it fails with PV_ENOMEM, as if the device
+ *               were that small (0: no limit besides the device).
+ *   tune_cache  path of the tuning cache, a JSON file written by pv_autotune
+ *               and read by pv_init (NULL: none).  A graph whose key (device
+ *               name and out-degree histogram, see pv_autotune) is in the
+ *               cache is walked with the cached settings.
+ *   dfs_max, dfs_budget, lane_max: the tuning settings below (0: default;
+ *               lane_max -1 turns the lane tier off).
  */
-pv_status pv_init(int32_t device, void *stream, pv_ctx **out);
+typedef struct {
+    void *stream;
+    int64_t hbm_budget;
+    const char *tune_cache;
+    int32_t dfs_max;
+    int32_t dfs_budget;
+    int32_t lane_max;
+} pv_config;
+
+/*
+ * Create a context on HIP device `device` with configuration `cfg` (NULL:
+ * all defaults).  The context owns the binomial table and per-device
+ * workspaces; it is released by pv_fini.
+ */
+pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out);
 void pv_fini(pv_ctx *ctx);
+
+/* Device bytes the context holds now (workspaces and its graphs). */
+pv_status pv_memory(const pv_ctx *ctx, int64_t *held_bytes);
+
+/*
+ * Measured peaks of the context's device, the denominators of the walk's
+ * roofline model (no passage of the method defines them: they are the
+ * device's own rates).  Each figure is the best of five timed runs on the
+ * context's stream after one untimed run:
+ *   hbm_copy_gbs  stream copy of copy_bytes (0: 1 GiB) between two device
+ *                 buffers, counting the bytes read plus the bytes written;
+ *   hbm_read_gbs  stream read of copy_bytes;
+ *   lds_read_gbs  64-bit LDS reads, conflict free, summed over all CUs;
+ *   valu_gops     32-bit VALU lane operations per second (XOR then
+ *                 popcount-accumulate, the pivot search's instructions).
+ * ms_* are the best kernel times.  Allocates 2 * copy_bytes of device
+ * memory (charged to the context's budget: PV_ENOMEM past it) and frees it
+ * before returning; synchronises the stream.
+ */
+typedef struct {
+    double hbm_copy_gbs;
+    double hbm_read_gbs;
+    double lds_read_gbs;
+    double valu_gops;
+    float ms_copy, ms_read, ms_lds, ms_valu;
+} pv_peaks;
+pv_status pv_measure_peaks(pv_ctx *ctx, int64_t copy_bytes, pv_peaks *out);
 
 /*
  * Environment variables read by pv_init besides the tuning defaults below;
@@ -119,7 +178,7 @@ void pv_fini(pv_ctx *ctx);
  *   PV_HU_BUDGET    bytes of device memory for the gathered neighbourhoods
  *                   of heavy roots (|N+(v)| > 64) per pass over them; the
  *                   roots are taken in as many chunks as that needs
- *                   (default 2^30).
+ *                   (default 2^30, at most a quarter of hbm_budget).
  *   PV_PREFIX_ROWS  per-vertex counts: rows of N+(root) summed per on-chip
  *                   pass when what the universes owe the vertices above them
  *                   is added up per heavy root (default: as many as fit).
@@ -165,6 +224,42 @@ pv_status pv_set_dfs_budget(pv_ctx *ctx, int32_t nodes);
  */
 pv_status pv_set_lane_max(pv_ctx *ctx, int32_t lane_max);
 
+/*
+ * Autotuning of how the walk is split (the tile widths of the batched
+ * persistent walk: which subtrees go one per lane, which one per
+ * wavefront, and how many nodes a wavefront walks before it hands work
+ * back to the queue).  No setting changes a count, a tree or a statistic
+ * other than timings (Thm. scr: the tree depends only on the pivot and
+ * order rules, which stay fixed).
+ *
+ * pv_autotune times pv_count on g (global counts for all k, plus the given
+ * local counts, local_out being a DEVICE buffer as pv_count's) under
+ * candidate settings, one setting at a time from the current best
+ * (lane_max in {0,4,6,8}; dfs_budget in {auto,1024,...,16384}; dfs_max in
+ * {32,48,64}), each the best of `reps` runs (>= 1).  The winner is kept
+ * for the graph's key, which is the device (architecture and CU count),
+ * the kind of count, and the out-degree histogram in powers of two with
+ * each count rounded to its power of two; later pv_count / pv_count_batch
+ * calls on this context use it for graphs with the same key, and with a
+ * tune_cache path (pv_config) it is also written to that JSON file, which
+ * later contexts read.
+ */
+typedef struct {
+    int32_t dfs_max;      /* chosen settings */
+    int32_t dfs_budget;   /* 0: chosen per tree level */
+    int32_t lane_max;     /* 0: lane tier off */
+    float ms_best;        /* best time of one pv_count with them */
+    float ms_default;     /* best time with the context's settings before tuning */
+    int32_t trials;       /* settings timed */
+} pv_tune;
+
+pv_status pv_autotune(pv_graph *g, int32_t local_kind, int32_t k_lo, int32_t k_hi, pv_u128 *local_out,
+                      int32_t reps, pv_tune *out);
+
+/* The key under which g's tuned settings are kept (static storage of this
+   host thread, valid until the next call on it). */
+const char *pv_tune_key(pv_graph *g, int32_t local_kind, int32_t k_lo, int32_t k_hi);
+
 /* Text of the last HIP error seen by this host thread (static storage). */
 const char *pv_last_error(void);
 
@@ -174,18 +269,23 @@ const char *pv_last_error(void);
  * duplicates (problem statement, Sec. 1.1: a simple undirected graph).
  * The inputs are copied; the caller keeps ownership.  Unless
  * PV_TRUST_INPUT is set the CSR is validated (PV_ENOTSIMPLE otherwise).
- * Isolated vertices are allowed.  The graph handle owns its device memory.
+ * PV_DEDUP and PV_SYMMETRIZE repair the copy first (on the host); a column
+ * id outside [0, n) cannot be repaired and gives PV_ENOTSIMPLE.  Isolated
+ * vertices are allowed.  The graph handle owns its device memory.
  */
 pv_status pv_graph_load_csr(pv_ctx *ctx, int32_t n, const int32_t *row_ptr,
                             const int32_t *col, uint32_t flags, pv_graph **out);
 
-/* Same, from a CSR already in device memory (device pointers, copied). */
+/* Same, from a CSR already in device memory (device pointers of the
+   context's device, copied; problem statement, Sec. 1.1).  nnz = row_ptr[n].
+   With a repair flag the CSR takes a round trip through host memory. */
 pv_status pv_graph_load_csr_device(pv_ctx *ctx, int32_t n, int64_t nnz,
                                    const int32_t *d_row_ptr, const int32_t *d_col,
                                    uint32_t flags, pv_graph **out);
 
-/* Release a graph and its device memory. */
-void pv_graph_free(pv_graph *g);
+/* Release a graph and its device memory.  PV_EAGAIN (nothing released) while
+   a count on another host thread uses it. */
+pv_status pv_graph_free(pv_graph *g);
 
 /* n and m (undirected edges) of a loaded graph. */
 pv_status pv_graph_size(const pv_graph *g, int32_t *n, int64_t *m);
@@ -200,7 +300,8 @@ pv_status pv_graph_size(const pv_graph *g, int32_t *n, int64_t *m);
  */
 pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out);
 
-/* Copy the peel sub-round of every vertex (int32[n], host). */
+/* Copy the peel sub-round of every vertex (int32[n], host): the key of the
+   degeneracy order of Sec. 3, Lemma lem:degen (ties by vertex id). */
 pv_status pv_graph_export_order(pv_graph *g, int32_t *sub_host);
 
 /*
@@ -267,7 +368,9 @@ pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int32_t k_hi,
                          pv_u128 *out, int64_t out_len, uint64_t *overflow_bits,
                          pv_stats *stats);
 
-/* The edges (u<v) in edge-id order: u[m], v[m] host arrays. */
+/* The edges (u<v) in edge-id order: u[m], v[m] host arrays.  Edge e's
+   per-edge counts c_k(e) (Sec. 1.1; Alg. 2 pair steps) are row e of
+   pv_count_local's and pv_count's per-edge output. */
 pv_status pv_graph_edge_list(pv_graph *g, int32_t *u, int32_t *v);
 
 /*
@@ -287,14 +390,23 @@ pv_status pv_count(pv_graph *g, int32_t reorient, int32_t k_max,
                    pv_u128 *local_out, uint64_t *local_ovf, pv_stats *stats);
 
 /*
- * Counts restricted to some root children of the SCT: only the subtrees of
- * the given roots (host int32 ids) are built, so counts[k] is the number of
- * k-cliques whose smallest-key vertex is one of the roots (counts[0] = 0).
- * Used for sampled checks on graphs whose full count is too large.
+ * Counts restricted to some root children of the SCT.  The root's children
+ * N+(v) are independent subproblems (Sec. 5, parallel version: each one is
+ * counted with its own counters and the results are summed), and the subtree
+ * of N+(v) holds exactly the cliques whose smallest-key vertex is v (Sec. 4,
+ * Thm. scr).  Only the subtrees of the given roots (host int32 ids, distinct)
+ * are built, so counts[k] is the number of k-cliques whose smallest-key
+ * vertex is one of the roots (counts[0] = 0).  Used for sampled checks on
+ * graphs whose full count is too large, and to split a count over calls.
+ *   local_kind PV_NONE, PV_VERTEX or PV_EDGE: local counts of those cliques
+ *   only, for k_lo <= k <= k_hi, into the DEVICE buffer local_out of
+ *   (n or m) * (k_hi-k_lo+1) pv_u128 (zero-filled by this call; layout and
+ *   limits as pv_count).  local_ovf (host, may be NULL) as pv_count.
  */
 pv_status pv_count_roots(pv_graph *g, const int32_t *roots, int32_t nroots, int32_t k_max,
                          pv_u128 *counts, int32_t cap, int32_t *omega_out,
-                         uint64_t *overflow_bits, pv_stats *stats);
+                         uint64_t *overflow_bits, int32_t local_kind, int32_t k_lo, int32_t k_hi,
+                         pv_u128 *local_out, uint64_t *local_ovf, pv_stats *stats);
 
 /*
  * Batched counts: G graphs (loaded on this context's device) counted in one
@@ -314,12 +426,15 @@ pv_status pv_count_roots(pv_graph *g, const int32_t *roots, int32_t nroots, int3
 pv_status pv_count_batch(pv_ctx *ctx, int32_t G, pv_graph *const *gs, int32_t k_max,
                          pv_u128 *counts, int32_t cap, int32_t *omega, uint64_t *overflow_bits,
                          int32_t local_kind, int32_t k_lo, int32_t k_hi, pv_u128 *local_out,
-                         uint64_t *local_ovf, pv_stats *stats);
+                         uint64_t *local_ovf, pv_status *status, pv_stats *stats);
 
-/* pv_count_batch with global counts only. */
+/* pv_count_batch with global counts only.  status [G] (host, may be NULL):
+ * each graph's own status (PV_OK, PV_EBUFSIZE if cap <= its omega,
+ * PV_EOVERFLOW if one of its counts reached 2^128); the return value is
+ * PV_EBUFSIZE if any graph's is, else PV_EOVERFLOW if any graph's is. */
 pv_status pv_count_global_batch(pv_ctx *ctx, int32_t G, pv_graph *const *gs, int32_t k_max,
                                 pv_u128 *counts, int32_t cap, int32_t *omega,
-                                uint64_t *overflow_bits, pv_stats *stats);
+                                uint64_t *overflow_bits, pv_status *status, pv_stats *stats);
 
 /* ------------------------------------------------------------ serving
  * A request loop (continuous batching) over graphs that stay resident on
@@ -335,8 +450,12 @@ typedef struct {
     int32_t device;       /* HIP device */
     int32_t workers;      /* worker threads (>= 1), one context and stream each */
     int32_t max_batch;    /* most requests in one pass (>= 1) */
-    int64_t cache_bytes;  /* device bytes of resident graph CSRs kept between requests (LRU) */
-    int64_t batch_bytes;  /* device bytes one pass may use (admission); larger requests are refused */
+    int64_t cache_bytes;  /* device bytes of idle resident graph CSRs kept between requests (LRU);
+                             graphs pinned by running passes come on top */
+    int64_t batch_bytes;  /* device bytes one pass may use by the admission estimate (its graphs'
+                             union copy and orientation, SCT workspace, per-vertex output);
+                             larger requests are refused.  A worker context's hard limit is
+                             2 * batch_bytes + 64 MiB; a pass that reaches it is split */
 } pv_server_cfg;
 
 #define PV_REQ_GLOBAL 0   /* global counts C_k for all k */

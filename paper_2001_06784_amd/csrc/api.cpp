@@ -16,10 +16,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <memory>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -86,27 +92,51 @@ static int variant_of(int kl, int lk) {
 
 // ------------------------------------------------------------ handles
 
+// Device bytes a context holds, against its configured limit.  Every
+// device allocation of the library goes through DBuf::ensure, which charges
+// the budget of the context whose entry point is running on this host
+// thread (set by BudgetScope) and is refunded when the buffer is released.
+struct Budget {
+    std::atomic<long long> held{0};
+    long long limit = 0;  // 0: no limit besides the device
+};
+static thread_local Budget *tl_budget = nullptr;
+
 template <class T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;  // elements
+    Budget *charged = nullptr;
+    size_t bytes = 0;
     void release() {
         if (p) (void)hipFree(p);
+        if (charged) charged->held -= (long long)bytes;
         p = nullptr;
         n = 0;
+        charged = nullptr;
+        bytes = 0;
     }
     // ensure room for at least `need` elements (contents not kept)
     pv_status ensure(size_t need) {
         if (need <= n && p) return PV_OK;
         release();
-        size_t bytes = std::max<size_t>(need, 1) * sizeof(T);
-        hipError_t e = hipMalloc((void **)&p, bytes);
+        const size_t want = std::max<size_t>(need, 1) * sizeof(T);
+        Budget *b = tl_budget;
+        if (b && b->limit > 0 && b->held.load() + (long long)want > b->limit) {
+            snprintf(g_last_error, sizeof g_last_error, "device memory budget of %lld bytes exceeded",
+                     b->limit);
+            return PV_ENOMEM;
+        }
+        hipError_t e = hipMalloc((void **)&p, want);
         if (e != hipSuccess) {
             set_err("hipMalloc", e);
             p = nullptr;
             return PV_ENOMEM;
         }
         n = std::max<size_t>(need, 1);
+        bytes = want;
+        charged = b;
+        if (b) b->held += (long long)want;
         return PV_OK;
     }
 };
@@ -141,7 +171,17 @@ struct Workspace {
     // per-edge counts
     DBuf<int> ueid, weid;
     DBuf<uint64_t> umem, utot, escr;
-    size_t c_cap = 1 << 20, mw_cap = 1 << 15, u_cap = 1 << 16, pref_cap = 1 << 19;
+    // persistent walk: the queues' slot flags and control block
+    DBuf<int> cready, mready;
+    DBuf<PersistCtl> pctl;
+    // capacities: the walk's first ones follow the graph's size (see
+    // run_sct_walk); a walk that fills a buffer runs again with the demand
+    // it saw, and they stay for later calls.  Persistent walk: c_cap is
+    // slots per slice of the compact queue, mw_cap slots of the multi-word
+    // queue, each over the whole walk.
+    static constexpr size_t C0 = 1 << 12, MW0 = 1 << 10, U0 = 1 << 10, PREF0 = 1 << 12;
+    size_t c_cap = C0, mw_cap = MW0, u_cap = U0, pref_cap = PREF0;
+    size_t pc_cap = C0, pm_cap = MW0;  // persistent walk: slots per compact slice, multi-word slots
     long long hu_budget = 1ll << 30;  // bytes of heavy universes per chunk
 
     void release() {
@@ -161,12 +201,31 @@ struct Workspace {
         u_pref.release();
         hist.release();
         counters.release();
+        cready.release();
+        mready.release();
+        pctl.release();
+        c_cap = C0;
+        mw_cap = MW0;
+        u_cap = U0;
+        pref_cap = PREF0;
+        pc_cap = C0;
+        pm_cap = MW0;
     }
+};
+
+// Settings of the walk chosen by pv_autotune for one key.
+struct TuneEntry {
+    int dfs_max = 64, dfs_budget = 0, lane_max = PV_LANE_MAX;
+    float ms_best = 0.f, ms_default = 0.f;
 };
 
 struct pv_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    Budget budget;
+    std::string arch;                       // device part of the tuning keys
+    std::string tune_path;                  // JSON cache file ("" : none)
+    std::map<std::string, TuneEntry> tune;  // tuned settings by key
     DevInfo dev{};
     // exact binomials
     int bn = 0;
@@ -179,7 +238,9 @@ struct pv_ctx {
     DBuf<LevelArgs> d_args;
     LevelArgs *h_args = nullptr;
     int *h_io = nullptr;  // pinned readback slots
-    int level_blocks[6][3] = {};  // [kernel variant, see variant_of][unit kind]
+    PersistCtl *h_pctl = nullptr;  // pinned readback of the persistent walk's control block
+    int level_blocks[6][4] = {};  // [kernel variant, see variant_of][unit kind, or PV_UNITS_ALL]
+    bool persist = false;  // one persistent launch per walk (PV_PERSIST set) instead of level by level
     int dfs_max = 64;
     int dfs_budget = 0;  // 0: chosen per request (see budget_of)
     int lane_max = PV_LANE_MAX;
@@ -215,6 +276,46 @@ struct pv_graph {
     bool eids = false;
     DBuf<int> eup, o2e;
     pv_stats last{};
+    std::atomic<int> busy{0};  // entry points running on this graph
+    std::string deg_key;       // out-degree histogram part of the tuning key ("" : not yet)
+};
+
+static void tune_load(pv_ctx *c);
+
+// A key's tuned settings on the context for the duration of one call.
+struct TuneScope {
+    pv_ctx *c;
+    bool on = false;
+    int dm = 0, db = 0, lm = 0;
+    TuneScope(pv_ctx *c_, const std::string &key);
+    ~TuneScope();
+    TuneScope(const TuneScope &) = delete;
+    TuneScope &operator=(const TuneScope &) = delete;
+};
+static pv_status tune_scope_for(pv_graph *g, int kind, int klo, int khi, int kmax,
+                                std::unique_ptr<TuneScope> &scope);
+
+// The context's budget for the allocations of one entry point.
+struct BudgetScope {
+    Budget *prev;
+    explicit BudgetScope(pv_ctx *c) : prev(tl_budget) { tl_budget = c ? &c->budget : nullptr; }
+    ~BudgetScope() { tl_budget = prev; }
+};
+
+// Graphs in use by an entry point (pv_graph_free refuses them meanwhile).
+struct GraphUse {
+    pv_graph *const *gs;
+    int count;
+    pv_graph *one;
+    explicit GraphUse(pv_graph *g) : gs(&one), count(1), one(g) { mark(1); }
+    GraphUse(pv_graph *const *list, int n) : gs(list), count(n), one(nullptr) { mark(1); }
+    ~GraphUse() { mark(-1); }
+    GraphUse(const GraphUse &) = delete;
+    GraphUse &operator=(const GraphUse &) = delete;
+    void mark(int d) {
+        for (int i = 0; i < count; i++)
+            if (gs[i]) gs[i]->busy += d;
+    }
 };
 
 // small device scalars in g->small: alpha, three work cursors, emitted multi-word and
@@ -223,9 +324,14 @@ struct pv_graph {
 enum { SM_ALPHA = 0, SM_NEXT, SM_NEXT1, SM_NEXT2, SM_MWN, SM_CN, SM_FLAGS, SM_UN, SM_PREFN,
        SM_OMEGA, SM_LOVF, SM_ERR, SM_BOUNDS, SM_BOUNDS1, SM_COUNT };
 
-extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
+extern "C" pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out) {
     if (!out) return PV_EINVAL;
     *out = nullptr;
+    pv_config conf{};
+    if (cfg) conf = *cfg;
+    if (conf.hbm_budget < 0 || conf.dfs_max < 0 || conf.dfs_max > 64 || conf.lane_max < -1 ||
+        conf.lane_max > PV_LANE_MAX || (conf.dfs_budget != 0 && (conf.dfs_budget < 16 || conf.dfs_budget > (1 << 20))))
+        return PV_EINVAL;
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return PV_EINVAL;
@@ -233,7 +339,9 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
     pv_ctx *c = new (std::nothrow) pv_ctx();
     if (!c) return PV_ENOMEM;
     c->device = device;
-    c->stream = (hipStream_t)stream;
+    c->stream = (hipStream_t)conf.stream;
+    c->budget.limit = conf.hbm_budget;
+    BudgetScope scope(c);
     hipDeviceProp_t prop;
     hipError_t e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) {
@@ -243,10 +351,15 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
     }
     c->dev.device = device;
     c->dev.num_cu = prop.multiProcessorCount;
+    {
+        std::string an = prop.gcnArchName;
+        c->arch = an.substr(0, an.find(':')) + "x" + std::to_string(prop.multiProcessorCount);
+    }
     c->dev.lds_per_block = (int)prop.sharedMemPerBlock;
     c->dev.lds_per_cu = (int)prop.maxSharedMemoryPerMultiProcessor;
     if (hipHostMalloc((void **)&c->h_args, sizeof(LevelArgs)) != hipSuccess ||
-        hipHostMalloc((void **)&c->h_io, 64 * sizeof(int)) != hipSuccess) {
+        hipHostMalloc((void **)&c->h_io, 64 * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_pctl, sizeof(PersistCtl)) != hipSuccess) {
         delete c;
         return PV_ENOMEM;
     }
@@ -255,7 +368,7 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
         return PV_ENOMEM;
     }
     for (int kv = 0; kv < 6; kv++)
-        for (int mode = 0; mode < 3; mode++) {
+        for (int mode = 0; mode < 4; mode++) {
             int kl, lk;
             variant_params(kv, kl, lk);
             int per_cu = pv_level_blocks_per_cu(kl, lk, mode);
@@ -263,12 +376,23 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
         }
     if (const char *env = getenv("PV_DFS_MAX")) c->dfs_max = std::max(1, std::min(64, atoi(env)));
     c->debug = getenv("PV_DEBUG") != nullptr;
+    c->persist = getenv("PV_PERSIST") != nullptr;
     if (const char *env = getenv("PV_DFS_BUDGET")) c->dfs_budget = std::max(16, std::min(1 << 20, atoi(env)));
     if (const char *env = getenv("PV_LANE_MAX")) c->lane_max = std::max(0, std::min(PV_LANE_MAX, atoi(env)));
     if (const char *env = getenv("PV_PREFIX_ROWS")) c->prefix_rows = std::max(0, atoi(env));
     if (const char *env = getenv("PV_HU_BUDGET")) {
         const long long b = atoll(env);
         if (b > 0) c->ws.hu_budget = b;
+    }
+    // the configuration's own settings come after the environment's
+    if (conf.dfs_max > 0) c->dfs_max = conf.dfs_max;
+    if (conf.dfs_budget > 0) c->dfs_budget = conf.dfs_budget;
+    if (conf.lane_max > 0) c->lane_max = conf.lane_max;
+    if (conf.lane_max < 0) c->lane_max = 0;
+    if (c->budget.limit > 0) c->ws.hu_budget = std::min(c->ws.hu_budget, std::max(1ll << 20, c->budget.limit / 4));
+    if (conf.tune_cache) {
+        c->tune_path = conf.tune_cache;
+        tune_load(c);
     }
     for (auto &ev : c->ev)
         if (hipEventCreate(&ev) != hipSuccess) {
@@ -296,6 +420,10 @@ extern "C" pv_status pv_init(int32_t device, void *stream, pv_ctx **out) {
 extern "C" void pv_fini(pv_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    // no work of this context may still be in flight when its memory goes
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &st : c->aux)
+        if (st) (void)hipStreamSynchronize(st);
     if (c->batch) pv_graph_free(c->batch);
     c->batch = nullptr;
     c->parts.release();
@@ -308,6 +436,7 @@ extern "C" void pv_fini(pv_ctx *c) {
     c->d_args.release();
     if (c->h_args) (void)hipHostFree(c->h_args);
     if (c->h_io) (void)hipHostFree(c->h_io);
+    if (c->h_pctl) (void)hipHostFree(c->h_pctl);
     for (auto &st : c->aux)
         if (st) {
             (void)hipStreamSynchronize(st);
@@ -321,17 +450,66 @@ extern "C" void pv_fini(pv_ctx *c) {
     delete c;
 }
 
+extern "C" pv_status pv_memory(const pv_ctx *c, int64_t *held_bytes) {
+    if (!c || !held_bytes) return PV_EINVAL;
+    *held_bytes = c->budget.held.load();
+    return PV_OK;
+}
+
+// Peaks: each kernel runs `reps` times after one untimed run; the best
+// rate counts.  The copy buffers are charged to the context's budget.
+extern "C" pv_status pv_measure_peaks(pv_ctx *c, int64_t copy_bytes, pv_peaks *out) {
+    if (!c || !out || copy_bytes < 0) return PV_EINVAL;
+    BudgetScope bs(c);
+    if (copy_bytes == 0) copy_bytes = (int64_t)1 << 30;
+    copy_bytes = (copy_bytes + 4095) / 4096 * 4096;
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    DBuf<uint8_t> a, b;
+    DBuf<unsigned long long> sink;
+    PVCHK(a.ensure((size_t)copy_bytes));
+    PVCHK(b.ensure((size_t)copy_bytes));
+    PVCHK(sink.ensure((size_t)PV_PEAK_BLOCKS * 256));
+    HIPCHK(hipMemsetAsync(a.p, 0x5a, (size_t)copy_bytes, s));
+    const int reps = 5, lds_iters = 1024, valu_iters = 256;
+    hipEvent_t e0 = c->ev[14], e1 = c->ev[15];
+    auto best_ms = [&](auto launch, float &ms_best) -> pv_status {
+        ms_best = 0.f;
+        HIPCHK(launch());
+        for (int r = 0; r < reps; r++) {
+            HIPCHK(hipEventRecord(e0, s));
+            HIPCHK(launch());
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms_best == 0.f || ms < ms_best) ms_best = ms;
+        }
+        return PV_OK;
+    };
+    float ms_copy, ms_read, ms_lds, ms_valu;
+    PVCHK(best_ms([&] { return pv_launch_peak_copy(a.p, b.p, copy_bytes, s); }, ms_copy));
+    PVCHK(best_ms([&] { return pv_launch_peak_read(a.p, copy_bytes, (unsigned *)sink.p, s); }, ms_read));
+    PVCHK(best_ms([&] { return pv_launch_peak_lds(lds_iters, 0, sink.p, s); }, ms_lds));
+    PVCHK(best_ms([&] { return pv_launch_peak_valu(valu_iters, 0x1234567u, (unsigned *)sink.p, s); }, ms_valu));
+    const double threads = (double)PV_PEAK_BLOCKS * 256.0;
+    out->hbm_copy_gbs = 2.0 * (double)copy_bytes / (ms_copy * 1e-3) / 1e9;
+    out->hbm_read_gbs = (double)copy_bytes / (ms_read * 1e-3) / 1e9;
+    out->lds_read_gbs = threads * lds_iters * (double)PV_PEAK_LDS_READS * 8.0 / (ms_lds * 1e-3) / 1e9;
+    out->valu_gops = threads * valu_iters * 8.0 * 8.0 * 2.0 / (ms_valu * 1e-3) / 1e9;
+    out->ms_copy = ms_copy;
+    out->ms_read = ms_read;
+    out->ms_lds = ms_lds;
+    out->ms_valu = ms_valu;
+    return PV_OK;
+}
+
 extern "C" pv_status pv_set_stream(pv_ctx *c, void *stream) {
     if (!c) return PV_EINVAL;
     c->stream = (hipStream_t)stream;
     return PV_OK;
 }
 
-// Nodes a wave walks before it splits: measured on the 1M-vertex power-law
-// graph, 4096 is best for global counts alone (fewer levels than 2048, and
-// larger budgets leave long walks at the end of a level) and 8192 with local
-// counts (every unit ends with a flush of its accumulators and a partial
-// lane batch, so fewer, larger units pay)
 // Depth-first budget of a level: the set value, else 4096 with global
 // counts alone and 8192 with local counts (each unit ends with a flush and
 // a partial lane batch there, so fewer, larger units pay).  With local
@@ -382,19 +560,24 @@ static pv_status ensure_binomials(pv_ctx *c, int need, int ts_need = 32) {
     if (need <= c->bn && ts_need <= c->ts) return PV_OK;
     int bn = std::max(need, c->bn);
     if (need > c->bn) bn = std::max(need, 2 * c->bn);
-    c->ts = std::max(c->ts, (ts_need + 7) / 8 * 8);
+    const int ts = std::max(c->ts, (ts_need + 7) / 8 * 8);
+    // the tables are rebuilt whole: until that succeeds the context has none
+    // (a failed allocation below has released the old ones)
+    c->bn = 0;
+    c->ts = 0;
     PVCHK(c->tab.ensure((size_t)bn * bn * 2));
     PVCHK(c->bad.ensure((size_t)bn * bn));
     PVCHK(c->tab64.ensure((size_t)bn * 16));
     PVCHK(c->fits64.ensure(16));
     std::vector<int> ones(16, 1);
     HIPCHK(hipMemcpyAsync(c->fits64.p, ones.data(), 16 * sizeof(int), hipMemcpyHostToDevice, c->stream));
-    PVCHK(c->tab_pad.ensure((size_t)(bn + 1) * c->ts));
+    PVCHK(c->tab_pad.ensure((size_t)2 * (bn + 1) * ts));
     HIPCHK(pv_launch_binomials(bn, c->tab.p, c->bad.p, c->tab64.p, c->fits64.p, c->stream));
-    HIPCHK(pv_launch_binom_pad(bn, c->ts, c->tab.p, c->tab_pad.p, c->stream));
+    HIPCHK(pv_launch_binom_pad(bn, ts, c->tab.p, c->bad.p, c->tab_pad.p, c->stream));
     HIPCHK(hipMemcpyAsync(c->fits64_h, c->fits64.p, 16 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->bn = bn;
+    c->ts = ts;
     return PV_OK;
 }
 
@@ -438,6 +621,47 @@ static pv_status graph_validate(pv_graph *g, uint32_t flags) {
     return *err ? PV_ENOTSIMPLE : PV_OK;
 }
 
+// Repair of a host CSR (PV_DEDUP, PV_SYMMETRIZE): every row sorted, repeated
+// entries and self loops dropped, and with PV_SYMMETRIZE the reverse of
+// every entry added.  The row pointers must already be monotone and every
+// column id in [0, n).
+static pv_status repair_csr(int32_t n, const int32_t *rp, const int32_t *col, uint32_t flags,
+                            std::vector<int32_t> &rp_out, std::vector<int32_t> &col_out) {
+    const long long nnz = rp[n];
+    for (long long i = 0; i < nnz; i++)
+        if (col[i] < 0 || col[i] >= n) return PV_ENOTSIMPLE;
+    std::vector<long long> deg((size_t)n + 1, 0);
+    const bool sym = (flags & PV_SYMMETRIZE) != 0;
+    for (int32_t v = 0; v < n; v++)
+        for (int32_t i = rp[v]; i < rp[v + 1]; i++) {
+            if (col[i] == v) continue;
+            deg[v]++;
+            if (sym) deg[col[i]]++;
+        }
+    std::vector<long long> off((size_t)n + 1, 0);
+    for (int32_t v = 0; v < n; v++) off[v + 1] = off[v] + deg[v];
+    if (off[n] >= (1ll << 31)) return PV_ETOOBIG;
+    std::vector<int32_t> tmp((size_t)std::max<long long>(off[n], 1));
+    std::vector<long long> fill(off.begin(), off.end() - 1);
+    for (int32_t v = 0; v < n; v++)
+        for (int32_t i = rp[v]; i < rp[v + 1]; i++) {
+            const int32_t u = col[i];
+            if (u == v) continue;
+            tmp[fill[v]++] = u;
+            if (sym) tmp[fill[u]++] = v;
+        }
+    rp_out.assign((size_t)n + 1, 0);
+    col_out.clear();
+    col_out.reserve((size_t)off[n]);
+    for (int32_t v = 0; v < n; v++) {
+        std::sort(tmp.begin() + off[v], tmp.begin() + off[v + 1]);
+        const auto end = std::unique(tmp.begin() + off[v], tmp.begin() + off[v + 1]);
+        col_out.insert(col_out.end(), tmp.begin() + off[v], end);
+        rp_out[v + 1] = (int32_t)col_out.size();
+    }
+    return PV_OK;
+}
+
 extern "C" pv_status pv_graph_load_csr(pv_ctx *c, int32_t n, const int32_t *row_ptr,
                                        const int32_t *col, uint32_t flags, pv_graph **out) {
     if (!c || !out || n < 0 || !row_ptr || (n > 0 && row_ptr[n] > 0 && !col)) return PV_EINVAL;
@@ -445,7 +669,14 @@ extern "C" pv_status pv_graph_load_csr(pv_ctx *c, int32_t n, const int32_t *row_
     if (row_ptr[0] != 0 || row_ptr[n] < 0) return PV_ENOTSIMPLE;
     for (int32_t i = 0; i < n; i++)
         if (row_ptr[i + 1] < row_ptr[i]) return PV_ENOTSIMPLE;
+    std::vector<int32_t> rrp, rcol;
+    if (flags & (PV_DEDUP | PV_SYMMETRIZE)) {
+        PVCHK(repair_csr(n, row_ptr, col, flags, rrp, rcol));
+        row_ptr = rrp.data();
+        col = rcol.data();
+    }
     HIPCHK(hipSetDevice(c->device));
+    BudgetScope scope(c);
     pv_graph *g = nullptr;
     PVCHK(graph_new(c, n, row_ptr[n], &g));
     hipError_t e = hipMemcpyAsync(g->rp.p, row_ptr, sizeof(int) * ((size_t)n + 1),
@@ -472,6 +703,18 @@ extern "C" pv_status pv_graph_load_csr_device(pv_ctx *c, int32_t n, int64_t nnz,
     if (!c || !out || n < 0 || nnz < 0 || !d_row_ptr || (nnz > 0 && !d_col)) return PV_EINVAL;
     *out = nullptr;
     HIPCHK(hipSetDevice(c->device));
+    if (flags & (PV_DEDUP | PV_SYMMETRIZE)) {
+        // repairs run on the host: a round trip of the CSR
+        if (nnz >= (1ll << 31)) return PV_ETOOBIG;
+        std::vector<int32_t> hrp((size_t)n + 1), hcol((size_t)std::max<long long>(nnz, 1));
+        HIPCHK(hipMemcpyAsync(hrp.data(), d_row_ptr, sizeof(int) * hrp.size(), hipMemcpyDeviceToHost, c->stream));
+        if (nnz)
+            HIPCHK(hipMemcpyAsync(hcol.data(), d_col, sizeof(int) * (size_t)nnz, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        if (hrp[n] != nnz) return PV_EINVAL;
+        return pv_graph_load_csr(c, n, hrp.data(), hcol.data(), flags, out);
+    }
+    BudgetScope scope(c);
     pv_graph *g = nullptr;
     PVCHK(graph_new(c, n, nnz, &g));
     hipError_t e = hipMemcpyAsync(g->rp.p, d_row_ptr, sizeof(int) * ((size_t)n + 1),
@@ -492,14 +735,19 @@ extern "C" pv_status pv_graph_load_csr_device(pv_ctx *c, int32_t n, int64_t nnz,
     return PV_OK;
 }
 
-extern "C" void pv_graph_free(pv_graph *g) {
-    if (!g) return;
+extern "C" pv_status pv_graph_free(pv_graph *g) {
+    if (!g) return PV_OK;
+    if (g->busy.load() > 0) {
+        snprintf(g_last_error, sizeof g_last_error, "graph in use by a running count");
+        return PV_EAGAIN;
+    }
     (void)hipSetDevice(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
     DBuf<int> *ib[] = {&g->rp, &g->col, &g->sub, &g->odeg, &g->orow, &g->ocol, &g->small, &g->order,
                        &g->vgraph, &g->eup, &g->o2e};
     for (auto *b : ib) b->release();
     delete g;
+    return PV_OK;
 }
 
 extern "C" pv_status pv_graph_size(const pv_graph *g, int32_t *n, int64_t *m) {
@@ -514,6 +762,8 @@ extern "C" pv_status pv_graph_size(const pv_graph *g, int32_t *n, int64_t *m) {
 extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     if (!g) return PV_EINVAL;
     pv_ctx *c = g->ctx;
+    GraphUse use(g);
+    BudgetScope scope(c);
     HIPCHK(hipSetDevice(c->device));
     const int n = g->n;
     PVCHK(g->sub.ensure(n));
@@ -593,6 +843,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
 
 extern "C" pv_status pv_graph_export_order(pv_graph *g, int32_t *sub_host) {
     if (!g || (!sub_host && g->n > 0)) return PV_EINVAL;
+    GraphUse use(g);
     if (!g->oriented) PVCHK(pv_graph_orient(g, nullptr));
     HIPCHK(hipSetDevice(g->ctx->device));
     if (g->n)
@@ -613,6 +864,7 @@ struct CountReq {
     int graphs = 1;       // batch: parts of the disjoint union (one histogram each)
     const int *vgraph = nullptr;  // batch: part of every vertex
     int klo = 1, K = 0;
+    bool wide_tab = false;     // some binomial the local sinks use passes 64 bits
     uint64_t *vout = nullptr;  // device [n][kstride] u128; this pass writes columns 0..K-1
     int kstride = 0;           // row stride of vout in slots (0: K)
     int c0 = 1;           // value of C_0
@@ -620,9 +872,23 @@ struct CountReq {
     const int *order = nullptr;
     int nheavy = 0, nlight = 0;
     bool whole = true;
+    // a root subset's size (its roots and their out-degrees' sum), which
+    // the first buffer capacities follow; -1: the graph's n and m
+    long long size_n = -1, size_m = -1;
 };
 
+static pv_status run_sct_walk(pv_graph *g, const CountReq &rq);
+
+// The walk; if it runs out of device memory (or of the context's budget)
+// the SCT buffers are released, so the context stays usable for smaller
+// work.
 static pv_status run_sct(pv_graph *g, const CountReq &rq) {
+    pv_status st = run_sct_walk(g, rq);
+    if (st == PV_ENOMEM) g->ctx->ws.release();
+    return st;
+}
+
+static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
     pv_ctx *c = g->ctx;
     hipStream_t s = c->stream;
     const int alpha = g->alpha;
@@ -646,7 +912,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
         auto at_least = [](size_t &cap, long long want) {
             if ((long long)cap < want) cap = (size_t)want;
         };
-        const long long n = g->n, m = g->nnz / 2;
+        const long long n = rq.size_n >= 0 ? rq.size_n : g->n, m = rq.size_m >= 0 ? rq.size_m : g->nnz / 2;
         // (on a 1M-vertex, 9.9M-edge power-law graph: 0.52M items in the
         // fullest level, 187k multi-word items from 6.4k heavy roots, 251k
         // universes and 2.5M prefix entries over the whole walk)
@@ -654,16 +920,30 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
         at_least(c->ws.u_cap, std::min<long long>(n / 2 + 1024, 1ll << 22));
         at_least(c->ws.pref_cap, std::min<long long>(4 * n + 4096, 1ll << 27));
         at_least(c->ws.mw_cap, std::min<long long>(rq.nheavy * 64ll + 1024, 1ll << 22));
+        // the persistent walk's queues hold every item of the walk, not one
+        // level's: twice the fullest level's demand, spread over the slices
+        at_least(c->ws.pc_cap, std::min<long long>(2 * (2 * n + m / 8) / PV_QSLICES + 1024, 1ll << 26));
+        at_least(c->ws.pm_cap, std::min<long long>(2 * rq.nheavy * 64ll + 1024, 1ll << 23));
     }
+    const bool persist = c->persist;
+    const int kli = variant_of(rq.kl, rq.lk);
     for (int attempt = 0;; attempt++) {
         if (attempt > 12) return PV_ENOMEM;
         g->last.attempts = attempt + 1;
         PVCHK(c->ws.hist.ensure((size_t)rq.graphs * hd * hd));
         if (rq.vgraph) PVCHK(c->ws.u_root.ensure(c->ws.u_cap));
-        PVCHK(c->ws.counters.ensure(8));
-        for (int i = 0; i < 2; i++) {
-            PVCHK(c->ws.citem[i].ensure(c->ws.c_cap));
-            PVCHK(c->ws.mwitem[i].ensure(c->ws.mw_cap * mw_stride));
+        PVCHK(c->ws.counters.ensure(PV_NCOUNTERS));
+        if (persist) {
+            PVCHK(c->ws.citem[0].ensure(c->ws.pc_cap * PV_QSLICES));
+            PVCHK(c->ws.cready.ensure(c->ws.pc_cap * PV_QSLICES));
+            PVCHK(c->ws.mwitem[0].ensure(c->ws.pm_cap * mw_stride));
+            PVCHK(c->ws.mready.ensure(c->ws.pm_cap));
+            PVCHK(c->ws.pctl.ensure(1));
+        } else {
+            for (int i = 0; i < 2; i++) {
+                PVCHK(c->ws.citem[i].ensure(c->ws.c_cap));
+                PVCHK(c->ws.mwitem[i].ensure(c->ws.mw_cap * mw_stride));
+            }
         }
         PVCHK(c->ws.u_rows.ensure(c->ws.u_cap * 64));
         if (local) {
@@ -684,9 +964,12 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             PVCHK(c->ws.umem.ensure(c->ws.u_cap * 64 * 2 * rq.K * 2));
             PVCHK(c->ws.utot.ensure(c->ws.u_cap * 3 * rq.K * 2));
             PVCHK(c->ws.ueid.ensure(c->ws.u_cap * 4096));
-            PVCHK(c->ws.weid.ensure((size_t)c->level_blocks[3][PV_UNITS_LIGHT] * WAVES_PER_LAUNCH_BLOCK * 4096));
-            // one region per unit kind (the kinds of a level run concurrently)
-            const int eb = c->level_blocks[3][0] + c->level_blocks[3][1] + c->level_blocks[3][2];
+            const int wb = persist ? c->level_blocks[3][PV_UNITS_ALL] : c->level_blocks[3][PV_UNITS_LIGHT];
+            PVCHK(c->ws.weid.ensure((size_t)wb * WAVES_PER_LAUNCH_BLOCK * 4096));
+            // one region per wave; level by level, per unit kind too (the
+            // kinds of a level run concurrently)
+            const int eb = persist ? c->level_blocks[3][PV_UNITS_ALL]
+                                   : c->level_blocks[3][0] + c->level_blocks[3][1] + c->level_blocks[3][2];
             const size_t escr_words = (size_t)eb * WAVES_PER_LAUNCH_BLOCK * 2 * 64 * 2 * rq.K * 2;
             PVCHK(c->ws.escr.ensure(escr_words));
             HIPCHK(hipMemsetAsync(c->ws.escr.p, 0, escr_words * 8, s));
@@ -696,7 +979,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             PVCHK(c->ws.hu_vl.ensure((size_t)chunk * dpad));
         }
         HIPCHK(hipMemsetAsync(c->ws.hist.p, 0, sizeof(unsigned long long) * (size_t)rq.graphs * hd * hd, s));
-        HIPCHK(hipMemsetAsync(c->ws.counters.p, 0, 8 * sizeof(unsigned long long), s));
+        HIPCHK(hipMemsetAsync(c->ws.counters.p, 0, PV_NCOUNTERS * sizeof(unsigned long long), s));
         HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, 5 * sizeof(int), s));  // flags,u_n,pref_n,omega,lovf
         const size_t lrows = rq.edge ? (size_t)(g->nnz / 2) : (size_t)g->n;
         const int kstride = rq.kstride > 0 ? rq.kstride : rq.K;
@@ -721,8 +1004,8 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
             const int hbase = ch * chunk;
             const int hcount = (chunk > 0) ? std::min(chunk, rq.nheavy - hbase) : 0;
             int n_mw = 0, n_c = 0, cur = 0;
-            for (int level = 0;; level++) {
-                LevelArgs a;
+            // launch arguments shared by both forms of the walk
+            auto fill_args = [&](LevelArgs &a, int level, int n_mw, int n_c, int cur, int nl) {
                 memset(&a, 0, sizeof a);
                 a.n = g->n;
                 a.orow = g->orow.p;
@@ -731,7 +1014,7 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.heavy_base = hbase;
                 a.nheavy = hcount;
                 a.light_base = rq.nheavy;
-                a.nlight = (ch == 0) ? rq.nlight : 0;
+                a.nlight = nl;
                 a.kmax = rq.kmax;
                 a.dfs_max = c->dfs_max;
                 a.dfs_budget = budget_of(c, local);
@@ -771,6 +1054,9 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.K = rq.K;
                 a.kstride = kstride;
                 a.bin_pad = c->tab_pad.p;
+                a.bin_pad_hi = rq.wide_tab ? c->tab_pad.p + (size_t)(c->bn + 1) * c->ts : nullptr;
+                a.bin_bad = c->bad.p;
+                a.bin_bn = c->bn;
                 a.tab_stride = c->ts;
                 a.lovf = g->small.p + SM_LOVF;
                 a.sub = g->sub.p;
@@ -785,6 +1071,83 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
                 a.escr_wave0[2] = (c->level_blocks[3][0] + c->level_blocks[3][1]) * WAVES_PER_LAUNCH_BLOCK;
                 a.vgraph = rq.vgraph;
                 a.u_root = rq.vgraph ? c->ws.u_root.p : nullptr;
+            };
+            if (persist) {
+                // the whole walk of this chunk in one launch: every unit
+                // from the device queues until the tree is done
+                LevelArgs a;
+                fill_args(a, 0, 0, 0, 0, (ch == 0) ? rq.nlight : 0);
+                a.persist = 1;
+                a.pctl = c->ws.pctl.p;
+                a.cready = c->ws.cready.p;
+                a.mready = c->ws.mready.p;
+                a.c_scap = (int)c->ws.pc_cap;
+                a.m_cap = (int)c->ws.pm_cap;
+                a.c_out = c->ws.citem[0].p;
+                a.mw_out = c->ws.mwitem[0].p;
+                a.escr_wave0[0] = a.escr_wave0[1] = a.escr_wave0[2] = 0;
+                const int blocks = c->level_blocks[kli][PV_UNITS_ALL];
+                const long long waves = (long long)blocks * WAVES_PER_LAUNCH_BLOCK;
+                // light roots: claimed in interleaved chunks, the last 8 per wave one at a time
+                const long long nl = a.nlight;
+                const long long lch = std::max(1ll, std::min(32ll, nl / (waves * 16)));
+                const long long ln0 = (lch > 1) ? std::max(0ll, nl - 8 * waves) : 0;
+                a.n0[PV_UNITS_LIGHT] = (int)ln0;
+                a.nch[PV_UNITS_LIGHT] = (int)((ln0 + lch - 1) / lch);
+                a.dfs_budget = budget_of(c, local);
+                *c->h_args = a;
+                HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 5 * sizeof(int), s));
+                HIPCHK(hipMemsetAsync(c->ws.pctl.p, 0, sizeof(PersistCtl), s));
+                HIPCHK(hipMemsetAsync(c->ws.cready.p, 0, c->ws.pc_cap * PV_QSLICES * sizeof(int), s));
+                HIPCHK(hipMemsetAsync(c->ws.mready.p, 0, c->ws.pm_cap * sizeof(int), s));
+                HIPCHK(hipMemcpyAsync(c->d_args.p, c->h_args, sizeof(LevelArgs), hipMemcpyHostToDevice, s));
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[3], s));
+                HIPCHK(pv_launch_level(c->d_args.p, rq.kl, rq.lk, PV_UNITS_ALL, blocks, s));
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[4], s));
+                HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
+                PersistCtl *pcs = c->h_pctl;
+                HIPCHK(hipMemcpyAsync(pcs, c->ws.pctl.p, sizeof(PersistCtl), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                io_fresh = true;
+                levels++;
+                launches_kind[PV_UNITS_ITEMS]++;
+                long long ctail_max = 0, pushed = (long long)(uint32_t)pcs->mtail.v;
+                for (int sl = 0; sl < PV_QSLICES; sl++) {
+                    ctail_max = std::max(ctail_max, (long long)(uint32_t)pcs->ctail[sl].v);
+                    pushed += (long long)(uint32_t)pcs->ctail[sl].v;
+                }
+                if (c->timing) {
+                    const float lv = elapsed(c, 3, 4);
+                    ms_levels += lv;
+                    ms_kind[PV_UNITS_ITEMS] += lv;
+                }
+                if (c->debug)
+                    fprintf(stderr, "[pivoter] attempt %d chunk %d: persistent walk, %d blocks, items %lld "
+                            "(largest slice %lld of %zu, multi-word %u of %zu), universes %d prefix %d, state %u\n",
+                            attempt, ch, blocks, pushed, ctail_max, c->ws.pc_cap, (unsigned)(uint32_t)pcs->mtail.v,
+                            c->ws.pm_cap, io[SM_UN], io[SM_PREFN], (unsigned)pcs->state.v);
+                if (pcs->state.v & 3) {
+                    snprintf(g_last_error, sizeof g_last_error, "persistent walk stopped: %s",
+                             (pcs->state.v & 1) ? "no unit finished for 10 s" : "a queue slot was never written");
+                    return PV_EDEVICE;
+                }
+                if (io[SM_FLAGS] & 1) {
+                    overflow = true;
+                    auto grow = [](size_t &cap, long long demand) {
+                        if ((size_t)demand >= cap) cap = std::max(cap * 2, (size_t)(demand * 5 / 4) + 1024);
+                    };
+                    grow(c->ws.pc_cap, ctail_max);
+                    grow(c->ws.pm_cap, (long long)(uint32_t)pcs->mtail.v);
+                    grow(c->ws.u_cap, (unsigned)io[SM_UN]);
+                    grow(c->ws.pref_cap, (unsigned)io[SM_PREFN]);
+                    break;
+                }
+                items += pushed;
+                continue;
+            }
+            for (int level = 0;; level++) {
+                LevelArgs a;
+                fill_args(a, level, n_mw, n_c, cur, (ch == 0) ? rq.nlight : 0);
                 const long long units = (long long)n_mw + n_c + (level == 0 ? (long long)a.nheavy + a.nlight : 0);
                 if (units == 0) break;
                 const int kli = variant_of(rq.kl, rq.lk);
@@ -907,9 +1270,30 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
     }
 }
 
+// Read the walk's work counters into g->last.  The leaf sums come from the
+// (h, p) leaf histogram; child work is one word per child (every node but
+// the roots is a child) plus the multi-word children's extra words.
+static pv_status read_counters(pv_graph *g, const CountReq &rq) {
+    pv_ctx *c = g->ctx;
+    hipStream_t s = c->stream;
+    unsigned long long hcnt[PV_NCOUNTERS];
+    HIPCHK(pv_launch_leaf_moments(c->ws.hist.p, g->alpha + 2, rq.graphs, c->ws.counters.p, s));
+    HIPCHK(hipMemcpyAsync(hcnt, c->ws.counters.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const unsigned long long roots = (unsigned long long)(rq.whole ? g->n : rq.size_n);
+    g->last.nodes = hcnt[0];
+    g->last.leaves = hcnt[1];
+    g->last.work = hcnt[2];
+    for (int mode = 0; mode < 3; mode++) g->last.work_kind[mode] = hcnt[4 + mode];
+    g->last.child_work = hcnt[0] - std::min(hcnt[0], roots) + hcnt[PV_CTR_CHILD];
+    g->last.leaf_hp = hcnt[PV_CTR_HP];
+    g->last.leaf_pp = hcnt[PV_CTR_PP];
+    return PV_OK;
+}
+
 static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts, int32_t cap,
                                int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats,
-                               uint64_t *local_ovf) {
+                               uint64_t *local_ovf, pv_status *status = nullptr) {
     pv_ctx *c = g->ctx;
     hipStream_t s = c->stream;
     const int hd = g->alpha + 2;
@@ -927,19 +1311,13 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
     if (c->timing) HIPCHK(hipEventRecord(c->ev[6], s));
     std::vector<uint64_t> hc((size_t)G * kcap * 2), ho((size_t)G * nw);
     std::vector<int> hom(G);
-    unsigned long long hcnt[8];
     HIPCHK(hipMemcpyAsync(hc.data(), c->ws.counts.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(ho.data(), c->ws.ovf.p, ho.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(hom.data(), c->ws.omegas.p, (size_t)G * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hcnt, c->ws.counters.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(c->h_io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    PVCHK(read_counters(g, rq));
     int omega_max = 0;
     for (int b = 0; b < G; b++) omega_max = std::max(omega_max, hom[b]);
-    g->last.nodes = hcnt[0];
-    g->last.leaves = hcnt[1];
-    g->last.work = hcnt[2];
-    for (int mode = 0; mode < 3; mode++) g->last.work_kind[mode] = hcnt[4 + mode];
     if (c->timing) g->last.ms_finalize = elapsed(c, 5, 6);
     g->last.alpha = g->alpha;
     g->last.omega = omega_max;
@@ -952,6 +1330,7 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
         const int omega = hom[b];
         if (omega_out) omega_out[b] = omega;
         const int top = (rq.kmax > 0) ? std::min(omega, rq.kmax) : omega;
+        bool b_short = false, b_ovf = false;
         if (counts) {
             pv_u128 *row = counts + (size_t)b * cap;
             const uint64_t *src = hc.data() + (size_t)b * kcap * 2;
@@ -959,16 +1338,17 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
                 row[k].lo = (k < kcap) ? src[2 * k] : 0;
                 row[k].hi = (k < kcap) ? src[2 * k + 1] : 0;
             }
-            if (cap <= top) short_buf = true;
+            if (cap <= top) short_buf = b_short = true;
         }
         uint64_t *ob = overflow_bits ? overflow_bits + (size_t)b * cw : nullptr;
         if (ob) memset(ob, 0, sizeof(uint64_t) * (size_t)cw);
         for (int k = 0; k < kcap; k++) {
             if ((ho[(size_t)b * nw + (k >> 6)] >> (k & 63)) & 1) {
-                any_ovf = true;
+                any_ovf = b_ovf = true;
                 if (ob && k < cap) ob[k >> 6] |= 1ull << (k & 63);
             }
         }
+        if (status) status[b] = b_short ? PV_EBUFSIZE : (b_ovf ? PV_EOVERFLOW : PV_OK);
     }
     if (short_buf) return PV_EBUFSIZE;
     if (any_ovf || (local_ovf && *local_ovf)) return PV_EOVERFLOW;
@@ -978,7 +1358,11 @@ static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts,
 static pv_status prepare(pv_graph *g, bool reorient) {
     HIPCHK(hipSetDevice(g->ctx->device));
     g->last = pv_stats{};
-    if (reorient || !g->oriented) PVCHK(pv_graph_orient(g, nullptr));
+    if (reorient || !g->oriented) {
+        const pv_status st = pv_graph_orient(g, nullptr);
+        if (st == PV_ENOMEM) g->ctx->ws.release();  // leave the context usable for smaller graphs
+        if (st != PV_OK) return st;
+    }
     if (g->alpha > PV_MAX_ALPHA) {
         snprintf(g_last_error, sizeof g_last_error, "degeneracy %d exceeds %d", g->alpha, PV_MAX_ALPHA);
         return PV_ETOOBIG;
@@ -1010,15 +1394,14 @@ static pv_status setup_local(pv_graph *g, int kind, int klo, int khi, CountReq &
     rq.K = khi - klo + 1;
     rq.kl = rq.K <= 8 ? 8 : 16;
     rq.edge = kind == PV_EDGE;
-    // the local paths keep C(a, b), a <= alpha, b <= khi - 1, in 64 bits;
-    // C(a, b) grows with a, so the largest value used is max over b of
-    // C(alpha, b)
+    // the local paths use C(a, b), a <= alpha, b <= khi - 1; C(a, b) grows
+    // with a, so the largest value used is at most max over b of C(alpha, b)
     // padded rows reach column klo + kl + 14 (a leaf's segment starts at
     // klo - h + 16 with h >= 1 and spans the kernel's kl slots)
     PVCHK(ensure_binomials(g->ctx, g->alpha + 3, klo + rq.kl + 15));
     unsigned __int128 cb = 1, cmax = 1;
-    bool fits = true;
-    for (int b = 1; b <= khi - 1 && b <= g->alpha; b++) {
+    bool fits = true;  // all of them below 2^64
+    for (int b = 1; b <= khi - 1 && b <= g->alpha && fits; b++) {
         cb = cb * (unsigned __int128)(g->alpha - b + 1) / (unsigned __int128)b;
         if (cb >> 64) fits = false;
         cmax = std::max(cmax, cb);
@@ -1035,22 +1418,18 @@ static pv_status setup_local(pv_graph *g, int kind, int klo, int khi, CountReq &
     // vertices) to a visit, and a lane's or a batch's sums stay below that
     rq.lane_ok = rq.lk == PV_LK_VERTEX64 && rq.kl == 8 &&
                  cmax * (visit_leaves + 64 * 34) < ((unsigned __int128)1 << 64);
-    if (!fits) {
-        snprintf(g_last_error, sizeof g_last_error,
-                 "local counts up to k=%d need binomials beyond 64 bits", khi);
-        return PV_ETOOBIG;
-    }
+    // binomials beyond 64 bits: the sinks add the table's high limbs too,
+    // and flag the (exact) overflow of any count that needs one of 2^128 or
+    // more (a leaf with at least 132 pivot vertices)
+    rq.wide_tab = !fits;
     if (rq.edge) PVCHK(ensure_edge_ids(g));
     return PV_OK;
 }
 
-extern "C" pv_status pv_count(pv_graph *g, int32_t reorient, int32_t k_max, pv_u128 *counts,
-                              int32_t cap, int32_t *omega_out, uint64_t *overflow_bits,
-                              int32_t local_kind, int32_t k_lo, int32_t k_hi, pv_u128 *local_out,
-                              uint64_t *local_ovf, pv_stats *stats) {
-    if (!g || cap < 0 || (cap > 0 && !counts)) return PV_EINVAL;
-    if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
-    PVCHK(prepare(g, reorient != 0));
+// pv_count on a prepared (oriented) graph with the context's settings
+static pv_status count_body(pv_graph *g, int32_t k_max, pv_u128 *counts, int32_t cap, int32_t *omega_out,
+                            uint64_t *overflow_bits, int32_t local_kind, int32_t k_lo, int32_t k_hi,
+                            pv_u128 *local_out, uint64_t *local_ovf, pv_stats *stats) {
     CountReq rq;
     rq.kmax = k_max > 0 ? k_max : 0;
     PVCHK(setup_local(g, local_kind, k_lo, k_hi, rq));
@@ -1060,6 +1439,34 @@ extern "C" pv_status pv_count(pv_graph *g, int32_t reorient, int32_t k_max, pv_u
     rq.nlight = g->nnonzero - g->nheavy;
     PVCHK(run_sct(g, rq));
     return finish_counts(g, rq, counts, cap, omega_out, overflow_bits, stats, local_ovf);
+}
+
+// pv_count without the tuning cache (pv_autotune times settings with it)
+static pv_status count_untuned(pv_graph *g, int32_t reorient, int32_t k_max, pv_u128 *counts, int32_t cap,
+                               int32_t *omega_out, uint64_t *overflow_bits, int32_t local_kind, int32_t k_lo,
+                               int32_t k_hi, pv_u128 *local_out, uint64_t *local_ovf, pv_stats *stats) {
+    if (!g || cap < 0 || (cap > 0 && !counts)) return PV_EINVAL;
+    if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
+    GraphUse use(g);
+    BudgetScope scope(g->ctx);
+    PVCHK(prepare(g, reorient != 0));
+    return count_body(g, k_max, counts, cap, omega_out, overflow_bits, local_kind, k_lo, k_hi, local_out,
+                      local_ovf, stats);
+}
+
+extern "C" pv_status pv_count(pv_graph *g, int32_t reorient, int32_t k_max, pv_u128 *counts,
+                              int32_t cap, int32_t *omega_out, uint64_t *overflow_bits,
+                              int32_t local_kind, int32_t k_lo, int32_t k_hi, pv_u128 *local_out,
+                              uint64_t *local_ovf, pv_stats *stats) {
+    if (!g || cap < 0 || (cap > 0 && !counts)) return PV_EINVAL;
+    if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
+    GraphUse use(g);
+    BudgetScope scope(g->ctx);
+    PVCHK(prepare(g, reorient != 0));
+    std::unique_ptr<TuneScope> tuned;
+    PVCHK(tune_scope_for(g, local_kind, k_lo, k_hi, k_max, tuned));
+    return count_body(g, k_max, counts, cap, omega_out, overflow_bits, local_kind, k_lo, k_hi, local_out,
+                      local_ovf, stats);
 }
 
 extern "C" pv_status pv_count_global(pv_graph *g, int32_t k_max, pv_u128 *counts, int32_t cap,
@@ -1073,6 +1480,8 @@ extern "C" pv_status pv_count_global_wide(pv_graph *g, int32_t k_max, uint64_t *
                                           pv_stats *stats) {
     if (!g || cap < 0 || (cap > 0 && !counts) || limbs < 1) return PV_EINVAL;
     pv_ctx *c = g->ctx;
+    GraphUse use(g);
+    BudgetScope scope(c);
     PVCHK(prepare(g, false));
     CountReq rq;
     rq.kmax = k_max > 0 ? k_max : 0;
@@ -1108,15 +1517,9 @@ extern "C" pv_status pv_count_global_wide(pv_graph *g, int32_t k_max, uint64_t *
     if (c->timing) HIPCHK(hipEventRecord(c->ev[6], s));
     std::vector<uint64_t> hc((size_t)kcap * W);
     int omega = 0;
-    unsigned long long hcnt[8];
     HIPCHK(hipMemcpyAsync(hc.data(), c->ws.wide_out.p, hc.size() * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&omega, c->ws.wide_i.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(hcnt, c->ws.counters.p, sizeof hcnt, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    g->last.nodes = hcnt[0];
-    g->last.leaves = hcnt[1];
-    g->last.work = hcnt[2];
-    for (int mode = 0; mode < 3; mode++) g->last.work_kind[mode] = hcnt[4 + mode];
+    PVCHK(read_counters(g, rq));
     if (c->timing) g->last.ms_finalize = elapsed(c, 5, 6);
     g->last.alpha = g->alpha;
     g->last.omega = omega;
@@ -1147,6 +1550,7 @@ extern "C" pv_status pv_local_frequency(pv_ctx *c, const pv_u128 *local, int64_t
         (rows > 0 && !local) || (cap > 0 && (!values || !freq)))
         return PV_EINVAL;
     HIPCHK(hipSetDevice(c->device));
+    BudgetScope scope(c);
     hipStream_t s = c->stream;
     const int n = (int)rows;
     long long npad = 1;
@@ -1186,6 +1590,8 @@ extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int
     const long long need = rows * K;
     if (out_len < need) return PV_EBUFSIZE;
     pv_ctx *c = g->ctx;
+    GraphUse use(g);
+    BudgetScope scope(c);
     PVCHK(prepare(g, false));
     PVCHK(c->ws.vout_own.ensure((size_t)std::max<long long>(need, 1) * 2));
     // k ranges wider than one pass's slots (16 per vertex, 8 per edge) are
@@ -1219,9 +1625,14 @@ extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int
 
 extern "C" pv_status pv_count_roots(pv_graph *g, const int32_t *roots, int32_t nroots, int32_t k_max,
                                     pv_u128 *counts, int32_t cap, int32_t *omega_out,
-                                    uint64_t *overflow_bits, pv_stats *stats) {
+                                    uint64_t *overflow_bits, int32_t local_kind, int32_t k_lo, int32_t k_hi,
+                                    pv_u128 *local_out, uint64_t *local_ovf, pv_stats *stats) {
     if (!g || nroots < 0 || (nroots > 0 && !roots) || cap < 0 || (cap > 0 && !counts))
         return PV_EINVAL;
+    if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
+    if (local_ovf) *local_ovf = 0;
+    GraphUse use(g);
+    BudgetScope scope(g->ctx);
     PVCHK(prepare(g, false));
     // out-degrees of the chosen roots, heavy first (host-side scheduling only)
     std::vector<int> od(g->n);
@@ -1232,8 +1643,10 @@ extern "C" pv_status pv_count_roots(pv_graph *g, const int32_t *roots, int32_t n
     }
     std::vector<int> rs;
     rs.reserve(nroots);
+    std::vector<uint8_t> seen(g->n, 0);
     for (int i = 0; i < nroots; i++) {
-        if (roots[i] < 0 || roots[i] >= g->n) return PV_EINVAL;
+        if (roots[i] < 0 || roots[i] >= g->n || seen[roots[i]]) return PV_EINVAL;
+        seen[roots[i]] = 1;
         rs.push_back(roots[i]);
     }
     std::stable_sort(rs.begin(), rs.end(), [&](int a, int b) { return od[a] > od[b]; });
@@ -1249,17 +1662,23 @@ extern "C" pv_status pv_count_roots(pv_graph *g, const int32_t *roots, int32_t n
     rq.kmax = k_max > 0 ? k_max : 0;
     rq.c0 = 0;
     rq.whole = false;
+    PVCHK(setup_local(g, local_kind, k_lo, k_hi, rq));
+    rq.vout = (uint64_t *)local_out;
     rq.order = dorder.p;
     rq.nheavy = nheavy;
     rq.nlight = (int)rs.size() - nheavy;  // roots with an empty N+(v) are single leaves
+    rq.size_n = (long long)rs.size();
+    rq.size_m = 0;
+    for (int v : rs) rq.size_m += od[v];
     pv_status st = run_sct(g, rq);
-    if (st == PV_OK) st = finish_counts(g, rq, counts, cap, omega_out, overflow_bits, stats, nullptr);
+    if (st == PV_OK) st = finish_counts(g, rq, counts, cap, omega_out, overflow_bits, stats, local_ovf);
     dorder.release();
     return st;
 }
 
 extern "C" pv_status pv_graph_edge_list(pv_graph *g, int32_t *u, int32_t *v) {
     if (!g || ((!u || !v) && g->nnz > 0)) return PV_EINVAL;
+    GraphUse use(g);
     HIPCHK(hipSetDevice(g->ctx->device));
     std::vector<int> rp((size_t)g->n + 1), col((size_t)std::max<long long>(g->nnz, 1));
     HIPCHK(hipMemcpyAsync(rp.data(), g->rp.p, sizeof(int) * rp.size(), hipMemcpyDeviceToHost,
@@ -1283,7 +1702,7 @@ extern "C" pv_status pv_count_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, i
                                     pv_u128 *counts, int32_t cap, int32_t *omega,
                                     uint64_t *overflow_bits, int32_t local_kind, int32_t k_lo,
                                     int32_t k_hi, pv_u128 *local_out, uint64_t *local_ovf,
-                                    pv_stats *stats) {
+                                    pv_status *status, pv_stats *stats) {
     if (!c || G < 0 || (G > 0 && (!gs || !counts)) || cap < 1) return PV_EINVAL;
     if (local_kind != PV_NONE && local_kind != PV_VERTEX) return PV_EINVAL;
     if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
@@ -1293,6 +1712,9 @@ extern "C" pv_status pv_count_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, i
         return PV_OK;
     }
     HIPCHK(hipSetDevice(c->device));
+    BudgetScope scope(c);
+    // the member graphs are in use until the pass ends
+    GraphUse use(gs, G);
     // the batch is counted as the disjoint union of its graphs
     std::vector<BatchPart> parts(G);
     long long N = 0, NNZ = 0;
@@ -1326,6 +1748,9 @@ extern "C" pv_status pv_count_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, i
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemcpy(u->rp.p + N, &nnz32, sizeof(int), hipMemcpyHostToDevice));
     PVCHK(prepare(u, true));
+    u->deg_key.clear();  // a new union
+    std::unique_ptr<TuneScope> tuned;
+    PVCHK(tune_scope_for(u, local_kind, k_lo, k_hi, k_max, tuned));
     CountReq rq;
     rq.kmax = k_max > 0 ? k_max : 0;
     PVCHK(setup_local(u, local_kind, k_lo, k_hi, rq));
@@ -1336,12 +1761,255 @@ extern "C" pv_status pv_count_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, i
     rq.nheavy = u->nheavy;
     rq.nlight = u->nnonzero - u->nheavy;
     PVCHK(run_sct(u, rq));
-    return finish_counts(u, rq, counts, cap, omega, overflow_bits, stats, local_ovf);
+    return finish_counts(u, rq, counts, cap, omega, overflow_bits, stats, local_ovf, status);
 }
 
 extern "C" pv_status pv_count_global_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, int32_t k_max,
                                            pv_u128 *counts, int32_t cap, int32_t *omega,
-                                           uint64_t *overflow_bits, pv_stats *stats) {
+                                           uint64_t *overflow_bits, pv_status *status, pv_stats *stats) {
     return pv_count_batch(c, G, gs, k_max, counts, cap, omega, overflow_bits, PV_NONE, 0, 0, nullptr,
-                          nullptr, stats);
+                          nullptr, status, stats);
+}
+
+// ------------------------------------------------------------- tuning
+// The settings that split the walk (dfs_max, dfs_budget, lane_max) change
+// neither the tree nor the counts, only how the work lands on the device.
+// pv_autotune times candidates on a graph and keeps the fastest under a key
+// made of the device, the kind of count and the graph's out-degree
+// histogram (powers of two, each count rounded to its power of two), so
+// graphs of the same shape share an entry.
+
+static std::string mode_key(int kind, int klo, int khi, int kmax) {
+    std::string m = kind == PV_VERTEX ? "v" : (kind == PV_EDGE ? "e" : "g");
+    if (kind != PV_NONE) m += std::to_string(khi - klo + 1);
+    if (kmax > 0) m += "t" + std::to_string(kmax);
+    return m;
+}
+
+// the out-degree histogram part of g's key (g oriented)
+static pv_status deg_key_of(pv_graph *g) {
+    if (!g->deg_key.empty()) return PV_OK;
+    pv_ctx *c = g->ctx;
+    DBuf<int> dh;
+    PVCHK(dh.ensure(PV_DEG_BUCKETS));
+    HIPCHK(hipMemsetAsync(dh.p, 0, PV_DEG_BUCKETS * sizeof(int), c->stream));
+    HIPCHK(pv_launch_deg_hist(g->n, g->odeg.p, dh.p, c->stream));
+    int h[PV_DEG_BUCKETS];
+    hipError_t e = hipMemcpyAsync(h, dh.p, sizeof h, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dh.release();
+    if (e != hipSuccess) {
+        set_err("deg_key_of", e);
+        return PV_EDEVICE;
+    }
+    std::string k = "h";
+    for (int b = 0; b < PV_DEG_BUCKETS; b++) {
+        const unsigned x = (unsigned)h[b];
+        k += std::to_string(x ? 32 - __builtin_clz(x) : 0);
+        if (b + 1 < PV_DEG_BUCKETS) k += ".";
+    }
+    g->deg_key = k;
+    return PV_OK;
+}
+
+static std::string full_key(const pv_graph *g, const std::string &mode) {
+    return g->ctx->arch + "|" + mode + "|" + g->deg_key;
+}
+
+// the tuned settings of a key for the duration of one call
+TuneScope::TuneScope(pv_ctx *c_, const std::string &key) : c(c_) {
+    auto it = c->tune.find(key);
+    if (it == c->tune.end()) return;
+    on = true;
+    dm = c->dfs_max;
+    db = c->dfs_budget;
+    lm = c->lane_max;
+    c->dfs_max = it->second.dfs_max;
+    c->dfs_budget = it->second.dfs_budget;
+    c->lane_max = it->second.lane_max;
+}
+
+TuneScope::~TuneScope() {
+    if (!on) return;
+    c->dfs_max = dm;
+    c->dfs_budget = db;
+    c->lane_max = lm;
+}
+
+static pv_status tune_scope_for(pv_graph *g, int kind, int klo, int khi, int kmax,
+                                std::unique_ptr<TuneScope> &scope) {
+    if (g->ctx->tune.empty()) return PV_OK;
+    PVCHK(deg_key_of(g));
+    scope.reset(new (std::nothrow) TuneScope(g->ctx, full_key(g, mode_key(kind, klo, khi, kmax))));
+    return PV_OK;
+}
+
+// numbers and strings after `"name":` inside one JSON object of the cache
+static bool json_num(const std::string &obj, const char *name, double &v) {
+    const std::string pat = std::string("\"") + name + "\"";
+    size_t i = obj.find(pat);
+    if (i == std::string::npos) return false;
+    i = obj.find(':', i + pat.size());
+    if (i == std::string::npos) return false;
+    char *end = nullptr;
+    v = strtod(obj.c_str() + i + 1, &end);
+    return end != obj.c_str() + i + 1;
+}
+
+static bool json_str(const std::string &obj, const char *name, std::string &v) {
+    const std::string pat = std::string("\"") + name + "\"";
+    size_t i = obj.find(pat);
+    if (i == std::string::npos) return false;
+    i = obj.find('"', obj.find(':', i + pat.size()));
+    if (i == std::string::npos) return false;
+    const size_t j = obj.find('"', i + 1);
+    if (j == std::string::npos) return false;
+    v = obj.substr(i + 1, j - i - 1);
+    return true;
+}
+
+static void tune_load(pv_ctx *c) {
+    std::ifstream f(c->tune_path);
+    if (!f) return;  // no cache yet: pv_autotune creates it
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string txt = ss.str();
+    size_t pos = txt.find("\"entries\"");
+    while (pos != std::string::npos) {
+        const size_t a = txt.find('{', pos + 1);
+        if (a == std::string::npos) break;
+        const size_t b = txt.find('}', a);
+        if (b == std::string::npos) break;
+        const std::string obj = txt.substr(a, b - a + 1);
+        std::string key;
+        double dm, db, lm, mb = 0, md = 0;
+        if (json_str(obj, "key", key) && json_num(obj, "dfs_max", dm) && json_num(obj, "dfs_budget", db) &&
+            json_num(obj, "lane_max", lm) && dm >= 1 && dm <= 64 && (db == 0 || (db >= 16 && db <= (1 << 20))) &&
+            lm >= 0 && lm <= PV_LANE_MAX) {
+            json_num(obj, "ms_best", mb);
+            json_num(obj, "ms_default", md);
+            TuneEntry e;
+            e.dfs_max = (int)dm;
+            e.dfs_budget = (int)db;
+            e.lane_max = (int)lm;
+            e.ms_best = (float)mb;
+            e.ms_default = (float)md;
+            c->tune[key] = e;
+        }
+        pos = b;
+    }
+}
+
+static pv_status tune_save(pv_ctx *c) {
+    if (c->tune_path.empty()) return PV_OK;
+    const std::string tmp = c->tune_path + ".tmp";
+    {
+        std::ofstream f(tmp);
+        if (!f) {
+            snprintf(g_last_error, sizeof g_last_error, "cannot write %s", tmp.c_str());
+            return PV_EINVAL;
+        }
+        f << "{\n  \"entries\": [\n";
+        size_t i = 0;
+        for (const auto &kv : c->tune) {
+            char line[256];
+            snprintf(line, sizeof line,
+                     "\"dfs_max\": %d, \"dfs_budget\": %d, \"lane_max\": %d, \"ms_best\": %.4f, \"ms_default\": %.4f",
+                     kv.second.dfs_max, kv.second.dfs_budget, kv.second.lane_max, kv.second.ms_best,
+                     kv.second.ms_default);
+            f << "    {\"key\": \"" << kv.first << "\", " << line << "}" << (++i < c->tune.size() ? "," : "")
+              << "\n";
+        }
+        f << "  ]\n}\n";
+    }
+    if (rename(tmp.c_str(), c->tune_path.c_str()) != 0) {
+        snprintf(g_last_error, sizeof g_last_error, "cannot replace %s", c->tune_path.c_str());
+        return PV_EINVAL;
+    }
+    return PV_OK;
+}
+
+extern "C" const char *pv_tune_key(pv_graph *g, int32_t local_kind, int32_t k_lo, int32_t k_hi) {
+    static thread_local std::string key;
+    key.clear();
+    if (!g) return "";
+    BudgetScope scope(g->ctx);
+    if (prepare(g, false) != PV_OK || deg_key_of(g) != PV_OK) return "";
+    key = full_key(g, mode_key(local_kind, k_lo, k_hi, 0));
+    return key.c_str();
+}
+
+extern "C" pv_status pv_autotune(pv_graph *g, int32_t local_kind, int32_t k_lo, int32_t k_hi,
+                                 pv_u128 *local_out, int32_t reps, pv_tune *out) {
+    if (!g || reps < 1 || (local_kind != PV_NONE && !local_out)) return PV_EINVAL;
+    pv_ctx *c = g->ctx;
+    {
+        GraphUse use(g);
+        BudgetScope scope(c);
+        PVCHK(prepare(g, false));
+        PVCHK(deg_key_of(g));
+    }
+    const std::string key = full_key(g, mode_key(local_kind, k_lo, k_hi, 0));
+    const int dm0 = c->dfs_max, db0 = c->dfs_budget, lm0 = c->lane_max;
+    std::vector<pv_u128> counts(PV_MAX_ALPHA + 2);
+    int trials = 0;
+    auto time_of = [&](int dm, int db, int lm, float &ms) -> pv_status {
+        c->dfs_max = dm;
+        c->dfs_budget = db;
+        c->lane_max = lm;
+        ms = 1e30f;
+        for (int r = 0; r < reps; r++) {
+            const auto t0 = std::chrono::steady_clock::now();
+            pv_status st = count_untuned(g, 0, 0, counts.data(), (int)counts.size(), nullptr, nullptr, local_kind,
+                                         k_lo, k_hi, local_out, nullptr, nullptr);
+            if (st != PV_OK && st != PV_EOVERFLOW) return st;
+            const float t = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            ms = std::min(ms, t);
+        }
+        trials++;
+        return PV_OK;
+    };
+    TuneEntry best;
+    best.dfs_max = dm0;
+    best.dfs_budget = db0;
+    best.lane_max = lm0;
+    pv_status st = time_of(dm0, db0, lm0, best.ms_default);
+    best.ms_best = best.ms_default;
+    // one setting at a time from the current best
+    static const int LANES[] = {0, 4, 6, 8};
+    static const int BUDGETS[] = {0, 1024, 2048, 4096, 8192, 16384};
+    static const int DMAX[] = {32, 48, 64};
+    for (int pass = 0; pass < 3 && st == PV_OK; pass++) {
+        const int *vals = pass == 0 ? LANES : (pass == 1 ? BUDGETS : DMAX);
+        const int nv = pass == 0 ? 4 : (pass == 1 ? 6 : 3);
+        for (int i = 0; i < nv && st == PV_OK; i++) {
+            TuneEntry e = best;
+            int &slot = pass == 0 ? e.lane_max : (pass == 1 ? e.dfs_budget : e.dfs_max);
+            if (slot == vals[i]) continue;
+            slot = vals[i];
+            float ms = 0.f;
+            st = time_of(e.dfs_max, e.dfs_budget, e.lane_max, ms);
+            if (st == PV_OK && ms < best.ms_best) {
+                best.dfs_max = e.dfs_max;
+                best.dfs_budget = e.dfs_budget;
+                best.lane_max = e.lane_max;
+                best.ms_best = ms;
+            }
+        }
+    }
+    c->dfs_max = dm0;
+    c->dfs_budget = db0;
+    c->lane_max = lm0;
+    if (st != PV_OK) return st;
+    c->tune[key] = best;
+    PVCHK(tune_save(c));
+    if (out) {
+        out->dfs_max = best.dfs_max;
+        out->dfs_budget = best.dfs_budget;
+        out->lane_max = best.lane_max;
+        out->ms_best = best.ms_best;
+        out->ms_default = best.ms_default;
+        out->trials = trials;
+    }
+    return PV_OK;
 }

@@ -14,7 +14,7 @@ struct DevInfo {
     int lds_per_cu;
 };
 
-// control block of the cooperative peel (zero-filled before a launch,
+// control block of the peel (zero-filled before a launch,
 // minv set to INT_MAX)
 struct PeelCtl {
     int cnt[3];          // frontier sizes, rotating by sub-round
@@ -72,6 +72,26 @@ struct CItem {
     uint32_t hp;
 };
 
+// Persistent walk: one launch takes every unit (roots, multi-word items,
+// compact node and frame items) from device queues until the whole tree is
+// walked.  The compact queue is split into PV_QSLICES slices, each with its
+// own claim and reservation counters on their own 128-byte lines (a wave
+// pushes to its home slice and claims from it first, then from the
+// others); the multi-word queue has one.  Queue storage is linear: slice s
+// of the compact queue is c_out[s * c_scap, (s + 1) * c_scap).
+#define PV_QSLICES 8
+struct alignas(128) PvLine {
+    unsigned long long v;
+};
+struct PersistCtl {
+    PvLine done;              // units finished (roots, items, unused slots), added by waves going idle
+    PvLine state;             // error bits: 1 no progress for 10 s, 2 a published slot never came
+    PvLine abort;             // set by the host: waves stop taking units
+    PvLine chead[PV_QSLICES];  // next slot to claim, per slice (int in .v)
+    PvLine ctail[PV_QSLICES];  // slots reserved by producers, per slice (may pass capacity)
+    PvLine mhead, mtail;       // the multi-word queue
+};
+
 struct LevelArgs {
     // graph
     int n;
@@ -114,13 +134,17 @@ struct LevelArgs {
     // outputs
     unsigned long long *hist;
     int hd;
-    unsigned long long *counters;  // nodes, leaves, work, -, work per unit kind [3]
+    unsigned long long *counters;  // PV_NCOUNTERS slots: nodes, leaves, work, -, work per unit kind [3],
+                                   // child work, leaf sum of h + p, leaf sum of p + 1
     int *flags;                    // bit0: buffer overflow
     // local counts
     uint64_t *vout;                // [n][kstride] (per vertex) or [m][kstride] (per edge) u128;
                                    // this pass writes columns 0..K-1
     int klo, K, kstride;
     const uint64_t *bin_pad;       // padded 64-bit binomials, rows tab_stride apart, see VertexSink
+    const uint64_t *bin_pad_hi;    // their high limbs (nullptr when every binomial used fits 64 bits)
+    const uint8_t *bin_bad;        // [bin_bn][bin_bn]: C(a, b) >= 2^128
+    int bin_bn;
     int tab_stride;
     int *lovf;
     // per-edge counts: edge ids and the universes' prefix-pair sums
@@ -139,6 +163,11 @@ struct LevelArgs {
     // for a single graph; hist then holds one hd*hd histogram per graph
     const int *vgraph;
     int *u_root;                   // [u_cap] root vertex of each universe (batch only)
+    // persistent walk (unit kind PV_UNITS_ALL); persist = 0: level by level
+    int persist;
+    PersistCtl *pctl;
+    int *cready, *mready;          // per queue slot: 0 not yet written, 1 written, 2 never written
+    int c_scap, m_cap;             // compact slots per slice; multi-word slots
 };
 
 
@@ -152,6 +181,11 @@ hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int 
 // roots by out-degree, largest first; bh: chunks * (PV_MAX_ALPHA + 1) ints
 hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *bh, int chunks,
                                 int *order, int *bounds, int light_max, hipStream_t s);
+// out-degree histogram in powers of two: bucket 0 holds d = 0, bucket b > 0
+// holds 2^(b-1) <= d < 2^b (last bucket: everything above); hist zeroed by
+// the caller
+#define PV_DEG_BUCKETS 16
+hipError_t pv_launch_deg_hist(int n, const int *odeg, int *hist, hipStream_t s);
 // chunks of the root ordering for n vertices
 static inline int pv_root_chunks(int n) {
     const int c = (n + 4095) / 4096;
@@ -163,6 +197,13 @@ static inline int pv_root_chunks(int n) {
 #define PV_UNITS_MW 0
 #define PV_UNITS_ITEMS 1
 #define PV_UNITS_LIGHT 2
+#define PV_UNITS_ALL 3   // the persistent walk: every kind from the device queues
+
+// slots of the level kernel's work counters
+#define PV_NCOUNTERS 12
+#define PV_CTR_CHILD 8
+#define PV_CTR_HP 9
+#define PV_CTR_PP 10
 // `a` is a device pointer to the launch arguments
 // local-count kinds of the level kernel: per vertex with u128 or u64 per-visit
 // accumulators, or per edge
@@ -211,11 +252,25 @@ hipError_t pv_launch_sink_roots(int n, const int *order, const int *bounds, unsi
                                 const int *vgraph, hipStream_t s);
 hipError_t pv_launch_binomials(int bn, uint64_t *tab128, uint8_t *bad, uint64_t *tab64, int *fits64,
                                hipStream_t s);
-hipError_t pv_launch_binom_pad(int bn, int ts, const uint64_t *tab128, uint64_t *pad, hipStream_t s);
+// pad: 2 (bn + 1) ts words, low limbs then high limbs (all ones where C >= 2^128)
+hipError_t pv_launch_binom_pad(int bn, int ts, const uint64_t *tab128, const uint8_t *bad, uint64_t *pad,
+                               hipStream_t s);
 hipError_t pv_launch_finalize(const unsigned long long *hist, int hd, const uint64_t *tab128,
                               const uint8_t *bad, int bn, int kcap, int kmax, int c0,
                               uint64_t *counts, uint64_t *ovf_words, int *omega, int graphs,
                               hipStream_t s);
+// counters[PV_CTR_HP] += sum over leaves of h + p, counters[PV_CTR_PP] +=
+// sum over leaves of p + 1, from graphs [hd][hd] leaf histograms
+hipError_t pv_launch_leaf_moments(const unsigned long long *hist, int hd, int graphs,
+                                  unsigned long long *counters, hipStream_t s);
+// peak microbenchmarks (PV_PEAK_BLOCKS workgroups of 256; sinks hold one
+// word per thread)
+#define PV_PEAK_BLOCKS 2048
+#define PV_PEAK_LDS_READS 15  // 64-bit LDS reads per thread and iteration
+hipError_t pv_launch_peak_copy(const void *src, void *dst, long long bytes, hipStream_t s);
+hipError_t pv_launch_peak_read(const void *src, long long bytes, unsigned *sink, hipStream_t s);
+hipError_t pv_launch_peak_lds(int iters, int zero, unsigned long long *sink, hipStream_t s);
+hipError_t pv_launch_peak_valu(int iters, unsigned seed, unsigned *sink, hipStream_t s);
 // batches: concatenate graphs into one disjoint union (device descriptors)
 struct BatchPart {
     const int *rp, *col;   // the part's own CSR (device)

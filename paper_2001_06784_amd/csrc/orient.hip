@@ -1194,3 +1194,24 @@ hipError_t pv_launch_concat(const BatchPart *parts, int G, int maxn, int *rp, in
     concat_kernel<<<std::min(G, 65535), 256, 0, s>>>(parts, G, rp, col, vgraph);
     return hipGetLastError();
 }
+
+// Out-degree histogram in powers of two (the graph part of a tuning key):
+// per-block counts in LDS, one atomic per nonzero bucket and block.
+__global__ void __launch_bounds__(256) deg_hist_kernel(int n, const int *__restrict__ odeg, int *__restrict__ hist) {
+    __shared__ int s_h[PV_DEG_BUCKETS];
+    if (threadIdx.x < PV_DEG_BUCKETS) s_h[threadIdx.x] = 0;
+    __syncthreads();
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long long)gridDim.x * blockDim.x) {
+        const unsigned d = (unsigned)odeg[v];
+        const int b = d ? min(32 - __builtin_clz(d), PV_DEG_BUCKETS - 1) : 0;
+        atomicAdd(&s_h[b], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < PV_DEG_BUCKETS && s_h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], s_h[threadIdx.x]);
+}
+
+hipError_t pv_launch_deg_hist(int n, const int *odeg, int *hist, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    deg_hist_kernel<<<grid_for(n, 256, 1024), 256, 0, s>>>(n, odeg, hist);
+    return hipGetLastError();
+}

@@ -138,14 +138,20 @@ struct VertexSink {
     uint64_t lo[KL > 0 ? KL : 1], hi[(KL > 0 && WIDE) ? KL : 1];
     // wave-uniform copies of the arguments
     const uint64_t *tab;
+    const uint64_t *tabh;    // high limbs of the table (nullptr: every binomial used fits 64 bits)
+    const uint8_t *bad;      // [bn][bn]: C(a, b) >= 2^128
+    bool wrapped;            // a 128-bit sum of this lane wrapped (with the wide table only)
     uint64_t *vout;
     uint64_t *utot;  // [u_cap][2][K]: what the hold / pivot vertices above a universe are owed
     const int *pool;
     int *lovf;
-    int klo, K, khi, ks, ts;
+    int klo, K, khi, ks, ts, bn;
 
     __device__ void init(const LevelArgs &a, uint64_t *, int) {
         tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
+        tabh = WIDE ? (const uint64_t *)uniform64((uint64_t)a.bin_pad_hi) : nullptr;
+        bad = (const uint8_t *)uniform64((uint64_t)a.bin_bad);
+        bn = uniformi(a.bin_bn);
         vout = (uint64_t *)uniform64((uint64_t)a.vout);
         utot = (uint64_t *)uniform64((uint64_t)a.utot);
         pool = (const int *)uniform64((uint64_t)a.pref_pool);
@@ -164,6 +170,7 @@ struct VertexSink {
             lo[i] = 0;
             if (WIDE) hi[i] = 0;
         }
+        wrapped = false;
     }
 
     __device__ __forceinline__ uint64_t hiw(int i) const { return WIDE ? hi[i] : 0ull; }
@@ -200,12 +207,48 @@ struct VertexSink {
         // keep the masks as opaque vector values: the AND/OR form then takes
         // the scalar binomials as direct operands (no per-slot moves/selects)
         asm volatile("" : "+v"(mH), "+v"(mP));
+        if (WIDE && tabh) {
+            // binomials beyond 64 bits: the high limbs from the second table
+            const long long hoff = tabh - tab;
+            u64x8 uH[NC], uP[NC];
+#pragma unroll
+            for (int c = 0; c < (KL + 7) / 8; c++) {
+                uH[c] = ldc64x8(rowH + hoff + 8 * c);
+                uP[c] = ldc64x8(rowP + hoff + 8 * c);
+            }
+#pragma unroll
+            for (int kk = 0; kk < KL; kk++) {
+                const uint64_t v = (vH[kk / 8][kk % 8] & mH) | (vP[kk / 8][kk % 8] & mP);
+                const uint64_t u = (uH[kk / 8][kk % 8] & mH) | (uP[kk / 8][kk % 8] & mP);
+                lo[kk] += v;
+                const uint64_t h0 = hi[kk], c = (lo[kk] < v) ? 1ull : 0ull;
+                hi[kk] = h0 + u + c;
+                if (kk < K) wrapped |= hi[kk] < h0 || (hi[kk] == h0 && (u | c) != 0);
+            }
+            // every C(a, b) with a <= 131 fits 128 bits; from p = 132 on a
+            // leaf may need one that does not (its counts then overflow)
+            if (p >= 132) overflow_check(h, p);
+            return;
+        }
 #pragma unroll
         for (int kk = 0; kk < KL; kk++) {
             const uint64_t v = (vH[kk / 8][kk % 8] & mH) | (vP[kk / 8][kk % 8] & mP);
             lo[kk] += v;
             if (WIDE) hi[kk] += (lo[kk] < v) ? 1ull : 0ull;
         }
+    }
+
+    // a leaf with p >= 132 pivots: does some k of the range need a binomial
+    // that reaches 2^128?  (C(p, k-h) for hold vertices, C(p-1, k-h-1) for
+    // pivot vertices; wave-uniform, rare)
+    __device__ void overflow_check(int h, int p) {
+        bool big = false;
+        for (int k = klo; k <= khi; k++) {
+            const int j = k - h;
+            if (j >= 0 && j <= p && p < bn) big |= bad[(long long)p * bn + j] != 0;
+            if (j >= 1 && j - 1 <= p - 1 && p - 1 < bn) big |= bad[(long long)(p - 1) * bn + j - 1] != 0;
+        }
+        if (big && lane_id() == 0) atomicOr(lovf, 1);
     }
 
     // lane tier: add x to slot kk
@@ -248,7 +291,7 @@ struct VertexSink {
     // a universe, the totals go to its accumulators (a final kernel adds them
     // to every vertex of its prefix once)
     __device__ void flush(int lane, int nm, int gid, int root, int2, int uni, const LevelArgs &) {
-        bool ovf = false;
+        bool ovf = WIDE && ballot64(wrapped && (lane < nm || lane >= 62)) != 0;
         if (lane < nm) {
             // the low-limb adds of all slots first, so that their latencies
             // overlap; then the (rare) carries and the high limbs
@@ -355,6 +398,9 @@ struct EdgeSink {
     uint64_t *vacc;   // scratch [64][2][K] u128: finished stays toward hold / pivot prefix vertices
     // wave-uniform copies of the arguments
     const uint64_t *tab;
+    const uint64_t *tabh;    // high limbs of the table (nullptr: every binomial used fits 64 bits)
+    const uint8_t *bad;      // [bn][bn]: C(a, b) >= 2^128
+    int bn;
     uint64_t *eout, *umem, *utot;
     const int *orow, *o2e;
     int *lovf, *flags;
@@ -364,6 +410,9 @@ struct EdgeSink {
     __device__ void init(const LevelArgs &a, uint64_t *lds_xch, int wave0) {
         xch = lds_xch;
         tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
+        tabh = (const uint64_t *)uniform64((uint64_t)a.bin_pad_hi);
+        bad = (const uint8_t *)uniform64((uint64_t)a.bin_bad);
+        bn = uniformi(a.bin_bn);
         eout = (uint64_t *)uniform64((uint64_t)a.vout);
         umem = (uint64_t *)uniform64((uint64_t)a.umem);
         utot = (uint64_t *)uniform64((uint64_t)a.utot);
@@ -441,6 +490,17 @@ struct EdgeSink {
         hi += (lo < v) ? 1ull : 0ull;
     }
 
+    // the same for a 128-bit x = (xl, xh); sets ovf if the sum wraps
+    __device__ __forceinline__ void add_at2(uint64_t &lo, uint64_t &hi, uint64_t xl, uint64_t xh, int kk,
+                                            int lane) {
+        const bool mine = lane == kk;
+        const uint64_t v = mine ? xl : 0ull, u = mine ? xh : 0ull;
+        lo += v;
+        const uint64_t h0 = hi, c = (lo < v) ? 1ull : 0ull;
+        hi = h0 + u + c;
+        ovf |= hi < h0 || (hi == h0 && (u | c) != 0);
+    }
+
     __device__ __forceinline__ void leaf(int h, int p, uint64_t, uint64_t, int lane, const LevelArgs &) {
         if (h > khi || h + p < klo) return;
         // rows of C(p, .), C(p-1, .), C(p-2, .) at column k - h, k - h - 1,
@@ -450,6 +510,31 @@ struct EdgeSink {
         const uint64_t *rowHP = tab + p * ts + (klo - h + 15);
         const uint64_t *rowPP = tab + max(p - 1, 0) * ts + (klo - h + 14);
         const u64x8 xHH = ldc64x8(rowHH), xHP = ldc64x8(rowHP), xPP = ldc64x8(rowPP);
+        if (tabh) {
+            // binomials beyond 64 bits: the high limbs from the second table
+            const long long hoff = tabh - tab;
+            const u64x8 yHH = ldc64x8(rowHH + hoff), yHP = ldc64x8(rowHP + hoff), yPP = ldc64x8(rowPP + hoff);
+#pragma unroll
+            for (int kk = 0; kk < KL; kk++) {
+                if (kk < K) {
+                    add_at2(t0l, t0h, xHH[kk], yHH[kk], kk, lane);
+                    add_at2(t1l, t1h, xHP[kk], yHP[kk], kk, lane);
+                    add_at2(t2l, t2h, xPP[kk], yPP[kk], kk, lane);
+                }
+            }
+            // from p = 132 on a leaf may need a binomial of 2^128 or more
+            if (p >= 132) {
+                bool big = false;
+                for (int k = klo; k <= khi; k++) {
+                    for (int t = 0; t < 3; t++) {  // C(p - t, k - h - t)
+                        const int r = p - t, j = k - h - t;
+                        if (r >= 0 && j >= 0 && j <= r && r < bn) big |= bad[(long long)r * bn + j] != 0;
+                    }
+                }
+                if (big && lane == 0) atomicOr(lovf, 1);
+            }
+            return;
+        }
 #pragma unroll
         for (int kk = 0; kk < KL; kk++) {
             if (kk < K) {
@@ -562,10 +647,14 @@ struct SinkOf<KL, PV_LK_EDGE> {
     using T = EdgeSink<KL>;
 };
 
-// Work counters of a wave: SCT nodes visited, and the algorithmic pivot
-// work sum over nodes of |S| * ceil(|S|/64) (64-bit AND+popcount pairs).
+// Work counters of a wave: SCT nodes visited; pivot work, the sum over
+// nodes of |S| * ceil(|S|/64) (64-bit AND+popcount pairs); and the extra
+// words of multi-word children, the sum over nodes with |S| > 64 of
+// (children) * (ceil(|S|/64) - 1).  Every other child is formed with one
+// word operation, so the child work, the sum over internal nodes of
+// (children) * ceil(|S|/64), is (nodes - roots) + extra.
 struct Ctr {
-    unsigned long long nodes, work;
+    unsigned long long nodes, work, child;
 };
 
 template <int KL, int LK>
@@ -814,6 +903,113 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
     }
 }
 
+// ------------------------------------------------ work queues
+// Units handed from one wave to others: compact node and frame items, and
+// multi-word items.  Level by level (persist = 0) a producer appends to the
+// next level's array and the kernel boundary makes the items visible.  In
+// the persistent walk the compact queue is split into PV_QSLICES slices
+// (a wave pushes to its home slice, so the reservation atomics of different
+// waves spread over eight cache lines), every slot has a flag that the
+// producer sets after its item is written and released, and consumers claim
+// slots with a compare-and-swap on the slice's head.
+
+__device__ __forceinline__ int home_slice() {
+    return (int)(((blockIdx.x * blockDim.x + threadIdx.x) >> 6) % PV_QSLICES);
+}
+
+__device__ __forceinline__ int ld_agent(const unsigned long long *p) {
+    return (int)(uint32_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Reserve n consecutive slots for this wave's items in the queue whose
+// reservation counter is *tail (capacity cap; in the persistent walk rdy
+// are its slot flags, base its first slot).  Returns the first slot (an
+// index into the item array) or -1 when they do not fit: the overflow flag
+// is set, and the host walks the tree again with larger buffers.  Reserved
+// slots inside the array are then marked never-written (a consumer skips
+// them) and those past its end count as done at once, so the walk still
+// ends.  Wave-uniform; every lane of the wave takes part.
+__device__ int reserve_slots(const LevelArgs &a, int *tail, int *rdy, int base, int cap, int n, int lane) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(tail, n);
+    t = bcast0(t);
+    if (t + n <= cap) return base + t;
+    if (a.persist) {
+        for (int i = t + lane; i < min(t + n, cap); i += 64)
+            __hip_atomic_store(&rdy[base + i], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0)
+            atomicAdd(&a.pctl->done.v, (unsigned long long)(t + n - max(t, cap)));
+    }
+    if (lane == 0) atomicOr(a.flags, 1);
+    return -1;
+}
+
+__device__ __forceinline__ int reserve_items(const LevelArgs &a, int n, int lane) {
+    if (!a.persist) return reserve_slots(a, a.c_out_n, nullptr, 0, a.c_cap, n, lane);
+    const int s = home_slice();
+    return reserve_slots(a, (int *)&a.pctl->ctail[s].v, a.cready, s * a.c_scap, a.c_scap, n, lane);
+}
+
+__device__ __forceinline__ int reserve_mw_items(const LevelArgs &a, int n, int lane) {
+    if (!a.persist) return reserve_slots(a, a.mw_out_n, nullptr, 0, a.mw_cap, n, lane);
+    return reserve_slots(a, (int *)&a.pctl->mtail.v, a.mready, 0, a.m_cap, n, lane);
+}
+
+// The items of slots [first, first + n) are written: release them (a fence
+// over all of this wave's stores), then set their flags.  Every lane of the
+// wave takes part.
+__device__ __forceinline__ void publish_slots(const LevelArgs &a, int *rdy, int first, int n, int lane) {
+    if (!a.persist) return;
+    __threadfence();
+    for (int i = lane; i < n; i += 64)
+        __hip_atomic_store(&rdy[first + i], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Claim one slot of a queue (head/tail lines of nsl slices of cap slots,
+// slice s0 first): its index into the item array, or -1 if every slice is
+// drained for now.  Wave-uniform.
+__device__ int claim_slot(PvLine *head, PvLine *tail, int nsl, int cap, int s0, int lane) {
+    int got = -1;
+    if (lane == 0) {
+        for (int i = 0; i < nsl && got < 0; i++) {
+            const int sl = (s0 + i) % nsl;
+            int h = ld_agent(&head[sl].v);
+            const int t = min(ld_agent(&tail[sl].v), cap);
+            while (h < t) {
+                const int prev = atomicCAS((int *)&head[sl].v, h, h + 1);
+                if (prev == h) {
+                    got = sl * cap + h;
+                    break;
+                }
+                h = prev;
+            }
+        }
+    }
+    return bcast0(got);
+}
+
+// Wait until the producer of a claimed slot has published it: 1 written,
+// 2 never written (its reservation did not fit); 0 after a bounded wait
+// (error bit 2 set).  The acquire fence makes the item's words visible to
+// every lane.
+__device__ int wait_slot(const LevelArgs &a, const int *rdy, int lane) {
+    int r = 0;
+    if (lane == 0) {
+        for (uint32_t spins = 0;; spins++) {
+            r = __hip_atomic_load(rdy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (r) break;
+            if (spins > (1u << 22)) {
+                atomicOr((int *)&a.pctl->state.v, 2);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    r = bcast0(r);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return r;
+}
+
 // ------------------------------------------------------ compact-tier DFS
 // Walk the whole subtree of node (S, H, P, h, p) of a compact universe
 // whose row for member `lane` is A.  Depth first, stack in lane-indexed
@@ -990,13 +1186,8 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                 if (uni < 0) break;  // buffers full: the host reruns with larger ones
             }
             const int total = depth + 1;
-            int slot = 0;
-            if (lane == 0) slot = atomicAdd(a.c_out_n, total);
-            slot = bcast0(slot);
-            if (slot + total > a.c_cap) {
-                if (lane == 0) atomicOr(a.flags, 1);
-                break;
-            }
+            const int slot = reserve_items(a, total, lane);
+            if (slot < 0) break;
             CItem it;
             if (lane == 0) {
                 it.S = S;
@@ -1014,11 +1205,13 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                 it.hp = stM;
                 a.c_out[slot + 1 + lane] = it;
             }
+            publish_slots(a, a.cready, slot, total, lane);
             break;
         }
     }
     if constexpr (LANE) {
-        if (qn > 0) lane_walk<KL, LOCAL>(A, qS, qmH, qmP, qhp, qn, lane, hlim, gs, vs, nodes, work, nleaves);
+        if (qn > 0)
+            lane_walk<KL, LOCAL>(A, qS, qmH, qmP, qhp, qn, lane, hlim, gs, vs, nodes, work, nleaves);
     }
     if (LOCAL) vs.leave(H | P, H, P, lane, gid);
     ct.nodes += nodes;
@@ -1093,20 +1286,19 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
             // hold child of member v (v in R, increasing): N(S,v) minus the
             // earlier non-neighbours; lane v builds its own child
             const int nR = __popcll(R);
-            int slot = 0;
-            if (lane == 0) slot = atomicAdd(a.c_out_n, nR);
-            slot = bcast0(slot);
-            if (slot + nR > a.c_cap) {
-                if (lane == 0) atomicOr(a.flags, 1);
-            } else if ((R >> lane) & 1) {
-                const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-                CItem it;
-                it.S = A & S & ~(R & below);
-                it.H = H | (1ull << lane);
-                it.P = P;
-                it.uni = (uint32_t)uni;
-                it.hp = (uint32_t)(h + 1) | ((uint32_t)p << 16);
-                a.c_out[slot + __popcll(R & below)] = it;
+            const int slot = reserve_items(a, nR, lane);
+            if (slot >= 0) {
+                if ((R >> lane) & 1) {
+                    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                    CItem it;
+                    it.S = A & S & ~(R & below);
+                    it.H = H | (1ull << lane);
+                    it.P = P;
+                    it.uni = (uint32_t)uni;
+                    it.hp = (uint32_t)(h + 1) | ((uint32_t)p << 16);
+                    a.c_out[slot + __popcll(R & below)] = it;
+                }
+                publish_slots(a, a.cready, slot, nR, lane);
             }
         }
         S &= Ap;
@@ -1293,17 +1485,18 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
         const int pw = piv >> 6;
         const uint64_t pb = (lane == pw) ? (1ull << (piv & 63)) : 0ull;
         const uint64_t Ap = wl ? rows[(long long)lane * dpad + piv] : 0ull;
+        {
+            // the pivot child and the hold children are formed word by word
+            const bool holds = pc + 1 != s && !(a.kmax > 0 && h + 1 > a.kmax);
+            ct.child += (unsigned long long)(holds ? s - pc : 1) * (unsigned long long)((s + 63) / 64 - 1);
+        }
         if (pc + 1 != s && !(a.kmax > 0 && h + 1 > a.kmax)) {
             // hold children, increasing id, each N(S,v) minus earlier ones
             uint64_t Rw = Sw & ~Ap & ~pb;
             uint64_t Scur = Sw;
             const int nR = (int)wave_add_u32(wl ? (uint32_t)__popcll(Rw) : 0u);
-            int slot = 0;
-            if (lane == 0) slot = atomicAdd(a.mw_out_n, nR);
-            slot = bcast0(slot);
-            if (slot + nR > a.mw_cap) {
-                if (lane == 0) atomicOr(a.flags, 1);
-            } else {
+            const int slot = reserve_mw_items(a, nR, lane);
+            if (slot >= 0) {
                 for (int i = 0; i < nR; i++) {
                     const uint64_t nzw = ballot64(wl && Rw != 0);
                     const int w0 = __builtin_ctzll(nzw);
@@ -1321,6 +1514,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
                     Scur &= ~vb;
                     Rw &= ~vb;
                 }
+                publish_slots(a, a.mready, slot, nR, lane);
             }
         }
         // continue with the pivot child N(S, piv)
@@ -1454,6 +1648,8 @@ struct Claim {
         const int t = n0 + (c - nch);
         return t < n ? t : -1;
     }
+    // the next call returns a unit of the chunk in hand without an atomic
+    __device__ __forceinline__ bool mid_chunk(int n0, int nch) const { return idx >= 0 && idx + nch < n0; }
 };
 
 // The per-vertex kernels with 64-bit visit sums (the lane tier's member
@@ -1464,6 +1660,8 @@ struct Claim {
 template <int KL, int LK>
 struct LevelShape {
     static constexpr bool V64 = KL == 8 && LK == PV_LK_VERTEX64;
+    // (the persistent walk keeps the budget of the compact-item kernel, whose
+    // units are the bulk of its work)
     static constexpr int waves_per_simd = V64 ? 4 : 3;
     static constexpr int lds_h = V64 ? 16 : PV_LDS_H;
 };
@@ -1492,10 +1690,13 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
         wave_sync();
     }
     Ctr ct;
-    ct.nodes = ct.work = 0;
-    int *cursor = a.next + MODE;
-    const int claim_n0 = uniformi(a.n0[MODE]), claim_nch = uniformi(a.nch[MODE]);
+    ct.nodes = ct.work = ct.child = 0;
+    constexpr int CK = MODE == PV_UNITS_ALL ? PV_UNITS_LIGHT : MODE;  // the claim cursor of a static range
+    int *cursor = a.next + CK;
+    const int claim_n0 = uniformi(a.n0[CK]), claim_nch = uniformi(a.nch[CK]);
     Claim claim;
+    // persistent walk: pivot work per unit kind
+    unsigned long long wk[3] = {0ull, 0ull, 0ull};
 
     if constexpr (MODE == PV_UNITS_MW) {
         __shared__ int s_memb[WAVES_PER_BLOCK][64];
@@ -1559,6 +1760,182 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
                             gid, -1, pref, lane, a, gs, vs, ct, fr, it.hp);
             if (LOCAL) vs.flush(lane, nm, gid, -1, pref, u, a);
         }
+    } else if constexpr (MODE == PV_UNITS_ALL) {
+        // The persistent walk: units in order of preference -- multi-word
+        // items, heavy roots, compact items, light roots -- until every unit
+        // is done.  A wave counts the units it finished and adds them to the
+        // shared count when it finds nothing to take; the walk is over once
+        // that count equals the roots plus every reserved queue slot (read in
+        // that order: a unit's pushes precede its count, so the sum cannot
+        // meet the count while work is left).
+        __shared__ int s_memb[WAVES_PER_BLOCK][64];
+        __shared__ int s_vl[WAVES_PER_BLOCK][64];
+        __shared__ int s_pre[WAVES_PER_BLOCK][64];
+        __shared__ unsigned long long s_A[WAVES_PER_BLOCK][64];
+        int *etab_w = EDGE ? a.weid + (long long)(blockIdx.x * WAVES_PER_BLOCK + wv) * 4096 : nullptr;
+        PersistCtl *pc = (PersistCtl *)uniform64((uint64_t)a.pctl);
+        const int home = home_slice();
+        const int nheavy = uniformi(a.nheavy), nlight = uniformi(a.nlight);
+        const int c_scap = uniformi(a.c_scap), m_cap = uniformi(a.m_cap);
+        const unsigned long long nroots = (unsigned long long)nheavy + (unsigned long long)nlight;
+        bool heavy_left = nheavy > 0, light_left = nlight > 0;
+        uint32_t my_done = 0, since_check = 0;
+        unsigned long long seen_done = ~0ull;
+        uint64_t t_seen = 0;
+        for (;;) {
+            // abort or error: checked every 16 units and whenever idle
+            if (++since_check >= 16) {
+                since_check = 0;
+                if (bcast0(ld_agent(&pc->state.v) | ld_agent(&pc->abort.v))) break;
+            }
+            const unsigned long long w0 = ct.work;
+            int kind = -1;
+            if (light_left && claim.mid_chunk(claim_n0, claim_nch)) {
+                kind = PV_UNITS_LIGHT;
+            } else {
+                // multi-word items, then heavy roots
+                int slot = claim_slot(&pc->mhead, &pc->mtail, 1, m_cap, 0, lane);
+                int hu = -1;
+                if (slot < 0 && heavy_left) {
+                    int b = 0;
+                    if (lane == 0) b = atomicAdd(a.next + PV_UNITS_MW, 1);
+                    b = bcast0(b);
+                    if (b < nheavy) hu = b;
+                    else heavy_left = false;
+                }
+                if (slot >= 0 || hu >= 0) {
+                    kind = PV_UNITS_MW;
+                    int h = 1, p = 0;
+                    uint64_t Sw = 0, Hw = 0, Pw = 0;
+                    bool skip = false;
+                    if (slot >= 0) {
+                        const int r = wait_slot(a, a.mready + slot, lane);
+                        if (r != 1) {
+                            skip = true;
+                        } else {
+                            const uint64_t *it = a.mw_out + (long long)slot * a.mw_stride;
+                            const bool wl = lane < a.W;
+                            Sw = wl ? it[lane] : 0ull;
+                            Hw = wl ? it[a.W + lane] : 0ull;
+                            Pw = wl ? it[2 * a.W + lane] : 0ull;
+                            const uint64_t meta = it[3 * a.W];
+                            hu = uniformi((int)(uint32_t)meta);
+                            const uint32_t hp = uniform32((uint32_t)(meta >> 32));
+                            h = (int)(hp & 0xFFFFu);
+                            p = (int)(hp >> 16);
+                        }
+                    } else {
+                        const int v = a.order[a.heavy_base + hu];
+                        gather_heavy(hu, v, lane, a);
+                        const int d = a.orow[v + 1] - a.orow[v];
+                        if (lane < a.W) {
+                            const int cnt = min(max(d - lane * 64, 0), 64);
+                            Sw = (cnt == 64) ? ~0ull : ((1ull << cnt) - 1);
+                        }
+                    }
+                    if (!skip) {
+                        gs.set_vertex(a.order[a.heavy_base + hu]);
+                        CState cs;
+                        if (mw_run<KL, LK>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs)) {
+                            if (EDGE) vs.set_table(a.ueid + (long long)cs.uni * 4096);
+                            compact_run<KL, LK>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
+                                                cs.pref, lane, a, gs, vs, ct);
+                            if (LOCAL) vs.flush(lane, cs.nm, cs.gid, cs.root, cs.pref, cs.uni, a);
+                        }
+                    }
+                } else {
+                    // compact node and frame items
+                    slot = claim_slot(pc->chead, pc->ctail, PV_QSLICES, c_scap, home, lane);
+                    if (slot >= 0) {
+                        kind = PV_UNITS_ITEMS;
+                        if (wait_slot(a, a.cready + slot, lane) == 1) {
+                            const CItem it = a.c_out[slot];
+                            const uint32_t uw = uniform32(it.uni);
+                            const int u = (int)(uw & 0x7fffffffu);
+                            const bool fr = (uw >> 31) != 0;
+                            const uint64_t A = a.u_rows[(long long)u * 64 + lane];
+                            if (a.vgraph) gs.set_vertex(a.u_root[u]);
+                            int gid = -1;
+                            int2 pref = make_int2(0, 0);
+                            if (LOCAL) {
+                                gid = a.u_gid[(long long)u * 64 + lane];
+                                pref = a.u_pref[u];
+                            }
+                            const int nm = (int)wave_add_u32(gid >= 0 ? 1u : 0u);
+                            if (EDGE) vs.set_table(a.ueid + (long long)u * 4096);
+                            compact_run<KL, LK>(A, it.S, it.H, it.P, (int)(it.hp & 0xFFFFu), (int)(it.hp >> 16), u,
+                                                nm, gid, -1, pref, lane, a, gs, vs, ct, fr, it.hp);
+                            if (LOCAL) vs.flush(lane, nm, gid, -1, pref, u, a);
+                        }
+                    } else if (light_left) {
+                        kind = PV_UNITS_LIGHT;
+                    }
+                }
+            }
+            if (kind == PV_UNITS_LIGHT) {
+                const int idx = claim.next(cursor, nlight, claim_n0, claim_nch, lane);
+                if (idx < 0) {
+                    light_left = false;
+                    kind = -1;
+                } else {
+                    const int v = a.order[a.light_base + idx];
+                    gs.set_vertex(v);
+                    if (EDGE) vs.set_table(etab_w);
+                    int d, gid;
+                    const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_A[wv], d, gid, etab_w);
+                    int uni = -1;
+                    int2 pref = make_int2(0, 0);
+                    bool ok = true;
+                    if (d > a.dfs_max) {
+                        uni = make_universe<KL, LK>(A, d, gid, lane, a, v, -1, 0ull, 0ull, nullptr, 0, pref, etab_w);
+                        ok = uni >= 0;  // buffers full: the host walks again with larger ones
+                    }
+                    if (ok) {
+                        const int root = (uni < 0) ? v : -1;
+                        compact_run<KL, LK, false>(A, (d == 64) ? ~0ull : ((1ull << d) - 1), 0ull, 0ull, 1, 0, uni, d,
+                                                   gid, root, pref, lane, a, gs, vs, ct);
+                        if (LOCAL) vs.flush(lane, d, gid, root, pref, uni, a);
+                    }
+                }
+            }
+            if (kind >= 0) {
+                my_done++;
+                wk[kind] += ct.work - w0;
+                // hand the count in now and then, so that idle waves see progress
+                if (my_done >= 256) {
+                    if (lane == 0) atomicAdd(&pc->done.v, (unsigned long long)my_done);
+                    my_done = 0;
+                }
+                continue;
+            }
+            // nothing to take now: hand in the finished count, then see
+            // whether the walk is over
+            if (lane == 0 && my_done) atomicAdd(&pc->done.v, (unsigned long long)my_done);
+            my_done = 0;
+            unsigned long long D = 0, T = 0;
+            int bad = 0;
+            if (lane == 0) {
+                D = __hip_atomic_load(&pc->done.v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                T = nroots + (unsigned long long)(uint32_t)ld_agent(&pc->mtail.v);
+                for (int sl = 0; sl < PV_QSLICES; sl++) T += (unsigned long long)(uint32_t)ld_agent(&pc->ctail[sl].v);
+                bad = ld_agent(&pc->state.v) | ld_agent(&pc->abort.v);
+            }
+            D = uniform64(D);
+            T = uniform64(T);
+            if (D >= T || bcast0(bad)) break;
+            // no unit finished or queued anywhere for 10 s (s_memrealtime
+            // counts at 100 MHz; a unit walks at most dfs_budget nodes): give
+            // up with an error instead of waiting for ever
+            const uint64_t now = __builtin_amdgcn_s_memrealtime();
+            if (D + (T << 32) != seen_done) {
+                seen_done = D + (T << 32);
+                t_seen = now;
+            } else if (now - t_seen > 1000000000ull) {
+                if (lane == 0) atomicOr((int *)&pc->state.v, 1);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(32);
+        }
     } else {
         __shared__ int s_vl[WAVES_PER_BLOCK][64];
         __shared__ int s_pre[WAVES_PER_BLOCK][64];
@@ -1600,7 +1977,13 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
         atomicAdd(&a.counters[0], ct.nodes);
         atomicAdd(&a.counters[1], gs.leaves);
         atomicAdd(&a.counters[2], ct.work);
-        atomicAdd(&a.counters[4 + MODE], ct.work);
+        if constexpr (MODE == PV_UNITS_ALL) {
+            for (int k = 0; k < 3; k++)
+                if (wk[k]) atomicAdd(&a.counters[4 + k], wk[k]);
+        } else {
+            atomicAdd(&a.counters[4 + MODE], ct.work);
+        }
+        if (ct.child) atomicAdd(&a.counters[PV_CTR_CHILD], ct.child);
     }
 }
 
@@ -1857,6 +2240,38 @@ __global__ void sct_sink_roots_kernel(int n, const int *__restrict__ order, cons
     }
 }
 
+// Leaf moments of the (h, p) histograms: each thread a strided share of the
+// cells, then a block reduction and one atomic per block and sum.
+__global__ void __launch_bounds__(256) leaf_moments_kernel(const unsigned long long *__restrict__ hist,
+                                                           long long cells, int hd,
+                                                           unsigned long long *counters) {
+    __shared__ unsigned long long s_hp[256], s_pp[256];
+    unsigned long long hp = 0, pp = 0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < cells;
+         i += (long long)gridDim.x * blockDim.x) {
+        const unsigned long long L = hist[i];
+        if (!L) continue;
+        const int c = (int)(i % ((long long)hd * hd));
+        const int h = c / hd, p = c % hd;
+        hp += L * (unsigned long long)(h + p);
+        pp += L * (unsigned long long)(p + 1);
+    }
+    s_hp[threadIdx.x] = hp;
+    s_pp[threadIdx.x] = pp;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_hp[threadIdx.x] += s_hp[threadIdx.x + w];
+            s_pp[threadIdx.x] += s_pp[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (s_hp[0]) atomicAdd(&counters[PV_CTR_HP], s_hp[0]);
+        if (s_pp[0]) atomicAdd(&counters[PV_CTR_PP], s_pp[0]);
+    }
+}
+
 // ============================================================== finalize
 // Exact binomials (Pascal's rule) in u128 with a flag for values >= 2^128,
 // and a u64 copy of the first 16 columns for the per-vertex path.
@@ -1896,11 +2311,18 @@ __global__ void binom_kernel(int bn, uint64_t *tab, uint8_t *bad, uint64_t *tab6
 
 // Padded 64-bit table for the per-vertex path (see VertexSink): row a =
 // -1..bn-1, column j = -16..ts-17 at [(a + 1) * ts + j + 16].
-__global__ void binom_pad_kernel(int bn, int ts, const uint64_t *__restrict__ tab, uint64_t *__restrict__ pad) {
+__global__ void binom_pad_kernel(int bn, int ts, const uint64_t *__restrict__ tab, const uint8_t *__restrict__ bad,
+                                 uint64_t *__restrict__ pad) {
+    // low limbs at pad[0, total), high limbs at pad[total, 2 total); an
+    // entry that reaches 2^128 holds all ones in both (the sinks flag it)
     const int total = (bn + 1) * ts;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         const int a = i / ts - 1, j = i % ts - 16;
-        pad[i] = (a >= 0 && j >= 0 && j <= a) ? tab[2 * ((long long)a * bn + j)] : 0ull;
+        const bool in = a >= 0 && j >= 0 && j <= a;
+        const long long t = (long long)a * bn + j;
+        const bool b = in && bad[t];
+        pad[i] = b ? ~0ull : (in ? tab[2 * t] : 0ull);
+        pad[total + i] = b ? ~0ull : (in ? tab[2 * t + 1] : 0ull);
     }
 }
 
@@ -2098,7 +2520,8 @@ static hipError_t launch_mode(const LevelArgs *a, int mode, int blocks, hipStrea
     dim3 g(blocks), b(64 * WAVES_PER_BLOCK);
     if (mode == PV_UNITS_MW) sct_level_kernel<KL, PV_UNITS_MW, LK><<<g, b, 0, s>>>(a);
     else if (mode == PV_UNITS_ITEMS) sct_level_kernel<KL, PV_UNITS_ITEMS, LK><<<g, b, 0, s>>>(a);
-    else sct_level_kernel<KL, PV_UNITS_LIGHT, LK><<<g, b, 0, s>>>(a);
+    else if (mode == PV_UNITS_LIGHT) sct_level_kernel<KL, PV_UNITS_LIGHT, LK><<<g, b, 0, s>>>(a);
+    else sct_level_kernel<KL, PV_UNITS_ALL, LK><<<g, b, 0, s>>>(a);
     return hipGetLastError();
 }
 
@@ -2123,8 +2546,11 @@ static int blocks_per_cu_kl(int mode) {
     else if (mode == PV_UNITS_ITEMS)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_ITEMS, LK>,
                                                          64 * WAVES_PER_BLOCK, 0);
-    else
+    else if (mode == PV_UNITS_LIGHT)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_LIGHT, LK>,
+                                                         64 * WAVES_PER_BLOCK, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sct_level_kernel<KL, PV_UNITS_ALL, LK>,
                                                          64 * WAVES_PER_BLOCK, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
@@ -2172,8 +2598,9 @@ hipError_t pv_launch_binomials(int bn, uint64_t *tab128, uint8_t *bad, uint64_t 
     return hipGetLastError();
 }
 
-hipError_t pv_launch_binom_pad(int bn, int ts, const uint64_t *tab128, uint64_t *pad, hipStream_t s) {
-    binom_pad_kernel<<<64, 256, 0, s>>>(bn, ts, tab128, pad);
+hipError_t pv_launch_binom_pad(int bn, int ts, const uint64_t *tab128, const uint8_t *bad, uint64_t *pad,
+                               hipStream_t s) {
+    binom_pad_kernel<<<64, 256, 0, s>>>(bn, ts, tab128, bad, pad);
     return hipGetLastError();
 }
 
@@ -2183,5 +2610,13 @@ hipError_t pv_launch_finalize(const unsigned long long *hist, int hd, const uint
                               hipStream_t s) {
     finalize_kernel<<<dim3(kcap, graphs), 256, 0, s>>>(hist, hd, tab128, bad, bn, kmax, c0, counts,
                                                       ovf_words, omega);
+    return hipGetLastError();
+}
+
+hipError_t pv_launch_leaf_moments(const unsigned long long *hist, int hd, int graphs,
+                                  unsigned long long *counters, hipStream_t s) {
+    const long long cells = (long long)graphs * hd * hd;
+    const long long b = (cells + 4095) / 4096;
+    leaf_moments_kernel<<<(int)(b < 1 ? 1 : (b > 1024 ? 1024 : b)), 256, 0, s>>>(hist, cells, hd, counters);
     return hipGetLastError();
 }

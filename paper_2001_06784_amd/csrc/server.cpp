@@ -9,6 +9,15 @@
 // bytes); a request names its graph by key and brings the host CSR for the
 // case that it is not resident.
 //
+// Device memory: the resident graphs are loaded through one loader context;
+// idle graphs are evicted (least recently used first) beyond cache_bytes,
+// and the loader's hard limit adds what the running passes may pin.  A pass admits requests while their
+// estimated footprint (union copy, orientation, SCT workspace, per-vertex
+// output rows) stays within batch_bytes; the worker context's hard limit is
+// twice that plus 64 MiB for its tables.  A pass that still runs out of it
+// is split in halves and retried, down to single requests, which then fail
+// with PV_ENOMEM.
+//
 // Built on the public C ABI only (pivoter.h) plus HIP for the per-worker
 // output buffers.
 #include <hip/hip_runtime.h>
@@ -51,15 +60,23 @@ struct CacheEntry {
 };
 
 // device bytes of a graph's CSR
-size_t csr_bytes(long long n, long long nnz) { return 4 * (size_t)(n + 1) + 4 * (size_t)nnz; }
+// (row pointers, columns, and the handle's small block of device counters)
+size_t csr_bytes(long long n, long long nnz) { return 4 * (size_t)(n + 1) + 4 * (size_t)std::max(nnz, 1ll) + 64; }
 
-// HBM a request occupies during a pass: its union copy and orientation
-// (CSR twice, oriented CSR, peel key, order, edge-id map bound) and its
+// HBM a request occupies during a pass: its share of the union copy and
+// orientation (CSR twice, oriented CSR, peel key, order, degrees and
+// frontiers), of the SCT workspace (the walk's first capacities: 2n + m/8
+// work items of 32 bytes, double-buffered; n/2 universes of 64 rows, with
+// member ids and visit totals for local counts; 4n prefix entries), and its
 // per-vertex output rows
 size_t pass_bytes(const pv_request &r, long long nnz) {
-    const long long n = r.n;
-    size_t b = 2 * csr_bytes(n, nnz) + 4 * (size_t)(n + 1) + 2 * (size_t)nnz + 16 * (size_t)n;
-    if (r.kind == PV_REQ_VERTEX) b += (size_t)n * (size_t)(r.k_hi - r.k_lo + 1) * 16;
+    const size_t n = (size_t)r.n, m = (size_t)nnz / 2;
+    size_t b = 2 * csr_bytes((long long)n, nnz) + 4 * (n + 1) + 2 * (size_t)nnz + 32 * n;
+    b += 2 * 32 * (2 * n + m / 8) + (n / 2) * 64 * 8 + 4 * 4 * n;
+    if (r.kind == PV_REQ_VERTEX) {
+        const size_t K = (size_t)(r.k_hi - r.k_lo + 1);
+        b += (n / 2) * (64 * 4 + 8 + 2 * K * 16 + 16) + n * K * 16;
+    }
     return b;
 }
 
@@ -79,21 +96,132 @@ struct pv_server {
     std::vector<std::thread> threads;
     std::vector<pv_ctx *> ctxs;
     std::vector<hipStream_t> streams;
+    // resident graphs are loaded and freed through this context (budget
+    // cache_bytes); a context is not thread-safe, so load_mu guards it
+    std::mutex load_mu;
+    pv_ctx *loader = nullptr;
+    hipStream_t load_stream = nullptr;
 
     void worker(int w);
-    void evict_locked();
+    // unpinned graphs to release, least recently used first, until the
+    // resident bytes plus `extra` fit the cache (taken out of the cache
+    // under mu; the caller frees them after unlocking)
+    std::vector<pv_graph *> evict_locked(size_t extra);
+    void free_graphs(const std::vector<pv_graph *> &gs);
+    pv_status resident(const pv_request &r, pv_graph **out);
+    void count_pass(pv_ctx *c, const std::vector<pv_graph *> &lg, const std::vector<pv_request> &rq,
+                    int klo, int khi, uint64_t *d_local, std::vector<pv_u128> &counts,
+                    std::vector<int32_t> &omega, std::vector<uint64_t> &ovf, std::vector<pv_status> &st,
+                    std::vector<uint64_t> &lovf, int cap);
 };
 
-void pv_server::evict_locked() {
-    while (cache_used > (size_t)cfg.cache_bytes) {
+std::vector<pv_graph *> pv_server::evict_locked(size_t extra) {
+    std::vector<pv_graph *> out;
+    while (cache_used + extra > (size_t)cfg.cache_bytes) {
         auto victim = cache.end();
         for (auto it = cache.begin(); it != cache.end(); ++it)
             if (it->second.pins == 0 && (victim == cache.end() || it->second.last_use < victim->second.last_use))
                 victim = it;
-        if (victim == cache.end()) return;  // everything resident is in use
+        if (victim == cache.end()) break;  // everything resident is in use
         cache_used -= victim->second.bytes;
-        pv_graph_free(victim->second.g);
+        out.push_back(victim->second.g);
         cache.erase(victim);
+    }
+    return out;
+}
+
+void pv_server::free_graphs(const std::vector<pv_graph *> &gs) {
+    if (gs.empty()) return;
+    std::lock_guard<std::mutex> lk(load_mu);
+    for (pv_graph *g : gs) (void)pv_graph_free(g);
+}
+
+// Make the request's graph resident (pinned once for the request).
+pv_status pv_server::resident(const pv_request &r, pv_graph **out) {
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(r.graph_key);
+        if (it != cache.end()) {
+            it->second.pins++;
+            it->second.last_use = ++use_clock;
+            *out = it->second.g;
+            return PV_OK;
+        }
+    }
+    const size_t want = csr_bytes(r.n, r.row_ptr[r.n]);
+    pv_graph *ng = nullptr;
+    pv_status s = PV_ENOMEM;
+    for (int attempt = 0; attempt < 2 && s == PV_ENOMEM; attempt++) {
+        std::vector<pv_graph *> victims;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            victims = evict_locked(want);
+        }
+        free_graphs(victims);
+        std::lock_guard<std::mutex> lk(load_mu);
+        s = pv_graph_load_csr(loader, r.n, r.row_ptr, r.col, 0, &ng);
+    }
+    if (s != PV_OK) return s;
+    int32_t n = 0;
+    int64_t m = 0;
+    pv_graph_size(ng, &n, &m);
+    pv_graph *dup = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(r.graph_key);
+        if (it != cache.end()) {  // another worker loaded it meanwhile
+            dup = ng;
+            it->second.pins++;
+            it->second.last_use = ++use_clock;
+            *out = it->second.g;
+        } else {
+            CacheEntry e;
+            e.g = ng;
+            e.bytes = csr_bytes(n, 2 * m);
+            e.pins = 1;
+            e.last_use = ++use_clock;
+            cache.emplace(r.graph_key, e);
+            cache_used += e.bytes;
+            *out = ng;
+        }
+    }
+    if (dup) free_graphs({dup});
+    return PV_OK;
+}
+
+// One batched pass over lg (global counts for all k, per-vertex counts for
+// klo..khi when khi > 0).  A pass that runs out of the worker's device
+// budget is split in halves, down to single requests.
+void pv_server::count_pass(pv_ctx *c, const std::vector<pv_graph *> &lg, const std::vector<pv_request> &rq,
+                           int klo, int khi, uint64_t *d_local, std::vector<pv_u128> &counts,
+                           std::vector<int32_t> &omega, std::vector<uint64_t> &ovf, std::vector<pv_status> &st,
+                           std::vector<uint64_t> &lovf, int cap) {
+    const int L = (int)lg.size();
+    const int K = khi > 0 ? khi - klo + 1 : 0;
+    const int cw = (cap + 63) / 64;
+    std::vector<long long> voff(L + 1, 0);
+    for (int j = 0; j < L; j++) voff[j + 1] = voff[j] + rq[j].n;
+    std::vector<std::pair<int, int>> todo{{0, L}};
+    while (!todo.empty()) {
+        const int a = todo.back().first, b = todo.back().second;
+        todo.pop_back();
+        if (a >= b) continue;
+        uint64_t lv = 0;
+        std::vector<pv_status> sub((size_t)(b - a), PV_OK);
+        pv_status pass = pv_count_batch(c, b - a, lg.data() + a, 0, counts.data() + (size_t)a * cap, cap,
+                                        omega.data() + a, ovf.data() + (size_t)a * cw, K > 0 ? PV_VERTEX : PV_NONE,
+                                        klo, khi, K > 0 ? (pv_u128 *)(d_local + (size_t)voff[a] * K * 2) : nullptr,
+                                        &lv, sub.data(), nullptr);
+        if (pass == PV_ENOMEM && b - a > 1) {
+            const int mid = (a + b) / 2;
+            todo.push_back({mid, b});
+            todo.push_back({a, mid});
+            continue;
+        }
+        for (int j = a; j < b; j++) {
+            st[j] = (pass == PV_OK || pass == PV_EBUFSIZE || pass == PV_EOVERFLOW) ? sub[j - a] : pass;
+            lovf[j] = lv;
+        }
     }
 }
 
@@ -130,50 +258,11 @@ void pv_server::worker(int w) {
             std::lock_guard<std::mutex> lk(mu);
             for (int i = 0; i < G; i++) rs[i] = reqs[batch[i]].r;
         }
-        // make every graph resident (a miss loads it with this worker's
-        // context); each request of the pass pins its entry once
+        // make every graph resident; each request of the pass pins its
+        // entry once
         std::vector<pv_graph *> gs(G, nullptr);
         std::vector<pv_status> sts(G, PV_OK);
-        for (int i = 0; i < G; i++) {
-            pv_graph *g = nullptr;
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                auto it = cache.find(rs[i].graph_key);
-                if (it != cache.end()) {
-                    g = it->second.g;
-                    it->second.pins++;
-                    it->second.last_use = ++use_clock;
-                }
-            }
-            if (!g) {
-                pv_graph *ng = nullptr;
-                pv_status s = pv_graph_load_csr(c, rs[i].n, rs[i].row_ptr, rs[i].col, 0, &ng);
-                if (s != PV_OK) {
-                    sts[i] = s;
-                    continue;
-                }
-                int32_t n = 0;
-                int64_t m = 0;
-                pv_graph_size(ng, &n, &m);
-                std::lock_guard<std::mutex> lk(mu);
-                auto it = cache.find(rs[i].graph_key);
-                if (it != cache.end()) {  // another worker loaded it meanwhile
-                    pv_graph_free(ng);
-                    it->second.pins++;
-                    g = it->second.g;
-                } else {
-                    CacheEntry e;
-                    e.g = ng;
-                    e.bytes = csr_bytes(n, 2 * m);
-                    e.pins = 1;
-                    e.last_use = ++use_clock;
-                    cache.emplace(rs[i].graph_key, e);
-                    cache_used += e.bytes;
-                    g = ng;
-                }
-            }
-            gs[i] = g;
-        }
+        for (int i = 0; i < G; i++) sts[i] = resident(rs[i], &gs[i]);
         // one pass over the loaded graphs: global counts for all k, and
         // per-vertex counts over the union of the requested k ranges
         std::vector<int> live;
@@ -194,12 +283,17 @@ void pv_server::worker(int w) {
         const int L = (int)live.size();
         const int K = klo ? khi - klo + 1 : 0;
         std::vector<pv_graph *> lg(L);
-        for (int j = 0; j < L; j++) lg[j] = gs[live[j]];
+        std::vector<pv_request> lr(L);
+        for (int j = 0; j < L; j++) {
+            lg[j] = gs[live[j]];
+            lr[j] = rs[live[j]];
+        }
         std::vector<pv_u128> counts((size_t)std::max(L, 1) * cap);
         std::vector<int32_t> omega(std::max(L, 1));
         const int cw = (cap + 63) / 64;
         std::vector<uint64_t> ovf((size_t)std::max(L, 1) * cw);
-        uint64_t lovf = 0;
+        std::vector<pv_status> pst(std::max(L, 1), PV_OK);
+        std::vector<uint64_t> plovf(std::max(L, 1), 0);
         pv_status pass = PV_OK;
         if (K > 0) {
             const size_t need = (size_t)std::max<long long>(N, 1) * K * 2;
@@ -219,17 +313,11 @@ void pv_server::worker(int w) {
             }
         }
         if (pass == PV_OK && L > 0) {
-            pass = pv_count_batch(c, L, lg.data(), 0, counts.data(), cap, omega.data(), ovf.data(),
-                                  K > 0 ? PV_VERTEX : PV_NONE, klo, khi,
-                                  K > 0 ? (pv_u128 *)d_local : nullptr, &lovf, nullptr);
-            if (pass == PV_OK || pass == PV_EBUFSIZE || pass == PV_EOVERFLOW) {
-                if (K > 0 && N > 0) {
-                    if (hipMemcpyAsync(h_local, d_local, (size_t)N * K * 16, hipMemcpyDeviceToHost, st) !=
-                            hipSuccess ||
-                        hipStreamSynchronize(st) != hipSuccess)
-                        pass = PV_EDEVICE;
-                }
-                if (pass != PV_EDEVICE) pass = PV_OK;  // per-request statuses below
+            count_pass(c, lg, lr, klo, K > 0 ? khi : 0, d_local, counts, omega, ovf, pst, plovf, cap);
+            if (K > 0 && N > 0) {
+                if (hipMemcpyAsync(h_local, d_local, (size_t)N * K * 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                    hipStreamSynchronize(st) != hipSuccess)
+                    pass = PV_EDEVICE;
             }
         }
         const Clock::time_point t1 = Clock::now();
@@ -240,6 +328,11 @@ void pv_server::worker(int w) {
             pv_result &r = out[i];
             r.status = pass;
             if (pass != PV_OK) continue;
+            if (pst[j] != PV_OK && pst[j] != PV_EBUFSIZE && pst[j] != PV_EOVERFLOW) {
+                r.status = pst[j];
+                continue;
+            }
+            const uint64_t lovf = plovf[j];
             const pv_request &q = rs[i];
             r.omega = omega[j];
             const pv_u128 *row = counts.data() + (size_t)j * cap;
@@ -265,6 +358,8 @@ void pv_server::worker(int w) {
             if (q.cap <= omega[j]) r.status = PV_EBUFSIZE;
             else if (any) r.status = PV_EOVERFLOW;
         }
+        std::vector<pv_graph *> victims;
+        {
         std::lock_guard<std::mutex> lk(mu);
         const Clock::time_point t2 = Clock::now();
         for (int i = 0; i < G; i++) {
@@ -279,8 +374,12 @@ void pv_server::worker(int w) {
             auto it = cache.find(rs[i].graph_key);
             if (sts[i] == PV_OK && it != cache.end() && it->second.pins > 0) it->second.pins--;
         }
-        evict_locked();
+        victims = evict_locked(0);
         cv_done.notify_all();
+        }
+        // released outside the server lock: a free waits for the loader's
+        // stream, and submit / wait / the other workers need not wait for it
+        free_graphs(victims);
     }
     if (d_local) (void)hipFree(d_local);
     if (h_local) (void)hipHostFree(h_local);
@@ -298,6 +397,22 @@ extern "C" pv_status pv_server_start(const pv_server_cfg *cfg, pv_server **out) 
         delete s;
         return PV_EINVAL;
     }
+    if (hipStreamCreateWithFlags(&s->load_stream, hipStreamNonBlocking) != hipSuccess) {
+        pv_server_stop(s);
+        return PV_EDEVICE;
+    }
+    {
+        pv_config lc{};
+        lc.stream = s->load_stream;
+        // the cache keeps at most cache_bytes of idle graphs; the graphs
+        // pinned by running passes may pass that by what the passes admit
+        lc.hbm_budget = cfg->cache_bytes + (int64_t)cfg->workers * cfg->batch_bytes;
+        pv_status e = pv_init(cfg->device, &lc, &s->loader);
+        if (e != PV_OK) {
+            pv_server_stop(s);
+            return e;
+        }
+    }
     for (int w = 0; w < cfg->workers; w++) {
         hipStream_t st = nullptr;
         // default priority: the passes of different workers overlap
@@ -306,8 +421,14 @@ extern "C" pv_status pv_server_start(const pv_server_cfg *cfg, pv_server **out) 
             return PV_EDEVICE;
         }
         s->streams.push_back(st);
+        pv_config wc{};
+        wc.stream = st;
+        // the admission estimate is the soft bound; the hard limit leaves
+        // room for estimates that fall short and for the context's own
+        // tables (binomials, the peel's fixed-size buffers)
+        wc.hbm_budget = 2 * cfg->batch_bytes + (64ll << 20);
         pv_ctx *c = nullptr;
-        pv_status e = pv_init(cfg->device, st, &c);
+        pv_status e = pv_init(cfg->device, &wc, &c);
         if (e != PV_OK) {
             pv_server_stop(s);
             return e;
@@ -400,10 +521,12 @@ extern "C" void pv_server_stop(pv_server *s) {
         s->cv_done.notify_all();
     }
     for (auto &t : s->threads) t.join();
-    for (auto &e : s->cache) pv_graph_free(e.second.g);
+    for (auto &e : s->cache) (void)pv_graph_free(e.second.g);
     s->cache.clear();
     for (pv_ctx *c : s->ctxs) pv_fini(c);
+    if (s->loader) pv_fini(s->loader);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    if (s->load_stream) (void)hipStreamDestroy(s->load_stream);
     delete s;
 }
 

@@ -32,12 +32,14 @@ PV_EAGAIN = -9
 
 PV_NONE, PV_VERTEX, PV_EDGE = 0, 1, 2
 PV_TRUST_INPUT = 1
+PV_DEDUP = 2
+PV_SYMMETRIZE = 4
 PV_MAX_ALPHA = 4096
 PV_MAX_LOCAL_K = 16
 
 # every function declared in include/pivoter.h
 ABI_FUNCTIONS = [
-    "pv_strerror", "pv_init", "pv_fini", "pv_set_stream", "pv_set_dfs_max", "pv_set_dfs_budget", "pv_set_lane_max",
+    "pv_strerror", "pv_init", "pv_fini", "pv_memory", "pv_measure_peaks", "pv_set_stream", "pv_set_dfs_max", "pv_set_dfs_budget", "pv_set_lane_max",
     "pv_set_timing",
     "pv_last_error",
     "pv_graph_load_csr", "pv_graph_load_csr_device", "pv_graph_free", "pv_graph_size",
@@ -45,7 +47,7 @@ ABI_FUNCTIONS = [
     "pv_local_frequency",
     "pv_graph_edge_list", "pv_count", "pv_count_roots", "pv_count_batch", "pv_count_global_batch",
     "pv_server_start", "pv_server_submit", "pv_server_wait", "pv_server_poll", "pv_server_cancel",
-    "pv_server_stats", "pv_server_stop",
+    "pv_server_stats", "pv_server_stop", "pv_autotune", "pv_tune_key",
 ]
 
 PV_REQ_GLOBAL, PV_REQ_VERTEX = 0, 1
@@ -62,7 +64,8 @@ class pv_stats(C.Structure):
                 ("ms_peel", C.c_float), ("ms_orient", C.c_float), ("ms_levels", C.c_float),
                 ("ms_finalize", C.c_float), ("launches_kind", C.c_uint32 * 3),
                 ("ms_kind", C.c_float * 3), ("work_kind", C.c_uint64 * 3),
-                ("kernel_kl", C.c_int32), ("kernel_lk", C.c_int32), ("attempts", C.c_int32)]
+                ("kernel_kl", C.c_int32), ("kernel_lk", C.c_int32), ("attempts", C.c_int32),
+                ("child_work", C.c_uint64), ("leaf_hp", C.c_uint64), ("leaf_pp", C.c_uint64)]
 
     def as_dict(self) -> dict:
         d = {}
@@ -70,6 +73,28 @@ class pv_stats(C.Structure):
             v = getattr(self, f)
             d[f] = list(v) if isinstance(v, C.Array) else v
         return d
+
+
+class pv_peaks(C.Structure):
+    _fields_ = [("hbm_copy_gbs", C.c_double), ("hbm_read_gbs", C.c_double), ("lds_read_gbs", C.c_double),
+                ("valu_gops", C.c_double), ("ms_copy", C.c_float), ("ms_read", C.c_float),
+                ("ms_lds", C.c_float), ("ms_valu", C.c_float)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class pv_config(C.Structure):
+    _fields_ = [("stream", C.c_void_p), ("hbm_budget", C.c_int64), ("tune_cache", C.c_char_p),
+                ("dfs_max", C.c_int32), ("dfs_budget", C.c_int32), ("lane_max", C.c_int32)]
+
+
+class pv_tune(C.Structure):
+    _fields_ = [("dfs_max", C.c_int32), ("dfs_budget", C.c_int32), ("lane_max", C.c_int32),
+                ("ms_best", C.c_float), ("ms_default", C.c_float), ("trials", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class pv_server_cfg(C.Structure):
@@ -128,8 +153,10 @@ def _lib():
         sig = {
             "pv_strerror": (C.c_char_p, [i32]),
             "pv_last_error": (C.c_char_p, []),
-            "pv_init": (i32, [i32, vp, pvp]),
+            "pv_init": (i32, [i32, C.POINTER(pv_config), pvp]),
             "pv_fini": (None, [vp]),
+            "pv_memory": (i32, [vp, C.POINTER(C.c_int64)]),
+            "pv_measure_peaks": (i32, [vp, C.c_int64, C.POINTER(pv_peaks)]),
             "pv_set_stream": (i32, [vp, vp]),
             "pv_set_dfs_max": (i32, [vp, i32]),
             "pv_set_timing": (i32, [vp, i32]),
@@ -137,7 +164,7 @@ def _lib():
             "pv_set_lane_max": (i32, [vp, i32]),
             "pv_graph_load_csr": (i32, [vp, i32, i32p, i32p, u32, pvp]),
             "pv_graph_load_csr_device": (i32, [vp, i32, i64, vp, vp, u32, pvp]),
-            "pv_graph_free": (None, [vp]),
+            "pv_graph_free": (i32, [vp]),
             "pv_graph_size": (i32, [vp, i32p, C.POINTER(C.c_int64)]),
             "pv_graph_orient": (i32, [vp, i32p]),
             "pv_graph_export_order": (i32, [vp, i32p]),
@@ -147,10 +174,12 @@ def _lib():
             "pv_count_local": (i32, [vp, i32, i32, i32, u128p, i64, u64p, sp]),
             "pv_graph_edge_list": (i32, [vp, i32p, i32p]),
             "pv_count": (i32, [vp, i32, i32, u128p, i32, i32p, u64p, i32, i32, i32, vp, u64p, sp]),
-            "pv_count_roots": (i32, [vp, i32p, i32, i32, u128p, i32, i32p, u64p, sp]),
+            "pv_count_roots": (i32, [vp, i32p, i32, i32, u128p, i32, i32p, u64p, i32, i32, i32, vp, u64p, sp]),
             "pv_count_batch": (i32, [vp, i32, pvp, i32, u128p, i32, i32p, u64p, i32, i32, i32, vp,
-                                     u64p, sp]),
-            "pv_count_global_batch": (i32, [vp, i32, pvp, i32, u128p, i32, i32p, u64p, sp]),
+                                     u64p, i32p, sp]),
+            "pv_count_global_batch": (i32, [vp, i32, pvp, i32, u128p, i32, i32p, u64p, i32p, sp]),
+            "pv_autotune": (i32, [vp, i32, i32, i32, vp, i32, C.POINTER(pv_tune)]),
+            "pv_tune_key": (C.c_char_p, [vp, i32, i32, i32]),
             "pv_server_start": (i32, [C.POINTER(pv_server_cfg), pvp]),
             "pv_server_submit": (i32, [vp, C.POINTER(pv_request), u64p]),
             "pv_server_wait": (i32, [vp, C.c_uint64, i64, C.POINTER(pv_result)]),
@@ -203,14 +232,30 @@ def pv_last_error() -> str:
     return _lib().pv_last_error().decode()
 
 
-def pv_init(device: int = 0, stream: int | None = None) -> int:
+def pv_init(device: int = 0, stream: int | None = None, hbm_budget: int = 0, tune_cache: str | None = None,
+            dfs_max: int = 0, dfs_budget: int = 0, lane_max: int = 0) -> int:
+    cfg = pv_config(stream, hbm_budget, tune_cache.encode() if tune_cache else None, dfs_max, dfs_budget,
+                    lane_max)
     out = C.c_void_p()
-    _check(_lib().pv_init(device, stream, C.byref(out)), "pv_init")
+    _check(_lib().pv_init(device, C.byref(cfg), C.byref(out)), "pv_init")
     return out.value
 
 
 def pv_fini(ctx: int) -> None:
     _lib().pv_fini(ctx)
+
+
+def pv_memory(ctx: int) -> int:
+    b = C.c_int64()
+    _check(_lib().pv_memory(ctx, C.byref(b)), "pv_memory")
+    return b.value
+
+
+def pv_measure_peaks(ctx: int, copy_bytes: int = 0) -> dict:
+    """The device's measured HBM copy/read, LDS read and VALU rates."""
+    out = pv_peaks()
+    _check(_lib().pv_measure_peaks(ctx, copy_bytes, C.byref(out)), "pv_measure_peaks")
+    return out.as_dict()
 
 
 def pv_set_stream(ctx: int, stream: int | None) -> None:
@@ -251,8 +296,9 @@ def pv_graph_load_csr_device(ctx: int, n: int, nnz: int, d_row_ptr: int, d_col: 
     return out.value
 
 
-def pv_graph_free(g: int) -> None:
-    _lib().pv_graph_free(g)
+def pv_graph_free(g: int) -> int:
+    """Returns PV_OK, or PV_EAGAIN while a count on another thread uses g."""
+    return _check(_lib().pv_graph_free(g), "pv_graph_free", allow=(PV_EAGAIN,))
 
 
 def pv_graph_size(g: int) -> tuple[int, int]:
@@ -363,16 +409,23 @@ def pv_count(g: int, reorient: bool = False, k_max: int = 0, cap: int = PV_MAX_A
     return GlobalResult(u128_to_ints(counts), om.value, ovf, st.as_dict(), s), lov.value
 
 
-def pv_count_roots(g: int, roots, k_max: int = 0, cap: int = PV_MAX_ALPHA + 2) -> GlobalResult:
+def pv_count_roots(g: int, roots, k_max: int = 0, cap: int = PV_MAX_ALPHA + 2, local_kind: int = PV_NONE,
+                   k_lo: int = 0, k_hi: int = 0, local_out: int | None = None, with_local_ovf: bool = False):
+    """Counts of the cliques whose smallest-key vertex is one of `roots`;
+    local counts go to the device buffer `local_out` (address).  Returns a
+    GlobalResult, or (GlobalResult, local overflow word) with_local_ovf."""
     r, rp = _i32(roots if len(roots) else np.zeros(1, np.int32))
     counts = (pv_u128 * cap)()
     ov = (C.c_uint64 * ((cap + 63) // 64))()
     om = C.c_int32()
+    lov = C.c_uint64()
     st = pv_stats()
-    s = _check(_lib().pv_count_roots(g, rp, len(roots), k_max, counts, cap, C.byref(om), ov,
-                                     C.byref(st)), "pv_count_roots", allow=(PV_EOVERFLOW,))
+    s = _check(_lib().pv_count_roots(g, rp, len(roots), k_max, counts, cap, C.byref(om), ov, local_kind,
+                                     k_lo, k_hi, local_out, C.byref(lov), C.byref(st)),
+               "pv_count_roots", allow=(PV_EOVERFLOW,))
     ovf = [k for k in range(cap) if (ov[k >> 6] >> (k & 63)) & 1]
-    return GlobalResult(u128_to_ints(counts), om.value, ovf, st.as_dict(), s)
+    res = GlobalResult(u128_to_ints(counts), om.value, ovf, st.as_dict(), s)
+    return (res, lov.value) if with_local_ovf else res
 
 
 def pv_count_global_batch_raw(ctx: int, graphs, k_max: int = 0, cap: int = 256):
@@ -385,13 +438,17 @@ def pv_count_global_batch_raw(ctx: int, graphs, k_max: int = 0, cap: int = 256):
     counts = np.zeros((max(G, 1), cap, 2), dtype=np.uint64)
     om = np.zeros(max(G, 1), dtype=np.int32)
     ov = np.zeros((max(G, 1), nw), dtype=np.uint64)
+    gst = np.zeros(max(G, 1), dtype=np.int32)
     st = pv_stats()
     s = _check(_lib().pv_count_global_batch(ctx, G, arr, k_max,
                                             counts.ctypes.data_as(C.POINTER(pv_u128)), cap,
                                             om.ctypes.data_as(C.POINTER(C.c_int32)),
-                                            ov.ctypes.data_as(C.POINTER(C.c_uint64)), C.byref(st)),
-               "pv_count_global_batch", allow=(PV_EOVERFLOW,))
-    return counts[:G], om[:G], ov[:G], s, st.as_dict()
+                                            ov.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                            gst.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(st)),
+               "pv_count_global_batch", allow=(PV_EOVERFLOW, PV_EBUFSIZE))
+    d = st.as_dict()
+    d["status"] = gst[:G].tolist()
+    return counts[:G], om[:G], ov[:G], s, d
 
 
 def pv_count_global_batch(ctx: int, graphs, k_max: int = 0, cap: int = 256):
@@ -416,13 +473,28 @@ def pv_count_batch(ctx: int, graphs, k_max: int = 0, cap: int = 256, local_kind:
     om = np.zeros(max(G, 1), dtype=np.int32)
     ov = np.zeros((max(G, 1), nw), dtype=np.uint64)
     lov = C.c_uint64()
+    gst = np.zeros(max(G, 1), dtype=np.int32)
     st = pv_stats()
     s = _check(_lib().pv_count_batch(ctx, G, arr, k_max, counts.ctypes.data_as(C.POINTER(pv_u128)),
                                      cap, om.ctypes.data_as(C.POINTER(C.c_int32)),
                                      ov.ctypes.data_as(C.POINTER(C.c_uint64)), local_kind, k_lo, k_hi,
-                                     local_out, C.byref(lov), C.byref(st)),
-               "pv_count_batch", allow=(PV_EOVERFLOW,))
-    return counts[:G], om[:G], ov[:G], s, lov.value, st.as_dict()
+                                     local_out, C.byref(lov), gst.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     C.byref(st)),
+               "pv_count_batch", allow=(PV_EOVERFLOW, PV_EBUFSIZE))
+    d = st.as_dict()
+    d["status"] = gst[:G].tolist()
+    return counts[:G], om[:G], ov[:G], s, lov.value, d
+
+
+def pv_autotune(g: int, local_kind: int = PV_NONE, k_lo: int = 0, k_hi: int = 0,
+                local_out: int | None = None, reps: int = 2) -> dict:
+    t = pv_tune()
+    _check(_lib().pv_autotune(g, local_kind, k_lo, k_hi, local_out, reps, C.byref(t)), "pv_autotune")
+    return t.as_dict()
+
+
+def pv_tune_key(g: int, local_kind: int = PV_NONE, k_lo: int = 0, k_hi: int = 0) -> str:
+    return _lib().pv_tune_key(g, local_kind, k_lo, k_hi).decode()
 
 
 class Server:

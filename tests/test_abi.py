@@ -40,17 +40,25 @@ def test_null_handles_are_rejected_without_touching_the_device():
     assert lib.pv_set_stream(None, None) == P.PV_EINVAL
     assert lib.pv_set_dfs_max(None, 8) == P.PV_EINVAL
     assert lib.pv_graph_size(None, None, None) == P.PV_EINVAL
-    lib.pv_graph_free(None)
+    assert lib.pv_graph_free(None) == P.PV_OK
     lib.pv_fini(None)
+    assert lib.pv_memory(None, None) == P.PV_EINVAL
+    assert lib.pv_autotune(None, 0, 0, 0, None, 1, None) == P.PV_EINVAL
+    assert lib.pv_count_roots(None, None, 0, 0, None, 0, None, None, 0, 0, 0, None, None, None) == P.PV_EINVAL
+    assert lib.pv_count_global_batch(None, 0, None, 0, None, 0, None, None, None, None) == P.PV_EINVAL
+    assert lib.pv_tune_key(None, 0, 0, 0) == b""
 
 
 def test_header_constants_match_binding():
     hdr = open(os.path.join(ROOT, "include", "pivoter.h")).read()
     for name in ["PV_OK", "PV_EINVAL", "PV_ENOTSIMPLE", "PV_ENOMEM", "PV_EOVERFLOW", "PV_EDEVICE",
                  "PV_ETOOBIG", "PV_EBUFSIZE", "PV_ECANCELLED", "PV_EAGAIN", "PV_NONE", "PV_VERTEX",
-                 "PV_EDGE", "PV_MAX_ALPHA", "PV_MAX_LOCAL_K"]:
-        m = re.search(rf"#define {name}\s+(-?\d+)", hdr)
+                 "PV_EDGE", "PV_MAX_ALPHA", "PV_MAX_LOCAL_K", "PV_TRUST_INPUT", "PV_DEDUP",
+                 "PV_SYMMETRIZE"]:
+        m = re.search(rf"#define {name}\s+(-?\d+)u?\b", hdr)
         assert m, name
         assert int(m.group(1)) == getattr(P, name), name
     assert ctypes.sizeof(P.pv_u128) == 16
-    assert ctypes.sizeof(P.pv_stats) == 136
+    assert ctypes.sizeof(P.pv_stats) == 160
+    assert ctypes.sizeof(P.pv_config) == 40
+    assert ctypes.sizeof(P.pv_tune) == 24

@@ -49,7 +49,8 @@ def check_global(ctx, g, name, kmax=0, check_order=True):
     if check_order:
         pe = O.peel(g)
         assert np.array_equal(sub, pe.sub), "peel order differs"
-    ref = O.count(g, key=sub, kmax=kmax)
+    ref = O.count(g, key=sub, kmax=kmax, hist_dim=res.stats["alpha"] + 2)
+    assert ref.stats["hist_out"] == 0
     top = len(ref.glob)
     ovf_ref = [k for k in range(top) if ref.glob_ovf[k]]
     assert res.overflow == ovf_ref
@@ -63,6 +64,11 @@ def check_global(ctx, g, name, kmax=0, check_order=True):
         assert res.stats["leaves"] == ref.stats["leaves"], (res.stats, ref.stats)
         assert res.stats["nodes"] == ref.stats["nodes"], (res.stats, ref.stats)
         assert res.stats["work"] == ref.stats["work_sw"], (res.stats, ref.stats)
+        # the roofline model's work terms: child formation and the leaves' additions
+        assert res.stats["child_work"] == ref.stats["work_child"], (res.stats, ref.stats)
+        assert res.stats["leaf_hp"] == ref.stats["leaf_hp"], (res.stats, ref.stats)
+        hh, pp = np.indices(ref.hist.shape)
+        assert res.stats["leaf_pp"] == int((ref.hist.astype(object) * (pp + 1)).sum())
     return res, ref
 
 

@@ -4,13 +4,19 @@ of 20..60 vertices planted on disjoint random vertex sets.
 
 Its degeneracy is 1318 and its tree cannot be walked whole, neither for all k
 nor truncated at k = 8: a single root of out-degree above 512 already keeps
-the oracle busy for minutes.  So parity at this size is the peel order of
-every vertex and the degeneracy, and the all-k and truncated counts, tree
-sizes and clique numbers of a seeded sample of roots in four out-degree
-strata (up to 512, so heavy roots with up to 8 words per row are included),
-against the oracle on the same roots.  Whole-graph per-edge counts are not
-checked here for the same reason; per-edge parity is covered on smaller
-graphs.
+the oracle busy for minutes.  So parity at this size is:
+  - the peel order of every vertex and the degeneracy;
+  - the all-k and truncated counts, tree sizes and clique numbers of a
+    seeded sample of roots in four out-degree strata (up to 512, so heavy
+    roots with up to 8 words per row are included), against the oracle on
+    the same roots;
+  - per-edge counts for k = 3..8 of a smaller seeded sample of roots, row by
+    row over all 95M edges, against the oracle on the same roots;
+  - the roots of largest out-degree (up to 1318 vertices, 21 words per row)
+    and roots in (512, 1024], truncated at k = 3, against closed forms that
+    need no oracle: the k-cliques whose smallest-key vertex is v are v plus a
+    (k-1)-clique of G[N+(v)], so C_2 sums |N+(v)| and C_3 sums the edges
+    inside N+(v).
 """
 import sys
 
@@ -78,3 +84,65 @@ def test_rmat22_sampled_roots(rmat22, kmax):
     if not kmax:
         assert got.stats["leaves"] == ref.stats["leaves"]
         assert got.stats["nodes"] == ref.stats["nodes"]
+
+
+def _out_neighbours(g, sub, v):
+    nb = g.col[g.row_ptr[v]:g.row_ptr[v + 1]]
+    fwd = (sub[nb] > sub[v]) | ((sub[nb] == sub[v]) & (nb > v))
+    return np.sort(nb[fwd])
+
+
+def _edges_inside(g, members):
+    """edges of G[members] (members sorted), from the CSR rows"""
+    cnt = 0
+    for u in members:
+        row = g.col[g.row_ptr[u]:g.row_ptr[u + 1]]
+        pos = np.searchsorted(members, row)
+        hit = (pos < len(members)) & (members[np.minimum(pos, len(members) - 1)] == row)
+        cnt += int(hit.sum())
+    return cnt // 2
+
+
+def test_rmat22_widest_roots_closed_form(rmat22):
+    g, h, alpha, sub = rmat22
+    od = O.out_degrees(g, sub)
+    rng = np.random.default_rng(2024)
+    top = np.argsort(-od, kind="stable")[:6]
+    mid = rng.choice(np.nonzero((od > 512) & (od <= 1024))[0], 6, replace=False)
+    roots = np.concatenate([top, mid]).astype(np.int32)
+    _say(f"[rmat22] widest roots: out-degrees {sorted(od[roots].tolist())}")
+    assert od[roots].max() == alpha and (od[roots].max() + 63) // 64 >= 21
+    got = P.pv_count_roots(h, roots, k_max=3)
+    c2 = c3 = 0
+    for v in roots:
+        nb = _out_neighbours(g, sub, v)
+        c2 += len(nb)
+        c3 += _edges_inside(g, nb)
+    assert got.counts[:5] == [0, len(roots), c2, c3, 0]
+    assert got.omega == 3
+
+
+def test_rmat22_sampled_roots_per_edge(rmat22):
+    import torch
+    g, h, alpha, sub = rmat22
+    od = O.out_degrees(g, sub)
+    rng = np.random.default_rng(2023)
+    parts = [rng.choice(np.nonzero((od > lo) & (od <= hi))[0], cnt, replace=False)
+             for lo, hi, cnt in [(0, 64, 300), (64, 128, 5), (128, 256, 2)]]
+    roots = np.concatenate(parts).astype(np.int32)
+    K = 6
+    _say(f"[rmat22] per-edge k=3..8 on {len(roots)} roots over all {g.m} edges")
+    dev = torch.zeros((g.m, K, 2), dtype=torch.int64, device="cuda:0")
+    got, lov = P.pv_count_roots(h, roots, k_max=8, local_kind=P.PV_EDGE, k_lo=3, k_hi=8,
+                                local_out=dev.data_ptr(), with_local_ovf=True)
+    torch.cuda.synchronize()
+    nz_gpu = torch.nonzero(dev.view(g.m, -1).ne(0).any(dim=1)).squeeze(1).cpu().numpy()
+    rows_gpu = dev[torch.from_numpy(nz_gpu).to("cuda:0")].cpu().numpy().view(np.uint64)
+    del dev
+    ref = O.count(g, key=sub, roots=roots, kmax=8, edge=(3, 8))
+    assert lov == 0 and not ref.edge_ovf.any()
+    nz_ref = np.nonzero(ref.edge.reshape(g.m, -1).any(axis=1))[0]
+    _say(f"[rmat22] {len(nz_ref)} edges with counts; leaves={ref.stats['leaves']}")
+    assert got.counts[1: len(ref.glob)] == ref.glob[1:]
+    assert np.array_equal(nz_gpu, nz_ref)
+    assert np.array_equal(rows_gpu, ref.edge[nz_ref])

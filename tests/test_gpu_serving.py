@@ -1,8 +1,8 @@
 """Batched per-vertex counts and the serving loop (through the C ABI).
 
-Every result must be the one a single call on the graph alone gives (the
-union pass builds each graph's own tree), bit for bit, whatever else shares
-the pass.
+Every served result must equal the oracle's on that graph, bit for bit, and
+the one a single call on the graph alone gives (the union pass builds each
+graph's own tree), whatever else shares the pass.
 """
 import sys
 import threading
@@ -81,10 +81,11 @@ def test_server_results_equal_single_calls(pool):
         klo = int(rng.integers(1, 4))
         khi = klo + int(rng.integers(0, 6))
         plan.append((j, kind, klo, khi))
-    alone = {}
+    alone, oracle = {}, {}
     for (j, kind, klo, khi) in plan:
         if (j, kind, klo, khi) not in alone:
             alone[(j, kind, klo, khi)] = _alone(ctx, pool[j], kind, klo, khi)
+            oracle[(j, kind, klo, khi)] = O.count(pool[j], vertex=(klo, khi) if kind == P.PV_REQ_VERTEX else None)
     P.pv_fini(ctx)
     srv = P.Server(workers=2, max_batch=8)
     tickets = [None] * len(plan)
@@ -104,11 +105,16 @@ def test_server_results_equal_single_calls(pool):
             assert r.status == P.PV_OK, (i, r.status)
             sizes.append(r.batch_size)
             ref, vref = alone[(j, kind, klo, khi)]
+            orc = oracle[(j, kind, klo, khi)]
             got = P.u128_to_ints(counts)
+            # the oracle's counts, and the same as the graph counted alone
+            assert got[: len(orc.glob)] == orc.glob, i
+            assert r.omega == orc.omega
             assert got[: ref.omega + 1] == ref.counts[: ref.omega + 1], i
             assert all(x == 0 for x in got[ref.omega + 1:])
             assert r.omega == ref.omega
             if kind == P.PV_REQ_VERTEX:
+                assert np.array_equal(vout, orc.vertex), i
                 assert np.array_equal(vout, vref), i
         resident, nbytes, pending = srv.stats()
         _say(f"[serving] 60 requests: batch sizes {sorted(set(sizes))}, resident {resident}")
@@ -122,6 +128,8 @@ def test_server_small_cache_evicts_and_stays_exact(pool):
     ctx = P.pv_init(0)
     ref = [_alone(ctx, g, P.PV_REQ_GLOBAL, 0, 0)[0] for g in graphs]
     P.pv_fini(ctx)
+    for g, r in zip(graphs, ref):
+        assert r.counts[: r.omega + 1] == O.count(g).glob[: r.omega + 1]
     one = 4 * (graphs[0].n + 1) + 8 * graphs[0].m
     srv = P.Server(workers=1, max_batch=3, cache_bytes=2 * one)
     try:

@@ -513,3 +513,24 @@ def test_leaf_sum_of_2_to_p_closed_form(parts):
     assert cliques == prod - 1
     # total size: each part contributes a vertex to a clique in a * prod / (a + 1) of them
     assert sizes == sum(a * prod // (a + 1) for a in parts)
+
+
+# ------------------------------------------- the oracle's parallel form
+# Sec. 5's parallel version splits the root subproblems over workers with
+# private counters; the sum must be the sequential oracle's result exactly.
+
+def test_parallel_form_equals_sequential():
+    from oracle import parallel as OP
+    g = gg.plant_cliques(gg.gnp(300, 0.06, 91), [16, 11], 92)
+    key = O.peel(g).sub
+    seq = O.count(g, key=key, vertex=(2, 9), edge=(2, 7))
+    par = OP.count_parallel(g, key, workers=3, chunks=17, vertex=(2, 9), edge=(2, 7))
+    assert par["glob"][: len(seq.glob)] == seq.glob
+    assert np.array_equal(par["vertex"], seq.vertex) and np.array_equal(par["edge"], seq.edge)
+    for k in ("nodes", "leaves", "work_sw", "work_child", "leaf_hp", "leaf_pairs"):
+        assert par["stats"][k] == seq.stats[k], k
+    roots = np.arange(0, g.n, 3, dtype=np.int32)
+    sub_seq = O.count(g, key=key, roots=roots, vertex=(3, 6))
+    sub_par = OP.count_parallel(g, key, roots=roots, workers=2, vertex=(3, 6))
+    assert sub_par["glob"][: len(sub_seq.glob)] == sub_seq.glob
+    assert np.array_equal(sub_par["vertex"], sub_seq.vertex)
