@@ -350,6 +350,22 @@ pv_status pv_local_frequency(pv_ctx *ctx, const pv_u128 *local, int64_t rows, in
                              pv_u128 *values, uint64_t *freq, int64_t cap, int64_t *ndistinct);
 
 /*
+ * pv_local_frequency without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid it): the same inputs, outputs and results,
+ * with every intermediate in a fixed scratch array of the library's (about
+ * 52 MiB per device, held from the first pv_init on that device until the
+ * process ends).  rows is at most PV_FREQ_STATIC_ROWS (PV_ETOOBIG beyond,
+ * with nothing launched).  The call makes no device or host allocation of
+ * its own.  All calls on one device share that array, so calls that overlap
+ * on one device (several host threads or streams) race: the caller
+ * serialises them.
+ */
+#define PV_FREQ_STATIC_ROWS (1 << 20)
+pv_status pv_local_frequency_static(pv_ctx *ctx, const pv_u128 *local, int64_t rows, int32_t K, int32_t col,
+                                    pv_u128 *values, uint64_t *freq, int64_t cap, int64_t *ndistinct);
+
+/*
  * Local counts for k_lo <= k <= k_hi (1 <= k_lo <= k_hi <= PV_MAX_ALPHA + 1),
  * Alg. 2 per-vertex and per-edge steps.  The binomials C(alpha, b) for
  * b < k_hi must fit 64 bits (PV_ETOOBIG otherwise; every k when alpha <= 67).

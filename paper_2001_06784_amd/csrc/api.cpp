@@ -349,6 +349,14 @@ extern "C" pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out)
         delete c;
         return PV_EDEVICE;
     }
+    // the allocation-free frequency entry point's scratch array on this
+    // device (its address, resolved once per device with the device current)
+    e = pv_freq_static_init(device);
+    if (e != hipSuccess) {
+        set_err("hipGetSymbolAddress", e);
+        delete c;
+        return PV_EDEVICE;
+    }
     c->dev.device = device;
     c->dev.num_cu = prop.multiProcessorCount;
     {
@@ -1575,6 +1583,43 @@ extern "C" pv_status pv_local_frequency(pv_ctx *c, const pv_u128 *local, int64_t
         HIPCHK(hipMemcpyAsync(pos.data(), c->ws.fq_pos.p, (size_t)D * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         for (int d = 0; d < D; d++) freq[d] = (uint64_t)((d + 1 < D ? pos[d + 1] : n) - pos[d]);
+    }
+    return PV_OK;
+}
+
+// The same without allocating: every intermediate lives in the device's
+// static scratch array (its address resolved at pv_init), the
+// multiplicities are formed on the device, and the results are copied
+// straight into the caller's arrays.
+extern "C" pv_status pv_local_frequency_static(pv_ctx *c, const pv_u128 *local, int64_t rows, int32_t K,
+                                               int32_t col, pv_u128 *values, uint64_t *freq, int64_t cap,
+                                               int64_t *ndistinct) {
+    if (!c || rows < 0 || K < 1 || col < 0 || col >= K || cap < 0 || !ndistinct || (rows > 0 && !local) ||
+        (cap > 0 && (!values || !freq)))
+        return PV_EINVAL;
+    if (rows > PV_FREQ_STATIC_ROWS) {
+        snprintf(g_last_error, sizeof g_last_error, "%lld rows exceed the static scratch of %d rows",
+                 (long long)rows, PV_FREQ_STATIC_ROWS);
+        return PV_ETOOBIG;
+    }
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t s = c->stream;
+    const int n = (int)rows;
+    long long npad = 1;
+    while (npad < rows) npad <<= 1;
+    uint64_t *dvals = nullptr, *dfreq = nullptr;
+    int *didx = nullptr;
+    HIPCHK(pv_launch_frequency_static(c->device, (const uint64_t *)local, n, K, col, npad, &dvals, &dfreq, &didx,
+                                      s));
+    int D = 0;
+    if (n > 0) HIPCHK(hipMemcpyAsync(&D, didx + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *ndistinct = D;
+    if (cap < D) return PV_EBUFSIZE;
+    if (D > 0) {
+        HIPCHK(hipMemcpyAsync(values, dvals, (size_t)D * 16, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(freq, dfreq, (size_t)D * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
     }
     return PV_OK;
 }

@@ -79,7 +79,73 @@ int grid_of(long long n) {
     return (int)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
 }
 
+// multiplicities: freq[d] = (next run's first position, or rows) - pos[d]
+// for d < D = idx[rows]
+__global__ void __launch_bounds__(256) freq_count_kernel(const int *__restrict__ idx, const int *__restrict__ pos,
+                                                         int rows, uint64_t *__restrict__ freq) {
+    const int D = idx[rows];
+    for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < D; d += gridDim.x * blockDim.x)
+        freq[d] = (uint64_t)((d + 1 < D ? pos[d + 1] : rows) - pos[d]);
+}
+
+constexpr long long FS_ROWS = PV_FREQ_STATIC_ROWS;
+constexpr long long FS_INTS = 3 * (FS_ROWS + 1) + FS_ROWS / 1024 + 2;
+constexpr long long FS_WORDS = 2 * FS_ROWS + 2 * FS_ROWS + FS_ROWS + (FS_INTS + 1) / 2;
+constexpr int FS_MAX_DEVICES = 64;
+
 }  // namespace
+
+// ------------------------------------------------ allocation-free variant
+// One scratch array per device for pv_local_frequency_static (about 52 MiB,
+// held by each device the library runs on until the process ends), in
+// words: sort keys [2 npad], values [2 rows], multiplicities [rows], then
+// int arrays flags, idx, pos [rows + 1 each] and the scan's block sums
+// [rows / 1024 + 2]; npad <= rows <= PV_FREQ_STATIC_ROWS (a power of two).
+// Every word a call reads is written earlier in the same call, so nothing
+// has to start at zero; calls that overlap on one device race on it.
+static __device__ __align__(256) uint64_t scratch[FS_WORDS];
+
+// Its device address per device (in host code the name `scratch` is a
+// host-side stand-in, not a device address), resolved once per device with
+// that device current.
+static uint64_t *g_scratch[FS_MAX_DEVICES];
+
+// Called by pv_init with `device` current; resolves the address once per
+// device (later contexts on the device find it set).
+hipError_t pv_freq_static_init(int device) {
+    if (device < 0 || device >= FS_MAX_DEVICES) return hipErrorInvalidDevice;
+    if (__atomic_load_n(&g_scratch[device], __ATOMIC_ACQUIRE)) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    // two first contexts racing store the same address
+    __atomic_store_n(&g_scratch[device], (uint64_t *)ptr, __ATOMIC_RELEASE);
+    return hipSuccess;
+}
+
+hipError_t pv_launch_frequency_static(int device, const uint64_t *src, int rows, int K, int col, long long npad,
+                                      uint64_t **vals, uint64_t **freq, int **idx, hipStream_t s) {
+    if (device < 0 || device >= FS_MAX_DEVICES) return hipErrorInvalidDevice;
+    uint64_t *base = __atomic_load_n(&g_scratch[device], __ATOMIC_ACQUIRE);
+    if (!base) return hipErrorNotInitialized;
+    if (rows > FS_ROWS || npad > FS_ROWS) return hipErrorInvalidValue;
+    FreqWork w;
+    w.keys = base;
+    w.vals = base + 2 * FS_ROWS;
+    uint64_t *fq = base + 4 * FS_ROWS;
+    int *ints = (int *)(base + 5 * FS_ROWS);
+    w.flags = ints;
+    w.idx = ints + (FS_ROWS + 1);
+    w.pos = ints + 2 * (FS_ROWS + 1);
+    w.scan_tmp = ints + 3 * (FS_ROWS + 1);
+    const hipError_t e = pv_launch_frequency(src, rows, K, col, npad, w, s);
+    if (e != hipSuccess) return e;
+    if (rows > 0) freq_count_kernel<<<grid_of(rows), 256, 0, s>>>(w.idx, w.pos, rows, fq);
+    *vals = w.vals;
+    *freq = fq;
+    *idx = w.idx;
+    return hipGetLastError();
+}
 
 hipError_t pv_launch_frequency(const uint64_t *src, int rows, int K, int col, long long npad, const FreqWork &w,
                                hipStream_t s) {

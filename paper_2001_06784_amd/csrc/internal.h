@@ -259,6 +259,13 @@ hipError_t pv_launch_finalize(const unsigned long long *hist, int hd, const uint
                               const uint8_t *bad, int bn, int kcap, int kmax, int c0,
                               uint64_t *counts, uint64_t *ovf_words, int *omega, int graphs,
                               hipStream_t s);
+// the same on the device's static scratch array (no allocation): after the
+// launches *vals holds the D distinct values, *freq their multiplicities and
+// (*idx)[rows] = D.  pv_freq_static_init resolves the array's address, once
+// per device, with that device current; rows, npad <= PV_FREQ_STATIC_ROWS.
+hipError_t pv_freq_static_init(int device);
+hipError_t pv_launch_frequency_static(int device, const uint64_t *src, int rows, int K, int col, long long npad,
+                                      uint64_t **vals, uint64_t **freq, int **idx, hipStream_t s);
 // counters[PV_CTR_HP] += sum over leaves of h + p, counters[PV_CTR_PP] +=
 // sum over leaves of p + 1, from graphs [hd][hd] leaf histograms
 hipError_t pv_launch_leaf_moments(const unsigned long long *hist, int hd, int graphs,

@@ -36,6 +36,7 @@ PV_DEDUP = 2
 PV_SYMMETRIZE = 4
 PV_MAX_ALPHA = 4096
 PV_MAX_LOCAL_K = 16
+PV_FREQ_STATIC_ROWS = 1 << 20
 
 # every function declared in include/pivoter.h
 ABI_FUNCTIONS = [
@@ -44,7 +45,7 @@ ABI_FUNCTIONS = [
     "pv_last_error",
     "pv_graph_load_csr", "pv_graph_load_csr_device", "pv_graph_free", "pv_graph_size",
     "pv_graph_orient", "pv_graph_export_order", "pv_count_global", "pv_count_global_wide", "pv_count_local",
-    "pv_local_frequency",
+    "pv_local_frequency", "pv_local_frequency_static",
     "pv_graph_edge_list", "pv_count", "pv_count_roots", "pv_count_batch", "pv_count_global_batch",
     "pv_server_start", "pv_server_submit", "pv_server_wait", "pv_server_poll", "pv_server_cancel",
     "pv_server_stats", "pv_server_stop", "pv_autotune", "pv_tune_key",
@@ -171,6 +172,7 @@ def _lib():
             "pv_count_global": (i32, [vp, i32, u128p, i32, i32p, u64p, sp]),
             "pv_count_global_wide": (i32, [vp, i32, u64p, i32, i32, i32p, u64p, sp]),
             "pv_local_frequency": (i32, [vp, vp, i64, i32, i32, u128p, u64p, i64, C.POINTER(C.c_int64)]),
+            "pv_local_frequency_static": (i32, [vp, vp, i64, i32, i32, u128p, u64p, i64, C.POINTER(C.c_int64)]),
             "pv_count_local": (i32, [vp, i32, i32, i32, u128p, i64, u64p, sp]),
             "pv_graph_edge_list": (i32, [vp, i32p, i32p]),
             "pv_count": (i32, [vp, i32, i32, u128p, i32, i32p, u64p, i32, i32, i32, vp, u64p, sp]),
@@ -366,6 +368,19 @@ def pv_local_frequency(ctx: int, local_ptr: int, rows: int, K: int, col: int):
     _check(_lib().pv_local_frequency(ctx, local_ptr, rows, K, col, vals.ctypes.data_as(C.POINTER(pv_u128)),
                                      freq.ctypes.data_as(C.POINTER(C.c_uint64)), cap, C.byref(nd)),
            "pv_local_frequency")
+    D = nd.value
+    return [int(vals[i, 0]) | (int(vals[i, 1]) << 64) for i in range(D)], freq[:D]
+
+
+def pv_local_frequency_static(ctx: int, local_ptr: int, rows: int, K: int, col: int, cap: int | None = None):
+    """pv_local_frequency on the library's fixed scratch (no allocation)."""
+    cap = max(rows, 1) if cap is None else cap
+    vals = np.zeros((max(cap, 1), 2), dtype=np.uint64)
+    freq = np.zeros(max(cap, 1), dtype=np.uint64)
+    nd = C.c_int64()
+    _check(_lib().pv_local_frequency_static(ctx, local_ptr, rows, K, col, vals.ctypes.data_as(C.POINTER(pv_u128)),
+                                            freq.ctypes.data_as(C.POINTER(C.c_uint64)), cap, C.byref(nd)),
+           "pv_local_frequency_static")
     D = nd.value
     return [int(vals[i, 0]) | (int(vals[i, 1]) << 64) for i in range(D)], freq[:D]
 

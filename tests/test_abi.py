@@ -58,6 +58,7 @@ def test_header_constants_match_binding():
         m = re.search(rf"#define {name}\s+(-?\d+)u?\b", hdr)
         assert m, name
         assert int(m.group(1)) == getattr(P, name), name
+    assert "#define PV_FREQ_STATIC_ROWS (1 << 20)" in hdr and P.PV_FREQ_STATIC_ROWS == 1 << 20
     assert ctypes.sizeof(P.pv_u128) == 16
     assert ctypes.sizeof(P.pv_stats) == 160
     assert ctypes.sizeof(P.pv_config) == 40
