@@ -156,7 +156,7 @@ struct Workspace {
     DBuf<uint64_t> hu_rows, u_rows;
     DBuf<int> hu_vl, u_gid, pref_pool;
     DBuf<int2> u_pref;
-    DBuf<unsigned long long> hist, counters;
+    DBuf<unsigned long long> hist, counters, phase;
     DBuf<uint64_t> counts, ovf, vout_own;
     DBuf<int> omegas;
     DBuf<int> u_root;  // batches: root vertex of every universe
@@ -201,6 +201,7 @@ struct Workspace {
         u_pref.release();
         hist.release();
         counters.release();
+        phase.release();
         cready.release();
         mready.release();
         pctl.release();
@@ -241,6 +242,7 @@ struct pv_ctx {
     PersistCtl *h_pctl = nullptr;  // pinned readback of the persistent walk's control block
     int level_blocks[6][4] = {};  // [kernel variant, see variant_of][unit kind, or PV_UNITS_ALL]
     bool persist = false;  // one persistent launch per walk (PV_PERSIST set) instead of level by level
+    bool phase_on = false; // per-level phase times (PV_PHASE set; builds with PV_PHASE_TIMING)
     int dfs_max = 64;
     int dfs_budget = 0;  // 0: chosen per request (see budget_of)
     int lane_max = PV_LANE_MAX;
@@ -385,6 +387,7 @@ extern "C" pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out)
     if (const char *env = getenv("PV_DFS_MAX")) c->dfs_max = std::max(1, std::min(64, atoi(env)));
     c->debug = getenv("PV_DEBUG") != nullptr;
     c->persist = getenv("PV_PERSIST") != nullptr;
+    c->phase_on = getenv("PV_PHASE") != nullptr;
     if (const char *env = getenv("PV_DFS_BUDGET")) c->dfs_budget = std::max(16, std::min(1 << 20, atoi(env)));
     if (const char *env = getenv("PV_LANE_MAX")) c->lane_max = std::max(0, std::min(PV_LANE_MAX, atoi(env)));
     if (const char *env = getenv("PV_PREFIX_ROWS")) c->prefix_rows = std::max(0, atoi(env));
@@ -1178,6 +1181,13 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                 }
                 a.dfs_budget = budget_of(c, local, units,
                                          (long long)c->level_blocks[kli][PV_UNITS_ITEMS] * WAVES_PER_LAUNCH_BLOCK);
+                if (c->phase_on) {
+                    // per-phase times of this level's units (libraries built
+                    // with PV_PHASE_TIMING fill them)
+                    PVCHK(c->ws.phase.ensure(48));
+                    HIPCHK(hipMemsetAsync(c->ws.phase.p, 0, 48 * sizeof(unsigned long long), s));
+                    a.phase = c->ws.phase.p;
+                }
                 *c->h_args = a;
                 HIPCHK(hipMemsetAsync(g->small.p + SM_NEXT, 0, 5 * sizeof(int), s));
                 HIPCHK(hipMemcpyAsync(c->d_args.p, c->h_args, sizeof(LevelArgs), hipMemcpyHostToDevice, s));
@@ -1214,6 +1224,19 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                         fprintf(stderr, "[pivoter] level %d: %.2f ms (multi-word %lld units %.2f ms, items %lld %.2f ms, "
                                 "light roots %lld %.2f ms)\n", level, lv, mode_units[0], km[0], mode_units[1], km[1],
                                 mode_units[2], km[2]);
+                }
+                if (c->phase_on) {
+                    unsigned long long ph[48];
+                    HIPCHK(hipMemcpy(ph, c->ws.phase.p, sizeof ph, hipMemcpyDeviceToHost));
+                    for (int mode = 0; mode < 3; mode++) {
+                        const unsigned long long *q = ph + 16 * mode;
+                        if (!q[15]) continue;
+                        fprintf(stderr, "[phase] level %d kind %d: waves %llu, per wave us: life %.1f", level, mode,
+                                q[15], q[12 + mode] * 0.01 / q[15]);
+                        for (int i = 0; i < 12; i++)
+                            if (q[i]) fprintf(stderr, " p%d %.1f", i, q[i] * 0.01 / q[15]);
+                        fprintf(stderr, "\n");
+                    }
                 }
                 if (c->debug)
                     fprintf(stderr, "[pivoter] attempt %d level %d: mw %d items %d universes %d prefix %d "

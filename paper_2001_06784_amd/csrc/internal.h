@@ -165,6 +165,9 @@ struct LevelArgs {
     int *u_root;                   // [u_cap] root vertex of each universe (batch only)
     // persistent walk (unit kind PV_UNITS_ALL); persist = 0: level by level
     int persist;
+    // phase times per unit kind ([3][16] ticks), filled by builds with
+    // PV_PHASE_TIMING only (nullptr: off)
+    unsigned long long *phase;
     PersistCtl *pctl;
     int *cready, *mready;          // per queue slot: 0 not yet written, 1 written, 2 never written
     int c_scap, m_cap;             // compact slots per slice; multi-word slots

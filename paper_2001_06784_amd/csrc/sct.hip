@@ -657,6 +657,23 @@ struct Ctr {
     unsigned long long nodes, work, child;
 };
 
+// Phase timing (built with -DPV_PHASE_TIMING only): wall time per phase of
+// a wave's units, summed over waves, in 10 ns ticks of s_memrealtime.
+#ifdef PV_PHASE_TIMING
+#define PT_N 16
+// sub-phase sums of compact walks, per wave in LDS: [0] lane batches, [1]
+// leaf read-off of the wave tier
+__device__ __forceinline__ unsigned long long *pt_sub() {
+    __shared__ unsigned long long s_pt_sub[WAVES_PER_BLOCK][2];
+    return s_pt_sub[threadIdx.x >> 6];
+}
+#define PT_MARK(t) const uint64_t t = __builtin_amdgcn_s_memrealtime()
+#define PT_ADD(slot, t0) (pt[slot] += __builtin_amdgcn_s_memrealtime() - (t0))
+#else
+#define PT_MARK(t)
+#define PT_ADD(slot, t0)
+#endif
+
 template <int KL, int LK>
 __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelArgs &a,
                              int root, int grp, uint64_t Hw, uint64_t Pw, const int *vl, int W,
@@ -690,6 +707,13 @@ template <int KL>
 __device__ __forceinline__ lds_u64 *lane_acc() {
     __shared__ unsigned long long s_lacc[WAVES_PER_BLOCK][64 * (KL + 1)];
     return (lds_u64 *)s_lacc[threadIdx.x >> 6];
+}
+
+// the lane tier's depth-first frames of this wave: frame t of lane l at
+// [t][l]; at most PV_LANE_MAX - 1 frames (each needs |S| >= 2, sets shrink)
+__device__ __forceinline__ uint32_t (*lane_frames())[64] {
+    __shared__ uint32_t s_lst[WAVES_PER_BLOCK][PV_LANE_MAX - 1][64];
+    return s_lst[threadIdx.x >> 6];
 }
 
 // Walk the queued subtrees: lane i < qn holds node qS (a set of at most
@@ -740,9 +764,7 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
     uint32_t S = smask;
     uint32_t Hl = 0, Pl = 0;  // hold / pivot members taken inside the subtree (local masks)
     int depth = 0;
-    // at most PV_LANE_MAX - 1 frames: each needs |S| >= 2 and sets shrink
-    __shared__ uint32_t s_lst[WAVES_PER_BLOCK][PV_LANE_MAX - 1][64];
-    uint32_t(*st)[64] = s_lst[threadIdx.x >> 6];
+    uint32_t(*st)[64] = lane_frames();
     lds_u64 *acc = nullptr;
     if constexpr (LOC) {
         acc = lane_acc<KL>();
@@ -1085,7 +1107,13 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                     qmP |= (uint64_t)inP << qn;
                 }
                 if (++qn == 64) {
+#ifdef PV_PHASE_TIMING
+                    const uint64_t t_lw = __builtin_amdgcn_s_memrealtime();
+#endif
                     lane_walk<KL, LOCAL>(A, qS, qmH, qmP, qhp, qn, lane, hlim, gs, vs, nodes, work, nleaves);
+#ifdef PV_PHASE_TIMING
+                    if (lane == 0) pt_sub()[0] += __builtin_amdgcn_s_memrealtime() - t_lw;
+#endif
                     qn = 0;
                     qmH = qmP = 0;
                 }
@@ -1150,8 +1178,14 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
             }
             // a leaf: S is empty (or a clique folded into P above)
             nleaves++;
+#ifdef PV_PHASE_TIMING
+            const uint64_t t_lf = __builtin_amdgcn_s_memrealtime();
+#endif
             gs.leaf(h, p, lane);
             if (LOCAL) vs.leaf(h, p, H, P, lane, a);
+#ifdef PV_PHASE_TIMING
+            if (lane == 0) pt_sub()[1] += __builtin_amdgcn_s_memrealtime() - t_lf;
+#endif
         }
         visit = true;
         if (depth == 0) break;
@@ -1210,8 +1244,15 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
         }
     }
     if constexpr (LANE) {
-        if (qn > 0)
+        if (qn > 0) {
+#ifdef PV_PHASE_TIMING
+            const uint64_t t_lw = __builtin_amdgcn_s_memrealtime();
+#endif
             lane_walk<KL, LOCAL>(A, qS, qmH, qmP, qhp, qn, lane, hlim, gs, vs, nodes, work, nleaves);
+#ifdef PV_PHASE_TIMING
+            if (lane == 0) pt_sub()[0] += __builtin_amdgcn_s_memrealtime() - t_lw;
+#endif
+        }
     }
     if (LOCAL) vs.leave(H | P, H, P, lane, gid);
     ct.nodes += nodes;
@@ -1403,21 +1444,36 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
 // Node sets over a heavy universe of up to 64*W vertices, lane w holding
 // word w.  Rows are word-major in HBM: row u, word w at rows[w*dpad + u].
 
+// Word w of member u's row: from HBM (stride dpad) or from a copy staged in
+// LDS for the unit (same layout).
+struct RowsG {
+    const uint64_t *p;
+    int stride;
+    __device__ __forceinline__ uint64_t operator()(int w, int u) const { return p[(long long)w * stride + u]; }
+};
+struct RowsL {
+    const lds_u64 *p;
+    int stride;
+    __device__ __forceinline__ uint64_t operator()(int w, int u) const { return p[w * stride + u]; }
+};
+
 // Returns true with a compact start state (A, S0, nm, gid, uni, root,
 // pref, h, p) once |S| <= 64, false if the buffers were full.
 struct CState {
     uint64_t A, S, H, P;
     int h, p, uni, nm, gid, root;
     int2 pref;
+#ifdef PV_PHASE_TIMING
+    uint64_t t_re;  // time of the re-index into a compact universe
+#endif
 };
 
-template <int KL, int LK>
-__device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int p, int lane,
+template <int KL, int LK, class R>
+__device__ bool mw_run(R rows, int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int p, int lane,
                        const LevelArgs &a, Ctr &ct, int *memb, CState &cs) {
     constexpr bool EDGE = LK == PV_LK_EDGE;
     constexpr bool LOCAL = KL > 0;
     const int W = a.W, dpad = a.dpad;
-    const uint64_t *rows = a.hu_rows + (long long)hu * W * dpad;
     const int *vl = a.hu_vl + (long long)hu * dpad;
     const int root = a.order[a.heavy_base + hu];
     const bool wl = lane < W;
@@ -1427,6 +1483,9 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
     for (;;) {
         const int s = (int)wave_add_u32(wl ? (uint32_t)__popcll(Sw) : 0u);
         if (s <= PV_LIGHT_MAX) {
+#ifdef PV_PHASE_TIMING
+            const uint64_t t_r = __builtin_amdgcn_s_memrealtime();
+#endif
             // re-index S into a compact universe (members in id order)
             int base = 0;
             for (int t = 0; t < W; t++) {
@@ -1438,12 +1497,21 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
             wave_sync();
             const int mj = (lane < s) ? memb[lane] : 0;
             wave_sync();
+            // member lane's row over the members (bit c: member c, in id
+            // order): its row words, all read at once, each compressed to
+            // the members of that word
+            uint64_t rw[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) rw[t] = (t < W && lane < s) ? rows(t, mj) : 0ull;
             uint64_t A = 0;
-            for (int c = 0; c < s; c++) {
-                const int mc = (int)readlane32((uint32_t)mj, c);
-                bool bit = false;
-                if (lane < s) bit = (rows[(long long)(mj >> 6) * dpad + mc] >> (mj & 63)) & 1;
-                A = writelane64(A, ballot64(bit), c);
+            int c0 = 0;
+            for (int t = 0; t < W; t++) {
+                const uint64_t St = readlane64(Sw, t);
+                const uint64_t r = (t < 4) ? (t == 0 ? rw[0] : t == 1 ? rw[1] : t == 2 ? rw[2] : rw[3])
+                                           : ((lane < s) ? rows(t, mj) : 0ull);
+                int c = c0;
+                for (uint64_t m = St; m; m &= m - 1, c++) A |= ((r >> __builtin_ctzll(m)) & 1ull) << c;
+                c0 = c;
             }
             const int gid = (lane < s) ? vl[mj] : -1;
             int2 pref = make_int2(0, 0);
@@ -1463,6 +1531,9 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
             cs.gid = gid;
             cs.root = -1;
             cs.pref = pref;
+#ifdef PV_PHASE_TIMING
+            cs.t_re = __builtin_amdgcn_s_memrealtime() - t_r;
+#endif
             return true;
         }
         ct.nodes++;
@@ -1474,8 +1545,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
             const int u = t * 64 + lane;
             if ((St >> lane) & 1) {
                 uint32_t c = 0;
-                for (int w = 0; w < W; w++) c += (uint32_t)__popcll(rows[(long long)w * dpad + u] &
-                                                                    readlane64(Sw, w));
+                for (int w = 0; w < W; w++) c += (uint32_t)__popcll(rows(w, u) & readlane64(Sw, w));
                 best = max(best, ((c + 1u) << 12) | (uint32_t)(4095 - u));
             }
         }
@@ -1484,7 +1554,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
         const int pc = (int)(best >> 12) - 1;
         const int pw = piv >> 6;
         const uint64_t pb = (lane == pw) ? (1ull << (piv & 63)) : 0ull;
-        const uint64_t Ap = wl ? rows[(long long)lane * dpad + piv] : 0ull;
+        const uint64_t Ap = wl ? rows(lane, piv) : 0ull;
         {
             // the pivot child and the hold children are formed word by word
             const bool holds = pc + 1 != s && !(a.kmax > 0 && h + 1 > a.kmax);
@@ -1504,7 +1574,7 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
                     const uint64_t vb = (lane == w0) ? (1ull << (v & 63)) : 0ull;
                     uint64_t *it = a.mw_out + (long long)(slot + i) * a.mw_stride;
                     if (wl) {
-                        it[lane] = rows[(long long)lane * dpad + v] & Scur;
+                        it[lane] = rows(lane, v) & Scur;
                         it[W + lane] = Hw | vb;
                         it[2 * W + lane] = Pw;
                     }
@@ -1529,17 +1599,21 @@ __device__ bool mw_run(int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, int h, int
 // w in N+(v) at position i means u_j ~ u_i (each edge inside N+(v) is seen
 // once, from its smaller-key end).
 
-__device__ uint64_t gather_light(int v, int lane, const LevelArgs &a, int *s_vl, int *s_pre,
+__device__ uint64_t gather_light(int v, int lane, const LevelArgs &a, int *s_vl, int *s_pre, int *s_base,
                                  unsigned long long *s_A, int &d, int &gid, int *etab) {
     const int b = a.orow[v];
     d = a.orow[v + 1] - b;
     const int u = (lane < d) ? a.ocol[b + lane] : 0x7fffffff;
     gid = (lane < d) ? u : -1;
-    const int od = (lane < d) ? (a.orow[u + 1] - a.orow[u]) : 0;
+    const int ub = (lane < d) ? a.orow[u] : 0;
+    const int od = (lane < d) ? (a.orow[u + 1] - ub) : 0;
     const int incl = wave_incl_scan(od);
     const int total = (int)readlane32((uint32_t)incl, 63);
     s_vl[lane] = u;
     s_pre[lane] = incl - od;
+    // edge q of the flattened lists sits at ocol[s_base[j] + q] (member j
+    // owning q): no second read of the row pointers
+    s_base[lane] = ub - (incl - od);
     s_A[lane] = 0ull;
     wave_sync();
     for (int q0 = 0; q0 < total; q0 += 64) {
@@ -1551,7 +1625,7 @@ __device__ uint64_t gather_light(int v, int lane, const LevelArgs &a, int *s_vl,
                 if (s_pre[mid] <= q) lo = mid; else hi = mid - 1;
             }
             const int j = lo;
-            const int pos = a.orow[s_vl[j]] + (q - s_pre[j]);
+            const int pos = s_base[j] + q;
             const int w = a.ocol[pos];
             int l2 = 0, h2 = d;
             while (l2 < h2) {
@@ -1608,6 +1682,87 @@ __device__ void gather_heavy(int hu, int v, int lane, const LevelArgs &a) {
             }
         }
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The same gather with the universe built in LDS (W <= 3): rows at
+// lrows[w * dpad + u] (the HBM layout), member ids in lvl.  The members'
+// out-lists are flattened: lane q of a pass takes edge q of their
+// concatenation, finds its owner j by binary search over the exclusive
+// prefix of the out-degrees (held in registers, member j in lane j % 64,
+// slot j / 64) and the other end among the members by binary search in
+// LDS, and sets the pair's two bits with LDS atomics.  The rows and ids are
+// then copied to HBM for the universe's units at later levels.
+__device__ __forceinline__ int slot_of(int v0, int v1, int v2, int m) {
+    const int src = m & 63;
+    const int a0 = __shfl(v0, src, 64), a1 = __shfl(v1, src, 64), a2 = __shfl(v2, src, 64);
+    const int sl = m >> 6;
+    return sl == 0 ? a0 : (sl == 1 ? a1 : a2);
+}
+
+__device__ void gather_heavy_lds(int hu, int v, int lane, const LevelArgs &a, lds_u64 *lrows, int *lvl) {
+    const int W = a.W, dpad = a.dpad;
+    uint64_t *rows = a.hu_rows + (long long)hu * W * dpad;
+    int *vl = a.hu_vl + (long long)hu * dpad;
+    const int b = a.orow[v];
+    const int d = a.orow[v + 1] - b;  // <= dpad <= 192
+    int id[3], st[3], ln[3];
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+        const int j = t * 64 + lane;
+        id[t] = (j < d) ? a.ocol[b + j] : 0x7fffffff;
+    }
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+        const int j = t * 64 + lane;
+        st[t] = (j < d) ? a.orow[id[t]] : 0;
+        ln[t] = (j < d) ? a.orow[id[t] + 1] - st[t] : 0;
+        if (j < dpad) lvl[j] = id[t];
+    }
+    for (int i = lane; i < W * dpad; i += 64) lrows[i] = 0ull;
+    // exclusive prefix of the out-degrees over the members, and each
+    // member's base: edge q of member j sits at ocol[base_j + q]
+    int off[3], base[3];
+    int run = 0;
+#pragma unroll
+    for (int t = 0; t < 3; t++) {
+        const int incl = wave_incl_scan(ln[t]);
+        off[t] = run + incl - ln[t];
+        base[t] = st[t] - off[t];
+        run += (int)readlane32((uint32_t)incl, 63);
+    }
+    const int total = run;
+    wave_sync();
+    for (int q0 = 0; q0 < total; q0 += 64) {
+        const int q = q0 + lane;
+        // owner: the last member j < d with off_j <= q (uniform trip count)
+        int j = 0;
+#pragma unroll
+        for (int step = 128; step > 0; step >>= 1) {
+            const int m = j + step;
+            const int om = slot_of(off[0], off[1], off[2], min(m, d - 1));
+            if (m < d && om <= q) j = m;
+        }
+        const int bj = slot_of(base[0], base[1], base[2], j);
+        if (q < total) {
+            const int w = a.ocol[bj + q];
+            // w's position among the members: how many ids are below it
+            int pos = 0;
+#pragma unroll
+            for (int step = 128; step > 0; step >>= 1)
+                if (pos + step <= d && lvl[pos + step - 1] < w) pos += step;
+            if (pos < d && lvl[pos] == w) {
+                __hip_atomic_fetch_or(lrows + (pos >> 6) * dpad + j, 1ull << (pos & 63), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_or(lrows + (j >> 6) * dpad + pos, 1ull << (j & 63), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    wave_sync();
+    for (int i = lane; i < W * dpad; i += 64) rows[i] = lrows[i];
+    for (int i = lane; i < dpad; i += 64) vl[i] = lvl[i];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
     __builtin_amdgcn_wave_barrier();
 }
@@ -1691,6 +1846,12 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
     }
     Ctr ct;
     ct.nodes = ct.work = ct.child = 0;
+#ifdef PV_PHASE_TIMING
+    uint64_t pt[PT_N];
+    for (int i = 0; i < PT_N; i++) pt[i] = 0;
+    if (lane == 0) pt_sub()[0] = pt_sub()[1] = 0ull;
+    PT_MARK(pt_kernel0);
+#endif
     constexpr int CK = MODE == PV_UNITS_ALL ? PV_UNITS_LIGHT : MODE;  // the claim cursor of a static range
     int *cursor = a.next + CK;
     const int claim_n0 = uniformi(a.n0[CK]), claim_nch = uniformi(a.nch[CK]);
@@ -1706,6 +1867,13 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
             if (idx < 0) break;
             int hu, h = 1, p = 0;
             uint64_t Sw = 0, Hw = 0, Pw = 0;
+            // the universe's rows staged in LDS for the unit (per vertex with
+            // 64-bit sums, W <= 3): in the lane tier's slots, which the
+            // walk below needs only after the multi-word part and which
+            // are cleared again before it
+            constexpr bool STAGE = LOCAL && LK == PV_LK_VERTEX64 && KL == 8;
+            const bool staged = STAGE && a.W <= 3 && a.W * a.dpad <= 64 * (KL + 1);
+            lds_u64 *lrows = STAGE ? lane_acc<KL>() : nullptr;
             if (idx < n0) {
                 const uint64_t *it = a.mw_in + (long long)idx * a.mw_stride;
                 const bool wl = lane < a.W;
@@ -1717,10 +1885,18 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
                 const uint32_t hp = (uint32_t)(meta >> 32);
                 h = (int)(hp & 0xFFFFu);
                 p = (int)(hp >> 16);
+                if (staged) {
+                    const uint64_t *src = a.hu_rows + (long long)uniformi(hu) * a.W * a.dpad;
+                    for (int i = lane; i < a.W * a.dpad; i += 64) lrows[i] = src[i];
+                    wave_sync();
+                }
             } else {
                 hu = idx - n0;
                 const int v = a.order[a.heavy_base + hu];
-                gather_heavy(hu, v, lane, a);
+                PT_MARK(t_g);
+                if (staged) gather_heavy_lds(hu, v, lane, a, lrows, (int *)lane_frames());
+                else gather_heavy(hu, v, lane, a);
+                PT_ADD(0, t_g);
                 const int d = a.orow[v + 1] - a.orow[v];
                 // root node N+(v): every member; the root is the first hold vertex
                 if (lane < a.W) {
@@ -1730,11 +1906,31 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
             }
             gs.set_vertex(a.order[a.heavy_base + hu]);
             CState cs;
-            if (mw_run<KL, LK>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs)) {
+            PT_MARK(t_m);
+            bool ok;
+            if (staged) {
+                ok = mw_run<KL, LK>(RowsL{lrows, a.dpad}, hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs);
+                // the lane tier's slots start at zero
+                wave_sync();
+                for (int i = lane; i < a.W * a.dpad; i += 64) lrows[i] = 0ull;
+                wave_sync();
+            } else {
+                ok = mw_run<KL, LK>(RowsG{a.hu_rows + (long long)uniformi(hu) * a.W * a.dpad, a.dpad}, hu, Sw, Hw,
+                                    Pw, h, p, lane, a, ct, s_memb[wv], cs);
+            }
+            PT_ADD(1, t_m);
+#ifdef PV_PHASE_TIMING
+            if (ok) pt[10] += cs.t_re;
+#endif
+            if (ok) {
                 if (EDGE) vs.set_table(a.ueid + (long long)cs.uni * 4096);
+                PT_MARK(t_c);
                 compact_run<KL, LK>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
                                 cs.pref, lane, a, gs, vs, ct);
+                PT_ADD(2, t_c);
+                PT_MARK(t_f);
                 if (LOCAL) vs.flush(lane, cs.nm, cs.gid, cs.root, cs.pref, cs.uni, a);
+                PT_ADD(3, t_f);
             }
         }
     } else if constexpr (MODE == PV_UNITS_ITEMS) {
@@ -1742,6 +1938,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
         for (;;) {
             const int idx = claim.next(cursor, n, claim_n0, claim_nch, lane);
             if (idx < 0) break;
+            PT_MARK(t_l);
             const CItem it = a.c_in[idx];
             const uint32_t uw = uniform32(it.uni);
             const int u = (int)(uw & 0x7fffffffu);
@@ -1756,9 +1953,14 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
             }
             const int nm = (int)wave_add_u32(gid >= 0 ? 1u : 0u);
             if (EDGE) vs.set_table(a.ueid + (long long)u * 4096);
+            PT_ADD(4, t_l);
+            PT_MARK(t_c);
             compact_run<KL, LK>(A, it.S, it.H, it.P, (int)(it.hp & 0xFFFFu), (int)(it.hp >> 16), u, nm,
                             gid, -1, pref, lane, a, gs, vs, ct, fr, it.hp);
+            PT_ADD(5, t_c);
+            PT_MARK(t_f);
             if (LOCAL) vs.flush(lane, nm, gid, -1, pref, u, a);
+            PT_ADD(6, t_f);
         }
     } else if constexpr (MODE == PV_UNITS_ALL) {
         // The persistent walk: units in order of preference -- multi-word
@@ -1771,6 +1973,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
         __shared__ int s_memb[WAVES_PER_BLOCK][64];
         __shared__ int s_vl[WAVES_PER_BLOCK][64];
         __shared__ int s_pre[WAVES_PER_BLOCK][64];
+        __shared__ int s_base[WAVES_PER_BLOCK][64];
         __shared__ unsigned long long s_A[WAVES_PER_BLOCK][64];
         int *etab_w = EDGE ? a.weid + (long long)(blockIdx.x * WAVES_PER_BLOCK + wv) * 4096 : nullptr;
         PersistCtl *pc = (PersistCtl *)uniform64((uint64_t)a.pctl);
@@ -1836,7 +2039,8 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
                     if (!skip) {
                         gs.set_vertex(a.order[a.heavy_base + hu]);
                         CState cs;
-                        if (mw_run<KL, LK>(hu, Sw, Hw, Pw, h, p, lane, a, ct, s_memb[wv], cs)) {
+                        if (mw_run<KL, LK>(RowsG{a.hu_rows + (long long)hu * a.W * a.dpad, a.dpad}, hu, Sw, Hw, Pw, h,
+                                           p, lane, a, ct, s_memb[wv], cs)) {
                             if (EDGE) vs.set_table(a.ueid + (long long)cs.uni * 4096);
                             compact_run<KL, LK>(cs.A, cs.S, cs.H, cs.P, cs.h, cs.p, cs.uni, cs.nm, cs.gid, cs.root,
                                                 cs.pref, lane, a, gs, vs, ct);
@@ -1882,7 +2086,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
                     gs.set_vertex(v);
                     if (EDGE) vs.set_table(etab_w);
                     int d, gid;
-                    const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_A[wv], d, gid, etab_w);
+                    const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_base[wv], s_A[wv], d, gid, etab_w);
                     int uni = -1;
                     int2 pref = make_int2(0, 0);
                     bool ok = true;
@@ -1939,6 +2143,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
     } else {
         __shared__ int s_vl[WAVES_PER_BLOCK][64];
         __shared__ int s_pre[WAVES_PER_BLOCK][64];
+        __shared__ int s_base[WAVES_PER_BLOCK][64];
         __shared__ unsigned long long s_A[WAVES_PER_BLOCK][64];
         const int n = a.nlight;
         // per-edge counts: this wave's table of member-pair edge ids
@@ -1950,13 +2155,16 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
             const int v = a.order[a.light_base + idx];
             gs.set_vertex(v);
             int d, gid;
-            const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_A[wv], d, gid, etab_w);
+            PT_MARK(t_g);
+            const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_base[wv], s_A[wv], d, gid, etab_w);
             int uni = -1;
             int2 pref = make_int2(0, 0);
             if (d > a.dfs_max) {
                 uni = make_universe<KL, LK>(A, d, gid, lane, a, v, -1, 0ull, 0ull, nullptr, 0, pref, etab_w);
                 if (uni < 0) continue;  // buffers full: the host reruns with larger ones
             }
+            PT_ADD(7, t_g);
+            PT_MARK(t_c);
             const int root = (uni < 0) ? v : -1;
             // light roots walk small trees (about 13 nodes on average on a
             // power-law graph) and rarely fill a lane batch: the lane tier is
@@ -1965,7 +2173,10 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
             // 6.1 ms per vertex)
             compact_run<KL, LK, false>(A, (d == 64) ? ~0ull : ((1ull << d) - 1), 0ull, 0ull, 1, 0, uni, d, gid,
                             root, pref, lane, a, gs, vs, ct);
+            PT_ADD(8, t_c);
+            PT_MARK(t_f);
             if (LOCAL) vs.flush(lane, d, gid, root, pref, uni, a);
+            PT_ADD(9, t_f);
         }
     }
     __syncthreads();
@@ -1984,6 +2195,16 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
             atomicAdd(&a.counters[4 + MODE], ct.work);
         }
         if (ct.child) atomicAdd(&a.counters[PV_CTR_CHILD], ct.child);
+#ifdef PV_PHASE_TIMING
+        if (a.phase) {
+            PT_ADD(12 + (MODE < 3 ? MODE : 0), pt_kernel0);
+            pt[15] = 1;  // waves
+            pt[11] = pt_sub()[0];
+            if (MODE != 0) pt[10] = pt_sub()[1];  // (kind 0 keeps slot 10 for its re-index)
+            for (int i = 0; i < PT_N; i++)
+                if (pt[i]) atomicAdd(&a.phase[(MODE < 3 ? MODE : 0) * PT_N + i], (unsigned long long)pt[i]);
+        }
+#endif
     }
 }
 
