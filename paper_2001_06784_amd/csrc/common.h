@@ -29,15 +29,28 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t x, int l) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// This lane's index computed afresh where it is used: a lane index the
+// compiler hoists out of a walk's loop is one more register live across
+// it, and under pressure it spills and comes back by a scratch load per
+// use.  (volatile: neither hoisted nor merged; two VALU instructions)
+__device__ __forceinline__ int lane_id_here() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+#else
+    return lane_id();
+#endif
+}
+
 // x with lane `l` replaced by the wave-uniform value v (a compare and a
-// select per 32-bit half; the compare is shared when several registers are
-// written at the same lane)
+// select per 32-bit half)
 __device__ __forceinline__ uint32_t writelane32(uint32_t x, uint32_t v, int l) {
-    return (lane_id() == l) ? v : x;
+    return (lane_id_here() == l) ? v : x;
 }
 
 __device__ __forceinline__ uint64_t writelane64(uint64_t x, uint64_t v, int l) {
-    return (lane_id() == l) ? v : x;
+    return (lane_id_here() == l) ? v : x;
 }
 
 // A value every lane holds alike, moved to scalar registers.  Values that
@@ -76,6 +89,19 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     x = max(x, dpp_mov<0x140, 0xF>(x));  // row_mirror
     x = max(x, dpp_mov<0x142, 0xA>(x));  // row_bcast15 -> rows 1,3
     x = max(x, dpp_mov<0x143, 0xC>(x));  // row_bcast31 -> rows 2,3
+    return readlane32(x, 63);
+}
+
+// Full-wave sum, returned wave-uniform, by the same DPP steps as
+// wave_max_u32 (each step adds a disjoint partial sum; lanes outside a
+// row mask read 0, the identity).  Every lane of the wave must be active.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
+    x += dpp_mov<0xB1, 0xF>(x);   // quad pairs
+    x += dpp_mov<0x4E, 0xF>(x);   // quads
+    x += dpp_mov<0x141, 0xF>(x);  // half rows (the other quad)
+    x += dpp_mov<0x140, 0xF>(x);  // rows (the other half)
+    x += dpp_mov<0x142, 0xA>(x);  // rows 1, 3 add rows 0, 2
+    x += dpp_mov<0x143, 0xC>(x);  // rows 2, 3 add rows 0 + 1
     return readlane32(x, 63);
 }
 

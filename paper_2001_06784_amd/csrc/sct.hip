@@ -858,9 +858,9 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
         Hl = ((F >> 11) & 0xFFu) | (1u << v);
         Pl = (F >> 19) & 0xFFu;
     }
-    nodes += wave_add_u32(nn);
-    work += wave_add_u32(ww);
-    nleaves += wave_add_u32(nl);
+    nodes += wave_sum_u32(nn);
+    work += wave_sum_u32(ww);
+    nleaves += wave_sum_u32(nl);
     if constexpr (LOC) {
         // members taken inside the subtrees: their LDS slots (then cleared)
         wave_sync();
@@ -1376,7 +1376,7 @@ __device__ int make_universe(uint64_t A, int nm, int gid, int lane, const LevelA
         // prefix: the root plus the hold and pivot vertices above (word-major
         // multi-word sets Hw/Pw, lane w = word w)
         const int nh = (lane < W) ? __popcll(Hw) : 0, np = (lane < W) ? __popcll(Pw) : 0;
-        const int tot = (int)wave_add_u32((uint32_t)(nh + np)) + 1;
+        const int tot = (int)wave_sum_u32((uint32_t)(nh + np)) + 1;
         int off = 0;
         if (lane == 0) off = atomicAdd(a.pref_n, tot);
         off = bcast0(off);
@@ -1481,7 +1481,7 @@ __device__ bool mw_run(R rows, int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, in
     // truncated tree: at h = k_max the subtree is one leaf (see compact_dfs)
     if (a.kmax > 0 && h >= a.kmax) Sw = 0;
     for (;;) {
-        const int s = (int)wave_add_u32(wl ? (uint32_t)__popcll(Sw) : 0u);
+        const int s = (int)wave_sum_u32(wl ? (uint32_t)__popcll(Sw) : 0u);
         if (s <= PV_LIGHT_MAX) {
 #ifdef PV_PHASE_TIMING
             const uint64_t t_r = __builtin_amdgcn_s_memrealtime();
@@ -1564,7 +1564,7 @@ __device__ bool mw_run(R rows, int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, in
             // hold children, increasing id, each N(S,v) minus earlier ones
             uint64_t Rw = Sw & ~Ap & ~pb;
             uint64_t Scur = Sw;
-            const int nR = (int)wave_add_u32(wl ? (uint32_t)__popcll(Rw) : 0u);
+            const int nR = (int)wave_sum_u32(wl ? (uint32_t)__popcll(Rw) : 0u);
             const int slot = reserve_mw_items(a, nR, lane);
             if (slot >= 0) {
                 for (int i = 0; i < nR; i++) {
@@ -1951,7 +1951,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
                 gid = a.u_gid[(long long)u * 64 + lane];
                 pref = a.u_pref[u];
             }
-            const int nm = (int)wave_add_u32(gid >= 0 ? 1u : 0u);
+            const int nm = (int)wave_sum_u32(gid >= 0 ? 1u : 0u);
             if (EDGE) vs.set_table(a.ueid + (long long)u * 4096);
             PT_ADD(4, t_l);
             PT_MARK(t_c);
@@ -2065,7 +2065,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
                                 gid = a.u_gid[(long long)u * 64 + lane];
                                 pref = a.u_pref[u];
                             }
-                            const int nm = (int)wave_add_u32(gid >= 0 ? 1u : 0u);
+                            const int nm = (int)wave_sum_u32(gid >= 0 ? 1u : 0u);
                             if (EDGE) vs.set_table(a.ueid + (long long)u * 4096);
                             compact_run<KL, LK>(A, it.S, it.H, it.P, (int)(it.hp & 0xFFFFu), (int)(it.hp >> 16), u,
                                                 nm, gid, -1, pref, lane, a, gs, vs, ct, fr, it.hp);
