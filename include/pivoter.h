@@ -109,6 +109,8 @@ typedef struct {
                                    operations that form the children's vertex sets */
     uint64_t leaf_hp;           /* sum over leaves of h + p: per-vertex additions per value of k */
     uint64_t leaf_pp;           /* sum over leaves of p + 1: global additions (one per k <= p + h) */
+    int32_t heavy_chunks;       /* chunks the heavy roots were walked in (their level buffers are
+                                   halved until one chunk's fit the device or the budget) */
 } pv_stats;
 
 /* Human-readable name of a status code (static string). */

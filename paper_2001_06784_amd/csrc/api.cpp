@@ -131,6 +131,9 @@ struct DBuf {
         if (e != hipSuccess) {
             set_err("hipMalloc", e);
             p = nullptr;
+            // a failed allocation is reported here; clear the runtime's
+            // last error so that a later launch check does not see it
+            (void)hipGetLastError();
             return PV_ENOMEM;
         }
         n = std::max<size_t>(need, 1);
@@ -156,7 +159,7 @@ struct Workspace {
     DBuf<uint64_t> hu_rows, u_rows;
     DBuf<int> hu_vl, u_gid, pref_pool;
     DBuf<int2> u_pref;
-    DBuf<unsigned long long> hist, counters, phase;
+    DBuf<unsigned long long> hist, counters, phase, hsnap;
     DBuf<uint64_t> counts, ovf, vout_own;
     DBuf<int> omegas;
     DBuf<int> u_root;  // batches: root vertex of every universe
@@ -184,6 +187,22 @@ struct Workspace {
     size_t pc_cap = C0, pm_cap = MW0;  // persistent walk: slots per compact slice, multi-word slots
     long long hu_budget = 1ll << 30;  // bytes of heavy universes per chunk
 
+    // the walk's level buffers only (not the orientation's temporaries, the
+    // tables, or outputs a caller's request points into)
+    void release_level() {
+        DBuf<int> *ib[] = {&hu_vl, &u_gid, &pref_pool, &u_root, &ueid, &weid, &u_grp, &pg_pos, &pg_list,
+                           &cready, &mready};
+        for (auto *b : ib) b->release();
+        citem[0].release();
+        citem[1].release();
+        mwitem[0].release();
+        mwitem[1].release();
+        DBuf<uint64_t> *ub[] = {&hu_rows, &u_rows, &umem, &utot, &escr};
+        for (auto *b : ub) b->release();
+        u_pref.release();
+        pctl.release();
+    }
+
     void release() {
         DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &lid, &uverts, &ldeg, &lrp, &lcol,
                            &bcnt, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid,
@@ -202,6 +221,7 @@ struct Workspace {
         hist.release();
         counters.release();
         phase.release();
+        hsnap.release();
         cready.release();
         mready.release();
         pctl.release();
@@ -899,6 +919,71 @@ static pv_status run_sct(pv_graph *g, const CountReq &rq) {
     return st;
 }
 
+// The walk's level buffers at the workspace's capacities: the item queues,
+// the universes and their per-count extras, the heavy roots' rows of one
+// chunk.  PV_ENOMEM if they do not fit (the device or the budget).
+static pv_status level_buffers(pv_ctx *c, pv_graph *g, const CountReq &rq, bool persist, int mw_stride, int chunk,
+                               int W, int dpad) {
+    const bool local = rq.kl > 0;
+    (void)g;
+    if (rq.vgraph) PVCHK(c->ws.u_root.ensure(c->ws.u_cap));
+    if (persist) {
+        PVCHK(c->ws.citem[0].ensure(c->ws.pc_cap * PV_QSLICES));
+        PVCHK(c->ws.cready.ensure(c->ws.pc_cap * PV_QSLICES));
+        PVCHK(c->ws.mwitem[0].ensure(c->ws.pm_cap * mw_stride));
+        PVCHK(c->ws.mready.ensure(c->ws.pm_cap));
+        PVCHK(c->ws.pctl.ensure(1));
+    } else {
+        for (int i = 0; i < 2; i++) {
+            PVCHK(c->ws.citem[i].ensure(c->ws.c_cap));
+            PVCHK(c->ws.mwitem[i].ensure(c->ws.mw_cap * mw_stride));
+        }
+    }
+    PVCHK(c->ws.u_rows.ensure(c->ws.u_cap * 64));
+    if (local) {
+        PVCHK(c->ws.u_gid.ensure(c->ws.u_cap * 64));
+        PVCHK(c->ws.u_pref.ensure(c->ws.u_cap));
+        PVCHK(c->ws.pref_pool.ensure(c->ws.pref_cap));
+    }
+    if (local && !rq.edge) {
+        PVCHK(c->ws.utot.ensure(c->ws.u_cap * 2 * rq.K * 2));
+        PVCHK(c->ws.u_grp.ensure(c->ws.u_cap));
+        PVCHK(c->ws.pg_pos.ensure(c->ws.u_cap));
+        PVCHK(c->ws.pg_list.ensure(c->ws.u_cap));
+        PVCHK(c->ws.pg_cnt.ensure((size_t)rq.nheavy + 1));
+        PVCHK(c->ws.pg_off.ensure((size_t)rq.nheavy + 1));
+        PVCHK(c->ws.scan.ensure((size_t)rq.nheavy / 1024 + 2));
+    }
+    if (rq.edge) {
+        PVCHK(c->ws.umem.ensure(c->ws.u_cap * 64 * 2 * rq.K * 2));
+        PVCHK(c->ws.utot.ensure(c->ws.u_cap * 3 * rq.K * 2));
+        PVCHK(c->ws.ueid.ensure(c->ws.u_cap * 4096));
+        const int wb = persist ? c->level_blocks[3][PV_UNITS_ALL] : c->level_blocks[3][PV_UNITS_LIGHT];
+        PVCHK(c->ws.weid.ensure((size_t)wb * WAVES_PER_LAUNCH_BLOCK * 4096));
+        // one region per wave; level by level, per unit kind too (the
+        // kinds of a level run concurrently)
+        const int eb = persist ? c->level_blocks[3][PV_UNITS_ALL]
+                               : c->level_blocks[3][0] + c->level_blocks[3][1] + c->level_blocks[3][2];
+        const size_t escr_words = (size_t)eb * WAVES_PER_LAUNCH_BLOCK * 2 * 64 * 2 * rq.K * 2;
+        PVCHK(c->ws.escr.ensure(escr_words));
+    }
+    if (chunk > 0) {
+        PVCHK(c->ws.hu_rows.ensure((size_t)chunk * W * dpad));
+        PVCHK(c->ws.hu_vl.ensure((size_t)chunk * dpad));
+    }
+    // leave the device room for the launches themselves (scratch for the
+    // kernels' spills, the runtime's own buffers): buffers that fill it to
+    // the last gigabytes count as not fitting
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    const size_t headroom = std::min<size_t>((size_t)4 << 30, total_b / 32);
+    if (free_b < headroom) {
+        snprintf(g_last_error, sizeof g_last_error, "level buffers leave %zu bytes of the device free", free_b);
+        return PV_ENOMEM;
+    }
+    return PV_OK;
+}
+
 static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
     pv_ctx *c = g->ctx;
     hipStream_t s = c->stream;
@@ -938,57 +1023,33 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
     }
     const bool persist = c->persist;
     const int kli = variant_of(rq.kl, rq.lk);
+    // the capacities the walk started from (a halved chunk never goes below)
+    const size_t c_cap0 = c->ws.c_cap, mw_cap0 = c->ws.mw_cap;
+    int resumes = 0;  // chunks run again after an overflow (global counts alone)
     for (int attempt = 0;; attempt++) {
-        if (attempt > 12) return PV_ENOMEM;
+        if (attempt > 48) return PV_ENOMEM;
         g->last.attempts = attempt + 1;
+        // The level buffers hold one level's items of a chunk of heavy roots
+        // (and of the light roots).  If they no longer fit the device or the
+        // budget, the chunk is halved and the walk starts over: a level's
+        // demand follows the heavy roots it descends from (R-MAT scale 18
+        // truncated at k = 8 asks for 6.2e8 multi-word items in one level
+        // with every heavy root in one chunk).
+        pv_status lvl = level_buffers(c, g, rq, persist, mw_stride, chunk, W, dpad);
+        if (lvl == PV_ENOMEM && chunk > 1) {
+            c->ws.release_level();
+            c->ws.c_cap = std::max(c_cap0, c->ws.c_cap / 2);
+            c->ws.mw_cap = std::max(mw_cap0, c->ws.mw_cap / 2);
+            chunk = (chunk + 1) / 2;
+            if (c->debug)
+                fprintf(stderr, "[pivoter] attempt %d: level buffers do not fit; %d heavy roots per chunk\n", attempt,
+                        chunk);
+            continue;
+        }
+        PVCHK(lvl);
         PVCHK(c->ws.hist.ensure((size_t)rq.graphs * hd * hd));
-        if (rq.vgraph) PVCHK(c->ws.u_root.ensure(c->ws.u_cap));
         PVCHK(c->ws.counters.ensure(PV_NCOUNTERS));
-        if (persist) {
-            PVCHK(c->ws.citem[0].ensure(c->ws.pc_cap * PV_QSLICES));
-            PVCHK(c->ws.cready.ensure(c->ws.pc_cap * PV_QSLICES));
-            PVCHK(c->ws.mwitem[0].ensure(c->ws.pm_cap * mw_stride));
-            PVCHK(c->ws.mready.ensure(c->ws.pm_cap));
-            PVCHK(c->ws.pctl.ensure(1));
-        } else {
-            for (int i = 0; i < 2; i++) {
-                PVCHK(c->ws.citem[i].ensure(c->ws.c_cap));
-                PVCHK(c->ws.mwitem[i].ensure(c->ws.mw_cap * mw_stride));
-            }
-        }
-        PVCHK(c->ws.u_rows.ensure(c->ws.u_cap * 64));
-        if (local) {
-            PVCHK(c->ws.u_gid.ensure(c->ws.u_cap * 64));
-            PVCHK(c->ws.u_pref.ensure(c->ws.u_cap));
-            PVCHK(c->ws.pref_pool.ensure(c->ws.pref_cap));
-        }
-        if (local && !rq.edge) {
-            PVCHK(c->ws.utot.ensure(c->ws.u_cap * 2 * rq.K * 2));
-            PVCHK(c->ws.u_grp.ensure(c->ws.u_cap));
-            PVCHK(c->ws.pg_pos.ensure(c->ws.u_cap));
-            PVCHK(c->ws.pg_list.ensure(c->ws.u_cap));
-            PVCHK(c->ws.pg_cnt.ensure((size_t)rq.nheavy + 1));
-            PVCHK(c->ws.pg_off.ensure((size_t)rq.nheavy + 1));
-            PVCHK(c->ws.scan.ensure((size_t)rq.nheavy / 1024 + 2));
-        }
-        if (rq.edge) {
-            PVCHK(c->ws.umem.ensure(c->ws.u_cap * 64 * 2 * rq.K * 2));
-            PVCHK(c->ws.utot.ensure(c->ws.u_cap * 3 * rq.K * 2));
-            PVCHK(c->ws.ueid.ensure(c->ws.u_cap * 4096));
-            const int wb = persist ? c->level_blocks[3][PV_UNITS_ALL] : c->level_blocks[3][PV_UNITS_LIGHT];
-            PVCHK(c->ws.weid.ensure((size_t)wb * WAVES_PER_LAUNCH_BLOCK * 4096));
-            // one region per wave; level by level, per unit kind too (the
-            // kinds of a level run concurrently)
-            const int eb = persist ? c->level_blocks[3][PV_UNITS_ALL]
-                                   : c->level_blocks[3][0] + c->level_blocks[3][1] + c->level_blocks[3][2];
-            const size_t escr_words = (size_t)eb * WAVES_PER_LAUNCH_BLOCK * 2 * 64 * 2 * rq.K * 2;
-            PVCHK(c->ws.escr.ensure(escr_words));
-            HIPCHK(hipMemsetAsync(c->ws.escr.p, 0, escr_words * 8, s));
-        }
-        if (chunk > 0) {
-            PVCHK(c->ws.hu_rows.ensure((size_t)chunk * W * dpad));
-            PVCHK(c->ws.hu_vl.ensure((size_t)chunk * dpad));
-        }
+        if (rq.edge) HIPCHK(hipMemsetAsync(c->ws.escr.p, 0, c->ws.escr.n * 8, s));
         HIPCHK(hipMemsetAsync(c->ws.hist.p, 0, sizeof(unsigned long long) * (size_t)rq.graphs * hd * hd, s));
         HIPCHK(hipMemsetAsync(c->ws.counters.p, 0, PV_NCOUNTERS * sizeof(unsigned long long), s));
         HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, 5 * sizeof(int), s));  // flags,u_n,pref_n,omega,lovf
@@ -1010,10 +1071,26 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
         float ms_kind[3] = {0.f, 0.f, 0.f};
         uint32_t launches_kind[3] = {0, 0, 0};
         long long items = 0;
-        const int nchunks = (chunk > 0) ? (rq.nheavy + chunk - 1) / chunk : 0;
-        for (int ch = 0; ch < std::max(1, nchunks) && !overflow; ch++) {
-            const int hbase = ch * chunk;
+        // Chunks of heavy roots, the light roots with the first.  A walk of
+        // global counts alone resumes at the chunk whose level overflowed:
+        // the histogram and counters are restored to their state before it,
+        // the buffers grow (or the chunk is halved until they fit), and only
+        // that chunk runs again.  Universes live for one chunk then.  Local
+        // counts accumulate into the caller's output and the universes'
+        // owed totals, so they start the whole walk over instead.
+        const bool resumable = !local && !persist;
+        if (resumable) PVCHK(c->ws.hsnap.ensure((size_t)rq.graphs * hd * hd + PV_NCOUNTERS));
+        int hbase = 0, nchunks = 0;
+        for (bool done = false; !done && !overflow;) {
             const int hcount = (chunk > 0) ? std::min(chunk, rq.nheavy - hbase) : 0;
+            const int ch = hbase == 0 ? 0 : 1;  // the light roots go with the first chunk
+            if (resumable) {
+                const size_t hw = (size_t)rq.graphs * hd * hd;
+                HIPCHK(hipMemcpyAsync(c->ws.hsnap.p, c->ws.hist.p, hw * 8, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(c->ws.hsnap.p + hw, c->ws.counters.p, PV_NCOUNTERS * 8,
+                                      hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemsetAsync(g->small.p + SM_UN, 0, sizeof(int), s));
+            }
             int n_mw = 0, n_c = 0, cur = 0;
             // launch arguments shared by both forms of the walk
             auto fill_args = [&](LevelArgs &a, int level, int n_mw, int n_c, int cur, int nl) {
@@ -1154,6 +1231,9 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                     break;
                 }
                 items += pushed;
+                nchunks++;
+                hbase += hcount;
+                done = hbase >= rq.nheavy;
                 continue;
             }
             for (int level = 0;; level++) {
@@ -1260,7 +1340,34 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                 items += (long long)n_mw + n_c;
                 cur ^= 1;
             }
+            if (overflow && resumable) {
+                // this chunk again, from the state before it
+                const size_t hw = (size_t)rq.graphs * hd * hd;
+                HIPCHK(hipMemcpyAsync(c->ws.hist.p, c->ws.hsnap.p, hw * 8, hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(c->ws.counters.p, c->ws.hsnap.p + hw, PV_NCOUNTERS * 8,
+                                      hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, sizeof(int), s));
+                pv_status lv = level_buffers(c, g, rq, persist, mw_stride, chunk, W, dpad);
+                while (lv == PV_ENOMEM && chunk > 1) {
+                    c->ws.release_level();
+                    c->ws.c_cap = std::max(c_cap0, c->ws.c_cap / 2);
+                    c->ws.mw_cap = std::max(mw_cap0, c->ws.mw_cap / 2);
+                    chunk = (chunk + 1) / 2;
+                    if (c->debug)
+                        fprintf(stderr, "[pivoter] level buffers do not fit; %d heavy roots per chunk\n", chunk);
+                    lv = level_buffers(c, g, rq, persist, mw_stride, chunk, W, dpad);
+                }
+                PVCHK(lv);
+                if (++resumes > 64) return PV_ENOMEM;
+                overflow = false;
+                continue;
+            }
+            if (overflow) break;
+            nchunks++;
+            hbase += hcount;
+            done = hbase >= rq.nheavy;
         }
+        g->last.heavy_chunks = nchunks;
         if (overflow) continue;
         if (local) {
             // what the universes' walks owe the vertices above them; the

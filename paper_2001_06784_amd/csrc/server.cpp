@@ -301,15 +301,23 @@ void pv_server::worker(int w) {
                 if (d_local) (void)hipFree(d_local);
                 d_local = nullptr;
                 d_local_n = 0;
-                if (hipMalloc((void **)&d_local, need * 8) == hipSuccess) d_local_n = need;
-                else pass = PV_ENOMEM;
+                if (hipMalloc((void **)&d_local, need * 8) == hipSuccess) {
+                    d_local_n = need;
+                } else {
+                    (void)hipGetLastError();  // reported as PV_ENOMEM; no later launch check sees it
+                    pass = PV_ENOMEM;
+                }
             }
             if (pass == PV_OK && need > h_local_n) {
                 if (h_local) (void)hipHostFree(h_local);
                 h_local = nullptr;
                 h_local_n = 0;
-                if (hipHostMalloc((void **)&h_local, need * 8) == hipSuccess) h_local_n = need;
-                else pass = PV_ENOMEM;
+                if (hipHostMalloc((void **)&h_local, need * 8) == hipSuccess) {
+                    h_local_n = need;
+                } else {
+                    (void)hipGetLastError();
+                    pass = PV_ENOMEM;
+                }
             }
         }
         if (pass == PV_OK && L > 0) {

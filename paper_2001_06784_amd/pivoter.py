@@ -66,7 +66,8 @@ class pv_stats(C.Structure):
                 ("ms_finalize", C.c_float), ("launches_kind", C.c_uint32 * 3),
                 ("ms_kind", C.c_float * 3), ("work_kind", C.c_uint64 * 3),
                 ("kernel_kl", C.c_int32), ("kernel_lk", C.c_int32), ("attempts", C.c_int32),
-                ("child_work", C.c_uint64), ("leaf_hp", C.c_uint64), ("leaf_pp", C.c_uint64)]
+                ("child_work", C.c_uint64), ("leaf_hp", C.c_uint64), ("leaf_pp", C.c_uint64),
+                ("heavy_chunks", C.c_int32)]
 
     def as_dict(self) -> dict:
         d = {}

@@ -60,6 +60,6 @@ def test_header_constants_match_binding():
         assert int(m.group(1)) == getattr(P, name), name
     assert "#define PV_FREQ_STATIC_ROWS (1 << 20)" in hdr and P.PV_FREQ_STATIC_ROWS == 1 << 20
     assert ctypes.sizeof(P.pv_u128) == 16
-    assert ctypes.sizeof(P.pv_stats) == 160
+    assert ctypes.sizeof(P.pv_stats) == 168
     assert ctypes.sizeof(P.pv_config) == 40
     assert ctypes.sizeof(P.pv_tune) == 24

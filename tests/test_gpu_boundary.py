@@ -273,3 +273,45 @@ def test_measure_peaks_plausible():
     assert 1000.0 < pk["lds_read_gbs"] < 256 * 256 * 2.5
     assert 1000.0 < pk["valu_gops"] < 2 * 256 * 64 * 2.5
     assert all(pk[k] > 0 for k in ("ms_copy", "ms_read", "ms_lds", "ms_valu"))
+
+
+# ------------------------------------- level buffers that do not fit at once
+
+def test_heavy_roots_split_into_chunks_under_a_budget():
+    """When the level buffers of all heavy roots at once do not fit the
+    budget, the walk halves the heavy-root chunk and starts over: same
+    counts, more chunks, never above the budget."""
+    g = gg.rmat_web(scale=13)
+    c0 = P.pv_init(0)
+    try:
+        h = P.pv_graph_load_csr(c0, g.n, g.row_ptr, g.col)
+        ref = P.pv_count_global(h, 8)
+        held = P.pv_memory(c0)
+        P.pv_graph_free(h)
+    finally:
+        P.pv_fini(c0)
+    _say(f"[boundary] rmat13 k<=8: {ref.stats['heavy_chunks']} chunk(s), {held} bytes held, "
+         f"nodes {ref.stats['nodes']}")
+    assert ref.stats["heavy_chunks"] == 1
+    seen = []
+    for frac in (0.9, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3):
+        budget = int(held * frac)
+        c = P.pv_init(0, hbm_budget=budget)
+        try:
+            h = P.pv_graph_load_csr(c, g.n, g.row_ptr, g.col)
+            try:
+                res = P.pv_count_global(h, 8)
+            except P.PivoterError as e:
+                assert e.status == P.PV_ENOMEM
+                res = None
+            assert P.pv_memory(c) <= budget
+            P.pv_graph_free(h)
+        finally:
+            P.pv_fini(c)
+        if res is None:
+            break
+        assert res.counts == ref.counts and res.omega == ref.omega
+        assert res.stats["leaves"] == ref.stats["leaves"]
+        seen.append((frac, res.stats["heavy_chunks"]))
+    _say(f"[boundary] budget fraction -> heavy chunks: {seen}")
+    assert any(ch > 1 for _, ch in seen), seen
