@@ -1312,9 +1312,12 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                         const unsigned long long *q = ph + 16 * mode;
                         if (!q[15]) continue;
                         fprintf(stderr, "[phase] level %d kind %d: waves %llu, per wave us: life %.1f", level, mode,
-                                q[15], q[12 + mode] * 0.01 / q[15]);
+                                q[15], q[12] * 0.01 / q[15]);
                         for (int i = 0; i < 12; i++)
                             if (q[i]) fprintf(stderr, " p%d %.1f", i, q[i] * 0.01 / q[15]);
+                        if (q[13])
+                            fprintf(stderr, " | lane batches: %llu trips, %llu lane-nodes, use %.3f", q[13], q[14],
+                                    (double)q[14] / (64.0 * (double)q[13]));
                         fprintf(stderr, "\n");
                     }
                 }

@@ -662,9 +662,10 @@ struct Ctr {
 #ifdef PV_PHASE_TIMING
 #define PT_N 16
 // sub-phase sums of compact walks, per wave in LDS: [0] lane batches, [1]
-// leaf read-off of the wave tier
+// leaf read-off of the wave tier, [2] lane-batch loop trips, [3] nodes the
+// lanes of those batches visited
 __device__ __forceinline__ unsigned long long *pt_sub() {
-    __shared__ unsigned long long s_pt_sub[WAVES_PER_BLOCK][2];
+    __shared__ unsigned long long s_pt_sub[WAVES_PER_BLOCK][4];
     return s_pt_sub[threadIdx.x >> 6];
 }
 #define PT_MARK(t) const uint64_t t = __builtin_amdgcn_s_memrealtime()
@@ -776,7 +777,13 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
     for (int kk = 0; kk < NK; kk++) sH[kk] = sP[kk] = 0;
     uint32_t nn = 0, ww = 0, nl = 0;
     bool visit = true, live = act;
+#ifdef PV_PHASE_TIMING
+    uint32_t trips = 0;
+#endif
     while (live) {
+#ifdef PV_PHASE_TIMING
+        trips++;
+#endif
         if (visit) {
             nn++;
             if (S != 0 && h0 + __popc(Hl) < hlim) {
@@ -858,6 +865,17 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
         Hl = ((F >> 11) & 0xFFu) | (1u << v);
         Pl = (F >> 19) & 0xFFu;
     }
+#ifdef PV_PHASE_TIMING
+    {
+        // the wave ran as many trips as its longest lane
+        const uint32_t tmax = wave_max_u32(trips);
+        const uint32_t tot = wave_sum_u32(nn);
+        if (lane == 0) {
+            pt_sub()[2] += tmax;
+            pt_sub()[3] += tot;
+        }
+    }
+#endif
     nodes += wave_sum_u32(nn);
     work += wave_sum_u32(ww);
     nleaves += wave_sum_u32(nl);
@@ -1158,13 +1176,14 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                 } else {
                     const uint64_t Ap = readlane64(A, piv);
                     if (h < hlim) {
-                        stS = writelane64(stS, S, depth);
+                        // frame `depth` in lane `depth` (one lane index for the four writes)
+                        const bool at = lane_id_here() == depth;
+                        stS = at ? S : stS;
                         if (LOCAL) {
-                            stH = writelane64(stH, H, depth);
-                            stP = writelane64(stP, P, depth);
+                            stH = at ? H : stH;
+                            stP = at ? P : stP;
                         }
-                        stM = writelane32(stM, (uint32_t)piv | ((uint32_t)h << 6) | ((uint32_t)p << 19),
-                                          depth);
+                        stM = at ? ((uint32_t)piv | ((uint32_t)h << 6) | ((uint32_t)p << 19)) : stM;
                         depth++;
                     }
                     S &= Ap;
@@ -1812,21 +1831,24 @@ struct Claim {
 // four waves share a SIMD: the walk is bound by the latency of each node's
 // dependent steps, and the fourth wave hides more of it than the registers
 // spilled to scratch cost.
-template <int KL, int LK>
+template <int KL, int LK, int MODE>
 struct LevelShape {
     static constexpr bool V64 = KL == 8 && LK == PV_LK_VERTEX64;
     // (the persistent walk keeps the budget of the compact-item kernel, whose
-    // units are the bulk of its work)
-    static constexpr int waves_per_simd = V64 ? 4 : 3;
+    // units are the bulk of its work).  The light-root kernel has no lane
+    // tier and fits five waves without spills (per vertex, 1M-vertex graph:
+    // its launch 6.6 -> 5.3 ms); the other per-vertex kinds spill at five
+    // (step 44.7 -> 51.3 ms).
+    static constexpr int waves_per_simd = V64 ? (MODE == PV_UNITS_LIGHT ? 5 : 4) : 3;
     static constexpr int lds_h = V64 ? 16 : PV_LDS_H;
 };
 
 template <int KL, int MODE, int LK>
-__global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::waves_per_simd))
+__global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE>::waves_per_simd))
     sct_level_kernel(const LevelArgs *__restrict__ pa) {
     constexpr bool EDGE = LK == PV_LK_EDGE;
     constexpr bool LOCAL = KL > 0;
-    constexpr int LDS_H = LevelShape<KL, LK>::lds_h;
+    constexpr int LDS_H = LevelShape<KL, LK, MODE>::lds_h;
     const LevelArgs &a = *pa;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -1849,7 +1871,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
 #ifdef PV_PHASE_TIMING
     uint64_t pt[PT_N];
     for (int i = 0; i < PT_N; i++) pt[i] = 0;
-    if (lane == 0) pt_sub()[0] = pt_sub()[1] = 0ull;
+    if (lane == 0) pt_sub()[0] = pt_sub()[1] = pt_sub()[2] = pt_sub()[3] = 0ull;
     PT_MARK(pt_kernel0);
 #endif
     constexpr int CK = MODE == PV_UNITS_ALL ? PV_UNITS_LIGHT : MODE;  // the claim cursor of a static range
@@ -2197,10 +2219,12 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK>::wav
         if (ct.child) atomicAdd(&a.counters[PV_CTR_CHILD], ct.child);
 #ifdef PV_PHASE_TIMING
         if (a.phase) {
-            PT_ADD(12 + (MODE < 3 ? MODE : 0), pt_kernel0);
+            PT_ADD(12, pt_kernel0);
             pt[15] = 1;  // waves
             pt[11] = pt_sub()[0];
             if (MODE != 0) pt[10] = pt_sub()[1];  // (kind 0 keeps slot 10 for its re-index)
+            pt[13] = pt_sub()[2];  // lane-batch loop trips and the nodes their lanes visited
+            pt[14] = pt_sub()[3];
             for (int i = 0; i < PT_N; i++)
                 if (pt[i]) atomicAdd(&a.phase[(MODE < 3 ? MODE : 0) * PT_N + i], (unsigned long long)pt[i]);
         }
