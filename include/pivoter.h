@@ -58,6 +58,7 @@ typedef int32_t pv_status;
 #define PV_EBUFSIZE -7     /* output buffer too small; required size reported */
 #define PV_ECANCELLED -8   /* request cancelled */
 #define PV_EAGAIN -9       /* not admitted now (memory budget); retry later */
+#define PV_ETIMEDOUT -10   /* the call ran past the context's timeout and was stopped */
 
 /* local count kinds */
 #define PV_NONE 0
@@ -129,6 +130,10 @@ const char *pv_strerror(pv_status s);
  *               cache is walked with the cached settings.
  *   dfs_max, dfs_budget, lane_max: the tuning settings below (0: default;
  *               lane_max -1 turns the lane tier off).
+ *   timeout_ms  watchdog of every count call on the context: a walk still
+ *               running after this many milliseconds is stopped (its waves
+ *               take no further units) and the call returns PV_ETIMEDOUT,
+ *               leaving the context usable (0: none).
  */
 typedef struct {
     void *stream;
@@ -137,6 +142,7 @@ typedef struct {
     int32_t dfs_max;
     int32_t dfs_budget;
     int32_t lane_max;
+    int32_t timeout_ms;
 } pv_config;
 
 /*
@@ -146,6 +152,16 @@ typedef struct {
  */
 pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out);
 void pv_fini(pv_ctx *ctx);
+
+/*
+ * Cancel the count call running on the context now, from any host thread:
+ * its waves take no further units, and the call returns PV_ECANCELLED once
+ * the units in hand are done (a unit walks at most the depth-first budget
+ * of nodes).  The context stays usable; no effect when no call runs.
+ * Results are not partial: a cancelled call's outputs are undefined and the
+ * call is simply run again.
+ */
+pv_status pv_cancel(pv_ctx *ctx);
 
 /* Device bytes the context holds now (workspaces and its graphs). */
 pv_status pv_memory(const pv_ctx *ctx, int64_t *held_bytes);
@@ -185,6 +201,12 @@ pv_status pv_measure_peaks(pv_ctx *ctx, int64_t copy_bytes, pv_peaks *out);
  *                   pass when what the universes owe the vertices above them
  *                   is added up per heavy root (default: as many as fit).
  *   PV_DEBUG        per-level buffer demands and times on stderr.
+ *   PV_RECORD       a file path: every count call on the context appends
+ *                   one JSON line to it (the call, the graph's n and m,
+ *                   alpha, omega, k_max, the local range, the walk's
+ *                   counters from pv_stats, the device times and the
+ *                   returned status).  Appends are serialised within the
+ *                   process; a file that cannot be opened is skipped.
  */
 
 /* Change the stream later work is issued on (hipStream_t, may be NULL). */

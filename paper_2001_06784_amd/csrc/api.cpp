@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <mutex>
+#include <thread>
 #include <memory>
 #include <cstdio>
 #include <cstdlib>
@@ -64,6 +66,7 @@ extern "C" const char *pv_strerror(pv_status s) {
         case PV_EBUFSIZE: return "output buffer too small";
         case PV_ECANCELLED: return "cancelled";
         case PV_EAGAIN: return "not admitted, retry";
+        case PV_ETIMEDOUT: return "timed out";
         default: return "unknown status";
     }
 }
@@ -263,6 +266,14 @@ struct pv_ctx {
     int level_blocks[6][4] = {};  // [kernel variant, see variant_of][unit kind, or PV_UNITS_ALL]
     bool persist = false;  // one persistent launch per walk (PV_PERSIST set) instead of level by level
     bool phase_on = false; // per-level phase times (PV_PHASE set; builds with PV_PHASE_TIMING)
+    std::string record_path;  // PV_RECORD: a JSON line per count call appended here
+    // cancellation and the watchdog: the device flag the walk's claims read,
+    // set through its own stream while a call's kernels run
+    int *d_abort = nullptr;
+    hipStream_t abort_stream = nullptr;
+    std::atomic<int> cancel_req{0};
+    bool timed_out = false;
+    int timeout_ms = 0;
     int dfs_max = 64;
     int dfs_budget = 0;  // 0: chosen per request (see budget_of)
     int lane_max = PV_LANE_MAX;
@@ -351,7 +362,7 @@ extern "C" pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out)
     *out = nullptr;
     pv_config conf{};
     if (cfg) conf = *cfg;
-    if (conf.hbm_budget < 0 || conf.dfs_max < 0 || conf.dfs_max > 64 || conf.lane_max < -1 ||
+    if (conf.hbm_budget < 0 || conf.dfs_max < 0 || conf.dfs_max > 64 || conf.lane_max < -1 || conf.timeout_ms < 0 ||
         conf.lane_max > PV_LANE_MAX || (conf.dfs_budget != 0 && (conf.dfs_budget < 16 || conf.dfs_budget > (1 << 20))))
         return PV_EINVAL;
     int ndev = 0;
@@ -408,6 +419,7 @@ extern "C" pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out)
     c->debug = getenv("PV_DEBUG") != nullptr;
     c->persist = getenv("PV_PERSIST") != nullptr;
     c->phase_on = getenv("PV_PHASE") != nullptr;
+    if (const char *env = getenv("PV_RECORD")) c->record_path = env;
     if (const char *env = getenv("PV_DFS_BUDGET")) c->dfs_budget = std::max(16, std::min(1 << 20, atoi(env)));
     if (const char *env = getenv("PV_LANE_MAX")) c->lane_max = std::max(0, std::min(PV_LANE_MAX, atoi(env)));
     if (const char *env = getenv("PV_PREFIX_ROWS")) c->prefix_rows = std::max(0, atoi(env));
@@ -436,6 +448,13 @@ extern "C" pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out)
             return PV_EDEVICE;
         }
     if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) {
+        pv_fini(c);
+        return PV_EDEVICE;
+    }
+    c->timeout_ms = conf.timeout_ms;
+    if (hipStreamCreateWithFlags(&c->abort_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc((void **)&c->d_abort, 256) != hipSuccess || hipMemset(c->d_abort, 0, 256) != hipSuccess) {
+        (void)hipGetLastError();
         pv_fini(c);
         return PV_EDEVICE;
     }
@@ -478,7 +497,53 @@ extern "C" void pv_fini(pv_ctx *c) {
         if (ev) (void)hipEventDestroy(ev);
     for (auto &ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
+    if (c->abort_stream) {
+        (void)hipStreamSynchronize(c->abort_stream);
+        (void)hipStreamDestroy(c->abort_stream);
+    }
+    if (c->d_abort) (void)hipFree(c->d_abort);
     delete c;
+}
+
+extern "C" pv_status pv_cancel(pv_ctx *c) {
+    if (!c || !c->d_abort) return PV_EINVAL;
+    c->cancel_req.store(1);
+    HIPCHK(hipMemsetAsync(c->d_abort, 1, sizeof(int), c->abort_stream));
+    return PV_OK;
+}
+
+// Wait for the walk's work on stream s; with a timeout, poll and raise the
+// abort flag once the call has run too long.  Then report a cancellation
+// or a timeout of this call.
+static pv_status wait_walk(pv_ctx *c, hipStream_t s, std::chrono::steady_clock::time_point t0) {
+    if (c->timeout_ms <= 0) {
+        HIPCHK(hipStreamSynchronize(s));
+    } else {
+        for (;;) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) {
+                set_err("hipStreamQuery", q);
+                return PV_EDEVICE;
+            }
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (!c->timed_out && ms > c->timeout_ms) {
+                c->timed_out = true;
+                HIPCHK(hipMemsetAsync(c->d_abort, 1, sizeof(int), c->abort_stream));
+            }
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+        }
+    }
+    if (c->timed_out) {
+        snprintf(g_last_error, sizeof g_last_error, "call stopped after its %d ms timeout", c->timeout_ms);
+        return PV_ETIMEDOUT;
+    }
+    if (c->cancel_req.load()) {
+        snprintf(g_last_error, sizeof g_last_error, "call cancelled");
+        return PV_ECANCELLED;
+    }
+    return PV_OK;
 }
 
 extern "C" pv_status pv_memory(const pv_ctx *c, int64_t *held_bytes) {
@@ -906,6 +971,7 @@ struct CountReq {
     // a root subset's size (its roots and their out-degrees' sum), which
     // the first buffer capacities follow; -1: the graph's n and m
     long long size_n = -1, size_m = -1;
+    const char *what = "count";  // the entry point, for run records
 };
 
 static pv_status run_sct_walk(pv_graph *g, const CountReq &rq);
@@ -987,6 +1053,12 @@ static pv_status level_buffers(pv_ctx *c, pv_graph *g, const CountReq &rq, bool 
 static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
     pv_ctx *c = g->ctx;
     hipStream_t s = c->stream;
+    // a new call: no cancellation or timeout of an earlier one applies
+    const auto t_call = std::chrono::steady_clock::now();
+    HIPCHK(hipStreamSynchronize(c->abort_stream));
+    c->cancel_req.store(0);
+    c->timed_out = false;
+    HIPCHK(hipMemsetAsync(c->d_abort, 0, sizeof(int), s));
     const int alpha = g->alpha;
     const int hd = alpha + 2;
     PVCHK(ensure_binomials(c, hd + 1));
@@ -1159,6 +1231,7 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                 a.escr_wave0[2] = (c->level_blocks[3][0] + c->level_blocks[3][1]) * WAVES_PER_LAUNCH_BLOCK;
                 a.vgraph = rq.vgraph;
                 a.u_root = rq.vgraph ? c->ws.u_root.p : nullptr;
+                a.abort = c->d_abort;
             };
             if (persist) {
                 // the whole walk of this chunk in one launch: every unit
@@ -1195,7 +1268,7 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                 HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
                 PersistCtl *pcs = c->h_pctl;
                 HIPCHK(hipMemcpyAsync(pcs, c->ws.pctl.p, sizeof(PersistCtl), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
+                PVCHK(wait_walk(c, s, t_call));
                 io_fresh = true;
                 levels++;
                 launches_kind[PV_UNITS_ITEMS]++;
@@ -1291,7 +1364,7 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                 }
                 if (c->timing) HIPCHK(hipEventRecord(c->ev[4], s));
                 HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
+                PVCHK(wait_walk(c, s, t_call));
                 io_fresh = true;
                 levels++;
                 if (c->timing) {
@@ -1432,9 +1505,51 @@ static pv_status read_counters(pv_graph *g, const CountReq &rq) {
     return PV_OK;
 }
 
+// Run records: with PV_RECORD naming a file at pv_init, every count call
+// appends one JSON line (the request, the graph, the walk's counters and
+// device times, the status).
+static std::mutex g_record_mu;
+
+static void record_run(const pv_graph *g, const CountReq &rq, pv_status st) {
+    const pv_ctx *c = g->ctx;
+    if (c->record_path.empty()) return;
+    const pv_stats &l = g->last;
+    const char *local = rq.kl == 0 ? "none" : (rq.edge ? "edge" : "vertex");
+    char line[1536];
+    snprintf(line, sizeof line,
+             "{\"t\": %.3f, \"call\": \"%s\", \"device\": \"%s\", \"n\": %d, \"m\": %lld, \"graphs\": %d, "
+             "\"alpha\": %d, \"omega\": %d, \"k_max\": %d, \"local\": \"%s\", \"k_lo\": %d, \"k_hi\": %d, "
+             "\"nodes\": %llu, \"leaves\": %llu, \"work\": %llu, \"child_work\": %llu, \"leaf_hp\": %llu, "
+             "\"items\": %llu, \"attempts\": %d, \"heavy_chunks\": %d, \"levels\": %d, \"ms_peel\": %.3f, "
+             "\"ms_orient\": %.3f, \"ms_levels\": %.3f, \"ms_finalize\": %.3f, \"status\": %d}\n",
+             std::chrono::duration<double>(std::chrono::system_clock::now().time_since_epoch()).count(), rq.what,
+             c->arch.c_str(), g->n, (long long)(g->nnz / 2), rq.graphs, l.alpha, l.omega, rq.kmax, local,
+             rq.kl ? rq.klo : 0, rq.kl ? rq.klo + rq.K - 1 : 0, (unsigned long long)l.nodes,
+             (unsigned long long)l.leaves, (unsigned long long)l.work, (unsigned long long)l.child_work,
+             (unsigned long long)l.leaf_hp, (unsigned long long)l.items, l.attempts, l.heavy_chunks, l.levels,
+             l.ms_peel, l.ms_orient, l.ms_levels, l.ms_finalize, (int)st);
+    std::lock_guard<std::mutex> lk(g_record_mu);
+    if (FILE *f = fopen(c->record_path.c_str(), "a")) {
+        fputs(line, f);
+        fclose(f);
+    }
+}
+
+static pv_status finish_counts_body(pv_graph *g, const CountReq &rq, pv_u128 *counts, int32_t cap,
+                                    int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats,
+                                    uint64_t *local_ovf, pv_status *status);
+
 static pv_status finish_counts(pv_graph *g, const CountReq &rq, pv_u128 *counts, int32_t cap,
                                int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats,
                                uint64_t *local_ovf, pv_status *status = nullptr) {
+    const pv_status st = finish_counts_body(g, rq, counts, cap, omega_out, overflow_bits, stats, local_ovf, status);
+    record_run(g, rq, st);
+    return st;
+}
+
+static pv_status finish_counts_body(pv_graph *g, const CountReq &rq, pv_u128 *counts, int32_t cap,
+                                    int32_t *omega_out, uint64_t *overflow_bits, pv_stats *stats,
+                                    uint64_t *local_ovf, pv_status *status) {
     pv_ctx *c = g->ctx;
     hipStream_t s = c->stream;
     const int hd = g->alpha + 2;
@@ -1626,6 +1741,7 @@ extern "C" pv_status pv_count_global_wide(pv_graph *g, int32_t k_max, uint64_t *
     PVCHK(prepare(g, false));
     CountReq rq;
     rq.kmax = k_max > 0 ? k_max : 0;
+    rq.what = "wide";
     PVCHK(setup_local(g, PV_NONE, 0, 0, rq));
     rq.order = g->order.p;
     rq.nheavy = g->nheavy;
@@ -1681,8 +1797,9 @@ extern "C" pv_status pv_count_global_wide(pv_graph *g, int32_t k_max, uint64_t *
         }
     }
     const int top = (rq.kmax > 0) ? std::min(omega, rq.kmax) : omega;
-    if (cap <= top) return PV_EBUFSIZE;
-    return any_ovf ? PV_EOVERFLOW : PV_OK;
+    const pv_status st = (cap <= top) ? PV_EBUFSIZE : (any_ovf ? PV_EOVERFLOW : PV_OK);
+    record_run(g, rq, st);
+    return st;
 }
 
 extern "C" pv_status pv_local_frequency(pv_ctx *c, const pv_u128 *local, int64_t rows, int32_t K, int32_t col,
@@ -1781,6 +1898,7 @@ extern "C" pv_status pv_count_local(pv_graph *g, int32_t kind, int32_t k_lo, int
         const int w1 = std::min(k_hi, w0 + win - 1);
         CountReq rq;
         rq.kmax = w1;
+        rq.what = "local";
         PVCHK(setup_local(g, kind, w0, w1, rq));
         rq.vout = c->ws.vout_own.p + 2 * (w0 - k_lo);
         rq.kstride = K;
@@ -1840,6 +1958,7 @@ extern "C" pv_status pv_count_roots(pv_graph *g, const int32_t *roots, int32_t n
     rq.kmax = k_max > 0 ? k_max : 0;
     rq.c0 = 0;
     rq.whole = false;
+    rq.what = "roots";
     PVCHK(setup_local(g, local_kind, k_lo, k_hi, rq));
     rq.vout = (uint64_t *)local_out;
     rq.order = dorder.p;
@@ -1934,6 +2053,7 @@ extern "C" pv_status pv_count_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, i
     PVCHK(setup_local(u, local_kind, k_lo, k_hi, rq));
     rq.vout = (uint64_t *)local_out;
     rq.graphs = G;
+    rq.what = "batch";
     rq.vgraph = u->vgraph.p;
     rq.order = u->order.p;
     rq.nheavy = u->nheavy;

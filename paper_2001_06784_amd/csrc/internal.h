@@ -168,6 +168,8 @@ struct LevelArgs {
     // phase times per unit kind ([3][16] ticks), filled by builds with
     // PV_PHASE_TIMING only (nullptr: off)
     unsigned long long *phase;
+    // the call's abort flag (nonzero: hand out no more units); nullptr: none
+    const int *abort;
     PersistCtl *pctl;
     int *cready, *mready;          // per queue slot: 0 not yet written, 1 written, 2 never written
     int c_scap, m_cap;             // compact slots per slice; multi-word slots

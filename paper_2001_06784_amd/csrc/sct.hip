@@ -961,6 +961,11 @@ __device__ __forceinline__ int ld_agent(const unsigned long long *p) {
     return (int)(uint32_t)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// the call's abort flag (cancellation or the host's watchdog)
+__device__ __forceinline__ int call_aborted(const LevelArgs &a) {
+    return a.abort ? __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+}
+
 // Reserve n consecutive slots for this wave's items in the queue whose
 // reservation counter is *tail (capacity cap; in the persistent walk rdy
 // are its slot flags, base its first slot).  Returns the first slot (an
@@ -1804,15 +1809,25 @@ __device__ void gather_heavy_lds(int hu, int v, int lane, const LevelArgs &a, ld
 // waves; the units from n0 on (8 per wave of the launch) are claimed one at
 // a time, so waves finish together.  The host picks n0 and nch.  All values
 // wave-uniform; -1 when the kind's n units are gone.
+// A claim that takes a new chunk also reads the call's abort flag (set by
+// the host to cancel, or by its watchdog): once it is set, no unit is
+// handed out, so every wave finishes the unit in hand and exits.
 struct Claim {
     int idx = -1;
-    __device__ __forceinline__ int next(int *cursor, int n, int n0, int nch, int lane) {
+    __device__ __forceinline__ int next(int *cursor, int n, int n0, int nch, int lane, const int *abort) {
         if (idx >= 0) {
             idx += nch;
             if (idx < n0) return idx;
         }
-        int b = 0;
-        if (lane == 0) b = atomicAdd(cursor, 1);
+        int b = 0, stop = 0;
+        if (lane == 0) {
+            b = atomicAdd(cursor, 1);
+            if (abort) stop = __hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (bcast0(__shfl(stop, 0, 64))) {
+            idx = -1;
+            return -1;
+        }
         const int c = bcast0(__shfl(b, 0, 64));
         if (c < nch) {
             idx = c;
@@ -1885,7 +1900,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
         __shared__ int s_memb[WAVES_PER_BLOCK][64];
         const int n0 = a.n_mw_in, n1 = n0 + (a.level == 0 ? a.nheavy : 0);
         for (;;) {
-            const int idx = claim.next(cursor, n1, claim_n0, claim_nch, lane);
+            const int idx = claim.next(cursor, n1, claim_n0, claim_nch, lane, a.abort);
             if (idx < 0) break;
             int hu, h = 1, p = 0;
             uint64_t Sw = 0, Hw = 0, Pw = 0;
@@ -1958,7 +1973,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
     } else if constexpr (MODE == PV_UNITS_ITEMS) {
         const int n = a.n_c_in;
         for (;;) {
-            const int idx = claim.next(cursor, n, claim_n0, claim_nch, lane);
+            const int idx = claim.next(cursor, n, claim_n0, claim_nch, lane, a.abort);
             if (idx < 0) break;
             PT_MARK(t_l);
             const CItem it = a.c_in[idx];
@@ -2011,7 +2026,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
             // abort or error: checked every 16 units and whenever idle
             if (++since_check >= 16) {
                 since_check = 0;
-                if (bcast0(ld_agent(&pc->state.v) | ld_agent(&pc->abort.v))) break;
+                if (bcast0(ld_agent(&pc->state.v) | ld_agent(&pc->abort.v) | call_aborted(a))) break;
             }
             const unsigned long long w0 = ct.work;
             int kind = -1;
@@ -2099,7 +2114,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
                 }
             }
             if (kind == PV_UNITS_LIGHT) {
-                const int idx = claim.next(cursor, nlight, claim_n0, claim_nch, lane);
+                const int idx = claim.next(cursor, nlight, claim_n0, claim_nch, lane, a.abort);
                 if (idx < 0) {
                     light_left = false;
                     kind = -1;
@@ -2144,7 +2159,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
                 D = __hip_atomic_load(&pc->done.v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
                 T = nroots + (unsigned long long)(uint32_t)ld_agent(&pc->mtail.v);
                 for (int sl = 0; sl < PV_QSLICES; sl++) T += (unsigned long long)(uint32_t)ld_agent(&pc->ctail[sl].v);
-                bad = ld_agent(&pc->state.v) | ld_agent(&pc->abort.v);
+                bad = ld_agent(&pc->state.v) | ld_agent(&pc->abort.v) | call_aborted(a);
             }
             D = uniform64(D);
             T = uniform64(T);
@@ -2172,7 +2187,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
         int *etab_w = EDGE ? a.weid + (long long)(blockIdx.x * WAVES_PER_BLOCK + wv) * 4096 : nullptr;
         if (EDGE) vs.set_table(etab_w);
         for (;;) {
-            const int idx = claim.next(cursor, n, claim_n0, claim_nch, lane);
+            const int idx = claim.next(cursor, n, claim_n0, claim_nch, lane, a.abort);
             if (idx < 0) break;
             const int v = a.order[a.light_base + idx];
             gs.set_vertex(v);

@@ -29,6 +29,7 @@ PV_ETOOBIG = -6
 PV_EBUFSIZE = -7
 PV_ECANCELLED = -8
 PV_EAGAIN = -9
+PV_ETIMEDOUT = -10
 
 PV_NONE, PV_VERTEX, PV_EDGE = 0, 1, 2
 PV_TRUST_INPUT = 1
@@ -40,7 +41,7 @@ PV_FREQ_STATIC_ROWS = 1 << 20
 
 # every function declared in include/pivoter.h
 ABI_FUNCTIONS = [
-    "pv_strerror", "pv_init", "pv_fini", "pv_memory", "pv_measure_peaks", "pv_set_stream", "pv_set_dfs_max", "pv_set_dfs_budget", "pv_set_lane_max",
+    "pv_strerror", "pv_init", "pv_fini", "pv_cancel", "pv_memory", "pv_measure_peaks", "pv_set_stream", "pv_set_dfs_max", "pv_set_dfs_budget", "pv_set_lane_max",
     "pv_set_timing",
     "pv_last_error",
     "pv_graph_load_csr", "pv_graph_load_csr_device", "pv_graph_free", "pv_graph_size",
@@ -88,7 +89,8 @@ class pv_peaks(C.Structure):
 
 class pv_config(C.Structure):
     _fields_ = [("stream", C.c_void_p), ("hbm_budget", C.c_int64), ("tune_cache", C.c_char_p),
-                ("dfs_max", C.c_int32), ("dfs_budget", C.c_int32), ("lane_max", C.c_int32)]
+                ("dfs_max", C.c_int32), ("dfs_budget", C.c_int32), ("lane_max", C.c_int32),
+                ("timeout_ms", C.c_int32)]
 
 
 class pv_tune(C.Structure):
@@ -157,6 +159,7 @@ def _lib():
             "pv_last_error": (C.c_char_p, []),
             "pv_init": (i32, [i32, C.POINTER(pv_config), pvp]),
             "pv_fini": (None, [vp]),
+            "pv_cancel": (i32, [vp]),
             "pv_memory": (i32, [vp, C.POINTER(C.c_int64)]),
             "pv_measure_peaks": (i32, [vp, C.c_int64, C.POINTER(pv_peaks)]),
             "pv_set_stream": (i32, [vp, vp]),
@@ -236,9 +239,9 @@ def pv_last_error() -> str:
 
 
 def pv_init(device: int = 0, stream: int | None = None, hbm_budget: int = 0, tune_cache: str | None = None,
-            dfs_max: int = 0, dfs_budget: int = 0, lane_max: int = 0) -> int:
+            dfs_max: int = 0, dfs_budget: int = 0, lane_max: int = 0, timeout_ms: int = 0) -> int:
     cfg = pv_config(stream, hbm_budget, tune_cache.encode() if tune_cache else None, dfs_max, dfs_budget,
-                    lane_max)
+                    lane_max, timeout_ms)
     out = C.c_void_p()
     _check(_lib().pv_init(device, C.byref(cfg), C.byref(out)), "pv_init")
     return out.value
@@ -246,6 +249,11 @@ def pv_init(device: int = 0, stream: int | None = None, hbm_budget: int = 0, tun
 
 def pv_fini(ctx: int) -> None:
     _lib().pv_fini(ctx)
+
+
+def pv_cancel(ctx: int) -> None:
+    """Cancel the count call running on ctx now (from any thread)."""
+    _check(_lib().pv_cancel(ctx), "pv_cancel")
 
 
 def pv_memory(ctx: int) -> int:

@@ -52,7 +52,7 @@ def test_null_handles_are_rejected_without_touching_the_device():
 def test_header_constants_match_binding():
     hdr = open(os.path.join(ROOT, "include", "pivoter.h")).read()
     for name in ["PV_OK", "PV_EINVAL", "PV_ENOTSIMPLE", "PV_ENOMEM", "PV_EOVERFLOW", "PV_EDEVICE",
-                 "PV_ETOOBIG", "PV_EBUFSIZE", "PV_ECANCELLED", "PV_EAGAIN", "PV_NONE", "PV_VERTEX",
+                 "PV_ETOOBIG", "PV_EBUFSIZE", "PV_ECANCELLED", "PV_EAGAIN", "PV_ETIMEDOUT", "PV_NONE", "PV_VERTEX",
                  "PV_EDGE", "PV_MAX_ALPHA", "PV_MAX_LOCAL_K", "PV_TRUST_INPUT", "PV_DEDUP",
                  "PV_SYMMETRIZE"]:
         m = re.search(rf"#define {name}\s+(-?\d+)u?\b", hdr)

@@ -315,3 +315,97 @@ def test_heavy_roots_split_into_chunks_under_a_budget():
         seen.append((frac, res.stats["heavy_chunks"]))
     _say(f"[boundary] budget fraction -> heavy chunks: {seen}")
     assert any(ch > 1 for _, ch in seen), seen
+
+
+# ------------------------------------------- cancellation and the watchdog
+
+@pytest.fixture(scope="module")
+def long_call_graph():
+    # per-edge counts of k = 3..8 on an R-MAT graph of 2^14 vertices: a call
+    # of about a second
+    return gg.rmat_web(scale=14)
+
+
+def _timed_edge_count(h):
+    t0 = time.perf_counter()
+    try:
+        P.pv_count_local(h, P.PV_EDGE, 3, 8)
+        st = P.PV_OK
+    except P.PivoterError as e:
+        st = e.status
+    return st, time.perf_counter() - t0
+
+
+def test_cancel_stops_a_running_call_and_the_context_stays_usable(long_call_graph):
+    g = long_call_graph
+    c = P.pv_init(0)
+    try:
+        h = P.pv_graph_load_csr(c, g.n, g.row_ptr, g.col)
+        ref = P.pv_count_global(h, 3)
+        # a cancellation while nothing runs does not touch the next call
+        P.pv_cancel(c)
+        assert P.pv_count_global(h, 3).counts == ref.counts
+        st, t_full = _timed_edge_count(h)
+        assert st == P.PV_OK
+        out = {}
+
+        def run():
+            out["status"], out["s"] = _timed_edge_count(h)
+
+        t = threading.Thread(target=run)
+        t.start()
+        time.sleep(0.15 * t_full)
+        P.pv_cancel(c)
+        t.join()
+        _say(f"[boundary] full call {t_full:.3f} s, cancelled at {0.15 * t_full:.3f} s, "
+             f"returned after {out['s']:.3f} s")
+        assert out["status"] == P.PV_ECANCELLED
+        assert out["s"] < 0.7 * t_full
+        res = P.pv_count_global(h, 3)
+        assert res.counts == ref.counts and res.stats["leaves"] == ref.stats["leaves"]
+        P.pv_graph_free(h)
+    finally:
+        P.pv_fini(c)
+
+
+def test_watchdog_stops_a_call_past_its_timeout(long_call_graph):
+    g = long_call_graph
+    small = gg.plant_cliques(gg.gnp(2000, 0.01, 51), [12], 52)
+    c = P.pv_init(0, timeout_ms=100)
+    try:
+        h = P.pv_graph_load_csr(c, g.n, g.row_ptr, g.col)
+        st, dt = _timed_edge_count(h)
+        _say(f"[boundary] stopped by the watchdog after {dt:.3f} s")
+        assert st == P.PV_ETIMEDOUT and dt < 0.8
+        P.pv_graph_free(h)
+        hs = P.pv_graph_load_csr(c, small.n, small.row_ptr, small.col)
+        res = P.pv_count_global(hs)
+        P.pv_graph_free(hs)
+    finally:
+        P.pv_fini(c)
+    want = O.count(small).glob
+    assert res.counts[: len(want)] == want
+
+
+# ---------------------------------------------------------- run records
+
+def test_run_records(tmp_path, monkeypatch):
+    path = tmp_path / "runs.jsonl"
+    monkeypatch.setenv("PV_RECORD", str(path))
+    g = gg.plant_cliques(gg.gnp(800, 0.02, 53), [15], 54)
+    c = P.pv_init(0)
+    monkeypatch.delenv("PV_RECORD")
+    try:
+        h = P.pv_graph_load_csr(c, g.n, g.row_ptr, g.col)
+        r1 = P.pv_count_global(h)
+        _, _, st2 = P.pv_count_local(h, P.PV_VERTEX, 3, 6)
+        P.pv_graph_free(h)
+    finally:
+        P.pv_fini(c)
+    recs = [json.loads(line) for line in path.read_text().splitlines()]
+    assert [r["call"] for r in recs] == ["count", "local"]
+    assert recs[0]["local"] == "none" and recs[1]["local"] == "vertex"
+    assert (recs[1]["k_lo"], recs[1]["k_hi"]) == (3, 6)
+    assert recs[0]["nodes"] == r1.stats["nodes"] and recs[0]["leaves"] == r1.stats["leaves"]
+    assert recs[0]["omega"] == r1.omega and recs[0]["status"] == P.PV_OK
+    assert recs[1]["leaves"] == st2["leaves"] and recs[0]["n"] == g.n and recs[0]["m"] == g.m
