@@ -37,6 +37,9 @@ static thread_local char g_last_error[256] = "";
 
 static void set_err(const char *what, hipError_t e) {
     snprintf(g_last_error, sizeof g_last_error, "%s: %s", what, hipGetErrorString(e));
+    // the failed call is reported here; its error must not stay behind as
+    // the thread's last error, where the next launch check would find it
+    (void)hipGetLastError();
 }
 
 #define HIPCHK(call)                                   \
@@ -53,6 +56,19 @@ static void set_err(const char *what, hipError_t e) {
         pv_status s_ = (call);           \
         if (s_ != PV_OK) return s_;      \
     } while (0)
+
+// p must be device memory (or managed memory) of the context's device.
+static pv_status require_device(int device, const void *p, const char *what) {
+    hipPointerAttribute_t at;
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) (void)hipGetLastError();
+    if (e != hipSuccess || (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) ||
+        at.device != device) {
+        snprintf(g_last_error, sizeof g_last_error, "%s must be device memory of device %d", what, device);
+        return PV_EINVAL;
+    }
+    return PV_OK;
+}
 
 extern "C" const char *pv_strerror(pv_status s) {
     switch (s) {
@@ -798,6 +814,8 @@ extern "C" pv_status pv_graph_load_csr_device(pv_ctx *c, int32_t n, int64_t nnz,
                                               uint32_t flags, pv_graph **out) {
     if (!c || !out || n < 0 || nnz < 0 || !d_row_ptr || (nnz > 0 && !d_col)) return PV_EINVAL;
     *out = nullptr;
+    PVCHK(require_device(c->device, d_row_ptr, "d_row_ptr"));
+    if (nnz > 0) PVCHK(require_device(c->device, d_col, "d_col"));
     HIPCHK(hipSetDevice(c->device));
     if (flags & (PV_DEDUP | PV_SYMMETRIZE)) {
         // repairs run on the host: a round trip of the CSR
@@ -926,6 +944,17 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     if (n > 0 && io[34]) {
         snprintf(g_last_error, sizeof g_last_error, "peel grid barrier timed out");
         return PV_EDEVICE;
+    }
+    if (c->debug && n > 0) {
+        PeelCtl pc;
+        HIPCHK(hipMemcpy(&pc, c->ws.ctl.p, offsetof(PeelCtl, bar_flag), hipMemcpyDeviceToHost));
+        const auto us = [&](int a, int b) { return (double)(pc.t_mark[b] - pc.t_mark[a]) * 0.01; };
+        fprintf(stderr,
+                "[pivoter] peel: %d sub-rounds, alpha %d; grid phase %.1f us (%d grid-wide sub-rounds, %d by "
+                "one block, %d level changes); compaction of the last %d vertices %.1f us; solo phase %.1f us "
+                "(%d sub-rounds)\n",
+                pc.subrounds, pc.alpha, us(0, 1), pc.n_grid, pc.n_block, pc.n_levels, pc.n_solo, us(1, 2),
+                us(2, 3), pc.subrounds - pc.n_grid - pc.n_block);
     }
     g->oriented = true;
     g->eids = false;
@@ -1124,7 +1153,9 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
         if (rq.edge) HIPCHK(hipMemsetAsync(c->ws.escr.p, 0, c->ws.escr.n * 8, s));
         HIPCHK(hipMemsetAsync(c->ws.hist.p, 0, sizeof(unsigned long long) * (size_t)rq.graphs * hd * hd, s));
         HIPCHK(hipMemsetAsync(c->ws.counters.p, 0, PV_NCOUNTERS * sizeof(unsigned long long), s));
-        HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, 5 * sizeof(int), s));  // flags,u_n,pref_n,omega,lovf
+        // flags, u_n, pref_n, omega, lovf, and the checked build's failed line
+        static_assert(SM_ERR == SM_FLAGS + 5, "walk scalars are contiguous");
+        HIPCHK(hipMemsetAsync(g->small.p + SM_FLAGS, 0, 6 * sizeof(int), s));
         const size_t lrows = rq.edge ? (size_t)(g->nnz / 2) : (size_t)g->n;
         const int kstride = rq.kstride > 0 ? rq.kstride : rq.K;
         if (local && lrows) {
@@ -1209,6 +1240,7 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                 a.hd = hd;
                 a.counters = c->ws.counters.p;
                 a.flags = g->small.p + SM_FLAGS;
+                a.check = g->small.p + SM_ERR;
                 a.vout = rq.vout;
                 a.klo = rq.klo;
                 a.K = rq.K;
@@ -1470,6 +1502,11 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
             snprintf(g_last_error, sizeof g_last_error, "edge id lookup failed");
             return PV_EDEVICE;
         }
+        if (io_fresh && (io[SM_FLAGS] & 8)) {
+            snprintf(g_last_error, sizeof g_last_error, "checked build: an invariant of the walk failed (sct.hip line %d)",
+                     io[SM_ERR]);
+            return PV_EDEVICE;
+        }
         g->last.items = (uint64_t)items;
         g->last.kernel_kl = rq.kl;
         g->last.kernel_lk = rq.kl ? rq.lk : 0;
@@ -1703,6 +1740,7 @@ static pv_status count_untuned(pv_graph *g, int32_t reorient, int32_t k_max, pv_
                                int32_t k_hi, pv_u128 *local_out, uint64_t *local_ovf, pv_stats *stats) {
     if (!g || cap < 0 || (cap > 0 && !counts)) return PV_EINVAL;
     if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
+    if (local_kind != PV_NONE) PVCHK(require_device(g->ctx->device, local_out, "local_out"));
     GraphUse use(g);
     BudgetScope scope(g->ctx);
     PVCHK(prepare(g, reorient != 0));
@@ -1716,6 +1754,7 @@ extern "C" pv_status pv_count(pv_graph *g, int32_t reorient, int32_t k_max, pv_u
                               uint64_t *local_ovf, pv_stats *stats) {
     if (!g || cap < 0 || (cap > 0 && !counts)) return PV_EINVAL;
     if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
+    if (local_kind != PV_NONE) PVCHK(require_device(g->ctx->device, local_out, "local_out"));
     GraphUse use(g);
     BudgetScope scope(g->ctx);
     PVCHK(prepare(g, reorient != 0));
@@ -1807,6 +1846,7 @@ extern "C" pv_status pv_local_frequency(pv_ctx *c, const pv_u128 *local, int64_t
     if (!c || rows < 0 || rows > INT32_MAX - 1 || K < 1 || col < 0 || col >= K || cap < 0 || !ndistinct ||
         (rows > 0 && !local) || (cap > 0 && (!values || !freq)))
         return PV_EINVAL;
+    if (rows > 0) PVCHK(require_device(c->device, local, "local"));
     HIPCHK(hipSetDevice(c->device));
     BudgetScope scope(c);
     hipStream_t s = c->stream;
@@ -1847,6 +1887,7 @@ extern "C" pv_status pv_local_frequency_static(pv_ctx *c, const pv_u128 *local, 
     if (!c || rows < 0 || K < 1 || col < 0 || col >= K || cap < 0 || !ndistinct || (rows > 0 && !local) ||
         (cap > 0 && (!values || !freq)))
         return PV_EINVAL;
+    if (rows > 0) PVCHK(require_device(c->device, local, "local"));
     if (rows > PV_FREQ_STATIC_ROWS) {
         snprintf(g_last_error, sizeof g_last_error, "%lld rows exceed the static scratch of %d rows",
                  (long long)rows, PV_FREQ_STATIC_ROWS);
@@ -1926,6 +1967,7 @@ extern "C" pv_status pv_count_roots(pv_graph *g, const int32_t *roots, int32_t n
     if (!g || nroots < 0 || (nroots > 0 && !roots) || cap < 0 || (cap > 0 && !counts))
         return PV_EINVAL;
     if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
+    if (local_kind != PV_NONE) PVCHK(require_device(g->ctx->device, local_out, "local_out"));
     if (local_ovf) *local_ovf = 0;
     GraphUse use(g);
     BudgetScope scope(g->ctx);
@@ -2003,6 +2045,7 @@ extern "C" pv_status pv_count_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, i
     if (!c || G < 0 || (G > 0 && (!gs || !counts)) || cap < 1) return PV_EINVAL;
     if (local_kind != PV_NONE && local_kind != PV_VERTEX) return PV_EINVAL;
     if (local_kind != PV_NONE && !local_out) return PV_EINVAL;
+    if (local_kind != PV_NONE) PVCHK(require_device(c->device, local_out, "local_out"));
     if (local_ovf) *local_ovf = 0;
     if (G == 0) {
         if (stats) *stats = pv_stats{};

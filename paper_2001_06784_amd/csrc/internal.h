@@ -24,6 +24,12 @@ struct PeelCtl {
     int err;             // out: a grid barrier timed out
     int nlong;           // rows of the solo subgraph split over the grid
     int blk_r, blk_nf, blk_removed;  // where block 0's run of small sub-rounds stopped
+    // out, for diagnostics: sub-rounds of the grid phase run by the whole
+    // grid, by block 0 alone, level changes of the grid phase, vertices left
+    // to the solo phase; the 100 MHz real-time clock at the start, at the
+    // end of the grid phase, after the compaction and at the end
+    int n_grid, n_block, n_levels, n_solo;
+    unsigned long long t_mark[4];
     unsigned bar_flag[256 * 32];  // grid barrier: barriers passed by each block, one 128-byte line each
 };
 
@@ -136,7 +142,9 @@ struct LevelArgs {
     int hd;
     unsigned long long *counters;  // PV_NCOUNTERS slots: nodes, leaves, work, -, work per unit kind [3],
                                    // child work, leaf sum of h + p, leaf sum of p + 1
-    int *flags;                    // bit0: buffer overflow
+    int *flags;                    // bit0: buffer overflow, bit2: edge id lookup failed,
+                                   // bit3: an invariant of the walk failed (checked builds)
+    int *check;                    // checked builds: source line of the first failed invariant
     // local counts
     uint64_t *vout;                // [n][kstride] (per vertex) or [m][kstride] (per edge) u128;
                                    // this pass writes columns 0..K-1

@@ -187,6 +187,8 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     const int nw = nth >> 6;
 
     unsigned epoch = 0;  // grid barriers this block has passed
+    if (tid == 0) ctl->t_mark[0] = __builtin_amdgcn_s_memrealtime();
+    int n_grid = 0, n_block = 0, n_levels = 0;  // kept by block 0 for the diagnostics
     for (int v = tid; v < n; v += nth) {
         deg[v] = rp[v + 1] - rp[v];
         sub[v] = -1;
@@ -225,6 +227,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             // loads in flight together; when one batch covers the graph, the
             // degrees stay in registers for the take pass (no decrement
             // happens between the two passes).
+            n_levels++;
             if (threadIdx.x == 0) s_kmin = 0x7fffffff;
             __syncthreads();
             int mymin = 0x7fffffff;
@@ -378,6 +381,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                     removed += nF;
                     nF = ld_acquire(ncnt);
                     r++;
+                    n_block++;
                     if (nF == 0 || nF > PEEL_BLOCK_FRONTIER || t + 1 >= PEEL_BLOCK_ROUNDS ||
                         n - removed <= PV_SOLO_MAX)
                         break;
@@ -444,6 +448,14 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         removed += nF;
         nF = ld_acquire(&ctl->cnt[(r + 1) % 3]);
         r++;
+        n_grid++;
+    }
+    if (tid == 0) {
+        ctl->t_mark[1] = __builtin_amdgcn_s_memrealtime();
+        ctl->n_grid = n_grid;
+        ctl->n_block = n_block;
+        ctl->n_levels = n_levels;
+        ctl->n_solo = n - removed;
     }
 
     // ------------------------------------ compaction of what is left (U)
@@ -616,6 +628,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     }
     if (!grid_barrier(ctl, nb, epoch)) return;
     if (blockIdx.x != 0) return;
+    if (threadIdx.x == 0) ctl->t_mark[2] = __builtin_amdgcn_s_memrealtime();
 
     // ------------------------------------------------ solo phase (block 0)
     // LDS holds the remaining degrees as 16-bit halves of 32-bit words (a
@@ -782,6 +795,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     if (threadIdx.x == 0) {
         ctl->subrounds = r;
         ctl->alpha = alpha;
+        ctl->t_mark[3] = __builtin_amdgcn_s_memrealtime();
     }
 }
 

@@ -34,6 +34,29 @@
 
 #define WAVES_PER_BLOCK 4
 
+// Checked builds (-DPV_CHECKED): invariants of the walk are tested on the
+// device -- a node's pivot lies in its set, the set, hold and pivot members
+// are disjoint, a universe's adjacency is symmetric without loops, stacks
+// stay within their frames, and a leaf's (h, p) bin lies in the histogram.
+// A failure sets bit 3 of the walk's flag word and keeps the source line of
+// the first one; the kernel runs on to its normal end and the host reports
+// the line.  Other builds compile the checks out (the condition is not
+// evaluated).
+#ifdef PV_CHECKED
+__device__ __noinline__ void pv_check_failed(int *flags, int *line_out, int line) {
+    atomicOr(flags, 8);
+    atomicCAS(line_out, 0, line);
+}
+#define PV_ASSERT(flags, line_out, cond)                                      \
+    do {                                                                      \
+        if (!(cond)) pv_check_failed((flags), (line_out), __LINE__);          \
+    } while (0)
+#else
+#define PV_ASSERT(flags, line_out, cond) \
+    do {                                 \
+    } while (0)
+#endif
+
 // ------------------------------------------------------------------ sinks
 
 // Global counts: leaf (h,p) -> L[h][p] += 1.  The workgroup keeps the bins
@@ -58,8 +81,15 @@ struct GlobalSink {
     const int *vgraph;          // batch: graph of every vertex (nullptr: one graph)
     int hd, lds_h;
     unsigned long long leaves;
+#ifdef PV_CHECKED
+    int *chk_flags, *chk_line;
+#endif
 
     __device__ void init(const LevelArgs &a, unsigned long long *lds_bins, int rows) {
+#ifdef PV_CHECKED
+        chk_flags = a.flags;
+        chk_line = a.check;
+#endif
         // an LDS-typed pointer: the bin update is a ds_add, not a flat atomic
         bins = (lds_u64 *)lds_bins;
         lds_h = rows;
@@ -78,6 +108,7 @@ struct GlobalSink {
     __device__ void add_leaves(uint32_t k, int) { leaves += k; }
 
     __device__ __forceinline__ void leaf(int h, int p, int lane) {
+        PV_ASSERT(chk_flags, chk_line, h >= 0 && p >= 0 && h + p < hd);
         if (vgraph) {
             if (lane == 0) atomicAdd(&ghist[(long long)h * hd + p], 1ull);
         } else if (h < lds_h && p < 64) {
@@ -90,6 +121,7 @@ struct GlobalSink {
 
     // a leaf of one lane's own subtree (lane tier): every lane its own (h,p)
     __device__ __forceinline__ void leaf_lane(int h, int p) {
+        PV_ASSERT(chk_flags, chk_line, h >= 0 && p >= 0 && h + p < hd);
         if (vgraph)
             atomicAdd(&ghist[(long long)h * hd + p], 1ull);
         else if (h < lds_h && p < 64)
@@ -802,8 +834,10 @@ __device__ __forceinline__ void lane_walk(uint64_t A, uint64_t qS, uint64_t qmH,
                         full = full && (c + 1 == sc);
                     }
                 }
+                PV_ASSERT(gs.chk_flags, gs.chk_line, ((S >> piv) & 1u) && (Hl & Pl) == 0 && (S & (Hl | Pl)) == 0);
                 if (best + 1 != sc) {
                     // frame: set, pivot, path members; then the pivot child
+                    PV_ASSERT(gs.chk_flags, gs.chk_line, depth < PV_LANE_MAX - 1);
                     st[depth][lane] = S | ((uint32_t)piv << 8) | (Hl << 11) | (Pl << 19);
                     depth++;
                     S &= row8(rows, piv);
@@ -1158,6 +1192,8 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                 const int piv = 63 - (int)(best & 63u);
                 const int pc = (int)(best >> 6) - 1;
                 const uint64_t pbit = 1ull << piv;
+                PV_ASSERT(a.flags, a.check, ((S >> piv) & 1) && (nm <= 0 || nm >= 64 || (S >> nm) == 0));
+                PV_ASSERT(a.flags, a.check, !LOCAL || ((H & P) == 0 && (S & (H | P)) == 0));
                 if (pc + 1 == s) {
                     // the pivot sees all of S: no hold child.  If every member
                     // does, S is a clique and its pivot chain ends in one leaf.
@@ -1181,6 +1217,7 @@ __device__ void compact_dfs(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
                 } else {
                     const uint64_t Ap = readlane64(A, piv);
                     if (h < hlim) {
+                        PV_ASSERT(a.flags, a.check, depth < 64);
                         // frame `depth` in lane `depth` (one lane index for the four writes)
                         const bool at = lane_id_here() == depth;
                         stS = at ? S : stS;
@@ -1303,6 +1340,21 @@ __device__ void compact_run(uint64_t A, uint64_t S, uint64_t H, uint64_t P, int 
     p = uniformi(p);
     uni = uniformi(uni);
     nm = uniformi(nm);
+#ifdef PV_CHECKED
+    {
+        // the universe's adjacency: rows inside the members, no loops,
+        // symmetric.  Walks of global counts do not carry the member count
+        // (nm = 0): then every lane is checked (a non-member's row is empty).
+        const int nmc = (nm > 0 && nm < 64) ? nm : 64;
+        const bool mem = lane < nmc;
+        bool okA = !mem || (((A >> lane) & 1) == 0 && (nmc >= 64 || (A >> nmc) == 0));
+        for (int j = 0; j < nmc; j++) {
+            const uint64_t Aj = readlane64(A, j);
+            okA = okA && (!mem || ((Aj >> lane) & 1) == ((A >> j) & 1));
+        }
+        PV_ASSERT(a.flags, a.check, okA && (nmc >= 64 || (S >> nmc) == 0));
+    }
+#endif
     // truncated tree: at h = k_max the subtree is one leaf (see compact_dfs);
     // a frame item carries its path totals in fmeta, not in h and p
     if (!from_frame && a.kmax > 0 && h >= a.kmax) S = 0;
@@ -1577,6 +1629,7 @@ __device__ bool mw_run(R rows, int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, in
         const int piv = 4095 - (int)(best & 4095u);
         const int pc = (int)(best >> 12) - 1;
         const int pw = piv >> 6;
+        PV_ASSERT(a.flags, a.check, pw < W && ((readlane64(Sw, pw) >> (piv & 63)) & 1) && pc >= 0 && pc < s);
         const uint64_t pb = (lane == pw) ? (1ull << (piv & 63)) : 0ull;
         const uint64_t Ap = wl ? rows(lane, piv) : 0ull;
         {
