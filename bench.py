@@ -229,7 +229,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["social", "batch", "serve", "copy", "rmat"], default="social")
     ap.add_argument("--scale", type=int, default=14, help="rmat: log2 of the vertex count")
-    ap.add_argument("--edge", action="store_true", help="rmat: also per-edge counts for k=3..8")
+    ap.add_argument("--edge", action="store_true",
+                    help="also per-edge counts for k=3..8 (one warm-up call, one timed call; not in the step)")
     ap.add_argument("--kmax", type=int, default=0, help="rmat: global counts truncated at k <= kmax (0: all k)")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: measured seconds")
     args = ap.parse_args()
@@ -315,6 +316,26 @@ def main():
                       "levels_by_kind": {kinds[i]: st["ms_kind"][i] for i in range(3)}},
         "roofline": roof,
     }
+    if args.edge:
+        # per-edge counts for k = 3..8 into a device table (m x 6 u128), after
+        # the timed steps; the graph is already oriented and the tree is cut at
+        # k_max = 8 hold vertices (Sec. 5, counting for a specific k)
+        del local
+        eloc = torch.zeros((g.m, 6, 2), dtype=torch.int64, device="cuda:0")
+        P.pv_count(h, reorient=False, k_max=8, local_kind=P.PV_EDGE, k_lo=3, k_hi=8, local_out=eloc.data_ptr())
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        eres, eovf = P.pv_count(h, reorient=False, k_max=8, local_kind=P.PV_EDGE, k_lo=3, k_hi=8,
+                                local_out=eloc.data_ptr())
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t1
+        est = eres.stats
+        line["per_edge_k3_8"] = {"s": te, "edges_per_s": g.m / te, "overflow": int(eovf),
+                                 "sct_nodes": est["nodes"], "sct_leaves": est["leaves"],
+                                 "device_ms": {"levels": est["ms_levels"],
+                                               "levels_by_kind": {kinds[i]: est["ms_kind"][i] for i in range(3)}}}
+        print(f"[bench] per-edge k=3..8: {te:.3f} s", file=sys.stderr, flush=True)
+        del eloc
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(g)
