@@ -229,8 +229,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=["social", "batch", "serve", "copy", "rmat"], default="social")
     ap.add_argument("--scale", type=int, default=14, help="rmat: log2 of the vertex count")
-    ap.add_argument("--edge", action="store_true",
-                    help="also per-edge counts for k=3..8 (one warm-up call, one timed call; not in the step)")
+    ap.add_argument("--edge", action=argparse.BooleanOptionalAction, default=None,
+                    help="also per-edge counts for k=3..8 (one warm-up call, one timed call; not in the step); "
+                         "default: on for the social workload, off for rmat")
     ap.add_argument("--kmax", type=int, default=0, help="rmat: global counts truncated at k <= kmax (0: all k)")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: measured seconds")
     args = ap.parse_args()
@@ -246,7 +247,9 @@ def main():
     if args.workload == "copy":
         return bench_copy()
     if args.workload == "rmat":
+        args.edge = bool(args.edge)
         return bench_rmat(args)
+    args.edge = args.edge is None or args.edge
 
     import torch
     from paper_2001_06784_amd import pivoter as P
