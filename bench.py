@@ -233,6 +233,10 @@ def main():
                     help="also per-edge counts for k=3..8 (one warm-up call, one timed call; not in the step); "
                          "default: on for the social workload, off for rmat")
     ap.add_argument("--kmax", type=int, default=0, help="rmat: global counts truncated at k <= kmax (0: all k)")
+    ap.add_argument("--sample", action="store_true",
+                    help="rmat: time the root subtrees of a stratified root sample instead of the whole graph")
+    ap.add_argument("--sample-scale", type=int, default=20,
+                    help="rmat --sample: roots per stratum as a multiple of the parity tests' sample (1: that sample)")
     ap.add_argument("--duration", type=float, default=20.0, help="serve: measured seconds")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -405,8 +409,12 @@ def bench_rmat(args):
     g = gg.rmat_web(scale=args.scale)
     print(f"[bench] rmat scale {args.scale}: n={g.n} m={g.m} generated in {time.perf_counter() - t0:.1f} s",
           file=sys.stderr, flush=True)
-    ctx = P.pv_init(0, torch.cuda.current_stream().cuda_stream)
+    # a sampled-root run stops with PV_ETIMEDOUT rather than run on if a
+    # call takes more than two minutes
+    ctx = P.pv_init(0, torch.cuda.current_stream().cuda_stream, timeout_ms=120000 if args.sample else 0)
     h = P.pv_graph_load_csr(ctx, g.n, g.row_ptr, g.col)
+    if args.sample:
+        return bench_rmat_sample(args, g, ctx, h)
     for i in range(max(1, args.warmup)):
         t1 = time.perf_counter()
         P.pv_count_global(h, args.kmax)
@@ -443,6 +451,66 @@ def bench_rmat(args):
         # the call returns the m x 6 u128 counts in host memory (copy included)
         line["per_edge_k3_8"] = {"s": te, "edges_per_s": g.m / te, "overflow": int(ovf),
                                  "sct_nodes": est["nodes"], "sct_leaves": est["leaves"]}
+    P.pv_graph_free(h)
+    P.pv_fini(ctx)
+    print(json.dumps(line), flush=True)
+
+
+def rmat_root_sample(g, key, scale=1):
+    """A seeded sample of roots in out-degree strata (0, 64], (64, 128],
+    (128, 256], (256, 512] (scale x 2000, 40, 10 and 5 roots) plus 5 roots
+    of out-degree 0.  With scale 1 it is the sample the sampled-root parity
+    tests check against the oracle.  Edge a->b iff (key[a], a) < (key[b], b)."""
+    deg = np.diff(g.row_ptr).astype(np.int64)
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    cols = g.col.astype(np.int64)
+    fwd = (key[rows] < key[cols]) | ((key[rows] == key[cols]) & (rows < cols))
+    od = np.bincount(rows[fwd], minlength=g.n)
+    rng = np.random.default_rng(2022)
+    parts = []
+    for lo, hi, cnt in [(0, 64, 2000), (64, 128, 40), (128, 256, 10), (256, 512, 5)]:
+        pool = np.nonzero((od > lo) & (od <= hi))[0]
+        parts.append(rng.choice(pool, min(cnt * scale, len(pool)), replace=False))
+    parts.append(np.nonzero(od == 0)[0][:5])
+    return np.concatenate(parts).astype(np.int32), od
+
+
+def bench_rmat_sample(args, g, ctx, h):
+    """SCT leaves/s of the root subtrees of a stratified root sample (the
+    R-MAT protocol where the whole tree cannot be walked): global counts of
+    the cliques whose smallest-key vertex is a sampled root, for all k or
+    truncated at --kmax."""
+    import torch
+    from paper_2001_06784_amd import pivoter as P
+    P.pv_graph_orient(h)
+    key = P.pv_graph_export_order(h)
+    roots, od = rmat_root_sample(g, key, args.sample_scale)
+    print(f"[bench] {len(roots)} sampled roots, out-degrees up to {int(od[roots].max())}", file=sys.stderr, flush=True)
+    for i in range(max(1, args.warmup)):
+        t1 = time.perf_counter()
+        P.pv_count_roots(h, roots, k_max=args.kmax)
+        print(f"[bench] warm-up {i}: {time.perf_counter() - t1:.2f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = P.pv_count_roots(h, roots, k_max=args.kmax)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    st = res.stats
+    line = {
+        "metric": "SCT leaves/sec over a stratified root sample" + (f" (k <= {args.kmax})" if args.kmax else " (all k)"),
+        "value": st["leaves"] / dt, "unit": "leaves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": max(1, args.warmup), "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u128", "data": "synthetic",
+        "config": {"workload": (f"rmat scale={args.scale} edge_factor=24 a=0.57 b=0.19 c=0.19 seed=1 "
+                                "+ 50 planted cliques of 20..60; root subtrees of a seeded sample in out-degree "
+                                f"strata (0,64]:{2000 * args.sample_scale} (64,128]:{40 * args.sample_scale} "
+                                f"(128,256]:{10 * args.sample_scale} (256,512]:{5 * args.sample_scale}, "
+                                "5 of out-degree 0"),
+                   "n": g.n, "m": g.m, "alpha": int(od.max()), "roots": int(len(roots)),
+                   "max_root_out_degree": int(od[roots].max()), "omega": res.omega,
+                   "sct_nodes": st["nodes"], "sct_leaves": st["leaves"], "overflow_k": res.overflow},
+    }
     P.pv_graph_free(h)
     P.pv_fini(ctx)
     print(json.dumps(line), flush=True)
