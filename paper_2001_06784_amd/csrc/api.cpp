@@ -727,7 +727,7 @@ static pv_status graph_validate(pv_graph *g, uint32_t flags) {
     HIPCHK(hipMemcpyAsync(err, g->small.p + SM_ERR, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (*err) return PV_ENOTSIMPLE;
-    HIPCHK(pv_launch_validate(g->n, g->rp.p, g->col.p, g->small.p + SM_ERR, c->stream));
+    HIPCHK(pv_launch_validate(g->n, g->nnz, g->rp.p, g->col.p, g->small.p + SM_ERR, c->stream));
     HIPCHK(hipMemcpyAsync(err, g->small.p + SM_ERR, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return *err ? PV_ENOTSIMPLE : PV_OK;

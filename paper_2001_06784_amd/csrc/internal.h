@@ -185,7 +185,7 @@ struct LevelArgs {
 
 
 hipError_t pv_launch_check_rowptr(int n, long long nnz, const int *rp, int *d_err, hipStream_t s);
-hipError_t pv_launch_validate(int n, const int *rp, const int *col, int *d_err, hipStream_t s);
+hipError_t pv_launch_validate(int n, long long nnz, const int *rp, const int *col, int *d_err, hipStream_t s);
 hipError_t pv_launch_peel(const DevInfo &dev, const PeelArgs &pa, hipStream_t s);
 // row_tmp: nnz ints of scratch (N+(v) staged at rp[v])
 hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,

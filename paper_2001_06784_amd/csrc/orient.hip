@@ -21,34 +21,54 @@
 #include <algorithm>
 
 // ------------------------------------------------------------ validation
-// One wave per vertex: sorted strictly increasing rows, ids in range, no
-// self loops, and every (v,u) has its reverse (u,v).
-__global__ void __launch_bounds__(256) validate_kernel(int n, const int *__restrict__ rp,
+// Every row entry is checked: ids in range, no self loops, rows strictly
+// increasing, and every (v,u) has its reverse (u,v), found by binary search
+// in row u.  The entries are taken in chunks of VALIDATE_CHUNK, a wave per
+// chunk, so a hub's row is spread over many waves; a lane finds the row of
+// its entry by binary search of the row pointers between the rows of the
+// chunk's first and last entries.  The row pointers are already checked
+// (monotone, rp[0] = 0, rp[n] = nnz).
+#define VALIDATE_CHUNK 512
+
+// the row holding entry i: the largest v in [lo, hi] with rp[v] <= i
+__device__ __forceinline__ int row_of(const int *__restrict__ rp, int lo, int hi, int i) {
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rp[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) validate_kernel(int n, int nnz, const int *__restrict__ rp,
                                                         const int *__restrict__ col,
                                                         int *__restrict__ err) {
     const int lane = threadIdx.x & 63;
-    const int nw = (gridDim.x * blockDim.x) >> 6;
-    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; v < n; v += nw) {
-        const int b = rp[v], e = rp[v + 1];
-        if (e < b) {
-            if (lane == 0) atomicOr(err, 1);
-            continue;
-        }
-        bool bad = false;
-        for (int i = b + lane; i < e; i += 64) {
+    const long long nw = (long long)(gridDim.x * blockDim.x) >> 6;
+    bool bad = false;
+    for (long long c0 = (long long)((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * VALIDATE_CHUNK; c0 < nnz;
+         c0 += nw * VALIDATE_CHUNK) {
+        const int i0 = (int)c0, i1 = (int)min(c0 + VALIDATE_CHUNK, (long long)nnz) - 1;
+        // rows of the chunk's first and last entries (lanes 0 and 1)
+        int r = 0;
+        if (lane < 2) r = row_of(rp, 0, n - 1, lane == 0 ? i0 : i1);
+        const int va = __shfl(r, 0), vb = __shfl(r, 1);
+        for (int i = i0 + lane; i <= i1; i += 64) {
+            const int v = (va == vb) ? va : row_of(rp, va, vb, i);
             const int u = col[i];
-            if (u < 0 || u >= n || u == v) { bad = true; continue; }
-            if (i > b && col[i - 1] >= u) bad = true;
-            // reverse edge by binary search in row u
+            if (u < 0 || u >= n || u == v) {
+                bad = true;
+                continue;
+            }
+            if (i > rp[v] && col[i - 1] >= u) bad = true;
             int lo = rp[u], hi = rp[u + 1];
             while (lo < hi) {
-                int mid = (lo + hi) >> 1;
+                const int mid = (lo + hi) >> 1;
                 if (col[mid] < v) lo = mid + 1; else hi = mid;
             }
             if (lo >= rp[u + 1] || col[lo] != v) bad = true;
         }
-        if (ballot64(bad) && lane == 0) atomicOr(err, 2);
     }
+    if (ballot64(bad) && lane == 0) atomicOr(err, 2);
 }
 
 __global__ void check_rowptr_kernel(int n, long long nnz, const int *__restrict__ rp,
@@ -1128,8 +1148,11 @@ hipError_t pv_launch_check_rowptr(int n, long long nnz, const int *rp, int *d_er
 }
 
 // only after the row pointers passed pv_launch_check_rowptr
-hipError_t pv_launch_validate(int n, const int *rp, const int *col, int *d_err, hipStream_t s) {
-    validate_kernel<<<grid_for((long long)n * 64, 256, 8192), 256, 0, s>>>(n, rp, col, d_err);
+hipError_t pv_launch_validate(int n, long long nnz, const int *rp, const int *col, int *d_err, hipStream_t s) {
+    if (n <= 0 || nnz <= 0) return hipSuccess;
+    // four waves per block, one chunk per wave and pass
+    validate_kernel<<<grid_for((nnz + VALIDATE_CHUNK - 1) / VALIDATE_CHUNK, 4, 8192), 256, 0, s>>>(
+        n, (int)nnz, rp, col, d_err);
     return hipGetLastError();
 }
 
