@@ -170,6 +170,7 @@ struct DBuf {
 struct Workspace {
     // peel / orientation temporaries
     DBuf<int> deg, fa, fb, scan, rcnt;  // rcnt: per-chunk out-degree histograms of the root order
+    DBuf<int> owide;                    // orientation: the rows walked by a whole workgroup
     DBuf<int> lid, uverts, ldeg, lrp, lcol, bcnt, lrow;  // solo phase of the peel
     DBuf<PeelCtl> ctl;
     // SCT work buffers
@@ -223,7 +224,7 @@ struct Workspace {
     }
 
     void release() {
-        DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &lid, &uverts, &ldeg, &lrp, &lcol,
+        DBuf<int> *ib[] = {&deg, &fa, &fb, &scan, &rcnt, &owide, &lid, &uverts, &ldeg, &lrp, &lcol,
                            &bcnt, &hu_vl, &u_gid, &pref_pool, &omegas, &u_root, &ueid, &weid,
                            &u_grp, &pg_cnt, &pg_off, &pg_pos, &pg_list, &wide_i, &fq_flags, &fq_idx,
                            &fq_pos, &lrow};
@@ -898,6 +899,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
     PVCHK(c->ws.lcol.ensure((size_t)std::max<long long>(g->nnz, 1)));
     PVCHK(c->ws.bcnt.ensure(PV_PEEL_MAX_BLOCKS));
     PVCHK(c->ws.lrow.ensure(2 * PV_SOLO_MAX));
+    PVCHK(c->ws.owide.ensure((size_t)(g->nnz / PV_ORIENT_BLOCK_ROW) + 2));
     hipStream_t s = c->stream;
     PeelCtl init;
     memset(&init, 0, sizeof init);
@@ -926,7 +928,7 @@ extern "C" pv_status pv_graph_orient(pv_graph *g, int32_t *alpha_out) {
         HIPCHK(pv_launch_peel(c->dev, pa, s));
         if (c->timing) HIPCHK(hipEventRecord(c->ev[1], s));
         HIPCHK(pv_launch_orient(c->dev, n, g->rp.p, g->col.p, g->sub.p, g->odeg.p, g->orow.p,
-                                g->ocol.p, g->small.p + SM_ALPHA, c->ws.scan.p, c->ws.lcol.p, s));
+                                g->ocol.p, g->small.p + SM_ALPHA, c->ws.scan.p, c->ws.lcol.p, c->ws.owide.p, s));
         HIPCHK(pv_launch_root_order(n, g->small.p + SM_ALPHA, g->odeg.p, c->ws.rcnt.p, pv_root_chunks(n),
                                     g->order.p, g->small.p + SM_BOUNDS, PV_LIGHT_MAX, s));
         if (c->timing) HIPCHK(hipEventRecord(c->ev[2], s));

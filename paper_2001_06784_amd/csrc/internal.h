@@ -188,9 +188,12 @@ hipError_t pv_launch_check_rowptr(int n, long long nnz, const int *rp, int *d_er
 hipError_t pv_launch_validate(int n, long long nnz, const int *rp, const int *col, int *d_err, hipStream_t s);
 hipError_t pv_launch_peel(const DevInfo &dev, const PeelArgs &pa, hipStream_t s);
 // row_tmp: nnz ints of scratch (N+(v) staged at rp[v])
+// rows longer than this are walked by a whole workgroup when the orientation
+// counts out-degrees (a hub's row would hold one wave for its whole length)
+#define PV_ORIENT_BLOCK_ROW 4096
 hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
                             int *odeg, int *orow, int *ocol, int *alpha, int *scan_tmp, int *row_tmp,
-                            hipStream_t s);
+                            int *wide, hipStream_t s);  // wide: [1 + nnz / PV_ORIENT_BLOCK_ROW] ints
 // roots by out-degree, largest first; bh: chunks * (PV_MAX_ALPHA + 1) ints
 hipError_t pv_launch_root_order(int n, const int *amax, const int *odeg, int *bh, int chunks,
                                 int *order, int *bounds, int light_max, hipStream_t s);

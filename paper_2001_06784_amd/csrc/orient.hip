@@ -833,12 +833,14 @@ __device__ __forceinline__ bool key_less(int su, int u, int sv, int v) {
 
 // out-degree of every vertex; N+(v) (row order kept, so increasing id) is
 // also written to tmp at v's own row start rp[v]: serial per lane, ballot
-// compaction per wave
+// compaction per wave.  Rows longer than PV_ORIENT_BLOCK_ROW are only
+// listed in wlist[1..] (count in wlist[0]) for odeg_rows_kernel.
 __global__ void __launch_bounds__(256) odeg_kernel(int n, const int *__restrict__ rp,
                                                     const int *__restrict__ col,
                                                     const int *__restrict__ sub,
                                                     int *__restrict__ odeg,
-                                                    int *__restrict__ alpha, int *__restrict__ tmp) {
+                                                    int *__restrict__ alpha, int *__restrict__ tmp,
+                                                    int *__restrict__ wlist) {
     const int lane = threadIdx.x & 63;
     const int nw = (gridDim.x * blockDim.x) >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -851,9 +853,11 @@ __global__ void __launch_bounds__(256) odeg_kernel(int n, const int *__restrict_
             e = rp[v + 1];
             sv = sub[v];
         }
-        const bool wide = v < n && e - b > ORIENT_LANE_ROW;
+        const bool huge = v < n && e - b > PV_ORIENT_BLOCK_ROW;
+        const bool wide = v < n && e - b > ORIENT_LANE_ROW && !huge;
         int c = 0;
-        if (v < n && !wide)
+        if (huge) wlist[1 + atomicAdd(wlist, 1)] = v;
+        if (v < n && !wide && !huge)
             // ORIENT_UNROLL entries a step: their column and key loads in
             // flight together rather than one dependent pair at a time
             for (int i0 = b; i0 < e; i0 += ORIENT_UNROLL) {
@@ -885,11 +889,61 @@ __global__ void __launch_bounds__(256) odeg_kernel(int n, const int *__restrict_
             }
             if (lane == L) c = w - xb;
         }
-        if (v < n) odeg[v] = c;
+        if (v < n && !huge) odeg[v] = c;
         amax = max(amax, c);
     }
     amax = wave_max_i32(amax);
     if (lane == 0) atomicMax(alpha, amax);
+}
+
+// The listed long rows, a workgroup per row: each step a thread reads four
+// consecutive entries, and a workgroup scan of the threads' take counts
+// keeps N+(v) in row order
+__global__ void __launch_bounds__(256) odeg_rows_kernel(const int *__restrict__ rp,
+                                                         const int *__restrict__ col,
+                                                         const int *__restrict__ sub,
+                                                         int *__restrict__ odeg,
+                                                         int *__restrict__ alpha, int *__restrict__ tmp,
+                                                         const int *__restrict__ wide) {
+    __shared__ int s_w[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nwide = wide[0];
+    for (int t = blockIdx.x; t < nwide; t += gridDim.x) {
+        const int x = wide[1 + t];
+        const int sx = sub[x], xb = rp[x], xe = rp[x + 1];
+        int w = xb;
+        for (int i0 = xb; i0 < xe; i0 += 4 * 256) {
+            const int base = i0 + 4 * (int)threadIdx.x;
+            int u[4];
+            bool tk[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) u[q] = (base + q < xe) ? col[base + q] : 0;
+            int cnt = 0;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                tk[q] = base + q < xe && key_less(sx, x, sub[u[q]], u[q]);
+                cnt += tk[q] ? 1 : 0;
+            }
+            const int inc = wave_incl_scan(cnt);
+            if (lane == 63) s_w[wv] = inc;
+            __syncthreads();
+            int off = inc - cnt, tot = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                off += (j < wv) ? s_w[j] : 0;
+                tot += s_w[j];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+                if (tk[q]) tmp[w + off++] = u[q];
+            w += tot;
+            __syncthreads();  // s_w is written again by the next step
+        }
+        if (threadIdx.x == 0) {
+            odeg[x] = w - xb;
+            atomicMax(alpha, w - xb);
+        }
+    }
 }
 
 // N+(v) moved from tmp (at rp[v]) to its place in the oriented CSR:
@@ -1191,10 +1245,14 @@ hipError_t pv_launch_excl_scan(int n, const int *in, int *tmp, int *out, hipStre
 
 hipError_t pv_launch_orient(const DevInfo &dev, int n, const int *rp, const int *col, const int *sub,
                             int *odeg, int *orow, int *ocol, int *alpha, int *scan_tmp, int *row_tmp,
-                            hipStream_t s) {
+                            int *wide, hipStream_t s) {
     // a wave takes 64 vertices per step
     const int wblocks = grid_for((long long)n, 256, dev.num_cu * 32);
-    odeg_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, odeg, alpha, row_tmp);
+    hipError_t e = hipMemsetAsync(wide, 0, sizeof(int), s);
+    if (e != hipSuccess) return e;
+    odeg_kernel<<<wblocks, 256, 0, s>>>(n, rp, col, sub, odeg, alpha, row_tmp, wide);
+    // the long rows, however many were listed: blocks without one exit
+    odeg_rows_kernel<<<dev.num_cu * 2, 256, 0, s>>>(rp, col, sub, odeg, alpha, row_tmp, wide);
     (void)pv_launch_excl_scan(n, odeg, scan_tmp, orow, s);
     ofill_kernel<<<wblocks, 256, 0, s>>>(n, rp, row_tmp, orow, ocol);
     return hipGetLastError();
