@@ -156,6 +156,10 @@ __device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
 // vertices per thread a level change reads with their loads in flight
 // together (and holds in registers when one batch covers the graph)
 #define PEEL_LC_BATCH 16
+// vertices per thread whose loads a level change's take pass has in flight
+// together when the degrees are read again (fewer than PEEL_LC_BATCH: the
+// take keeps three values per vertex live)
+#define PEEL_TAKE_BATCH 8
 // row entries per lane a step of U's compaction reads (loads in flight)
 #define PEEL_CSR_UNROLL 8
 // rows of U longer than this are split over the grid's waves
@@ -306,11 +310,45 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                     }
                 }
             } else {
-                for (int vb = wid * 64; vb < n; vb += nw * 64) {
-                    const int v = vb + lane;
-                    const bool take = v < n && sub[v] < 0 && deg[v] <= k;
-                    if (take) sub[v] = r;
-                    list_add(take, v, F, &ctl->cnt[r % 3]);
+                // the same take, reading the degrees again: PEEL_TAKE_BATCH
+                // vertices per thread with their loads in flight together
+                // (a pass of one vertex per lane waits on a load pair per
+                // 64 vertices of a wave: 64 round trips per level change on
+                // a 4M-vertex graph)
+                const uint64_t bl = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+                for (int vb = 0; vb < n; vb += nth * PEEL_TAKE_BATCH) {
+                    bool tk[PEEL_TAKE_BATCH];
+                    int sq[PEEL_TAKE_BATCH], dq[PEEL_TAKE_BATCH];
+#pragma unroll
+                    for (int q = 0; q < PEEL_TAKE_BATCH; q++) {
+                        const int v = vb + q * nth + tid;
+                        const int vv = v < n ? v : 0;
+                        sq[q] = sub[vv];
+                        dq[q] = deg[vv];
+                    }
+                    int tt = 0;
+#pragma unroll
+                    for (int q = 0; q < PEEL_TAKE_BATCH; q++) {
+                        tk[q] = vb + q * nth + tid < n && sq[q] < 0 && dq[q] <= k;
+                        tt += __popcll(ballot64(tk[q]));
+                    }
+                    if (tt) {
+                        int slot = 0;
+                        if (lane == 0) slot = atomicAdd(&s_nj, tt);
+                        slot = __shfl(slot, 0);
+#pragma unroll
+                        for (int q = 0; q < PEEL_TAKE_BATCH; q++) {
+                            const uint64_t m = ballot64(tk[q]);
+                            if (tk[q]) {
+                                const int v = vb + q * nth + tid;
+                                sub[v] = r;
+                                const int sl = slot + __popcll(m & bl);
+                                if (sl < PEEL_JOIN_LDS) s_join[sl] = v;
+                                else F[atomicAdd(&ctl->cnt[r % 3], 1)] = v;
+                            }
+                            slot += __popcll(m);
+                        }
+                    }
                 }
             }
             list_flush(F, &ctl->cnt[r % 3]);
