@@ -131,20 +131,6 @@ __device__ bool grid_barrier(PeelCtl *ctl, int nblocks, unsigned &epoch) {
     return s_ok != 0;
 }
 
-// Frontier slot of every lane where pred holds, taken from *cnt with one
-// atomic per wave (the order inside a frontier is immaterial: a vertex's key
-// is its sub-round); -1 elsewhere.  All lanes of the wave take part.
-__device__ __forceinline__ int wave_slot(bool pred, int *cnt) {
-    const uint64_t m = ballot64(pred);
-    if (m == 0) return -1;
-    const int lane = threadIdx.x & 63;
-    const int leader = __builtin_ctzll(m);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(cnt, __popcll(m));
-    base = __shfl(base, leader);
-    return pred ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
-}
-
 // edges a wave takes per step of a frontier vertex's row (4 per lane, so
 // that four independent load/atomic chains are in flight)
 #define PEEL_UNROLL 4
@@ -228,12 +214,17 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
     // done.
     __shared__ int s_join[PEEL_JOIN_LDS];
     __shared__ int s_nj, s_jbase, s_kmin;
-    const auto list_add = [&](bool add, int x, int *Fo, int *cnt) {
-        const int slot = wave_slot(add, &s_nj);
-        if (add) {
-            if (slot < PEEL_JOIN_LDS) s_join[slot] = x;
-            else Fo[atomicAdd(cnt, 1)] = x;
-        }
+    // a wave holding list slots [slot, slot + cnt_) sends those past the LDS
+    // list's end straight to the frontier, reserved with one global atomic
+    // for the wave (one per vertex serialises on the counter: 1.6M vertices
+    // of a first level took 21 ms); entry sl >= PEEL_JOIN_LDS goes to
+    // Fo[base + sl - first]
+    const auto overflow_base = [&](int slot, int cnt_, int *cnt) {
+        const int first = max(slot, PEEL_JOIN_LDS);
+        const int over = slot + cnt_ - first;
+        int base = 0;
+        if (over > 0 && lane == 0) base = atomicAdd(cnt, over);
+        return __shfl(base, 0) - first;
     };
     const auto list_flush = [&](int *Fo, int *cnt) {
         __syncthreads();
@@ -295,6 +286,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                     int slot = 0;
                     if (lane == 0) slot = atomicAdd(&s_nj, tt);
                     slot = __shfl(slot, 0);
+                    const int ob = overflow_base(slot, tt, &ctl->cnt[r % 3]);
 #pragma unroll
                     for (int q = 0; q < PEEL_LC_BATCH; q++) {
                         const bool take = dk[q] <= k;
@@ -304,7 +296,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                             sub[v] = r;
                             const int sl = slot + __popcll(m & bl);
                             if (sl < PEEL_JOIN_LDS) s_join[sl] = v;
-                            else F[atomicAdd(&ctl->cnt[r % 3], 1)] = v;
+                            else F[ob + sl] = v;
                         }
                         slot += __popcll(m);
                     }
@@ -336,6 +328,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                         int slot = 0;
                         if (lane == 0) slot = atomicAdd(&s_nj, tt);
                         slot = __shfl(slot, 0);
+                        const int ob = overflow_base(slot, tt, &ctl->cnt[r % 3]);
 #pragma unroll
                         for (int q = 0; q < PEEL_TAKE_BATCH; q++) {
                             const uint64_t m = ballot64(tk[q]);
@@ -344,7 +337,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                                 sub[v] = r;
                                 const int sl = slot + __popcll(m & bl);
                                 if (sl < PEEL_JOIN_LDS) s_join[sl] = v;
-                                else F[atomicAdd(&ctl->cnt[r % 3], 1)] = v;
+                                else F[ob + sl] = v;
                             }
                             slot += __popcll(m);
                         }
@@ -394,12 +387,13 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                 int slot = 0;
                 if (lane == 0) slot = atomicAdd(&s_nj, jt);
                 slot = __shfl(slot, 0);
+                const int ob = overflow_base(slot, jt, ncnt);
 #pragma unroll
                 for (int q = 0; q < PEEL_UNROLL; q++) {
                     if (join[q]) {
                         const int sl = slot + __popcll(jm[q] & bl);
                         if (sl < PEEL_JOIN_LDS) s_join[sl] = u[q];
-                        else Fn[atomicAdd(ncnt, 1)] = u[q];
+                        else Fn[ob + sl] = u[q];
                     }
                     slot += __popcll(jm[q]);
                 }
