@@ -37,3 +37,26 @@ def test_rmat_web_plants_disjoint_cliques():
         for a in vs:
             row = set(g.col[g.row_ptr[a]: g.row_ptr[a + 1]].tolist())
             assert all(b in row for b in vs if b != a)
+
+
+def test_rmat_root_sample_matches_the_parity_sample():
+    # the benchmark's stratified root sample: with scale 1 it is the sample
+    # the sampled-root parity tests draw (same strata, seed and order), and a
+    # larger scale keeps to the strata
+    sys.path.insert(0, ROOT)
+    import bench
+    from oracle import oracle as O
+    g = gg.rmat_web(scale=12, cliques=4, clique_lo=20, clique_hi=24)
+    key = O.peel(g).sub
+    roots, od = bench.rmat_root_sample(g, key, 1)
+    assert np.array_equal(od, O.out_degrees(g, key))
+    rng = np.random.default_rng(2022)
+    want = []
+    for lo, hi, cnt in [(0, 64, 2000), (64, 128, 40), (128, 256, 10), (256, 512, 5)]:
+        pool = np.nonzero((od > lo) & (od <= hi))[0]
+        want.append(rng.choice(pool, min(cnt, len(pool)), replace=False))
+    want.append(np.nonzero(od == 0)[0][:5])
+    assert np.array_equal(roots, np.concatenate(want).astype(np.int32))
+    big, _ = bench.rmat_root_sample(g, key, 3)
+    assert len(np.unique(big)) == len(big)
+    assert len(big) >= len(roots) and od[big].max() <= 512
