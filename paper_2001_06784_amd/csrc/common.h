@@ -105,6 +105,18 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t x) {
     return readlane32(x, 63);
 }
 
+// Full-wave bitwise OR, returned wave-uniform (the steps of wave_max_u32:
+// OR is idempotent too).  Every lane of the wave must be active.
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t x) {
+    x |= dpp_mov<0xB1, 0xF>(x);
+    x |= dpp_mov<0x4E, 0xF>(x);
+    x |= dpp_mov<0x141, 0xF>(x);
+    x |= dpp_mov<0x140, 0xF>(x);
+    x |= dpp_mov<0x142, 0xA>(x);
+    x |= dpp_mov<0x143, 0xC>(x);
+    return readlane32(x, 63);
+}
+
 // Sum over the wave via cross-lane shuffles (not on the hot path).
 __device__ __forceinline__ uint32_t wave_add_u32(uint32_t x) {
     for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);

@@ -1675,9 +1675,26 @@ __device__ bool mw_run(R rows, int hu, uint64_t Sw, uint64_t Hw, uint64_t Pw, in
 // Induced adjacency of N+(v): for each u_j in N+(v) and each w in N+(u_j),
 // w in N+(v) at position i means u_j ~ u_i (each edge inside N+(v) is seen
 // once, from its smaller-key end).
+//
+// A light root's members' out-lists are flattened over the lanes, 64 edges
+// a step.  The owner of edge q is the member with the largest start <= q
+// among those with a nonempty list: a wave-wide OR marks the starts that
+// fall in the step, and a popcount below the lane ranks the owner.  Whether
+// the other end w is a member, and which, comes from a hash of the member
+// ids in LDS (HS slots, linear probing, at most 62 keys).  The kernels of
+// global counts, whose occupancy the LDS bounds, take 128 slots; the
+// per-vertex and per-edge kernels, bound by registers, take 256 (shorter
+// probe runs).
 
-__device__ uint64_t gather_light(int v, int lane, const LevelArgs &a, int *s_vl, int *s_pre, int *s_base,
-                                 unsigned long long *s_A, int &d, int &gid, int *etab) {
+template <int HS>
+__device__ __forceinline__ int gather_slot(int x) {
+    static_assert(HS == 128 || HS == 256, "hash of 7 or 8 bits");
+    return (int)(((uint32_t)x * 2654435761u) >> (HS == 256 ? 24 : 25));
+}
+
+template <int HS>
+__device__ uint64_t gather_light(int v, int lane, const LevelArgs &a, int *s_nz, int *s_base,
+                                 unsigned long long *s_A, int *s_hk, uint8_t *s_hv, int &d, int &gid, int *etab) {
     const int b = a.orow[v];
     d = a.orow[v + 1] - b;
     const int u = (lane < d) ? a.ocol[b + lane] : 0x7fffffff;
@@ -1686,30 +1703,48 @@ __device__ uint64_t gather_light(int v, int lane, const LevelArgs &a, int *s_vl,
     const int od = (lane < d) ? (a.orow[u + 1] - ub) : 0;
     const int incl = wave_incl_scan(od);
     const int total = (int)readlane32((uint32_t)incl, 63);
-    s_vl[lane] = u;
-    s_pre[lane] = incl - od;
+    const int pre = incl - od;  // this member's first edge in the flattened order
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t nzm = ballot64(od > 0);
+    if (od > 0) s_nz[__popcll(nzm & below)] = lane;  // rank among nonempty lists -> member
     // edge q of the flattened lists sits at ocol[s_base[j] + q] (member j
     // owning q): no second read of the row pointers
-    s_base[lane] = ub - (incl - od);
+    s_base[lane] = ub - pre;
     s_A[lane] = 0ull;
+#pragma unroll
+    for (int i = 0; i < HS / 64; i++) s_hk[lane + 64 * i] = -1;
+    wave_sync();
+    if (lane < d) {
+        int h = gather_slot<HS>(u);
+        while (atomicCAS(&s_hk[h], -1, u) != -1) h = (h + 1) & (HS - 1);
+        s_hv[h] = (uint8_t)lane;
+    }
     wave_sync();
     for (int q0 = 0; q0 < total; q0 += 64) {
+        // starts of nonempty lists in [q0, q0 + 64), and how many came before
+        const bool inwin = od > 0 && pre >= q0 && pre < q0 + 64;
+        const int sh = inwin ? pre - q0 : 0;
+        const uint32_t mlo = wave_or_u32((inwin && sh < 32) ? 1u << sh : 0u);
+        const uint32_t mhi = wave_or_u32((inwin && sh >= 32) ? 1u << (sh - 32) : 0u);
+        const uint64_t mwin = ((uint64_t)mhi << 32) | mlo;
+        const int before = __popcll(ballot64(od > 0 && pre < q0));
         const int q = q0 + lane;
         if (q < total) {
-            int lo = 0, hi = d - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_pre[mid] <= q) lo = mid; else hi = mid - 1;
-            }
-            const int j = lo;
+            const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+            const int j = s_nz[before + __popcll(mwin & upto) - 1];
             const int pos = s_base[j] + q;
             const int w = a.ocol[pos];
-            int l2 = 0, h2 = d;
-            while (l2 < h2) {
-                const int mid = (l2 + h2) >> 1;
-                if (s_vl[mid] < w) l2 = mid + 1; else h2 = mid;
+            int h = gather_slot<HS>(w), l2 = -1;
+            for (;;) {
+                const int k = s_hk[h];
+                if (k == w) {
+                    l2 = s_hv[h];
+                    break;
+                }
+                if (k < 0) break;
+                h = (h + 1) & (HS - 1);
             }
-            if (l2 < d && s_vl[l2] == w) {
+            if (l2 >= 0) {
                 atomicOr(&s_A[j], 1ull << l2);
                 atomicOr(&s_A[l2], 1ull << j);
                 if (etab) {
@@ -2061,10 +2096,12 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
         // that order: a unit's pushes precede its count, so the sum cannot
         // meet the count while work is left).
         __shared__ int s_memb[WAVES_PER_BLOCK][64];
-        __shared__ int s_vl[WAVES_PER_BLOCK][64];
-        __shared__ int s_pre[WAVES_PER_BLOCK][64];
+        __shared__ int s_nz[WAVES_PER_BLOCK][64];
         __shared__ int s_base[WAVES_PER_BLOCK][64];
         __shared__ unsigned long long s_A[WAVES_PER_BLOCK][64];
+        constexpr int GATHER_HS = LOCAL ? 256 : 128;
+        __shared__ int s_hk[WAVES_PER_BLOCK][GATHER_HS];
+        __shared__ uint8_t s_hv[WAVES_PER_BLOCK][GATHER_HS];
         int *etab_w = EDGE ? a.weid + (long long)(blockIdx.x * WAVES_PER_BLOCK + wv) * 4096 : nullptr;
         PersistCtl *pc = (PersistCtl *)uniform64((uint64_t)a.pctl);
         const int home = home_slice();
@@ -2176,7 +2213,8 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
                     gs.set_vertex(v);
                     if (EDGE) vs.set_table(etab_w);
                     int d, gid;
-                    const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_base[wv], s_A[wv], d, gid, etab_w);
+                    const uint64_t A = gather_light<GATHER_HS>(v, lane, a, s_nz[wv], s_base[wv], s_A[wv], s_hk[wv], s_hv[wv], d,
+                                                    gid, etab_w);
                     int uni = -1;
                     int2 pref = make_int2(0, 0);
                     bool ok = true;
@@ -2231,10 +2269,12 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
             __builtin_amdgcn_s_sleep(32);
         }
     } else {
-        __shared__ int s_vl[WAVES_PER_BLOCK][64];
-        __shared__ int s_pre[WAVES_PER_BLOCK][64];
+        __shared__ int s_nz[WAVES_PER_BLOCK][64];
         __shared__ int s_base[WAVES_PER_BLOCK][64];
         __shared__ unsigned long long s_A[WAVES_PER_BLOCK][64];
+        constexpr int GATHER_HS = LOCAL ? 256 : 128;
+        __shared__ int s_hk[WAVES_PER_BLOCK][GATHER_HS];
+        __shared__ uint8_t s_hv[WAVES_PER_BLOCK][GATHER_HS];
         const int n = a.nlight;
         // per-edge counts: this wave's table of member-pair edge ids
         int *etab_w = EDGE ? a.weid + (long long)(blockIdx.x * WAVES_PER_BLOCK + wv) * 4096 : nullptr;
@@ -2246,7 +2286,8 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
             gs.set_vertex(v);
             int d, gid;
             PT_MARK(t_g);
-            const uint64_t A = gather_light(v, lane, a, s_vl[wv], s_pre[wv], s_base[wv], s_A[wv], d, gid, etab_w);
+            const uint64_t A = gather_light<GATHER_HS>(v, lane, a, s_nz[wv], s_base[wv], s_A[wv], s_hk[wv], s_hv[wv], d, gid,
+                                            etab_w);
             int uni = -1;
             int2 pref = make_int2(0, 0);
             if (d > a.dfs_max) {
