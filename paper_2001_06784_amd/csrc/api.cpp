@@ -287,7 +287,11 @@ struct pv_ctx {
     // cancellation and the watchdog: the device flag the walk's claims read,
     // set through its own stream while a call's kernels run
     int *d_abort = nullptr;
+    // the stream that raises d_abort: created only for a context with a
+    // watchdog or on its first pv_cancel (each stream takes one of the few
+    // hardware queues, which the serving loop's workers share)
     hipStream_t abort_stream = nullptr;
+    std::mutex abort_mu;
     std::atomic<int> cancel_req{0};
     bool timed_out = false;
     int timeout_ms = 0;
@@ -469,7 +473,7 @@ extern "C" pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out)
         return PV_EDEVICE;
     }
     c->timeout_ms = conf.timeout_ms;
-    if (hipStreamCreateWithFlags(&c->abort_stream, hipStreamNonBlocking) != hipSuccess ||
+    if ((c->timeout_ms > 0 && hipStreamCreateWithFlags(&c->abort_stream, hipStreamNonBlocking) != hipSuccess) ||
         hipMalloc((void **)&c->d_abort, 256) != hipSuccess || hipMemset(c->d_abort, 0, 256) != hipSuccess) {
         (void)hipGetLastError();
         pv_fini(c);
@@ -524,7 +528,17 @@ extern "C" void pv_fini(pv_ctx *c) {
 
 extern "C" pv_status pv_cancel(pv_ctx *c) {
     if (!c || !c->d_abort) return PV_EINVAL;
+    std::lock_guard<std::mutex> lk(c->abort_mu);
     c->cancel_req.store(1);
+    if (!c->abort_stream) {
+        // on the context's device; the calling thread's current device is kept
+        int prev = 0;
+        HIPCHK(hipGetDevice(&prev));
+        HIPCHK(hipSetDevice(c->device));
+        const hipError_t e = hipStreamCreateWithFlags(&c->abort_stream, hipStreamNonBlocking);
+        (void)hipSetDevice(prev);
+        HIPCHK(e);
+    }
     HIPCHK(hipMemsetAsync(c->d_abort, 1, sizeof(int), c->abort_stream));
     return PV_OK;
 }
@@ -1086,8 +1100,11 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
     hipStream_t s = c->stream;
     // a new call: no cancellation or timeout of an earlier one applies
     const auto t_call = std::chrono::steady_clock::now();
-    HIPCHK(hipStreamSynchronize(c->abort_stream));
-    c->cancel_req.store(0);
+    {
+        std::lock_guard<std::mutex> lk(c->abort_mu);
+        if (c->abort_stream) HIPCHK(hipStreamSynchronize(c->abort_stream));
+        c->cancel_req.store(0);
+    }
     c->timed_out = false;
     HIPCHK(hipMemsetAsync(c->d_abort, 0, sizeof(int), s));
     const int alpha = g->alpha;
