@@ -159,7 +159,10 @@ void pv_fini(pv_ctx *ctx);
  * the units in hand are done (a unit walks at most the depth-first budget
  * of nodes).  The context stays usable; no effect when no call runs.
  * Results are not partial: a cancelled call's outputs are undefined and the
- * call is simply run again.
+ * call is simply run again.  The flag is raised on a HIP stream of the
+ * context's own, created by the first pv_cancel of a context without a
+ * timeout (PV_EDEVICE if that fails); the calling thread's current device is
+ * left as it was.
  */
 pv_status pv_cancel(pv_ctx *ctx);
 
