@@ -19,7 +19,7 @@ Other workloads are selected with --workload:
          a/b/c = 0.57/0.19/0.19) with 50 planted cliques of 20..60 vertices;
          --edge adds per-edge counts for k = 3..8.  Scale 22 itself is a
          parity case: its tree is far too large to walk whole.
-  serve  an open-loop Poisson stream (200 requests/s) over a pool of 256
+  serve  (disabled: see main) an open-loop Poisson stream (200 requests/s) over a pool of 256
          Chung-Lu graphs (edge counts log-uniform in [1e3, 2e6], exponent
          2.5); graph per request Zipf(1.1) over the pool, type 50/50 global
          all-k / global + per-vertex k=3..8.  The library's serving loop with
@@ -247,7 +247,14 @@ def main():
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "serve":
-        return bench_serve(args)
+        # Off until its GPU memory fault is explained: two runs of this
+        # workload (each after runs of the test suite in the same session)
+        # ended with the device faulted, and no cause has been found in the
+        # serving loop or the kernels it launches.  The serving tests, with
+        # small graphs, pass.
+        print("bench.py --workload serve is disabled: it has ended with a GPU memory fault whose cause "
+              "is not found", file=sys.stderr)
+        sys.exit(2)
     if args.workload == "copy":
         return bench_copy()
     if args.workload == "rmat":
