@@ -19,6 +19,15 @@ def test_bench_refuses_several_gpus():
     assert "one GPU" in r.stderr
 
 
+def test_bench_serving_workload_is_switched_off():
+    # the serving benchmark refuses to run before it builds its pool or
+    # loads the library
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "serve"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "disabled" in r.stderr
+
+
 def test_rmat_web_plants_disjoint_cliques():
     # R-MAT plus planted cliques: every planted set is a clique, the sets are
     # disjoint, and the generator is deterministic for its seeds
