@@ -194,6 +194,7 @@ struct Workspace {
     // per-edge counts
     DBuf<int> ueid, weid;
     DBuf<uint64_t> umem, utot, escr;
+    DBuf<uint64_t> epk, ewrap;  // packed pair charges and their carries (counts below 2^62)
     // persistent walk: the queues' slot flags and control block
     DBuf<int> cready, mready;
     DBuf<PersistCtl> pctl;
@@ -217,7 +218,7 @@ struct Workspace {
         citem[1].release();
         mwitem[0].release();
         mwitem[1].release();
-        DBuf<uint64_t> *ub[] = {&hu_rows, &u_rows, &umem, &utot, &escr};
+        DBuf<uint64_t> *ub[] = {&hu_rows, &u_rows, &umem, &utot, &escr, &epk, &ewrap};
         for (auto *b : ub) b->release();
         u_pref.release();
         pctl.release();
@@ -235,7 +236,7 @@ struct Workspace {
         mwitem[0].release();
         mwitem[1].release();
         DBuf<uint64_t> *ub[] = {&hu_rows, &u_rows, &counts, &ovf, &vout_own, &umem, &utot, &escr,
-                                &wide_tab, &wide_out, &fq_keys, &fq_vals};
+                                &epk, &ewrap, &wide_tab, &wide_out, &fq_keys, &fq_vals};
         for (auto *b : ub) b->release();
         u_pref.release();
         hist.release();
@@ -299,6 +300,12 @@ struct pv_ctx {
     int dfs_budget = 0;  // 0: chosen per request (see budget_of)
     int lane_max = PV_LANE_MAX;
     int prefix_rows = 0;  // PV_PREFIX_ROWS: N+(root) rows per LDS pass of the prefix sums (0: all that fit)
+    // per-edge pair charges in packed 32-bit halves when every count stays
+    // below 2^62 (PV_EDGE_PACK=0 turns it off); edge_bias starts every half
+    // at that value instead of 0 (PV_EDGE_BIAS, for tests: with a value near
+    // 2^32 the halves wrap after a few charges)
+    bool edge_pack = true;
+    uint32_t edge_bias = 0;
     bool debug = false;  // PV_DEBUG set: per-level buffer demands on stderr
     Workspace ws;
     // batches: the union graph (reused between calls) and its part table
@@ -444,6 +451,8 @@ extern "C" pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out)
     if (const char *env = getenv("PV_DFS_BUDGET")) c->dfs_budget = std::max(16, std::min(1 << 20, atoi(env)));
     if (const char *env = getenv("PV_LANE_MAX")) c->lane_max = std::max(0, std::min(PV_LANE_MAX, atoi(env)));
     if (const char *env = getenv("PV_PREFIX_ROWS")) c->prefix_rows = std::max(0, atoi(env));
+    if (const char *env = getenv("PV_EDGE_PACK")) c->edge_pack = atoi(env) != 0;
+    if (const char *env = getenv("PV_EDGE_BIAS")) c->edge_bias = (uint32_t)strtoul(env, nullptr, 0);
     if (const char *env = getenv("PV_HU_BUDGET")) {
         const long long b = atoll(env);
         if (b > 0) c->ws.hu_budget = b;
@@ -1115,6 +1124,23 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
     const int mw_stride = 3 * W + 1;
     const bool local = rq.kl > 0;
     int *io = c->h_io;
+    // Per-edge pair charges in packed 32-bit halves, when no count can reach
+    // 2^62: a k-clique through edge uv has a lowest vertex r, either u or v
+    // (its other members in N+(r)) or a common neighbour (u, v and k - 3
+    // more in N+(r)), so c_k(uv) <= n * C(alpha, k - 2).
+    bool pack = false;
+    const int kw = (rq.K + 1) / 2;
+    const long long m_edges = g->nnz / 2;
+    if (rq.edge && c->edge_pack && m_edges > 0) {
+        double worst = 0.0;
+        for (int k = std::max(rq.klo, 2); k < rq.klo + rq.K; k++) {
+            double b = 1.0;  // C(alpha, k - 2)
+            for (int i = 1; i <= k - 2 && i <= alpha; i++) b = b * (double)(alpha - i + 1) / (double)i;
+            if (k - 2 > alpha) b = 0.0;
+            worst = std::max(worst, (double)g->n * b);
+        }
+        pack = worst < 0x1p62;
+    }
 
     // heavy roots per chunk, bounded by the universe budget
     const long long hu_bytes = (long long)W * dpad * 8 + (long long)dpad * 4;
@@ -1170,6 +1196,13 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
         PVCHK(c->ws.hist.ensure((size_t)rq.graphs * hd * hd));
         PVCHK(c->ws.counters.ensure(PV_NCOUNTERS));
         if (rq.edge) HIPCHK(hipMemsetAsync(c->ws.escr.p, 0, c->ws.escr.n * 8, s));
+        if (pack) {
+            const size_t words = (size_t)m_edges * kw;
+            PVCHK(c->ws.epk.ensure(words));
+            PVCHK(c->ws.ewrap.ensure(words));
+            HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->ws.epk.p, (int)c->edge_bias, 2 * words, s));
+            HIPCHK(hipMemsetAsync(c->ws.ewrap.p, 0, words * 8, s));
+        }
         HIPCHK(hipMemsetAsync(c->ws.hist.p, 0, sizeof(unsigned long long) * (size_t)rq.graphs * hd * hd, s));
         HIPCHK(hipMemsetAsync(c->ws.counters.p, 0, PV_NCOUNTERS * sizeof(unsigned long long), s));
         // flags, u_n, pref_n, omega, lovf, and the checked build's failed line
@@ -1277,6 +1310,9 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                 a.ueid = rq.edge ? c->ws.ueid.p : nullptr;
                 a.weid = rq.edge ? c->ws.weid.p : nullptr;
                 a.escr = rq.edge ? c->ws.escr.p : nullptr;
+                a.epk = pack ? c->ws.epk.p : nullptr;
+                a.ewrap = pack ? c->ws.ewrap.p : nullptr;
+                a.kw = kw;
                 a.escr_wave0[0] = 0;
                 a.escr_wave0[1] = c->level_blocks[3][0] * WAVES_PER_LAUNCH_BLOCK;
                 a.escr_wave0[2] = (c->level_blocks[3][0] + c->level_blocks[3][1]) * WAVES_PER_LAUNCH_BLOCK;
@@ -1505,6 +1541,9 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
             if (io_fresh) {  // no level ran: no universe, nothing to add
                 if (rq.edge) {
                     HIPCHK(pv_launch_edge_prefix(c->d_args.p, blocks, s));
+                    if (pack)
+                        HIPCHK(pv_launch_edge_unpack(c->ws.epk.p, c->ws.ewrap.p, m_edges, kw, rq.K, rq.vout,
+                                                     kstride, c->edge_bias, c->dev.num_cu, s));
                 } else {
                     const PrefixWork pw{c->ws.pg_cnt.p, c->ws.pg_off.p, c->ws.pg_pos.p, c->ws.pg_list.p,
                                         c->ws.scan.p};

@@ -434,9 +434,10 @@ struct EdgeSink {
     const uint8_t *bad;      // [bn][bn]: C(a, b) >= 2^128
     int bn;
     uint64_t *eout, *umem, *utot;
+    uint64_t *epk, *ewrap;  // packed 32-bit halves (nullptr: charges go to eout)
     const int *orow, *o2e;
     int *lovf, *flags;
-    int klo, K, khi, ks, ts;
+    int klo, K, khi, ks, ts, kw;
     bool ovf;
 
     __device__ void init(const LevelArgs &a, uint64_t *lds_xch, int wave0) {
@@ -448,6 +449,9 @@ struct EdgeSink {
         eout = (uint64_t *)uniform64((uint64_t)a.vout);
         umem = (uint64_t *)uniform64((uint64_t)a.umem);
         utot = (uint64_t *)uniform64((uint64_t)a.utot);
+        epk = (uint64_t *)uniform64((uint64_t)a.epk);
+        ewrap = (uint64_t *)uniform64((uint64_t)a.ewrap);
+        kw = uniformi(a.kw);
         orow = (const int *)uniform64((uint64_t)a.orow);
         o2e = (const int *)uniform64((uint64_t)a.o2e);
         lovf = (int *)uniform64((uint64_t)a.lovf);
@@ -577,6 +581,34 @@ struct EdgeSink {
         }
     }
 
+    // One pair's charges (column sel of the hand-over slots) in the packed
+    // table: the values of k = 2i and 2i + 1 added to word i's halves with
+    // one 64-bit atomic.  The old word gives the carries: out of the low
+    // half (it went into the high half) and out of the word; both are
+    // counted in ewrap and settled when the table is added to eout.  A
+    // charge of 2^32 or more goes to eout itself.
+    __device__ __forceinline__ void charge_packed(int e, uint64_t *dst, int sel) {
+        uint64_t *wp = epk + (long long)e * kw;
+        for (int i = 0; i < kw; i++) {
+            const int k0 = 2 * i, k1 = 2 * i + 1;
+            const uint64_t v0 = xch[4 * k0 + sel], h0 = xch[4 * k0 + sel + 1];
+            const uint64_t v1 = (k1 < K) ? xch[4 * k1 + sel] : 0ull, h1 = (k1 < K) ? xch[4 * k1 + sel + 1] : 0ull;
+            if ((v0 | h0 | v1 | h1) == 0) continue;
+            if (((v0 | v1) >> 32) == 0 && (h0 | h1) == 0) {
+                const uint64_t x = v0 | (v1 << 32);
+                const uint64_t old = atomicAdd((unsigned long long *)(wp + i), (unsigned long long)x);
+                const uint64_t c0 = ((old & 0xffffffffull) + v0) >> 32;
+                const uint64_t c1 = (old + x < old) ? 1ull : 0ull;
+                if (c0 | c1)
+                    atomicAdd((unsigned long long *)(ewrap + (long long)e * kw + i),
+                              (unsigned long long)(c0 | (c1 << 32)));
+            } else {
+                if (v0 | h0) ovf |= atomic_add_u128(dst + 2 * k0, v0, h0);
+                if (k1 < K && (v1 | h1)) ovf |= atomic_add_u128(dst + 2 * k1, v1, h1);
+            }
+        }
+    }
+
     // members in L leave the path (H, P: the path they leave from)
     __device__ void leave(uint64_t L, uint64_t H, uint64_t P, int lane, int) {
         L = uniform64(L) & ((1ull << 62) - 1);
@@ -617,9 +649,13 @@ struct EdgeSink {
                 if (e < 0) atomicOr(flags, 4);
                 const int sel = ((bh >> lane) & 1) ? 0 : 2;
                 uint64_t *dst = eout + 2 * ((long long)e * ks);
-                for (int kk = 0; kk < K; kk++) {
-                    const uint64_t l = xch[4 * kk + sel], hv = xch[4 * kk + sel + 1];
-                    if (e >= 0 && (l | hv)) ovf |= atomic_add_u128(dst + 2 * kk, l, hv);
+                if (epk) {
+                    if (e >= 0) charge_packed(e, dst, sel);
+                } else {
+                    for (int kk = 0; kk < K; kk++) {
+                        const uint64_t l = xch[4 * kk + sel], hv = xch[4 * kk + sel + 1];
+                        if (e >= 0 && (l | hv)) ovf |= atomic_add_u128(dst + 2 * kk, l, hv);
+                    }
                 }
             }
             wave_sync();
@@ -2392,6 +2428,40 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
     if (ovf) atomicOr(a.lovf, 1);
 }
 
+// Per-edge counts from the packed table, added to the output once the walk
+// is done.  Half 0 of a word has taken b + sum of its k = 2i charges modulo
+// 2^32, each wrap counted in the low half of the word's carry count, and
+// passed every such wrap on to half 1; half 1 has taken b + its k = 2i + 1
+// charges plus those wraps modulo 2^32, each wrap out of the word counted in
+// the high half of the carry count.  So with b the halves' starting value,
+//   sum(k = 2i)     = half0 + 2^32 * wraps0 - b,
+//   sum(k = 2i + 1) = half1 + 2^32 * wraps1 - wraps0 - b,
+// exactly, as every count is below 2^62.
+__global__ void __launch_bounds__(256) edge_unpack_kernel(const uint64_t *__restrict__ epk,
+                                                          const uint64_t *__restrict__ ewrap, long long words,
+                                                          int kw, int K, uint64_t *__restrict__ vout, int kstride,
+                                                          uint32_t bias) {
+    const uint64_t start = (uint64_t)bias | ((uint64_t)bias << 32);
+    for (long long w = blockIdx.x * 256ll + threadIdx.x; w < words; w += (long long)gridDim.x * 256) {
+        const uint64_t x = epk[w], c = ewrap[w];
+        if (x == start && c == 0) continue;
+        const long long e = w / kw;
+        const int k0 = 2 * (int)(w - e * kw);
+        const uint64_t w0 = c & 0xffffffffull, w1 = c >> 32;
+        const uint64_t s0 = (x & 0xffffffffull) + (w0 << 32) - bias;
+        const uint64_t s1 = (x >> 32) + (w1 << 32) - w0 - bias;
+        uint64_t *row = vout + 2 * (e * kstride + k0);
+        uint64_t lo = row[0] + s0;
+        row[1] += (lo < s0) ? 1ull : 0ull;
+        row[0] = lo;
+        if (k0 + 1 < K) {
+            lo = row[2] + s1;
+            row[3] += (lo < s1) ? 1ull : 0ull;
+            row[2] = lo;
+        }
+    }
+}
+
 // Per-vertex counts: what each universe's walks owe the vertices above it
 // (its prefix: the root, then hold or pivot vertices), added once after the
 // last level.  The universes of one heavy root share most of their prefix
@@ -2921,6 +2991,15 @@ int pv_level_blocks_per_cu(int kl, int lk, int mode) {
 
 hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s) {
     edge_prefix_kernel<<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t pv_launch_edge_unpack(const uint64_t *epk, const uint64_t *ewrap, long long m, int kw, int K,
+                                 uint64_t *vout, int kstride, uint32_t bias, int num_cu, hipStream_t s) {
+    const long long words = m * kw;
+    if (words <= 0) return hipSuccess;
+    const int blocks = (int)std::min<long long>((words + 255) / 256, (long long)num_cu * 8);
+    edge_unpack_kernel<<<blocks, 256, 0, s>>>(epk, ewrap, words, kw, K, vout, kstride, bias);
     return hipGetLastError();
 }
 

@@ -174,3 +174,49 @@ def test_every_k_per_vertex_identities_full(full):
         assert sums[k - 1] == k * res.counts[k], k
     # the columns of k = 3..10 are the benchmark's own table
     assert np.array_equal(out[:, K_LO - 1:K_HI, :], vert.reshape(g.n, K_HI - K_LO + 1, 2))
+
+
+def test_per_edge_full(full, monkeypatch):
+    # per-edge counts k = 3..8 in the benchmark's call (tree cut at k_max =
+    # 8): each column sums to C(k, 2) C_k; at every vertex the counts of its
+    # edges sum to (k - 1) c_k(v), against the per-vertex table pinned to the
+    # oracle's digests above; and the pair charges in packed 32-bit halves
+    # give the same table as charges straight to the output
+    import torch
+    g, ctx, h, res, lovf, vert, sub = full
+    klo, khi = 3, 8
+    K = khi - klo + 1
+    dev = torch.zeros((g.m, K, 2), dtype=torch.int64, device="cuda:0")
+    eres, eovf = P.pv_count(h, reorient=False, k_max=khi, local_kind=P.PV_EDGE, k_lo=klo, k_hi=khi,
+                            local_out=dev.data_ptr())
+    torch.cuda.synchronize()
+    _say(f"[fullsize] per-edge k={klo}..{khi}: leaves={eres.stats['leaves']}")
+    assert eres.status == P.PV_OK and eovf == 0
+    assert eres.counts[: khi + 1] == res.counts[: khi + 1]
+    sums = _sum_u128(dev.cpu().numpy().view(np.uint64))
+    for i, k in enumerate(range(klo, khi + 1)):
+        assert sums[i] == k * (k - 1) // 2 * res.counts[k], k
+    # the vertex identity modulo 2^64, from the low limbs
+    eu, ev = P.pv_graph_edge_list(h)
+    lo = dev[:, :, 0]
+    at = torch.zeros((g.n, K), dtype=torch.int64, device="cuda:0")
+    at.index_add_(0, torch.from_numpy(eu.astype(np.int64)).to("cuda:0"), lo)
+    at.index_add_(0, torch.from_numpy(ev.astype(np.int64)).to("cuda:0"), lo)
+    got = at.cpu().numpy().view(np.uint64)
+    vt = vert.reshape(g.n, K_HI - K_LO + 1, 2)[:, :K, 0]
+    assert np.array_equal(got, vt * np.arange(klo - 1, khi, dtype=np.uint64)[None, :])
+    # packing off: every charge straight to the u128 output
+    monkeypatch.setenv("PV_EDGE_PACK", "0")
+    c2 = P.pv_init(0, torch.cuda.current_stream().cuda_stream)
+    try:
+        h2 = P.pv_graph_load_csr(c2, g.n, g.row_ptr, g.col)
+        try:
+            dev2 = torch.zeros_like(dev)
+            P.pv_count(h2, reorient=True, k_max=khi, local_kind=P.PV_EDGE, k_lo=klo, k_hi=khi,
+                       local_out=dev2.data_ptr())
+            torch.cuda.synchronize()
+        finally:
+            P.pv_graph_free(h2)
+    finally:
+        P.pv_fini(c2)
+    assert torch.equal(dev, dev2)
