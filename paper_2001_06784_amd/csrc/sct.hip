@@ -425,7 +425,7 @@ struct EdgeSink {
     uint64_t t0l, t0h, t1l, t1h, t2l, t2h;
     uint64_t BH, BP;  // path members above this lane
     const int *etab;  // edge ids of the member pairs of the universe walked now
-    uint64_t *xch;    // LDS hand-over slot of this wave (4 * KL words)
+    uint64_t *xch;    // LDS hand-over slot of this wave (4 * KL words, then 64 partner lanes as bytes)
     uint64_t *snap;   // scratch [64][2][K] u128: T at the member's join (its role's two types)
     uint64_t *vacc;   // scratch [64][2][K] u128: finished stays toward hold / pivot prefix vertices
     // wave-uniform copies of the arguments
@@ -581,31 +581,46 @@ struct EdgeSink {
         }
     }
 
-    // One pair's charges (column sel of the hand-over slots) in the packed
-    // table: the values of k = 2i and 2i + 1 added to word i's halves with
-    // one 64-bit atomic.  The old word gives the carries: out of the low
-    // half (it went into the high half) and out of the word; both are
-    // counted in ewrap and settled when the table is added to eout.  A
+    // Word i of one pair's charges (column sel of the hand-over slots) in
+    // the packed table: the values of k = 2i and 2i + 1 added to the word's
+    // halves with one 64-bit atomic.  The old word gives the carries: out of
+    // the low half (it went into the high half) and out of the word; both
+    // are counted in ewrap and settled when the table is added to eout.  A
     // charge of 2^32 or more goes to eout itself.
-    __device__ __forceinline__ void charge_packed(int e, uint64_t *dst, int sel) {
-        uint64_t *wp = epk + (long long)e * kw;
-        for (int i = 0; i < kw; i++) {
-            const int k0 = 2 * i, k1 = 2 * i + 1;
-            const uint64_t v0 = xch[4 * k0 + sel], h0 = xch[4 * k0 + sel + 1];
-            const uint64_t v1 = (k1 < K) ? xch[4 * k1 + sel] : 0ull, h1 = (k1 < K) ? xch[4 * k1 + sel + 1] : 0ull;
-            if ((v0 | h0 | v1 | h1) == 0) continue;
-            if (((v0 | v1) >> 32) == 0 && (h0 | h1) == 0) {
-                const uint64_t x = v0 | (v1 << 32);
-                const uint64_t old = atomicAdd((unsigned long long *)(wp + i), (unsigned long long)x);
-                const uint64_t c0 = ((old & 0xffffffffull) + v0) >> 32;
-                const uint64_t c1 = (old + x < old) ? 1ull : 0ull;
-                if (c0 | c1)
-                    atomicAdd((unsigned long long *)(ewrap + (long long)e * kw + i),
-                              (unsigned long long)(c0 | (c1 << 32)));
-            } else {
-                if (v0 | h0) ovf |= atomic_add_u128(dst + 2 * k0, v0, h0);
-                if (k1 < K && (v1 | h1)) ovf |= atomic_add_u128(dst + 2 * k1, v1, h1);
-            }
+    __device__ __forceinline__ void charge_word(int e, int i, int sel) {
+        const int k0 = 2 * i, k1 = 2 * i + 1;
+        const uint64_t v0 = xch[4 * k0 + sel], h0 = xch[4 * k0 + sel + 1];
+        const uint64_t v1 = (k1 < K) ? xch[4 * k1 + sel] : 0ull, h1 = (k1 < K) ? xch[4 * k1 + sel + 1] : 0ull;
+        if ((v0 | h0 | v1 | h1) == 0) return;
+        if (((v0 | v1) >> 32) == 0 && (h0 | h1) == 0) {
+            const uint64_t x = v0 | (v1 << 32);
+            const uint64_t old = atomicAdd((unsigned long long *)(epk + (long long)e * kw + i), (unsigned long long)x);
+            const uint64_t c0 = ((old & 0xffffffffull) + v0) >> 32;
+            const uint64_t c1 = (old + x < old) ? 1ull : 0ull;
+            if (c0 | c1)
+                atomicAdd((unsigned long long *)(ewrap + (long long)e * kw + i), (unsigned long long)(c0 | (c1 << 32)));
+        } else {
+            uint64_t *dst = eout + 2 * ((long long)e * ks);
+            if (v0 | h0) ovf |= atomic_add_u128(dst + 2 * k0, v0, h0);
+            if (k1 < K && (v1 | h1)) ovf |= atomic_add_u128(dst + 2 * k1, v1, h1);
+        }
+    }
+
+    // Member j's stay owes its partners pm (hold partners bh): every
+    // (partner, word) pair is one lane's task, the words of a partner on
+    // neighbouring lanes, so one instruction's atomics fall on few lines.
+    __device__ __forceinline__ void charge_partners_packed(int j, uint64_t pm, uint64_t bh, int lane) {
+        uint8_t *plist = (uint8_t *)(xch + 4 * KL);
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        if ((pm >> lane) & 1) plist[__popcll(pm & below)] = (uint8_t)lane;
+        wave_sync();
+        const int ntask = __popcll(pm) * kw;
+        for (int t = lane; t < ntask; t += 64) {
+            const int pi = t / kw, wi = t - pi * kw;
+            const int pl = plist[pi];
+            const int e = etab[j * 64 + pl];
+            if (e < 0) atomicOr(flags, 4);
+            else charge_word(e, wi, ((bh >> pl) & 1) ? 0 : 2);
         }
     }
 
@@ -644,18 +659,16 @@ struct EdgeSink {
                 xch[4 * lane + 3] = bhh;
             }
             wave_sync();
-            if (((bh | bp) >> lane) & 1) {
+            if (epk) {
+                charge_partners_packed(j, bh | bp, bh, lane);
+            } else if (((bh | bp) >> lane) & 1) {
                 const int e = etab[j * 64 + lane];
                 if (e < 0) atomicOr(flags, 4);
                 const int sel = ((bh >> lane) & 1) ? 0 : 2;
                 uint64_t *dst = eout + 2 * ((long long)e * ks);
-                if (epk) {
-                    if (e >= 0) charge_packed(e, dst, sel);
-                } else {
-                    for (int kk = 0; kk < K; kk++) {
-                        const uint64_t l = xch[4 * kk + sel], hv = xch[4 * kk + sel + 1];
-                        if (e >= 0 && (l | hv)) ovf |= atomic_add_u128(dst + 2 * kk, l, hv);
-                    }
+                for (int kk = 0; kk < K; kk++) {
+                    const uint64_t l = xch[4 * kk + sel], hv = xch[4 * kk + sel + 1];
+                    if (e >= 0 && (l | hv)) ovf |= atomic_add_u128(dst + 2 * kk, l, hv);
                 }
             }
             wave_sync();
@@ -1997,7 +2010,7 @@ __global__ void __launch_bounds__(64 * WAVES_PER_BLOCK, (LevelShape<KL, LK, MODE
     GlobalSink gs;
     gs.init(a, s_bins, LDS_H);
     typename SinkOf<KL, LK>::T vs;
-    __shared__ uint64_t s_xch[WAVES_PER_BLOCK][EDGE ? 4 * KL : 1];
+    __shared__ uint64_t s_xch[WAVES_PER_BLOCK][EDGE ? 4 * KL + 8 : 1];
     if (LOCAL) vs.init(a, s_xch[wv], EDGE ? a.escr_wave0[MODE] : 0);
     if constexpr (LOCAL && LK == PV_LK_VERTEX64 && KL == 8 && MODE != PV_UNITS_LIGHT) {
         // the lane tier's per-member slots of this wave start at zero
