@@ -1130,6 +1130,7 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
     // more in N+(r)), so c_k(uv) <= n * C(alpha, k - 2).
     bool pack = false;
     const int kw = (rq.K + 1) / 2;
+    const int kws = kw > 2 ? 4 : kw;  // an edge's words within one 64-byte line
     const long long m_edges = g->nnz / 2;
     if (rq.edge && c->edge_pack && m_edges > 0) {
         double worst = 0.0;
@@ -1197,7 +1198,7 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
         PVCHK(c->ws.counters.ensure(PV_NCOUNTERS));
         if (rq.edge) HIPCHK(hipMemsetAsync(c->ws.escr.p, 0, c->ws.escr.n * 8, s));
         if (pack) {
-            const size_t words = (size_t)m_edges * kw;
+            const size_t words = (size_t)m_edges * kws;
             PVCHK(c->ws.epk.ensure(words));
             PVCHK(c->ws.ewrap.ensure(words));
             HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->ws.epk.p, (int)c->edge_bias, 2 * words, s));
@@ -1313,6 +1314,7 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                 a.epk = pack ? c->ws.epk.p : nullptr;
                 a.ewrap = pack ? c->ws.ewrap.p : nullptr;
                 a.kw = kw;
+                a.kws = kws;
                 a.escr_wave0[0] = 0;
                 a.escr_wave0[1] = c->level_blocks[3][0] * WAVES_PER_LAUNCH_BLOCK;
                 a.escr_wave0[2] = (c->level_blocks[3][0] + c->level_blocks[3][1]) * WAVES_PER_LAUNCH_BLOCK;
@@ -1542,7 +1544,7 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                 if (rq.edge) {
                     HIPCHK(pv_launch_edge_prefix(c->d_args.p, blocks, s));
                     if (pack)
-                        HIPCHK(pv_launch_edge_unpack(c->ws.epk.p, c->ws.ewrap.p, m_edges, kw, rq.K, rq.vout,
+                        HIPCHK(pv_launch_edge_unpack(c->ws.epk.p, c->ws.ewrap.p, m_edges, kw, kws, rq.K, rq.vout,
                                                      kstride, c->edge_bias, c->dev.num_cu, s));
                 } else {
                     const PrefixWork pw{c->ws.pg_cnt.p, c->ws.pg_off.p, c->ws.pg_pos.p, c->ws.pg_list.p,

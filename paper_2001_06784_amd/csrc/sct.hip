@@ -437,7 +437,7 @@ struct EdgeSink {
     uint64_t *epk, *ewrap;  // packed 32-bit halves (nullptr: charges go to eout)
     const int *orow, *o2e;
     int *lovf, *flags;
-    int klo, K, khi, ks, ts, kw;
+    int klo, K, khi, ks, ts, kw, kws;
     bool ovf;
 
     __device__ void init(const LevelArgs &a, uint64_t *lds_xch, int wave0) {
@@ -452,6 +452,7 @@ struct EdgeSink {
         epk = (uint64_t *)uniform64((uint64_t)a.epk);
         ewrap = (uint64_t *)uniform64((uint64_t)a.ewrap);
         kw = uniformi(a.kw);
+        kws = uniformi(a.kws);
         orow = (const int *)uniform64((uint64_t)a.orow);
         o2e = (const int *)uniform64((uint64_t)a.o2e);
         lovf = (int *)uniform64((uint64_t)a.lovf);
@@ -594,11 +595,11 @@ struct EdgeSink {
         if ((v0 | h0 | v1 | h1) == 0) return;
         if (((v0 | v1) >> 32) == 0 && (h0 | h1) == 0) {
             const uint64_t x = v0 | (v1 << 32);
-            const uint64_t old = atomicAdd((unsigned long long *)(epk + (long long)e * kw + i), (unsigned long long)x);
+            const uint64_t old = atomicAdd((unsigned long long *)(epk + (long long)e * kws + i), (unsigned long long)x);
             const uint64_t c0 = ((old & 0xffffffffull) + v0) >> 32;
             const uint64_t c1 = (old + x < old) ? 1ull : 0ull;
             if (c0 | c1)
-                atomicAdd((unsigned long long *)(ewrap + (long long)e * kw + i), (unsigned long long)(c0 | (c1 << 32)));
+                atomicAdd((unsigned long long *)(ewrap + (long long)e * kws + i), (unsigned long long)(c0 | (c1 << 32)));
         } else {
             uint64_t *dst = eout + 2 * ((long long)e * ks);
             if (v0 | h0) ovf |= atomic_add_u128(dst + 2 * k0, v0, h0);
@@ -2452,14 +2453,15 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
 // exactly, as every count is below 2^62.
 __global__ void __launch_bounds__(256) edge_unpack_kernel(const uint64_t *__restrict__ epk,
                                                           const uint64_t *__restrict__ ewrap, long long words,
-                                                          int kw, int K, uint64_t *__restrict__ vout, int kstride,
-                                                          uint32_t bias) {
+                                                          int kw, int kws, int K, uint64_t *__restrict__ vout,
+                                                          int kstride, uint32_t bias) {
     const uint64_t start = (uint64_t)bias | ((uint64_t)bias << 32);
     for (long long w = blockIdx.x * 256ll + threadIdx.x; w < words; w += (long long)gridDim.x * 256) {
-        const uint64_t x = epk[w], c = ewrap[w];
-        if (x == start && c == 0) continue;
         const long long e = w / kw;
-        const int k0 = 2 * (int)(w - e * kw);
+        const int i = (int)(w - e * kw);
+        const uint64_t x = epk[e * kws + i], c = ewrap[e * kws + i];
+        if (x == start && c == 0) continue;
+        const int k0 = 2 * i;
         const uint64_t w0 = c & 0xffffffffull, w1 = c >> 32;
         const uint64_t s0 = (x & 0xffffffffull) + (w0 << 32) - bias;
         const uint64_t s1 = (x >> 32) + (w1 << 32) - w0 - bias;
@@ -3007,12 +3009,12 @@ hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t pv_launch_edge_unpack(const uint64_t *epk, const uint64_t *ewrap, long long m, int kw, int K,
+hipError_t pv_launch_edge_unpack(const uint64_t *epk, const uint64_t *ewrap, long long m, int kw, int kws, int K,
                                  uint64_t *vout, int kstride, uint32_t bias, int num_cu, hipStream_t s) {
     const long long words = m * kw;
     if (words <= 0) return hipSuccess;
     const int blocks = (int)std::min<long long>((words + 255) / 256, (long long)num_cu * 8);
-    edge_unpack_kernel<<<blocks, 256, 0, s>>>(epk, ewrap, words, kw, K, vout, kstride, bias);
+    edge_unpack_kernel<<<blocks, 256, 0, s>>>(epk, ewrap, words, kw, kws, K, vout, kstride, bias);
     return hipGetLastError();
 }
 
