@@ -86,7 +86,9 @@ __global__ void check_rowptr_kernel(int n, long long nnz, const int *__restrict_
 // degrees and frontiers in LDS and block-level barriers.  Both phases run
 // the same sub-rounds, so the keys are those of the canonical peel.
 
-__device__ __forceinline__ int ld_acquire(const int *p) {
+// a relaxed device-scope load (no ordering of its own: where a value read
+// this way publishes other data, a fence after it gives the acquire)
+__device__ __forceinline__ int ld_agent_rlx(const int *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -117,7 +119,7 @@ __device__ bool grid_barrier(PeelCtl *ctl, int nblocks, unsigned &epoch) {
             bool behind = false;
             for (int b = lane; b < nblocks; b += 64) behind = behind || ld_u(&ctl->bar_flag[b * 32]) < e;
             if (ballot64(behind) == 0) break;
-            if (ld_acquire(&ctl->err) != 0 || ++spins > (1u << 24)) {
+            if (ld_agent_rlx(&ctl->err) != 0 || ++spins > (1u << 24)) {
                 if (lane == 0) atomicOr(&ctl->err, 1);
                 ok = 0;
                 break;
@@ -269,7 +271,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             __syncthreads();
             if (threadIdx.x == 0 && s_kmin != 0x7fffffff) atomicMin(&ctl->minv[r & 1], s_kmin);
             if (!grid_barrier(ctl, nb, epoch)) return;
-            k = ld_acquire(&ctl->minv[r & 1]);
+            k = ld_agent_rlx(&ctl->minv[r & 1]);
             alpha = max(alpha, k);
             int *F = (r & 1) ? pa.fb : pa.fa;
             if (threadIdx.x == 0) s_nj = 0;
@@ -346,7 +348,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
             }
             list_flush(F, &ctl->cnt[r % 3]);
             if (!grid_barrier(ctl, nb, epoch)) return;
-            nF = ld_acquire(&ctl->cnt[r % 3]);
+            nF = ld_agent_rlx(&ctl->cnt[r % 3]);
             if (nF == 0) break;  // cannot happen while vertices remain
         }
         const int *F = (r & 1) ? pa.fb : pa.fa;
@@ -425,13 +427,13 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                 const int bw = threadIdx.x >> 6, nbw = blockDim.x >> 6;
                 for (int t = 0;; t++) {
                     for (int i = bw; i < nF; i += nbw) {
-                        const int v = ld_acquire(&F[i]);
+                        const int v = ld_agent_rlx(&F[i]);
                         wave_row(rp[v], rp[v + 1]);
                     }
                     list_flush(Fn, ncnt);
                     __syncthreads();
                     removed += nF;
-                    nF = ld_acquire(ncnt);
+                    nF = ld_agent_rlx(ncnt);
                     r++;
                     n_block++;
                     if (nF == 0 || nF > PEEL_BLOCK_FRONTIER || t + 1 >= PEEL_BLOCK_ROUNDS ||
@@ -454,9 +456,9 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
                 }
             }
             if (!grid_barrier(ctl, nb, epoch)) return;
-            r = ld_acquire(&ctl->blk_r);
-            nF = ld_acquire(&ctl->blk_nf);
-            removed = ld_acquire(&ctl->blk_removed);
+            r = ld_agent_rlx(&ctl->blk_r);
+            nF = ld_agent_rlx(&ctl->blk_nf);
+            removed = ld_agent_rlx(&ctl->blk_removed);
             continue;
         }
         if (nF >= nw * 8) {
@@ -498,7 +500,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         list_flush(Fn, ncnt);
         if (!grid_barrier(ctl, nb, epoch)) return;
         removed += nF;
-        nF = ld_acquire(&ctl->cnt[(r + 1) % 3]);
+        nF = ld_agent_rlx(&ctl->cnt[(r + 1) % 3]);
         r++;
         n_grid++;
     }
@@ -600,7 +602,7 @@ __global__ void __launch_bounds__(PV_PEEL_THREADS) peel_kernel(PeelArgs pa) {
         if (lane == 0) pa.ldeg[i] = c;
     }
     if (!grid_barrier(ctl, nb, epoch)) return;
-    const int nl = ld_acquire(&ctl->nlong);
+    const int nl = ld_agent_rlx(&ctl->nlong);
     const int G = nl > 0 ? max(1, nw / nl) : 1;
     // long rows: wave t takes row t % nl from step t / nl on, every G-th step
     for (int t = wid; t < nl * G; t += nw) {
