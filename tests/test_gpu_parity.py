@@ -586,7 +586,10 @@ def test_batch_workload_whole(ctx):
         for h in hs:
             P.pv_graph_free(h)
     for i, (r, s1) in enumerate(zip(res, single)):
-        assert r.counts == s1.counts and r.omega == s1.omega and r.overflow == s1.overflow == [], i
+        # (the two calls return count buffers of different lengths, zero past omega)
+        top = min(len(r.counts), len(s1.counts))
+        assert r.counts[:top] == s1.counts[:top] and not any(r.counts[top:]) and not any(s1.counts[top:]), i
+        assert r.omega == s1.omega and r.omega < top and r.overflow == s1.overflow == [], i
     assert st["leaves"] == sum(s1.stats["leaves"] for s1 in single)
     for i in range(0, len(graphs), 16):
         ref = O.count(graphs[i])
