@@ -1198,11 +1198,20 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
         PVCHK(c->ws.counters.ensure(PV_NCOUNTERS));
         if (rq.edge) HIPCHK(hipMemsetAsync(c->ws.escr.p, 0, c->ws.escr.n * 8, s));
         if (pack) {
+            // the packed tables are an option: without room for them the
+            // charges go straight to the output
             const size_t words = (size_t)m_edges * kws;
-            PVCHK(c->ws.epk.ensure(words));
-            PVCHK(c->ws.ewrap.ensure(words));
-            HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->ws.epk.p, (int)c->edge_bias, 2 * words, s));
-            HIPCHK(hipMemsetAsync(c->ws.ewrap.p, 0, words * 8, s));
+            pv_status st = c->ws.epk.ensure(words);
+            if (st == PV_OK) st = c->ws.ewrap.ensure(words);
+            if (st == PV_ENOMEM) {
+                c->ws.epk.release();
+                c->ws.ewrap.release();
+                pack = false;
+            } else {
+                PVCHK(st);
+                HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->ws.epk.p, (int)c->edge_bias, 2 * words, s));
+                HIPCHK(hipMemsetAsync(c->ws.ewrap.p, 0, words * 8, s));
+            }
         }
         HIPCHK(hipMemsetAsync(c->ws.hist.p, 0, sizeof(unsigned long long) * (size_t)rq.graphs * hd * hd, s));
         HIPCHK(hipMemsetAsync(c->ws.counters.p, 0, PV_NCOUNTERS * sizeof(unsigned long long), s));

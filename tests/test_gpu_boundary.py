@@ -140,6 +140,38 @@ def test_budget_refuses_then_context_stays_usable():
         P.pv_fini(c)
 
 
+def test_per_edge_packed_tables_give_way_to_the_budget(monkeypatch):
+    # the packed per-edge tables (2 x m x 4 words here) are an option: a
+    # budget that holds the unpacked walk but not them still gives the
+    # oracle's counts, with the charges sent straight to the output
+    g = gg.plant_cliques(gg.chung_lu(20000, 14, 2.3, 800, 611), [30], 612)
+    ref = O.count(g, edge=(3, 8))
+    tables = 2 * g.m * 4 * 8
+    monkeypatch.setenv("PV_EDGE_PACK", "0")
+    c0 = P.pv_init(0)
+    try:
+        h = P.pv_graph_load_csr(c0, g.n, g.row_ptr, g.col)
+        out0, ovf0, _ = P.pv_count_local(h, P.PV_EDGE, 3, 8)
+        need = P.pv_memory(c0)
+        P.pv_graph_free(h)
+    finally:
+        P.pv_fini(c0)
+    monkeypatch.delenv("PV_EDGE_PACK")
+    budget = need + (2 << 20)
+    assert budget < need + tables
+    _say(f"[boundary] per-edge under a budget: m={g.m} unpacked walk holds {need} bytes, budget {budget}")
+    c = P.pv_init(0, hbm_budget=budget)
+    try:
+        h = P.pv_graph_load_csr(c, g.n, g.row_ptr, g.col)
+        out, ovf, _ = P.pv_count_local(h, P.PV_EDGE, 3, 8)
+        assert P.pv_memory(c) <= budget
+        P.pv_graph_free(h)
+    finally:
+        P.pv_fini(c)
+    assert ovf0 == 0 and np.array_equal(out0, ref.edge)
+    assert ovf == 0 and np.array_equal(out, ref.edge)
+
+
 # -------------------------------------------- a graph in use is not freed
 
 def test_free_refuses_a_graph_in_use(ctx):
