@@ -204,14 +204,16 @@ pv_status pv_measure_peaks(pv_ctx *ctx, int64_t copy_bytes, pv_peaks *out);
  *                   pass when what the universes owe the vertices above them
  *                   is added up per heavy root (default: as many as fit).
  *   PV_DEBUG        per-level buffer demands and times on stderr.
- *   PV_EDGE_PACK    per-edge counts: 0 sends every pair charge straight to
- *                   the u128 output; by default, when no count can reach
- *                   2^62 (n * C(alpha, k - 2) < 2^62 for every k asked
- *                   for), two values of k share one 64-bit atomic in 32-bit
- *                   halves and the carries are counted beside them.
- *   PV_EDGE_BIAS    per-edge counts, packed: the halves' starting value
+ *   PV_PACK         local counts: 0 sends every addition straight to the
+ *                   u128 output; by default, when no count can reach 2^62
+ *                   (per edge n * C(alpha, k - 2), per vertex
+ *                   (max degree + 1) * C(alpha, k - 1), for every k asked
+ *                   for; per vertex only with 64-bit visit sums), two values
+ *                   of k share one 64-bit atomic in 32-bit halves and the
+ *                   carries are counted beside them.
+ *   PV_PACK_BIAS    local counts, packed: the halves' starting value
  *                   (default 0; a value near 2^32 makes them wrap after a
- *                   few charges, which tests use).
+ *                   few additions, which tests use).
  *   PV_RECORD       a file path: every count call on the context appends
  *                   one JSON line to it (the call, the graph's n and m,
  *                   alpha, omega, k_max, the local range, the walk's

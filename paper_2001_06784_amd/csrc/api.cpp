@@ -300,12 +300,13 @@ struct pv_ctx {
     int dfs_budget = 0;  // 0: chosen per request (see budget_of)
     int lane_max = PV_LANE_MAX;
     int prefix_rows = 0;  // PV_PREFIX_ROWS: N+(root) rows per LDS pass of the prefix sums (0: all that fit)
-    // per-edge pair charges in packed 32-bit halves when every count stays
-    // below 2^62 (PV_EDGE_PACK=0 turns it off); edge_bias starts every half
-    // at that value instead of 0 (PV_EDGE_BIAS, for tests: with a value near
-    // 2^32 the halves wrap after a few charges)
-    bool edge_pack = true;
-    uint32_t edge_bias = 0;
+    // local counts (per vertex with 64-bit visit sums, per edge) added in
+    // packed 32-bit halves when every count stays below 2^62 (PV_PACK=0
+    // turns it off); pack_bias starts every half at that value instead of 0
+    // (PV_PACK_BIAS, for tests: with a value near 2^32 the halves wrap after
+    // a few additions)
+    bool pack = true;
+    uint32_t pack_bias = 0;
     bool debug = false;  // PV_DEBUG set: per-level buffer demands on stderr
     Workspace ws;
     // batches: the union graph (reused between calls) and its part table
@@ -326,6 +327,7 @@ struct pv_graph {
     int n = 0;
     long long nnz = 0;
     DBuf<int> rp, col;
+    int maxdeg = -1;  // largest degree (-1: not known); bounds the local counts
     // orientation
     bool oriented = false;
     int alpha = 0, subrounds = 0;
@@ -451,8 +453,8 @@ extern "C" pv_status pv_init(int32_t device, const pv_config *cfg, pv_ctx **out)
     if (const char *env = getenv("PV_DFS_BUDGET")) c->dfs_budget = std::max(16, std::min(1 << 20, atoi(env)));
     if (const char *env = getenv("PV_LANE_MAX")) c->lane_max = std::max(0, std::min(PV_LANE_MAX, atoi(env)));
     if (const char *env = getenv("PV_PREFIX_ROWS")) c->prefix_rows = std::max(0, atoi(env));
-    if (const char *env = getenv("PV_EDGE_PACK")) c->edge_pack = atoi(env) != 0;
-    if (const char *env = getenv("PV_EDGE_BIAS")) c->edge_bias = (uint32_t)strtoul(env, nullptr, 0);
+    if (const char *env = getenv("PV_PACK")) c->pack = atoi(env) != 0;
+    if (const char *env = getenv("PV_PACK_BIAS")) c->pack_bias = (uint32_t)strtoul(env, nullptr, 0);
     if (const char *env = getenv("PV_HU_BUDGET")) {
         const long long b = atoll(env);
         if (b > 0) c->ws.hu_budget = b;
@@ -829,6 +831,9 @@ extern "C" pv_status pv_graph_load_csr(pv_ctx *c, int32_t n, const int32_t *row_
         pv_graph_free(g);
         return s;
     }
+    int32_t dmax = 0;
+    for (int32_t v = 0; v < n; v++) dmax = std::max(dmax, row_ptr[v + 1] - row_ptr[v]);
+    g->maxdeg = dmax;
     *out = g;
     return PV_OK;
 }
@@ -868,6 +873,20 @@ extern "C" pv_status pv_graph_load_csr_device(pv_ctx *c, int32_t n, int64_t nnz,
     if (s != PV_OK) {
         pv_graph_free(g);
         return s;
+    }
+    {
+        // the largest degree, from a host copy of the row pointers
+        std::vector<int32_t> hrp((size_t)n + 1);
+        hipError_t e2 = hipMemcpyAsync(hrp.data(), g->rp.p, sizeof(int) * hrp.size(), hipMemcpyDeviceToHost, c->stream);
+        if (e2 == hipSuccess) e2 = hipStreamSynchronize(c->stream);
+        if (e2 != hipSuccess) {
+            set_err("hipMemcpyAsync", e2);
+            pv_graph_free(g);
+            return PV_EDEVICE;
+        }
+        int32_t dmax = 0;
+        for (int32_t v = 0; v < n; v++) dmax = std::max(dmax, hrp[v + 1] - hrp[v]);
+        g->maxdeg = dmax;
     }
     *out = g;
     return PV_OK;
@@ -1124,21 +1143,30 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
     const int mw_stride = 3 * W + 1;
     const bool local = rq.kl > 0;
     int *io = c->h_io;
-    // Per-edge pair charges in packed 32-bit halves, when no count can reach
-    // 2^62: a k-clique through edge uv has a lowest vertex r, either u or v
-    // (its other members in N+(r)) or a common neighbour (u, v and k - 3
-    // more in N+(r)), so c_k(uv) <= n * C(alpha, k - 2).
+    // Local counts added in packed 32-bit halves (two values of k per 64-bit
+    // atomic) when no count can reach 2^62.  A k-clique has a lowest vertex
+    // r, and its other members lie in N+(r).  Through vertex v: r is v or a
+    // neighbour of v, so c_k(v) <= (maxdeg + 1) * C(alpha, k - 1).  Through
+    // edge uv: r is u, v or a common neighbour, so c_k(uv) <= n *
+    // C(alpha, k - 2).  Per-vertex counts whose visit sums are 128 bits wide
+    // are not packed.
     bool pack = false;
     const int kw = (rq.K + 1) / 2;
-    const int kws = kw > 2 ? 4 : kw;  // an edge's words within one 64-byte line
-    const long long m_edges = g->nnz / 2;
-    if (rq.edge && c->edge_pack && m_edges > 0) {
+    // a row's words padded to a power of two (within one 64-byte line for
+    // up to 8 words)
+    int kws = 1;
+    while (kws < kw) kws *= 2;
+    const long long lrows_all = rq.edge ? g->nnz / 2 : (long long)g->n;
+    if (local && c->pack && lrows_all > 0 && (rq.edge || rq.lk == PV_LK_VERTEX64) &&
+        (rq.edge || g->maxdeg >= 0)) {
+        const double mult = rq.edge ? (double)g->n : (double)g->maxdeg + 1.0;
+        const int drop = rq.edge ? 2 : 1;  // C(alpha, k - drop)
         double worst = 0.0;
-        for (int k = std::max(rq.klo, 2); k < rq.klo + rq.K; k++) {
-            double b = 1.0;  // C(alpha, k - 2)
-            for (int i = 1; i <= k - 2 && i <= alpha; i++) b = b * (double)(alpha - i + 1) / (double)i;
-            if (k - 2 > alpha) b = 0.0;
-            worst = std::max(worst, (double)g->n * b);
+        for (int k = std::max(rq.klo, drop); k < rq.klo + rq.K; k++) {
+            double b = 1.0;
+            for (int i = 1; i <= k - drop && i <= alpha; i++) b = b * (double)(alpha - i + 1) / (double)i;
+            if (k - drop > alpha) b = 0.0;
+            worst = std::max(worst, mult * b);
         }
         pack = worst < 0x1p62;
     }
@@ -1199,8 +1227,8 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
         if (rq.edge) HIPCHK(hipMemsetAsync(c->ws.escr.p, 0, c->ws.escr.n * 8, s));
         if (pack) {
             // the packed tables are an option: without room for them the
-            // charges go straight to the output
-            const size_t words = (size_t)m_edges * kws;
+            // additions go straight to the output
+            const size_t words = (size_t)lrows_all * kws;
             pv_status st = c->ws.epk.ensure(words);
             if (st == PV_OK) st = c->ws.ewrap.ensure(words);
             if (st == PV_ENOMEM) {
@@ -1209,7 +1237,7 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                 pack = false;
             } else {
                 PVCHK(st);
-                HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->ws.epk.p, (int)c->edge_bias, 2 * words, s));
+                HIPCHK(hipMemsetD32Async((hipDeviceptr_t)c->ws.epk.p, (int)c->pack_bias, 2 * words, s));
                 HIPCHK(hipMemsetAsync(c->ws.ewrap.p, 0, words * 8, s));
             }
         }
@@ -1552,9 +1580,6 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
             if (io_fresh) {  // no level ran: no universe, nothing to add
                 if (rq.edge) {
                     HIPCHK(pv_launch_edge_prefix(c->d_args.p, blocks, s));
-                    if (pack)
-                        HIPCHK(pv_launch_edge_unpack(c->ws.epk.p, c->ws.ewrap.p, m_edges, kw, kws, rq.K, rq.vout,
-                                                     kstride, c->edge_bias, c->dev.num_cu, s));
                 } else {
                     const PrefixWork pw{c->ws.pg_cnt.p, c->ws.pg_off.p, c->ws.pg_pos.p, c->ws.pg_list.p,
                                         c->ws.scan.p};
@@ -1563,6 +1588,9 @@ static pv_status run_sct_walk(pv_graph *g, const CountReq &rq) {
                     HIPCHK(pv_launch_vertex_prefix(c->d_args.p, std::min(io[SM_UN], (int)c->ws.u_cap), rq.nheavy,
                                                    pw, rows, s));
                 }
+                if (pack)
+                    HIPCHK(pv_launch_local_unpack(c->ws.epk.p, c->ws.ewrap.p, lrows_all, kw, kws, rq.K, rq.vout,
+                                                  kstride, c->pack_bias, c->dev.num_cu, s));
                 HIPCHK(hipMemcpyAsync(io, g->small.p, SM_COUNT * sizeof(int), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
             }
@@ -2127,9 +2155,11 @@ extern "C" pv_status pv_count_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, i
     // the batch is counted as the disjoint union of its graphs
     std::vector<BatchPart> parts(G);
     long long N = 0, NNZ = 0;
+    int maxdeg = 0;  // the union's largest degree (-1: some member's is not known)
     for (int b = 0; b < G; b++) {
         const pv_graph *g = gs[b];
         if (!g || g->ctx->device != c->device) return PV_EINVAL;
+        maxdeg = (maxdeg < 0 || g->maxdeg < 0) ? -1 : std::max(maxdeg, g->maxdeg);
         parts[b].rp = g->rp.p;
         parts[b].col = g->col.p;
         parts[b].n = g->n;
@@ -2144,6 +2174,7 @@ extern "C" pv_status pv_count_batch(pv_ctx *c, int32_t G, pv_graph *const *gs, i
     pv_graph *u = c->batch;
     u->n = (int)N;
     u->nnz = NNZ;
+    u->maxdeg = maxdeg;
     u->oriented = false;
     u->eids = false;
     PVCHK(u->rp.ensure((size_t)N + 1));

@@ -167,12 +167,13 @@ struct LevelArgs {
                                    // sums of the path members; the kinds of a level run
                                    // concurrently, so kind m's waves start at escr_wave0[m]
     int escr_wave0[3];
-    // per-edge counts known to stay below 2^62: the path's pair charges go to
-    // 32-bit halves, two values of k per 64-bit word (nullptr: straight to
-    // vout).  epk [m][kws] words, the first kw = ceil(K / 2) used, k = 2i in
-    // the low half and 2i + 1 in the high half (kws, a power of two, keeps
-    // an edge's words in one 64-byte line); ewrap [m][kws]: carries out of
-    // the low half (low 32 bits) and out of the word (high 32 bits), counted
+    // local counts known to stay below 2^62: the additions (a vertex's sums,
+    // an edge's pair charges) go to 32-bit halves, two values of k per 64-bit
+    // word (nullptr: straight to vout).  epk [rows][kws] words (rows: n or
+    // m), the first kw = ceil(K / 2) used, k = 2i in the low half and 2i + 1
+    // in the high half (kws, a power of two, keeps a row's words in one
+    // 64-byte line); ewrap [rows][kws]: carries out of the low half (low 32
+    // bits) and out of the word (high 32 bits), counted
     uint64_t *epk;
     uint64_t *ewrap;
     int kw, kws;
@@ -238,8 +239,8 @@ static inline int pv_root_chunks(int n) {
 hipError_t pv_launch_level(const LevelArgs *a, int kl, int lk, int mode, int blocks, hipStream_t s);
 int pv_level_blocks_per_cu(int kl, int lk, int mode);
 hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s);
-// adds the packed per-edge table (m rows of kw words, kws apart) to vout's K columns
-hipError_t pv_launch_edge_unpack(const uint64_t *epk, const uint64_t *ewrap, long long m, int kw, int kws, int K,
+// adds the packed local table (rows of kw words, kws apart) to vout's K columns
+hipError_t pv_launch_local_unpack(const uint64_t *epk, const uint64_t *ewrap, long long m, int kw, int kws, int K,
                                  uint64_t *vout, int kstride, uint32_t bias, int num_cu, hipStream_t s);
 // per-vertex prefix sums, grouped by heavy root (max_units >= universes made;
 // ngroups = number of heavy roots; rows: N+(root) rows summed per LDS pass,

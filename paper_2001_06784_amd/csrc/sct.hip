@@ -174,10 +174,11 @@ struct VertexSink {
     const uint8_t *bad;      // [bn][bn]: C(a, b) >= 2^128
     bool wrapped;            // a 128-bit sum of this lane wrapped (with the wide table only)
     uint64_t *vout;
+    uint64_t *epk, *ewrap;   // packed 32-bit halves (64-bit sums only; nullptr: additions go to vout)
     uint64_t *utot;  // [u_cap][2][K]: what the hold / pivot vertices above a universe are owed
     const int *pool;
     int *lovf;
-    int klo, K, khi, ks, ts, bn;
+    int klo, K, khi, ks, ts, bn, kw, kws;
 
     __device__ void init(const LevelArgs &a, uint64_t *, int) {
         tab = (const uint64_t *)uniform64((uint64_t)a.bin_pad);
@@ -185,6 +186,10 @@ struct VertexSink {
         bad = (const uint8_t *)uniform64((uint64_t)a.bin_bad);
         bn = uniformi(a.bin_bn);
         vout = (uint64_t *)uniform64((uint64_t)a.vout);
+        epk = WIDE ? nullptr : (uint64_t *)uniform64((uint64_t)a.epk);
+        ewrap = (uint64_t *)uniform64((uint64_t)a.ewrap);
+        kw = uniformi(a.kw);
+        kws = uniformi(a.kws);
         utot = (uint64_t *)uniform64((uint64_t)a.utot);
         pool = (const int *)uniform64((uint64_t)a.pref_pool);
         lovf = (int *)uniform64((uint64_t)a.lovf);
@@ -318,13 +323,54 @@ struct VertexSink {
         }
     }
 
+    // Member vertex gid's sums in the packed table: the values of k = 2i and
+    // 2i + 1 added to word i's 32-bit halves with one 64-bit atomic (all
+    // words first, so that their latencies overlap), then the carries out of
+    // each half, read off the old words, counted in ewrap (the table is
+    // added to vout after the walk).  A sum of 2^32 or more goes to vout.
+    __device__ __forceinline__ void flush_packed(int gid) {
+        constexpr int KWL = KL > 0 ? (KL + 1) / 2 : 1;
+        uint64_t old[KWL], x[KWL];
+#pragma unroll
+        for (int i = 0; i < KWL; i++) {
+            old[i] = 0ull;
+            x[i] = 0ull;
+            if (i < kw) {
+                const uint64_t v0 = lo[2 * i], v1 = (2 * i + 1 < K) ? lo[(2 * i + 1) % KL] : 0ull;
+                if (((v0 | v1) >> 32) == 0) {
+                    x[i] = v0 | (v1 << 32);
+                    if (x[i]) old[i] = atomicAdd((unsigned long long *)(epk + (long long)gid * kws + i),
+                                                 (unsigned long long)x[i]);
+                } else {
+                    uint64_t *dst = vout + 2 * ((long long)gid * ks + 2 * i);
+                    if (v0) (void)atomic_add_u128(dst, v0, 0ull);
+                    if (v1) (void)atomic_add_u128(dst + 2, v1, 0ull);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < KWL; i++) asm volatile("" : "+v"(old[i]));
+#pragma unroll
+        for (int i = 0; i < KWL; i++) {
+            if (x[i]) {
+                const uint64_t c0 = ((old[i] & 0xffffffffull) + (x[i] & 0xffffffffull)) >> 32;
+                const uint64_t c1 = (old[i] + x[i] < old[i]) ? 1ull : 0ull;
+                if (c0 | c1)
+                    atomicAdd((unsigned long long *)(ewrap + (long long)gid * kws + i),
+                              (unsigned long long)(c0 | (c1 << 32)));
+            }
+        }
+    }
+
     // members: lane j < nm owns vertex gid; above the universe: `root` (a
     // light root walked without a universe in memory, a hold vertex) or, with
     // a universe, the totals go to its accumulators (a final kernel adds them
     // to every vertex of its prefix once)
     __device__ void flush(int lane, int nm, int gid, int root, int2, int uni, const LevelArgs &) {
         bool ovf = WIDE && ballot64(wrapped && (lane < nm || lane >= 62)) != 0;
-        if (lane < nm) {
+        if (!WIDE && epk) {
+            if (lane < nm) flush_packed(gid);
+        } else if (lane < nm) {
             // the low-limb adds of all slots first, so that their latencies
             // overlap; then the (rare) carries and the high limbs
             uint64_t old[KL > 0 ? KL : 1];
@@ -2442,7 +2488,7 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
     if (ovf) atomicOr(a.lovf, 1);
 }
 
-// Per-edge counts from the packed table, added to the output once the walk
+// Local counts from the packed table, added to the output once the walk
 // is done.  Half 0 of a word has taken b + sum of its k = 2i charges modulo
 // 2^32, each wrap counted in the low half of the word's carry count, and
 // passed every such wrap on to half 1; half 1 has taken b + its k = 2i + 1
@@ -2451,7 +2497,7 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
 //   sum(k = 2i)     = half0 + 2^32 * wraps0 - b,
 //   sum(k = 2i + 1) = half1 + 2^32 * wraps1 - wraps0 - b,
 // exactly, as every count is below 2^62.
-__global__ void __launch_bounds__(256) edge_unpack_kernel(const uint64_t *__restrict__ epk,
+__global__ void __launch_bounds__(256) local_unpack_kernel(const uint64_t *__restrict__ epk,
                                                           const uint64_t *__restrict__ ewrap, long long words,
                                                           int kw, int kws, int K, uint64_t *__restrict__ vout,
                                                           int kstride, uint32_t bias) {
@@ -3009,12 +3055,12 @@ hipError_t pv_launch_edge_prefix(const LevelArgs *a, int blocks, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t pv_launch_edge_unpack(const uint64_t *epk, const uint64_t *ewrap, long long m, int kw, int kws, int K,
+hipError_t pv_launch_local_unpack(const uint64_t *epk, const uint64_t *ewrap, long long m, int kw, int kws, int K,
                                  uint64_t *vout, int kstride, uint32_t bias, int num_cu, hipStream_t s) {
     const long long words = m * kw;
     if (words <= 0) return hipSuccess;
     const int blocks = (int)std::min<long long>((words + 255) / 256, (long long)num_cu * 8);
-    edge_unpack_kernel<<<blocks, 256, 0, s>>>(epk, ewrap, words, kw, kws, K, vout, kstride, bias);
+    local_unpack_kernel<<<blocks, 256, 0, s>>>(epk, ewrap, words, kw, kws, K, vout, kstride, bias);
     return hipGetLastError();
 }
 

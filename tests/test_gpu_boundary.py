@@ -147,7 +147,7 @@ def test_per_edge_packed_tables_give_way_to_the_budget(monkeypatch):
     g = gg.plant_cliques(gg.chung_lu(20000, 14, 2.3, 800, 611), [30], 612)
     ref = O.count(g, edge=(3, 8))
     tables = 2 * g.m * 4 * 8
-    monkeypatch.setenv("PV_EDGE_PACK", "0")
+    monkeypatch.setenv("PV_PACK", "0")
     c0 = P.pv_init(0)
     try:
         h = P.pv_graph_load_csr(c0, g.n, g.row_ptr, g.col)
@@ -156,7 +156,7 @@ def test_per_edge_packed_tables_give_way_to_the_budget(monkeypatch):
         P.pv_graph_free(h)
     finally:
         P.pv_fini(c0)
-    monkeypatch.delenv("PV_EDGE_PACK")
+    monkeypatch.delenv("PV_PACK")
     budget = need + (2 << 20)
     assert budget < need + tables
     _say(f"[boundary] per-edge under a budget: m={g.m} unpacked walk holds {need} bytes, budget {budget}")

@@ -206,7 +206,7 @@ def test_per_edge_full(full, monkeypatch):
     vt = vert.reshape(g.n, K_HI - K_LO + 1, 2)[:, :K, 0]
     assert np.array_equal(got, vt * np.arange(klo - 1, khi, dtype=np.uint64)[None, :])
     # packing off: every charge straight to the u128 output
-    monkeypatch.setenv("PV_EDGE_PACK", "0")
+    monkeypatch.setenv("PV_PACK", "0")
     c2 = P.pv_init(0, torch.cuda.current_stream().cuda_stream)
     try:
         h2 = P.pv_graph_load_csr(c2, g.n, g.row_ptr, g.col)

@@ -492,33 +492,37 @@ def test_per_edge_wide_range(ctx):
     assert ovf == 0 and np.array_equal(out, O.count(g, edge=(2, 10)).edge)
 
 
-# Pair charges in packed 32-bit halves (counts below 2^62).  A starting value
-# just under 2^32 makes both halves of a word wrap after a few charges, so the
-# carry bookkeeping is exercised on small graphs; with packing off the pairs
-# go straight to the output.  Both must give the oracle's counts.
+# Local counts added in packed 32-bit halves (counts below 2^62): per edge the
+# pair charges, per vertex the members' sums.  A starting value just under
+# 2^32 makes both halves of a word wrap after a few additions, so the carry
+# bookkeeping is exercised on small graphs; with packing off the additions
+# go straight to the output.  All must give the oracle's counts.
 PACKED = [("heavy", lambda: gg.plant_cliques(gg.gnp(400, 0.04, 144), [90, 12], 145), (3, 8)),
           ("gnp_odd_K", lambda: gg.gnp(150, 0.2, 141), (1, 5)),
-          ("K40", lambda: gg.complete(40), (2, 9))]
+          ("K40", lambda: gg.complete(40), (2, 9)),
+          ("K40_16k", lambda: gg.complete(40), (1, 16))]
 
 
-@pytest.mark.parametrize("env", [{"PV_EDGE_BIAS": "0xfffffffa"}, {"PV_EDGE_BIAS": "0xffffffff"},
-                                 {"PV_EDGE_PACK": "0"}], ids=["bias_fffffffa", "bias_ffffffff", "unpacked"])
+@pytest.mark.parametrize("env", [{"PV_PACK_BIAS": "0xfffffffa"}, {"PV_PACK_BIAS": "0xffffffff"},
+                                 {"PV_PACK": "0"}], ids=["bias_fffffffa", "bias_ffffffff", "unpacked"])
+@pytest.mark.parametrize("kind", [P.PV_EDGE, P.PV_VERTEX], ids=["edge", "vertex"])
 @pytest.mark.parametrize("name,maker,krange", PACKED, ids=[x[0] for x in PACKED])
-def test_per_edge_packed_halves(monkeypatch, env, name, maker, krange):
+def test_local_counts_packed_halves(monkeypatch, env, kind, name, maker, krange):
     for key, val in env.items():
         monkeypatch.setenv(key, val)
     g = maker()
     klo, khi = krange
-    _say(f"[parity] per-edge {name} {env}: n={g.n} m={g.m} k={klo}..{khi}")
+    what = "edge" if kind == P.PV_EDGE else "vertex"
+    _say(f"[parity] per-{what} {name} {env}: n={g.n} m={g.m} k={klo}..{khi}")
     c = P.pv_init(0)
     try:
         with Loaded(c, g) as h:
-            out, ovf, st = P.pv_count_local(h, P.PV_EDGE, klo, khi)
+            out, ovf, st = P.pv_count_local(h, kind, klo, khi)
     finally:
         P.pv_fini(c)
-    ref = O.count(g, edge=(klo, khi))
+    ref = O.count(g, **{what: (klo, khi)})
     assert ovf == 0
-    assert np.array_equal(out, ref.edge)
+    assert np.array_equal(out, ref.edge if kind == P.PV_EDGE else ref.vertex)
 
 
 # ------------------------------------------------------------------ batches
