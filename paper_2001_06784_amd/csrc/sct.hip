@@ -465,6 +465,30 @@ __device__ __forceinline__ int edge_id(int x, int y, const int *__restrict__ sub
 // prefix/prefix pairs are owed.  With a universe in memory these sums go to
 // per-universe accumulators that a final kernel adds to the prefix pairs
 // once per universe.
+// Add the values of k = 2i (v0, h0) and 2i + 1 (v1, h1) of local row `row`
+// to word i of the packed table: both halves with one 64-bit atomic when
+// both values are below 2^32, the carries out of each half (read off the
+// old word) counted in ewrap; otherwise straight to the row's u128 slots at
+// out (k1_in: whether k = 2i + 1 is in the range).  Returns true if a u128
+// add wrapped.
+__device__ __forceinline__ bool packed_add(uint64_t *epk, uint64_t *ewrap, int kws, long long row, int i,
+                                           uint64_t v0, uint64_t h0, uint64_t v1, uint64_t h1, uint64_t *out,
+                                           bool k1_in) {
+    if ((v0 | h0 | v1 | h1) == 0) return false;
+    if (((v0 | v1) >> 32) == 0 && (h0 | h1) == 0) {
+        const uint64_t x = v0 | (v1 << 32);
+        const uint64_t old = atomicAdd((unsigned long long *)(epk + row * kws + i), (unsigned long long)x);
+        const uint64_t c0 = ((old & 0xffffffffull) + v0) >> 32;
+        const uint64_t c1 = (old + x < old) ? 1ull : 0ull;
+        if (c0 | c1) atomicAdd((unsigned long long *)(ewrap + row * kws + i), (unsigned long long)(c0 | (c1 << 32)));
+        return false;
+    }
+    bool ovf = false;
+    if (v0 | h0) ovf |= atomic_add_u128(out, v0, h0);
+    if (k1_in && (v1 | h1)) ovf |= atomic_add_u128(out + 2, v1, h1);
+    return ovf;
+}
+
 template <int KL>
 struct EdgeSink {
     // lane kk < K: running sums over the visit's leaves, types HH, HP, PP
@@ -638,19 +662,7 @@ struct EdgeSink {
         const int k0 = 2 * i, k1 = 2 * i + 1;
         const uint64_t v0 = xch[4 * k0 + sel], h0 = xch[4 * k0 + sel + 1];
         const uint64_t v1 = (k1 < K) ? xch[4 * k1 + sel] : 0ull, h1 = (k1 < K) ? xch[4 * k1 + sel + 1] : 0ull;
-        if ((v0 | h0 | v1 | h1) == 0) return;
-        if (((v0 | v1) >> 32) == 0 && (h0 | h1) == 0) {
-            const uint64_t x = v0 | (v1 << 32);
-            const uint64_t old = atomicAdd((unsigned long long *)(epk + (long long)e * kws + i), (unsigned long long)x);
-            const uint64_t c0 = ((old & 0xffffffffull) + v0) >> 32;
-            const uint64_t c1 = (old + x < old) ? 1ull : 0ull;
-            if (c0 | c1)
-                atomicAdd((unsigned long long *)(ewrap + (long long)e * kws + i), (unsigned long long)(c0 | (c1 << 32)));
-        } else {
-            uint64_t *dst = eout + 2 * ((long long)e * ks);
-            if (v0 | h0) ovf |= atomic_add_u128(dst + 2 * k0, v0, h0);
-            if (k1 < K && (v1 | h1)) ovf |= atomic_add_u128(dst + 2 * k1, v1, h1);
-        }
+        ovf |= packed_add(epk, ewrap, kws, e, i, v0, h0, v1, h1, eout + 2 * ((long long)e * ks + k0), k1 < K);
     }
 
     // Member j's stay owes its partners pm (hold partners bh): every
@@ -2457,14 +2469,19 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
             if (gid < 0) continue;
             const uint64_t *src = a.umem + 2 * ((((long long)u * 64 + lane) * 2 + role) * K);
             int e = -2;
-            for (int kk = 0; kk < K; kk++) {
+            for (int kk = 0; kk < K; kk += a.epk ? 2 : 1) {
                 const uint64_t l = src[2 * kk], hv = src[2 * kk + 1];
-                if ((l | hv) == 0) continue;
+                const uint64_t l1 = (a.epk && kk + 1 < K) ? src[2 * kk + 2] : 0ull;
+                const uint64_t h1 = (a.epk && kk + 1 < K) ? src[2 * kk + 3] : 0ull;
+                if ((l | hv | l1 | h1) == 0) continue;
                 if (e == -2) {
                     e = edge_id(x, gid, a.sub, a.orow, a.ocol, a.o2e);
                     if (e < 0) atomicOr(a.flags, 4);
                 }
-                if (e >= 0) ovf |= atomic_add_u128(a.vout + 2 * ((long long)e * a.kstride + kk), l, hv);
+                if (e < 0) continue;
+                uint64_t *dst = a.vout + 2 * ((long long)e * a.kstride + kk);
+                if (a.epk) ovf |= packed_add(a.epk, a.ewrap, a.kws, e, kk / 2, l, hv, l1, h1, dst, kk + 1 < K);
+                else ovf |= atomic_add_u128(dst, l, hv);
             }
         }
         const uint64_t *tot = a.utot + 2 * ((long long)u * 3 * K);
@@ -2478,9 +2495,17 @@ __global__ void __launch_bounds__(256) edge_prefix_kernel(const LevelArgs *__res
                     atomicOr(a.flags, 4);
                     continue;
                 }
-                for (int kk = 0; kk < K; kk++) {
+                for (int kk = 0; kk < K; kk += a.epk ? 2 : 1) {
                     const uint64_t l = tot[2 * (type * K + kk)], hv = tot[2 * (type * K + kk) + 1];
-                    if (l | hv) ovf |= atomic_add_u128(a.vout + 2 * ((long long)e * a.kstride + kk), l, hv);
+                    uint64_t *dst = a.vout + 2 * ((long long)e * a.kstride + kk);
+                    if (a.epk) {
+                        const bool in1 = kk + 1 < K;
+                        const uint64_t l1 = in1 ? tot[2 * (type * K + kk + 1)] : 0ull;
+                        const uint64_t h1 = in1 ? tot[2 * (type * K + kk + 1) + 1] : 0ull;
+                        ovf |= packed_add(a.epk, a.ewrap, a.kws, e, kk / 2, l, hv, l1, h1, dst, in1);
+                    } else if (l | hv) {
+                        ovf |= atomic_add_u128(dst, l, hv);
+                    }
                 }
             }
         }
